@@ -1,0 +1,258 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each check ties one part of the oracle to the mathematics: library routines
+(numpy / scipy), an independent state-space formulation of the same circuit,
+closed-form solutions, conservation identities and structural properties of
+G.  A plausible slip in the oracle (wrong sign of a history term, a dropped
+conductance, a transposed incidence, a wrong initial condition, a swapped
+pivot) fails at least one of them.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2105_10661_amd import cases
+
+
+def _net_from(n_bus, frm, to, R, L, C, src_bus, amp, phase, dt, freq=60.0):
+    parent, bus_leaf = np.array([-1], np.int32), np.zeros(n_bus, np.int32)
+    return cases.Network(name="hand", n_bus=n_bus, frm=np.asarray(frm, np.int32), to=np.asarray(to, np.int32),
+                         R=np.asarray(R, float), L=np.asarray(L, float), C=np.asarray(C, float),
+                         src_bus=np.asarray(src_bus, np.int32), src_amp=np.asarray(amp, float),
+                         src_phase=np.asarray(phase, float), parent=parent, bus_leaf=bus_leaf, dt=dt, freq=freq)
+
+
+# --------------------------------------------------------------------------
+# G: structure (Section II: real, symmetric conductance matrix)
+# --------------------------------------------------------------------------
+
+def test_G_structure_179():
+    net = cases.net_179()
+    G = oracle.assemble_G(net)
+    assert np.array_equal(G, G.T)
+    off = G - np.diag(np.diag(G))
+    assert (off <= 0).all()
+    # each branch touches exactly 4 entries: count the off-diagonal non-zeros
+    assert np.count_nonzero(off) == 2 * net.n_branch
+    # row sums: branch terms cancel, leaving the shunt conductance 2C/dt
+    rs = G.sum(1)
+    assert np.allclose(rs, 2 * net.C / net.dt, rtol=0, atol=1e-15 * np.abs(G).max() * 8)
+    np.linalg.cholesky(G)                      # SPD (library Cholesky succeeds)
+    # the sparse assembly is the same matrix
+    Gs = oracle.sparse_G(net).toarray()
+    assert np.array_equal(Gs != 0, G != 0)
+    assert np.abs(Gs - G).max() <= 4 * np.finfo(float).eps * np.abs(G).max()
+
+
+def test_G_removed_branch_is_rank_one_change():
+    net = cases.net_179()
+    e = 17
+    alive = np.ones(net.n_branch, np.uint8)
+    alive[e] = 0
+    G = oracle.assemble_G(net)
+    Gp = oracle.assemble_G(net, alive)
+    D = G - Gp
+    a, b = net.frm[e], net.to[e]
+    nz = np.argwhere(D != 0)
+    assert sorted(map(tuple, nz)) == sorted([(a, a), (a, b), (b, a), (b, b)])
+    assert np.linalg.matrix_rank(D) == 1
+
+
+# --------------------------------------------------------------------------
+# LU solve / explicit inverse (Eq. (2)) against library routines
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 200])
+def test_lu_solve_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n)) + 0.1 * np.eye(n)     # general matrix: pivoting matters
+    b = rng.standard_normal(n)
+    x = oracle.solve(A, b)
+    xr = np.linalg.solve(A, b)
+    assert np.abs(x - xr).max() <= 1e-10 * max(1.0, np.abs(xr).max())
+
+
+def test_lu_needs_pivoting():
+    A = np.array([[0.0, 2.0, 1.0], [1.0, 0.0, 0.0], [3.0, 1.0, 0.0]])
+    b = np.array([1.0, 2.0, 3.0])
+    np.testing.assert_allclose(oracle.solve(A, b), np.linalg.solve(A, b), rtol=1e-14)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.solve(np.zeros((3, 3)), b)
+
+
+def test_solve_many_rows():
+    net = cases.net_179()
+    G = oracle.assemble_G(net)
+    B = np.random.default_rng(0).standard_normal((5, net.n_bus))
+    X = oracle.solve(G, B)
+    np.testing.assert_allclose(X, scipy.linalg.solve(G, B.T, assume_a="pos").T, rtol=1e-10, atol=0)
+
+
+def test_inverse_properties_179():
+    net = cases.net_179()
+    G = oracle.assemble_G(net)
+    Gi = oracle.inverse(G)
+    n = net.n_bus
+    kappa = np.linalg.cond(G)
+    assert np.abs(G @ Gi - np.eye(n)).max() <= 50 * kappa * np.finfo(float).eps
+    assert np.abs(Gi - Gi.T).max() <= 1e-12 * np.abs(Gi).max()
+    # G is an irreducible Stieltjes matrix (connected network): G^{-1} > 0 entrywise
+    assert Gi.min() > 0
+    np.testing.assert_allclose(Gi, np.linalg.inv(G), rtol=1e-10, atol=0)
+
+
+def test_sparse_solver_matches_dense():
+    net = cases.net_179()
+    G = oracle.assemble_G(net)
+    b = np.random.default_rng(1).standard_normal(net.n_bus)
+    x1 = oracle.sparse_solver(net)(b)
+    x2 = oracle.solve(G, b)
+    assert np.abs(x1 - x2).max() <= 1e-12 * np.abs(x2).max()
+
+
+# --------------------------------------------------------------------------
+# Time loop (Eq. (1)) against closed forms and an independent formulation
+# --------------------------------------------------------------------------
+
+def test_capacitor_only_bus_is_trapezoidal_sum():
+    """No branches: C dv/dt = u; trapezoid gives v_n = sum_k dt/(2C) (u_k + u_{k-1})."""
+    dt, C, A, ph, f = 1e-4, 3e-6, 1.7, 0.4, 60.0
+    net = _net_from(1, [], [], [], [], [C], [0], [A], [ph], dt, f)
+    V, _ = oracle.emt_run(net, 200)
+    t = np.arange(0, 201) * dt
+    u = A * np.sin(2 * np.pi * f * t + ph)
+    ref = np.cumsum(dt / (2 * C) * (u[1:] + u[:-1]))
+    np.testing.assert_allclose(V[:, 0], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def _state_space_run(net, n_steps, loss_steps=(), loss_branches=()):
+    """Independent check: trapezoidal (Tustin) rule on the state x = (bus voltages, branch currents).
+
+    C_a dv_a/dt = u_a - sum_e A[a,e] i_e ;  L_e di_e/dt = v_from - v_to - R_e i_e.
+    x_n = x_{n-1} + dt/2 (f_n(x_n) + f_{n-1}(x_{n-1})), a lost branch's current
+    is held at zero from its loss step on.  Start: x_0 = 0.
+    """
+    n, m, dt = net.n_bus, net.n_branch, net.dt
+    A = np.zeros((n, m))
+    A[net.frm, np.arange(m)] = 1.0
+    A[net.to, np.arange(m)] = -1.0
+    dead_from = np.full(m, 1 << 60)
+    for s, e in zip(loss_steps, loss_branches):
+        dead_from[e] = s
+
+    def jac(step):
+        alive = (dead_from > step).astype(float)
+        K = np.zeros((n + m, n + m))
+        K[:n, n:] = -(A * alive) / net.C[:, None]
+        K[n:, :n] = (A.T / net.L[:, None]) * alive[:, None]
+        K[n:, n:] = np.diag(-net.R / net.L * alive)
+        return K, alive
+
+    def src(step):
+        u = np.zeros(n + m)
+        t = step * dt
+        np.add.at(u, net.src_bus, net.src_amp * np.sin(2 * np.pi * net.freq * t + net.src_phase))
+        u[:n] /= net.C
+        return u
+
+    x = np.zeros(n + m)
+    out = np.zeros((n_steps, n))
+    Kp, _ = jac(0)
+    for step in range(1, n_steps + 1):
+        K, alive = jac(step)
+        rhs = x + dt / 2 * (Kp @ x + src(step - 1) + src(step))
+        M = np.eye(n + m) - dt / 2 * K
+        dead = np.where(alive == 0)[0] + n          # algebraic rows: i_e = 0
+        M[dead, :] = 0.0
+        M[dead, dead] = 1.0
+        rhs[dead] = 0.0
+        x = np.linalg.solve(M, rhs)
+        out[step - 1] = x[:n]
+        Kp = K
+    return out
+
+
+def test_matches_state_space_trapezoid_small():
+    net = cases.small_network(7, 10, seed=3)
+    V, _ = oracle.emt_run(net, 600, solver="lu")
+    ref = _state_space_run(net, 600)
+    assert np.abs(V - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_matches_state_space_trapezoid_with_line_loss():
+    net = cases.small_network(8, 12, seed=5)
+    V, _ = oracle.emt_run(net, 500, loss_steps=[137], loss_branches=[4], solver="inv")
+    ref = _state_space_run(net, 500, loss_steps=[137], loss_branches=[4])
+    assert np.abs(V - ref).max() <= 1e-9 * np.abs(ref).max()
+    # the loss visibly changes the trajectory (the check is not vacuous)
+    V0, _ = oracle.emt_run(net, 500, solver="inv")
+    assert np.abs(V0 - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_converges_to_continuous_solution_second_order():
+    """2-bus R-L-C circuit with a 60 Hz source: error vs the exact ODE solution shrinks ~4x per dt/2."""
+    R, L, C0, C1, A, ph, f = 1.0, 1e-2, 1e-3, 2e-3, 1.3, 0.7, 60.0
+    T = 0.02
+    w = 2 * np.pi * f
+    # exact: augmented linear system z = (v0, v1, i, sin, cos), z' = M z
+    M = np.array([[0, 0, -1 / C0, A / C0, 0],
+                  [0, 0, 1 / C1, 0, 0],
+                  [1 / L, -1 / L, -R / L, 0, 0],
+                  [0, 0, 0, 0, w],
+                  [0, 0, 0, -w, 0]], float)
+    z0 = np.array([0, 0, 0, np.sin(ph), np.cos(ph)])
+    exact = (scipy.linalg.expm(M * T) @ z0)[:2]
+    errs = []
+    for dt in (2e-4, 1e-4, 5e-5, 2.5e-5):
+        net = _net_from(2, [0], [1], [R], [L], [C0, C1], [0], [A], [ph], dt, f)
+        V, _ = oracle.emt_run(net, int(round(T / dt)), solver="lu")
+        errs.append(np.abs(V[-1] - exact).max())
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(ratios > 3.6) and np.all(ratios < 4.4), (errs, ratios)
+
+
+def test_discrete_charge_balance_across_loss():
+    """Summing KCL over all buses: (2/dt) sum_a C_a (v_a^n - v_a^{n-1}) = sum_a (i_in^n + i_in^{n-1})."""
+    case = cases.case_c1(n_steps=400)
+    net = case.net
+    V, _ = oracle.emt_run(net, 400, loss_steps=[150], loss_branches=[33])
+    Vp = np.vstack([np.zeros(net.n_bus), V])
+    lhs = (2 / net.dt) * ((Vp[1:] - Vp[:-1]) * net.C).sum(1)
+    t = np.arange(0, 401) * net.dt
+    u = np.array([oracle.source_current(net, tt).sum() for tt in t])
+    rhs = u[1:] + u[:-1]
+    scale = (2 / net.dt) * (np.abs(Vp[1:] - Vp[:-1]) * net.C).sum(1) + np.abs(rhs)
+    assert np.all(np.abs(lhs - rhs) <= 1e-9 * scale.max())
+
+
+def test_kcl_residual_every_step():
+    case = cases.case_c1(n_steps=200)
+    net = case.net
+    V, B = oracle.emt_run(net, 200, record_b=True, solver="inv")
+    G = oracle.assemble_G(net)
+    r = B - V @ G.T
+    assert np.abs(r).max() <= 1e-9 * np.abs(G).max() * np.abs(V).max()
+
+
+def test_solver_variants_agree_fp64_floor():
+    """LU vs explicit inverse vs sparse LU on the 179-bus network, 1000 steps, with a loss."""
+    case = cases.case_c1()
+    net = case.net
+    kw = dict(loss_steps=[400], loss_branches=[100])
+    Vi, _ = oracle.emt_run(net, 1000, solver="inv", **kw)
+    Vl, _ = oracle.emt_run(net, 1000, solver="lu", **kw)
+    Vs, _ = oracle.emt_run(net, 1000, solver="sparse", **kw)
+    peak = np.abs(Vl).max()
+    assert np.abs(Vi - Vl).max() <= 1e-11 * peak
+    assert np.abs(Vs - Vl).max() <= 1e-11 * peak
+
+
+def test_generator_is_deterministic():
+    a = cases.net_ring(8, 2)
+    b = cases.net_ring(8, 2)
+    for k in ("frm", "to", "R", "L", "C", "src_bus", "src_amp", "src_phase", "parent", "bus_leaf"):
+        assert np.array_equal(getattr(a, k), getattr(b, k))
+    c = cases.net_ring(8, 3)
+    k = 8 * cases.BASE_BRANCHES                 # copies share the topology; tie lines are drawn
+    assert not np.array_equal(a.R, c.R) and np.array_equal(a.frm[:k], c.frm[:k])
