@@ -1,0 +1,215 @@
+/*
+ * libhinv — hierarchical-inverse EMT network solver for AMD MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  "Host" arguments are CPU memory
+ * that the library copies during the call (the caller may free them on
+ * return).  "Device" arguments are HIP device memory owned by the caller.
+ * A stream argument is a hipStream_t passed as void* (NULL = the null
+ * stream).  Every call returns a hinv_status; hinv_last_error() gives a
+ * message for the last non-OK status of the calling thread.  No call throws
+ * or aborts across this boundary.  One handle must not be used from two
+ * threads at once.
+ *
+ * The paper (Zhang et al., "An Efficient Network Solver for EMT Simulation
+ * ... Hierarchical Inverse Computation and Modification") defines:
+ *   - the network equation G v(t) = i_in(t) + i_his(t - dt), real values
+ *     (Section II, Eq. (1)); its inverse-based solution v = G^{-1} i (Eq. (2));
+ *   - a partition tree whose nodes own bus sets, leaves being small
+ *     sub-networks (Section III.B, Fig. 2-3); the inverse of each node's
+ *     diagonal block is built from its children's inverses and a low-rank
+ *     coupling H = h_l h_r^T over the cut lines (Eq. (9), Algorithm 1);
+ *   - the update of G^{-1} when a line between buses i and j changes
+ *     (Section IV, Algorithm 2).
+ * This library keeps that structure but stores the exact inverse: at each
+ * tree node the coupling level is a Woodbury capacitance matrix
+ * S = C + U^T B^{-1} U over the cut lines (the paper's M of Eq. (8)-(9) is
+ * this form with S truncated to C).  A line change is applied as a
+ * Sherman-Morrison-Woodbury low-rank correction of the stored inverse.
+ */
+#ifndef HINV_H
+#define HINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HINV_OK = 0,
+    HINV_E_INVALID = 1,        /* bad argument; nothing was launched */
+    HINV_E_NOT_SPD = 2,        /* a leaf block is not positive definite, or a change makes G indefinite */
+    HINV_E_NO_MEMORY = 3,      /* workspace smaller than hinv_workspace_size / emt_workspace_size */
+    HINV_E_DEVICE = 4,         /* a HIP runtime call failed */
+    HINV_E_NO_SUCH_LINE = 5,   /* the line to change does not exist (or has less conductance) */
+    HINV_E_NO_CONVERGENCE = 6, /* iterative refinement did not reach rel_tol in max_refine steps */
+    HINV_E_RANK_LIMIT = 7,     /* more line changes than max_mod_rank */
+    HINV_E_SINGULAR = 8        /* a coupling (capacitance) matrix is singular */
+} hinv_status;
+
+/* Storage / arithmetic precision of the stored inverse blocks used by the
+ * per-step apply.  FP64 applies in FP64.  The others apply in that storage
+ * precision with FP32 accumulation and recover FP64 accuracy by iterative
+ * refinement against the sparse G in FP64. */
+typedef enum { HINV_FP64 = 0, HINV_FP32 = 1, HINV_BF16 = 2, HINV_FP8 = 3 } hinv_precision;
+
+typedef struct hinv_ctx* hinv_handle;
+typedef struct emt_ctx* emt_handle;
+
+/* Symmetric sparse matrix, full pattern (both triangles), 0-based, FP64,
+ * column indices sorted within a row.  Host memory. */
+typedef struct {
+    int32_t n;
+    const int32_t* row_ptr;   /* [n+1] */
+    const int32_t* col_idx;   /* [row_ptr[n]] */
+    const double* val;        /* [row_ptr[n]] */
+} hinv_csr;
+
+/* Partition tree (Section III.B).  parent[k] is the parent of node k, -1 for
+ * the single root; a node's children are the nodes naming it as parent, in
+ * index order.  bus_leaf[a] is the leaf that owns bus a; every leaf owns at
+ * least one bus and at most HINV_MAX_LEAF buses; internal nodes own the union
+ * of their children.  Host memory. */
+typedef struct {
+    int32_t n_nodes;
+    const int32_t* parent;    /* [n_nodes] */
+    const int32_t* bus_leaf;  /* [n] */
+} hinv_tree;
+
+#define HINV_MAX_LEAF 128
+
+typedef struct {
+    int32_t prec;          /* hinv_precision of the per-step apply */
+    double rel_tol;        /* refinement stop: ||dv||_inf <= rel_tol * ||v||_inf (mixed precision only) */
+    int32_t max_refine;    /* refinement iterations after the first apply (mixed precision only) */
+    int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
+    int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
+} hinv_options;
+
+typedef struct {
+    int64_t n, n_leaves, n_internal, n_levels, n_cols;
+    int64_t leaf_entries, z_entries, s_entries;   /* stored FP64 entries of each kind */
+    int64_t max_leaf, max_cols;                   /* largest leaf, largest coupling level (2 x cut lines) */
+} hinv_info_t;
+
+/* ---- Hierarchical inverse of a conductance matrix ---------------------- */
+
+/* Device workspace bytes hinv_build needs for this matrix, tree and options.
+ * Validates the inputs (symmetry, index ranges, tree shape, leaf sizes). */
+hinv_status hinv_workspace_size(const hinv_csr* G, const hinv_tree* tree, const hinv_options* opt,
+                                size_t* bytes);
+
+/* Build the exact hierarchical inverse of G (Algorithm 1, exact coupling
+ * levels) in FP64 on the GPU: leaf-block inverses, then per tree level the
+ * panels Z = B^{-1} U and the inverses of the capacitance matrices S; then
+ * the low-precision copies.  d_ws: device workspace of ws_bytes bytes
+ * (>= hinv_workspace_size), owned by the caller, must outlive the handle and
+ * must not be shared with another handle.  Synchronises the stream before
+ * returning so that HINV_E_NOT_SPD / HINV_E_SINGULAR can be reported. */
+hinv_status hinv_build(const hinv_csr* G, const hinv_tree* tree, const hinv_options* opt,
+                       void* d_ws, size_t ws_bytes, void* stream, hinv_handle* out);
+
+/* Apply a change of delta_g siemens to the line between buses a and b
+ * (b = -1: between a and ground), i.e. G <- G + delta_g (e_a - e_b)(e_a - e_b)^T
+ * (Section IV; the paper's "loss of a line" is delta_g = -g).  The stored
+ * inverse gets a rank-1 Sherman-Morrison-Woodbury correction: u = G^{-1} w is
+ * computed by one FP64 apply and the small capacitance matrix is inverted in
+ * FP64.  Later solves use the changed G (also in refinement residuals).
+ * Errors: HINV_E_INVALID (indices), HINV_E_NO_SUCH_LINE (delta_g < 0 larger
+ * than the conductance between a and b), HINV_E_RANK_LIMIT, HINV_E_NOT_SPD
+ * (the change makes G indefinite).  Synchronises the stream. */
+hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream);
+
+/* v = G^{-1} i for nrhs right-hand sides (Eq. (2)).  d_i, d_v: device FP64,
+ * column k at offset k*ld, rows in the caller's bus order; d_i and d_v may
+ * not overlap.  nrhs <= opt.max_nrhs, ld >= n.  Asynchronous on the stream;
+ * device-side failures surface through hinv_sync_status. */
+hinv_status hinv_solve(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld,
+                       void* stream);
+
+/* After the caller has synchronised the stream: HINV_E_NO_CONVERGENCE or
+ * HINV_E_NOT_SPD if a kernel flagged it since the last call, else HINV_OK.
+ * Clears the flags. */
+hinv_status hinv_sync_status(hinv_handle h);
+
+hinv_status hinv_get_info(hinv_handle h, hinv_info_t* out);
+hinv_status hinv_destroy(hinv_handle h);
+
+/* ---- EMT time stepping (Section II, Eq. (1)) ---------------------------- */
+
+/* Network: branch e is a series R[e]-L[e] between buses from[e] and to[e];
+ * bus a has a shunt capacitance C[a] to ground; n_src current sources
+ * amp*sin(2*pi*freq*t + phase) inject into src_bus.  Trapezoidal companion
+ * models with step dt.  Host memory. */
+typedef struct {
+    int32_t n_bus, n_branch;
+    const int32_t* from;
+    const int32_t* to;
+    const double* R;
+    const double* L;
+    const double* C;
+    double dt;
+    int32_t n_src;
+    const int32_t* src_bus;
+    const double* amp;
+    const double* phase;
+    double freq;
+} emt_network;
+
+/* Line-loss schedule for n_cases cases sharing one network: case k loses
+ * branches loss_branch[loss_ptr[k] .. loss_ptr[k+1]) from steps
+ * loss_step[...] on (step >= 1).  A lost branch carries no current from that
+ * step on (it is removed from G and its history is dropped).  NULL pointers
+ * with n_cases >= 1 mean no scheduled losses.  Host memory. */
+typedef struct {
+    int32_t n_cases;
+    const int32_t* loss_ptr;     /* [n_cases+1] */
+    const int32_t* loss_step;    /* [loss_ptr[n_cases]] */
+    const int32_t* loss_branch;  /* [loss_ptr[n_cases]] */
+} emt_cases;
+
+/* The network's nodal conductance matrix G (trapezoidal companions:
+ * g = 1/(R + 2L/dt) per branch, 2C/dt per shunt; Section II) as the full
+ * symmetric CSR that hinv_build takes, in the network's bus order.  Call with
+ * row_ptr == NULL to get *nnz only; otherwise row_ptr [n_bus+1], col_idx and
+ * val [*nnz] (host memory, caller-owned) are filled. */
+hinv_status emt_network_csr(const emt_network* net, int32_t* row_ptr, int32_t* col_idx, double* val, int64_t* nnz);
+
+hinv_status emt_workspace_size(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
+                               const emt_cases* cases, size_t* bytes);
+
+/* Build the hierarchical inverse of the network's G, the SMW factors of every
+ * scheduled loss, and the initial state (v = 0, branch currents 0, capacitor
+ * currents consistent with KCL at t = 0).  The next step is step 1.
+ * Synchronises the stream. */
+hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
+                       const emt_cases* cases, void* d_ws, size_t ws_bytes, void* stream, emt_handle* out);
+
+/* Advance every case by n_steps steps: at step n, solve G_n v_n = i_in(t_n) + i_his
+ * (t_n = n*dt) and update the trapezoidal history currents.  If d_v_record
+ * is not NULL, v of case k at the j-th step of this call (bus order of the
+ * network) is written to d_v_record[(j*n_cases + k)*n_bus + a]; d_b_record
+ * likewise receives the right-hand side.  Asynchronous on the stream. */
+hinv_status emt_step(emt_handle c, int32_t n_steps, double* d_v_record, double* d_b_record, void* stream);
+
+/* Lose branch `branch` of case `case_idx` from the next step on (Algorithm 2's
+ * situation, handled by a rank-1 SMW correction).  Synchronises the stream. */
+hinv_status emt_lose_line(emt_handle c, int32_t case_idx, int32_t branch, void* stream);
+
+/* Index of the next step to be computed (1 after emt_create). */
+hinv_status emt_get_step(emt_handle c, int64_t* step);
+
+/* Refinement statistics since emt_create (mixed precision): total applies,
+ * largest final ||dv||/||v|| seen.  Synchronises nothing; call after the
+ * stream is idle. */
+hinv_status emt_get_stats(emt_handle c, int64_t* applies, double* max_rel_update);
+
+hinv_status emt_destroy(emt_handle c);
+
+const char* hinv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1062 @@
+// Host side of libhinv: argument validation, the partition-tree bookkeeping
+// (bus renumbering, cut lines and their coupling columns, storage layout),
+// workspace carving, and the C ABI declared in include/hinv.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hinv_internal.h"
+
+using namespace hinv;
+
+namespace {
+
+thread_local std::string g_err;
+
+hinv_status fail(hinv_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(HINV_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+// Bump allocator over the caller's workspace; with base == nullptr it only measures.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(int64_t count)
+    {
+        off = (off + kAlign - 1) / kAlign * kAlign;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)(count > 0 ? count : 1);
+        return p;
+    }
+};
+
+int64_t align_elems(int64_t x) { return (x + 31) / 32 * 32; }
+
+// ---------------------------------------------------------------------------
+// Plan: everything about the hierarchy that depends only on G's pattern/values
+// and the tree, computed on the host.
+struct Plan {
+    int n = 0, n_nodes = 0, n_levels = 0, anc_stride = 1;
+    std::vector<int> perm, iperm;
+    std::vector<int> leaf_lo, leaf_n, leaf_anc, row_leaf;
+    std::vector<int64_t> leaf_off;
+    std::vector<int> node_lo, node_n, node_m, node_col0, node_pan0, node_npan, node_level;
+    std::vector<int64_t> node_soff;
+    std::vector<int> pan_lo, pan_n, pan_col0, pan_m;
+    std::vector<int64_t> pan_zoff;
+    std::vector<int> col_row, col_partner, col_pan;
+    std::vector<double> col_w, col_sign;
+    std::vector<int> lvl_node, lvl_pan, lvl_col;
+    std::vector<LevelHost> lv;
+    std::vector<int> rp, ci;
+    std::vector<double> cv;
+    int64_t leaf_entries = 0, z_entries = 0, s_entries = 0;
+    int max_cols = 0, max_pan_rows = 0, max_leaf = 0;
+};
+
+hinv_status check_csr(const hinv_csr* G)
+{
+    if (!G) return fail(HINV_E_INVALID, "G is NULL");
+    const int n = G->n;
+    if (n < 1) return fail(HINV_E_INVALID, "n = %d < 1", n);
+    if (!G->row_ptr || !G->col_idx || !G->val) return fail(HINV_E_INVALID, "CSR arrays must not be NULL");
+    if (G->row_ptr[0] != 0) return fail(HINV_E_INVALID, "row_ptr[0] != 0");
+    for (int i = 0; i < n; ++i) {
+        if (G->row_ptr[i + 1] < G->row_ptr[i]) return fail(HINV_E_INVALID, "row_ptr not non-decreasing at %d", i);
+        bool diag = false;
+        for (int e = G->row_ptr[i]; e < G->row_ptr[i + 1]; ++e) {
+            const int c = G->col_idx[e];
+            if (c < 0 || c >= n) return fail(HINV_E_INVALID, "column index %d out of range in row %d", c, i);
+            if (e > G->row_ptr[i] && G->col_idx[e - 1] >= c)
+                return fail(HINV_E_INVALID, "columns of row %d not strictly increasing", i);
+            if (!isfinite(G->val[e])) return fail(HINV_E_INVALID, "non-finite value in row %d", i);
+            if (c == i) {
+                diag = true;
+                if (!(G->val[e] > 0.0)) return fail(HINV_E_NOT_SPD, "diagonal G[%d][%d] = %g is not positive", i, i, G->val[e]);
+            } else {
+                const int* b = G->col_idx + G->row_ptr[c];
+                const int* en = G->col_idx + G->row_ptr[c + 1];
+                const int* f = std::lower_bound(b, en, i);
+                if (f == en || *f != i) return fail(HINV_E_INVALID, "G is not symmetric: (%d,%d) has no mirror", i, c);
+                if (G->val[G->row_ptr[c] + (f - b)] != G->val[e])
+                    return fail(HINV_E_INVALID, "G is not symmetric: G[%d][%d] != G[%d][%d]", i, c, c, i);
+            }
+        }
+        if (!diag) return fail(HINV_E_INVALID, "row %d has no diagonal entry", i);
+    }
+    return HINV_OK;
+}
+
+hinv_status make_plan(const hinv_csr* G, const hinv_tree* T, Plan& P)
+{
+    hinv_status st = check_csr(G);
+    if (st != HINV_OK) return st;
+    if (!T || !T->parent || !T->bus_leaf || T->n_nodes < 1) return fail(HINV_E_INVALID, "tree is missing or empty");
+    const int n = G->n, nn = T->n_nodes;
+    P.n = n;
+    P.n_nodes = nn;
+    std::vector<std::vector<int>> children(nn);
+    int root = -1;
+    for (int k = 0; k < nn; ++k) {
+        const int p = T->parent[k];
+        if (p == -1) {
+            if (root >= 0) return fail(HINV_E_INVALID, "tree has two roots (%d and %d)", root, k);
+            root = k;
+        } else if (p < 0 || p >= nn || p == k) {
+            return fail(HINV_E_INVALID, "parent[%d] = %d is invalid", k, p);
+        } else {
+            children[p].push_back(k);
+        }
+    }
+    if (root < 0) return fail(HINV_E_INVALID, "tree has no root");
+    std::vector<int> depth(nn, -1);
+    // depth by walking up (bounded: a cycle never reaches the root)
+    for (int k = 0; k < nn; ++k) {
+        int d = 0, x = k;
+        while (x != root) {
+            x = T->parent[x];
+            if (++d > nn) return fail(HINV_E_INVALID, "tree has a cycle through node %d", k);
+        }
+        depth[k] = d;
+    }
+    std::vector<std::vector<int>> leaf_buses(nn);
+    for (int a = 0; a < n; ++a) {
+        const int l = T->bus_leaf[a];
+        if (l < 0 || l >= nn) return fail(HINV_E_INVALID, "bus_leaf[%d] = %d out of range", a, l);
+        if (!children[l].empty()) return fail(HINV_E_INVALID, "bus %d is assigned to internal node %d", a, l);
+        leaf_buses[l].push_back(a);
+    }
+    // depth-first order (children in index order); post-order for ranges and heights
+    std::vector<int> order, stack{root};
+    std::vector<int> leaf_of_node(nn, -1);
+    while (!stack.empty()) {
+        const int x = stack.back();
+        stack.pop_back();
+        order.push_back(x);
+        for (int i = (int)children[x].size() - 1; i >= 0; --i) stack.push_back(children[x][i]);
+    }
+    std::vector<int> lo(nn, 0), hi(nn, 0), height(nn, 0);
+    P.perm.clear();
+    for (int x : order) {
+        if (children[x].empty()) {
+            if (leaf_buses[x].empty()) return fail(HINV_E_INVALID, "leaf %d owns no bus", x);
+            if ((int)leaf_buses[x].size() > kMaxLeaf)
+                return fail(HINV_E_INVALID, "leaf %d owns %d buses (limit %d)", x, (int)leaf_buses[x].size(), kMaxLeaf);
+            leaf_of_node[x] = (int)P.leaf_lo.size();
+            lo[x] = (int)P.perm.size();
+            for (int a : leaf_buses[x]) P.perm.push_back(a);
+            hi[x] = (int)P.perm.size();
+            P.leaf_lo.push_back(lo[x]);
+            P.leaf_n.push_back(hi[x] - lo[x]);
+        }
+    }
+    if ((int)P.perm.size() != n) return fail(HINV_E_INVALID, "tree leaves do not cover all buses");
+    for (int i = (int)order.size() - 1; i >= 0; --i) {
+        const int x = order[i];
+        if (children[x].empty()) continue;
+        lo[x] = lo[children[x].front()];
+        hi[x] = hi[children[x].back()];
+        int h = 0;
+        for (int c : children[x]) h = std::max(h, height[c] + 1);
+        height[x] = h;
+    }
+    P.iperm.assign(n, 0);
+    for (int r = 0; r < n; ++r) P.iperm[P.perm[r]] = r;
+    P.n_levels = height[root];
+    // internal nodes ordered by (height, id)
+    std::vector<int> internal;
+    for (int k = 0; k < nn; ++k)
+        if (!children[k].empty()) internal.push_back(k);
+    std::stable_sort(internal.begin(), internal.end(), [&](int x, int y) { return height[x] < height[y]; });
+    std::vector<int> int_idx(nn, -1);
+    for (size_t i = 0; i < internal.size(); ++i) int_idx[internal[i]] = (int)i;
+    // leaves: offsets, ancestors, row -> leaf
+    const int L = (int)P.leaf_lo.size();
+    int maxdepth = 1;
+    for (int k = 0; k < nn; ++k) maxdepth = std::max(maxdepth, depth[k]);
+    P.anc_stride = maxdepth;
+    P.leaf_anc.assign((size_t)L * maxdepth, -1);
+    P.row_leaf.assign(n, 0);
+    P.leaf_off.resize(L);
+    int64_t off = 0;
+    for (int x : order) {
+        const int l = leaf_of_node[x];
+        if (l < 0) continue;
+        P.leaf_off[l] = off;
+        off += align_elems((int64_t)P.leaf_n[l] * P.leaf_n[l]);
+        P.max_leaf = std::max(P.max_leaf, P.leaf_n[l]);
+        for (int r = P.leaf_lo[l]; r < P.leaf_lo[l] + P.leaf_n[l]; ++r) P.row_leaf[r] = l;
+        int y = x, d = 0;
+        while (y != root) {
+            y = T->parent[y];
+            P.leaf_anc[(size_t)l * maxdepth + d++] = int_idx[y];
+        }
+    }
+    P.leaf_entries = off;
+    // node of each leaf index (tree node id)
+    std::vector<int> leaf_node(L);
+    for (int k = 0; k < nn; ++k)
+        if (leaf_of_node[k] >= 0) leaf_node[leaf_of_node[k]] = k;
+    // permuted CSR
+    P.rp.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+        const int a = P.perm[r];
+        P.rp[r + 1] = P.rp[r] + (G->row_ptr[a + 1] - G->row_ptr[a]);
+    }
+    P.ci.resize(P.rp[n]);
+    P.cv.resize(P.rp[n]);
+    {
+        std::vector<std::pair<int, double>> row;
+        for (int r = 0; r < n; ++r) {
+            const int a = P.perm[r];
+            row.clear();
+            for (int e = G->row_ptr[a]; e < G->row_ptr[a + 1]; ++e) row.push_back({P.iperm[G->col_idx[e]], G->val[e]});
+            std::sort(row.begin(), row.end(), [](const std::pair<int, double>& x, const std::pair<int, double>& y) {
+                return x.first < y.first;
+            });
+            for (size_t q = 0; q < row.size(); ++q) {
+                P.ci[P.rp[r] + q] = row[q].first;
+                P.cv[P.rp[r] + q] = row[q].second;
+            }
+        }
+    }
+    // cut lines: entry (r, c), r < c, in different leaves, belongs to their lowest common ancestor
+    struct Cut { int r, c, cr, cc; double val; };
+    std::vector<std::vector<Cut>> cuts(internal.size());
+    for (int r = 0; r < n; ++r) {
+        for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
+            const int c = P.ci[e];
+            if (c <= r || P.cv[e] == 0.0) continue;
+            int x = leaf_node[P.row_leaf[r]], y = leaf_node[P.row_leaf[c]];
+            if (x == y) continue;
+            int px = -1, py = -1;
+            while (depth[x] > depth[y]) { px = x; x = T->parent[x]; }
+            while (depth[y] > depth[x]) { py = y; y = T->parent[y]; }
+            while (x != y) { px = x; x = T->parent[x]; py = y; y = T->parent[y]; }
+            cuts[int_idx[x]].push_back({r, c, px, py, P.cv[e]});
+        }
+    }
+    // columns and panels, node by node in level order
+    const int NI = (int)internal.size();
+    P.node_lo.resize(NI); P.node_n.resize(NI); P.node_m.resize(NI); P.node_col0.resize(NI);
+    P.node_pan0.resize(NI); P.node_npan.resize(NI); P.node_level.resize(NI); P.node_soff.resize(NI);
+    P.lvl_node.assign(P.n_levels + 1, 0);
+    P.lvl_pan.assign(P.n_levels + 1, 0);
+    P.lvl_col.assign(P.n_levels + 1, 0);
+    P.lv.assign(P.n_levels, LevelHost{0, 0, 0, 0, 0});
+    int64_t soff = 0, zoff = 0;
+    for (int i = 0; i < NI; ++i) {
+        const int t = internal[i];
+        const int h = height[t];
+        P.node_lo[i] = lo[t];
+        P.node_n[i] = hi[t] - lo[t];
+        P.node_level[i] = h;
+        P.node_col0[i] = (int)P.col_row.size();
+        P.node_pan0[i] = (int)P.pan_lo.size();
+        const std::vector<Cut>& cs = cuts[i];
+        const int m = 2 * (int)cs.size();
+        P.node_m[i] = m;
+        P.node_soff[i] = soff;
+        soff += align_elems((int64_t)m * m);
+        // endpoint columns grouped by child
+        std::vector<int> col_of_end(2 * cs.size(), -1);
+        for (int c : children[t]) {
+            const int pan = (int)P.pan_lo.size();
+            const int col0 = (int)P.col_row.size();
+            for (size_t j = 0; j < cs.size(); ++j) {
+                if (cs[j].cr == c) { col_of_end[2 * j] = (int)P.col_row.size(); P.col_row.push_back(cs[j].r); }
+                if (cs[j].cc == c) { col_of_end[2 * j + 1] = (int)P.col_row.size(); P.col_row.push_back(cs[j].c); }
+            }
+            const int pm = (int)P.col_row.size() - col0;
+            if (pm == 0) continue;
+            P.pan_lo.push_back(lo[c]);
+            P.pan_n.push_back(hi[c] - lo[c]);
+            P.pan_col0.push_back(col0);
+            P.pan_m.push_back(pm);
+            P.pan_zoff.push_back(zoff);
+            zoff += align_elems((int64_t)(hi[c] - lo[c]) * pm);
+            for (int q = 0; q < pm; ++q) P.col_pan.push_back(pan);
+            P.max_pan_rows = std::max(P.max_pan_rows, hi[c] - lo[c]);
+            P.lv[h - 1].max_pan_rows = std::max(P.lv[h - 1].max_pan_rows, hi[c] - lo[c]);
+        }
+        P.col_w.resize(P.col_row.size());
+        P.col_sign.resize(P.col_row.size());
+        P.col_partner.resize(P.col_row.size());
+        for (size_t j = 0; j < cs.size(); ++j) {
+            const int ca = col_of_end[2 * j], cb = col_of_end[2 * j + 1];
+            const double w = sqrt(fabs(cs[j].val)), sg = cs[j].val > 0 ? 1.0 : -1.0;
+            P.col_w[ca] = w; P.col_w[cb] = w;
+            P.col_sign[ca] = sg; P.col_sign[cb] = sg;
+            P.col_partner[ca] = cb; P.col_partner[cb] = ca;
+        }
+        P.node_npan[i] = (int)P.pan_lo.size() - P.node_pan0[i];
+        P.max_cols = std::max(P.max_cols, m);
+        LevelHost& Lh = P.lv[h - 1];
+        Lh.nnodes += 1;
+        Lh.npan += P.node_npan[i];
+        Lh.ncols += m;
+        Lh.max_m = std::max(Lh.max_m, m);
+        P.lvl_node[h] = i + 1;
+        P.lvl_pan[h] = (int)P.pan_lo.size();
+        P.lvl_col[h] = (int)P.col_row.size();
+    }
+    for (int h = 1; h <= P.n_levels; ++h) {   // empty levels inherit the previous end
+        if (P.lvl_node[h] < P.lvl_node[h - 1]) P.lvl_node[h] = P.lvl_node[h - 1];
+        if (P.lvl_pan[h] < P.lvl_pan[h - 1]) P.lvl_pan[h] = P.lvl_pan[h - 1];
+        if (P.lvl_col[h] < P.lvl_col[h - 1]) P.lvl_col[h] = P.lvl_col[h - 1];
+    }
+    P.z_entries = zoff;
+    P.s_entries = soff;
+    if (P.max_cols > 4096) return fail(HINV_E_INVALID, "a tree node has %d coupling columns (limit 4096)", P.max_cols);
+    return HINV_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct hinv_ctx {
+    Plan P;
+    hinv_options opt{};
+    HierDev H{};
+    ModDev M{};            // one change set (hinv_modify_line)
+    int* d_perm = nullptr;
+    int* d_flags = nullptr;
+    double* colbuf = nullptr;
+    int* ipiv = nullptr;
+    double *X = nullptr, *Xo = nullptr, *D = nullptr, *Rv = nullptr, *Y = nullptr;
+    unsigned long long* stats = nullptr;
+    // change-set host mirror
+    std::vector<int> mod_a, mod_b, mod_act;
+    std::vector<double> mod_dg;
+    int* m_count = nullptr; int* m_a = nullptr; int* m_b = nullptr; int* m_act = nullptr; double* m_dg = nullptr;
+    int64_t applies = 0;
+};
+
+namespace {
+
+// Carve the hierarchy's device storage (base == nullptr: measure only).
+void carve_hier(hinv_ctx& c, Arena& A, int n_sets, int R, int max_nrhs)
+{
+    const Plan& P = c.P;
+    HierDev& H = c.H;
+    const int L = (int)P.leaf_lo.size(), NI = (int)P.node_lo.size(), NP = (int)P.pan_lo.size();
+    const int NC = (int)P.col_row.size();
+    H.n = P.n; H.n_leaves = L; H.n_internal = NI; H.n_levels = P.n_levels; H.n_cols = NC;
+    H.anc_stride = P.anc_stride; H.max_cols = P.max_cols; H.max_pan_rows = P.max_pan_rows;
+    c.d_perm = A.take<int>(P.n);
+    H.leaf_lo = A.take<int>(L); H.leaf_n = A.take<int>(L); H.leaf_off = A.take<int64_t>(L);
+    H.leaf_anc = A.take<int>((int64_t)L * P.anc_stride); H.row_leaf = A.take<int>(P.n);
+    H.node_lo = A.take<int>(NI); H.node_n = A.take<int>(NI); H.node_m = A.take<int>(NI);
+    H.node_col0 = A.take<int>(NI); H.node_soff = A.take<int64_t>(NI); H.node_pan0 = A.take<int>(NI);
+    H.node_npan = A.take<int>(NI); H.node_level = A.take<int>(NI);
+    H.pan_lo = A.take<int>(NP); H.pan_n = A.take<int>(NP); H.pan_col0 = A.take<int>(NP); H.pan_m = A.take<int>(NP);
+    H.pan_zoff = A.take<int64_t>(NP);
+    H.col_row = A.take<int>(NC); H.col_w = A.take<double>(NC); H.col_partner = A.take<int>(NC);
+    H.col_sign = A.take<double>(NC); H.col_pan = A.take<int>(NC);
+    H.lvl_node = A.take<int>(P.n_levels + 1); H.lvl_pan = A.take<int>(P.n_levels + 1);
+    H.lvl_col = A.take<int>(P.n_levels + 1);
+    H.rp = A.take<int>(P.n + 1); H.ci = A.take<int>(P.rp.empty() ? 1 : P.rp[P.n]);
+    H.cv = A.take<double>(P.rp.empty() ? 1 : P.rp[P.n]);
+    H.blk = A.take<double>(P.leaf_entries); H.Z = A.take<double>(P.z_entries); H.Sinv = A.take<double>(P.s_entries);
+    if (c.opt.prec != HINV_FP64) {
+        H.blk32 = A.take<float>(P.leaf_entries); H.Z32 = A.take<float>(P.z_entries);
+        H.Sinv32 = A.take<float>(P.s_entries);
+    } else {
+        H.blk32 = H.Z32 = H.Sinv32 = nullptr;
+    }
+    c.colbuf = A.take<double>(NC);
+    c.ipiv = A.take<int>(NC);
+    c.d_flags = A.take<int>(4);
+    c.X = A.take<double>((int64_t)P.n * max_nrhs);
+    c.Xo = A.take<double>((int64_t)P.n * max_nrhs);
+    c.D = A.take<double>((int64_t)P.n * max_nrhs);
+    c.Rv = A.take<double>((int64_t)P.n * max_nrhs);
+    c.Y = A.take<double>((int64_t)NC * max_nrhs);
+    c.stats = A.take<unsigned long long>((int64_t)max_nrhs);
+    // change sets
+    ModDev& M = c.M;
+    M.n_sets = n_sets; M.R = R; M.n = P.n;
+    c.m_count = A.take<int>(n_sets);
+    c.m_a = A.take<int>((int64_t)n_sets * R); c.m_b = A.take<int>((int64_t)n_sets * R);
+    c.m_act = A.take<int>((int64_t)n_sets * R); c.m_dg = A.take<double>((int64_t)n_sets * R);
+    M.count = c.m_count; M.a = c.m_a; M.b = c.m_b; M.act = c.m_act; M.dg = c.m_dg;
+    M.U = A.take<double>((int64_t)n_sets * R * P.n);
+    M.U32 = (c.opt.prec != HINV_FP64) ? A.take<float>((int64_t)n_sets * R * P.n) : nullptr;
+    M.Cinv = A.take<double>((int64_t)n_sets * R * R * R);
+}
+
+template <typename T>
+hipError_t up(const T* dst, const std::vector<T>& src, hipStream_t s)
+{
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync((void*)dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s);
+}
+
+hinv_status check_options(const hinv_options* o, int min_nrhs)
+{
+    if (!o) return fail(HINV_E_INVALID, "options are NULL");
+    if (o->prec < HINV_FP64 || o->prec > HINV_FP8) return fail(HINV_E_INVALID, "unknown precision %d", o->prec);
+    if (o->prec == HINV_BF16 || o->prec == HINV_FP8)
+        return fail(HINV_E_INVALID, "precision %d is not available in this build", o->prec);
+    if (o->max_mod_rank < 0 || o->max_mod_rank > kMaxModRank)
+        return fail(HINV_E_INVALID, "max_mod_rank %d outside 0..%d", o->max_mod_rank, kMaxModRank);
+    if (o->max_nrhs < min_nrhs) return fail(HINV_E_INVALID, "max_nrhs %d < %d", o->max_nrhs, min_nrhs);
+    if (o->prec != HINV_FP64 && (o->max_refine < 0 || o->max_refine > 64))
+        return fail(HINV_E_INVALID, "max_refine %d outside 0..64", o->max_refine);
+    return HINV_OK;
+}
+
+// Upload the plan and run the FP64 build (leaf inverses, then per level Z and S^{-1}).
+hinv_status build_device(hinv_ctx& c, hipStream_t s)
+{
+    const Plan& P = c.P;
+    HierDev& H = c.H;
+    HIP_TRY(up(c.d_perm, P.perm, s));
+    HIP_TRY(up(H.leaf_lo, P.leaf_lo, s)); HIP_TRY(up(H.leaf_n, P.leaf_n, s)); HIP_TRY(up(H.leaf_off, P.leaf_off, s));
+    HIP_TRY(up(H.leaf_anc, P.leaf_anc, s)); HIP_TRY(up(H.row_leaf, P.row_leaf, s));
+    HIP_TRY(up(H.node_lo, P.node_lo, s)); HIP_TRY(up(H.node_n, P.node_n, s)); HIP_TRY(up(H.node_m, P.node_m, s));
+    HIP_TRY(up(H.node_col0, P.node_col0, s)); HIP_TRY(up(H.node_soff, P.node_soff, s));
+    HIP_TRY(up(H.node_pan0, P.node_pan0, s)); HIP_TRY(up(H.node_npan, P.node_npan, s));
+    HIP_TRY(up(H.node_level, P.node_level, s));
+    HIP_TRY(up(H.pan_lo, P.pan_lo, s)); HIP_TRY(up(H.pan_n, P.pan_n, s)); HIP_TRY(up(H.pan_col0, P.pan_col0, s));
+    HIP_TRY(up(H.pan_m, P.pan_m, s)); HIP_TRY(up(H.pan_zoff, P.pan_zoff, s));
+    HIP_TRY(up(H.col_row, P.col_row, s)); HIP_TRY(up(H.col_w, P.col_w, s)); HIP_TRY(up(H.col_partner, P.col_partner, s));
+    HIP_TRY(up(H.col_sign, P.col_sign, s)); HIP_TRY(up(H.col_pan, P.col_pan, s));
+    HIP_TRY(up(H.lvl_node, P.lvl_node, s)); HIP_TRY(up(H.lvl_pan, P.lvl_pan, s)); HIP_TRY(up(H.lvl_col, P.lvl_col, s));
+    HIP_TRY(up(H.rp, P.rp, s)); HIP_TRY(up(H.ci, P.ci, s)); HIP_TRY(up(H.cv, P.cv, s));
+    HIP_TRY(hipMemsetAsync(c.d_flags, 0, 4 * sizeof(int), s));
+    HIP_TRY(hipMemsetAsync((void*)c.M.count, 0, sizeof(int) * c.M.n_sets, s));
+    HIP_TRY(hipMemsetAsync(c.stats, 0, sizeof(unsigned long long) * c.opt.max_nrhs, s));
+    launch_leaf_inverse(H, c.d_flags, s);
+    for (int l = 1; l <= P.n_levels; ++l) {
+        const LevelHost& L = P.lv[l - 1];
+        if (L.nnodes == 0 || L.ncols == 0) continue;
+        launch_build_z(H, l, L.ncols, s);
+        launch_fill_s(H, l, L.nnodes, s);
+        launch_gj_level(H, l, L.nnodes, L.max_m, c.colbuf, c.ipiv, c.d_flags, s);
+    }
+    if (c.opt.prec != HINV_FP64) {
+        launch_to_f32(H.blk, H.blk32, P.leaf_entries, s);
+        launch_to_f32(H.Z, H.Z32, P.z_entries, s);
+        launch_to_f32(H.Sinv, H.Sinv32, P.s_entries, s);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    int flags = 0;
+    HIP_TRY(hipMemcpy(&flags, c.d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags & kFlagNotSPD) return fail(HINV_E_NOT_SPD, "a leaf block of G is not positive definite");
+    if (flags & kFlagSingular) return fail(HINV_E_SINGULAR, "a coupling capacitance matrix is singular");
+    return HINV_OK;
+}
+
+// v = P x for nrhs columns already in the new order (X -> out), in the apply
+// precision, including the active line changes of sets set0.. .
+void precond(hinv_ctx& c, int prec, const double* X, double* out, int nrhs, int set_stride, const int64_t* step,
+             hipStream_t s)
+{
+    launch_apply(c.H, c.P.lv.data(), prec, X, out, c.Y, nrhs, s);
+    launch_smw_apply(c.M, prec, out, nrhs, 0, set_stride, step, s);
+}
+
+// Full solve in the new order: FP64 apply, or low-precision apply + FP64
+// refinement.  set_stride 0: every column uses change set 0; 1: column k uses set k.
+void solve_new_order(hinv_ctx& c, const double* B, double* V, int nrhs, int set_stride, const int64_t* step,
+                     hipStream_t s)
+{
+    if (c.opt.prec == HINV_FP64) {
+        precond(c, HINV_FP64, B, V, nrhs, set_stride, step, s);
+        c.applies += nrhs;
+        return;
+    }
+    precond(c, c.opt.prec, B, V, nrhs, set_stride, step, s);
+    for (int it = 0; it < c.opt.max_refine; ++it) {
+        launch_residual(c.H, c.M, B, V, c.Rv, nrhs, set_stride, step, s);
+        precond(c, c.opt.prec, c.Rv, c.D, nrhs, set_stride, step, s);
+        launch_axpy_stats(c.P.n, nrhs, V, c.D, (it == c.opt.max_refine - 1) ? c.stats : nullptr, c.opt.rel_tol,
+                          c.d_flags, s);
+    }
+    c.applies += (int64_t)nrhs * (1 + c.opt.max_refine);
+}
+
+hinv_status plan_and_size(const hinv_csr* G, const hinv_tree* T, const hinv_options* o, int n_sets, int R,
+                          int max_nrhs, hinv_ctx& c, size_t* bytes)
+{
+    hinv_status st = make_plan(G, T, c.P);
+    if (st != HINV_OK) return st;
+    c.opt = *o;
+    Arena A;
+    carve_hier(c, A, n_sets, R, max_nrhs);
+    *bytes = A.off + kAlign;
+    return HINV_OK;
+}
+
+}  // namespace
+
+// =============================== C ABI =====================================
+extern "C" {
+
+const char* hinv_last_error(void) { return g_err.c_str(); }
+
+hinv_status hinv_workspace_size(const hinv_csr* G, const hinv_tree* tree, const hinv_options* opt, size_t* bytes)
+{
+    if (!bytes) return fail(HINV_E_INVALID, "bytes is NULL");
+    hinv_status st = check_options(opt, 1);
+    if (st != HINV_OK) return st;
+    std::unique_ptr<hinv_ctx> c(new (std::nothrow) hinv_ctx);
+    if (!c) return fail(HINV_E_NO_MEMORY, "host allocation failed");
+    return plan_and_size(G, tree, opt, 1, std::max(1, opt->max_mod_rank), opt->max_nrhs, *c, bytes);
+}
+
+hinv_status hinv_build(const hinv_csr* G, const hinv_tree* tree, const hinv_options* opt, void* d_ws,
+                       size_t ws_bytes, void* stream, hinv_handle* out)
+{
+    if (!out) return fail(HINV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hinv_status st = check_options(opt, 1);
+    if (st != HINV_OK) return st;
+    std::unique_ptr<hinv_ctx> c(new (std::nothrow) hinv_ctx);
+    if (!c) return fail(HINV_E_NO_MEMORY, "host allocation failed");
+    size_t need = 0;
+    const int R = std::max(1, opt->max_mod_rank);
+    st = plan_and_size(G, tree, opt, 1, R, opt->max_nrhs, *c, &need);
+    if (st != HINV_OK) return st;
+    if (!d_ws) return fail(HINV_E_INVALID, "workspace is NULL");
+    if (ws_bytes < need) return fail(HINV_E_NO_MEMORY, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    Arena A;
+    A.base = (char*)d_ws;
+    carve_hier(*c, A, 1, R, opt->max_nrhs);
+    c->M.R = opt->max_mod_rank;     // 0 disables the correction entirely
+    st = build_device(*c, (hipStream_t)stream);
+    if (st != HINV_OK) return st;
+    *out = c.release();
+    return HINV_OK;
+}
+
+hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    hinv_ctx& c = *h;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = c.P.n;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return fail(HINV_E_INVALID, "bad buses (%d, %d)", a, b);
+    if (!isfinite(delta_g) || delta_g == 0.0) return fail(HINV_E_INVALID, "delta_g must be finite and non-zero");
+    const int cnt = (int)c.mod_a.size();
+    if (cnt >= c.opt.max_mod_rank) return fail(HINV_E_RANK_LIMIT, "already %d changes (max_mod_rank)", cnt);
+    const int ra = c.P.iperm[a], rb = b >= 0 ? c.P.iperm[b] : -1;
+    if (delta_g < 0 && rb >= 0) {   // removing conductance needs that much conductance between a and b
+        double gab = 0.0;
+        for (int e = c.P.rp[ra]; e < c.P.rp[ra + 1]; ++e)
+            if (c.P.ci[e] == rb) gab = -c.P.cv[e];
+        for (int j = 0; j < cnt; ++j)
+            if ((c.mod_a[j] == ra && c.mod_b[j] == rb) || (c.mod_a[j] == rb && c.mod_b[j] == ra)) gab += c.mod_dg[j];
+        if (gab + delta_g < -1e-12 * fabs(delta_g))
+            return fail(HINV_E_NO_SUCH_LINE, "no line of conductance %g between %d and %d", -delta_g, a, b);
+    }
+    // u = G0^{-1} w, w = e_a - e_b, by one FP64 apply
+    std::vector<double> w(n, 0.0);
+    w[ra] = 1.0;
+    if (rb >= 0) w[rb] = -1.0;
+    HIP_TRY(hipMemcpyAsync(c.X, w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    launch_apply(c.H, c.P.lv.data(), HINV_FP64, c.X, c.Xo, c.Y, 1, s);
+    const int R = c.M.R;
+    HIP_TRY(hipMemcpyAsync(c.M.U + (int64_t)cnt * n, c.Xo, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (c.M.U32) launch_to_f32(c.M.U + (int64_t)cnt * n, c.M.U32 + (int64_t)cnt * n, n, s);
+    c.mod_a.push_back(ra); c.mod_b.push_back(rb); c.mod_dg.push_back(delta_g); c.mod_act.push_back(INT32_MIN);
+    std::vector<int> cntv{cnt + 1};
+    HIP_TRY(hipMemcpyAsync(c.m_a, c.mod_a.data(), sizeof(int) * (cnt + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.m_b, c.mod_b.data(), sizeof(int) * (cnt + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.m_dg, c.mod_dg.data(), sizeof(double) * (cnt + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.m_act, c.mod_act.data(), sizeof(int) * (cnt + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.m_count, cntv.data(), sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
+    (void)R;
+    launch_smw_capacitance(c.M, c.d_flags, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    int flags = 0;
+    HIP_TRY(hipMemcpy(&flags, c.d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags & (kFlagNotSPD | kFlagSingular)) {
+        // roll back
+        c.mod_a.pop_back(); c.mod_b.pop_back(); c.mod_dg.pop_back(); c.mod_act.pop_back();
+        std::vector<int> back{cnt};
+        HIP_TRY(hipMemcpy(c.m_count, back.data(), sizeof(int), hipMemcpyHostToDevice));
+        return fail(HINV_E_NOT_SPD, "the change makes G indefinite or singular");
+    }
+    return HINV_OK;
+}
+
+hinv_status hinv_solve(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    hinv_ctx& c = *h;
+    if (nrhs < 0 || nrhs > c.opt.max_nrhs) return fail(HINV_E_INVALID, "nrhs %d outside 0..%d", nrhs, c.opt.max_nrhs);
+    if (ld < c.P.n) return fail(HINV_E_INVALID, "ld %d < n %d", ld, c.P.n);
+    if (nrhs == 0) return HINV_OK;
+    if (!d_i || !d_v) return fail(HINV_E_INVALID, "NULL vector");
+    hipStream_t s = (hipStream_t)stream;
+    launch_permute_in(c.P.n, nrhs, c.d_perm, d_i, ld, c.X, s);
+    solve_new_order(c, c.X, c.Xo, nrhs, 0, nullptr, s);
+    launch_permute_out(c.P.n, nrhs, c.d_perm, c.Xo, d_v, ld, s);
+    HIP_TRY(hipGetLastError());
+    return HINV_OK;
+}
+
+hinv_status hinv_sync_status(hinv_handle h)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    int flags[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(flags, h->d_flags, sizeof flags, hipMemcpyDeviceToHost));
+    int zero[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(h->d_flags, zero, sizeof zero, hipMemcpyHostToDevice));
+    if (flags[0] & kFlagNoConv) return fail(HINV_E_NO_CONVERGENCE, "refinement did not converge");
+    if (flags[0] & (kFlagNotSPD | kFlagNaN)) return fail(HINV_E_NOT_SPD, "non-finite or indefinite result");
+    return HINV_OK;
+}
+
+hinv_status hinv_get_info(hinv_handle h, hinv_info_t* out)
+{
+    if (!h || !out) return fail(HINV_E_INVALID, "NULL argument");
+    const Plan& P = h->P;
+    out->n = P.n;
+    out->n_leaves = (int64_t)P.leaf_lo.size();
+    out->n_internal = (int64_t)P.node_lo.size();
+    out->n_levels = P.n_levels;
+    out->n_cols = (int64_t)P.col_row.size();
+    int64_t le = 0, ze = 0, se = 0;
+    for (int x : P.leaf_n) le += (int64_t)x * x;
+    for (size_t i = 0; i < P.pan_n.size(); ++i) ze += (int64_t)P.pan_n[i] * P.pan_m[i];
+    for (int m : P.node_m) se += (int64_t)m * m;
+    out->leaf_entries = le;
+    out->z_entries = ze;
+    out->s_entries = se;
+    out->max_leaf = P.max_leaf;
+    out->max_cols = P.max_cols;
+    return HINV_OK;
+}
+
+hinv_status hinv_destroy(hinv_handle h)
+{
+    delete h;
+    return HINV_OK;
+}
+
+}  // extern "C"
+
+// =========================== EMT time stepping ==============================
+struct emt_ctx {
+    hinv_ctx hc;                 // hierarchy of G; change set k belongs to case k
+    EmtDev E{};
+    RecParams* d_rec = nullptr;
+    int n = 0, nbr = 0, n_cases = 0, R = 0;
+    std::vector<int> fr_p, to_p;
+    std::vector<double> g;
+    std::vector<std::vector<std::pair<int, int>>> losses;   // per case: (step, branch), sorted
+    int64_t step = 1;
+};
+
+namespace {
+
+hinv_status check_network(const emt_network* N)
+{
+    if (!N) return fail(HINV_E_INVALID, "network is NULL");
+    if (N->n_bus < 1 || N->n_branch < 0 || N->n_src < 0) return fail(HINV_E_INVALID, "negative or zero sizes");
+    if (!(N->dt > 0.0) || !isfinite(N->dt)) return fail(HINV_E_INVALID, "dt must be positive");
+    if (!isfinite(N->freq)) return fail(HINV_E_INVALID, "freq must be finite");
+    if (N->n_branch > 0 && (!N->from || !N->to || !N->R || !N->L))
+        return fail(HINV_E_INVALID, "branch arrays must not be NULL");
+    if (!N->C) return fail(HINV_E_INVALID, "C must not be NULL");
+    if (N->n_src > 0 && (!N->src_bus || !N->amp || !N->phase)) return fail(HINV_E_INVALID, "source arrays must not be NULL");
+    for (int e = 0; e < N->n_branch; ++e) {
+        const int a = N->from[e], b = N->to[e];
+        if (a < 0 || a >= N->n_bus || b < 0 || b >= N->n_bus || a == b)
+            return fail(HINV_E_INVALID, "branch %d has bad buses (%d, %d)", e, a, b);
+        const double z = N->R[e] + 2.0 * N->L[e] / N->dt;
+        if (!(N->R[e] >= 0.0) || !(N->L[e] >= 0.0) || !(z > 0.0) || !isfinite(z))
+            return fail(HINV_E_INVALID, "branch %d has bad R/L", e);
+    }
+    for (int a = 0; a < N->n_bus; ++a)
+        if (!(N->C[a] >= 0.0) || !isfinite(N->C[a])) return fail(HINV_E_INVALID, "C[%d] is negative or not finite", a);
+    for (int q = 0; q < N->n_src; ++q)
+        if (N->src_bus[q] < 0 || N->src_bus[q] >= N->n_bus || !isfinite(N->amp[q]) || !isfinite(N->phase[q]))
+            return fail(HINV_E_INVALID, "source %d is invalid", q);
+    return HINV_OK;
+}
+
+hinv_status check_cases(const emt_cases* C, int nbr, int R, std::vector<std::vector<std::pair<int, int>>>& out)
+{
+    if (!C || C->n_cases < 1) return fail(HINV_E_INVALID, "need at least one case");
+    out.assign(C->n_cases, {});
+    if (!C->loss_ptr) return HINV_OK;
+    if (C->loss_ptr[0] != 0) return fail(HINV_E_INVALID, "loss_ptr[0] != 0");
+    for (int k = 0; k < C->n_cases; ++k) {
+        const int b = C->loss_ptr[k], e = C->loss_ptr[k + 1];
+        if (e < b) return fail(HINV_E_INVALID, "loss_ptr not non-decreasing at case %d", k);
+        if (e > b && (!C->loss_step || !C->loss_branch)) return fail(HINV_E_INVALID, "loss arrays are NULL");
+        if (e - b > R) return fail(HINV_E_RANK_LIMIT, "case %d has %d losses (max_mod_rank %d)", k, e - b, R);
+        for (int j = b; j < e; ++j) {
+            const int br = C->loss_branch[j], st = C->loss_step[j];
+            if (br < 0 || br >= nbr) return fail(HINV_E_INVALID, "case %d loses unknown branch %d", k, br);
+            if (st < 1) return fail(HINV_E_INVALID, "case %d: loss step %d < 1", k, st);
+            for (auto& x : out[k])
+                if (x.second == br) return fail(HINV_E_INVALID, "case %d loses branch %d twice", k, br);
+            out[k].push_back({st, br});
+        }
+        std::stable_sort(out[k].begin(), out[k].end());
+    }
+    return HINV_OK;
+}
+
+// Nodal conductance matrix of the network (trapezoidal companions), CSR with sorted columns.
+void assemble_csr(const emt_network* N, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv)
+{
+    const int n = N->n_bus;
+    struct T { int r, c; double v; };
+    std::vector<T> t;
+    t.reserve((size_t)n + 4 * (size_t)N->n_branch);
+    for (int a = 0; a < n; ++a) t.push_back({a, a, 2.0 * N->C[a] / N->dt});
+    for (int e = 0; e < N->n_branch; ++e) {
+        const double g = 1.0 / (N->R[e] + 2.0 * N->L[e] / N->dt);
+        const int a = N->from[e], b = N->to[e];
+        t.push_back({a, a, g});
+        t.push_back({b, b, g});
+        t.push_back({a, b, -g});
+        t.push_back({b, a, -g});
+    }
+    std::stable_sort(t.begin(), t.end(), [](const T& x, const T& y) { return x.r != y.r ? x.r < y.r : x.c < y.c; });
+    rp.assign(n + 1, 0);
+    ci.clear();
+    cv.clear();
+    int last_row = -1;
+    for (size_t i = 0; i < t.size(); ++i) {
+        if (t[i].r == last_row && ci.back() == t[i].c) {
+            cv.back() += t[i].v;          // parallel branches and the diagonal sum up
+        } else {
+            ci.push_back(t[i].c);
+            cv.push_back(t[i].v);
+        }
+        last_row = t[i].r;
+        rp[t[i].r + 1] = (int)ci.size();
+    }
+    for (int r = 0; r < n; ++r)
+        if (rp[r + 1] < rp[r]) rp[r + 1] = rp[r];
+}
+
+// Device storage of the EMT state (base == nullptr: measure only).
+void carve_emt(emt_ctx& c, Arena& A, int n_src)
+{
+    EmtDev& E = c.E;
+    const int n = c.n, nbr = c.nbr, K = c.n_cases, R = c.R;
+    E.n = n; E.nbr = nbr; E.n_cases = K; E.R = R;
+    E.fr = A.take<int>(nbr); E.to = A.take<int>(nbr);
+    E.g = A.take<double>(nbr); E.alpha = A.take<double>(nbr); E.gC = A.take<double>(n);
+    E.inc_ptr = A.take<int>(n + 1); E.inc_br = A.take<int>(2 * (int64_t)nbr);
+    E.src_ptr = A.take<int>(n + 1); E.src_amp = A.take<double>(n_src); E.src_ph = A.take<double>(n_src);
+    E.loss_cnt = A.take<int>(K); E.loss_step = A.take<int>((int64_t)K * R); E.loss_br = A.take<int>((int64_t)K * R);
+    E.h = A.take<double>(2 * (int64_t)K * nbr);
+    E.hC = A.take<double>((int64_t)K * n); E.b = A.take<double>((int64_t)K * n); E.v = A.take<double>((int64_t)K * n);
+    E.step = A.take<int64_t>(1);
+    E.done = A.take<unsigned int>(1);
+    c.d_rec = A.take<RecParams>(1);
+}
+
+hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_options* o, const emt_cases* C,
+                     emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv, size_t* bytes)
+{
+    hinv_status st = check_network(N);
+    if (st != HINV_OK) return st;
+    st = check_options(o, 1);
+    if (st != HINV_OK) return st;
+    c.R = std::max(1, o->max_mod_rank);
+    st = check_cases(C, N->n_branch, o->max_mod_rank, c.losses);
+    if (st != HINV_OK) return st;
+    c.n = N->n_bus;
+    c.nbr = N->n_branch;
+    c.n_cases = C->n_cases;
+    int total_losses = 0;
+    for (auto& l : c.losses) total_losses += (int)l.size();
+    assemble_csr(N, rp, ci, cv);
+    hinv_csr G{N->n_bus, rp.data(), ci.data(), cv.data()};
+    st = make_plan(&G, T, c.hc.P);
+    if (st != HINV_OK) return st;
+    c.hc.opt = *o;
+    // scratch columns: one per case per step, one per loss at creation, a full change set later
+    c.hc.opt.max_nrhs = std::max(std::max(c.n_cases, c.R), std::max(total_losses, 1));
+    Arena A;
+    carve_hier(c.hc, A, c.n_cases, c.R, c.hc.opt.max_nrhs);
+    carve_emt(c, A, N->n_src);
+    *bytes = A.off + kAlign;
+    return HINV_OK;
+}
+
+// Store the line changes of the given cases (from c.losses) in their change
+// sets: u = G0^{-1} w for all of them in one batched FP64 apply, then the
+// capacitance inverses.  Synchronises.
+hinv_status load_case_losses(emt_ctx& c, const std::vector<int>& which, hipStream_t s)
+{
+    hinv_ctx& h = c.hc;
+    const int n = c.n, R = c.R;
+    std::vector<int> cols;    // (case*R + j) of each apply column
+    std::vector<double> W;
+    for (int k : which) {
+        std::vector<int> a(R, -1), b(R, -1), act(R, INT32_MAX);
+        std::vector<double> dg(R, 0.0);
+        std::vector<int> lst(R, INT32_MAX), lbr(R, -1);
+        const auto& L = c.losses[k];
+        for (size_t j = 0; j < L.size(); ++j) {
+            const int e = L[j].second;
+            a[j] = c.fr_p[e];
+            b[j] = c.to_p[e];
+            dg[j] = -c.g[e];
+            act[j] = L[j].first;
+            lst[j] = L[j].first;
+            lbr[j] = e;
+            cols.push_back(k * R + (int)j);
+            std::vector<double> w(n, 0.0);
+            w[a[j]] = 1.0;
+            w[b[j]] = -1.0;
+            W.insert(W.end(), w.begin(), w.end());
+        }
+        const int cnt = (int)L.size();
+        HIP_TRY(hipMemcpyAsync((void*)(h.m_a + k * R), a.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(h.m_b + k * R), b.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(h.m_act + k * R), act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(h.m_dg + k * R), dg.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(h.m_count + k), &cnt, sizeof(int), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(c.E.loss_step + k * R), lst.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(c.E.loss_br + k * R), lbr.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(c.E.loss_cnt + k), &cnt, sizeof(int), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));     // host vectors above are loop-local
+    }
+    const int nc = (int)cols.size();
+    if (nc > 0) {
+        HIP_TRY(hipMemcpyAsync(h.X, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice, s));
+        launch_apply(h.H, h.P.lv.data(), HINV_FP64, h.X, h.Xo, h.Y, nc, s);
+        for (int q = 0; q < nc; ++q) {
+            double* dst = h.M.U + (int64_t)cols[q] * n;
+            HIP_TRY(hipMemcpyAsync(dst, h.Xo + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            if (h.M.U32) launch_to_f32(dst, h.M.U32 + (int64_t)cols[q] * n, n, s);
+        }
+    }
+    HIP_TRY(hipMemsetAsync(h.d_flags, 0, sizeof(int), s));
+    launch_smw_capacitance(h.M, h.d_flags, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    int flags = 0;
+    HIP_TRY(hipMemcpy(&flags, h.d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags & (kFlagNotSPD | kFlagSingular)) return fail(HINV_E_NOT_SPD, "a line loss makes G indefinite or singular");
+    return HINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hinv_status emt_network_csr(const emt_network* net, int32_t* row_ptr, int32_t* col_idx, double* val, int64_t* nnz)
+{
+    if (!nnz) return fail(HINV_E_INVALID, "nnz is NULL");
+    hinv_status st = check_network(net);
+    if (st != HINV_OK) return st;
+    std::vector<int> rp, ci;
+    std::vector<double> cv;
+    assemble_csr(net, rp, ci, cv);
+    *nnz = (int64_t)ci.size();
+    if (!row_ptr) return HINV_OK;
+    if (!col_idx || !val) return fail(HINV_E_INVALID, "NULL output array");
+    memcpy(row_ptr, rp.data(), sizeof(int) * rp.size());
+    memcpy(col_idx, ci.data(), sizeof(int) * ci.size());
+    memcpy(val, cv.data(), sizeof(double) * cv.size());
+    return HINV_OK;
+}
+
+hinv_status emt_workspace_size(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
+                               const emt_cases* cases, size_t* bytes)
+{
+    if (!bytes) return fail(HINV_E_INVALID, "bytes is NULL");
+    std::unique_ptr<emt_ctx> c(new (std::nothrow) emt_ctx);
+    if (!c) return fail(HINV_E_NO_MEMORY, "host allocation failed");
+    std::vector<int> rp, ci;
+    std::vector<double> cv;
+    return emt_plan(net, tree, opt, cases, *c, rp, ci, cv, bytes);
+}
+
+hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
+                       const emt_cases* cases, void* d_ws, size_t ws_bytes, void* stream, emt_handle* out)
+{
+    if (!out) return fail(HINV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<emt_ctx> c(new (std::nothrow) emt_ctx);
+    if (!c) return fail(HINV_E_NO_MEMORY, "host allocation failed");
+    std::vector<int> rp, ci;
+    std::vector<double> cv;
+    size_t need = 0;
+    hinv_status st = emt_plan(net, tree, opt, cases, *c, rp, ci, cv, &need);
+    if (st != HINV_OK) return st;
+    if (!d_ws) return fail(HINV_E_INVALID, "workspace is NULL");
+    if (ws_bytes < need) return fail(HINV_E_NO_MEMORY, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    Arena A;
+    A.base = (char*)d_ws;
+    carve_hier(c->hc, A, c->n_cases, c->R, c->hc.opt.max_nrhs);
+    carve_emt(*c, A, net->n_src);
+    c->hc.M.R = c->R;
+    // network arrays in the new bus order
+    const Plan& P = c->hc.P;
+    const int n = c->n, nbr = c->nbr;
+    c->fr_p.resize(nbr);
+    c->to_p.resize(nbr);
+    c->g.resize(nbr);
+    std::vector<double> alpha(nbr), gC(n);
+    std::vector<int> inc_ptr(n + 1, 0), inc_br(2 * (size_t)nbr);
+    for (int e = 0; e < nbr; ++e) {
+        c->fr_p[e] = P.iperm[net->from[e]];
+        c->to_p[e] = P.iperm[net->to[e]];
+        const double z2 = 2.0 * net->L[e] / net->dt;
+        c->g[e] = 1.0 / (net->R[e] + z2);
+        alpha[e] = c->g[e] * (z2 - net->R[e]);
+        inc_ptr[c->fr_p[e] + 1]++;
+        inc_ptr[c->to_p[e] + 1]++;
+    }
+    for (int r = 0; r < n; ++r) {
+        inc_ptr[r + 1] += inc_ptr[r];
+        gC[r] = 2.0 * net->C[P.perm[r]] / net->dt;
+    }
+    {
+        std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int e = 0; e < nbr; ++e) {
+            inc_br[fill[c->fr_p[e]]++] = e;
+            inc_br[fill[c->to_p[e]]++] = e;
+        }
+    }
+    std::vector<int> src_ptr(n + 1, 0);
+    std::vector<double> samp(net->n_src), sph(net->n_src);
+    for (int q = 0; q < net->n_src; ++q) src_ptr[P.iperm[net->src_bus[q]] + 1]++;
+    for (int r = 0; r < n; ++r) src_ptr[r + 1] += src_ptr[r];
+    {
+        std::vector<int> fill(src_ptr.begin(), src_ptr.end() - 1);
+        for (int q = 0; q < net->n_src; ++q) {
+            const int r = P.iperm[net->src_bus[q]];
+            samp[fill[r]] = net->amp[q];
+            sph[fill[r]] = net->phase[q];
+            fill[r]++;
+        }
+    }
+    EmtDev& E = c->E;
+    E.dt = net->dt;
+    E.omega = 2.0 * M_PI * net->freq;
+    E.perm = c->hc.d_perm;
+    HIP_TRY(up(E.fr, c->fr_p, s)); HIP_TRY(up(E.to, c->to_p, s)); HIP_TRY(up(E.g, c->g, s));
+    HIP_TRY(up(E.alpha, alpha, s)); HIP_TRY(up(E.gC, gC, s));
+    HIP_TRY(up(E.inc_ptr, inc_ptr, s)); HIP_TRY(up(E.inc_br, inc_br, s));
+    HIP_TRY(up(E.src_ptr, src_ptr, s)); HIP_TRY(up(E.src_amp, samp, s)); HIP_TRY(up(E.src_ph, sph, s));
+    st = build_device(c->hc, s);        // synchronises: the host vectors above may go
+    if (st != HINV_OK) return st;
+    std::vector<int> all(c->n_cases);
+    for (int k = 0; k < c->n_cases; ++k) all[k] = k;
+    st = load_case_losses(*c, all, s);
+    if (st != HINV_OK) return st;
+    launch_emt_init(E, s);
+    launch_set_rec(c->d_rec, RecParams{nullptr, nullptr, 0, 0}, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    c->step = 1;
+    *out = c.release();
+    return HINV_OK;
+}
+
+hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* d_b_record, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    if (n_steps < 0) return fail(HINV_E_INVALID, "n_steps < 0");
+    if (n_steps == 0) return HINV_OK;
+    emt_ctx& c = *h;
+    hipStream_t s = (hipStream_t)stream;
+    launch_set_rec(c.d_rec, RecParams{d_v_record, d_b_record, c.step, n_steps}, s);
+    for (int i = 0; i < n_steps; ++i) {
+        solve_new_order(c.hc, c.E.b, c.E.v, c.n_cases, 1, c.E.step, s);
+        launch_emt_history(c.E, c.d_rec, s);
+    }
+    HIP_TRY(hipGetLastError());
+    c.step += n_steps;
+    return HINV_OK;
+}
+
+hinv_status emt_lose_line(emt_handle h, int32_t case_idx, int32_t branch, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    emt_ctx& c = *h;
+    if (case_idx < 0 || case_idx >= c.n_cases) return fail(HINV_E_INVALID, "case %d out of range", case_idx);
+    if (branch < 0 || branch >= c.nbr) return fail(HINV_E_INVALID, "branch %d out of range", branch);
+    auto& L = c.losses[case_idx];
+    for (auto& x : L)
+        if (x.second == branch) return fail(HINV_E_NO_SUCH_LINE, "branch %d is already lost in case %d", branch, case_idx);
+    if ((int)L.size() >= c.hc.opt.max_mod_rank)
+        return fail(HINV_E_RANK_LIMIT, "case %d already has %d losses", case_idx, (int)L.size());
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    L.push_back({(int)c.step, branch});
+    std::stable_sort(L.begin(), L.end());
+    hinv_status st = load_case_losses(c, std::vector<int>{case_idx}, s);
+    if (st != HINV_OK) {
+        for (size_t j = 0; j < L.size(); ++j)
+            if (L[j].second == branch) { L.erase(L.begin() + j); break; }
+        load_case_losses(c, std::vector<int>{case_idx}, s);
+        return st;
+    }
+    return HINV_OK;
+}
+
+hinv_status emt_get_step(emt_handle h, int64_t* step)
+{
+    if (!h || !step) return fail(HINV_E_INVALID, "NULL argument");
+    *step = h->step;
+    return HINV_OK;
+}
+
+hinv_status emt_get_stats(emt_handle h, int64_t* applies, double* max_rel_update)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    if (applies) *applies = h->hc.applies;
+    if (max_rel_update) {
+        std::vector<unsigned long long> st(h->n_cases);
+        HIP_TRY(hipMemcpy(st.data(), h->hc.stats, sizeof(unsigned long long) * h->n_cases, hipMemcpyDeviceToHost));
+        double m = 0.0;
+        for (auto u : st) {
+            double d;
+            memcpy(&d, &u, sizeof d);
+            m = std::max(m, d);
+        }
+        *max_rel_update = m;
+    }
+    return HINV_OK;
+}
+
+hinv_status emt_destroy(emt_handle h)
+{
+    delete h;
+    return HINV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+"""ctypes binding of libhinv.so (argument marshalling only).
+
+Device memory and streams come from PyTorch: workspaces and vectors are torch
+tensors on a ROCm device, streams are ``torch.cuda.current_stream()``.  Every
+step of the computation runs in the library's HIP kernels; if the library is
+not built this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhinv.so")
+
+FP64, FP32, BF16, FP8 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8": FP8}
+
+STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "NO_SUCH_LINE",
+          6: "NO_CONVERGENCE", 7: "RANK_LIMIT", 8: "SINGULAR"}
+
+EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_solve", "hinv_sync_status",
+           "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_workspace_size", "emt_create",
+           "emt_step", "emt_lose_line", "emt_get_step", "emt_get_stats", "emt_destroy", "hinv_last_error")
+
+
+class HinvError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class _Tree(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("parent", ctypes.c_void_p), ("bus_leaf", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("max_mod_rank", ctypes.c_int32), ("max_nrhs", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_leaves", "n_internal", "n_levels", "n_cols", "leaf_entries",
+                                             "z_entries", "s_entries", "max_leaf", "max_cols")]
+
+
+class _Network(ctypes.Structure):
+    _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("from_", ctypes.c_void_p),
+                ("to", ctypes.c_void_p), ("R", ctypes.c_void_p), ("L", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("dt", ctypes.c_double), ("n_src", ctypes.c_int32), ("src_bus", ctypes.c_void_p),
+                ("amp", ctypes.c_void_p), ("phase", ctypes.c_void_p), ("freq", ctypes.c_double)]
+
+
+class _Cases(ctypes.Structure):
+    _fields_ = [("n_cases", ctypes.c_int32), ("loss_ptr", ctypes.c_void_p), ("loss_step", ctypes.c_void_p),
+                ("loss_branch", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhinv.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "hinv_workspace_size": [P, P, P, P],
+        "hinv_build": [P, P, P, P, ctypes.c_size_t, P, P],
+        "hinv_modify_line": [P, i32, i32, d, P],
+        "hinv_solve": [P, P, P, i32, i32, P],
+        "hinv_sync_status": [P],
+        "hinv_get_info": [P, P],
+        "hinv_destroy": [P],
+        "emt_network_csr": [P, P, P, P, P],
+        "emt_workspace_size": [P, P, P, P, P],
+        "emt_create": [P, P, P, P, P, ctypes.c_size_t, P, P],
+        "emt_step": [P, i32, P, P, P],
+        "emt_lose_line": [P, i32, i32, P],
+        "emt_get_step": [P, P],
+        "emt_get_stats": [P, P, P],
+        "emt_destroy": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.hinv_last_error.restype = ctypes.c_char_p
+    lib.hinv_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str) -> None:
+    if st != 0:
+        raise HinvError(st, where, load().hinv_last_error().decode())
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return 0
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _stream(torch_stream=None) -> int:
+    import torch
+    s = torch_stream if torch_stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs) -> _Options:
+    if isinstance(prec, str):
+        prec = PRECISIONS[prec]
+    return _Options(int(prec), float(rel_tol), int(max_refine), int(max_mod_rank), int(max_nrhs))
+
+
+class _NetArrays:
+    """Keeps the contiguous host arrays of a network alive while the library reads them."""
+
+    def __init__(self, net):
+        c = np.ascontiguousarray
+        self.frm = c(net.frm, np.int32)
+        self.to = c(net.to, np.int32)
+        self.R = c(net.R, np.float64)
+        self.L = c(net.L, np.float64)
+        self.C = c(net.C, np.float64)
+        self.sb = c(net.src_bus, np.int32)
+        self.sa = c(net.src_amp, np.float64)
+        self.sp = c(net.src_phase, np.float64)
+        self.parent = c(net.parent, np.int32)
+        self.bus_leaf = c(net.bus_leaf, np.int32)
+        self.s = _Network(int(net.n_bus), int(len(self.frm)), _ptr(self.frm), _ptr(self.to), _ptr(self.R),
+                          _ptr(self.L), _ptr(self.C), float(net.dt), int(len(self.sb)), _ptr(self.sb),
+                          _ptr(self.sa), _ptr(self.sp), float(net.freq))
+        self.tree = _Tree(int(len(self.parent)), _ptr(self.parent), _ptr(self.bus_leaf))
+
+
+def network_csr(net) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """G of the network as assembled by the library (row_ptr, col_idx, val)."""
+    lib = load()
+    na = _NetArrays(net)
+    nnz = ctypes.c_int64(0)
+    _check(lib.emt_network_csr(ctypes.byref(na.s), None, None, None, ctypes.byref(nnz)), "emt_network_csr")
+    rp = np.zeros(net.n_bus + 1, np.int32)
+    ci = np.zeros(nnz.value, np.int32)
+    cv = np.zeros(nnz.value, np.float64)
+    _check(lib.emt_network_csr(ctypes.byref(na.s), _ptr(rp), _ptr(ci), _ptr(cv), ctypes.byref(nnz)),
+           "emt_network_csr")
+    return rp, ci, cv
+
+
+class Hierarchy:
+    """Exact hierarchical inverse of a symmetric G (hinv_build / hinv_solve / hinv_modify_line)."""
+
+    def __init__(self, row_ptr, col_idx, val, parent, bus_leaf, prec="fp64", rel_tol=1e-9, max_refine=2,
+                 max_mod_rank=4, max_nrhs=1, device="cuda"):
+        import torch
+        self._lib = load()
+        self.device = torch.device(device)
+        c = np.ascontiguousarray
+        self._rp, self._ci, self._cv = c(row_ptr, np.int32), c(col_idx, np.int32), c(val, np.float64)
+        self._parent, self._leaf = c(parent, np.int32), c(bus_leaf, np.int32)
+        self.n = len(self._rp) - 1
+        self._csr = _CSR(self.n, _ptr(self._rp), _ptr(self._ci), _ptr(self._cv))
+        self._tree = _Tree(len(self._parent), _ptr(self._parent), _ptr(self._leaf))
+        self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs)
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.hinv_workspace_size(ctypes.byref(self._csr), ctypes.byref(self._tree),
+                                             ctypes.byref(self._opt), ctypes.byref(nb)), "hinv_workspace_size")
+        self.ws_bytes = nb.value
+        self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            _check(self._lib.hinv_build(ctypes.byref(self._csr), ctypes.byref(self._tree), ctypes.byref(self._opt),
+                                        _ptr(self._ws), nb.value, _stream(), ctypes.byref(h)), "hinv_build")
+        self._h = h
+
+    @classmethod
+    def from_network(cls, net, **kw):
+        rp, ci, cv = network_csr(net)
+        return cls(rp, ci, cv, net.parent, net.bus_leaf, **kw)
+
+    def solve(self, i, out=None):
+        """v = G^{-1} i; i: (n,) or (nrhs, n) float64 tensor on the device."""
+        import torch
+        x = i.contiguous()
+        squeeze = x.dim() == 1
+        if squeeze:
+            x = x.unsqueeze(0)
+        if x.dtype != torch.float64 or x.device.type != "cuda":
+            raise ValueError("i must be a float64 device tensor")
+        if out is None:
+            out = torch.empty_like(x)
+        _check(self._lib.hinv_solve(self._h, _ptr(x), _ptr(out), x.shape[0], self.n, _stream()), "hinv_solve")
+        return out[0] if squeeze else out
+
+    def modify_line(self, a: int, b: int, delta_g: float) -> None:
+        _check(self._lib.hinv_modify_line(self._h, int(a), int(b), float(delta_g), _stream()), "hinv_modify_line")
+
+    def sync_status(self) -> None:
+        import torch
+        torch.cuda.current_stream().synchronize()
+        _check(self._lib.hinv_sync_status(self._h), "hinv_sync_status")
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(self._lib.hinv_get_info(self._h, ctypes.byref(inf)), "hinv_get_info")
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.hinv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _case_arrays(n_cases: int, losses: Optional[Sequence[Sequence[Tuple[int, int]]]]):
+    ptr = np.zeros(n_cases + 1, np.int32)
+    st, br = [], []
+    if losses is not None:
+        if len(losses) != n_cases:
+            raise ValueError("one loss list per case")
+        for k, lst in enumerate(losses):
+            for (s, b) in lst:
+                st.append(int(s))
+                br.append(int(b))
+            ptr[k + 1] = len(st)
+    return ptr, np.asarray(st, np.int32), np.asarray(br, np.int32)
+
+
+class EMT:
+    """EMT time stepping of n_cases cases sharing one network (emt_create / emt_step).
+
+    losses: per case a list of (step, branch) line losses (branch lost from that step on).
+    """
+
+    def __init__(self, net, n_cases: int = 1, losses=None, prec="fp64", rel_tol=1e-9, max_refine=2,
+                 max_mod_rank=2, device="cuda"):
+        import torch
+        self._lib = load()
+        self.device = torch.device(device)
+        self.net = net
+        self.n = int(net.n_bus)
+        self.n_cases = int(n_cases)
+        self._na = _NetArrays(net)
+        self._ptr, self._st, self._br = _case_arrays(self.n_cases, losses)
+        self._cases = _Cases(self.n_cases, _ptr(self._ptr), _ptr(self._st), _ptr(self._br))
+        self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, 1)
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.emt_workspace_size(ctypes.byref(self._na.s), ctypes.byref(self._na.tree),
+                                            ctypes.byref(self._opt), ctypes.byref(self._cases), ctypes.byref(nb)),
+               "emt_workspace_size")
+        self.ws_bytes = nb.value
+        self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            _check(self._lib.emt_create(ctypes.byref(self._na.s), ctypes.byref(self._na.tree), ctypes.byref(self._opt),
+                                        ctypes.byref(self._cases), _ptr(self._ws), nb.value, _stream(),
+                                        ctypes.byref(h)), "emt_create")
+        self._h = h
+
+    def step(self, n_steps: int, record_v: bool = True, record_b: bool = False, v_out=None, b_out=None):
+        """Advance all cases; returns (V, B) of shape (n_steps, n_cases, n_bus) or None."""
+        import torch
+        V = B = None
+        if record_v:
+            V = v_out if v_out is not None else torch.empty((n_steps, self.n_cases, self.n), dtype=torch.float64,
+                                                            device=self.device)
+        if record_b:
+            B = b_out if b_out is not None else torch.empty((n_steps, self.n_cases, self.n), dtype=torch.float64,
+                                                            device=self.device)
+        _check(self._lib.emt_step(self._h, int(n_steps), _ptr(V), _ptr(B), _stream()), "emt_step")
+        return V, B
+
+    def lose_line(self, case_idx: int, branch: int) -> None:
+        _check(self._lib.emt_lose_line(self._h, int(case_idx), int(branch), _stream()), "emt_lose_line")
+
+    @property
+    def next_step(self) -> int:
+        s = ctypes.c_int64(0)
+        _check(self._lib.emt_get_step(self._h, ctypes.byref(s)), "emt_get_step")
+        return s.value
+
+    def stats(self) -> Tuple[int, float]:
+        import torch
+        torch.cuda.current_stream().synchronize()
+        a, r = ctypes.c_int64(0), ctypes.c_double(0)
+        _check(self._lib.emt_get_stats(self._h, ctypes.byref(a), ctypes.byref(r)), "emt_get_stats")
+        return a.value, r.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.emt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative, infinity norm):
+  * assembled inverse and single solves, FP64 path: 1e-12 (the exact
+    hierarchy's rounding is ~1e-15; kappa(G) ~ 1e3);
+  * every solve and every trajectory: 1e-10, the target accuracy;
+  * trajectories are compared normalised by their peak voltage, because two
+    correct FP64 solvers drift apart on this marginally stable recursion
+    (one eigenvalue of the step map is exactly 1);
+  * cases run in a batch must equal the same case run alone bitwise (every
+    column goes through the same kernels in the same order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10661_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    from paper_2105_10661_amd import hinv
+    torch.cuda.set_device(0)
+    hinv.load()
+    return hinv
+
+
+def _gpu_inverse(H, n):
+    import torch
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    V = H.solve(eye)                     # row k = G^{-1} e_k
+    torch.cuda.synchronize()
+    return V.cpu().numpy().T
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("name", ["c1-179", "ring4-716", "ring8-1432"])
+def test_assembled_inverse_matches_oracle(hv, name):
+    net = {"c1-179": cases.net_179(), "ring4-716": cases.net_ring(4, 7), "ring8-1432": cases.net_ring(8, 2)}[name]
+    print(f"[gpu] inverse parity {name}", flush=True)
+    H = hv.Hierarchy.from_network(net, max_nrhs=net.n_bus)
+    Gi = _gpu_inverse(H, net.n_bus)
+    Go = oracle.inverse(oracle.assemble_G(net))
+    assert _rel(Gi, Go) <= 1e-12
+    info = H.info()
+    assert info["n_leaves"] == net.n_leaves()
+    H.close()
+
+
+def test_tiny_networks_all_trees_and_line_losses(hv):
+    """Brute force: small networks, several leaf sizes, every single-line loss."""
+    import torch
+    for n_bus, n_br, seed in ((3, 3, 1), (5, 7, 2), (8, 12, 3), (8, 9, 4)):
+        base = cases.small_network(n_bus, n_br, seed)
+        G = oracle.assemble_G(base)
+        Go = oracle.inverse(G)
+        for d_th in range(1, n_bus + 1):
+            parent, leaf = cases.threshold_tree(base.pos, d_th)
+            base.parent, base.bus_leaf = parent, leaf
+            print(f"[gpu] tiny n={n_bus} d_th={d_th}", flush=True)
+            H = hv.Hierarchy.from_network(base, max_nrhs=n_bus, max_mod_rank=1)
+            assert _rel(_gpu_inverse(H, n_bus), Go) <= 1e-12
+            H.close()
+        g = oracle.branch_conductance(base)
+        for e in range(base.n_branch):
+            H = hv.Hierarchy.from_network(base, max_nrhs=n_bus, max_mod_rank=1)
+            H.modify_line(int(base.frm[e]), int(base.to[e]), -float(g[e]))
+            alive = np.ones(base.n_branch, np.uint8)
+            alive[e] = 0
+            ref = oracle.inverse(oracle.assemble_G(base, alive))
+            assert _rel(_gpu_inverse(H, n_bus), ref) <= 1e-11, (n_bus, e)
+            H.close()
+        torch.cuda.synchronize()
+
+
+def test_modify_line_rank_two_and_ground(hv):
+    net = cases.net_179()
+    H = hv.Hierarchy.from_network(net, max_nrhs=net.n_bus, max_mod_rank=3)
+    g = oracle.branch_conductance(net)
+    e1, e2 = 10, 200
+    H.modify_line(int(net.frm[e1]), int(net.to[e1]), -float(g[e1]))
+    H.modify_line(int(net.frm[e2]), int(net.to[e2]), -float(g[e2]))
+    H.modify_line(37, -1, 0.1)                  # a 10 ohm fault from bus 37 to ground
+    alive = np.ones(net.n_branch, np.uint8)
+    alive[[e1, e2]] = 0
+    G = oracle.assemble_G(net, alive)
+    G[37, 37] += 0.1
+    assert _rel(_gpu_inverse(H, net.n_bus), oracle.inverse(G)) <= 1e-11
+    H.close()
+
+
+def test_modify_line_errors(hv):
+    net = cases.net_179()
+    H = hv.Hierarchy.from_network(net, max_mod_rank=1)
+    g = oracle.branch_conductance(net)
+    with pytest.raises(hv.HinvError) as ei:
+        H.modify_line(int(net.frm[0]), int(net.to[0]), -2.0 * float(g[0]))
+    assert ei.value.name == "NO_SUCH_LINE"
+    with pytest.raises(hv.HinvError) as ei:
+        H.modify_line(0, 0, 1.0)
+    assert ei.value.name == "INVALID"
+    H.modify_line(int(net.frm[0]), int(net.to[0]), -float(g[0]))
+    with pytest.raises(hv.HinvError) as ei:
+        H.modify_line(int(net.frm[1]), int(net.to[1]), -float(g[1]))
+    assert ei.value.name == "RANK_LIMIT"
+    H.close()
+
+
+def test_indefinite_input_is_reported(hv):
+    # symmetric, positive diagonal, indefinite: the leaf elimination meets a negative pivot
+    rp = np.array([0, 2, 4]); ci = np.array([0, 1, 0, 1]); cv = np.array([1.0, 2.0, 2.0, 1.0])
+    with pytest.raises(hv.HinvError) as ei:
+        hv.Hierarchy(rp, ci, cv, np.array([-1]), np.array([0, 0]))
+    assert ei.value.name == "NOT_SPD"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_solves(hv, prec):
+    import torch
+    net = cases.net_ring(8, 2)
+    H = hv.Hierarchy.from_network(net, prec=prec, max_refine=2, max_nrhs=16)
+    rng = np.random.default_rng(7)
+    B = rng.standard_normal((16, net.n_bus))
+    X = H.solve(torch.tensor(B, device="cuda")).cpu().numpy()
+    Xo = oracle.solve(oracle.assemble_G(net), B)
+    err = np.abs(X - Xo).max(1) / np.abs(Xo).max(1)
+    assert err.max() <= (1e-12 if prec == "fp64" else 1e-10), err.max()
+    H.sync_status()
+    H.close()
+
+
+# ---------------------------------------------------------------------------
+# EMT trajectories
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    case = cases.case_c1()
+    V, B = oracle.emt_run(case.net, case.n_steps, loss_steps=[300], loss_branches=[50], solver="inv", record_b=True)
+    return case, V, B
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_emt_179_trajectory(hv, c1_ref, prec):
+    case, Vref, _ = c1_ref
+    print(f"[gpu] emt 179 {prec}", flush=True)
+    emt = hv.EMT(case.net, 1, losses=[[(300, 50)]], prec=prec, max_refine=2)
+    V, _ = emt.step(case.n_steps)
+    Vg = V[:, 0, :].cpu().numpy()
+    peak = np.abs(Vref).max()
+    assert np.abs(Vg - Vref).max() / peak <= 1e-10
+    assert emt.next_step == case.n_steps + 1
+    emt.close()
+
+
+def test_emt_per_solve_with_oracle_rhs(hv, c1_ref):
+    """Identical inputs: the oracle's right-hand sides solved by the GPU hierarchy."""
+    import torch
+    case, Vref, Bref = c1_ref
+    steps = np.array([1, 2, 10, 299, 300, 301, 999]) - 1
+    net = case.net
+    for prec in ("fp64", "fp32"):
+        H = hv.Hierarchy.from_network(net, prec=prec, max_refine=2, max_nrhs=len(steps), max_mod_rank=1)
+        pre = steps < 299
+        X = H.solve(torch.tensor(Bref[steps[pre]], device="cuda")).cpu().numpy()
+        err = np.abs(X - Vref[steps[pre]]).max(1) / np.abs(Vref[steps[pre]]).max(1)
+        assert err.max() <= 1e-10
+        g = oracle.branch_conductance(net)
+        H.modify_line(int(net.frm[50]), int(net.to[50]), -float(g[50]))
+        X = H.solve(torch.tensor(Bref[steps[~pre]], device="cuda")).cpu().numpy()
+        err = np.abs(X - Vref[steps[~pre]]).max(1) / np.abs(Vref[steps[~pre]]).max(1)
+        assert err.max() <= 1e-10
+        H.close()
+
+
+@pytest.fixture(scope="module")
+def c2_ref():
+    case = cases.case_c2()
+    V, _ = oracle.emt_run(case.net, case.n_steps, loss_steps=case.loss_steps, loss_branches=case.loss_branches,
+                          solver="inv")
+    return case, V
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_emt_1432_with_line_loss(hv, c2_ref, prec):
+    case, Vref = c2_ref
+    print(f"[gpu] emt 1432 {prec}", flush=True)
+    losses = [list(zip(case.loss_steps.tolist(), case.loss_branches.tolist()))]
+    emt = hv.EMT(case.net, 1, losses=losses, prec=prec, max_refine=2)
+    V, _ = emt.step(case.n_steps)
+    Vg = V[:, 0, :].cpu().numpy()
+    peak = np.abs(Vref).max()
+    err_peak = np.abs(Vg - Vref).max() / peak
+    err_step = (np.abs(Vg - Vref).max(1) / np.abs(Vref).max(1)).max()
+    print(f"[gpu] 1432 {prec}: peak-normalised {err_peak:.2e}, per-step {err_step:.2e}", flush=True)
+    assert err_peak <= 1e-10
+    if prec != "fp64":
+        applies, rel = emt.stats()
+        assert rel <= 1e-9
+    emt.close()
+
+
+def test_batched_cases_equal_alone_and_dynamic_loss(hv):
+    import torch
+    net = cases.net_179()
+    losses = [[], [(40, 5)], [(10, 100), (70, 3)], [(55, 262)]]
+    emt = hv.EMT(net, len(losses), losses=losses, prec="fp32", max_refine=2, max_mod_rank=2)
+    V, _ = emt.step(120)
+    Vb = V.cpu().numpy()
+    for k, lst in enumerate(losses):
+        one = hv.EMT(net, 1, losses=[lst], prec="fp32", max_refine=2, max_mod_rank=2)
+        V1, _ = one.step(120)
+        assert np.array_equal(V1[:, 0, :].cpu().numpy(), Vb[:, k, :]), k
+        one.close()
+    # a loss requested while running equals the same loss scheduled in advance
+    dyn = hv.EMT(net, 1, losses=[[]], prec="fp32", max_refine=2, max_mod_rank=2)
+    Va, _ = dyn.step(39)
+    dyn.lose_line(0, 5)
+    Vb2, _ = dyn.step(81)
+    Vd = torch.cat([Va, Vb2]).cpu().numpy()
+    assert np.array_equal(Vd[:, 0, :], Vb[:, 1, :])
+    emt.close()
+    dyn.close()
