@@ -85,6 +85,13 @@ typedef struct {
     int32_t max_refine;    /* refinement iterations after the first apply (mixed precision only) */
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
+    int32_t warm_start;    /* EMT, mixed precision: refine from the previous step's v instead of P b */
+    int32_t kernel_mode;   /* EMT engine: 0 = automatic (3 for one case when it fits, else 2 when it
+                              fits, else 1); 1 = one launch per kernel per step (any size);
+                              2 = one fused launch per emt_step, one workgroup per case (case
+                              vectors in LDS); 3 = one fused cooperative launch per emt_step, one
+                              workgroup per leaf of a single case (mixed precision runs exactly
+                              max_refine (+1 when warm-started) corrections per step) */
 } hinv_options;
 
 typedef struct {
@@ -204,6 +211,17 @@ hinv_status emt_get_step(emt_handle c, int64_t* step);
  * largest final ||dv||/||v|| seen.  Synchronises nothing; call after the
  * stream is idle. */
 hinv_status emt_get_stats(emt_handle c, int64_t* applies, double* max_rel_update);
+
+/* Per-step timing for latency percentiles: while set, every fused emt_step
+ * launch writes the GPU wall clock (wall_clock64(), constant rate, see
+ * hipDeviceAttributeWallClockRate) after each step of case 0 into
+ * d_clock[j], j = 0 .. min(n_steps, capacity)-1 of that call (device memory,
+ * caller-owned).  d_clock == NULL switches it off.  The per-kernel engine
+ * does not write it. */
+hinv_status emt_set_step_clock(emt_handle c, int64_t* d_clock, int64_t capacity);
+
+/* Rate of that wall clock on device `device`, in kHz. */
+hinv_status hinv_wall_clock_khz(int32_t device, int32_t* khz);
 
 hinv_status emt_destroy(emt_handle c);
 

@@ -71,6 +71,8 @@ struct Plan {
     std::vector<double> col_w, col_sign;
     std::vector<int> lvl_node, lvl_pan, lvl_col;
     std::vector<LevelHost> lv;
+    std::vector<int> row_lo, row_nl, col_node, lvl_frow, frow_pan, pan_frow0;
+    std::vector<int64_t> row_boff;
     std::vector<int> rp, ci;
     std::vector<double> cv;
     int64_t leaf_entries = 0, z_entries = 0, s_entries = 0;
@@ -330,6 +332,26 @@ hinv_status make_plan(const hinv_csr* G, const hinv_tree* T, Plan& P)
     }
     P.z_entries = zoff;
     P.s_entries = soff;
+    // lookups for the fused kernel
+    P.row_lo.resize(n); P.row_nl.resize(n); P.row_boff.resize(n);
+    for (int r = 0; r < n; ++r) {
+        const int l = P.row_leaf[r];
+        P.row_lo[r] = P.leaf_lo[l];
+        P.row_nl[r] = P.leaf_n[l];
+        P.row_boff[r] = P.leaf_off[l] + (r - P.leaf_lo[l]);
+    }
+    P.col_node.resize(P.col_row.size());
+    for (int i = 0; i < NI; ++i)
+        for (int q = 0; q < P.node_m[i]; ++q) P.col_node[P.node_col0[i] + q] = i;
+    P.lvl_frow.assign(P.n_levels + 1, 0);
+    P.pan_frow0.resize(P.pan_lo.size());
+    for (int h = 1; h <= P.n_levels; ++h) {
+        for (int pp = P.lvl_pan[h - 1]; pp < P.lvl_pan[h]; ++pp) {
+            P.pan_frow0[pp] = (int)P.frow_pan.size();
+            for (int i = 0; i < P.pan_n[pp]; ++i) P.frow_pan.push_back(pp);
+        }
+        P.lvl_frow[h] = (int)P.frow_pan.size();
+    }
     if (P.max_cols > 4096) return fail(HINV_E_INVALID, "a tree node has %d coupling columns (limit 4096)", P.max_cols);
     return HINV_OK;
 }
@@ -378,6 +400,9 @@ void carve_hier(hinv_ctx& c, Arena& A, int n_sets, int R, int max_nrhs)
     H.col_sign = A.take<double>(NC); H.col_pan = A.take<int>(NC);
     H.lvl_node = A.take<int>(P.n_levels + 1); H.lvl_pan = A.take<int>(P.n_levels + 1);
     H.lvl_col = A.take<int>(P.n_levels + 1);
+    H.row_lo = A.take<int>(P.n); H.row_nl = A.take<int>(P.n); H.row_boff = A.take<int64_t>(P.n);
+    H.col_node = A.take<int>(NC); H.lvl_frow = A.take<int>(P.n_levels + 1);
+    H.frow_pan = A.take<int>((int64_t)P.frow_pan.size()); H.pan_frow0 = A.take<int>(NP);
     H.rp = A.take<int>(P.n + 1); H.ci = A.take<int>(P.rp.empty() ? 1 : P.rp[P.n]);
     H.cv = A.take<double>(P.rp.empty() ? 1 : P.rp[P.n]);
     H.blk = A.take<double>(P.leaf_entries); H.Z = A.take<double>(P.z_entries); H.Sinv = A.take<double>(P.s_entries);
@@ -426,6 +451,8 @@ hinv_status check_options(const hinv_options* o, int min_nrhs)
     if (o->max_nrhs < min_nrhs) return fail(HINV_E_INVALID, "max_nrhs %d < %d", o->max_nrhs, min_nrhs);
     if (o->prec != HINV_FP64 && (o->max_refine < 0 || o->max_refine > 64))
         return fail(HINV_E_INVALID, "max_refine %d outside 0..64", o->max_refine);
+    if (o->kernel_mode < 0 || o->kernel_mode > 3) return fail(HINV_E_INVALID, "kernel_mode %d unknown", o->kernel_mode);
+    if (o->prec != HINV_FP64 && !(o->rel_tol >= 0.0)) return fail(HINV_E_INVALID, "rel_tol must be >= 0");
     return HINV_OK;
 }
 
@@ -446,6 +473,9 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
     HIP_TRY(up(H.col_row, P.col_row, s)); HIP_TRY(up(H.col_w, P.col_w, s)); HIP_TRY(up(H.col_partner, P.col_partner, s));
     HIP_TRY(up(H.col_sign, P.col_sign, s)); HIP_TRY(up(H.col_pan, P.col_pan, s));
     HIP_TRY(up(H.lvl_node, P.lvl_node, s)); HIP_TRY(up(H.lvl_pan, P.lvl_pan, s)); HIP_TRY(up(H.lvl_col, P.lvl_col, s));
+    HIP_TRY(up(H.row_lo, P.row_lo, s)); HIP_TRY(up(H.row_nl, P.row_nl, s)); HIP_TRY(up(H.row_boff, P.row_boff, s));
+    HIP_TRY(up(H.col_node, P.col_node, s)); HIP_TRY(up(H.lvl_frow, P.lvl_frow, s));
+    HIP_TRY(up(H.frow_pan, P.frow_pan, s)); HIP_TRY(up(H.pan_frow0, P.pan_frow0, s));
     HIP_TRY(up(H.rp, P.rp, s)); HIP_TRY(up(H.ci, P.ci, s)); HIP_TRY(up(H.cv, P.cv, s));
     HIP_TRY(hipMemsetAsync(c.d_flags, 0, 4 * sizeof(int), s));
     HIP_TRY(hipMemsetAsync((void*)c.M.count, 0, sizeof(int) * c.M.n_sets, s));
@@ -675,6 +705,20 @@ struct emt_ctx {
     std::vector<double> g;
     std::vector<std::vector<std::pair<int, int>>> losses;   // per case: (step, branch), sorted
     int64_t step = 1;
+    unsigned long long* d_applies = nullptr;   // [n_cases] fused-path apply counters
+    int64_t* d_clock = nullptr;
+    int64_t clock_cap = 0;
+    // new-order network data kept for the team plan
+    std::vector<int> inc_ptr, inc_br, src_ptr;
+    std::vector<double> alpha, samp, sph, gC;
+    int engine = 1;              // 1 per-kernel, 2 one workgroup per case, 3 team
+    // team engine
+    bool team_ok = false;
+    int team_nx_cap = 0;
+    std::vector<int> tw_lo, tw_nl, tw_nx, tw_nb, txrow, txzo, txpm, txpc, tozo, topm, topc, topan, txpan, txpos, torp,
+        tocol, tbglob, tbf, tbt, tbown, tiptr, tibr, tsptr;
+    std::vector<double> toval, tbg, tbal, tsamp, tsph;
+    TeamDev TD{};
 };
 
 namespace {
@@ -780,7 +824,52 @@ void carve_emt(emt_ctx& c, Arena& A, int n_src)
     E.step = A.take<int64_t>(1);
     E.done = A.take<unsigned int>(1);
     c.d_rec = A.take<RecParams>(1);
+    c.d_applies = A.take<unsigned long long>(K);
 }
+
+// Network data in the new bus order (kept on the host for uploads and the team plan).
+void prepare_network(emt_ctx& c, const emt_network* net)
+{
+    const Plan& P = c.hc.P;
+    const int n = c.n, nbr = c.nbr;
+    c.fr_p.assign(nbr, 0); c.to_p.assign(nbr, 0); c.g.assign(nbr, 0.0); c.alpha.assign(nbr, 0.0);
+    c.gC.assign(n, 0.0);
+    c.inc_ptr.assign(n + 1, 0);
+    c.inc_br.assign(2 * (size_t)nbr, 0);
+    for (int e = 0; e < nbr; ++e) {
+        c.fr_p[e] = P.iperm[net->from[e]];
+        c.to_p[e] = P.iperm[net->to[e]];
+        const double z2 = 2.0 * net->L[e] / net->dt;
+        c.g[e] = 1.0 / (net->R[e] + z2);
+        c.alpha[e] = c.g[e] * (z2 - net->R[e]);
+        c.inc_ptr[c.fr_p[e] + 1]++;
+        c.inc_ptr[c.to_p[e] + 1]++;
+    }
+    for (int r = 0; r < n; ++r) {
+        c.inc_ptr[r + 1] += c.inc_ptr[r];
+        c.gC[r] = 2.0 * net->C[P.perm[r]] / net->dt;
+    }
+    std::vector<int> fill(c.inc_ptr.begin(), c.inc_ptr.end() - 1);
+    for (int e = 0; e < nbr; ++e) {
+        c.inc_br[fill[c.fr_p[e]]++] = e;
+        c.inc_br[fill[c.to_p[e]]++] = e;
+    }
+    c.src_ptr.assign(n + 1, 0);
+    c.samp.assign(net->n_src, 0.0);
+    c.sph.assign(net->n_src, 0.0);
+    for (int q = 0; q < net->n_src; ++q) c.src_ptr[P.iperm[net->src_bus[q]] + 1]++;
+    for (int r = 0; r < n; ++r) c.src_ptr[r + 1] += c.src_ptr[r];
+    std::vector<int> sf(c.src_ptr.begin(), c.src_ptr.end() - 1);
+    for (int q = 0; q < net->n_src; ++q) {
+        const int r = P.iperm[net->src_bus[q]];
+        c.samp[sf[r]] = net->amp[q];
+        c.sph[sf[r]] = net->phase[q];
+        sf[r]++;
+    }
+}
+
+bool build_team_plan(emt_ctx& c, int R);
+void carve_team(emt_ctx& c, Arena& A);
 
 hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_options* o, const emt_cases* C,
                      emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv, size_t* bytes)
@@ -804,10 +893,229 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
     c.hc.opt = *o;
     // scratch columns: one per case per step, one per loss at creation, a full change set later
     c.hc.opt.max_nrhs = std::max(std::max(c.n_cases, c.R), std::max(total_losses, 1));
+    prepare_network(c, N);
     Arena A;
     carve_hier(c.hc, A, c.n_cases, c.R, c.hc.opt.max_nrhs);
     carve_emt(c, A, N->n_src);
+    // engine
+    const int mode = o->kernel_mode;
+    c.team_ok = false;
+    if (mode == 0 || mode == 3) {
+        c.team_nx_cap = 0;
+        if (build_team_plan(c, c.R)) {
+            c.team_nx_cap = c.TD.NX + 2 * c.R;      // room for the endpoints of later line losses
+            c.team_ok = build_team_plan(c, c.R);
+        }
+        if (c.team_ok) carve_team(c, A);
+    }
+    const bool fits = run_fits(c.hc.H);
+    if (mode == 3 && !c.team_ok) return fail(HINV_E_INVALID, "the team engine needs one case, <= 256 leaves and fitting LDS");
+    if (mode == 2 && !fits) return fail(HINV_E_INVALID, "the case does not fit one workgroup's LDS");
+    c.engine = (mode == 1) ? 1 : (mode == 2) ? 2 : (mode == 3) ? 3 : c.team_ok ? 3 : fits ? 2 : 1;
     *bytes = A.off + kAlign;
+    return HINV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Team plan: per-leaf tables of the team engine (one case; see k_team.hip).
+bool build_team_plan(emt_ctx& c, int R)
+{
+    const Plan& P = c.hc.P;
+    const int L = (int)P.leaf_lo.size(), H = P.n_levels, n = c.n;
+    const int NC = (int)P.col_row.size();
+    if (c.n_cases != 1 || L < 1 || L > 256) return false;
+    // panel of every leaf's rows at every level
+    std::vector<int> lpan((size_t)L * std::max(H, 1), -1);
+    for (int l = 0; l < L; ++l) {
+        for (int k = 0; k < P.anc_stride; ++k) {
+            const int t = P.leaf_anc[(size_t)l * P.anc_stride + k];
+            if (t < 0) break;
+            const int h = P.node_level[t];
+            for (int pp = P.node_pan0[t]; pp < P.node_pan0[t] + P.node_npan[t]; ++pp)
+                if (P.pan_lo[pp] <= P.leaf_lo[l] && P.leaf_lo[l] < P.pan_lo[pp] + P.pan_n[pp]) lpan[(size_t)l * H + h - 1] = pp;
+        }
+    }
+    std::vector<int> loss_rows;
+    for (auto& x : c.losses[0]) {
+        loss_rows.push_back(c.fr_p[x.second]);
+        loss_rows.push_back(c.to_p[x.second]);
+    }
+    struct W {
+        std::vector<int> xrow, xzo, xpm, xpc, xpan, ozo, opm, opc, opan, xpos, orp, ocol, bglob, bf, bt, bown, iptr, ibr,
+            sptr;
+        std::vector<double> oval, bg, bal, samp, sph;
+        int xz = 0, zo = 0;
+    };
+    std::vector<W> ws(L);
+    int NL = 1, NX = 1, NB = 1, NE = 1, NI = 1, NS = 1, XZ = 1, ZO = 1;
+    for (int l = 0; l < L; ++l) {
+        W& w = ws[l];
+        const int lo = P.leaf_lo[l], nl = P.leaf_n[l];
+        auto own = [&](int r) { return r >= lo && r < lo + nl; };
+        std::vector<int> X(P.col_row.begin(), P.col_row.end());
+        for (int r = lo; r < lo + nl; ++r)
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
+                if (!own(P.ci[e])) X.push_back(P.ci[e]);
+        for (int r : loss_rows) X.push_back(r);
+        std::sort(X.begin(), X.end());
+        X.erase(std::unique(X.begin(), X.end()), X.end());
+        w.xrow = X;
+        auto xpos_of = [&](int row) { return (int)(std::lower_bound(X.begin(), X.end(), row) - X.begin()); };
+        auto comb = [&](int row) { return own(row) ? row - lo : nl + xpos_of(row); };
+        const int nx = (int)X.size();
+        w.xzo.assign((size_t)nx * H, -1); w.xpm.assign((size_t)nx * H, 0); w.xpc.assign((size_t)nx * H, 0);
+        w.xpan.assign((size_t)nx * H, -1);
+        for (int x = 0; x < nx; ++x) {
+            const int lx = P.row_leaf[X[x]];
+            for (int h = 1; h <= H; ++h) {
+                const int pp = lpan[(size_t)lx * H + h - 1];
+                if (pp < 0) continue;
+                const size_t i = (size_t)x * H + h - 1;
+                w.xpan[i] = pp; w.xzo[i] = w.xz; w.xpm[i] = P.pan_m[pp]; w.xpc[i] = P.pan_col0[pp];
+                w.xz += P.pan_m[pp];
+            }
+        }
+        w.ozo.assign(H, -1); w.opm.assign(H, 0); w.opc.assign(H, 0); w.opan.assign(H, -1);
+        for (int h = 1; h <= H; ++h) {
+            const int pp = lpan[(size_t)l * H + h - 1];
+            if (pp < 0) continue;
+            w.opan[h - 1] = pp; w.ozo[h - 1] = w.zo; w.opm[h - 1] = P.pan_m[pp]; w.opc[h - 1] = P.pan_col0[pp];
+            w.zo += P.pan_m[pp] * nl;
+        }
+        w.xpos.resize(NC);
+        for (int g = 0; g < NC; ++g) w.xpos[g] = xpos_of(P.col_row[g]);
+        w.orp.assign(nl + 1, 0);
+        for (int r = lo; r < lo + nl; ++r) {
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
+                w.ocol.push_back(comb(P.ci[e]));
+                w.oval.push_back(P.cv[e]);
+            }
+            w.orp[r - lo + 1] = (int)w.ocol.size();
+        }
+        // incident branches (global order of first appearance in the incidence lists)
+        std::vector<int> br;
+        for (int r = lo; r < lo + nl; ++r)
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q) br.push_back(c.inc_br[q]);
+        std::sort(br.begin(), br.end());
+        br.erase(std::unique(br.begin(), br.end()), br.end());
+        for (int e : br) {
+            w.bglob.push_back(e);
+            w.bf.push_back(comb(c.fr_p[e]));
+            w.bt.push_back(comb(c.to_p[e]));
+            w.bown.push_back(own(c.fr_p[e]) ? 1 : 0);
+            w.bg.push_back(c.g[e]);
+            w.bal.push_back(c.alpha[e]);
+        }
+        w.iptr.assign(nl + 1, 0);
+        w.sptr.assign(nl + 1, 0);
+        for (int r = lo; r < lo + nl; ++r) {
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q)
+                w.ibr.push_back((int)(std::lower_bound(br.begin(), br.end(), c.inc_br[q]) - br.begin()));
+            w.iptr[r - lo + 1] = (int)w.ibr.size();
+            for (int q = c.src_ptr[r]; q < c.src_ptr[r + 1]; ++q) {
+                w.samp.push_back(c.samp[q]);
+                w.sph.push_back(c.sph[q]);
+            }
+            w.sptr[r - lo + 1] = (int)w.samp.size();
+        }
+        NL = std::max(NL, nl); NX = std::max(NX, nx); NB = std::max(NB, (int)br.size());
+        NE = std::max(NE, (int)w.ocol.size()); NI = std::max(NI, (int)w.ibr.size());
+        NS = std::max(NS, (int)w.samp.size()); XZ = std::max(XZ, w.xz); ZO = std::max(ZO, w.zo);
+    }
+    (void)n;
+    if (c.team_nx_cap > 0 && NX > c.team_nx_cap) return false;
+    TeamDev& D = c.TD;
+    D.T = L; D.H = H; D.NL = NL; D.NX = NX; D.NB = NB; D.NE = NE; D.NI = NI; D.NS = NS; D.XZ = XZ; D.ZO = ZO;
+    D.nc = NC;
+    D.sent = (int)P.s_entries;
+    if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
+    const int Hs = std::max(H, 1);
+    (void)Hs;
+    auto flat = [&](std::vector<int>& dst, size_t stride, auto get) {
+        dst.assign((size_t)L * stride, 0);
+        for (int l = 0; l < L; ++l) {
+            const std::vector<int>& src = get(ws[l]);
+            std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
+        }
+    };
+    auto flatd = [&](std::vector<double>& dst, size_t stride, auto get) {
+        dst.assign((size_t)L * stride, 0.0);
+        for (int l = 0; l < L; ++l) {
+            const std::vector<double>& src = get(ws[l]);
+            std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
+        }
+    };
+    const int NXc = c.team_nx_cap > 0 ? c.team_nx_cap : NX;
+    c.tw_lo = P.leaf_lo; c.tw_nl = P.leaf_n;
+    c.tw_nx.resize(L); c.tw_nb.resize(L);
+    for (int l = 0; l < L; ++l) { c.tw_nx[l] = (int)ws[l].xrow.size(); c.tw_nb[l] = (int)ws[l].bglob.size(); }
+    // X-row tables use the capacity stride so that a later rebuild fits the carve
+    flat(c.txrow, NXc, [](W& w) -> std::vector<int>& { return w.xrow; });
+    flat(c.txzo, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xzo; });
+    flat(c.txpm, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpm; });
+    flat(c.txpc, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpc; });
+    flat(c.txpan, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpan; });
+    flat(c.tozo, H, [](W& w) -> std::vector<int>& { return w.ozo; });
+    flat(c.topm, H, [](W& w) -> std::vector<int>& { return w.opm; });
+    flat(c.topc, H, [](W& w) -> std::vector<int>& { return w.opc; });
+    flat(c.topan, H, [](W& w) -> std::vector<int>& { return w.opan; });
+    flat(c.txpos, NC, [](W& w) -> std::vector<int>& { return w.xpos; });
+    flat(c.torp, NL + 1, [](W& w) -> std::vector<int>& { return w.orp; });
+    flat(c.tocol, NE, [](W& w) -> std::vector<int>& { return w.ocol; });
+    flat(c.tbglob, NB, [](W& w) -> std::vector<int>& { return w.bglob; });
+    flat(c.tbf, NB, [](W& w) -> std::vector<int>& { return w.bf; });
+    flat(c.tbt, NB, [](W& w) -> std::vector<int>& { return w.bt; });
+    flat(c.tbown, NB, [](W& w) -> std::vector<int>& { return w.bown; });
+    flat(c.tiptr, NL + 1, [](W& w) -> std::vector<int>& { return w.iptr; });
+    flat(c.tibr, NI, [](W& w) -> std::vector<int>& { return w.ibr; });
+    flat(c.tsptr, NL + 1, [](W& w) -> std::vector<int>& { return w.sptr; });
+    flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
+    flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
+    flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
+    flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
+    flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
+    D.NX = NXc;   // strides of the device tables (and the LDS layout)
+    if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
+    return true;
+}
+
+// Workspace for the team tables (sizes from the current plan, X rows with capacity).
+void carve_team(emt_ctx& c, Arena& A)
+{
+    TeamDev& D = c.TD;
+    const int64_t L = D.T, H = D.H;
+    auto ti = [&](size_t cnt) { return A.take<int>((int64_t)cnt); };
+    auto td = [&](size_t cnt) { return A.take<double>((int64_t)cnt); };
+    D.w_lo = ti(L); D.w_nl = ti(L); D.w_nx = ti(L); D.w_nb = ti(L);
+    D.xrow = ti(L * D.NX); D.xzo = ti(L * D.NX * H); D.xpm = ti(L * D.NX * H); D.xpc = ti(L * D.NX * H);
+    D.xpan = ti(L * D.NX * H);
+    D.ozo = ti(L * H); D.opm = ti(L * H); D.opc = ti(L * H); D.opan = ti(L * H);
+    D.xpos = ti(L * D.nc);
+    D.orp = ti(L * (D.NL + 1)); D.ocol = ti(L * D.NE); D.oval = td(L * D.NE);
+    D.bglob = ti(L * D.NB); D.bf = ti(L * D.NB); D.bt = ti(L * D.NB); D.bown = ti(L * D.NB);
+    D.bg = td(L * D.NB); D.bal = td(L * D.NB);
+    D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
+    D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
+    D.sync = A.take<unsigned int>(2);
+    D.X0 = td(2 * (size_t)c.n);
+}
+
+hinv_status upload_team(emt_ctx& c, hipStream_t s)
+{
+    TeamDev& D = c.TD;
+    HIP_TRY(up(D.w_lo, c.tw_lo, s)); HIP_TRY(up(D.w_nl, c.tw_nl, s)); HIP_TRY(up(D.w_nx, c.tw_nx, s));
+    HIP_TRY(up(D.w_nb, c.tw_nb, s));
+    HIP_TRY(up(D.xrow, c.txrow, s)); HIP_TRY(up(D.xzo, c.txzo, s)); HIP_TRY(up(D.xpm, c.txpm, s));
+    HIP_TRY(up(D.xpc, c.txpc, s)); HIP_TRY(up(D.xpan, c.txpan, s));
+    HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.opc, c.topc, s));
+    HIP_TRY(up(D.opan, c.topan, s)); HIP_TRY(up(D.xpos, c.txpos, s));
+    HIP_TRY(up(D.orp, c.torp, s)); HIP_TRY(up(D.ocol, c.tocol, s)); HIP_TRY(up(D.oval, c.toval, s));
+    HIP_TRY(up(D.bglob, c.tbglob, s)); HIP_TRY(up(D.bf, c.tbf, s)); HIP_TRY(up(D.bt, c.tbt, s));
+    HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
+    HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
+    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
+    HIP_TRY(hipMemsetAsync(D.sync, 0, 2 * sizeof(unsigned int), s));
+    HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;
 }
 
@@ -921,57 +1229,23 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     A.base = (char*)d_ws;
     carve_hier(c->hc, A, c->n_cases, c->R, c->hc.opt.max_nrhs);
     carve_emt(*c, A, net->n_src);
+    if (c->team_ok) carve_team(*c, A);
+    if (A.off > ws_bytes) return fail(HINV_E_NO_MEMORY, "workspace layout exceeds %zu bytes", ws_bytes);
     c->hc.M.R = c->R;
-    // network arrays in the new bus order
-    const Plan& P = c->hc.P;
-    const int n = c->n, nbr = c->nbr;
-    c->fr_p.resize(nbr);
-    c->to_p.resize(nbr);
-    c->g.resize(nbr);
-    std::vector<double> alpha(nbr), gC(n);
-    std::vector<int> inc_ptr(n + 1, 0), inc_br(2 * (size_t)nbr);
-    for (int e = 0; e < nbr; ++e) {
-        c->fr_p[e] = P.iperm[net->from[e]];
-        c->to_p[e] = P.iperm[net->to[e]];
-        const double z2 = 2.0 * net->L[e] / net->dt;
-        c->g[e] = 1.0 / (net->R[e] + z2);
-        alpha[e] = c->g[e] * (z2 - net->R[e]);
-        inc_ptr[c->fr_p[e] + 1]++;
-        inc_ptr[c->to_p[e] + 1]++;
-    }
-    for (int r = 0; r < n; ++r) {
-        inc_ptr[r + 1] += inc_ptr[r];
-        gC[r] = 2.0 * net->C[P.perm[r]] / net->dt;
-    }
-    {
-        std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
-        for (int e = 0; e < nbr; ++e) {
-            inc_br[fill[c->fr_p[e]]++] = e;
-            inc_br[fill[c->to_p[e]]++] = e;
-        }
-    }
-    std::vector<int> src_ptr(n + 1, 0);
-    std::vector<double> samp(net->n_src), sph(net->n_src);
-    for (int q = 0; q < net->n_src; ++q) src_ptr[P.iperm[net->src_bus[q]] + 1]++;
-    for (int r = 0; r < n; ++r) src_ptr[r + 1] += src_ptr[r];
-    {
-        std::vector<int> fill(src_ptr.begin(), src_ptr.end() - 1);
-        for (int q = 0; q < net->n_src; ++q) {
-            const int r = P.iperm[net->src_bus[q]];
-            samp[fill[r]] = net->amp[q];
-            sph[fill[r]] = net->phase[q];
-            fill[r]++;
-        }
-    }
     EmtDev& E = c->E;
     E.dt = net->dt;
     E.omega = 2.0 * M_PI * net->freq;
     E.perm = c->hc.d_perm;
     HIP_TRY(up(E.fr, c->fr_p, s)); HIP_TRY(up(E.to, c->to_p, s)); HIP_TRY(up(E.g, c->g, s));
-    HIP_TRY(up(E.alpha, alpha, s)); HIP_TRY(up(E.gC, gC, s));
-    HIP_TRY(up(E.inc_ptr, inc_ptr, s)); HIP_TRY(up(E.inc_br, inc_br, s));
-    HIP_TRY(up(E.src_ptr, src_ptr, s)); HIP_TRY(up(E.src_amp, samp, s)); HIP_TRY(up(E.src_ph, sph, s));
-    st = build_device(c->hc, s);        // synchronises: the host vectors above may go
+    HIP_TRY(up(E.alpha, c->alpha, s)); HIP_TRY(up(E.gC, c->gC, s));
+    HIP_TRY(up(E.inc_ptr, c->inc_ptr, s)); HIP_TRY(up(E.inc_br, c->inc_br, s));
+    HIP_TRY(up(E.src_ptr, c->src_ptr, s)); HIP_TRY(up(E.src_amp, c->samp, s)); HIP_TRY(up(E.src_ph, c->sph, s));
+    st = build_device(c->hc, s);        // synchronises
+    if (st != HINV_OK) return st;
+    if (c->team_ok) {
+        st = upload_team(*c, s);
+        if (st != HINV_OK) return st;
+    }
     if (st != HINV_OK) return st;
     std::vector<int> all(c->n_cases);
     for (int k = 0; k < c->n_cases; ++k) all[k] = k;
@@ -979,6 +1253,7 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     if (st != HINV_OK) return st;
     launch_emt_init(E, s);
     launch_set_rec(c->d_rec, RecParams{nullptr, nullptr, 0, 0}, s);
+    HIP_TRY(hipMemsetAsync(c->d_applies, 0, sizeof(unsigned long long) * c->n_cases, s));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     c->step = 1;
@@ -993,6 +1268,16 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
     if (n_steps == 0) return HINV_OK;
     emt_ctx& c = *h;
     hipStream_t s = (hipStream_t)stream;
+    if (c.engine != 1) {
+        RunParams P{c.step, n_steps, c.hc.opt.max_refine, c.hc.opt.rel_tol, c.hc.opt.warm_start ? 1 : 0,
+                    d_v_record, d_b_record, c.hc.d_flags, c.hc.stats, c.d_applies, c.d_clock, c.clock_cap};
+        if (c.engine == 3)
+            HIP_TRY(launch_emt_team(c.TD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
+        else
+            HIP_TRY(launch_emt_run(c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
+        c.step += n_steps;
+        return HINV_OK;
+    }
     launch_set_rec(c.d_rec, RecParams{d_v_record, d_b_record, c.step, n_steps}, s);
     for (int i = 0; i < n_steps; ++i) {
         solve_new_order(c.hc, c.E.b, c.E.v, c.n_cases, 1, c.E.step, s);
@@ -1025,6 +1310,19 @@ hinv_status emt_lose_line(emt_handle h, int32_t case_idx, int32_t branch, void* 
         load_case_losses(c, std::vector<int>{case_idx}, s);
         return st;
     }
+    // b of the next step was assembled with the branch still in service
+    launch_emt_rebuild_rhs(c.E, case_idx, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c.engine == 3) {       // the new endpoints must become X rows of every workgroup
+        if (!build_team_plan(c, c.R)) {
+            c.engine = run_fits(c.hc.H) ? 2 : 1;
+            c.team_ok = false;
+        } else {
+            st = upload_team(c, s);
+            if (st != HINV_OK) return st;
+        }
+    }
     return HINV_OK;
 }
 
@@ -1038,7 +1336,13 @@ hinv_status emt_get_step(emt_handle h, int64_t* step)
 hinv_status emt_get_stats(emt_handle h, int64_t* applies, double* max_rel_update)
 {
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
-    if (applies) *applies = h->hc.applies;
+    if (applies) {
+        std::vector<unsigned long long> ap(h->n_cases);
+        HIP_TRY(hipMemcpy(ap.data(), h->d_applies, sizeof(unsigned long long) * h->n_cases, hipMemcpyDeviceToHost));
+        int64_t tot = h->hc.applies;
+        for (auto a : ap) tot += (int64_t)a;
+        *applies = tot;
+    }
     if (max_rel_update) {
         std::vector<unsigned long long> st(h->n_cases);
         HIP_TRY(hipMemcpy(st.data(), h->hc.stats, sizeof(unsigned long long) * h->n_cases, hipMemcpyDeviceToHost));
@@ -1050,6 +1354,24 @@ hinv_status emt_get_stats(emt_handle h, int64_t* applies, double* max_rel_update
         }
         *max_rel_update = m;
     }
+    return HINV_OK;
+}
+
+hinv_status emt_set_step_clock(emt_handle h, int64_t* d_clock, int64_t capacity)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    if (d_clock && capacity < 1) return fail(HINV_E_INVALID, "capacity must be >= 1");
+    h->d_clock = d_clock;
+    h->clock_cap = d_clock ? capacity : 0;
+    return HINV_OK;
+}
+
+hinv_status hinv_wall_clock_khz(int32_t device, int32_t* khz)
+{
+    if (!khz) return fail(HINV_E_INVALID, "khz is NULL");
+    int v = 0;
+    HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, device));
+    *khz = v;
     return HINV_OK;
 }
 

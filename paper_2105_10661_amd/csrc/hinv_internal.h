@@ -60,6 +60,14 @@ struct HierDev {
     const int* lvl_node;
     const int* lvl_pan;
     const int* lvl_col;
+    // fused-kernel lookups
+    const int* row_lo;         // [n] first row of the row's leaf
+    const int* row_nl;         // [n] size of the row's leaf
+    const int64_t* row_boff;   // [n] offset of the row's entry in column 0 of its leaf block
+    const int* col_node;       // [n_cols] internal node of each column
+    const int* lvl_frow;       // [n_levels+1] flat panel-row ranges per level
+    const int* frow_pan;       // [total panel rows] panel of each flat panel row
+    const int* pan_frow0;      // [n_pan] first flat row of each panel
     // G in the new order (CSR)
     const int* rp;
     const int* ci;
@@ -121,13 +129,69 @@ struct RecParams {
     int64_t nsteps;
 };
 
+// Fused stepping launch parameters.
+struct RunParams {
+    int64_t step0;
+    int n_steps;
+    int max_refine;
+    double rel_tol;
+    int warm;
+    double* v_rec;
+    double* b_rec;
+    int* flags;
+    unsigned long long* stats;     // [n_cases] largest final correction ratio
+    unsigned long long* applies;   // [n_cases] applies performed
+    int64_t* clk;                  // optional: wall clock after each step of case 0
+    int64_t clk_cap;
+};
+
+// Team stepping (k_team.hip): one workgroup per leaf of a single case.  All
+// per-workgroup tables use fixed strides (the maxima over workgroups) so the
+// LDS layout is the same in every workgroup.  "Combined" indices: own rows of
+// the leaf are 0..nl-1, the workgroup's external rows ("X rows": coupling
+// column endpoints, tie-line neighbours, line-loss endpoints) are nl + x.
+struct TeamDev {
+    int T, H, NL, NX, NB, NE, NI, NS, XZ, ZO;
+    int nc, sent;        // coupling columns, stored S^{-1} entries (whole hierarchy)
+    const int* w_lo;
+    const int* w_nl;
+    const int* w_nx;
+    const int* w_nb;
+    const int* xrow;     // [T*NX] new-order row of each X row (sorted)
+    const int* xzo;      // [T*NX*H] offset of the row's Z values at level h in the xz region, -1: none
+    const int* xpm;      // [T*NX*H] columns of that panel
+    const int* xpc;      // [T*NX*H] first global column of that panel
+    const int* ozo;      // [T*H] offset of the own rows' Z values at level h in the zown region, -1: none
+    const int* opm;
+    const int* opc;
+    const int* opan;     // [T*H] panel index of the own rows at level h, -1: none
+    const int* xpan;     // [T*NX*H] panel index of each X row at level h, -1: none
+    const int* xpos;     // [T*n_cols] X position of each coupling column's row
+    const int* orp;      // [T*(NL+1)] own CSR rows of G, combined column indices
+    const int* ocol;     // [T*NE]
+    const double* oval;
+    const int* bglob;    // [T*NB] incident branches: global id, endpoints (combined), owner flag
+    const int* bf;
+    const int* bt;
+    const int* bown;
+    const double* bg;
+    const double* bal;
+    const int* iptr;     // [T*(NL+1)] incident local branches of each own row
+    const int* ibr;      // [T*NI]
+    const int* sptr;     // [T*(NL+1)] sources of each own row
+    const double* samp;  // [T*NS]
+    const double* sph;
+    unsigned int* sync;  // [2] barrier counter and generation
+    double* X0;          // [2*n] exchange of leaf results (double-buffered by apply parity)
+};
+
 // Host-side per-level launch sizes (level l = 1..n_levels at index l-1).
 struct LevelHost {
     int nnodes, npan, ncols, max_m, max_pan_rows;
 };
 
 // Status flag bits written by kernels.
-enum : int { kFlagNotSPD = 1, kFlagSingular = 2, kFlagNaN = 4, kFlagNoConv = 8 };
+enum : int { kFlagNotSPD = 1, kFlagSingular = 2, kFlagNaN = 4, kFlagNoConv = 8, kFlagBarrier = 16, kFlagTeamRow = 32 };
 
 // ---------------- kernel launchers (k_build.hip / k_apply.hip / k_emt.hip)
 void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s);
@@ -158,8 +222,18 @@ void launch_residual(const HierDev& H, const ModDev& M, const double* Bv, const 
                      int nrhs, int set_stride, const int64_t* step_ptr, hipStream_t s);
 
 void launch_emt_init(const EmtDev& E, hipStream_t s);
+// Re-assemble the current step's b of case k (after a loss was added for this step).
+void launch_emt_rebuild_rhs(const EmtDev& E, int k, hipStream_t s);
 // Stream-ordered update of the record parameters (kernel argument, no host buffer to keep alive).
 void launch_set_rec(RecParams* d, const RecParams& val, hipStream_t s);
+// Team stepping (k_team.hip): LDS bytes of the layout, and the launch.
+size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec);
+hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
+                           int prec, hipStream_t s);
+// Fused stepping (k_run.hip): one workgroup per case, all steps in one launch.
+bool run_fits(const HierDev& H);
+hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, int prec,
+                          hipStream_t s);
 // History update with v_n and assembly of b_{n+1}; records; advances *E.step.
 void launch_emt_history(const EmtDev& E, const RecParams* rec, hipStream_t s);
 

@@ -116,6 +116,33 @@ void launch_emt_history(const EmtDev& E, const RecParams* rec, hipStream_t s)
     hipLaunchKernelGGL(k_emt_history, dim3((E.n + kBlock - 1) / kBlock, E.n_cases), dim3(kBlock), 0, s, E, rec);
 }
 
+// Re-assemble b of the current step for case k from the stored histories,
+// after a line loss was added for this step: b_a = i_in,a(t_n) - sum_e A[a,e] h_e^n
+// - hC_a^n, with lost branches contributing nothing (same operation order as
+// k_emt_history, so the result equals a loss scheduled in advance).
+__global__ __launch_bounds__(kBlock) void k_emt_rebuild_rhs(EmtDev E, int k)
+{
+    const int64_t step = *E.step;
+    const int64_t base = (int64_t)k * E.n;
+    double* hcur = E.h + (int64_t)(step & 1) * E.n_cases * E.nbr + (int64_t)k * E.nbr;
+    for (int a = blockIdx.x * kBlock + threadIdx.x; a < E.n; a += gridDim.x * kBlock) {
+        double bn = source_at(E, a, (double)step * E.dt);
+        for (int q = E.inc_ptr[a]; q < E.inc_ptr[a + 1]; ++q) {
+            const int e = E.inc_br[q];
+            const int f = E.fr[e];
+            const double hn = lost_by(E, k, e, step) ? 0.0 : hcur[e];
+            bn -= (a == f) ? hn : -hn;
+        }
+        bn -= E.hC[base + a];
+        E.b[base + a] = bn;
+    }
+}
+
+void launch_emt_rebuild_rhs(const EmtDev& E, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_emt_rebuild_rhs, dim3((E.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, E, k);
+}
+
 __global__ void k_set_rec(RecParams* d, RecParams val) { *d = val; }
 
 void launch_set_rec(RecParams* d, const RecParams& val, hipStream_t s)

@@ -1,0 +1,328 @@
+// Fused EMT stepping: one workgroup owns one case and advances it through
+// all requested time steps in a single launch (paper Section II, Eq. (1)-(2)
+// per step; Section IV's line change as the SMW correction).
+//
+// Per step, inside the workgroup:
+//   apply        v0 = B^{-1} b leaf by leaf, then every coupling level bottom-up
+//                (s = U^T v, y = S^{-1} s, v -= Z y), then the active line
+//                changes v -= U_m C_m^{-1} W_m^T v;
+//   refinement   (low-precision storage) t = b - G v in FP64, v += P t, until the
+//                correction is below rel_tol * |v| or max_refine corrections;
+//                optionally warm-started from the previous step's v;
+//   history      trapezoidal history currents with v_n and b_{n+1}.
+// The case's vectors b (right-hand side), v (solution), t (residual) and d
+// (correction) live in LDS for the whole launch; the stored
+// inverse (shared by all cases of the network) streams from L2.  Nothing is
+// exchanged between workgroups, so the same kernel runs one case or a batch
+// (one workgroup per case), and every case's arithmetic is independent of the
+// batch it runs in.
+//
+// Thread layout (1024 threads): four lanes per row share the columns of the
+// row's leaf-block dot product (reduced with lane shuffles), a wavefront covers
+// 16 consecutive rows, so each column of a block is read as 128-byte runs.
+#include "hinv_internal.h"
+
+namespace hinv {
+
+constexpr int kRunThreads = 1024;
+constexpr int kChunks = 4;
+constexpr int kRowsPerPass = kRunThreads / kChunks;
+
+template <typename TB>
+struct Acc { using T = float; };
+template <>
+struct Acc<double> { using T = double; };
+
+__device__ inline double block_max(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double m = red[0];
+    for (int w = 1; w < kRunThreads / 64; ++w) m = fmax(m, red[w]);
+    __syncthreads();
+    return m;
+}
+
+// out = B^{-1} x over all leaves (x, out: distinct LDS vectors).
+template <typename TB>
+__device__ void wg_leaf_apply(const HierDev& H, const TB* __restrict__ blk, const double* x, double* out)
+{
+    using TA = typename Acc<TB>::T;
+    const int c = threadIdx.x & (kChunks - 1);
+    const int rsub = threadIdx.x / kChunks;
+    for (int r0 = 0; r0 < H.n; r0 += kRowsPerPass) {
+        const int r = r0 + rsub;
+        TA acc = 0;
+        if (r < H.n) {
+            const int lo = H.row_lo[r], nl = H.row_nl[r];
+            const TB* Bp = blk + H.row_boff[r];
+            const double* xl = x + lo;
+            int j = c;
+            for (; j + 3 * kChunks < nl; j += 4 * kChunks) {
+                const TA b0 = (TA)Bp[(int64_t)j * nl];
+                const TA b1 = (TA)Bp[(int64_t)(j + kChunks) * nl];
+                const TA b2 = (TA)Bp[(int64_t)(j + 2 * kChunks) * nl];
+                const TA b3 = (TA)Bp[(int64_t)(j + 3 * kChunks) * nl];
+                acc += b0 * (TA)xl[j];
+                acc += b1 * (TA)xl[j + kChunks];
+                acc += b2 * (TA)xl[j + 2 * kChunks];
+                acc += b3 * (TA)xl[j + 3 * kChunks];
+            }
+            for (; j < nl; j += kChunks) acc += (TA)Bp[(int64_t)j * nl] * (TA)xl[j];
+        }
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        if (r < H.n && c == 0) out[r] = (double)acc;
+    }
+    __syncthreads();
+}
+
+// Coupling levels bottom-up on out (LDS).  s, y: LDS scratch of n_cols.
+template <typename TB>
+__device__ void wg_levels(const HierDev& H, const TB* __restrict__ Z, const TB* __restrict__ Sinv, double* out,
+                          double* s, double* y)
+{
+    using TA = typename Acc<TB>::T;
+    const int tid = threadIdx.x;
+    for (int h = 1; h <= H.n_levels; ++h) {
+        const int c0 = H.lvl_col[h - 1], c1 = H.lvl_col[h];
+        if (c1 == c0) continue;
+        for (int g = c0 + tid; g < c1; g += kRunThreads) s[g] = H.col_w[g] * out[H.col_row[g]];
+        __syncthreads();
+        for (int g = c0 + tid; g < c1; g += kRunThreads) {
+            const int t = H.col_node[g];
+            const int m = H.node_m[t], nc0 = H.node_col0[t], q = g - nc0;
+            const TB* Si = Sinv + H.node_soff[t];
+            TA acc = 0;
+            for (int pp = 0; pp < m; ++pp) acc += (TA)Si[(int64_t)pp * m + q] * (TA)s[nc0 + pp];
+            y[g] = (double)acc;
+        }
+        __syncthreads();
+        const int f0 = H.lvl_frow[h - 1], f1 = H.lvl_frow[h];
+        for (int f = f0 + tid; f < f1; f += kRunThreads) {
+            const int P = H.frow_pan[f];
+            const int i = f - H.pan_frow0[P];
+            const int pn = H.pan_n[P], pm = H.pan_m[P], pc0 = H.pan_col0[P];
+            const TB* Zp = Z + H.pan_zoff[P] + i;
+            TA acc = 0;
+            for (int j = 0; j < pm; ++j) acc += (TA)Zp[(int64_t)j * pn] * (TA)y[pc0 + j];
+            out[H.pan_lo[P] + i] -= (double)acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Active line changes of case k at `step` on out (LDS).
+template <typename TU>
+__device__ void wg_smw(const ModDev& M, const TU* __restrict__ U, int k, int64_t step, double* out, double* tz)
+{
+    const int cnt = M.count[k];
+    int r = 0;
+    while (r < cnt && (int64_t)M.act[k * M.R + r] <= step) ++r;
+    if (r == 0) return;
+    const int tid = threadIdx.x;
+    if (tid < r) {
+        const int a = M.a[k * M.R + tid], b = M.b[k * M.R + tid];
+        tz[tid] = out[a] - (b >= 0 ? out[b] : 0.0);
+    }
+    __syncthreads();
+    if (tid < r) {
+        const double* Ci = M.Cinv + ((int64_t)k * M.R + (r - 1)) * M.R * M.R;
+        double acc = 0.0;
+        for (int j = 0; j < r; ++j) acc += Ci[tid * M.R + j] * tz[j];
+        tz[kMaxModRank + tid] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < M.n; i += kRunThreads) {
+        double acc = 0.0;
+        for (int j = 0; j < r; ++j) acc += (double)U[((int64_t)k * M.R + j) * M.n + i] * tz[kMaxModRank + j];
+        out[i] -= acc;
+    }
+    __syncthreads();
+}
+
+template <typename TB>
+__device__ void wg_precond(const HierDev& H, const ModDev& M, const TB* blk, const TB* Z, const TB* Sinv,
+                           const TB* U, int k, int64_t step, const double* x, double* out, double* s, double* y,
+                           double* tz)
+{
+    wg_leaf_apply<TB>(H, blk, x, out);
+    wg_levels<TB>(H, Z, Sinv, out, s, y);
+    if (M.R > 0) wg_smw<TB>(M, U, k, step, out, tz);
+}
+
+// t = b - G_step v (FP64, LDS vectors).
+__device__ void wg_residual(const HierDev& H, const ModDev& M, int k, int64_t step, const double* b, const double* v,
+                            double* t)
+{
+    int r = 0;
+    if (M.R > 0) {
+        const int cnt = M.count[k];
+        while (r < cnt && (int64_t)M.act[k * M.R + r] <= step) ++r;
+    }
+    for (int i = threadIdx.x; i < H.n; i += kRunThreads) {
+        double acc = 0.0;
+        for (int e = H.rp[i]; e < H.rp[i + 1]; ++e) acc += H.cv[e] * v[H.ci[e]];
+        for (int j = 0; j < r; ++j) {
+            const int a = M.a[k * M.R + j], bb = M.b[k * M.R + j];
+            if (i != a && i != bb) continue;
+            const double wv = v[a] - (bb >= 0 ? v[bb] : 0.0);
+            acc += (i == a ? 1.0 : -1.0) * M.dg[k * M.R + j] * wv;
+        }
+        t[i] = b[i] - acc;
+    }
+    __syncthreads();
+}
+
+__device__ inline bool run_lost_by(const EmtDev& E, int k, int e, int64_t step)
+{
+    const int cnt = E.loss_cnt[k];
+    for (int j = 0; j < cnt; ++j)
+        if (E.loss_br[k * E.R + j] == e && (int64_t)E.loss_step[k * E.R + j] <= step) return true;
+    return false;
+}
+
+template <typename TB, bool MIXED, bool WARM>
+__global__ __launch_bounds__(kRunThreads) void k_emt_run(EmtDev E, HierDev H, ModDev M, RunParams P)
+{
+    extern __shared__ double lds[];
+    const int n = H.n;
+    const int k = blockIdx.x;
+    double* b = lds;
+    double* v = b + n;
+    double* t = v + n;
+    double* d = t + n;
+    double* s = d + n;
+    double* y = s + H.n_cols;
+    double* red = y + H.n_cols;          // 16
+    double* tz = red + 16;               // 2 * kMaxModRank
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)k * n;
+    const TB* blk;
+    const TB* Zs;
+    const TB* Si;
+    const TB* U;
+    if constexpr (sizeof(TB) == 8) {
+        blk = (const TB*)H.blk; Zs = (const TB*)H.Z; Si = (const TB*)H.Sinv; U = (const TB*)M.U;
+    } else {
+        blk = (const TB*)H.blk32; Zs = (const TB*)H.Z32; Si = (const TB*)H.Sinv32; U = (const TB*)M.U32;
+    }
+    for (int i = tid; i < n; i += kRunThreads) {
+        b[i] = E.b[base + i];
+        v[i] = E.v[base + i];
+    }
+    __syncthreads();
+    double worst = 0.0;
+    int64_t applies = 0;
+    for (int it = 0; it < P.n_steps; ++it) {
+        const int64_t step = P.step0 + it;
+        // ---- solve G_step v = b
+        if (!MIXED) {
+            wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz);
+            applies += 1;
+        } else {
+            int done = 0;
+            if (!WARM) {
+                wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz);
+                applies += 1;
+            }
+            for (int rf = 0; rf < P.max_refine + (WARM ? 1 : 0) && !done; ++rf) {
+                wg_residual(H, M, k, step, b, v, t);
+                wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, t, d, s, y, tz);
+                applies += 1;
+                double dmax = 0.0, vmax = 0.0;
+                for (int i = tid; i < n; i += kRunThreads) {
+                    const double nv = v[i] + d[i];
+                    v[i] = nv;
+                    dmax = fmax(dmax, fabs(d[i]));
+                    vmax = fmax(vmax, fabs(nv));
+                }
+                dmax = block_max(dmax, red);
+                vmax = block_max(vmax, red);
+                const double ratio = vmax > 0.0 ? dmax / vmax : (dmax > 0.0 ? INFINITY : 0.0);
+                if (!isfinite(ratio)) {
+                    if (tid == 0) atomicOr(P.flags, kFlagNaN);
+                    done = 1;
+                } else if (ratio <= P.rel_tol) {
+                    done = 1;
+                    worst = fmax(worst, ratio);
+                } else if (rf == P.max_refine + (WARM ? 1 : 0) - 1) {
+                    if (tid == 0) atomicOr(P.flags, kFlagNoConv);
+                    worst = fmax(worst, ratio);
+                }
+            }
+        }
+        // ---- history update with v_step, right-hand side of step+1, records
+        const double* hcur = E.h + (int64_t)(step & 1) * E.n_cases * E.nbr + (int64_t)k * E.nbr;
+        double* hnext = E.h + (int64_t)((step + 1) & 1) * E.n_cases * E.nbr + (int64_t)k * E.nbr;
+        const int64_t j = step - P.step0;
+        for (int a = tid; a < n; a += kRunThreads) {
+            const double va = v[a];
+            double bn = 0.0;
+            for (int q = E.src_ptr[a]; q < E.src_ptr[a + 1]; ++q)
+                bn += E.src_amp[q] * sin(E.omega * ((double)(step + 1) * E.dt) + E.src_ph[q]);
+            for (int q = E.inc_ptr[a]; q < E.inc_ptr[a + 1]; ++q) {
+                const int e = E.inc_br[q];
+                const int f = E.fr[e], to = E.to[e];
+                double hn = 0.0;
+                if (!run_lost_by(E, k, e, step + 1)) {
+                    const double vft = v[f] - v[to];
+                    const double ie = E.g[e] * vft + hcur[e];
+                    hn = E.g[e] * vft + E.alpha[e] * ie;
+                }
+                bn -= (a == f) ? hn : -hn;
+                if (a == f) hnext[e] = hn;
+            }
+            const double ic = E.gC[a] * va + E.hC[base + a];
+            const double hcn = -E.gC[a] * va - ic;
+            E.hC[base + a] = hcn;
+            bn -= hcn;
+            const int64_t o = (j * E.n_cases + k) * (int64_t)n + E.perm[a];
+            if (P.v_rec) P.v_rec[o] = va;
+            if (P.b_rec) P.b_rec[o] = b[a];
+            b[a] = bn;
+        }
+        __syncthreads();
+        if (P.clk && k == 0 && tid == 0 && j < P.clk_cap) P.clk[j] = (int64_t)wall_clock64();
+    }
+    for (int i = tid; i < n; i += kRunThreads) {
+        E.b[base + i] = b[i];
+        E.v[base + i] = v[i];
+    }
+    if (tid == 0) {
+        if (MIXED && P.stats) atomicMax(&P.stats[k], (unsigned long long)__double_as_longlong(worst));
+        if (P.applies) atomicAdd(&P.applies[k], (unsigned long long)applies);
+        if (k == 0) *E.step = P.step0 + P.n_steps;
+    }
+}
+
+size_t run_lds_bytes(const HierDev& H)
+{
+    return sizeof(double) * (4 * (size_t)H.n + 2 * (size_t)H.n_cols + 16 + 2 * kMaxModRank);
+}
+
+bool run_fits(const HierDev& H) { return run_lds_bytes(H) <= 160 * 1024; }
+
+template <typename TB, bool MIXED, bool WARM>
+static hipError_t launch_run_t(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, hipStream_t s)
+{
+    const size_t lds = run_lds_bytes(H);
+    hipError_t e = hipFuncSetAttribute((const void*)k_emt_run<TB, MIXED, WARM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_emt_run<TB, MIXED, WARM>), dim3(E.n_cases), dim3(kRunThreads), lds, s, E, H, M, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, int prec,
+                          hipStream_t s)
+{
+    if (prec == HINV_FP64) return launch_run_t<double, false, false>(E, H, M, P, s);
+    if (P.warm) return launch_run_t<float, true, true>(E, H, M, P, s);
+    return launch_run_t<float, true, false>(E, H, M, P, s);
+}
+
+}  // namespace hinv

@@ -1,0 +1,540 @@
+// Team stepping of one EMT case: one workgroup per leaf of the partition
+// tree, all steps in one cooperative launch (paper Section II, Eq. (1)-(2);
+// coupling levels as in Section III.B made exact; line changes as the SMW
+// correction standing in for Section IV's update).
+//
+// Each workgroup holds in LDS: its leaf block B_l^{-1}, every capacitance
+// inverse S_t^{-1}, the Z-panel rows of its own buses and of its "X rows"
+// (coupling-column endpoints, tie-line neighbours, line-loss endpoints), the
+// SMW vectors at those rows, and the case state of its buses.  Per apply:
+//   1. own rows: v0 = B_l^{-1} x (LDS GEMV), published in a global exchange
+//      vector (double-buffered by apply parity);
+//   2. one team barrier;
+//   3. every workgroup reads v0 at its X rows and computes, redundantly, every
+//      level's y = S^{-1} U^T v bottom-up, then the corrected values of its own
+//      rows and X rows, then the SMW correction.
+// Rows shared by two workgroups are computed with identical operations in
+// both, so their values agree bitwise and the history update of a tie line
+// (and the refinement residual) needs no second exchange.
+#include "hinv_internal.h"
+
+namespace hinv {
+
+constexpr int kTeamThreads = 256;
+constexpr int kTeamSpinLimit = 1 << 24;
+
+template <typename TB>
+struct TAcc { using T = float; };
+template <>
+struct TAcc<double> { using T = double; };
+
+struct TeamLayout {
+    size_t blk, sall, zown, xz, uown, ux;
+    size_t b, v, t, d, part, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, colw, cinv, mdg, red, tz;
+    size_t xrow, xzo, xpm, xpc, ozo, opm, opc, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
+    size_t lpa, lpb, loa, lob, mact, lbr, lst, ctl;
+    size_t total;
+};
+
+template <typename TB>
+__host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
+{
+    TeamLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = (o + bytes + 15) & ~(size_t)15;
+        return r;
+    };
+    const size_t NL = T.NL, NX = T.NX, H = T.H, nc = T.nc;
+    L.blk = take(sizeof(TB) * NL * NL);
+    L.sall = take(sizeof(TB) * (size_t)T.sent);
+    L.zown = take(sizeof(TB) * (size_t)T.ZO);
+    L.xz = take(sizeof(TB) * (size_t)T.XZ);
+    L.uown = take(sizeof(TB) * R * NL);
+    L.ux = take(sizeof(TB) * R * NX);
+    const size_t D = sizeof(double);
+    L.b = take(D * NL); L.v = take(D * NL); L.t = take(D * NL); L.d = take(D * NL);
+    L.part = take(D * 4 * NL);
+    L.xv = take(D * NX); L.xd = take(D * NX);
+    L.s = take(D * nc); L.y = take(D * nc);
+    L.h0 = take(D * T.NB); L.h1 = take(D * T.NB);
+    L.hC = take(D * NL); L.gC = take(D * NL);
+    L.oval = take(D * T.NE); L.bg = take(D * T.NB); L.bal = take(D * T.NB);
+    L.samp = take(D * T.NS); L.sph = take(D * T.NS);
+    L.colw = take(D * nc);
+    L.cinv = take(D * R * R * R); L.mdg = take(D * R);
+    L.red = take(D * 8); L.tz = take(D * 2 * R);
+    const size_t I = sizeof(int);
+    L.xrow = take(I * NX); L.xzo = take(I * NX * H); L.xpm = take(I * NX * H); L.xpc = take(I * NX * H);
+    L.ozo = take(I * H); L.opm = take(I * H); L.opc = take(I * H);
+    L.xpos = take(I * nc); L.cm = take(I * nc); L.cc0 = take(I * nc); L.cso = take(I * nc);
+    L.lvlc = take(I * (H + 1));
+    L.orp = take(I * (NL + 1)); L.ocol = take(I * T.NE);
+    L.bglob = take(I * T.NB); L.bf = take(I * T.NB); L.bt = take(I * T.NB);
+    L.iptr = take(I * (NL + 1)); L.ibr = take(I * T.NI); L.sptr = take(I * (NL + 1));
+    L.lpa = take(I * R); L.lpb = take(I * R); L.loa = take(I * R); L.lob = take(I * R);
+    L.mact = take(I * R); L.lbr = take(I * R); L.lst = take(I * R);
+    L.ctl = take(I * 8);
+    L.total = o;
+    return L;
+}
+
+size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec)
+{
+    (void)H;
+    return prec == HINV_FP64 ? team_layout<double>(T, R).total : team_layout<float>(T, R).total;
+}
+
+// Barrier of the T workgroups of the team.  Agent-scope release/acquire make
+// every workgroup's global writes before the barrier visible to all after it.
+// The wait is bounded: on time-out it flags kFlagBarrier and returns false.
+__device__ inline bool team_barrier(unsigned int* sync, int T, int* flags, int* ctl)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned int g = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int prev = __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == (unsigned int)(T - 1)) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int spins = 0;
+            while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++spins > kTeamSpinLimit) {
+                    ok = 0;
+                    atomicOr(flags, kFlagBarrier);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        ctl[0] = ok;
+    }
+    __syncthreads();
+    return ctl[0] != 0;
+}
+
+template <typename TB, bool MIXED, bool WARM>
+__global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, HierDev H, ModDev M, RunParams P)
+{
+    using TA = typename TAcc<TB>::T;
+    extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
+    const int R = M.R;
+    const TeamLayout Ly = team_layout<TB>(T, R);
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const int n = H.n, NL = T.NL, NX = T.NX, Hn = T.H, nc = T.nc;
+    const int lo = T.w_lo[w], nl = T.w_nl[w], nx = T.w_nx[w], nb = T.w_nb[w];
+    TB* blk = (TB*)(L8 + Ly.blk);
+    TB* sall = (TB*)(L8 + Ly.sall);
+    TB* zown = (TB*)(L8 + Ly.zown);
+    TB* xz = (TB*)(L8 + Ly.xz);
+    TB* uown = (TB*)(L8 + Ly.uown);
+    TB* ux = (TB*)(L8 + Ly.ux);
+    double* b = (double*)(L8 + Ly.b);
+    double* v = (double*)(L8 + Ly.v);
+    double* t = (double*)(L8 + Ly.t);
+    double* d = (double*)(L8 + Ly.d);
+    double* part = (double*)(L8 + Ly.part);
+    double* xv = (double*)(L8 + Ly.xv);
+    double* xd = (double*)(L8 + Ly.xd);
+    double* s = (double*)(L8 + Ly.s);
+    double* y = (double*)(L8 + Ly.y);
+    double* hc = (double*)(L8 + Ly.h0);
+    double* hn = (double*)(L8 + Ly.h1);
+    double* hC = (double*)(L8 + Ly.hC);
+    double* gC = (double*)(L8 + Ly.gC);
+    double* oval = (double*)(L8 + Ly.oval);
+    double* bg = (double*)(L8 + Ly.bg);
+    double* bal = (double*)(L8 + Ly.bal);
+    double* samp = (double*)(L8 + Ly.samp);
+    double* sph = (double*)(L8 + Ly.sph);
+    double* colw = (double*)(L8 + Ly.colw);
+    double* cinv = (double*)(L8 + Ly.cinv);
+    double* mdg = (double*)(L8 + Ly.mdg);
+    double* red = (double*)(L8 + Ly.red);
+    double* tz = (double*)(L8 + Ly.tz);
+    int* xrow = (int*)(L8 + Ly.xrow);
+    int* xzo = (int*)(L8 + Ly.xzo);
+    int* xpm = (int*)(L8 + Ly.xpm);
+    int* xpc = (int*)(L8 + Ly.xpc);
+    int* ozo = (int*)(L8 + Ly.ozo);
+    int* opm = (int*)(L8 + Ly.opm);
+    int* opc = (int*)(L8 + Ly.opc);
+    int* xpos = (int*)(L8 + Ly.xpos);
+    int* cm = (int*)(L8 + Ly.cm);
+    int* cc0 = (int*)(L8 + Ly.cc0);
+    int* cso = (int*)(L8 + Ly.cso);
+    int* lvlc = (int*)(L8 + Ly.lvlc);
+    int* orp = (int*)(L8 + Ly.orp);
+    int* ocol = (int*)(L8 + Ly.ocol);
+    int* bglob = (int*)(L8 + Ly.bglob);
+    int* bf = (int*)(L8 + Ly.bf);
+    int* bt = (int*)(L8 + Ly.bt);
+    int* iptr = (int*)(L8 + Ly.iptr);
+    int* ibr = (int*)(L8 + Ly.ibr);
+    int* sptr = (int*)(L8 + Ly.sptr);
+    int* lpa = (int*)(L8 + Ly.lpa);
+    int* lpb = (int*)(L8 + Ly.lpb);
+    int* loa = (int*)(L8 + Ly.loa);
+    int* lob = (int*)(L8 + Ly.lob);
+    int* mact = (int*)(L8 + Ly.mact);
+    int* lbr = (int*)(L8 + Ly.lbr);
+    int* lst = (int*)(L8 + Ly.lst);
+    int* ctl = (int*)(L8 + Ly.ctl);
+
+    const TB* gblk;
+    const TB* gS;
+    const TB* gZ;
+    const TB* gU;
+    if constexpr (sizeof(TB) == 8) {
+        gblk = (const TB*)H.blk; gS = (const TB*)H.Sinv; gZ = (const TB*)H.Z; gU = (const TB*)M.U;
+    } else {
+        gblk = (const TB*)H.blk32; gS = (const TB*)H.Sinv32; gZ = (const TB*)H.Z32; gU = (const TB*)M.U32;
+    }
+    // ---------------- load the workgroup's tables and state into LDS
+    {
+        const TB* src = gblk + H.leaf_off[w];
+        for (int i = tid; i < nl * nl; i += kTeamThreads) blk[i] = src[i];
+        for (int i = tid; i < T.sent; i += kTeamThreads) sall[i] = gS[i];
+        const int* wxrow = T.xrow + (int64_t)w * NX;
+        for (int x = tid; x < nx; x += kTeamThreads) xrow[x] = wxrow[x];
+        for (int i = tid; i < nx * Hn; i += kTeamThreads) {
+            const int64_t gi = (int64_t)w * NX * Hn + i;
+            xzo[i] = T.xzo[gi];
+            xpm[i] = T.xpm[gi];
+            xpc[i] = T.xpc[gi];
+            const int zo = T.xzo[gi];
+            if (zo >= 0) {
+                const int P = T.xpan[gi];
+                const int row = wxrow[i / Hn];
+                const TB* zp = gZ + H.pan_zoff[P] + (row - H.pan_lo[P]);
+                for (int j = 0; j < T.xpm[gi]; ++j) xz[zo + j] = zp[(int64_t)j * H.pan_n[P]];
+            }
+        }
+        for (int h = 0; h < Hn; ++h) {
+            const int zo = T.ozo[w * Hn + h];
+            if (tid == 0) { ozo[h] = zo; opm[h] = T.opm[w * Hn + h]; opc[h] = T.opc[w * Hn + h]; }
+            if (zo >= 0) {
+                const int P = T.opan[w * Hn + h], pm = T.opm[w * Hn + h];
+                const TB* zp = gZ + H.pan_zoff[P] + (lo - H.pan_lo[P]);
+                for (int i = tid; i < pm * nl; i += kTeamThreads) {
+                    const int j = i / nl, r = i - j * nl;
+                    zown[zo + i] = zp[(int64_t)j * H.pan_n[P] + r];
+                }
+            }
+        }
+        for (int g = tid; g < nc; g += kTeamThreads) {
+            xpos[g] = T.xpos[(int64_t)w * nc + g];
+            const int node = H.col_node[g];
+            cm[g] = H.node_m[node];
+            cc0[g] = H.node_col0[node];
+            cso[g] = (int)H.node_soff[node];
+            colw[g] = H.col_w[g];
+        }
+        for (int h = tid; h <= Hn; h += kTeamThreads) lvlc[h] = H.lvl_col[h];
+        const int* worp = T.orp + (int64_t)w * (NL + 1);
+        for (int r = tid; r <= nl; r += kTeamThreads) {
+            orp[r] = worp[r];
+            iptr[r] = T.iptr[(int64_t)w * (NL + 1) + r];
+            sptr[r] = T.sptr[(int64_t)w * (NL + 1) + r];
+        }
+        for (int e = tid; e < worp[nl]; e += kTeamThreads) {
+            ocol[e] = T.ocol[(int64_t)w * T.NE + e];
+            oval[e] = T.oval[(int64_t)w * T.NE + e];
+        }
+        for (int q = tid; q < nb; q += kTeamThreads) {
+            const int64_t gq = (int64_t)w * T.NB + q;
+            bglob[q] = T.bglob[gq];
+            bf[q] = T.bf[gq];
+            bt[q] = T.bt[gq];
+            bg[q] = T.bg[gq];
+            bal[q] = T.bal[gq];
+            hc[q] = E.h[(int64_t)(P.step0 & 1) * E.n_cases * E.nbr + T.bglob[gq]];
+        }
+        for (int i = tid; i < T.iptr[(int64_t)w * (NL + 1) + nl]; i += kTeamThreads) ibr[i] = T.ibr[(int64_t)w * T.NI + i];
+        for (int i = tid; i < T.sptr[(int64_t)w * (NL + 1) + nl]; i += kTeamThreads) {
+            samp[i] = T.samp[(int64_t)w * T.NS + i];
+            sph[i] = T.sph[(int64_t)w * T.NS + i];
+        }
+        for (int r = tid; r < nl; r += kTeamThreads) {
+            b[r] = E.b[lo + r];
+            v[r] = E.v[lo + r];
+            hC[r] = E.hC[lo + r];
+            gC[r] = E.gC[lo + r];
+        }
+        for (int x = tid; x < nx; x += kTeamThreads) xv[x] = E.v[wxrow[x]];
+        // line changes of the case (case 0): activation steps, endpoints as X / own indices
+        const int cnt = R > 0 ? M.count[0] : 0;
+        if (tid == 0) ctl[1] = cnt;
+        if (tid < cnt) {
+            mact[tid] = M.act[tid];
+            mdg[tid] = M.dg[tid];
+            const int a = M.a[tid], bb = M.b[tid];
+            int pa = -1, pb = -1;
+            for (int x = 0; x < nx; ++x) {
+                if (wxrow[x] == a) pa = x;
+                if (wxrow[x] == bb) pb = x;
+            }
+            lpa[tid] = pa;
+            lpb[tid] = bb >= 0 ? pb : -1;
+            loa[tid] = (a >= lo && a < lo + nl) ? a - lo : -1;
+            lob[tid] = (bb >= lo && bb < lo + nl) ? bb - lo : -1;
+            if (pa < 0 || (bb >= 0 && pb < 0)) atomicOr(P.flags, kFlagTeamRow);
+        }
+        for (int i = tid; i < R * R * R; i += kTeamThreads) cinv[i] = M.Cinv[i];
+        for (int i = tid; i < cnt * nl; i += kTeamThreads) {
+            const int j = i / nl, r = i - j * nl;
+            uown[j * NL + r] = gU[(int64_t)j * n + lo + r];
+        }
+        for (int i = tid; i < cnt * nx; i += kTeamThreads) {
+            const int j = i / nx, x = i - j * nx;
+            ux[j * NX + x] = gU[(int64_t)j * n + wxrow[x]];
+        }
+        const int nlost = E.loss_cnt[0];
+        if (tid == 0) ctl[2] = nlost;
+        if (tid < nlost) {
+            lbr[tid] = E.loss_br[tid];
+            lst[tid] = E.loss_step[tid];
+        }
+    }
+    __syncthreads();
+    const int cnt = ctl[1], nlost = ctl[2];
+    int par = 0;
+    bool alive = true;
+    double worst = 0.0;
+    const int wave = tid >> 6, lane = tid & 63;
+
+    // one application of the stored inverse (with the active line changes):
+    // out (own rows), outx (X rows) from xin (own rows)
+    auto apply = [&](const double* xin, double* out, double* outx, int ract) -> bool {
+        for (int r = lane; r < nl; r += 64) {
+            TA acc = 0;
+            for (int j = wave; j < nl; j += 4) acc += (TA)blk[j * nl + r] * (TA)xin[j];
+            part[wave * NL + r] = (double)acc;
+        }
+        __syncthreads();
+        double* X0 = T.X0 + (int64_t)par * n;
+        for (int r = tid; r < nl; r += kTeamThreads) {
+            const double val = part[r] + part[NL + r] + part[2 * NL + r] + part[3 * NL + r];
+            out[r] = val;
+            X0[lo + r] = val;
+        }
+        if (!team_barrier(T.sync, T.T, P.flags, ctl)) return false;
+        for (int x = tid; x < nx; x += kTeamThreads) outx[x] = X0[xrow[x]];
+        __syncthreads();
+        for (int h = 1; h <= Hn; ++h) {
+            const int c0 = lvlc[h - 1], c1 = lvlc[h];
+            if (c1 == c0) continue;
+            for (int g = c0 + tid; g < c1; g += kTeamThreads) s[g] = colw[g] * outx[xpos[g]];
+            __syncthreads();
+            for (int g = c0 + tid; g < c1; g += kTeamThreads) {
+                const int m = cm[g], q0 = cc0[g];
+                const TB* Si = sall + cso[g] + (g - q0);
+                TA acc = 0;
+                for (int p = 0; p < m; ++p) acc += (TA)Si[p * m] * (TA)s[q0 + p];
+                y[g] = (double)acc;
+            }
+            __syncthreads();
+            for (int x = tid; x < nx; x += kTeamThreads) {
+                const int zo = xzo[x * Hn + h - 1];
+                if (zo < 0) continue;
+                const int pm = xpm[x * Hn + h - 1], pc = xpc[x * Hn + h - 1];
+                TA acc = 0;
+                for (int j = 0; j < pm; ++j) acc += (TA)xz[zo + j] * (TA)y[pc + j];
+                outx[x] -= (double)acc;
+            }
+            const int zo = ozo[h - 1];
+            if (zo >= 0) {
+                const int pm = opm[h - 1], pc = opc[h - 1];
+                for (int r = tid; r < nl; r += kTeamThreads) {
+                    TA acc = 0;
+                    for (int j = 0; j < pm; ++j) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
+                    out[r] -= (double)acc;
+                }
+            }
+            __syncthreads();
+        }
+        if (ract > 0) {
+            if (tid < ract) tz[tid] = outx[lpa[tid]] - (lpb[tid] >= 0 ? outx[lpb[tid]] : 0.0);
+            __syncthreads();
+            if (tid < ract) {
+                const double* Ci = cinv + (ract - 1) * R * R;
+                double acc = 0.0;
+                for (int j = 0; j < ract; ++j) acc += Ci[tid * R + j] * tz[j];
+                tz[R + tid] = acc;
+            }
+            __syncthreads();
+            for (int r = tid; r < nl; r += kTeamThreads) {
+                double acc = 0.0;
+                for (int j = 0; j < ract; ++j) acc += (double)uown[j * NL + r] * tz[R + j];
+                out[r] -= acc;
+            }
+            for (int x = tid; x < nx; x += kTeamThreads) {
+                double acc = 0.0;
+                for (int j = 0; j < ract; ++j) acc += (double)ux[j * NX + x] * tz[R + j];
+                outx[x] -= acc;
+            }
+            __syncthreads();
+        }
+        par ^= 1;
+        return true;
+    };
+
+    // t = b - G_step v on own rows (FP64), then v += P t
+    auto refine = [&](int ract, bool last) -> bool {
+        for (int r = tid; r < nl; r += kTeamThreads) {
+            double acc = 0.0;
+            for (int e = orp[r]; e < orp[r + 1]; ++e) {
+                const int c = ocol[e];
+                acc += oval[e] * (c < nl ? v[c] : xv[c - nl]);
+            }
+            for (int j = 0; j < ract; ++j) {
+                if (loa[j] != r && lob[j] != r) continue;
+                const double wv = xv[lpa[j]] - (lpb[j] >= 0 ? xv[lpb[j]] : 0.0);
+                acc += (loa[j] == r ? 1.0 : -1.0) * mdg[j] * wv;
+            }
+            t[r] = b[r] - acc;
+        }
+        __syncthreads();
+        if (!apply(t, d, xd, ract)) return false;
+        double dm = 0.0, vm = 0.0;
+        for (int r = tid; r < nl; r += kTeamThreads) {
+            const double nv = v[r] + d[r];
+            v[r] = nv;
+            dm = fmax(dm, fabs(d[r]));
+            vm = fmax(vm, fabs(nv));
+        }
+        for (int x = tid; x < nx; x += kTeamThreads) xv[x] += xd[x];
+        if (last) {
+            for (int o = 32; o > 0; o >>= 1) {
+                dm = fmax(dm, __shfl_xor(dm, o));
+                vm = fmax(vm, __shfl_xor(vm, o));
+            }
+            if (lane == 0) { red[wave] = dm; red[4 + wave] = vm; }
+            __syncthreads();
+            if (tid == 0) {
+                double D = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+                double V = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+                const double ratio = V > 0.0 ? D / V : (D > 0.0 ? INFINITY : 0.0);
+                if (!isfinite(ratio)) atomicOr(P.flags, kFlagNaN);
+                else {
+                    worst = fmax(worst, ratio);
+                    if (ratio > P.rel_tol) atomicOr(P.flags, kFlagNoConv);
+                }
+            }
+        }
+        __syncthreads();
+        return true;
+    };
+
+    int64_t applies = 0;
+    for (int it = 0; it < P.n_steps && alive; ++it) {
+        const int64_t step = P.step0 + it;
+        int ract = 0;
+        while (ract < cnt && (int64_t)mact[ract] <= step) ++ract;
+        if (!MIXED) {
+            alive = apply(b, v, xv, ract);
+            applies += 1;
+        } else {
+            const int nref = WARM ? P.max_refine + 1 : P.max_refine;
+            if (!WARM) {
+                alive = apply(b, v, xv, ract);
+                applies += 1;
+            }
+            for (int q = 0; q < nref && alive; ++q) {
+                alive = refine(ract, q == nref - 1);
+                applies += 1;
+            }
+        }
+        if (!alive) break;
+        // history: new branch histories, then the right-hand side of step+1
+        for (int q = tid; q < nb; q += kTeamThreads) {
+            const int e = bglob[q];
+            bool lost = false;
+            for (int j = 0; j < nlost; ++j)
+                if (lbr[j] == e && (int64_t)lst[j] <= step + 1) lost = true;
+            double hv = 0.0;
+            if (!lost) {
+                const int f = bf[q], to = bt[q];
+                const double vft = (f < nl ? v[f] : xv[f - nl]) - (to < nl ? v[to] : xv[to - nl]);
+                const double ie = bg[q] * vft + hc[q];
+                hv = bg[q] * vft + bal[q] * ie;
+            }
+            hn[q] = hv;
+        }
+        __syncthreads();
+        const int64_t j = step - P.step0;
+        for (int r = tid; r < nl; r += kTeamThreads) {
+            const double va = v[r];
+            double bn = 0.0;
+            for (int q = sptr[r]; q < sptr[r + 1]; ++q) bn += samp[q] * sin(E.omega * ((double)(step + 1) * E.dt) + sph[q]);
+            for (int q = iptr[r]; q < iptr[r + 1]; ++q) {
+                const int lb = ibr[q];
+                const double hv = hn[lb];
+                bn -= (bf[lb] == r) ? hv : -hv;
+            }
+            const double ic = gC[r] * va + hC[r];
+            const double hcn = -gC[r] * va - ic;
+            hC[r] = hcn;
+            bn -= hcn;
+            const int64_t o = j * (int64_t)n + E.perm[lo + r];
+            if (P.v_rec) P.v_rec[o] = va;
+            if (P.b_rec) P.b_rec[o] = b[r];
+            b[r] = bn;
+        }
+        double* tmp = hc;
+        hc = hn;
+        hn = tmp;
+        __syncthreads();
+        if (P.clk && w == 0 && tid == 0 && j < P.clk_cap) P.clk[j] = (int64_t)wall_clock64();
+    }
+    if (!alive) return;
+    const int64_t nstep = P.step0 + P.n_steps;
+    for (int r = tid; r < nl; r += kTeamThreads) {
+        E.b[lo + r] = b[r];
+        E.v[lo + r] = v[r];
+        E.hC[lo + r] = hC[r];
+    }
+    for (int q = tid; q < nb; q += kTeamThreads)
+        if (T.bown[(int64_t)w * T.NB + q]) E.h[(int64_t)(nstep & 1) * E.n_cases * E.nbr + bglob[q]] = hc[q];
+    if (tid == 0) {
+        if (MIXED && P.stats) atomicMax(&P.stats[0], (unsigned long long)__double_as_longlong(worst));
+        if (w == 0) {
+            if (P.applies) atomicAdd(&P.applies[0], (unsigned long long)applies);
+            *E.step = nstep;
+        }
+    }
+}
+
+template <typename TB, bool MIXED, bool WARM>
+static hipError_t launch_team_t(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M,
+                                const RunParams& P, hipStream_t s)
+{
+    const size_t lds = team_layout<TB>(T, M.R).total;
+    const void* fn = (const void*)k_emt_team<TB, MIXED, WARM>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    TeamDev Tc = T;
+    EmtDev Ec = E;
+    HierDev Hc = H;
+    ModDev Mc = M;
+    RunParams Pc = P;
+    void* args[] = {&Tc, &Ec, &Hc, &Mc, &Pc};
+    e = hipMemsetAsync(T.sync, 0, 2 * sizeof(unsigned int), s);
+    if (e != hipSuccess) return e;
+    e = hipLaunchCooperativeKernel(fn, dim3(T.T), dim3(kTeamThreads), args, (unsigned int)lds, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
+                           int prec, hipStream_t s)
+{
+    if (prec == HINV_FP64) return launch_team_t<double, false, false>(T, E, H, M, P, s);
+    if (P.warm) return launch_team_t<float, true, true>(T, E, H, M, P, s);
+    return launch_team_t<float, true, false>(T, E, H, M, P, s);
+}
+
+}  // namespace hinv

@@ -24,7 +24,8 @@ STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "
 
 EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_solve", "hinv_sync_status",
            "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_workspace_size", "emt_create",
-           "emt_step", "emt_lose_line", "emt_get_step", "emt_get_stats", "emt_destroy", "hinv_last_error")
+           "emt_step", "emt_lose_line", "emt_get_step", "emt_get_stats", "emt_set_step_clock", "emt_destroy",
+           "hinv_wall_clock_khz", "hinv_last_error")
 
 
 class HinvError(RuntimeError):
@@ -45,7 +46,8 @@ class _Tree(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("max_mod_rank", ctypes.c_int32), ("max_nrhs", ctypes.c_int32)]
+                ("max_mod_rank", ctypes.c_int32), ("max_nrhs", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("kernel_mode", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -92,6 +94,8 @@ def load() -> ctypes.CDLL:
         "emt_lose_line": [P, i32, i32, P],
         "emt_get_step": [P, P],
         "emt_get_stats": [P, P, P],
+        "emt_set_step_clock": [P, P, i64],
+        "hinv_wall_clock_khz": [i32, P],
         "emt_destroy": [P],
     }
     for name, args in sig.items():
@@ -123,10 +127,16 @@ def _stream(torch_stream=None) -> int:
     return s.cuda_stream
 
 
-def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs) -> _Options:
+KERNEL_MODES = {"auto": 0, "per_kernel": 1, "fused": 2, "team": 3}
+
+
+def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs, warm_start=False, kernel_mode="auto") -> _Options:
     if isinstance(prec, str):
         prec = PRECISIONS[prec]
-    return _Options(int(prec), float(rel_tol), int(max_refine), int(max_mod_rank), int(max_nrhs))
+    if isinstance(kernel_mode, str):
+        kernel_mode = KERNEL_MODES[kernel_mode]
+    return _Options(int(prec), float(rel_tol), int(max_refine), int(max_mod_rank), int(max_nrhs),
+                    int(bool(warm_start)), int(kernel_mode))
 
 
 class _NetArrays:
@@ -148,6 +158,12 @@ class _NetArrays:
                           _ptr(self.L), _ptr(self.C), float(net.dt), int(len(self.sb)), _ptr(self.sb),
                           _ptr(self.sa), _ptr(self.sp), float(net.freq))
         self.tree = _Tree(int(len(self.parent)), _ptr(self.parent), _ptr(self.bus_leaf))
+
+
+def wall_clock_khz(device: int = 0) -> int:
+    v = ctypes.c_int32(0)
+    _check(load().hinv_wall_clock_khz(int(device), ctypes.byref(v)), "hinv_wall_clock_khz")
+    return v.value
 
 
 def network_csr(net) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
@@ -255,7 +271,7 @@ class EMT:
     """
 
     def __init__(self, net, n_cases: int = 1, losses=None, prec="fp64", rel_tol=1e-9, max_refine=2,
-                 max_mod_rank=2, device="cuda"):
+                 max_mod_rank=2, warm_start=False, kernel_mode="auto", device="cuda"):
         import torch
         self._lib = load()
         self.device = torch.device(device)
@@ -265,7 +281,7 @@ class EMT:
         self._na = _NetArrays(net)
         self._ptr, self._st, self._br = _case_arrays(self.n_cases, losses)
         self._cases = _Cases(self.n_cases, _ptr(self._ptr), _ptr(self._st), _ptr(self._br))
-        self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, 1)
+        self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, 1, warm_start, kernel_mode)
         nb = ctypes.c_size_t(0)
         _check(self._lib.emt_workspace_size(ctypes.byref(self._na.s), ctypes.byref(self._na.tree),
                                             ctypes.byref(self._opt), ctypes.byref(self._cases), ctypes.byref(nb)),
@@ -307,6 +323,12 @@ class EMT:
         a, r = ctypes.c_int64(0), ctypes.c_double(0)
         _check(self._lib.emt_get_stats(self._h, ctypes.byref(a), ctypes.byref(r)), "emt_get_stats")
         return a.value, r.value
+
+    def set_step_clock(self, clock=None) -> None:
+        """clock: int64 device tensor receiving the GPU wall clock after each step (or None)."""
+        cap = 0 if clock is None else clock.numel()
+        _check(self._lib.emt_set_step_clock(self._h, _ptr(clock), cap), "emt_set_step_clock")
+        self._clock = clock
 
     def close(self) -> None:
         if getattr(self, "_h", None):

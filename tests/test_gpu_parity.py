@@ -146,11 +146,14 @@ def c1_ref():
     return case, V, B
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_emt_179_trajectory(hv, c1_ref, prec):
+@pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp32", "fused", False),
+                                            ("fp32", "fused", True), ("fp64", "per_kernel", False),
+                                            ("fp32", "per_kernel", False), ("fp64", "team", False),
+                                            ("fp32", "team", False), ("fp32", "team", True)])
+def test_emt_179_trajectory(hv, c1_ref, prec, mode, warm):
     case, Vref, _ = c1_ref
-    print(f"[gpu] emt 179 {prec}", flush=True)
-    emt = hv.EMT(case.net, 1, losses=[[(300, 50)]], prec=prec, max_refine=2)
+    print(f"[gpu] emt 179 {prec} {mode} warm={warm}", flush=True)
+    emt = hv.EMT(case.net, 1, losses=[[(300, 50)]], prec=prec, max_refine=2, kernel_mode=mode, warm_start=warm)
     V, _ = emt.step(case.n_steps)
     Vg = V[:, 0, :].cpu().numpy()
     peak = np.abs(Vref).max()
@@ -187,12 +190,15 @@ def c2_ref():
     return case, V
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_emt_1432_with_line_loss(hv, c2_ref, prec):
+@pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp32", "fused", False),
+                                            ("fp32", "fused", True), ("fp64", "per_kernel", False),
+                                            ("fp64", "team", False), ("fp32", "team", False),
+                                            ("fp32", "team", True)])
+def test_emt_1432_with_line_loss(hv, c2_ref, prec, mode, warm):
     case, Vref = c2_ref
-    print(f"[gpu] emt 1432 {prec}", flush=True)
+    print(f"[gpu] emt 1432 {prec} {mode} warm={warm}", flush=True)
     losses = [list(zip(case.loss_steps.tolist(), case.loss_branches.tolist()))]
-    emt = hv.EMT(case.net, 1, losses=losses, prec=prec, max_refine=2)
+    emt = hv.EMT(case.net, 1, losses=losses, prec=prec, max_refine=2, kernel_mode=mode, warm_start=warm)
     V, _ = emt.step(case.n_steps)
     Vg = V[:, 0, :].cpu().numpy()
     peak = np.abs(Vref).max()
@@ -203,27 +209,49 @@ def test_emt_1432_with_line_loss(hv, c2_ref, prec):
     if prec != "fp64":
         applies, rel = emt.stats()
         assert rel <= 1e-9
+        print(f"[gpu] applies per step {applies / case.n_steps:.2f}", flush=True)
     emt.close()
 
 
-def test_batched_cases_equal_alone_and_dynamic_loss(hv):
+@pytest.mark.parametrize("mode", ["fused", "per_kernel"])
+def test_batched_cases_equal_alone_and_dynamic_loss(hv, mode):
     import torch
     net = cases.net_179()
     losses = [[], [(40, 5)], [(10, 100), (70, 3)], [(55, 262)]]
-    emt = hv.EMT(net, len(losses), losses=losses, prec="fp32", max_refine=2, max_mod_rank=2)
+    kw = dict(prec="fp32", max_refine=2, max_mod_rank=2, kernel_mode=mode)
+    emt = hv.EMT(net, len(losses), losses=losses, **kw)
     V, _ = emt.step(120)
     Vb = V.cpu().numpy()
     for k, lst in enumerate(losses):
-        one = hv.EMT(net, 1, losses=[lst], prec="fp32", max_refine=2, max_mod_rank=2)
+        one = hv.EMT(net, 1, losses=[lst], **kw)
         V1, _ = one.step(120)
         assert np.array_equal(V1[:, 0, :].cpu().numpy(), Vb[:, k, :]), k
         one.close()
     # a loss requested while running equals the same loss scheduled in advance
-    dyn = hv.EMT(net, 1, losses=[[]], prec="fp32", max_refine=2, max_mod_rank=2)
+    dyn = hv.EMT(net, 1, losses=[[]], **kw)
     Va, _ = dyn.step(39)
     dyn.lose_line(0, 5)
     Vb2, _ = dyn.step(81)
     Vd = torch.cat([Va, Vb2]).cpu().numpy()
     assert np.array_equal(Vd[:, 0, :], Vb[:, 1, :])
     emt.close()
+    dyn.close()
+
+
+def test_team_engine_dynamic_loss_equals_scheduled(hv):
+    """One workgroup per leaf: a loss requested between launches equals the same loss scheduled."""
+    import torch
+    net = cases.net_ring(4, 7)
+    kw = dict(prec="fp32", max_refine=1, warm_start=True, rel_tol=1e-6, max_mod_rank=2, kernel_mode="team")
+    ref = hv.EMT(net, 1, losses=[[(70, 11), (130, 900)]], **kw)
+    Vr, _ = ref.step(200)
+    dyn = hv.EMT(net, 1, losses=[[(70, 11)]], **kw)
+    Va, _ = dyn.step(129)
+    dyn.lose_line(0, 900)
+    Vb, _ = dyn.step(71)
+    assert np.array_equal(torch.cat([Va, Vb]).cpu().numpy(), Vr.cpu().numpy())
+    # and both agree with the oracle
+    Vo, _ = oracle.emt_run(net, 200, loss_steps=[70, 130], loss_branches=[11, 900], solver="lu")
+    assert np.abs(Vr[:, 0, :].cpu().numpy() - Vo).max() / np.abs(Vo).max() <= 1e-10
+    ref.close()
     dyn.close()
