@@ -8,10 +8,12 @@ apply, line-loss correction, FP64 refinement (mixed precision), history
 update, all inside the fused stepping kernel.  Inputs are resident in HBM
 before the timed region.
 
-Paths on the same case: FP64 apply; FP32 apply + FP64 refinement from a cold
-start (P b) and warm-started from the previous step's voltages ("mixed", the
-headline value).  Each trajectory is compared with the FP64 CPU oracle's; the
-oracle is also timed on the host as the CPU baseline.  A batch of 256
+Paths on the same case: FP64 apply; FP32 apply + FP64 residual refinement
+warm-started from the previous step's voltages with two corrections
+("mixed") and with one ("mixed_2apply").  Each trajectory is compared with
+the FP64 CPU oracle's; the headline value is the fastest path whose trajectory
+meets 1e-10 relative (peak-normalised).  The oracle is also timed on the host
+as the CPU baseline.  A batch of 256
 contingency cases on the same network (each loses a different line) is timed
 as well (FP64 and mixed).
 
@@ -82,8 +84,8 @@ def main():
     ap.add_argument("--steps", type=int, default=9500)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--chunk", type=int, default=500)
-    ap.add_argument("--max-refine", type=int, default=1)
-    ap.add_argument("--rel-tol", type=float, default=1e-6)
+    ap.add_argument("--max-refine", type=int, default=2)
+    ap.add_argument("--rel-tol", type=float, default=1e-9)
     ap.add_argument("--batch-cases", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -111,8 +113,9 @@ def main():
     record = not args.no_accuracy
 
     # (precision, warm start, refinement corrections, stop tolerance on the last correction)
-    paths = {"fp64": ("fp64", False, 0, 1e-9), "fp32_cold": ("fp32", False, 2, 1e-9),
-             "mixed": ("fp32", True, args.max_refine, args.rel_tol)}
+    paths = {"fp64": ("fp64", False, 0, 1e-9),
+             "mixed": ("fp32", True, args.max_refine, args.rel_tol),
+             "mixed_2apply": ("fp32", True, 1, 1e-6)}
     res = {}
     for name, (prec, warm, mr, tol) in paths.items():
         res[name] = timed_run(hinv, torch, net, losses, prec, warm, args.warmup, args.steps, args.chunk, mr, tol,
@@ -187,36 +190,40 @@ def main():
             r = timed_run(hinv, torch, base, bl, prec, warm, 0, args.batch_steps, args.chunk, mr, tol, False, khz)
             batch[name], _ = summary(r, prec)
 
-    mixed = table["mixed"]
-    r = res["mixed"]
-    launch_bytes = step_bytes("fp32", apsd["mixed"], max(0.0, apsd["mixed"])) * args.chunk
+    # headline: the fastest path whose trajectory meets 1e-10 (peak-normalised) against the oracle
+    ok = [k for k in paths if k in acc and acc[k]["peak_norm"] <= 1e-10] if acc else ["fp64"]
+    head = max(ok, key=lambda k: table[k]["solves_per_s"]) if ok else "fp64"
+    hp = table[head]
+    r = res[head]
+    prec_h, warm_h, mr_h, _ = paths[head]
+    launch_bytes = step_bytes(prec_h, apsd[head], apsd[head] if prec_h != "fp64" else 0) * args.chunk
     achieved = launch_bytes / (r["launch_ms"] * 1e-3) / 1e9
+    kname = ("k_emt_team<double, false, false>" if prec_h == "fp64"
+             else f"k_emt_team<float, true, {'true' if warm_h else 'false'}>")
     line = {
         "metric": METRIC,
-        "value": mixed["solves_per_s"],
+        "value": hp["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": r["steps"],
         "warmup": args.warmup,
-        "ms_per_step": mixed["ms_per_step"],
+        "ms_per_step": hp["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32 apply + fp64 residual refinement",
+        "dtype": "fp64" if prec_h == "fp64" else "fp32 apply + fp64 residual refinement",
         "data": "synthetic",
         "config": {"workload": "1432-bus 8-copy ring (16 leaves, 2 coupling levels), 10000 EMT steps at dt 50 us, "
                                "one line lost at step 2000 (rank-1 SMW); one case",
-                   "n_bus": n, "n_branch": nbr, "max_refine": args.max_refine, "rel_tol": args.rel_tol,
-                   "warm_start": True,
-                   "launch_steps": args.chunk},
-        "p50_step_us": mixed["p50_step_us"],
-        "p99_step_us": mixed["p99_step_us"],
+                   "n_bus": n, "n_branch": nbr, "headline_path": head, "launch_steps": args.chunk},
+        "p50_step_us": hp["p50_step_us"],
+        "p99_step_us": hp["p99_step_us"],
         "paths": table,
         "batched_contingencies": batch,
         "stored_entries": entries,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_emt_team<float, true, true> (one cooperative launch of 500 steps, one workgroup per leaf)",
+            "kernel": f"{kname} (one cooperative launch of {args.chunk} steps, one workgroup per leaf)",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -225,6 +225,31 @@ hinv_status hinv_wall_clock_khz(int32_t device, int32_t* khz);
 
 hinv_status emt_destroy(emt_handle c);
 
+/* ---- Serving: continuous batching of EMT cases -------------------------- */
+
+/* A pool of single-case EMT handles advanced together: each serve_step is one
+ * launch that advances every attached case by n_steps steps, one workgroup
+ * per case, each case with its own network, hierarchy, line losses and state
+ * (cases whose vectors do not fit a workgroup's LDS keep them in their own
+ * workspace).  Cases can be attached and detached between steps, so requests
+ * are admitted as slots free up.  A case's arithmetic does not depend on the
+ * other cases in the launch.  The pool's precision and warm start must match
+ * each attached case's options; refinement count and tolerance are the
+ * case's own.  Do not call emt_step on an attached handle. */
+typedef struct serve_ctx* serve_handle;
+
+hinv_status serve_workspace_size(int32_t max_slots, size_t* bytes);
+hinv_status serve_create(const hinv_options* opt, int32_t max_slots, void* d_ws, size_t ws_bytes, serve_handle* out);
+/* d_v_record (optional, device): row j receives the case's v at its j-th step after attaching (bus order of
+ * its network), j < record_capacity.  Synchronises the stream. */
+hinv_status serve_attach(serve_handle s, emt_handle c, double* d_v_record, int64_t record_capacity, void* stream,
+                         int32_t* slot_id);
+/* Synchronises the stream, then removes the case from the pool. */
+hinv_status serve_detach(serve_handle s, int32_t slot_id, void* stream);
+hinv_status serve_step(serve_handle s, int32_t n_steps, void* stream);
+hinv_status serve_active(serve_handle s, int32_t* n_active);
+hinv_status serve_destroy(serve_handle s);
+
 const char* hinv_last_error(void);
 
 #ifdef __cplusplus

@@ -73,6 +73,8 @@ struct Plan {
     std::vector<LevelHost> lv;
     std::vector<int> row_lo, row_nl, col_node, lvl_frow, frow_pan, pan_frow0;
     std::vector<int64_t> row_boff;
+    std::vector<int> col_m, col_c0, frow_pn, frow_pm, frow_pc, frow_row;
+    std::vector<int64_t> col_soff, frow_z;
     std::vector<int> rp, ci;
     std::vector<double> cv;
     int64_t leaf_entries = 0, z_entries = 0, s_entries = 0;
@@ -348,9 +350,23 @@ hinv_status make_plan(const hinv_csr* G, const hinv_tree* T, Plan& P)
     for (int h = 1; h <= P.n_levels; ++h) {
         for (int pp = P.lvl_pan[h - 1]; pp < P.lvl_pan[h]; ++pp) {
             P.pan_frow0[pp] = (int)P.frow_pan.size();
-            for (int i = 0; i < P.pan_n[pp]; ++i) P.frow_pan.push_back(pp);
+            for (int i = 0; i < P.pan_n[pp]; ++i) {
+                P.frow_pan.push_back(pp);
+                P.frow_z.push_back(P.pan_zoff[pp] + i);
+                P.frow_pn.push_back(P.pan_n[pp]);
+                P.frow_pm.push_back(P.pan_m[pp]);
+                P.frow_pc.push_back(P.pan_col0[pp]);
+                P.frow_row.push_back(P.pan_lo[pp] + i);
+            }
         }
         P.lvl_frow[h] = (int)P.frow_pan.size();
+    }
+    P.col_m.resize(P.col_row.size()); P.col_c0.resize(P.col_row.size()); P.col_soff.resize(P.col_row.size());
+    for (size_t g = 0; g < P.col_row.size(); ++g) {
+        const int t = P.col_node[g];
+        P.col_m[g] = P.node_m[t];
+        P.col_c0[g] = P.node_col0[t];
+        P.col_soff[g] = P.node_soff[t] + ((int)g - P.node_col0[t]);
     }
     if (P.max_cols > 4096) return fail(HINV_E_INVALID, "a tree node has %d coupling columns (limit 4096)", P.max_cols);
     return HINV_OK;
@@ -403,6 +419,12 @@ void carve_hier(hinv_ctx& c, Arena& A, int n_sets, int R, int max_nrhs)
     H.row_lo = A.take<int>(P.n); H.row_nl = A.take<int>(P.n); H.row_boff = A.take<int64_t>(P.n);
     H.col_node = A.take<int>(NC); H.lvl_frow = A.take<int>(P.n_levels + 1);
     H.frow_pan = A.take<int>((int64_t)P.frow_pan.size()); H.pan_frow0 = A.take<int>(NP);
+    H.col_m = A.take<int>(NC); H.col_c0 = A.take<int>(NC); H.col_soff = A.take<int64_t>(NC);
+    {
+        const int64_t nf = (int64_t)P.frow_pan.size();
+        H.frow_z = A.take<int64_t>(nf); H.frow_pn = A.take<int>(nf); H.frow_pm = A.take<int>(nf);
+        H.frow_pc = A.take<int>(nf); H.frow_row = A.take<int>(nf);
+    }
     H.rp = A.take<int>(P.n + 1); H.ci = A.take<int>(P.rp.empty() ? 1 : P.rp[P.n]);
     H.cv = A.take<double>(P.rp.empty() ? 1 : P.rp[P.n]);
     H.blk = A.take<double>(P.leaf_entries); H.Z = A.take<double>(P.z_entries); H.Sinv = A.take<double>(P.s_entries);
@@ -476,6 +498,9 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
     HIP_TRY(up(H.row_lo, P.row_lo, s)); HIP_TRY(up(H.row_nl, P.row_nl, s)); HIP_TRY(up(H.row_boff, P.row_boff, s));
     HIP_TRY(up(H.col_node, P.col_node, s)); HIP_TRY(up(H.lvl_frow, P.lvl_frow, s));
     HIP_TRY(up(H.frow_pan, P.frow_pan, s)); HIP_TRY(up(H.pan_frow0, P.pan_frow0, s));
+    HIP_TRY(up(H.col_m, P.col_m, s)); HIP_TRY(up(H.col_c0, P.col_c0, s)); HIP_TRY(up(H.col_soff, P.col_soff, s));
+    HIP_TRY(up(H.frow_z, P.frow_z, s)); HIP_TRY(up(H.frow_pn, P.frow_pn, s)); HIP_TRY(up(H.frow_pm, P.frow_pm, s));
+    HIP_TRY(up(H.frow_pc, P.frow_pc, s)); HIP_TRY(up(H.frow_row, P.frow_row, s));
     HIP_TRY(up(H.rp, P.rp, s)); HIP_TRY(up(H.ci, P.ci, s)); HIP_TRY(up(H.cv, P.cv, s));
     HIP_TRY(hipMemsetAsync(c.d_flags, 0, 4 * sizeof(int), s));
     HIP_TRY(hipMemsetAsync((void*)c.M.count, 0, sizeof(int) * c.M.n_sets, s));
@@ -708,6 +733,7 @@ struct emt_ctx {
     unsigned long long* d_applies = nullptr;   // [n_cases] fused-path apply counters
     int64_t* d_clock = nullptr;
     int64_t clock_cap = 0;
+    double* gscr = nullptr;      // [4 * n * n_cases] case vectors when they do not fit LDS (serving)
     // new-order network data kept for the team plan
     std::vector<int> inc_ptr, inc_br, src_ptr;
     std::vector<double> alpha, samp, sph, gC;
@@ -825,6 +851,7 @@ void carve_emt(emt_ctx& c, Arena& A, int n_src)
     E.done = A.take<unsigned int>(1);
     c.d_rec = A.take<RecParams>(1);
     c.d_applies = A.take<unsigned long long>(K);
+    c.gscr = A.take<double>(4 * (int64_t)n * K);
 }
 
 // Network data in the new bus order (kept on the host for uploads and the team plan).
@@ -1270,7 +1297,8 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
     hipStream_t s = (hipStream_t)stream;
     if (c.engine != 1) {
         RunParams P{c.step, n_steps, c.hc.opt.max_refine, c.hc.opt.rel_tol, c.hc.opt.warm_start ? 1 : 0,
-                    d_v_record, d_b_record, c.hc.d_flags, c.hc.stats, c.d_applies, c.d_clock, c.clock_cap};
+                    d_v_record, d_b_record, c.hc.d_flags, c.hc.stats, c.d_applies, c.d_clock, c.clock_cap,
+                    c.step, n_steps};
         if (c.engine == 3)
             HIP_TRY(launch_emt_team(c.TD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         else
@@ -1376,6 +1404,137 @@ hinv_status hinv_wall_clock_khz(int32_t device, int32_t* khz)
 }
 
 hinv_status emt_destroy(emt_handle h)
+{
+    delete h;
+    return HINV_OK;
+}
+
+}  // extern "C"
+
+// =============================== serving ====================================
+struct serve_ctx {
+    hinv_options opt{};
+    int max_slots = 0;
+    ServeSlot* d_slots = nullptr;
+    std::vector<ServeSlot> table;      // dense, in launch order
+    std::vector<emt_ctx*> owner;       // handle of each dense entry
+    std::vector<int> ids;              // stable id of each dense entry
+    int next_id = 0;
+};
+
+namespace {
+hinv_status serve_upload(serve_ctx& S, hipStream_t s)
+{
+    if (!S.table.empty())
+        HIP_TRY(hipMemcpyAsync(S.d_slots, S.table.data(), sizeof(ServeSlot) * S.table.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HINV_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hinv_status serve_workspace_size(int32_t max_slots, size_t* bytes)
+{
+    if (!bytes || max_slots < 1) return fail(HINV_E_INVALID, "max_slots must be >= 1");
+    *bytes = sizeof(ServeSlot) * (size_t)max_slots + kAlign;
+    return HINV_OK;
+}
+
+hinv_status serve_create(const hinv_options* opt, int32_t max_slots, void* d_ws, size_t ws_bytes, serve_handle* out)
+{
+    if (!out) return fail(HINV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hinv_status st = check_options(opt, 1);
+    if (st != HINV_OK) return st;
+    size_t need = 0;
+    st = serve_workspace_size(max_slots, &need);
+    if (st != HINV_OK) return st;
+    if (!d_ws || ws_bytes < need) return fail(HINV_E_NO_MEMORY, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    std::unique_ptr<serve_ctx> c(new (std::nothrow) serve_ctx);
+    if (!c) return fail(HINV_E_NO_MEMORY, "host allocation failed");
+    c->opt = *opt;
+    c->max_slots = max_slots;
+    Arena A;
+    A.base = (char*)d_ws;
+    c->d_slots = A.take<ServeSlot>(max_slots);
+    *out = c.release();
+    return HINV_OK;
+}
+
+hinv_status serve_attach(serve_handle h, emt_handle e, double* d_v_record, int64_t record_capacity, void* stream,
+                         int32_t* slot_id)
+{
+    if (!h || !e || !slot_id) return fail(HINV_E_INVALID, "NULL argument");
+    serve_ctx& S = *h;
+    emt_ctx& c = *e;
+    if ((int)S.table.size() >= S.max_slots) return fail(HINV_E_NO_MEMORY, "all %d slots are in use", S.max_slots);
+    if (c.n_cases != 1) return fail(HINV_E_INVALID, "a served handle holds exactly one case");
+    if (c.hc.opt.prec != S.opt.prec || (c.hc.opt.prec != HINV_FP64 && (c.hc.opt.warm_start != 0) != (S.opt.warm_start != 0)))
+        return fail(HINV_E_INVALID, "the case's precision / warm start differ from the pool's");
+    for (emt_ctx* o : S.owner)
+        if (o == e) return fail(HINV_E_INVALID, "the case is already attached");
+    if (d_v_record && record_capacity < 1) return fail(HINV_E_INVALID, "record capacity must be >= 1");
+    ServeSlot sl{};
+    sl.E = c.E;
+    sl.H = c.hc.H;
+    sl.M = c.hc.M;
+    sl.k = 0;
+    sl.gvec = run_fits(c.hc.H) ? 0 : 1;
+    sl.gscr = c.gscr;
+    sl.v_rec = d_v_record;
+    sl.rec_step0 = c.step;
+    sl.rec_cap = d_v_record ? record_capacity : 0;
+    sl.max_refine = c.hc.opt.max_refine;
+    sl.rel_tol = c.hc.opt.rel_tol;
+    sl.flags = c.hc.d_flags;
+    sl.stats = c.hc.stats;
+    sl.applies = c.d_applies;
+    S.table.push_back(sl);
+    S.owner.push_back(e);
+    S.ids.push_back(S.next_id);
+    *slot_id = S.next_id++;
+    return serve_upload(S, (hipStream_t)stream);
+}
+
+hinv_status serve_detach(serve_handle h, int32_t slot_id, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    serve_ctx& S = *h;
+    for (size_t i = 0; i < S.ids.size(); ++i) {
+        if (S.ids[i] != slot_id) continue;
+        HIP_TRY(hipStreamSynchronize((hipStream_t)stream));     // no launch may still read the table
+        S.table.erase(S.table.begin() + i);
+        S.owner.erase(S.owner.begin() + i);
+        S.ids.erase(S.ids.begin() + i);
+        return serve_upload(S, (hipStream_t)stream);
+    }
+    return fail(HINV_E_INVALID, "no slot %d", slot_id);
+}
+
+hinv_status serve_step(serve_handle h, int32_t n_steps, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    serve_ctx& S = *h;
+    if (n_steps < 0) return fail(HINV_E_INVALID, "n_steps < 0");
+    if (n_steps == 0 || S.table.empty()) return HINV_OK;
+    size_t lds = 0;
+    for (const ServeSlot& sl : S.table) lds = std::max(lds, serve_lds_bytes(sl.H, sl.gvec != 0));
+    if (lds > 160 * 1024) return fail(HINV_E_INVALID, "a served case's coupling levels exceed LDS");
+    HIP_TRY(launch_emt_serve(S.d_slots, (int)S.table.size(), n_steps, lds, S.opt.prec, S.opt.warm_start,
+                             (hipStream_t)stream));
+    for (emt_ctx* o : S.owner) o->step += n_steps;
+    return HINV_OK;
+}
+
+hinv_status serve_active(serve_handle h, int32_t* n_active)
+{
+    if (!h || !n_active) return fail(HINV_E_INVALID, "NULL argument");
+    *n_active = (int32_t)h->table.size();
+    return HINV_OK;
+}
+
+hinv_status serve_destroy(serve_handle h)
 {
     delete h;
     return HINV_OK;

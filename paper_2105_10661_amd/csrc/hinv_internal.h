@@ -68,6 +68,14 @@ struct HierDev {
     const int* lvl_frow;       // [n_levels+1] flat panel-row ranges per level
     const int* frow_pan;       // [total panel rows] panel of each flat panel row
     const int* pan_frow0;      // [n_pan] first flat row of each panel
+    const int* col_m;          // [n_cols] size m of the column's node
+    const int* col_c0;         // [n_cols] first column of the column's node
+    const int64_t* col_soff;   // [n_cols] S^{-1} offset of the column's node + (column - first column)
+    const int64_t* frow_z;     // [flat rows] offset of the row's entry in column 0 of its Z panel
+    const int* frow_pn;        // [flat rows] panel rows (column stride)
+    const int* frow_pm;        // [flat rows] panel columns
+    const int* frow_pc;        // [flat rows] panel's first global column
+    const int* frow_row;       // [flat rows] new-order row
     // G in the new order (CSR)
     const int* rp;
     const int* ci;
@@ -143,6 +151,26 @@ struct RunParams {
     unsigned long long* applies;   // [n_cases] applies performed
     int64_t* clk;                  // optional: wall clock after each step of case 0
     int64_t clk_cap;
+    int64_t rec_step0;             // v_rec/b_rec row j holds step rec_step0 + j, j < rec_cap
+    int64_t rec_cap;
+};
+
+// One slot of a serving launch: one case of an EMT handle (k_run.hip).
+struct ServeSlot {
+    EmtDev E;
+    HierDev H;
+    ModDev M;
+    int k;
+    int gvec;                      // case vectors in global scratch instead of LDS
+    double* gscr;                  // [4*n] scratch of the case (gvec)
+    double* v_rec;
+    int64_t rec_step0;
+    int64_t rec_cap;
+    int max_refine;
+    double rel_tol;
+    int* flags;
+    unsigned long long* stats;
+    unsigned long long* applies;
 };
 
 // Team stepping (k_team.hip): one workgroup per leaf of a single case.  All
@@ -232,6 +260,9 @@ hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, 
                            int prec, hipStream_t s);
 // Fused stepping (k_run.hip): one workgroup per case, all steps in one launch.
 bool run_fits(const HierDev& H);
+size_t serve_lds_bytes(const HierDev& H, bool gvec);
+hipError_t launch_emt_serve(const ServeSlot* d_slots, int n_slots, int n_steps, size_t lds, int prec, int warm,
+                            hipStream_t s);
 hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, int prec,
                           hipStream_t s);
 // History update with v_n and assembly of b_{n+1}; records; advances *E.step.

@@ -17,16 +17,14 @@
 // (one workgroup per case), and every case's arithmetic is independent of the
 // batch it runs in.
 //
-// Thread layout (1024 threads): four lanes per row share the columns of the
-// row's leaf-block dot product (reduced with lane shuffles), a wavefront covers
-// 16 consecutive rows, so each column of a block is read as 128-byte runs.
+// Thread layout (1024 threads): one thread per row in the leaf apply (a
+// wavefront reads 64 consecutive rows of a block column per load), one thread
+// per coupling column or panel row in the level phases.
 #include "hinv_internal.h"
 
 namespace hinv {
 
 constexpr int kRunThreads = 1024;
-constexpr int kChunks = 4;
-constexpr int kRowsPerPass = kRunThreads / kChunks;
 
 template <typename TB>
 struct Acc { using T = float; };
@@ -46,36 +44,29 @@ __device__ inline double block_max(double v, double* red)
     return m;
 }
 
-// out = B^{-1} x over all leaves (x, out: distinct LDS vectors).
+// out = B^{-1} x over all leaves (x, out: distinct LDS vectors).  One thread
+// per row; a wavefront covers 64 consecutive rows, so every load instruction
+// reads one contiguous run of a block column.  Loads are issued in batches of
+// kBatch before they are consumed, to keep many requests in flight per CU.
 template <typename TB>
 __device__ void wg_leaf_apply(const HierDev& H, const TB* __restrict__ blk, const double* x, double* out)
 {
     using TA = typename Acc<TB>::T;
-    const int c = threadIdx.x & (kChunks - 1);
-    const int rsub = threadIdx.x / kChunks;
-    for (int r0 = 0; r0 < H.n; r0 += kRowsPerPass) {
-        const int r = r0 + rsub;
+    constexpr int kBatch = 16;
+    for (int r = threadIdx.x; r < H.n; r += kRunThreads) {
+        const int lo = H.row_lo[r], nl = H.row_nl[r];
+        const TB* Bp = blk + H.row_boff[r];
+        const double* xl = x + lo;
         TA acc = 0;
-        if (r < H.n) {
-            const int lo = H.row_lo[r], nl = H.row_nl[r];
-            const TB* Bp = blk + H.row_boff[r];
-            const double* xl = x + lo;
-            int j = c;
-            for (; j + 3 * kChunks < nl; j += 4 * kChunks) {
-                const TA b0 = (TA)Bp[(int64_t)j * nl];
-                const TA b1 = (TA)Bp[(int64_t)(j + kChunks) * nl];
-                const TA b2 = (TA)Bp[(int64_t)(j + 2 * kChunks) * nl];
-                const TA b3 = (TA)Bp[(int64_t)(j + 3 * kChunks) * nl];
-                acc += b0 * (TA)xl[j];
-                acc += b1 * (TA)xl[j + kChunks];
-                acc += b2 * (TA)xl[j + 2 * kChunks];
-                acc += b3 * (TA)xl[j + 3 * kChunks];
-            }
-            for (; j < nl; j += kChunks) acc += (TA)Bp[(int64_t)j * nl] * (TA)xl[j];
+        for (int j0 = 0; j0 < nl; j0 += kBatch) {
+            TB bv[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) bv[q] = (j0 + q < nl) ? Bp[(int64_t)(j0 + q) * nl] : (TB)0;
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q)
+                if (j0 + q < nl) acc += (TA)bv[q] * (TA)xl[j0 + q];
         }
-        acc += __shfl_xor(acc, 1);
-        acc += __shfl_xor(acc, 2);
-        if (r < H.n && c == 0) out[r] = (double)acc;
+        out[r] = (double)acc;
     }
     __syncthreads();
 }
@@ -93,23 +84,20 @@ __device__ void wg_levels(const HierDev& H, const TB* __restrict__ Z, const TB* 
         for (int g = c0 + tid; g < c1; g += kRunThreads) s[g] = H.col_w[g] * out[H.col_row[g]];
         __syncthreads();
         for (int g = c0 + tid; g < c1; g += kRunThreads) {
-            const int t = H.col_node[g];
-            const int m = H.node_m[t], nc0 = H.node_col0[t], q = g - nc0;
-            const TB* Si = Sinv + H.node_soff[t];
+            const int m = H.col_m[g], nc0 = H.col_c0[g];
+            const TB* Si = Sinv + H.col_soff[g];
             TA acc = 0;
-            for (int pp = 0; pp < m; ++pp) acc += (TA)Si[(int64_t)pp * m + q] * (TA)s[nc0 + pp];
+            for (int pp = 0; pp < m; ++pp) acc += (TA)Si[(int64_t)pp * m] * (TA)s[nc0 + pp];
             y[g] = (double)acc;
         }
         __syncthreads();
         const int f0 = H.lvl_frow[h - 1], f1 = H.lvl_frow[h];
         for (int f = f0 + tid; f < f1; f += kRunThreads) {
-            const int P = H.frow_pan[f];
-            const int i = f - H.pan_frow0[P];
-            const int pn = H.pan_n[P], pm = H.pan_m[P], pc0 = H.pan_col0[P];
-            const TB* Zp = Z + H.pan_zoff[P] + i;
+            const int pn = H.frow_pn[f], pm = H.frow_pm[f], pc0 = H.frow_pc[f];
+            const TB* Zp = Z + H.frow_z[f];
             TA acc = 0;
             for (int j = 0; j < pm; ++j) acc += (TA)Zp[(int64_t)j * pn] * (TA)y[pc0 + j];
-            out[H.pan_lo[P] + i] -= (double)acc;
+            out[H.frow_row[f]] -= (double)acc;
         }
         __syncthreads();
     }
@@ -185,20 +173,14 @@ __device__ inline bool run_lost_by(const EmtDev& E, int k, int e, int64_t step)
     return false;
 }
 
+// The whole per-case stepping loop; b, v, t, d are LDS (or, for cases too big
+// for LDS, the case's global scratch), s, y, red, tz are LDS.
 template <typename TB, bool MIXED, bool WARM>
-__global__ __launch_bounds__(kRunThreads) void k_emt_run(EmtDev E, HierDev H, ModDev M, RunParams P)
+__device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
+                                             int k, double* b, double* v, double* t, double* d, double* s, double* y,
+                                             double* red, double* tz)
 {
-    extern __shared__ double lds[];
     const int n = H.n;
-    const int k = blockIdx.x;
-    double* b = lds;
-    double* v = b + n;
-    double* t = v + n;
-    double* d = t + n;
-    double* s = d + n;
-    double* y = s + H.n_cols;
-    double* red = y + H.n_cols;          // 16
-    double* tz = red + 16;               // 2 * kMaxModRank
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)k * n;
     const TB* blk;
@@ -280,9 +262,12 @@ __global__ __launch_bounds__(kRunThreads) void k_emt_run(EmtDev E, HierDev H, Mo
             const double hcn = -E.gC[a] * va - ic;
             E.hC[base + a] = hcn;
             bn -= hcn;
-            const int64_t o = (j * E.n_cases + k) * (int64_t)n + E.perm[a];
-            if (P.v_rec) P.v_rec[o] = va;
-            if (P.b_rec) P.b_rec[o] = b[a];
+            const int64_t jr = step - P.rec_step0;
+            if (jr >= 0 && jr < P.rec_cap) {
+                const int64_t o = (jr * E.n_cases + k) * (int64_t)n + E.perm[a];
+                if (P.v_rec) P.v_rec[o] = va;
+                if (P.b_rec) P.b_rec[o] = b[a];
+            }
             b[a] = bn;
         }
         __syncthreads();
@@ -296,6 +281,62 @@ __global__ __launch_bounds__(kRunThreads) void k_emt_run(EmtDev E, HierDev H, Mo
         if (MIXED && P.stats) atomicMax(&P.stats[k], (unsigned long long)__double_as_longlong(worst));
         if (P.applies) atomicAdd(&P.applies[k], (unsigned long long)applies);
         if (k == 0) *E.step = P.step0 + P.n_steps;
+    }
+}
+
+template <typename TB, bool MIXED, bool WARM>
+__global__ __launch_bounds__(kRunThreads) void k_emt_run(EmtDev E, HierDev H, ModDev M, RunParams P)
+{
+    extern __shared__ double lds[];
+    const int n = H.n;
+    double* b = lds;
+    double* v = b + n;
+    double* t = v + n;
+    double* d = t + n;
+    double* s = d + n;
+    double* y = s + H.n_cols;
+    double* red = y + H.n_cols;          // 16
+    double* tz = red + 16;               // 2 * kMaxModRank
+    emt_run_body<TB, MIXED, WARM>(E, H, M, P, blockIdx.x, b, v, t, d, s, y, red, tz);
+}
+
+// Serving: one workgroup per slot; every slot is its own case (own network,
+// hierarchy and state); the start step comes from the case's step counter.
+template <typename TB, bool MIXED, bool WARM>
+__global__ __launch_bounds__(kRunThreads) void k_emt_serve(const ServeSlot* __restrict__ slots, int n_steps)
+{
+    extern __shared__ double lds[];
+    __shared__ ServeSlot sl;
+    __shared__ RunParams P;
+    if (threadIdx.x == 0) {
+        sl = slots[blockIdx.x];
+        P.step0 = __hip_atomic_load(sl.E.step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.n_steps = n_steps;
+        P.max_refine = sl.max_refine;
+        P.rel_tol = sl.rel_tol;
+        P.warm = WARM ? 1 : 0;
+        P.v_rec = sl.v_rec;
+        P.b_rec = nullptr;
+        P.rec_step0 = sl.rec_step0;
+        P.rec_cap = sl.rec_cap;
+        P.flags = sl.flags;
+        P.stats = sl.stats;
+        P.applies = sl.applies;
+        P.clk = nullptr;
+        P.clk_cap = 0;
+    }
+    __syncthreads();
+    const int n = sl.H.n;
+    double* s = lds;
+    double* y = s + sl.H.n_cols;
+    double* red = y + sl.H.n_cols;
+    double* tz = red + 16;
+    if (sl.gvec) {
+        double* g = sl.gscr;
+        emt_run_body<TB, MIXED, WARM>(sl.E, sl.H, sl.M, P, sl.k, g, g + n, g + 2 * n, g + 3 * n, s, y, red, tz);
+    } else {
+        double* vb = tz + 2 * kMaxModRank;
+        emt_run_body<TB, MIXED, WARM>(sl.E, sl.H, sl.M, P, sl.k, vb, vb + n, vb + 2 * n, vb + 3 * n, s, y, red, tz);
     }
 }
 
@@ -315,6 +356,30 @@ static hipError_t launch_run_t(const EmtDev& E, const HierDev& H, const ModDev& 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_emt_run<TB, MIXED, WARM>), dim3(E.n_cases), dim3(kRunThreads), lds, s, E, H, M, P);
     return hipGetLastError();
+}
+
+size_t serve_lds_bytes(const HierDev& H, bool gvec)
+{
+    return sizeof(double) * ((gvec ? 0 : 4 * (size_t)H.n) + 2 * (size_t)H.n_cols + 16 + 2 * kMaxModRank);
+}
+
+template <typename TB, bool MIXED, bool WARM>
+static hipError_t launch_serve_t(const ServeSlot* slots, int n_slots, int n_steps, size_t lds, hipStream_t s)
+{
+    hipError_t e = hipFuncSetAttribute((const void*)k_emt_serve<TB, MIXED, WARM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_emt_serve<TB, MIXED, WARM>), dim3(n_slots), dim3(kRunThreads), lds, s, slots, n_steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_emt_serve(const ServeSlot* d_slots, int n_slots, int n_steps, size_t lds, int prec, int warm,
+                            hipStream_t s)
+{
+    if (n_slots <= 0) return hipSuccess;
+    if (prec == HINV_FP64) return launch_serve_t<double, false, false>(d_slots, n_slots, n_steps, lds, s);
+    if (warm) return launch_serve_t<float, true, true>(d_slots, n_slots, n_steps, lds, s);
+    return launch_serve_t<float, true, false>(d_slots, n_slots, n_steps, lds, s);
 }
 
 hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, int prec,

@@ -25,7 +25,8 @@ STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "
 EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_solve", "hinv_sync_status",
            "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_workspace_size", "emt_create",
            "emt_step", "emt_lose_line", "emt_get_step", "emt_get_stats", "emt_set_step_clock", "emt_destroy",
-           "hinv_wall_clock_khz", "hinv_last_error")
+           "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
+           "serve_step", "serve_active", "serve_destroy", "hinv_last_error")
 
 
 class HinvError(RuntimeError):
@@ -96,6 +97,13 @@ def load() -> ctypes.CDLL:
         "emt_get_stats": [P, P, P],
         "emt_set_step_clock": [P, P, i64],
         "hinv_wall_clock_khz": [i32, P],
+        "serve_workspace_size": [i32, P],
+        "serve_create": [P, i32, P, ctypes.c_size_t, P],
+        "serve_attach": [P, P, P, i64, P, P],
+        "serve_detach": [P, i32, P],
+        "serve_step": [P, i32, P],
+        "serve_active": [P, P],
+        "serve_destroy": [P],
         "emt_destroy": [P],
     }
     for name, args in sig.items():
@@ -333,6 +341,66 @@ class EMT:
     def close(self) -> None:
         if getattr(self, "_h", None):
             self._lib.emt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Serve:
+    """Pool of single-case EMT handles advanced by one launch per step call (serve_*)."""
+
+    def __init__(self, max_slots: int, prec="fp32", warm_start=True, max_refine=2, rel_tol=1e-9, device="cuda"):
+        import torch
+        self._lib = load()
+        self.device = torch.device(device)
+        self.prec, self.warm_start, self.max_refine, self.rel_tol = prec, warm_start, max_refine, rel_tol
+        self._opt = _options(prec, rel_tol, max_refine, 0, 1, warm_start, "auto")
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.serve_workspace_size(int(max_slots), ctypes.byref(nb)), "serve_workspace_size")
+        self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        _check(self._lib.serve_create(ctypes.byref(self._opt), int(max_slots), _ptr(self._ws), nb.value,
+                                      ctypes.byref(h)), "serve_create")
+        self._h = h
+        self._cases = {}
+
+    def new_case(self, net, losses=None, max_mod_rank=2) -> "EMT":
+        """An EMT handle with the pool's precision settings (one case)."""
+        return EMT(net, 1, losses=[losses or []], prec=self.prec, rel_tol=self.rel_tol, max_refine=self.max_refine,
+                   max_mod_rank=max_mod_rank, warm_start=self.warm_start, device=self.device)
+
+    def attach(self, emt: "EMT", record_steps: int = 0):
+        """Attach a case; returns (slot id, record tensor or None)."""
+        import torch
+        rec = None
+        if record_steps:
+            rec = torch.empty((record_steps, emt.n), dtype=torch.float64, device=self.device)
+        sid = ctypes.c_int32(0)
+        _check(self._lib.serve_attach(self._h, emt._h, _ptr(rec), int(record_steps), _stream(), ctypes.byref(sid)),
+               "serve_attach")
+        self._cases[sid.value] = (emt, rec)
+        return sid.value, rec
+
+    def detach(self, slot_id: int) -> None:
+        _check(self._lib.serve_detach(self._h, int(slot_id), _stream()), "serve_detach")
+        self._cases.pop(slot_id, None)
+
+    def step(self, n_steps: int) -> None:
+        _check(self._lib.serve_step(self._h, int(n_steps), _stream()), "serve_step")
+
+    @property
+    def active(self) -> int:
+        v = ctypes.c_int32(0)
+        _check(self._lib.serve_active(self._h, ctypes.byref(v)), "serve_active")
+        return v.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.serve_destroy(self._h)
             self._h = None
 
     def __del__(self):
