@@ -1123,7 +1123,7 @@ void carve_team(emt_ctx& c, Arena& A)
     D.bg = td(L * D.NB); D.bal = td(L * D.NB);
     D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
     D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
-    D.sync = A.take<unsigned int>(2);
+    D.sync = A.take<unsigned int>(L);
     D.X0 = td(2 * (size_t)c.n);
 }
 
@@ -1141,7 +1141,7 @@ hinv_status upload_team(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
     HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
     HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
-    HIP_TRY(hipMemsetAsync(D.sync, 0, 2 * sizeof(unsigned int), s));
+    HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;
 }

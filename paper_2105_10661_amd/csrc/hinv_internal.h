@@ -209,7 +209,7 @@ struct TeamDev {
     const int* sptr;     // [T*(NL+1)] sources of each own row
     const double* samp;  // [T*NS]
     const double* sph;
-    unsigned int* sync;  // [2] barrier counter and generation
+    unsigned int* sync;  // [T] barrier epoch flag of each workgroup
     double* X0;          // [2*n] exchange of leaf results (double-buffered by apply parity)
 };
 

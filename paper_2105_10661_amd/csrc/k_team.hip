@@ -20,7 +20,10 @@
 
 namespace hinv {
 
-constexpr int kTeamThreads = 256;
+constexpr int kTeamThreads = 1024;
+constexpr int kTeamWaves = kTeamThreads / 64;
+constexpr int kGemvChunks = kTeamWaves / 2;   // leaf GEMV: 2 row halves (lanes) x 8 column chunks
+constexpr int kSub = 4;                 // lanes per coupling-column dot product
 constexpr int kTeamSpinLimit = 1 << 24;
 
 template <typename TB>
@@ -55,7 +58,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.ux = take(sizeof(TB) * R * NX);
     const size_t D = sizeof(double);
     L.b = take(D * NL); L.v = take(D * NL); L.t = take(D * NL); L.d = take(D * NL);
-    L.part = take(D * 4 * NL);
+    L.part = take(D * kGemvChunks * NL);
     L.xv = take(D * NX); L.xd = take(D * NX);
     L.s = take(D * nc); L.y = take(D * nc);
     L.h0 = take(D * T.NB); L.h1 = take(D * T.NB);
@@ -64,7 +67,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.samp = take(D * T.NS); L.sph = take(D * T.NS);
     L.colw = take(D * nc);
     L.cinv = take(D * R * R * R); L.mdg = take(D * R);
-    L.red = take(D * 8); L.tz = take(D * 2 * R);
+    L.red = take(D * 2 * kTeamWaves); L.tz = take(D * 2 * R);
     const size_t I = sizeof(int);
     L.xrow = take(I * NX); L.xzo = take(I * NX * H); L.xpm = take(I * NX * H); L.xpc = take(I * NX * H);
     L.ozo = take(I * H); L.opm = take(I * H); L.opc = take(I * H);
@@ -86,31 +89,35 @@ size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec)
     return prec == HINV_FP64 ? team_layout<double>(T, R).total : team_layout<float>(T, R).total;
 }
 
-// Barrier of the T workgroups of the team.  Agent-scope release/acquire make
-// every workgroup's global writes before the barrier visible to all after it.
-// The wait is bounded: on time-out it flags kFlagBarrier and returns false.
-__device__ inline bool team_barrier(unsigned int* sync, int T, int* flags, int* ctl)
+// Barrier of the T workgroups of the team, by per-workgroup epoch flags:
+// each workgroup release-stores its epoch (after all its threads' global
+// writes), then one wavefront polls every flag with relaxed agent-scope loads
+// and a wave vote, and a single acquire fence follows; no read-modify-write
+// on a shared counter.  The wait is bounded: on time-out it flags
+// kFlagBarrier and returns false.
+__device__ inline bool team_barrier(unsigned int* flags, int T, unsigned int epoch, int* errflags, int* ctl)
 {
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {
         int ok = 1;
-        const unsigned int g = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned int prev = __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == (unsigned int)(T - 1)) {
-            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            int spins = 0;
-            while (__hip_atomic_load(&sync[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (++spins > kTeamSpinLimit) {
-                    ok = 0;
-                    atomicOr(flags, kFlagBarrier);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+        int spins = 0;
+        while (true) {
+            int mine = 1;
+            for (int i = threadIdx.x; i < T; i += 64)
+                mine &= (__hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch) ? 1 : 0;
+            if (__all(mine)) break;
+            if (++spins > kTeamSpinLimit) {
+                ok = 0;
+                break;
             }
+            __builtin_amdgcn_s_sleep(1);
         }
-        ctl[0] = ok;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (threadIdx.x == 0) {
+            ctl[0] = ok;
+            if (!ok) atomicOr(errflags, kFlagBarrier);
+        }
     }
     __syncthreads();
     return ctl[0] != 0;
@@ -302,6 +309,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     __syncthreads();
     const int cnt = ctl[1], nlost = ctl[2];
     int par = 0;
+    unsigned int epoch = 0;
     bool alive = true;
     double worst = 0.0;
     const int wave = tid >> 6, lane = tid & 63;
@@ -309,19 +317,24 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     // one application of the stored inverse (with the active line changes):
     // out (own rows), outx (X rows) from xin (own rows)
     auto apply = [&](const double* xin, double* out, double* outx, int ract) -> bool {
-        for (int r = lane; r < nl; r += 64) {
-            TA acc = 0;
-            for (int j = wave; j < nl; j += 4) acc += (TA)blk[j * nl + r] * (TA)xin[j];
-            part[wave * NL + r] = (double)acc;
+        // wavefront w: rows 64*(w / kGemvChunks) + lane, block columns j = w % kGemvChunks (mod kGemvChunks)
+        {
+            const int r = (wave / kGemvChunks) * 64 + lane, c = wave % kGemvChunks;
+            if (r < nl) {
+                TA acc = 0;
+                for (int j = c; j < nl; j += kGemvChunks) acc += (TA)blk[j * nl + r] * (TA)xin[j];
+                part[c * NL + r] = (double)acc;
+            }
         }
         __syncthreads();
         double* X0 = T.X0 + (int64_t)par * n;
         for (int r = tid; r < nl; r += kTeamThreads) {
-            const double val = part[r] + part[NL + r] + part[2 * NL + r] + part[3 * NL + r];
+            double val = part[r];
+            for (int q = 1; q < kGemvChunks; ++q) val += part[q * NL + r];
             out[r] = val;
             X0[lo + r] = val;
         }
-        if (!team_barrier(T.sync, T.T, P.flags, ctl)) return false;
+        if (!team_barrier(T.sync, T.T, ++epoch, P.flags, ctl)) return false;
         for (int x = tid; x < nx; x += kTeamThreads) outx[x] = X0[xrow[x]];
         __syncthreads();
         for (int h = 1; h <= Hn; ++h) {
@@ -329,29 +342,41 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             if (c1 == c0) continue;
             for (int g = c0 + tid; g < c1; g += kTeamThreads) s[g] = colw[g] * outx[xpos[g]];
             __syncthreads();
-            for (int g = c0 + tid; g < c1; g += kTeamThreads) {
+            // y = S^{-1} s: kSub lanes share each column's dot product (lane shuffles)
+            for (int idx = tid; idx < (c1 - c0) * kSub; idx += kTeamThreads) {
+                const int g = c0 + idx / kSub, sub = idx & (kSub - 1);
                 const int m = cm[g], q0 = cc0[g];
                 const TB* Si = sall + cso[g] + (g - q0);
                 TA acc = 0;
-                for (int p = 0; p < m; ++p) acc += (TA)Si[p * m] * (TA)s[q0 + p];
-                y[g] = (double)acc;
+                for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * m] * (TA)s[q0 + p];
+                acc += __shfl_xor(acc, 1);
+                acc += __shfl_xor(acc, 2);
+                if (sub == 0) y[g] = (double)acc;
             }
             __syncthreads();
-            for (int x = tid; x < nx; x += kTeamThreads) {
+            // v -= Z y on X rows and own rows, kSub lanes per row
+            for (int idx = tid; idx < nx * kSub; idx += kTeamThreads) {
+                const int x = idx / kSub, sub = idx & (kSub - 1);
                 const int zo = xzo[x * Hn + h - 1];
-                if (zo < 0) continue;
-                const int pm = xpm[x * Hn + h - 1], pc = xpc[x * Hn + h - 1];
                 TA acc = 0;
-                for (int j = 0; j < pm; ++j) acc += (TA)xz[zo + j] * (TA)y[pc + j];
-                outx[x] -= (double)acc;
+                if (zo >= 0) {
+                    const int pm = xpm[x * Hn + h - 1], pc = xpc[x * Hn + h - 1];
+                    for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
+                }
+                acc += __shfl_xor(acc, 1);
+                acc += __shfl_xor(acc, 2);
+                if (sub == 0 && zo >= 0) outx[x] -= (double)acc;
             }
             const int zo = ozo[h - 1];
             if (zo >= 0) {
                 const int pm = opm[h - 1], pc = opc[h - 1];
-                for (int r = tid; r < nl; r += kTeamThreads) {
+                for (int idx = tid; idx < nl * kSub; idx += kTeamThreads) {
+                    const int r = idx / kSub, sub = idx & (kSub - 1);
                     TA acc = 0;
-                    for (int j = 0; j < pm; ++j) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
-                    out[r] -= (double)acc;
+                    for (int j = sub; j < pm; j += kSub) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
+                    acc += __shfl_xor(acc, 1);
+                    acc += __shfl_xor(acc, 2);
+                    if (sub == 0) out[r] -= (double)acc;
                 }
             }
             __syncthreads();
@@ -412,11 +437,14 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 dm = fmax(dm, __shfl_xor(dm, o));
                 vm = fmax(vm, __shfl_xor(vm, o));
             }
-            if (lane == 0) { red[wave] = dm; red[4 + wave] = vm; }
+            if (lane == 0) { red[wave] = dm; red[kTeamWaves + wave] = vm; }
             __syncthreads();
             if (tid == 0) {
-                double D = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-                double V = fmax(fmax(red[4], red[5]), fmax(red[6], red[7]));
+                double D = 0.0, V = 0.0;
+                for (int q = 0; q < kTeamWaves; ++q) {
+                    D = fmax(D, red[q]);
+                    V = fmax(V, red[kTeamWaves + q]);
+                }
                 const double ratio = V > 0.0 ? D / V : (D > 0.0 ? INFINITY : 0.0);
                 if (!isfinite(ratio)) atomicOr(P.flags, kFlagNaN);
                 else {
@@ -522,7 +550,7 @@ static hipError_t launch_team_t(const TeamDev& T, const EmtDev& E, const HierDev
     ModDev Mc = M;
     RunParams Pc = P;
     void* args[] = {&Tc, &Ec, &Hc, &Mc, &Pc};
-    e = hipMemsetAsync(T.sync, 0, 2 * sizeof(unsigned int), s);
+    e = hipMemsetAsync(T.sync, 0, (size_t)T.T * sizeof(unsigned int), s);
     if (e != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(fn, dim3(T.T), dim3(kTeamThreads), args, (unsigned int)lds, s);
     if (e != hipSuccess) return e;
