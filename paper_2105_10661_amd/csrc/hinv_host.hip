@@ -744,6 +744,7 @@ struct emt_ctx {
     std::vector<int> tw_lo, tw_nl, tw_nx, tw_nb, txrow, txzo, txpm, txpc, tozo, topm, topc, topan, txpan, txpos, torp,
         tocol, tbglob, tbf, tbt, tbown, tiptr, tibr, tsptr;
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
+    std::vector<int> tcsop;
     TeamDev TD{};
 };
 
@@ -1054,7 +1055,17 @@ bool build_team_plan(emt_ctx& c, int R)
     TeamDev& D = c.TD;
     D.T = L; D.H = H; D.NL = NL; D.NX = NX; D.NB = NB; D.NE = NE; D.NI = NI; D.NS = NS; D.XZ = XZ; D.ZO = ZO;
     D.nc = NC;
-    D.sent = (int)P.s_entries;
+    // S^{-1} of every node in LDS with rows padded to m+1 (breaks LDS bank aliasing of the row stride)
+    c.tcsop.assign(NC, 0);
+    {
+        int64_t off = 0;
+        for (size_t t = 0; t < P.node_m.size(); ++t) {
+            const int m = P.node_m[t];
+            for (int q = 0; q < m; ++q) c.tcsop[P.node_col0[t] + q] = (int)(off + q);
+            off += (int64_t)m * (m + 1);
+        }
+        D.sent = (int)std::max<int64_t>(off, 1);
+    }
     if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
     const int Hs = std::max(H, 1);
     (void)Hs;
@@ -1124,6 +1135,7 @@ void carve_team(emt_ctx& c, Arena& A)
     D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
     D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
     D.sync = A.take<unsigned int>(L);
+    D.csop = ti(D.nc);
     D.X0 = td(2 * (size_t)c.n);
 }
 
@@ -1140,7 +1152,7 @@ hinv_status upload_team(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.bglob, c.tbglob, s)); HIP_TRY(up(D.bf, c.tbf, s)); HIP_TRY(up(D.bt, c.tbt, s));
     HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
     HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
-    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
+    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s)); HIP_TRY(up(D.csop, c.tcsop, s));
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;

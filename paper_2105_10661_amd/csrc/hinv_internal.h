@@ -180,7 +180,8 @@ struct ServeSlot {
 // column endpoints, tie-line neighbours, line-loss endpoints) are nl + x.
 struct TeamDev {
     int T, H, NL, NX, NB, NE, NI, NS, XZ, ZO;
-    int nc, sent;        // coupling columns, stored S^{-1} entries (whole hierarchy)
+    int nc, sent;        // coupling columns, S^{-1} entries in LDS (rows padded to m+1, see csop)
+    const int* csop;     // [n_cols] LDS offset of the column's node S^{-1} (row stride m+1) + column index in node
     const int* w_lo;
     const int* w_nl;
     const int* w_nx;

@@ -204,7 +204,13 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     {
         const TB* src = gblk + H.leaf_off[w];
         for (int i = tid; i < nl * nl; i += kTeamThreads) blk[i] = src[i];
-        for (int i = tid; i < T.sent; i += kTeamThreads) sall[i] = gS[i];
+        for (int g = tid; g < nc; g += kTeamThreads) {      // S^{-1} rows padded to m+1 in LDS
+            const int node = H.col_node[g];
+            const int m = H.node_m[node], q = g - H.node_col0[node];
+            const TB* src = gS + H.node_soff[node] + q;
+            TB* dst = sall + T.csop[g];
+            for (int p = 0; p < m; ++p) dst[p * (m + 1)] = src[(int64_t)p * m];
+        }
         const int* wxrow = T.xrow + (int64_t)w * NX;
         for (int x = tid; x < nx; x += kTeamThreads) xrow[x] = wxrow[x];
         for (int i = tid; i < nx * Hn; i += kTeamThreads) {
@@ -237,7 +243,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             const int node = H.col_node[g];
             cm[g] = H.node_m[node];
             cc0[g] = H.node_col0[node];
-            cso[g] = (int)H.node_soff[node];
+            cso[g] = T.csop[g];
             colw[g] = H.col_w[g];
         }
         for (int h = tid; h <= Hn; h += kTeamThreads) lvlc[h] = H.lvl_col[h];
@@ -337,50 +343,71 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         if (!team_barrier(T.sync, T.T, ++epoch, P.flags, ctl)) return false;
         for (int x = tid; x < nx; x += kTeamThreads) outx[x] = X0[xrow[x]];
         __syncthreads();
+        // coupling levels bottom-up: gather s (an endpoint row's lower-level
+        // corrections are applied inline, in the same order as the final
+        // update), then y = S^{-1} s; all rows are updated once at the end.
         for (int h = 1; h <= Hn; ++h) {
             const int c0 = lvlc[h - 1], c1 = lvlc[h];
             if (c1 == c0) continue;
-            for (int g = c0 + tid; g < c1; g += kTeamThreads) s[g] = colw[g] * outx[xpos[g]];
+            for (int idx = tid; idx < (c1 - c0) * kSub; idx += kTeamThreads) {
+                const int g = c0 + idx / kSub, sub = idx & (kSub - 1);
+                const int x = xpos[g];
+                double val = outx[x];
+                for (int hh = 1; hh < h; ++hh) {
+                    const int zo = xzo[x * Hn + hh - 1];
+                    TA acc = 0;
+                    if (zo >= 0) {
+                        const int pm = xpm[x * Hn + hh - 1], pc = xpc[x * Hn + hh - 1];
+                        for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
+                    }
+                    acc += __shfl_xor(acc, 1);
+                    acc += __shfl_xor(acc, 2);
+                    if (zo >= 0) val -= (double)acc;
+                }
+                if (sub == 0) s[g] = colw[g] * val;
+            }
             __syncthreads();
             // y = S^{-1} s: kSub lanes share each column's dot product (lane shuffles)
             for (int idx = tid; idx < (c1 - c0) * kSub; idx += kTeamThreads) {
                 const int g = c0 + idx / kSub, sub = idx & (kSub - 1);
                 const int m = cm[g], q0 = cc0[g];
-                const TB* Si = sall + cso[g] + (g - q0);
+                const TB* Si = sall + cso[g];
                 TA acc = 0;
-                for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * m] * (TA)s[q0 + p];
+                for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * (m + 1)] * (TA)s[q0 + p];
                 acc += __shfl_xor(acc, 1);
                 acc += __shfl_xor(acc, 2);
                 if (sub == 0) y[g] = (double)acc;
             }
             __syncthreads();
-            // v -= Z y on X rows and own rows, kSub lanes per row
-            for (int idx = tid; idx < nx * kSub; idx += kTeamThreads) {
-                const int x = idx / kSub, sub = idx & (kSub - 1);
-                const int zo = xzo[x * Hn + h - 1];
+        }
+        // v -= sum over levels of Z y, on X rows (first nx items) and own rows, kSub lanes per row
+        for (int idx = tid; idx < (nx + nl) * kSub; idx += kTeamThreads) {
+            const int i = idx / kSub, sub = idx & (kSub - 1);
+            const bool isx = i < nx;
+            const int r = i - nx;
+            double val = isx ? outx[i] : out[r];
+            for (int h = 1; h <= Hn; ++h) {
+                const int zo = isx ? xzo[i * Hn + h - 1] : ozo[h - 1];
                 TA acc = 0;
                 if (zo >= 0) {
-                    const int pm = xpm[x * Hn + h - 1], pc = xpc[x * Hn + h - 1];
-                    for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
+                    const int pm = isx ? xpm[i * Hn + h - 1] : opm[h - 1];
+                    const int pc = isx ? xpc[i * Hn + h - 1] : opc[h - 1];
+                    if (isx) {
+                        for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
+                    } else {
+                        for (int j = sub; j < pm; j += kSub) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
+                    }
                 }
                 acc += __shfl_xor(acc, 1);
                 acc += __shfl_xor(acc, 2);
-                if (sub == 0 && zo >= 0) outx[x] -= (double)acc;
+                if (zo >= 0) val -= (double)acc;
             }
-            const int zo = ozo[h - 1];
-            if (zo >= 0) {
-                const int pm = opm[h - 1], pc = opc[h - 1];
-                for (int idx = tid; idx < nl * kSub; idx += kTeamThreads) {
-                    const int r = idx / kSub, sub = idx & (kSub - 1);
-                    TA acc = 0;
-                    for (int j = sub; j < pm; j += kSub) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
-                    acc += __shfl_xor(acc, 1);
-                    acc += __shfl_xor(acc, 2);
-                    if (sub == 0) out[r] -= (double)acc;
-                }
+            if (sub == 0) {
+                if (isx) outx[i] = val;
+                else out[r] = val;
             }
-            __syncthreads();
         }
+        __syncthreads();
         if (ract > 0) {
             if (tid < ract) tz[tid] = outx[lpa[tid]] - (lpb[tid] >= 0 ? outx[lpb[tid]] : 0.0);
             __syncthreads();
