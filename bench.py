@@ -78,6 +78,48 @@ def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_re
             "lat_us": lat_us, "applies": applies, "max_last_update": rel, "V": V, "n_cases": n_cases}
 
 
+def study_11456(hinv, torch, khz, steps=200):
+    """11456-bus 8x8 torus (3 coupling levels, root capacitance 384^2): per-kernel engine.
+
+    Per storage precision: time per EMT step and trajectory error against the
+    sparse-LU oracle over `steps` steps; per-solve error after k FP64-residual
+    corrections (one random right-hand side).
+    """
+    import oracle
+    from paper_2105_10661_amd import cases
+    net = cases.net_torus(8, 8, seed=3)
+    out = {"n_bus": net.n_bus, "steps": steps, "engine": "per-kernel launches"}
+    Vref, _ = oracle.emt_run(net, steps, loss_steps=[120], loss_branches=[4321], solver="sparse")
+    for prec, refine in (("fp64", 0), ("fp32", 2), ("bf16", 18)):
+        emt = hinv.EMT(net, 1, losses=[[(120, 4321)]], prec=prec, max_refine=refine, rel_tol=1.0)
+        V, _ = emt.step(20)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        V = torch.empty((steps - 20, 1, net.n_bus), dtype=torch.float64, device="cuda")
+        t0.record()
+        emt.step(steps - 20, v_out=V)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / (steps - 20)
+        err = float(np.abs(V[:, 0, :].cpu().numpy() - Vref[20:]).max() / np.abs(Vref).max())
+        out[prec] = {"corrections": refine, "ms_per_step": round(ms, 4), "solves_per_s": round(1e3 / ms, 1),
+                     "err_peak_norm": err}
+        emt.close()
+    b = np.random.default_rng(5).standard_normal(net.n_bus)
+    xo = oracle.sparse_solver(net)(b)
+    conv = {}
+    for prec in ("fp32", "bf16", "fp8"):
+        row = {}
+        for k in (0, 1, 2, 4, 8, 12, 16, 20):
+            H = hinv.Hierarchy.from_network(net, prec=prec, max_refine=k, max_nrhs=1, rel_tol=1.0)
+            x = H.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+            row[str(k)] = float(np.abs(x - xo).max() / np.abs(xo).max())
+            H.close()
+        conv[prec] = row
+    out["per_solve_error_vs_corrections"] = conv
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +133,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--study-11456", action="store_true",
+                    help="also time the 11456-bus torus per storage precision and record error vs corrections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
@@ -190,6 +234,10 @@ def main():
             r = timed_run(hinv, torch, base, bl, prec, warm, 0, args.batch_steps, args.chunk, mr, tol, False, khz)
             batch[name], _ = summary(r, prec)
 
+    study = None
+    if args.study_11456:
+        study = study_11456(hinv, torch, khz)
+
     # headline: the fastest path whose trajectory meets 1e-10 (peak-normalised) against the oracle
     ok = [k for k in paths if k in acc and acc[k]["peak_norm"] <= 1e-10] if acc else ["fp64"]
     head = max(ok, key=lambda k: table[k]["solves_per_s"]) if ok else "fp64"
@@ -220,6 +268,7 @@ def main():
         "p99_step_us": hp["p99_step_us"],
         "paths": table,
         "batched_contingencies": batch,
+        "torus_11456": study,
         "stored_entries": entries,
         "roofline": {
             "bound": "hbm",

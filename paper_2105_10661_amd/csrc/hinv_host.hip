@@ -428,11 +428,20 @@ void carve_hier(hinv_ctx& c, Arena& A, int n_sets, int R, int max_nrhs)
     H.rp = A.take<int>(P.n + 1); H.ci = A.take<int>(P.rp.empty() ? 1 : P.rp[P.n]);
     H.cv = A.take<double>(P.rp.empty() ? 1 : P.rp[P.n]);
     H.blk = A.take<double>(P.leaf_entries); H.Z = A.take<double>(P.z_entries); H.Sinv = A.take<double>(P.s_entries);
-    if (c.opt.prec != HINV_FP64) {
+    H.blk32 = H.Z32 = H.Sinv32 = nullptr;
+    H.blk16 = H.Z16 = H.Sinv16 = nullptr;
+    H.blk8 = H.Z8 = H.Sinv8 = H.blk8s = H.Z8s = H.Sinv8s = nullptr;
+    if (c.opt.prec == HINV_FP32) {
         H.blk32 = A.take<float>(P.leaf_entries); H.Z32 = A.take<float>(P.z_entries);
         H.Sinv32 = A.take<float>(P.s_entries);
-    } else {
-        H.blk32 = H.Z32 = H.Sinv32 = nullptr;
+    } else if (c.opt.prec == HINV_BF16) {
+        H.blk16 = A.take<uint16_t>(P.leaf_entries); H.Z16 = A.take<uint16_t>(P.z_entries);
+        H.Sinv16 = A.take<uint16_t>(P.s_entries);
+    } else if (c.opt.prec == HINV_FP8) {
+        H.blk8 = A.take<uint8_t>(P.leaf_entries); H.Z8 = A.take<uint8_t>(P.z_entries);
+        H.Sinv8 = A.take<uint8_t>(P.s_entries);
+        H.blk8s = A.take<uint8_t>(P.leaf_entries / 32 + 1); H.Z8s = A.take<uint8_t>(P.z_entries / 32 + 1);
+        H.Sinv8s = A.take<uint8_t>(P.s_entries / 32 + 1);
     }
     c.colbuf = A.take<double>(NC);
     c.ipiv = A.take<int>(NC);
@@ -466,8 +475,6 @@ hinv_status check_options(const hinv_options* o, int min_nrhs)
 {
     if (!o) return fail(HINV_E_INVALID, "options are NULL");
     if (o->prec < HINV_FP64 || o->prec > HINV_FP8) return fail(HINV_E_INVALID, "unknown precision %d", o->prec);
-    if (o->prec == HINV_BF16 || o->prec == HINV_FP8)
-        return fail(HINV_E_INVALID, "precision %d is not available in this build", o->prec);
     if (o->max_mod_rank < 0 || o->max_mod_rank > kMaxModRank)
         return fail(HINV_E_INVALID, "max_mod_rank %d outside 0..%d", o->max_mod_rank, kMaxModRank);
     if (o->max_nrhs < min_nrhs) return fail(HINV_E_INVALID, "max_nrhs %d < %d", o->max_nrhs, min_nrhs);
@@ -513,10 +520,18 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
         launch_fill_s(H, l, L.nnodes, s);
         launch_gj_level(H, l, L.nnodes, L.max_m, c.colbuf, c.ipiv, c.d_flags, s);
     }
-    if (c.opt.prec != HINV_FP64) {
+    if (c.opt.prec == HINV_FP32) {
         launch_to_f32(H.blk, H.blk32, P.leaf_entries, s);
         launch_to_f32(H.Z, H.Z32, P.z_entries, s);
         launch_to_f32(H.Sinv, H.Sinv32, P.s_entries, s);
+    } else if (c.opt.prec == HINV_BF16) {
+        launch_to_bf16(H.blk, H.blk16, P.leaf_entries, s);
+        launch_to_bf16(H.Z, H.Z16, P.z_entries, s);
+        launch_to_bf16(H.Sinv, H.Sinv16, P.s_entries, s);
+    } else if (c.opt.prec == HINV_FP8) {
+        launch_to_fp8(H.blk, H.blk8, H.blk8s, P.leaf_entries, s);
+        launch_to_fp8(H.Z, H.Z8, H.Z8s, P.z_entries, s);
+        launch_to_fp8(H.Sinv, H.Sinv8, H.Sinv8s, P.s_entries, s);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
@@ -927,8 +942,9 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
     carve_emt(c, A, N->n_src);
     // engine
     const int mode = o->kernel_mode;
+    const bool fused_prec = (o->prec == HINV_FP64 || o->prec == HINV_FP32);   // the fused engines' formats
     c.team_ok = false;
-    if (mode == 0 || mode == 3) {
+    if ((mode == 0 || mode == 3) && fused_prec) {
         c.team_nx_cap = 0;
         if (build_team_plan(c, c.R)) {
             c.team_nx_cap = c.TD.NX + 2 * c.R;      // room for the endpoints of later line losses
@@ -936,9 +952,10 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
         }
         if (c.team_ok) carve_team(c, A);
     }
-    const bool fits = run_fits(c.hc.H);
-    if (mode == 3 && !c.team_ok) return fail(HINV_E_INVALID, "the team engine needs one case, <= 256 leaves and fitting LDS");
-    if (mode == 2 && !fits) return fail(HINV_E_INVALID, "the case does not fit one workgroup's LDS");
+    const bool fits = run_fits(c.hc.H) && fused_prec;
+    if (mode == 3 && !c.team_ok)
+        return fail(HINV_E_INVALID, "the team engine needs FP64/FP32, one case, <= 256 leaves and fitting LDS");
+    if (mode == 2 && !fits) return fail(HINV_E_INVALID, "the one-workgroup-per-case engine needs FP64/FP32 and a case that fits LDS");
     c.engine = (mode == 1) ? 1 : (mode == 2) ? 2 : (mode == 3) ? 3 : c.team_ok ? 3 : fits ? 2 : 1;
     *bytes = A.off + kAlign;
     return HINV_OK;

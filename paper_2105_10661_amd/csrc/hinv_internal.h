@@ -87,6 +87,44 @@ struct HierDev {
     float* blk32;
     float* Z32;
     float* Sinv32;
+    uint16_t* blk16;           // BF16 copies (round to nearest even)
+    uint16_t* Z16;
+    uint16_t* Sinv16;
+    uint8_t* blk8;             // OCP FP8 E4M3 copies, one E8M0 scale per 32 consecutive entries
+    uint8_t* Z8;
+    uint8_t* Sinv8;
+    uint8_t* blk8s;
+    uint8_t* Z8s;
+    uint8_t* Sinv8s;
+};
+
+// Element accessors for the stored-inverse formats (value as the accumulator type).
+struct StF64 {
+    const double* p;
+    __device__ __forceinline__ double operator[](int64_t i) const { return p[i]; }
+};
+struct StF32 {
+    const float* p;
+    __device__ __forceinline__ float operator[](int64_t i) const { return p[i]; }
+};
+struct StBF16 {
+    const uint16_t* p;
+    __device__ __forceinline__ float operator[](int64_t i) const { return __uint_as_float((uint32_t)p[i] << 16); }
+};
+// OCP E4M3: sign, 4-bit exponent (bias 7), 3-bit mantissa; exponent 0 is subnormal.
+__device__ __forceinline__ float e4m3_to_float(uint8_t b)
+{
+    const int e = (b >> 3) & 15, m = b & 7;
+    const float mag = e == 0 ? ldexpf((float)m, -9) : ldexpf(1.0f + 0.125f * (float)m, e - 7);
+    return (b & 0x80) ? -mag : mag;
+}
+struct StFP8 {
+    const uint8_t* p;
+    const uint8_t* e;          // E8M0 scale exponents (2^(e-127)) of each 32-entry group
+    __device__ __forceinline__ float operator[](int64_t i) const
+    {
+        return ldexpf(e4m3_to_float(p[i]), (int)e[i >> 5] - 127);
+    }
 };
 
 // Line changes (Sherman-Morrison-Woodbury) for n_sets independent sets
@@ -229,6 +267,9 @@ void launch_fill_s(const HierDev& H, int level, int nnodes, hipStream_t s);
 void launch_gj_level(const HierDev& H, int level, int nnodes, int m_max, double* colbuf, int* ipiv, int* flags,
                      hipStream_t s);
 void launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);
+void launch_to_bf16(const double* src, uint16_t* dst, int64_t count, hipStream_t s);
+// E4M3 with one E8M0 scale per 32 entries (count rounded up to whole groups in `scale`)
+void launch_to_fp8(const double* src, uint8_t* dst, uint8_t* scale, int64_t count, hipStream_t s);
 
 void launch_permute_in(int n, int nrhs, const int* perm, const double* src, int ld, double* X, hipStream_t s);
 void launch_permute_out(int n, int nrhs, const int* perm, const double* X, double* dst, int ld, hipStream_t s);

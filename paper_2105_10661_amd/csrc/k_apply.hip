@@ -21,22 +21,22 @@
 
 namespace hinv {
 
-template <typename TB, typename TA>
-__global__ __launch_bounds__(kBlock) void k_leaf_apply(HierDev H, const TB* __restrict__ blk,
-                                                        const double* __restrict__ X, double* __restrict__ Xo)
+template <typename S, typename TA>
+__global__ __launch_bounds__(kBlock) void k_leaf_apply(HierDev H, S blk, const double* __restrict__ X,
+                                                        double* __restrict__ Xo)
 {
     __shared__ TA xs[kMaxLeaf];
     __shared__ TA part[kBlock / 64][kMaxLeaf];
     const int l = blockIdx.x;
     const int64_t col = (int64_t)blockIdx.y * H.n;
     const int lo = H.leaf_lo[l], nl = H.leaf_n[l];
-    const TB* B = blk + H.leaf_off[l];
+    const int64_t B = H.leaf_off[l];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < nl; i += kBlock) xs[i] = (TA)X[col + lo + i];
     __syncthreads();
     for (int r = lane; r < nl; r += 64) {
         TA acc = 0;
-        for (int j = wave; j < nl; j += kBlock / 64) acc += (TA)B[j * nl + r] * xs[j];
+        for (int j = wave; j < nl; j += kBlock / 64) acc += (TA)blk[B + j * nl + r] * xs[j];
         part[wave][r] = acc;
     }
     __syncthreads();
@@ -47,9 +47,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_apply(HierDev H, const TB* __re
     }
 }
 
-template <typename TB, typename TA>
-__global__ __launch_bounds__(kBlock) void k_level_solve(HierDev H, const TB* __restrict__ Sinv, int level,
-                                                         const double* __restrict__ X, double* __restrict__ Y)
+template <typename S, typename TA>
+__global__ __launch_bounds__(kBlock) void k_level_solve(HierDev H, S Sinv, int level, const double* __restrict__ X,
+                                                         double* __restrict__ Y)
 {
     extern __shared__ unsigned char shraw[];
     TA* s = reinterpret_cast<TA*>(shraw);
@@ -57,19 +57,19 @@ __global__ __launch_bounds__(kBlock) void k_level_solve(HierDev H, const TB* __r
     const int64_t xc = (int64_t)blockIdx.y * H.n;
     const int64_t yc = (int64_t)blockIdx.y * H.n_cols;
     const int m = H.node_m[t], c0 = H.node_col0[t];
-    const TB* Si = Sinv + H.node_soff[t];
+    const int64_t Si = H.node_soff[t];
     for (int q = threadIdx.x; q < m; q += kBlock) s[q] = (TA)(H.col_w[c0 + q] * X[xc + H.col_row[c0 + q]]);
     __syncthreads();
     for (int q = threadIdx.x; q < m; q += kBlock) {
         TA acc = 0;
-        for (int j = 0; j < m; ++j) acc += (TA)Si[(int64_t)j * m + q] * s[j];
+        for (int j = 0; j < m; ++j) acc += (TA)Sinv[Si + (int64_t)j * m + q] * s[j];
         Y[yc + c0 + q] = (double)acc;
     }
 }
 
-template <typename TB, typename TA>
-__global__ __launch_bounds__(kBlock) void k_level_update(HierDev H, const TB* __restrict__ Z, int level,
-                                                          double* __restrict__ X, const double* __restrict__ Y)
+template <typename S, typename TA>
+__global__ __launch_bounds__(kBlock) void k_level_update(HierDev H, S Z, int level, double* __restrict__ X,
+                                                          const double* __restrict__ Y)
 {
     extern __shared__ unsigned char shraw[];
     TA* y = reinterpret_cast<TA*>(shraw);
@@ -77,30 +77,29 @@ __global__ __launch_bounds__(kBlock) void k_level_update(HierDev H, const TB* __
     const int64_t xc = (int64_t)blockIdx.z * H.n;
     const int64_t yc = (int64_t)blockIdx.z * H.n_cols;
     const int plo = H.pan_lo[P], pn = H.pan_n[P], pm = H.pan_m[P], pc0 = H.pan_col0[P];
-    const TB* Zp = Z + H.pan_zoff[P];
+    const int64_t Zp = H.pan_zoff[P];
     for (int j = threadIdx.x; j < pm; j += kBlock) y[j] = (TA)Y[yc + pc0 + j];
     __syncthreads();
     const int i = blockIdx.y * kBlock + threadIdx.x;
     if (i < pn) {
         TA acc = 0;
-        for (int j = 0; j < pm; ++j) acc += (TA)Zp[(int64_t)j * pn + i] * y[j];
+        for (int j = 0; j < pm; ++j) acc += (TA)Z[Zp + (int64_t)j * pn + i] * y[j];
         X[xc + plo + i] -= (double)acc;
     }
 }
 
-template <typename TB, typename TA>
-static void apply_t(const HierDev& H, const LevelHost* lv, const TB* blk, const TB* Z, const TB* Sinv,
-                    const double* X, double* Xo, double* Y, int nrhs, hipStream_t s)
+template <typename S, typename TA>
+static void apply_t(const HierDev& H, const LevelHost* lv, S blk, S Z, S Sinv, const double* X, double* Xo, double* Y,
+                    int nrhs, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_leaf_apply<TB, TA>), dim3(H.n_leaves, nrhs), dim3(kBlock), 0, s, H, blk, X, Xo);
+    hipLaunchKernelGGL((k_leaf_apply<S, TA>), dim3(H.n_leaves, nrhs), dim3(kBlock), 0, s, H, blk, X, Xo);
     for (int l = 1; l <= H.n_levels; ++l) {
         const LevelHost& L = lv[l - 1];
         if (L.nnodes == 0 || L.ncols == 0) continue;
-        hipLaunchKernelGGL((k_level_solve<TB, TA>), dim3(L.nnodes, nrhs), dim3(kBlock), sizeof(TA) * L.max_m, s, H,
+        hipLaunchKernelGGL((k_level_solve<S, TA>), dim3(L.nnodes, nrhs), dim3(kBlock), sizeof(TA) * L.max_m, s, H,
                            Sinv, l, (const double*)Xo, Y);
         const int gy = (L.max_pan_rows + kBlock - 1) / kBlock;
-        int maxpm = L.max_m;
-        hipLaunchKernelGGL((k_level_update<TB, TA>), dim3(L.npan, gy, nrhs), dim3(kBlock), sizeof(TA) * maxpm, s, H,
+        hipLaunchKernelGGL((k_level_update<S, TA>), dim3(L.npan, gy, nrhs), dim3(kBlock), sizeof(TA) * L.max_m, s, H,
                            Z, l, Xo, (const double*)Y);
     }
 }
@@ -109,10 +108,21 @@ void launch_apply(const HierDev& H, const LevelHost* lv, int prec, const double*
                   int nrhs, hipStream_t s)
 {
     if (nrhs <= 0) return;
-    if (prec == HINV_FP64)
-        apply_t<double, double>(H, lv, H.blk, H.Z, H.Sinv, X, Xout, Y, nrhs, s);
-    else
-        apply_t<float, float>(H, lv, H.blk32, H.Z32, H.Sinv32, X, Xout, Y, nrhs, s);
+    switch (prec) {
+    case HINV_FP64:
+        apply_t<StF64, double>(H, lv, StF64{H.blk}, StF64{H.Z}, StF64{H.Sinv}, X, Xout, Y, nrhs, s);
+        break;
+    case HINV_FP32:
+        apply_t<StF32, float>(H, lv, StF32{H.blk32}, StF32{H.Z32}, StF32{H.Sinv32}, X, Xout, Y, nrhs, s);
+        break;
+    case HINV_BF16:
+        apply_t<StBF16, float>(H, lv, StBF16{H.blk16}, StBF16{H.Z16}, StBF16{H.Sinv16}, X, Xout, Y, nrhs, s);
+        break;
+    default:
+        apply_t<StFP8, float>(H, lv, StFP8{H.blk8, H.blk8s}, StFP8{H.Z8, H.Z8s}, StFP8{H.Sinv8, H.Sinv8s}, X, Xout, Y,
+                              nrhs, s);
+        break;
+    }
 }
 
 // ----------------------------------------------------------------------------

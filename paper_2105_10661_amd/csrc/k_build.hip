@@ -233,6 +233,83 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
         dst[i] = (float)src[i];
 }
 
+// FP64 -> BF16, round to nearest even (through FP32; NaN stays NaN).
+__device__ inline uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void k_to_bf16(const double* __restrict__ src, uint16_t* __restrict__ dst, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = f32_to_bf16((float)src[i]);
+}
+
+// float -> OCP E4M3 (round to nearest even, saturating at +-448).
+__device__ inline uint8_t f32_to_e4m3(float f)
+{
+    const uint8_t sgn = f < 0.0f ? 0x80 : 0;
+    float a = fabsf(f);
+    if (!(a > 0.0f)) return sgn;
+    if (a >= 448.0f) return sgn | 0x7e;                       // 1.75 * 2^8
+    int e;
+    frexpf(a, &e);                                            // a = f * 2^e, f in [0.5, 1)
+    int eu = e - 1;                                           // a in [2^eu, 2^(eu+1))
+    if (eu < -6) {                                            // subnormal: units of 2^-9
+        const float q = rintf(ldexpf(a, 9));
+        const int m = (int)q;
+        return sgn | (uint8_t)(m >= 8 ? (1 << 3) : m);
+    }
+    int m = (int)rintf((ldexpf(a, -eu) - 1.0f) * 8.0f);
+    if (m == 8) { m = 0; ++eu; }
+    if (eu > 8 || (eu == 8 && m > 6)) return sgn | 0x7e;
+    return sgn | (uint8_t)(((eu + 7) << 3) | m);
+}
+
+// One block per 32-entry group: scale 2^k, smallest k with max|x| / 2^k <= 448.
+__global__ void k_to_fp8(const double* __restrict__ src, uint8_t* __restrict__ dst, uint8_t* __restrict__ scale,
+                         int64_t count)
+{
+    const int64_t groups = (count + 31) / 32;
+    const int lane = threadIdx.x & 31;
+    for (int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 32; gi < groups;
+         gi += ((int64_t)gridDim.x * blockDim.x) / 32) {
+        const int64_t i = gi * 32 + lane;
+        const float x = i < count ? (float)src[i] : 0.0f;
+        float amax = fabsf(x);
+        for (int o = 16; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 32));
+        int k = 0;
+        if (amax > 0.0f) {
+            int e;
+            frexpf(amax / 448.0f, &e);                        // amax/448 in [2^(e-1), 2^e)
+            k = e;
+            if (ldexpf(amax, -(k - 1)) <= 448.0f) k = k - 1;
+        }
+        k = k < -127 ? -127 : (k > 127 ? 127 : k);
+        if (lane == 0) scale[gi] = (uint8_t)(k + 127);
+        if (i < count) dst[i] = f32_to_e4m3(ldexpf(x, -k));
+    }
+}
+
+void launch_to_bf16(const double* src, uint16_t* dst, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    int64_t blocks = (count + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, count);
+}
+
+void launch_to_fp8(const double* src, uint8_t* dst, uint8_t* scale, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    int64_t blocks = ((count + 31) / 32 * 32 + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_to_fp8, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, scale, count);
+}
+
 void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s)
 {
     if (H.n_leaves > 0) hipLaunchKernelGGL(k_leaf_inverse, dim3(H.n_leaves), dim3(kBlock), 0, s, H, flags);
