@@ -86,12 +86,16 @@ typedef struct {
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
     int32_t warm_start;    /* EMT, mixed precision: refine from the previous step's v instead of P b */
-    int32_t kernel_mode;   /* EMT engine: 0 = automatic (3 for one case when it fits, else 2 when it
-                              fits, else 1); 1 = one launch per kernel per step (any size);
-                              2 = one fused launch per emt_step, one workgroup per case (case
-                              vectors in LDS); 3 = one fused cooperative launch per emt_step, one
-                              workgroup per leaf of a single case (mixed precision runs exactly
-                              max_refine (+1 when warm-started) corrections per step) */
+    int32_t kernel_mode;   /* EMT engine: 0 = automatic (one case: 3 when it fits; several
+                              cases: 4 when it fits; else 2 when it fits, else 1); 1 = one launch
+                              per kernel per step (any size); 2 = one fused launch per emt_step,
+                              one workgroup per case (case vectors in LDS); 3 = one fused
+                              cooperative launch per emt_step, one workgroup per leaf of a single
+                              case; 4 = fused cooperative launches, cases in panels of 16 with
+                              one workgroup per leaf per panel, leaf blocks applied to a panel as
+                              one matrix-core product (max_mod_rank <= 2).  Engines 3 and 4 run
+                              exactly max_refine (+1 when warm-started) corrections per step in
+                              mixed precision */
 } hinv_options;
 
 typedef struct {
@@ -203,6 +207,14 @@ hinv_status emt_step(emt_handle c, int32_t n_steps, double* d_v_record, double* 
 /* Lose branch `branch` of case `case_idx` from the next step on (Algorithm 2's
  * situation, handled by a rank-1 SMW correction).  Synchronises the stream. */
 hinv_status emt_lose_line(emt_handle c, int32_t case_idx, int32_t branch, void* stream);
+
+/* Device-side status of the steps run since the last call (call after the
+ * stream is idle; clears it).  HINV_E_NO_CONVERGENCE: in mixed precision a
+ * step's last correction ||dv||/||v|| exceeded rel_tol; HINV_E_NOT_SPD: a
+ * non-finite value; HINV_E_DEVICE: a cooperative engine's inter-workgroup
+ * barrier timed out or a line change's endpoint had no row in a workgroup's
+ * tables (the trajectory is then invalid). */
+hinv_status emt_sync_status(emt_handle c);
 
 /* Index of the next step to be computed (1 after emt_create). */
 hinv_status emt_get_step(emt_handle c, int64_t* step);

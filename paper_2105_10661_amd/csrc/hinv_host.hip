@@ -480,7 +480,7 @@ hinv_status check_options(const hinv_options* o, int min_nrhs)
     if (o->max_nrhs < min_nrhs) return fail(HINV_E_INVALID, "max_nrhs %d < %d", o->max_nrhs, min_nrhs);
     if (o->prec != HINV_FP64 && (o->max_refine < 0 || o->max_refine > 64))
         return fail(HINV_E_INVALID, "max_refine %d outside 0..64", o->max_refine);
-    if (o->kernel_mode < 0 || o->kernel_mode > 3) return fail(HINV_E_INVALID, "kernel_mode %d unknown", o->kernel_mode);
+    if (o->kernel_mode < 0 || o->kernel_mode > 4) return fail(HINV_E_INVALID, "kernel_mode %d unknown", o->kernel_mode);
     if (o->prec != HINV_FP64 && !(o->rel_tol >= 0.0)) return fail(HINV_E_INVALID, "rel_tol must be >= 0");
     return HINV_OK;
 }
@@ -752,7 +752,7 @@ struct emt_ctx {
     // new-order network data kept for the team plan
     std::vector<int> inc_ptr, inc_br, src_ptr;
     std::vector<double> alpha, samp, sph, gC;
-    int engine = 1;              // 1 per-kernel, 2 one workgroup per case, 3 team
+    int engine = 1;              // 1 per-kernel, 2 one workgroup per case, 3 team, 4 panel
     // team engine
     bool team_ok = false;
     int team_nx_cap = 0;
@@ -761,6 +761,11 @@ struct emt_ctx {
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
     std::vector<int> tcsop;
     TeamDev TD{};
+    // panel engine (cases in panels of kPanelCases, one workgroup per leaf per panel)
+    bool panel_ok = false;
+    int panel_nx_cap = 0, panel_xz_cap = 0;
+    std::vector<int> pw_nx, pxrow, pxzo, pxpm, pxpc, pxpan, plpa, plpb, pczo, pcpm, pcpc, pcpan;
+    PanelDev PD{};
 };
 
 namespace {
@@ -913,6 +918,8 @@ void prepare_network(emt_ctx& c, const emt_network* net)
 
 bool build_team_plan(emt_ctx& c, int R);
 void carve_team(emt_ctx& c, Arena& A);
+bool build_panel_plan(emt_ctx& c, int R);
+void carve_panel(emt_ctx& c, Arena& A);
 
 hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_options* o, const emt_cases* C,
                      emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv, size_t* bytes)
@@ -952,11 +959,21 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
         }
         if (c.team_ok) carve_team(c, A);
     }
+    c.panel_ok = false;
+    if (((mode == 0 && c.n_cases > 1) || mode == 4) && fused_prec) {
+        c.panel_nx_cap = 0;
+        c.panel_ok = build_panel_plan(c, c.R);
+        if (c.panel_ok) carve_panel(c, A);
+    }
     const bool fits = run_fits(c.hc.H) && fused_prec;
     if (mode == 3 && !c.team_ok)
         return fail(HINV_E_INVALID, "the team engine needs FP64/FP32, one case, <= 256 leaves and fitting LDS");
+    if (mode == 4 && !c.panel_ok)
+        return fail(HINV_E_INVALID, "the panel engine needs FP64/FP32, max_mod_rank <= %d, leaves of <= 96 rows, <= 256 leaves and "
+                    "coupling columns, and tables that fit LDS", kPanelMaxRank);
     if (mode == 2 && !fits) return fail(HINV_E_INVALID, "the one-workgroup-per-case engine needs FP64/FP32 and a case that fits LDS");
-    c.engine = (mode == 1) ? 1 : (mode == 2) ? 2 : (mode == 3) ? 3 : c.team_ok ? 3 : fits ? 2 : 1;
+    c.engine = (mode == 1) ? 1 : (mode == 2) ? 2 : (mode == 3) ? 3 : (mode == 4) ? 4
+             : c.team_ok ? 3 : c.panel_ok ? 4 : fits ? 2 : 1;
     *bytes = A.off + kAlign;
     return HINV_OK;
 }
@@ -1154,6 +1171,293 @@ void carve_team(emt_ctx& c, Arena& A)
     D.sync = A.take<unsigned int>(L);
     D.csop = ti(D.nc);
     D.X0 = td(2 * (size_t)c.n);
+    D.VM = td(2 * L);
+}
+
+// ---------------------------------------------------------------------------
+// Panel plan: per-leaf tables (shared with the team layout's per-leaf vectors;
+// an EMT handle uses one of the two engines), per (team, leaf) X rows and
+// change endpoints, and the coupling columns' lower-level Z rows.
+bool build_panel_plan(emt_ctx& c, int R)
+{
+    const Plan& P = c.hc.P;
+    const int L = (int)P.leaf_lo.size(), H = P.n_levels, NC = (int)P.col_row.size();
+    if (R > kPanelMaxRank || L < 1 || L > 256 || NC > kPanelMaxCols || H < 0) return false;
+    const int n_teams = (c.n_cases + kPanelCases - 1) / kPanelCases;
+    std::vector<int> lpan((size_t)L * H, -1);
+    for (int l = 0; l < L; ++l) {
+        for (int k = 0; k < P.anc_stride; ++k) {
+            const int t = P.leaf_anc[(size_t)l * P.anc_stride + k];
+            if (t < 0) break;
+            const int h = P.node_level[t];
+            for (int pp = P.node_pan0[t]; pp < P.node_pan0[t] + P.node_npan[t]; ++pp)
+                if (P.pan_lo[pp] <= P.leaf_lo[l] && P.leaf_lo[l] < P.pan_lo[pp] + P.pan_n[pp]) lpan[(size_t)l * H + h - 1] = pp;
+        }
+    }
+    int rowz = 1;           // largest number of Z values of one row over all levels
+    for (int l = 0; l < L; ++l) {
+        int z = 0;
+        for (int h = 1; h <= H; ++h)
+            if (lpan[(size_t)l * H + h - 1] >= 0) z += P.pan_m[lpan[(size_t)l * H + h - 1]];
+        rowz = std::max(rowz, z);
+    }
+    // per leaf: fixed X rows (neighbours through G), own Z panels, CSR rows, branches, sources
+    struct W {
+        std::vector<int> fx, ozo, opm, opc, opan, orp, ocol, bglob, bf, bt, bown, iptr, ibr, sptr;
+        std::vector<double> oval, bg, bal, samp, sph;
+        int zo = 0;
+    };
+    std::vector<W> ws(L);
+    int NL = 1, NB = 1, NE = 1, NI = 1, NS = 1, ZO = 1;
+    for (int l = 0; l < L; ++l) {
+        W& w = ws[l];
+        const int lo = P.leaf_lo[l], nl = P.leaf_n[l];
+        auto own = [&](int r) { return r >= lo && r < lo + nl; };
+        for (int r = lo; r < lo + nl; ++r)
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
+                if (!own(P.ci[e])) w.fx.push_back(P.ci[e]);
+        std::sort(w.fx.begin(), w.fx.end());
+        w.fx.erase(std::unique(w.fx.begin(), w.fx.end()), w.fx.end());
+        auto comb = [&](int row) {
+            return own(row) ? row - lo : nl + (int)(std::lower_bound(w.fx.begin(), w.fx.end(), row) - w.fx.begin());
+        };
+        w.ozo.assign(H, -1); w.opm.assign(H, 0); w.opc.assign(H, 0); w.opan.assign(H, -1);
+        for (int h = 1; h <= H; ++h) {
+            const int pp = lpan[(size_t)l * H + h - 1];
+            if (pp < 0) continue;
+            w.opan[h - 1] = pp; w.ozo[h - 1] = w.zo; w.opm[h - 1] = P.pan_m[pp]; w.opc[h - 1] = P.pan_col0[pp];
+            w.zo += P.pan_m[pp] * nl;
+        }
+        w.orp.assign(nl + 1, 0);
+        for (int r = lo; r < lo + nl; ++r) {
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
+                w.ocol.push_back(comb(P.ci[e]));
+                w.oval.push_back(P.cv[e]);
+            }
+            w.orp[r - lo + 1] = (int)w.ocol.size();
+        }
+        std::vector<int> br;
+        for (int r = lo; r < lo + nl; ++r)
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q) br.push_back(c.inc_br[q]);
+        std::sort(br.begin(), br.end());
+        br.erase(std::unique(br.begin(), br.end()), br.end());
+        for (int e : br) {
+            w.bglob.push_back(e);
+            w.bf.push_back(comb(c.fr_p[e]));
+            w.bt.push_back(comb(c.to_p[e]));
+            w.bown.push_back(own(c.fr_p[e]) ? 1 : 0);
+            w.bg.push_back(c.g[e]);
+            w.bal.push_back(c.alpha[e]);
+        }
+        w.iptr.assign(nl + 1, 0);
+        w.sptr.assign(nl + 1, 0);
+        for (int r = lo; r < lo + nl; ++r) {
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q)
+                w.ibr.push_back((int)(std::lower_bound(br.begin(), br.end(), c.inc_br[q]) - br.begin()));
+            w.iptr[r - lo + 1] = (int)w.ibr.size();
+            for (int q = c.src_ptr[r]; q < c.src_ptr[r + 1]; ++q) {
+                w.samp.push_back(c.samp[q]);
+                w.sph.push_back(c.sph[q]);
+            }
+            w.sptr[r - lo + 1] = (int)w.samp.size();
+        }
+        NL = std::max(NL, nl); NB = std::max(NB, (int)br.size());
+        NE = std::max(NE, (int)w.ocol.size()); NI = std::max(NI, (int)w.ibr.size());
+        NS = std::max(NS, (int)w.samp.size()); ZO = std::max(ZO, w.zo);
+    }
+    // coupling columns: Z values of the column's row below the column's level
+    c.pczo.assign((size_t)NC * H, -1); c.pcpm.assign((size_t)NC * H, 0);
+    c.pcpc.assign((size_t)NC * H, 0); c.pcpan.assign((size_t)NC * H, -1);
+    int CZ = 0;
+    for (int g = 0; g < NC; ++g) {
+        const int hg = P.node_level[P.col_node[g]];
+        const int lx = P.row_leaf[P.col_row[g]];
+        for (int hh = 1; hh < hg; ++hh) {
+            const int pp = lpan[(size_t)lx * H + hh - 1];
+            if (pp < 0) continue;
+            const size_t i = (size_t)g * H + hh - 1;
+            c.pczo[i] = CZ; c.pcpm[i] = P.pan_m[pp]; c.pcpc[i] = P.pan_col0[pp]; c.pcpan[i] = pp;
+            CZ += P.pan_m[pp];
+        }
+    }
+    int max_lw = 1;
+    for (int h = 1; h <= H; ++h) max_lw = std::max(max_lw, P.lvl_col[h] - P.lvl_col[h - 1]);
+    // per (team, leaf): X rows = fixed rows, then the team's loss endpoints
+    std::vector<std::vector<int>> X((size_t)n_teams * L);
+    std::vector<std::vector<int>> lpa((size_t)n_teams * L), lpb((size_t)n_teams * L);
+    int NX = 1, XZ = 1;
+    for (int tm = 0; tm < n_teams; ++tm) {
+        std::vector<int> lrows;
+        for (int cc = 0; cc < kPanelCases; ++cc) {
+            const int k = tm * kPanelCases + cc;
+            if (k >= c.n_cases) break;
+            for (auto& x : c.losses[k]) {
+                lrows.push_back(c.fr_p[x.second]);
+                lrows.push_back(c.to_p[x.second]);
+            }
+        }
+        for (int l = 0; l < L; ++l) {
+            const int lo = P.leaf_lo[l], nl = P.leaf_n[l];
+            auto own = [&](int r) { return r >= lo && r < lo + nl; };
+            std::vector<int>& xr = X[(size_t)tm * L + l];
+            xr = ws[l].fx;
+            for (int r : lrows)
+                if (!own(r) && std::find(xr.begin(), xr.end(), r) == xr.end()) xr.push_back(r);
+            auto comb = [&](int row) {
+                if (own(row)) return row - lo;
+                return nl + (int)(std::find(xr.begin(), xr.end(), row) - xr.begin());
+            };
+            int xz = 0;
+            for (int row : xr) {
+                const int lx = P.row_leaf[row];
+                for (int h = 1; h <= H; ++h)
+                    if (lpan[(size_t)lx * H + h - 1] >= 0) xz += P.pan_m[lpan[(size_t)lx * H + h - 1]];
+            }
+            std::vector<int>& pa = lpa[(size_t)tm * L + l];
+            std::vector<int>& pb = lpb[(size_t)tm * L + l];
+            pa.assign((size_t)kPanelCases * R, -1);
+            pb.assign((size_t)kPanelCases * R, -1);
+            for (int cc = 0; cc < kPanelCases; ++cc) {
+                const int k = tm * kPanelCases + cc;
+                if (k >= c.n_cases) break;
+                const auto& Lk = c.losses[k];
+                for (size_t j = 0; j < Lk.size(); ++j) {
+                    pa[(size_t)cc * R + j] = comb(c.fr_p[Lk[j].second]);
+                    pb[(size_t)cc * R + j] = comb(c.to_p[Lk[j].second]);
+                }
+            }
+            NX = std::max(NX, (int)xr.size());
+            XZ = std::max(XZ, xz);
+        }
+    }
+    if (c.panel_nx_cap == 0) {            // room for the endpoints of later line losses
+        c.panel_nx_cap = NX + 8;
+        c.panel_xz_cap = XZ + 8 * rowz;
+    }
+    if (NX > c.panel_nx_cap || XZ > c.panel_xz_cap) return false;
+    PanelDev& D = c.PD;
+    D.T = L; D.H = H; D.NL = NL; D.NLp = (NL + 15) / 16 * 16; D.NX = c.panel_nx_cap; D.NB = NB; D.NE = NE;
+    D.NI = NI; D.NS = NS; D.XZ = c.panel_xz_cap; D.ZO = ZO; D.CZ = std::max(CZ, 1); D.nc = NC; D.max_lw = max_lw;
+    D.n_teams = n_teams; D.team0 = 0;
+    if (D.NX > kPanelMaxX || D.NL > kPanelMaxLeaf) return false;
+    c.tcsop.assign(NC, 0);
+    {
+        int64_t off = 0;
+        for (size_t t = 0; t < P.node_m.size(); ++t) {
+            const int m = P.node_m[t];
+            for (int q = 0; q < m; ++q) c.tcsop[P.node_col0[t] + q] = (int)(off + q);
+            off += (int64_t)m * (m + 1);
+        }
+        D.sent = (int)std::max<int64_t>(off, 1);
+    }
+    if (panel_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) return false;
+    auto flat = [&](std::vector<int>& dst, size_t stride, auto get) {
+        dst.assign((size_t)L * stride, 0);
+        for (int l = 0; l < L; ++l) {
+            const std::vector<int>& src = get(ws[l]);
+            std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
+        }
+    };
+    auto flatd = [&](std::vector<double>& dst, size_t stride, auto get) {
+        dst.assign((size_t)L * stride, 0.0);
+        for (int l = 0; l < L; ++l) {
+            const std::vector<double>& src = get(ws[l]);
+            std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
+        }
+    };
+    c.tw_lo = P.leaf_lo; c.tw_nl = P.leaf_n;
+    c.tw_nb.resize(L);
+    for (int l = 0; l < L; ++l) c.tw_nb[l] = (int)ws[l].bglob.size();
+    flat(c.tozo, H, [](W& w) -> std::vector<int>& { return w.ozo; });
+    flat(c.topm, H, [](W& w) -> std::vector<int>& { return w.opm; });
+    flat(c.topc, H, [](W& w) -> std::vector<int>& { return w.opc; });
+    flat(c.topan, H, [](W& w) -> std::vector<int>& { return w.opan; });
+    flat(c.torp, NL + 1, [](W& w) -> std::vector<int>& { return w.orp; });
+    flat(c.tocol, NE, [](W& w) -> std::vector<int>& { return w.ocol; });
+    flat(c.tbglob, NB, [](W& w) -> std::vector<int>& { return w.bglob; });
+    flat(c.tbf, NB, [](W& w) -> std::vector<int>& { return w.bf; });
+    flat(c.tbt, NB, [](W& w) -> std::vector<int>& { return w.bt; });
+    flat(c.tbown, NB, [](W& w) -> std::vector<int>& { return w.bown; });
+    flat(c.tiptr, NL + 1, [](W& w) -> std::vector<int>& { return w.iptr; });
+    flat(c.tibr, NI, [](W& w) -> std::vector<int>& { return w.ibr; });
+    flat(c.tsptr, NL + 1, [](W& w) -> std::vector<int>& { return w.sptr; });
+    flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
+    flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
+    flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
+    flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
+    flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
+    const size_t TW = (size_t)n_teams * L, NXc = D.NX;
+    c.pw_nx.assign(TW, 0);
+    c.pxrow.assign(TW * NXc, 0);
+    c.pxzo.assign(TW * NXc * H, -1); c.pxpm.assign(TW * NXc * H, 0); c.pxpc.assign(TW * NXc * H, 0);
+    c.pxpan.assign(TW * NXc * H, -1);
+    c.plpa.assign(TW * kPanelCases * R, -1); c.plpb.assign(TW * kPanelCases * R, -1);
+    for (size_t tw = 0; tw < TW; ++tw) {
+        const std::vector<int>& xr = X[tw];
+        c.pw_nx[tw] = (int)xr.size();
+        int xz = 0;
+        for (size_t x = 0; x < xr.size(); ++x) {
+            c.pxrow[tw * NXc + x] = xr[x];
+            const int lx = P.row_leaf[xr[x]];
+            for (int h = 1; h <= H; ++h) {
+                const int pp = lpan[(size_t)lx * H + h - 1];
+                if (pp < 0) continue;
+                const size_t i = (tw * NXc + x) * H + h - 1;
+                c.pxzo[i] = xz; c.pxpm[i] = P.pan_m[pp]; c.pxpc[i] = P.pan_col0[pp]; c.pxpan[i] = pp;
+                xz += P.pan_m[pp];
+            }
+        }
+        std::copy(lpa[tw].begin(), lpa[tw].end(), c.plpa.begin() + tw * kPanelCases * R);
+        std::copy(lpb[tw].begin(), lpb[tw].end(), c.plpb.begin() + tw * kPanelCases * R);
+    }
+    return true;
+}
+
+// Workspace for the panel tables (X-row tables with capacity strides).
+void carve_panel(emt_ctx& c, Arena& A)
+{
+    PanelDev& D = c.PD;
+    const int64_t L = D.T, H = D.H, TW = (int64_t)D.n_teams * D.T, R = c.R;
+    auto ti = [&](int64_t cnt) { return A.take<int>(cnt); };
+    auto td = [&](int64_t cnt) { return A.take<double>(cnt); };
+    D.w_lo = ti(L); D.w_nl = ti(L); D.w_nb = ti(L);
+    D.ozo = ti(L * H); D.opm = ti(L * H); D.opc = ti(L * H); D.opan = ti(L * H);
+    D.orp = ti(L * (D.NL + 1)); D.ocol = ti(L * D.NE); D.oval = td(L * D.NE);
+    D.bglob = ti(L * D.NB); D.bf = ti(L * D.NB); D.bt = ti(L * D.NB); D.bown = ti(L * D.NB);
+    D.bg = td(L * D.NB); D.bal = td(L * D.NB);
+    D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
+    D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
+    D.w_nx = ti(TW); D.xrow = ti(TW * D.NX);
+    D.xzo = ti(TW * D.NX * H); D.xpm = ti(TW * D.NX * H); D.xpc = ti(TW * D.NX * H); D.xpan = ti(TW * D.NX * H);
+    D.lpa = ti(TW * kPanelCases * R); D.lpb = ti(TW * kPanelCases * R);
+    D.csop = ti(D.nc);
+    D.czo = ti((int64_t)D.nc * H); D.cpm = ti((int64_t)D.nc * H); D.cpc = ti((int64_t)D.nc * H);
+    D.cpan = ti((int64_t)D.nc * H);
+    D.sync = A.take<unsigned int>(TW);
+    D.X0 = td((int64_t)D.n_teams * 2 * c.n * kPanelCases);
+    D.VM = td(TW * 2 * kPanelCases);
+}
+
+hinv_status upload_panel(emt_ctx& c, hipStream_t s)
+{
+    PanelDev& D = c.PD;
+    HIP_TRY(up(D.w_lo, c.tw_lo, s)); HIP_TRY(up(D.w_nl, c.tw_nl, s)); HIP_TRY(up(D.w_nb, c.tw_nb, s));
+    HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.opc, c.topc, s));
+    HIP_TRY(up(D.opan, c.topan, s));
+    HIP_TRY(up(D.orp, c.torp, s)); HIP_TRY(up(D.ocol, c.tocol, s)); HIP_TRY(up(D.oval, c.toval, s));
+    HIP_TRY(up(D.bglob, c.tbglob, s)); HIP_TRY(up(D.bf, c.tbf, s)); HIP_TRY(up(D.bt, c.tbt, s));
+    HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
+    HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
+    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
+    HIP_TRY(up(D.w_nx, c.pw_nx, s)); HIP_TRY(up(D.xrow, c.pxrow, s));
+    HIP_TRY(up(D.xzo, c.pxzo, s)); HIP_TRY(up(D.xpm, c.pxpm, s)); HIP_TRY(up(D.xpc, c.pxpc, s));
+    HIP_TRY(up(D.xpan, c.pxpan, s)); HIP_TRY(up(D.lpa, c.plpa, s)); HIP_TRY(up(D.lpb, c.plpb, s));
+    HIP_TRY(up(D.csop, c.tcsop, s));
+    HIP_TRY(up(D.czo, c.pczo, s)); HIP_TRY(up(D.cpm, c.pcpm, s)); HIP_TRY(up(D.cpc, c.pcpc, s));
+    HIP_TRY(up(D.cpan, c.pcpan, s));
+    HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.n_teams * D.T * sizeof(unsigned int), s));
+    HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
+    return HINV_OK;
 }
 
 hinv_status upload_team(emt_ctx& c, hipStream_t s)
@@ -1286,6 +1590,7 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     carve_hier(c->hc, A, c->n_cases, c->R, c->hc.opt.max_nrhs);
     carve_emt(*c, A, net->n_src);
     if (c->team_ok) carve_team(*c, A);
+    if (c->panel_ok) carve_panel(*c, A);
     if (A.off > ws_bytes) return fail(HINV_E_NO_MEMORY, "workspace layout exceeds %zu bytes", ws_bytes);
     c->hc.M.R = c->R;
     EmtDev& E = c->E;
@@ -1300,6 +1605,10 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     if (st != HINV_OK) return st;
     if (c->team_ok) {
         st = upload_team(*c, s);
+        if (st != HINV_OK) return st;
+    }
+    if (c->panel_ok) {
+        st = upload_panel(*c, s);
         if (st != HINV_OK) return st;
     }
     if (st != HINV_OK) return st;
@@ -1330,6 +1639,8 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
                     c.step, n_steps};
         if (c.engine == 3)
             HIP_TRY(launch_emt_team(c.TD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
+        else if (c.engine == 4)
+            HIP_TRY(launch_emt_panel(c.PD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         else
             HIP_TRY(launch_emt_run(c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         c.step += n_steps;
@@ -1380,6 +1691,29 @@ hinv_status emt_lose_line(emt_handle h, int32_t case_idx, int32_t branch, void* 
             if (st != HINV_OK) return st;
         }
     }
+    if (c.engine == 4) {       // the same for the workgroups of the case's team
+        if (!build_panel_plan(c, c.R)) {
+            c.engine = run_fits(c.hc.H) ? 2 : 1;
+            c.panel_ok = false;
+        } else {
+            st = upload_panel(c, s);
+            if (st != HINV_OK) return st;
+        }
+    }
+    return HINV_OK;
+}
+
+hinv_status emt_sync_status(emt_handle h)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    int flags[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(flags, h->hc.d_flags, sizeof flags, hipMemcpyDeviceToHost));
+    int zero[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(h->hc.d_flags, zero, sizeof zero, hipMemcpyHostToDevice));
+    if (flags[0] & kFlagBarrier) return fail(HINV_E_DEVICE, "an inter-workgroup barrier timed out");
+    if (flags[0] & kFlagTeamRow) return fail(HINV_E_DEVICE, "a line change endpoint has no row in a workgroup's tables");
+    if (flags[0] & (kFlagNotSPD | kFlagNaN)) return fail(HINV_E_NOT_SPD, "non-finite or indefinite result");
+    if (flags[0] & kFlagNoConv) return fail(HINV_E_NO_CONVERGENCE, "refinement did not reach rel_tol");
     return HINV_OK;
 }
 

@@ -250,6 +250,63 @@ struct TeamDev {
     const double* sph;
     unsigned int* sync;  // [T] barrier epoch flag of each workgroup
     double* X0;          // [2*n] exchange of leaf results (double-buffered by apply parity)
+    double* VM;          // [2*T] each workgroup's max |v| (same buffering)
+};
+
+// Panel stepping (k_panel.hip): cases that share one base network advance in
+// panels of kPanelCases; a team of one workgroup per leaf owns one panel and
+// applies the leaf blocks to the panel as one matrix product.  Per-leaf tables
+// use fixed strides as in TeamDev.  X rows of a (team, leaf) pair: first the
+// leaf's fixed external rows (neighbours of its buses through G, the same in
+// every team), then the endpoints of the team's line losses.  Combined index:
+// own row r -> r, X row x -> nl + x.  Vectors are row-major [row][case].
+constexpr int kPanelCases = 16;
+constexpr int kPanelMaxRank = 2;
+constexpr int kPanelMaxLeaf = 96;    // rows of a leaf
+constexpr int kPanelMaxCols = 256;   // coupling columns of the tree
+constexpr int kPanelMaxX = 128;      // X rows of a (team, leaf) pair
+struct PanelDev {
+    int T, H, NL, NLp, NX, NB, NE, NI, NS, XZ, ZO, CZ, nc, sent, max_lw, n_teams, team0;
+    // per leaf l
+    const int* w_lo;
+    const int* w_nl;
+    const int* w_nb;
+    const int* ozo;      // [T*H] offset of the own rows' Z values at level h in the zown region, -1: none
+    const int* opm;
+    const int* opc;
+    const int* opan;
+    const int* orp;      // [T*(NL+1)] own CSR rows of G, combined column indices (fixed X rows)
+    const int* ocol;     // [T*NE]
+    const double* oval;
+    const int* bglob;    // [T*NB] incident branches: global id, endpoints (combined), owner flag
+    const int* bf;
+    const int* bt;
+    const int* bown;
+    const double* bg;
+    const double* bal;
+    const int* iptr;     // [T*(NL+1)] incident local branches of each own row
+    const int* ibr;      // [T*NI]
+    const int* sptr;     // [T*(NL+1)] sources of each own row
+    const double* samp;  // [T*NS]
+    const double* sph;
+    // per (team, leaf) pair tw = team*T + l
+    const int* w_nx;     // [n_teams*T]
+    const int* xrow;     // [n_teams*T*NX] new-order row of each X row
+    const int* xzo;      // [n_teams*T*NX*H] offset of the row's Z values at level h in the xz region, -1: none
+    const int* xpm;
+    const int* xpc;
+    const int* xpan;
+    const int* lpa;      // [n_teams*T*kPanelCases*R] combined index of each change's endpoints (-1: ground/unused)
+    const int* lpb;
+    // coupling columns (the same for every workgroup)
+    const int* csop;     // [nc] LDS offset of the column's node S^{-1} (row stride m+1) + column index in node
+    const int* czo;      // [nc*H] offset of the column row's Z values at level h < level(column) in the cz region
+    const int* cpm;
+    const int* cpc;
+    const int* cpan;
+    unsigned int* sync;  // [n_teams*T] barrier epoch flags
+    double* X0;          // [n_teams][2][n][kPanelCases] exchange of leaf products (double-buffered)
+    double* VM;          // [n_teams][2][T][kPanelCases] each workgroup's max |v| per case (same buffering)
 };
 
 // Host-side per-level launch sizes (level l = 1..n_levels at index l-1).
@@ -300,6 +357,11 @@ void launch_set_rec(RecParams* d, const RecParams& val, hipStream_t s);
 size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec);
 hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                            int prec, hipStream_t s);
+// Panel stepping (k_panel.hip): LDS bytes of the layout, and the launch (all
+// teams, in as many consecutive cooperative launches as residency requires).
+size_t panel_lds_bytes(const PanelDev& D, int R, int prec);
+hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
+                            int prec, hipStream_t s);
 // Fused stepping (k_run.hip): one workgroup per case, all steps in one launch.
 bool run_fits(const HierDev& H);
 size_t serve_lds_bytes(const HierDev& H, bool gvec);

@@ -17,6 +17,7 @@
 // both, so their values agree bitwise and the history update of a tie line
 // (and the refinement residual) needs no second exchange.
 #include "hinv_internal.h"
+#include "team_sync.h"
 
 namespace hinv {
 
@@ -24,7 +25,6 @@ constexpr int kTeamThreads = 1024;
 constexpr int kTeamWaves = kTeamThreads / 64;
 constexpr int kGemvChunks = kTeamWaves / 2;   // leaf GEMV: 2 row halves (lanes) x 8 column chunks
 constexpr int kSub = 4;                 // lanes per coupling-column dot product
-constexpr int kTeamSpinLimit = 1 << 24;
 
 template <typename TB>
 struct TAcc { using T = float; };
@@ -35,7 +35,7 @@ struct TeamLayout {
     size_t blk, sall, zown, xz, uown, ux;
     size_t b, v, t, d, part, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, colw, cinv, mdg, red, tz;
     size_t xrow, xzo, xpm, xpc, ozo, opm, opc, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
-    size_t lpa, lpb, loa, lob, mact, lbr, lst, ctl;
+    size_t lpa, lpb, loa, lob, mact, lbr, lst, vg, ctl;
     size_t total;
 };
 
@@ -78,6 +78,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.iptr = take(I * (NL + 1)); L.ibr = take(I * T.NI); L.sptr = take(I * (NL + 1));
     L.lpa = take(I * R); L.lpb = take(I * R); L.loa = take(I * R); L.lob = take(I * R);
     L.mact = take(I * R); L.lbr = take(I * R); L.lst = take(I * R);
+    L.vg = take(sizeof(unsigned long long));
     L.ctl = take(I * 8);
     L.total = o;
     return L;
@@ -87,40 +88,6 @@ size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec)
 {
     (void)H;
     return prec == HINV_FP64 ? team_layout<double>(T, R).total : team_layout<float>(T, R).total;
-}
-
-// Barrier of the T workgroups of the team, by per-workgroup epoch flags:
-// each workgroup release-stores its epoch (after all its threads' global
-// writes), then one wavefront polls every flag with relaxed agent-scope loads
-// and a wave vote, and a single acquire fence follows; no read-modify-write
-// on a shared counter.  The wait is bounded: on time-out it flags
-// kFlagBarrier and returns false.
-__device__ inline bool team_barrier(unsigned int* flags, int T, unsigned int epoch, int* errflags, int* ctl)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x < 64) {
-        int ok = 1;
-        int spins = 0;
-        while (true) {
-            int mine = 1;
-            for (int i = threadIdx.x; i < T; i += 64)
-                mine &= (__hip_atomic_load(&flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch) ? 1 : 0;
-            if (__all(mine)) break;
-            if (++spins > kTeamSpinLimit) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (threadIdx.x == 0) {
-            ctl[0] = ok;
-            if (!ok) atomicOr(errflags, kFlagBarrier);
-        }
-    }
-    __syncthreads();
-    return ctl[0] != 0;
 }
 
 template <typename TB, bool MIXED, bool WARM>
@@ -189,6 +156,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     int* mact = (int*)(L8 + Ly.mact);
     int* lbr = (int*)(L8 + Ly.lbr);
     int* lst = (int*)(L8 + Ly.lst);
+    unsigned long long* vg = (unsigned long long*)(L8 + Ly.vg);
     int* ctl = (int*)(L8 + Ly.ctl);
 
     const TB* gblk;
@@ -322,7 +290,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
 
     // one application of the stored inverse (with the active line changes):
     // out (own rows), outx (X rows) from xin (own rows)
-    auto apply = [&](const double* xin, double* out, double* outx, int ract) -> bool {
+    auto apply = [&](const double* xin, double* out, double* outx, int ract, bool want_vm) -> bool {
         // wavefront w: rows 64*(w / kGemvChunks) + lane, block columns j = w % kGemvChunks (mod kGemvChunks)
         {
             const int r = (wave / kGemvChunks) * 64 + lane, c = wave % kGemvChunks;
@@ -340,7 +308,11 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             out[r] = val;
             X0[lo + r] = val;
         }
-        if (!team_barrier(T.sync, T.T, ++epoch, P.flags, ctl)) return false;
+        if (!team_barrier(T.sync, w, T.T, ++epoch, P.flags, ctl)) return false;
+        if (want_vm) {   // the team's largest |v| (vg was cleared before the barrier)
+            for (int i = tid; i < T.T; i += kTeamThreads)
+                atomicMax(vg, (unsigned long long)__double_as_longlong(T.VM[(int64_t)par * T.T + i]));
+        }
         for (int x = tid; x < nx; x += kTeamThreads) outx[x] = X0[xrow[x]];
         __syncthreads();
         // coupling levels bottom-up: gather s (an endpoint row's lower-level
@@ -449,29 +421,35 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             }
             t[r] = b[r] - acc;
         }
-        __syncthreads();
-        if (!apply(t, d, xd, ract)) return false;
-        double dm = 0.0, vm = 0.0;
-        for (int r = tid; r < nl; r += kTeamThreads) {
-            const double nv = v[r] + d[r];
-            v[r] = nv;
-            dm = fmax(dm, fabs(d[r]));
-            vm = fmax(vm, fabs(nv));
-        }
-        for (int x = tid; x < nx; x += kTeamThreads) xv[x] += xd[x];
-        if (last) {
-            for (int o = 32; o > 0; o >>= 1) {
-                dm = fmax(dm, __shfl_xor(dm, o));
-                vm = fmax(vm, __shfl_xor(vm, o));
-            }
-            if (lane == 0) { red[wave] = dm; red[kTeamWaves + wave] = vm; }
+        if (last) {        // publish this workgroup's max |v| for the team-wide norm
+            double vm = 0.0;
+            for (int r = tid; r < nl; r += kTeamThreads) vm = fmax(vm, fabs(v[r]));
+            for (int o = 32; o > 0; o >>= 1) vm = fmax(vm, __shfl_xor(vm, o));
+            if (lane == 0) red[kTeamWaves + wave] = vm;
             __syncthreads();
             if (tid == 0) {
-                double D = 0.0, V = 0.0;
-                for (int q = 0; q < kTeamWaves; ++q) {
-                    D = fmax(D, red[q]);
-                    V = fmax(V, red[kTeamWaves + q]);
-                }
+                double V = 0.0;
+                for (int q = 0; q < kTeamWaves; ++q) V = fmax(V, red[kTeamWaves + q]);
+                T.VM[(int64_t)par * T.T + w] = V;
+                *vg = 0ull;
+            }
+        }
+        __syncthreads();
+        if (!apply(t, d, xd, ract, last)) return false;
+        double dm = 0.0;
+        for (int r = tid; r < nl; r += kTeamThreads) {
+            v[r] += d[r];
+            dm = fmax(dm, fabs(d[r]));
+        }
+        for (int x = tid; x < nx; x += kTeamThreads) xv[x] += xd[x];
+        if (last) {        // max |d| over the own rows / the team's max |v|
+            for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
+            if (lane == 0) red[wave] = dm;
+            __syncthreads();
+            if (tid == 0) {
+                double D = 0.0;
+                for (int q = 0; q < kTeamWaves; ++q) D = fmax(D, red[q]);
+                const double V = __longlong_as_double((long long)*vg);
                 const double ratio = V > 0.0 ? D / V : (D > 0.0 ? INFINITY : 0.0);
                 if (!isfinite(ratio)) atomicOr(P.flags, kFlagNaN);
                 else {
@@ -490,12 +468,12 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         int ract = 0;
         while (ract < cnt && (int64_t)mact[ract] <= step) ++ract;
         if (!MIXED) {
-            alive = apply(b, v, xv, ract);
+            alive = apply(b, v, xv, ract, false);
             applies += 1;
         } else {
             const int nref = WARM ? P.max_refine + 1 : P.max_refine;
             if (!WARM) {
-                alive = apply(b, v, xv, ract);
+                alive = apply(b, v, xv, ract, false);
                 applies += 1;
             }
             for (int q = 0; q < nref && alive; ++q) {

@@ -24,7 +24,8 @@ STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "
 
 EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_solve", "hinv_sync_status",
            "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_workspace_size", "emt_create",
-           "emt_step", "emt_lose_line", "emt_get_step", "emt_get_stats", "emt_set_step_clock", "emt_destroy",
+           "emt_step", "emt_lose_line", "emt_sync_status", "emt_get_step", "emt_get_stats", "emt_set_step_clock",
+           "emt_destroy",
            "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
            "serve_step", "serve_active", "serve_destroy", "hinv_last_error")
 
@@ -93,6 +94,7 @@ def load() -> ctypes.CDLL:
         "emt_create": [P, P, P, P, P, ctypes.c_size_t, P, P],
         "emt_step": [P, i32, P, P, P],
         "emt_lose_line": [P, i32, i32, P],
+        "emt_sync_status": [P],
         "emt_get_step": [P, P],
         "emt_get_stats": [P, P, P],
         "emt_set_step_clock": [P, P, i64],
@@ -135,7 +137,7 @@ def _stream(torch_stream=None) -> int:
     return s.cuda_stream
 
 
-KERNEL_MODES = {"auto": 0, "per_kernel": 1, "fused": 2, "team": 3}
+KERNEL_MODES = {"auto": 0, "per_kernel": 1, "fused": 2, "team": 3, "panel": 4}
 
 
 def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs, warm_start=False, kernel_mode="auto") -> _Options:
@@ -318,6 +320,13 @@ class EMT:
 
     def lose_line(self, case_idx: int, branch: int) -> None:
         _check(self._lib.emt_lose_line(self._h, int(case_idx), int(branch), _stream()), "emt_lose_line")
+
+    def sync_status(self) -> None:
+        """Raise HinvError if a device-side failure (barrier time-out, unmapped change
+        endpoint, non-finite value, refinement above rel_tol) happened since the last call."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+        _check(self._lib.emt_sync_status(self._h), "emt_sync_status")
 
     @property
     def next_step(self) -> int:

@@ -4,8 +4,9 @@ The 11456-bus (8x8 torus) and 5728-bus (8x4 torus) networks run on the
 per-kernel engine (their root capacitance matrices do not fit a workgroup's
 LDS); the oracle there is the library sparse LU of G (SuperLU), pinned
 against the dense LU on the 179-bus network.  The 256-case contingency batch
-runs on the one-workgroup-per-case engine; sampled cases are checked against
-full oracle trajectories and against the same case run alone (bitwise).
+runs on the one-workgroup-per-case engine and on the panel engine; sampled
+cases are checked against full oracle trajectories and against the same case
+run alone on the same engine (bitwise).
 Tolerance: 1e-10 relative (per solve: per-vector infinity norm; trajectories:
 normalised by the peak voltage).
 """
@@ -59,11 +60,13 @@ def test_torus_11456_trajectory_with_loss(hv, prec):
     emt.close()
 
 
-def test_contingency_batch_256(hv):
+@pytest.mark.parametrize("mode,prec,warm", [("fused", "fp32", True), ("panel", "fp32", True),
+                                            ("panel", "fp32", False), ("panel", "fp64", False)])
+def test_contingency_batch_256(hv, mode, prec, warm):
     base, bcases = cases.cases_c4(n_cases=256, n_steps=1200, step_range=(1, 900))
     losses = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
-    print("[gpu] 256-case batch", flush=True)
-    kw = dict(prec="fp32", max_refine=2, rel_tol=1e-9, warm_start=True, max_mod_rank=1)
+    print(f"[gpu] 256-case batch {mode} {prec} warm={warm}", flush=True)
+    kw = dict(prec=prec, max_refine=2, rel_tol=1e-9, warm_start=warm, max_mod_rank=1, kernel_mode=mode)
     emt = hv.EMT(base, 256, losses=losses, **kw)
     V, _ = emt.step(1200)
     Vb = V.cpu().numpy()
@@ -71,8 +74,9 @@ def test_contingency_batch_256(hv):
         st, br = losses[k][0]
         Vref, _ = oracle.emt_run(base, 1200, loss_steps=[st], loss_branches=[br], solver="inv")
         assert np.abs(Vb[:, k, :] - Vref).max() / np.abs(Vref).max() <= 1e-10, k
+    emt.sync_status()
     for k in (3, 130):
-        one = hv.EMT(base, 1, losses=[losses[k]], kernel_mode="fused", **kw)
+        one = hv.EMT(base, 1, losses=[losses[k]], **kw)
         V1, _ = one.step(1200)
         assert np.array_equal(V1[:, 0, :].cpu().numpy(), Vb[:, k, :]), k
         one.close()

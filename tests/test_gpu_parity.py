@@ -159,6 +159,7 @@ def test_emt_179_trajectory(hv, c1_ref, prec, mode, warm):
     peak = np.abs(Vref).max()
     assert np.abs(Vg - Vref).max() / peak <= 1e-10
     assert emt.next_step == case.n_steps + 1
+    emt.sync_status()
     emt.close()
 
 
@@ -210,6 +211,7 @@ def test_emt_1432_with_line_loss(hv, c2_ref, prec, mode, warm):
         applies, rel = emt.stats()
         assert rel <= 1e-9
         print(f"[gpu] applies per step {applies / case.n_steps:.2f}", flush=True)
+    emt.sync_status()
     emt.close()
 
 
