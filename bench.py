@@ -37,7 +37,8 @@ METRIC = "EMT network solves/s + p99 step latency, mixed vs FP64 at 1e-10 rel er
 HBM_PEAK_GBS = 8000.0
 
 
-def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_refine, rel_tol, record, khz):
+def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_refine, rel_tol, record, khz,
+              kernel_mode="auto", max_mod_rank=2):
     """Chunked launches of `chunk` steps: warmup launches untimed, then the timed launches.
 
     Returns timing of the whole timed region, the mean duration of one launch of
@@ -45,8 +46,8 @@ def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_re
     the kernel's wall-clock stamps (case 0), stats, and the recorded trajectory.
     """
     n_cases = len(losses)
-    emt = hinv.EMT(net, n_cases, losses=losses, prec=prec, max_refine=max_refine, rel_tol=rel_tol, max_mod_rank=2,
-                   warm_start=warm)
+    emt = hinv.EMT(net, n_cases, losses=losses, prec=prec, max_refine=max_refine, rel_tol=rel_tol,
+                   max_mod_rank=max_mod_rank, warm_start=warm, kernel_mode=kernel_mode)
     n = net.n_bus
     total = warmup + steps
     V = torch.empty((total, n_cases, n), dtype=torch.float64, device="cuda") if record else None
@@ -73,9 +74,15 @@ def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_re
     c = clk.cpu().numpy().astype(np.float64)
     lat_us = (np.diff(c, axis=1) / khz * 1e3).ravel()
     applies, rel = emt.stats()
+    try:
+        emt.sync_status()
+        status = "ok"
+    except hinv.HinvError as e:          # e.g. a step whose last correction stayed above rel_tol
+        status = e.name
     emt.close()
     return {"region_ms": region_ms, "launch_ms": float(launch_ms.mean()), "steps": n_launch * chunk,
-            "lat_us": lat_us, "applies": applies, "max_last_update": rel, "V": V, "n_cases": n_cases}
+            "lat_us": lat_us, "applies": applies, "max_last_update": rel, "V": V, "n_cases": n_cases,
+            "status": status, "warmup": warmup}
 
 
 def study_11456(hinv, torch, khz, steps=200):
@@ -209,12 +216,12 @@ def main():
     def summary(r, prec):
         steps = r["steps"]
         ms_step = r["region_ms"] / steps
-        aps = r["applies"] / (r["n_cases"] * (args.warmup + steps)) if r["n_cases"] else 0
+        aps = r["applies"] / (r["n_cases"] * (r["warmup"] + steps)) if r["n_cases"] else 0
         out = {"solves_per_s": round(r["n_cases"] * steps / (r["region_ms"] * 1e-3), 1),
                "ms_per_step": round(ms_step, 6),
                "p50_step_us": round(float(np.percentile(r["lat_us"], 50)), 3),
                "p99_step_us": round(float(np.percentile(r["lat_us"], 99)), 3),
-               "applies_per_step": round(aps, 3)}
+               "applies_per_step": round(aps, 3), "device_status": r["status"]}
         if prec != "fp64":
             out["max_last_correction"] = r["max_last_update"]
         return out, aps
@@ -232,11 +239,41 @@ def main():
                                       step_range=(1, max(2, args.batch_steps // 2)))
         bl = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
         batch = {"cases": args.batch_cases, "steps": args.batch_steps,
-                 "network": "1432-bus 8-copy ring, each case loses a distinct line at a random step"}
-        for name, (prec, warm, mr, tol) in (("fp64", ("fp64", False, 0, 1e-9)),
-                                            ("mixed", ("fp32", True, args.max_refine, args.rel_tol))):
-            r = timed_run(hinv, torch, base, bl, prec, warm, 0, args.batch_steps, args.chunk, mr, tol, False, khz)
-            batch[name], _ = summary(r, prec)
+                 "network": "1432-bus 8-copy ring, each case loses a distinct line at a random step",
+                 "engines": {"per_case": "one workgroup per case (leaf applies as LDS GEMVs)",
+                             "panel": "panels of 16 cases, one workgroup per leaf per panel, leaf blocks applied "
+                                      "to the panel with 16x16x4 MFMA, per-case SMW fused"}}
+        Hb = hinv.Hierarchy.from_network(base)
+        binfo = Hb.info()
+        Hb.close()
+        bpaths = {"fp64": ("fp64", False, 0, 1e-9), "mixed": ("fp32", True, args.max_refine, args.rel_tol)}
+        for eng, mode in (("per_case", "fused"), ("panel", "panel")):
+            for name, (prec, warm, mr, tol) in bpaths.items():
+                r = timed_run(hinv, torch, base, bl, prec, warm, 0, args.batch_steps, args.chunk, mr, tol, False, khz,
+                              kernel_mode=mode, max_mod_rank=1)
+                batch[f"{eng}_{name}"], aps = summary(r, prec)
+                if eng == "panel":
+                    # dense work of the leaf products on the matrix cores: 2 flops per leaf entry per case per apply
+                    leaf_flops = 2.0 * binfo["leaf_entries"] * aps * args.batch_cases * args.chunk
+                    tf = leaf_flops / (r["launch_ms"] * 1e-3) / 1e12
+                    peak = 78.6 if prec == "fp64" else 157.3
+                    batch[f"{eng}_{name}"]["mfma_leaf_tflops"] = round(tf, 3)
+                    batch[f"{eng}_{name}"]["mfma_peak_tflops"] = peak
+                    batch[f"{eng}_{name}"]["mfma_frac"] = round(tf / peak, 5)
+        if record:
+            # accuracy of the batched mixed panel path: sampled cases against full oracle trajectories
+            import oracle
+            r = timed_run(hinv, torch, base, bl, "fp32", True, 0, args.chunk, args.chunk, args.max_refine,
+                          args.rel_tol, True, khz, kernel_mode="panel", max_mod_rank=1)
+            Vb = r["V"]
+            errs = {}
+            for k in (0, args.batch_cases - 1):
+                st, br = bl[k][0]
+                Vo, _ = oracle.emt_run(base, args.chunk, loss_steps=[st], loss_branches=[br], solver="inv")
+                errs[k] = float(np.abs(Vb[:, k, :].cpu().numpy() - Vo).max() / np.abs(Vo).max())
+            batch["panel_mixed_err_vs_oracle"] = {"steps": args.chunk, "cases": list(errs),
+                                                  "peak_norm_max": max(errs.values())}
+            del Vb
 
     study = None
     if args.study_11456:

@@ -477,7 +477,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                     const int r = mt * 16 + Mfma16<TB>::row(lane, i), c = lane & 15;
                     if (r < nl) {
                         out[r * kPB + c] = val;
-                        X0p[(int64_t)(lo + r) * kPB + c] = val;
+                        xchg_store(&X0p[(int64_t)(lo + r) * kPB + c], val);
                     }
                 }
             }
@@ -485,19 +485,19 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         if (!team_barrier(tflags, l, T, ++epoch, P.flags, ctl)) return false;
         if (want_vm) {   // the team's largest |v| per case (vg was cleared before the barrier)
             for (int i = tid; i < T * kPB; i += kPThreads)
-                atomicMax(&vg[i & 15], (unsigned long long)__double_as_longlong(VMp[i]));
+                atomicMax(&vg[i & 15], (unsigned long long)__double_as_longlong(xchg_load(&VMp[i])));
         }
         {   // every load of the exchange is issued before the first wait
             double xl[kPXItems], cl[kPColItems];
 #pragma unroll
             for (int it = 0; it < kPXItems; ++it) {
                 const int i = tid + it * kPThreads;
-                xl[it] = i < nx * kPB ? X0p[(int64_t)xrow[i >> 4] * kPB + (i & 15)] : 0.0;
+                xl[it] = i < nx * kPB ? xchg_load(&X0p[(int64_t)xrow[i >> 4] * kPB + (i & 15)]) : 0.0;
             }
 #pragma unroll
             for (int it = 0; it < kPColItems; ++it) {
                 const int i = tid + it * kPThreads;
-                cl[it] = i < nc * kPB ? X0p[(int64_t)crow[i >> 4] * kPB + (i & 15)] : 0.0;
+                cl[it] = i < nc * kPB ? xchg_load(&X0p[(int64_t)crow[i >> 4] * kPB + (i & 15)]) : 0.0;
             }
 #pragma unroll
             for (int it = 0; it < kPXItems; ++it) {
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             if (tid < kPB) {
                 double Vm = 0.0;
                 for (int q = 0; q < kPWaves; ++q) Vm = fmax(Vm, red[(kPWaves + q) * kPB + tid]);
-                D.VM[(((int64_t)team * 2 + par) * T + l) * kPB + tid] = Vm;
+                xchg_store(&D.VM[(((int64_t)team * 2 + par) * T + l) * kPB + tid], Vm);
                 vg[tid] = 0ull;
             }
         }

@@ -306,14 +306,14 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             double val = part[r];
             for (int q = 1; q < kGemvChunks; ++q) val += part[q * NL + r];
             out[r] = val;
-            X0[lo + r] = val;
+            xchg_store(&X0[lo + r], val);
         }
         if (!team_barrier(T.sync, w, T.T, ++epoch, P.flags, ctl)) return false;
         if (want_vm) {   // the team's largest |v| (vg was cleared before the barrier)
             for (int i = tid; i < T.T; i += kTeamThreads)
-                atomicMax(vg, (unsigned long long)__double_as_longlong(T.VM[(int64_t)par * T.T + i]));
+                atomicMax(vg, (unsigned long long)__double_as_longlong(xchg_load(&T.VM[(int64_t)par * T.T + i])));
         }
-        for (int x = tid; x < nx; x += kTeamThreads) outx[x] = X0[xrow[x]];
+        for (int x = tid; x < nx; x += kTeamThreads) outx[x] = xchg_load(&X0[xrow[x]]);
         __syncthreads();
         // coupling levels bottom-up: gather s (an endpoint row's lower-level
         // corrections are applied inline, in the same order as the final
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             if (tid == 0) {
                 double V = 0.0;
                 for (int q = 0; q < kTeamWaves; ++q) V = fmax(V, red[kTeamWaves + q]);
-                T.VM[(int64_t)par * T.T + w] = V;
+                xchg_store(&T.VM[(int64_t)par * T.T + w], V);
                 *vg = 0ull;
             }
         }

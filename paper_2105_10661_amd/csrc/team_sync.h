@@ -1,10 +1,17 @@
 // Barrier among the T workgroups of one team (cooperative launches of the
-// team and panel engines), by per-workgroup epoch flags: each workgroup
-// release-stores its epoch after all its threads' global writes, one
-// wavefront polls every flag of the team with relaxed agent-scope loads and a
-// wave vote, and a single acquire fence follows; there is no read-modify-write
-// on a shared counter.  The wait is bounded: on time-out the barrier raises
-// kFlagBarrier in *errflags and returns false in every thread.
+// team and panel engines), by per-workgroup epoch flags, and the accessors of
+// the data the workgroups exchange through global memory.
+//
+// Every value that one workgroup writes for another is stored and loaded with
+// device-scope ("agent") relaxed atomics (xchg_store / xchg_load).  Those are
+// coherent at device scope without the per-XCD L2 (stores complete at the
+// device coherence point, loads are served from it), so the barrier needs no
+// L2 write-back or invalidate: each wavefront waits until its stores have
+// completed (vmcnt(0)), the workgroup synchronises, one thread stores the
+// epoch flag, one wavefront polls the team's flags (relaxed device-scope
+// loads and a wave vote), and the workgroup synchronises again before any
+// exchanged value is loaded.  The wait is bounded: on time-out the barrier
+// raises kFlagBarrier in *errflags and returns false in every thread.
 #pragma once
 #include "hinv_internal.h"
 
@@ -12,11 +19,21 @@ namespace hinv {
 
 constexpr int kTeamSpinLimit = 1 << 24;
 
+__device__ __forceinline__ void xchg_store(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xchg_load(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // flags: the team's T flags; me: this workgroup's flag; ctl: one int of LDS.
 __device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned int epoch, int* errflags, int* ctl)
 {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // gfx9 encoding of vmcnt(0): this wave's stores have completed
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(&flags[me], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(&flags[me], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x < 64) {
         int ok = 1;
         int spins = 0;
@@ -31,7 +48,6 @@ __device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (threadIdx.x == 0) {
             ctl[0] = ok;
             if (!ok) atomicOr(errflags, kFlagBarrier);
