@@ -36,6 +36,23 @@ sys.path.insert(0, ROOT)
 METRIC = "EMT network solves/s + p99 step latency, mixed vs FP64 at 1e-10 rel error"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the FP64 team kernel per 500-step launch, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0, scales from a copy of known size; profiles/k_emt_team_1432bus_hbm_counters.md).  Valid
+# only while the kernel's sources are the profiled ones.
+TEAM_TRAFFIC = {"sources": ("k_team.hip", "team_sync.h", "hinv_internal.h"), "sha256_16": "72ae137c36314e31",
+                "launch_steps": 500, "bytes": 49328640}
+
+
+def team_traffic(chunk):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TEAM_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_2105_10661_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TEAM_TRAFFIC["sha256_16"] or chunk != TEAM_TRAFFIC["launch_steps"]:
+        return None
+    return TEAM_TRAFFIC["bytes"]
+
 
 def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_refine, rel_tol, record, khz,
               kernel_mode="auto", max_mod_rank=2):
@@ -144,6 +161,9 @@ def main():
                     help="also run the serving workload (Poisson arrivals of mixed-size cases)")
     ap.add_argument("--serve-cases", type=int, default=64)
     ap.add_argument("--serve-budget-mb", type=int, default=256)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first copy a buffer of this many MiB three times (device to device): the known-size "
+                         "kernel that scales hardware byte counters")
     ap.add_argument("--study-11456", action="store_true",
                     help="also time the 11456-bus torus per storage precision and record error vs corrections")
     args = ap.parse_args()
@@ -160,6 +180,13 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     khz = hinv.wall_clock_khz(0)
     n_total = args.warmup + args.steps
     case = cases.case_c2(n_steps=n_total)
@@ -333,7 +360,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
+            "traffic": team_traffic(args.chunk) if head == "fp64" else None,
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launch_ms": round(r["launch_ms"], 4),
             "bytes_per_launch": int(launch_bytes),
         },
