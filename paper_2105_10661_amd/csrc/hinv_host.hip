@@ -1281,7 +1281,12 @@ bool build_panel_plan(emt_ctx& c, int R)
         }
     }
     int max_lw = 1;
-    for (int h = 1; h <= H; ++h) max_lw = std::max(max_lw, P.lvl_col[h] - P.lvl_col[h - 1]);
+    for (int h = 1; h <= H; ++h) {
+        max_lw = std::max(max_lw, P.lvl_col[h] - P.lvl_col[h - 1]);
+        int tiles = 0;             // 16-row tiles of the level's S^{-1} (the level solve's matrix products)
+        for (int t = P.lvl_node[h - 1]; t < P.lvl_node[h]; ++t) tiles += (P.node_m[t] + 15) / 16;
+        if (tiles > kPanelMaxLevelTiles) return false;
+    }
     // per (team, leaf): X rows = fixed rows, then the team's loss endpoints
     std::vector<std::vector<int>> X((size_t)n_teams * L);
     std::vector<std::vector<int>> lpa((size_t)n_teams * L), lpb((size_t)n_teams * L);

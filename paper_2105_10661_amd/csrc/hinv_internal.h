@@ -265,6 +265,7 @@ constexpr int kPanelMaxRank = 2;
 constexpr int kPanelMaxLeaf = 96;    // rows of a leaf
 constexpr int kPanelMaxCols = 256;   // coupling columns of the tree
 constexpr int kPanelMaxX = 128;      // X rows of a (team, leaf) pair
+constexpr int kPanelMaxLevelTiles = 24;   // 16-row tiles of S^{-1} in one level (2 per wavefront)
 struct PanelDev {
     int T, H, NL, NLp, NX, NB, NE, NI, NS, XZ, ZO, CZ, nc, sent, max_lw, n_teams, team0;
     // per leaf l

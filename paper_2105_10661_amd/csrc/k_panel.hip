@@ -32,6 +32,7 @@ constexpr int kPRowItems = (kPanelMaxLeaf * kPanelCases + kPThreads - 1) / kPThr
 constexpr int kPColItems = (kPanelMaxCols * kPanelCases + kPThreads - 1) / kPThreads;   // (column, case) items
 constexpr int kPXItems = (kPanelMaxX * kPanelCases + kPThreads - 1) / kPThreads;        // (X row, case) items
 constexpr int kPMaxFrag = 12;     // A fragments per wavefront (leaf <= 96 rows, see panel_gemm)
+constexpr int kPLevelTiles = 2;   // 16-row tiles of the level solve per wavefront
 static_assert(kPB == 16, "the panel is the N dimension of a 16x16x4 MFMA");
 static_assert(kPThreads % kPB == 0, "all items of a thread belong to one case");
 
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     const int l = blockIdx.x % T, team = D.team0 + blockIdx.x / T, tw = team * T + l;
     const int case0 = team * kPB;
     const int nvc = K - case0 < kPB ? K - case0 : kPB;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wavefront
     const int lo = D.w_lo[l], nl = D.w_nl[l], nb = D.w_nb[l], nx = D.w_nx[tw];
     const int NLp = D.NLp;
     TB* sall = (TB*)(L8 + Ly.sall);
@@ -526,36 +528,109 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 y[i] = colw[g] * val;
             }
             __syncthreads();
-            double yn[kPColItems];
+            // y = S^{-1} s on the matrix cores: every node's S^{-1} in 16-row tiles (zero beyond m)
+            // times the node's s for the 16 cases, k-steps of 4; wavefront w takes the level's
+            // tiles w and w + kPWaves (the host keeps a level at <= 2 * kPWaves tiles)
+            {
+                int tg[kPLevelTiles], tqt[kPLevelTiles];
 #pragma unroll
-            for (int it = 0; it < kPColItems; ++it) {
-                const int i = c0 * kPB + tid + it * kPThreads, g = i >> 4, c = i & 15;
-                yn[it] = 0.0;
-                if (i < c1 * kPB) {
-                    const int m = cm[g], q0 = cc0[g];
-                    const TB* Si = sall + cso[g];
-                    TA acc = 0;
-                    for (int p = 0; p < m; ++p) acc = pfma((TA)Si[p * (m + 1)], (TA)y[(q0 + p) * kPB + c], acc);
-                    yn[it] = (double)acc;
+                for (int k = 0; k < kPLevelTiles; ++k) tg[k] = -1;
+                {
+                    int tcount = 0;
+                    for (int g = c0; g < c1; g += cm[g]) {
+                        for (int qt = 0; qt * 16 < cm[g]; ++qt, ++tcount) {
+#pragma unroll
+                            for (int k = 0; k < kPLevelTiles; ++k)
+                                if (tcount == wave + k * kPWaves) { tg[k] = g; tqt[k] = qt; }
+                        }
+                    }
+                }
+                typename Mfma16<TB>::V yacc[kPLevelTiles];
+#pragma unroll
+                for (int k = 0; k < kPLevelTiles; ++k) {
+                    yacc[k] = typename Mfma16<TB>::V{0, 0, 0, 0};
+                    if (tg[k] >= 0) {
+                        const int g0 = __builtin_amdgcn_readfirstlane(tg[k]);
+                        const int m = __builtin_amdgcn_readfirstlane(cm[g0]);
+                        const TB* Si = sall + cso[g0];
+                        const int q = tqt[k] * 16 + (lane & 15), qc = q < m ? q : m - 1;
+                        // four k-steps per round: clamped loads first (zero outside the node's
+                        // m x m block), then four dependent matrix products
+                        for (int k0 = 0; k0 < m; k0 += 16) {
+                            TB a[4], bb[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int pp = k0 + u * 4 + (lane >> 4), pc = pp < m ? pp : m - 1;
+                                const TB a0 = Si[qc + pc * (m + 1)];
+                                const TB b0 = (TB)y[(g0 + pc) * kPB + (lane & 15)];
+                                a[u] = (q < m && pp < m) ? a0 : (TB)0;
+                                bb[u] = pp < m ? b0 : (TB)0;
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) yacc[k] = Mfma16<TB>::op(a[u], bb[u], yacc[k]);
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kPLevelTiles; ++k) {
+                    if (tg[k] >= 0) {
+                        const int g0 = tg[k], m = cm[g0];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int q = tqt[k] * 16 + Mfma16<TB>::row(lane, e);
+                            if (q < m) y[(g0 + q) * kPB + (lane & 15)] = (double)yacc[k][e];
+                        }
+                    }
                 }
             }
             __syncthreads();
-#pragma unroll
-            for (int it = 0; it < kPColItems; ++it) {
-                const int i = c0 * kPB + tid + it * kPThreads;
-                if (i < c1 * kPB) y[i] = yn[it];
-            }
-            __syncthreads();
         }
-        // own rows and X rows: v -= sum over levels of Z y
-        for (int i = tid; i < nl * kPB; i += kPThreads) {
-            const int r = i >> 4, c = i & 15;
-            double val = out[i];
-            for (int hh = 0; hh < Hn; ++hh) {
-                const int zo = ozo[hh];
-                if (zo >= 0) val -= (double)pdot<TA>(zown + zo + r, nl, y, opc[hh], opm[hh], c);
+        // own rows and X rows: v -= sum over levels of Z y (one dot-product order for every row, so
+        // rows shared by two workgroups stay bitwise identical)
+        if constexpr (sizeof(TB) == 8) {
+            // own rows on the matrix cores, one 16-row tile per wavefront: the FP64 16x16x4 product
+            // rounds as a chain of fused multiply-adds over k (measured bitwise on gfx950), which is
+            // the chain the X-row loop below uses for the same rows in other workgroups
+            if (wave < gm.MT) {
+                const int r0 = wave * 16, c = lane & 15;
+                double val[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = r0 + Mfma16<TB>::row(lane, e);
+                    val[e] = r < nl ? out[r * kPB + c] : 0.0;
+                }
+                const int ra_ = r0 + (lane & 15), rc = ra_ < nl ? ra_ : nl - 1;
+                for (int hh = 0; hh < Hn; ++hh) {
+                    const int zo = __builtin_amdgcn_readfirstlane(ozo[hh]);
+                    if (zo < 0) continue;
+                    const int pm = __builtin_amdgcn_readfirstlane(opm[hh]), pc = opc[hh];
+                    typename Mfma16<TB>::V acc = {0, 0, 0, 0};
+                    for (int k0 = 0; k0 < pm; k0 += 4) {
+                        const int j = k0 + (lane >> 4), jc = j < pm ? j : pm - 1;
+                        const TB a0 = zown[zo + jc * nl + rc];
+                        const TB b0 = (TB)y[(pc + jc) * kPB + c];
+                        acc = Mfma16<TB>::op((ra_ < nl && j < pm) ? a0 : (TB)0, j < pm ? b0 : (TB)0, acc);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) val[e] -= (double)acc[e];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = r0 + Mfma16<TB>::row(lane, e);
+                    if (r < nl) out[r * kPB + c] = val[e];
+                }
             }
-            out[i] = val;
+        } else {
+            for (int i = tid; i < nl * kPB; i += kPThreads) {
+                const int r = i >> 4, c = i & 15;
+                double val = out[i];
+                for (int hh = 0; hh < Hn; ++hh) {
+                    const int zo = ozo[hh];
+                    if (zo >= 0) val -= (double)pdot<TA>(zown + zo + r, nl, y, opc[hh], opm[hh], c);
+                }
+                out[i] = val;
+            }
         }
         for (int i = tid; i < nx * kPB; i += kPThreads) {
             const int x = i >> 4, c = i & 15;

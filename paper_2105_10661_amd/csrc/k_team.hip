@@ -33,7 +33,7 @@ struct TAcc<double> { using T = double; };
 
 struct TeamLayout {
     size_t blk, sall, zown, xz, uown, ux;
-    size_t b, v, t, d, part, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, colw, cinv, mdg, red, tz;
+    size_t b, v, t, d, part, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, colw, cinv, mdg, red, tz;
     size_t xrow, xzo, xpm, xpc, ozo, opm, opc, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
     size_t lpa, lpb, loa, lob, mact, lbr, lst, vg, ctl;
     size_t total;
@@ -64,7 +64,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.h0 = take(D * T.NB); L.h1 = take(D * T.NB);
     L.hC = take(D * NL); L.gC = take(D * NL);
     L.oval = take(D * T.NE); L.bg = take(D * T.NB); L.bal = take(D * T.NB);
-    L.samp = take(D * T.NS); L.sph = take(D * T.NS);
+    L.samp = take(D * T.NS); L.sph = take(D * T.NS); L.sn = take(D * T.NS);
     L.colw = take(D * nc);
     L.cinv = take(D * R * R * R); L.mdg = take(D * R);
     L.red = take(D * 2 * kTeamWaves); L.tz = take(D * 2 * R);
@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     double* bal = (double*)(L8 + Ly.bal);
     double* samp = (double*)(L8 + Ly.samp);
     double* sph = (double*)(L8 + Ly.sph);
+    double* sn = (double*)(L8 + Ly.sn);
     double* colw = (double*)(L8 + Ly.colw);
     double* cinv = (double*)(L8 + Ly.cinv);
     double* mdg = (double*)(L8 + Ly.mdg);
@@ -286,7 +287,8 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     unsigned int epoch = 0;
     bool alive = true;
     double worst = 0.0;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wavefront
 
     // one application of the stored inverse (with the active line changes):
     // out (own rows), outx (X rows) from xin (own rows)
@@ -463,6 +465,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     };
 
     int64_t applies = 0;
+    const int ns = sptr[nl];
     for (int it = 0; it < P.n_steps && alive; ++it) {
         const int64_t step = P.step0 + it;
         int ract = 0;
@@ -497,12 +500,16 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             }
             hn[q] = hv;
         }
+        if (tid >= kTeamThreads - 64) {      // source injections of step+1, by the last wavefront
+            for (int q = tid - (kTeamThreads - 64); q < ns; q += 64)
+                sn[q] = samp[q] * sin(E.omega * ((double)(step + 1) * E.dt) + sph[q]);
+        }
         __syncthreads();
         const int64_t j = step - P.step0;
         for (int r = tid; r < nl; r += kTeamThreads) {
             const double va = v[r];
             double bn = 0.0;
-            for (int q = sptr[r]; q < sptr[r + 1]; ++q) bn += samp[q] * sin(E.omega * ((double)(step + 1) * E.dt) + sph[q]);
+            for (int q = sptr[r]; q < sptr[r + 1]; ++q) bn += sn[q];
             for (int q = iptr[r]; q < iptr[r + 1]; ++q) {
                 const int lb = ibr[q];
                 const double hv = hn[lb];
