@@ -86,16 +86,19 @@ typedef struct {
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
     int32_t warm_start;    /* EMT, mixed precision: refine from the previous step's v instead of P b */
-    int32_t kernel_mode;   /* EMT engine: 0 = automatic (one case: 3 when it fits; several
-                              cases: 4 when it fits; else 2 when it fits, else 1); 1 = one launch
-                              per kernel per step (any size); 2 = one fused launch per emt_step,
-                              one workgroup per case (case vectors in LDS); 3 = one fused
+    int32_t kernel_mode;   /* EMT engine: 0 = automatic (one case: 3, else 5, when it fits;
+                              several cases: 4 when it fits; else 2 when it fits, else 1); 1 = one
+                              launch per kernel per step (any size); 2 = one fused launch per
+                              emt_step, one workgroup per case (case vectors in LDS); 3 = one fused
                               cooperative launch per emt_step, one workgroup per leaf of a single
-                              case; 4 = fused cooperative launches, cases in panels of 16 with
-                              one workgroup per leaf per panel, leaf blocks applied to a panel as
-                              one matrix-core product (max_mod_rank <= 2).  Engines 3 and 4 run
-                              exactly max_refine (+1 when warm-started) corrections per step in
-                              mixed precision */
+                              case, every coupling level in every workgroup's LDS; 4 = fused
+                              cooperative launches, cases in panels of 16 with one workgroup per
+                              leaf per panel, leaf blocks applied to a panel as one matrix-core
+                              product (max_mod_rank <= 2); 5 = one fused cooperative launch, one
+                              workgroup per leaf of a single case, coupling levels computed by the
+                              owners of their columns with a barrier per exchange (trees too large
+                              for 3).  Engines 3-5 run exactly max_refine (+1 when warm-started)
+                              corrections per step in mixed precision */
 } hinv_options;
 
 typedef struct {

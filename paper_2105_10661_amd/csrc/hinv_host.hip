@@ -480,7 +480,7 @@ hinv_status check_options(const hinv_options* o, int min_nrhs)
     if (o->max_nrhs < min_nrhs) return fail(HINV_E_INVALID, "max_nrhs %d < %d", o->max_nrhs, min_nrhs);
     if (o->prec != HINV_FP64 && (o->max_refine < 0 || o->max_refine > 64))
         return fail(HINV_E_INVALID, "max_refine %d outside 0..64", o->max_refine);
-    if (o->kernel_mode < 0 || o->kernel_mode > 4) return fail(HINV_E_INVALID, "kernel_mode %d unknown", o->kernel_mode);
+    if (o->kernel_mode < 0 || o->kernel_mode > 5) return fail(HINV_E_INVALID, "kernel_mode %d unknown", o->kernel_mode);
     if (o->prec != HINV_FP64 && !(o->rel_tol >= 0.0)) return fail(HINV_E_INVALID, "rel_tol must be >= 0");
     return HINV_OK;
 }
@@ -752,7 +752,7 @@ struct emt_ctx {
     // new-order network data kept for the team plan
     std::vector<int> inc_ptr, inc_br, src_ptr;
     std::vector<double> alpha, samp, sph, gC;
-    int engine = 1;              // 1 per-kernel, 2 one workgroup per case, 3 team, 4 panel
+    int engine = 1;              // 1 per-kernel, 2 one workgroup per case, 3 team, 4 panel, 5 level
     // team engine
     bool team_ok = false;
     int team_nx_cap = 0;
@@ -766,6 +766,11 @@ struct emt_ctx {
     int panel_nx_cap = 0, panel_xz_cap = 0;
     std::vector<int> pw_nx, pxrow, pxzo, pxpm, pxpc, pxpan, plpa, plpb, pczo, pcpm, pcpc, pcpan;
     PanelDev PD{};
+    // level engine (one case, distributed coupling levels)
+    bool level_ok = false;
+    int level_nx_cap = 0;
+    std::vector<int> lw_nx, loptr, locl, lorow, losoff, lxrow, llpa, llpb;
+    LevelDev LD{};
 };
 
 namespace {
@@ -920,6 +925,9 @@ bool build_team_plan(emt_ctx& c, int R);
 void carve_team(emt_ctx& c, Arena& A);
 bool build_panel_plan(emt_ctx& c, int R);
 void carve_panel(emt_ctx& c, Arena& A);
+bool build_level_plan(emt_ctx& c, int R);
+void carve_level(emt_ctx& c, Arena& A);
+hinv_status upload_level(emt_ctx& c, hipStream_t s);
 
 hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_options* o, const emt_cases* C,
                      emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv, size_t* bytes)
@@ -965,15 +973,23 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
         c.panel_ok = build_panel_plan(c, c.R);
         if (c.panel_ok) carve_panel(c, A);
     }
+    c.level_ok = false;
+    if (((mode == 0 && c.n_cases == 1 && !c.team_ok) || mode == 5) && fused_prec) {
+        c.level_nx_cap = 0;
+        c.level_ok = build_level_plan(c, c.R);
+        if (c.level_ok) carve_level(c, A);
+    }
     const bool fits = run_fits(c.hc.H) && fused_prec;
+    if (mode == 5 && !c.level_ok)
+        return fail(HINV_E_INVALID, "the level engine needs FP64/FP32, one case, <= 256 leaves of <= %d rows and "
+                    "tables that fit LDS", HINV_MAX_LEAF);
     if (mode == 3 && !c.team_ok)
         return fail(HINV_E_INVALID, "the team engine needs FP64/FP32, one case, <= 256 leaves and fitting LDS");
     if (mode == 4 && !c.panel_ok)
         return fail(HINV_E_INVALID, "the panel engine needs FP64/FP32, max_mod_rank <= %d, leaves of <= 96 rows, <= 256 leaves and "
                     "coupling columns, and tables that fit LDS", kPanelMaxRank);
     if (mode == 2 && !fits) return fail(HINV_E_INVALID, "the one-workgroup-per-case engine needs FP64/FP32 and a case that fits LDS");
-    c.engine = (mode == 1) ? 1 : (mode == 2) ? 2 : (mode == 3) ? 3 : (mode == 4) ? 4
-             : c.team_ok ? 3 : c.panel_ok ? 4 : fits ? 2 : 1;
+    c.engine = (mode >= 1) ? mode : c.team_ok ? 3 : c.panel_ok ? 4 : c.level_ok ? 5 : fits ? 2 : 1;
     *bytes = A.off + kAlign;
     return HINV_OK;
 }
@@ -1465,6 +1481,212 @@ hinv_status upload_panel(emt_ctx& c, hipStream_t s)
     return HINV_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Level plan (one case): per leaf its own rows, owned coupling columns per level with their
+// S^{-1} rows, own Z panels, X rows (neighbours through G, then line-loss endpoints), CSR rows,
+// branches and sources.  Per-leaf tables share the team layout's per-leaf vectors.
+bool build_level_plan(emt_ctx& c, int R)
+{
+    const Plan& P = c.hc.P;
+    const int L = (int)P.leaf_lo.size(), H = P.n_levels, NC = (int)P.col_row.size();
+    if (c.n_cases != 1 || L < 1 || L > 256 || H < 0) return false;
+    std::vector<int> lpan((size_t)L * std::max(H, 1), -1);
+    for (int l = 0; l < L; ++l) {
+        for (int k = 0; k < P.anc_stride; ++k) {
+            const int t = P.leaf_anc[(size_t)l * P.anc_stride + k];
+            if (t < 0) break;
+            const int h = P.node_level[t];
+            for (int pp = P.node_pan0[t]; pp < P.node_pan0[t] + P.node_npan[t]; ++pp)
+                if (P.pan_lo[pp] <= P.leaf_lo[l] && P.leaf_lo[l] < P.pan_lo[pp] + P.pan_n[pp]) lpan[(size_t)l * H + h - 1] = pp;
+        }
+    }
+    std::vector<int> loss_rows;
+    for (auto& x : c.losses[0]) {
+        loss_rows.push_back(c.fr_p[x.second]);
+        loss_rows.push_back(c.to_p[x.second]);
+    }
+    struct W {
+        std::vector<int> xr, ozo, opm, opc, opan, optr, ocl, orow, osoff, orp, ocol, bglob, bf, bt, bown, iptr, ibr,
+            sptr, lpa, lpb;
+        std::vector<double> oval, bg, bal, samp, sph;
+        int zo = 0, so = 0;
+    };
+    std::vector<W> ws(L);
+    int NL = 1, NX = 1, NB = 1, NE = 1, NI = 1, NS = 1, ZO = 1, NO = 1, SO = 1, PM = 1;
+    for (size_t pp = 0; pp < P.pan_m.size(); ++pp) PM = std::max(PM, P.pan_m[pp]);
+    for (int l = 0; l < L; ++l) {
+        W& w = ws[l];
+        const int lo = P.leaf_lo[l], nl = P.leaf_n[l];
+        auto own = [&](int r) { return r >= lo && r < lo + nl; };
+        for (int r = lo; r < lo + nl; ++r)
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
+                if (!own(P.ci[e])) w.xr.push_back(P.ci[e]);
+        std::sort(w.xr.begin(), w.xr.end());
+        w.xr.erase(std::unique(w.xr.begin(), w.xr.end()), w.xr.end());
+        for (int r : loss_rows)
+            if (!own(r) && std::find(w.xr.begin(), w.xr.end(), r) == w.xr.end()) w.xr.push_back(r);
+        auto comb = [&](int row) {
+            return own(row) ? row - lo : nl + (int)(std::find(w.xr.begin(), w.xr.end(), row) - w.xr.begin());
+        };
+        // owned columns, grouped by level (columns are numbered level by level)
+        w.optr.assign(H + 1, 0);
+        for (int h = 1; h <= H; ++h) {
+            for (int g = P.lvl_col[h - 1]; g < P.lvl_col[h]; ++g) {
+                if (!own(P.col_row[g])) continue;
+                w.ocl.push_back(g);
+                w.orow.push_back(P.col_row[g] - lo);
+                w.osoff.push_back(w.so);
+                w.so += P.node_m[P.col_node[g]];
+            }
+            w.optr[h] = (int)w.ocl.size();
+        }
+        w.ozo.assign(H, -1); w.opm.assign(H, 0); w.opc.assign(H, 0); w.opan.assign(H, -1);
+        for (int h = 1; h <= H; ++h) {
+            const int pp = lpan[(size_t)l * H + h - 1];
+            if (pp < 0) continue;
+            w.opan[h - 1] = pp; w.ozo[h - 1] = w.zo; w.opm[h - 1] = P.pan_m[pp]; w.opc[h - 1] = P.pan_col0[pp];
+            w.zo += P.pan_m[pp] * nl;
+        }
+        w.orp.assign(nl + 1, 0);
+        for (int r = lo; r < lo + nl; ++r) {
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
+                w.ocol.push_back(comb(P.ci[e]));
+                w.oval.push_back(P.cv[e]);
+            }
+            w.orp[r - lo + 1] = (int)w.ocol.size();
+        }
+        std::vector<int> br;
+        for (int r = lo; r < lo + nl; ++r)
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q) br.push_back(c.inc_br[q]);
+        std::sort(br.begin(), br.end());
+        br.erase(std::unique(br.begin(), br.end()), br.end());
+        for (int e : br) {
+            w.bglob.push_back(e);
+            w.bf.push_back(comb(c.fr_p[e]));
+            w.bt.push_back(comb(c.to_p[e]));
+            w.bown.push_back(own(c.fr_p[e]) ? 1 : 0);
+            w.bg.push_back(c.g[e]);
+            w.bal.push_back(c.alpha[e]);
+        }
+        w.iptr.assign(nl + 1, 0);
+        w.sptr.assign(nl + 1, 0);
+        for (int r = lo; r < lo + nl; ++r) {
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q)
+                w.ibr.push_back((int)(std::lower_bound(br.begin(), br.end(), c.inc_br[q]) - br.begin()));
+            w.iptr[r - lo + 1] = (int)w.ibr.size();
+            for (int q = c.src_ptr[r]; q < c.src_ptr[r + 1]; ++q) {
+                w.samp.push_back(c.samp[q]);
+                w.sph.push_back(c.sph[q]);
+            }
+            w.sptr[r - lo + 1] = (int)w.samp.size();
+        }
+        w.lpa.assign(R, -1);
+        w.lpb.assign(R, -1);
+        for (size_t j = 0; j < c.losses[0].size(); ++j) {
+            w.lpa[j] = comb(c.fr_p[c.losses[0][j].second]);
+            w.lpb[j] = comb(c.to_p[c.losses[0][j].second]);
+        }
+        NL = std::max(NL, nl); NX = std::max(NX, (int)w.xr.size()); NB = std::max(NB, (int)br.size());
+        NE = std::max(NE, (int)w.ocol.size()); NI = std::max(NI, (int)w.ibr.size());
+        NS = std::max(NS, (int)w.samp.size()); ZO = std::max(ZO, w.zo); NO = std::max(NO, (int)w.ocl.size());
+        SO = std::max(SO, w.so);
+    }
+    (void)NC;
+    if (c.level_nx_cap == 0) c.level_nx_cap = NX + 8;    // room for the endpoints of later line losses
+    if (NX > c.level_nx_cap) return false;
+    LevelDev& D = c.LD;
+    D.T = L; D.H = H; D.NL = NL; D.NX = c.level_nx_cap; D.NB = NB; D.NE = NE; D.NI = NI; D.NS = NS; D.ZO = ZO;
+    D.NO = NO; D.SO = SO; D.PM = PM;
+    if (level_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) return false;
+    const int Hs = std::max(H, 1);
+    auto flat = [&](std::vector<int>& dst, size_t stride, auto get) {
+        dst.assign((size_t)L * stride, 0);
+        for (int l = 0; l < L; ++l) {
+            const std::vector<int>& src = get(ws[l]);
+            std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
+        }
+    };
+    auto flatd = [&](std::vector<double>& dst, size_t stride, auto get) {
+        dst.assign((size_t)L * stride, 0.0);
+        for (int l = 0; l < L; ++l) {
+            const std::vector<double>& src = get(ws[l]);
+            std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
+        }
+    };
+    c.tw_lo = P.leaf_lo; c.tw_nl = P.leaf_n;
+    c.tw_nb.resize(L); c.lw_nx.resize(L);
+    for (int l = 0; l < L; ++l) { c.tw_nb[l] = (int)ws[l].bglob.size(); c.lw_nx[l] = (int)ws[l].xr.size(); }
+    flat(c.tozo, Hs, [](W& w) -> std::vector<int>& { return w.ozo; });
+    flat(c.topm, Hs, [](W& w) -> std::vector<int>& { return w.opm; });
+    flat(c.topc, Hs, [](W& w) -> std::vector<int>& { return w.opc; });
+    flat(c.topan, Hs, [](W& w) -> std::vector<int>& { return w.opan; });
+    flat(c.loptr, H + 1, [](W& w) -> std::vector<int>& { return w.optr; });
+    flat(c.locl, NO, [](W& w) -> std::vector<int>& { return w.ocl; });
+    flat(c.lorow, NO, [](W& w) -> std::vector<int>& { return w.orow; });
+    flat(c.losoff, NO, [](W& w) -> std::vector<int>& { return w.osoff; });
+    flat(c.lxrow, D.NX, [](W& w) -> std::vector<int>& { return w.xr; });
+    flat(c.torp, NL + 1, [](W& w) -> std::vector<int>& { return w.orp; });
+    flat(c.tocol, NE, [](W& w) -> std::vector<int>& { return w.ocol; });
+    flat(c.tbglob, NB, [](W& w) -> std::vector<int>& { return w.bglob; });
+    flat(c.tbf, NB, [](W& w) -> std::vector<int>& { return w.bf; });
+    flat(c.tbt, NB, [](W& w) -> std::vector<int>& { return w.bt; });
+    flat(c.tbown, NB, [](W& w) -> std::vector<int>& { return w.bown; });
+    flat(c.tiptr, NL + 1, [](W& w) -> std::vector<int>& { return w.iptr; });
+    flat(c.tibr, NI, [](W& w) -> std::vector<int>& { return w.ibr; });
+    flat(c.tsptr, NL + 1, [](W& w) -> std::vector<int>& { return w.sptr; });
+    flat(c.llpa, R, [](W& w) -> std::vector<int>& { return w.lpa; });
+    flat(c.llpb, R, [](W& w) -> std::vector<int>& { return w.lpb; });
+    flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
+    flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
+    flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
+    flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
+    flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
+    return true;
+}
+
+void carve_level(emt_ctx& c, Arena& A)
+{
+    LevelDev& D = c.LD;
+    const int64_t L = D.T, Hs = std::max(D.H, 1), R = c.R;
+    auto ti = [&](int64_t cnt) { return A.take<int>(cnt); };
+    auto td = [&](int64_t cnt) { return A.take<double>(cnt); };
+    D.w_lo = ti(L); D.w_nl = ti(L); D.w_nb = ti(L); D.w_nx = ti(L);
+    D.ozo = ti(L * Hs); D.opm = ti(L * Hs); D.opc = ti(L * Hs); D.opan = ti(L * Hs);
+    D.optr = ti(L * (D.H + 1)); D.ocl = ti(L * D.NO); D.orow = ti(L * D.NO); D.osoff = ti(L * D.NO);
+    D.xrow = ti(L * D.NX);
+    D.orp = ti(L * (D.NL + 1)); D.ocol = ti(L * D.NE); D.oval = td(L * D.NE);
+    D.bglob = ti(L * D.NB); D.bf = ti(L * D.NB); D.bt = ti(L * D.NB); D.bown = ti(L * D.NB);
+    D.bg = td(L * D.NB); D.bal = td(L * D.NB);
+    D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
+    D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
+    D.lpa = ti(L * R); D.lpb = ti(L * R);
+    D.sync = A.take<unsigned int>(L);
+    D.Sx = td(std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
+    D.Yx = td(std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
+    D.V1 = td(c.n);
+    D.VM = td(L);
+}
+
+hinv_status upload_level(emt_ctx& c, hipStream_t s)
+{
+    LevelDev& D = c.LD;
+    HIP_TRY(up(D.w_lo, c.tw_lo, s)); HIP_TRY(up(D.w_nl, c.tw_nl, s)); HIP_TRY(up(D.w_nb, c.tw_nb, s));
+    HIP_TRY(up(D.w_nx, c.lw_nx, s));
+    HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.opc, c.topc, s));
+    HIP_TRY(up(D.opan, c.topan, s));
+    HIP_TRY(up(D.optr, c.loptr, s)); HIP_TRY(up(D.ocl, c.locl, s)); HIP_TRY(up(D.orow, c.lorow, s));
+    HIP_TRY(up(D.osoff, c.losoff, s)); HIP_TRY(up(D.xrow, c.lxrow, s));
+    HIP_TRY(up(D.orp, c.torp, s)); HIP_TRY(up(D.ocol, c.tocol, s)); HIP_TRY(up(D.oval, c.toval, s));
+    HIP_TRY(up(D.bglob, c.tbglob, s)); HIP_TRY(up(D.bf, c.tbf, s)); HIP_TRY(up(D.bt, c.tbt, s));
+    HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
+    HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
+    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
+    HIP_TRY(up(D.lpa, c.llpa, s)); HIP_TRY(up(D.lpb, c.llpb, s));
+    HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
+    HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
+    return HINV_OK;
+}
+
 hinv_status upload_team(emt_ctx& c, hipStream_t s)
 {
     TeamDev& D = c.TD;
@@ -1596,6 +1818,7 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     carve_emt(*c, A, net->n_src);
     if (c->team_ok) carve_team(*c, A);
     if (c->panel_ok) carve_panel(*c, A);
+    if (c->level_ok) carve_level(*c, A);
     if (A.off > ws_bytes) return fail(HINV_E_NO_MEMORY, "workspace layout exceeds %zu bytes", ws_bytes);
     c->hc.M.R = c->R;
     EmtDev& E = c->E;
@@ -1614,6 +1837,10 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     }
     if (c->panel_ok) {
         st = upload_panel(*c, s);
+        if (st != HINV_OK) return st;
+    }
+    if (c->level_ok) {
+        st = upload_level(*c, s);
         if (st != HINV_OK) return st;
     }
     if (st != HINV_OK) return st;
@@ -1646,6 +1873,8 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
             HIP_TRY(launch_emt_team(c.TD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         else if (c.engine == 4)
             HIP_TRY(launch_emt_panel(c.PD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
+        else if (c.engine == 5)
+            HIP_TRY(launch_emt_level(c.LD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         else
             HIP_TRY(launch_emt_run(c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         c.step += n_steps;
@@ -1693,6 +1922,15 @@ hinv_status emt_lose_line(emt_handle h, int32_t case_idx, int32_t branch, void* 
             c.team_ok = false;
         } else {
             st = upload_team(c, s);
+            if (st != HINV_OK) return st;
+        }
+    }
+    if (c.engine == 5) {       // the new endpoints must become X rows of every workgroup
+        if (!build_level_plan(c, c.R)) {
+            c.engine = run_fits(c.hc.H) ? 2 : 1;
+            c.level_ok = false;
+        } else {
+            st = upload_level(c, s);
             if (st != HINV_OK) return st;
         }
     }

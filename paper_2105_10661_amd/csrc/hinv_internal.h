@@ -310,6 +310,52 @@ struct PanelDev {
     double* VM;          // [n_teams][2][T][kPanelCases] each workgroup's max |v| per case (same buffering)
 };
 
+// Level stepping (k_level.hip): one case, one workgroup per leaf, for trees whose coupling
+// levels do not fit every workgroup's LDS.  Every row has one owner; each coupling column is
+// owned by the workgroup that owns its endpoint row, and owns the matching row of its node's
+// S^{-1}.  Per apply: leaf product of the own rows; per level, the owners publish s, a barrier,
+// the owners publish y = S^{-1} s, a barrier, and every workgroup corrects its own rows; then
+// the own rows' values are published and a last barrier lets every workgroup read its X rows
+// (neighbours through G, line-loss endpoints).  Per-leaf tables use fixed strides; combined
+// index: own row r -> r, X row x -> nl + x.
+struct LevelDev {
+    int T, H, NL, NX, NB, NE, NI, NS, ZO, NO, SO, PM;
+    const int* w_lo;
+    const int* w_nl;
+    const int* w_nb;
+    const int* w_nx;
+    const int* ozo;      // [T*H] offset of the own rows' Z values at level h in the zown region, -1: none
+    const int* opm;
+    const int* opc;
+    const int* opan;
+    const int* optr;     // [T*(H+1)] owned columns of level h: entries optr[h-1] .. optr[h]
+    const int* ocl;      // [T*NO] owned column (global index)
+    const int* orow;     // [T*NO] own row of the column's endpoint
+    const int* osoff;    // [T*NO] LDS offset of the column's S^{-1} row
+    const int* xrow;     // [T*NX] new-order row of each X row
+    const int* orp;      // [T*(NL+1)] own CSR rows of G, combined column indices
+    const int* ocol;     // [T*NE]
+    const double* oval;
+    const int* bglob;    // [T*NB] incident branches: global id, endpoints (combined), owner flag
+    const int* bf;
+    const int* bt;
+    const int* bown;
+    const double* bg;
+    const double* bal;
+    const int* iptr;     // [T*(NL+1)] incident local branches of each own row
+    const int* ibr;      // [T*NI]
+    const int* sptr;     // [T*(NL+1)] sources of each own row
+    const double* samp;  // [T*NS]
+    const double* sph;
+    const int* lpa;      // [T*R] combined index of each change's endpoints (-1: ground / unused)
+    const int* lpb;
+    unsigned int* sync;  // [T] barrier epoch flags
+    double* Sx;          // [n_cols] exchange of s
+    double* Yx;          // [n_cols] exchange of y
+    double* V1;          // [n] exchange of the own rows' values at the end of an apply
+    double* VM;          // [T] max |v| of each workgroup (convergence norm)
+};
+
 // Host-side per-level launch sizes (level l = 1..n_levels at index l-1).
 struct LevelHost {
     int nnodes, npan, ncols, max_m, max_pan_rows;
@@ -362,6 +408,10 @@ hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, 
 // teams, in as many consecutive cooperative launches as residency requires).
 size_t panel_lds_bytes(const PanelDev& D, int R, int prec);
 hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
+                            int prec, hipStream_t s);
+// Level stepping (k_level.hip): LDS bytes of the layout, and the launch.
+size_t level_lds_bytes(const LevelDev& D, int R, int prec);
+hipError_t launch_emt_level(const LevelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
 // Fused stepping (k_run.hip): one workgroup per case, all steps in one launch.
 bool run_fits(const HierDev& H);

@@ -137,7 +137,7 @@ def _stream(torch_stream=None) -> int:
     return s.cuda_stream
 
 
-KERNEL_MODES = {"auto": 0, "per_kernel": 1, "fused": 2, "team": 3, "panel": 4}
+KERNEL_MODES = {"auto": 0, "per_kernel": 1, "fused": 2, "team": 3, "panel": 4, "level": 5}
 
 
 def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs, warm_start=False, kernel_mode="auto") -> _Options:

@@ -1,8 +1,8 @@
 """GPU parity at the benchmark configurations' full sizes.
 
-The 11456-bus (8x8 torus) and 5728-bus (8x4 torus) networks run on the
-per-kernel engine (their root capacitance matrices do not fit a workgroup's
-LDS); the oracle there is the library sparse LU of G (SuperLU), pinned
+The 11456-bus (8x8 torus) network runs on the level engine (its coupling
+levels do not fit every workgroup's LDS, so they are computed by the owners
+of their columns) and on the per-kernel engine; the oracle there is the library sparse LU of G (SuperLU), pinned
 against the dense LU on the 179-bus network.  The 256-case contingency batch
 runs on the one-workgroup-per-case engine and on the panel engine; sampled
 cases are checked against full oracle trajectories and against the same case
@@ -46,14 +46,14 @@ def test_torus_per_solve_random(hv, shape, prec):
     H.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_torus_11456_trajectory_with_loss(hv, prec):
+@pytest.mark.parametrize("prec,mode", [("fp64", "auto"), ("fp32", "auto"), ("fp64", "per_kernel")])
+def test_torus_11456_trajectory_with_loss(hv, prec, mode):
     net = cases.net_torus(8, 8, seed=3)
     steps = 300
     loss = (120, 4321)
-    print(f"[gpu] 11456 trajectory {prec}", flush=True)
+    print(f"[gpu] 11456 trajectory {prec} {mode}", flush=True)
     Vref, _ = oracle.emt_run(net, steps, loss_steps=[loss[0]], loss_branches=[loss[1]], solver="sparse")
-    emt = hv.EMT(net, 1, losses=[[loss]], prec=prec, max_refine=2, rel_tol=1e-9)
+    emt = hv.EMT(net, 1, losses=[[loss]], prec=prec, max_refine=2, rel_tol=1e-9, kernel_mode=mode)
     V, _ = emt.step(steps)
     Vg = V[:, 0, :].cpu().numpy()
     assert np.abs(Vg - Vref).max() / np.abs(Vref).max() <= 1e-10

@@ -149,7 +149,9 @@ def c1_ref():
 @pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp32", "fused", False),
                                             ("fp32", "fused", True), ("fp64", "per_kernel", False),
                                             ("fp32", "per_kernel", False), ("fp64", "team", False),
-                                            ("fp32", "team", False), ("fp32", "team", True)])
+                                            ("fp32", "team", False), ("fp32", "team", True),
+                                            ("fp64", "level", False), ("fp32", "level", False),
+                                            ("fp32", "level", True)])
 def test_emt_179_trajectory(hv, c1_ref, prec, mode, warm):
     case, Vref, _ = c1_ref
     print(f"[gpu] emt 179 {prec} {mode} warm={warm}", flush=True)
@@ -194,7 +196,8 @@ def c2_ref():
 @pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp32", "fused", False),
                                             ("fp32", "fused", True), ("fp64", "per_kernel", False),
                                             ("fp64", "team", False), ("fp32", "team", False),
-                                            ("fp32", "team", True)])
+                                            ("fp32", "team", True), ("fp64", "level", False),
+                                            ("fp32", "level", True)])
 def test_emt_1432_with_line_loss(hv, c2_ref, prec, mode, warm):
     case, Vref = c2_ref
     print(f"[gpu] emt 1432 {prec} {mode} warm={warm}", flush=True)
@@ -240,11 +243,12 @@ def test_batched_cases_equal_alone_and_dynamic_loss(hv, mode):
     dyn.close()
 
 
-def test_team_engine_dynamic_loss_equals_scheduled(hv):
+@pytest.mark.parametrize("mode", ["team", "level"])
+def test_team_engine_dynamic_loss_equals_scheduled(hv, mode):
     """One workgroup per leaf: a loss requested between launches equals the same loss scheduled."""
     import torch
     net = cases.net_ring(4, 7)
-    kw = dict(prec="fp32", max_refine=1, warm_start=True, rel_tol=1e-6, max_mod_rank=2, kernel_mode="team")
+    kw = dict(prec="fp32", max_refine=1, warm_start=True, rel_tol=1e-6, max_mod_rank=2, kernel_mode=mode)
     ref = hv.EMT(net, 1, losses=[[(70, 11), (130, 900)]], **kw)
     Vr, _ = ref.step(200)
     dyn = hv.EMT(net, 1, losses=[[(70, 11)]], **kw)
@@ -257,3 +261,25 @@ def test_team_engine_dynamic_loss_equals_scheduled(hv):
     assert np.abs(Vr[:, 0, :].cpu().numpy() - Vo).max() / np.abs(Vo).max() <= 1e-10
     ref.close()
     dyn.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_level_engine_chunks_and_single_leaf(hv, prec):
+    """Distributed coupling levels: launches of 40 + 40 + 40 steps equal one launch of 120; a
+    single-leaf tree (no coupling level) against the oracle."""
+    net = cases.net_ring(8, 2)
+    kw = dict(prec=prec, max_refine=2, max_mod_rank=1, kernel_mode="level")
+    one = hv.EMT(net, 1, losses=[[(50, 77)]], **kw)
+    V1, _ = one.step(120)
+    ch = hv.EMT(net, 1, losses=[[(50, 77)]], **kw)
+    parts = [ch.step(40)[0].cpu().numpy() for _ in range(3)]
+    assert np.array_equal(np.concatenate(parts), V1.cpu().numpy())
+    one.sync_status()
+    one.close()
+    ch.close()
+    small = cases.small_network(40, 60, seed=9, d_th=40)
+    emt = hv.EMT(small, 1, losses=[[(12, 3)]], **kw)
+    V, _ = emt.step(60)
+    Vo, _ = oracle.emt_run(small, 60, loss_steps=[12], loss_branches=[3], solver="lu")
+    assert np.abs(V[:, 0, :].cpu().numpy() - Vo).max() / np.abs(Vo).max() <= 1e-10
+    emt.close()
