@@ -2018,21 +2018,69 @@ hinv_status emt_destroy(emt_handle h)
 }  // extern "C"
 
 // =============================== serving ====================================
+// Attached cases: those that fit one workgroup's LDS are slots of the one-workgroup-per-case
+// serve launch; larger ones with a level plan are teams of one level launch; the rest run in
+// the serve launch with their vectors in global memory.
 struct serve_ctx {
     hinv_options opt{};
     int max_slots = 0;
     ServeSlot* d_slots = nullptr;
-    std::vector<ServeSlot> table;      // dense, in launch order
-    std::vector<emt_ctx*> owner;       // handle of each dense entry
-    std::vector<int> ids;              // stable id of each dense entry
+    LevelCase* d_lcases = nullptr;
+    std::vector<ServeSlot> slot;       // per attached case (in attach order)
+    std::vector<int> level;            // 1: stepped by the level launch
+    std::vector<emt_ctx*> owner;       // handle of each attached case
+    std::vector<int> ids;              // stable id of each attached case
     int next_id = 0;
+    // dense launch tables (rebuilt on attach / detach)
+    std::vector<ServeSlot> table;
+    std::vector<LevelCase> ltable;
+    std::vector<int> lwg;
+    std::vector<unsigned int*> lsync;
+    LevelDev Ld{};
+    int lR = 1;
 };
 
 namespace {
 hinv_status serve_upload(serve_ctx& S, hipStream_t s)
 {
+    S.table.clear();
+    S.ltable.clear();
+    S.lwg.clear();
+    S.lsync.clear();
+    S.Ld = LevelDev{};
+    S.lR = 1;
+    int wg0 = 0;
+    for (size_t i = 0; i < S.slot.size(); ++i) {
+        if (!S.level[i]) {
+            S.table.push_back(S.slot[i]);
+            continue;
+        }
+        const emt_ctx& c = *S.owner[i];
+        const ServeSlot& sl = S.slot[i];
+        LevelCase lc{};
+        lc.D = c.LD;
+        lc.E = c.E;
+        lc.H = c.hc.H;
+        lc.M = c.hc.M;
+        lc.P = RunParams{0, 0, sl.max_refine, sl.rel_tol, S.opt.warm_start ? 1 : 0, sl.v_rec, nullptr, sl.flags,
+                         sl.stats, sl.applies, nullptr, 0, sl.rec_step0, sl.rec_cap};
+        lc.wg0 = wg0;
+        wg0 += c.LD.T;
+        S.ltable.push_back(lc);
+        S.lwg.push_back(c.LD.T);
+        S.lsync.push_back(c.LD.sync);
+        LevelDev& L = S.Ld;
+        L.NL = std::max(L.NL, c.LD.NL); L.NX = std::max(L.NX, c.LD.NX); L.NB = std::max(L.NB, c.LD.NB);
+        L.NE = std::max(L.NE, c.LD.NE); L.NI = std::max(L.NI, c.LD.NI); L.NS = std::max(L.NS, c.LD.NS);
+        L.ZO = std::max(L.ZO, c.LD.ZO); L.NO = std::max(L.NO, c.LD.NO); L.SO = std::max(L.SO, c.LD.SO);
+        L.PM = std::max(L.PM, c.LD.PM); L.H = std::max(L.H, c.LD.H);
+        S.lR = std::max(S.lR, c.hc.M.R);
+    }
     if (!S.table.empty())
         HIP_TRY(hipMemcpyAsync(S.d_slots, S.table.data(), sizeof(ServeSlot) * S.table.size(), hipMemcpyHostToDevice, s));
+    if (!S.ltable.empty())
+        HIP_TRY(hipMemcpyAsync(S.d_lcases, S.ltable.data(), sizeof(LevelCase) * S.ltable.size(), hipMemcpyHostToDevice,
+                               s));
     HIP_TRY(hipStreamSynchronize(s));
     return HINV_OK;
 }
@@ -2043,7 +2091,7 @@ extern "C" {
 hinv_status serve_workspace_size(int32_t max_slots, size_t* bytes)
 {
     if (!bytes || max_slots < 1) return fail(HINV_E_INVALID, "max_slots must be >= 1");
-    *bytes = sizeof(ServeSlot) * (size_t)max_slots + kAlign;
+    *bytes = (sizeof(ServeSlot) + sizeof(LevelCase)) * (size_t)max_slots + 2 * kAlign;
     return HINV_OK;
 }
 
@@ -2064,6 +2112,7 @@ hinv_status serve_create(const hinv_options* opt, int32_t max_slots, void* d_ws,
     Arena A;
     A.base = (char*)d_ws;
     c->d_slots = A.take<ServeSlot>(max_slots);
+    c->d_lcases = A.take<LevelCase>(max_slots);
     *out = c.release();
     return HINV_OK;
 }
@@ -2074,7 +2123,7 @@ hinv_status serve_attach(serve_handle h, emt_handle e, double* d_v_record, int64
     if (!h || !e || !slot_id) return fail(HINV_E_INVALID, "NULL argument");
     serve_ctx& S = *h;
     emt_ctx& c = *e;
-    if ((int)S.table.size() >= S.max_slots) return fail(HINV_E_NO_MEMORY, "all %d slots are in use", S.max_slots);
+    if ((int)S.slot.size() >= S.max_slots) return fail(HINV_E_NO_MEMORY, "all %d slots are in use", S.max_slots);
     if (c.n_cases != 1) return fail(HINV_E_INVALID, "a served handle holds exactly one case");
     if (c.hc.opt.prec != S.opt.prec || (c.hc.opt.prec != HINV_FP64 && (c.hc.opt.warm_start != 0) != (S.opt.warm_start != 0)))
         return fail(HINV_E_INVALID, "the case's precision / warm start differ from the pool's");
@@ -2096,7 +2145,8 @@ hinv_status serve_attach(serve_handle h, emt_handle e, double* d_v_record, int64
     sl.flags = c.hc.d_flags;
     sl.stats = c.hc.stats;
     sl.applies = c.d_applies;
-    S.table.push_back(sl);
+    S.slot.push_back(sl);
+    S.level.push_back(sl.gvec && c.level_ok ? 1 : 0);
     S.owner.push_back(e);
     S.ids.push_back(S.next_id);
     *slot_id = S.next_id++;
@@ -2110,7 +2160,8 @@ hinv_status serve_detach(serve_handle h, int32_t slot_id, void* stream)
     for (size_t i = 0; i < S.ids.size(); ++i) {
         if (S.ids[i] != slot_id) continue;
         HIP_TRY(hipStreamSynchronize((hipStream_t)stream));     // no launch may still read the table
-        S.table.erase(S.table.begin() + i);
+        S.slot.erase(S.slot.begin() + i);
+        S.level.erase(S.level.begin() + i);
         S.owner.erase(S.owner.begin() + i);
         S.ids.erase(S.ids.begin() + i);
         return serve_upload(S, (hipStream_t)stream);
@@ -2123,12 +2174,20 @@ hinv_status serve_step(serve_handle h, int32_t n_steps, void* stream)
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
     serve_ctx& S = *h;
     if (n_steps < 0) return fail(HINV_E_INVALID, "n_steps < 0");
-    if (n_steps == 0 || S.table.empty()) return HINV_OK;
-    size_t lds = 0;
-    for (const ServeSlot& sl : S.table) lds = std::max(lds, serve_lds_bytes(sl.H, sl.gvec != 0));
-    if (lds > 160 * 1024) return fail(HINV_E_INVALID, "a served case's coupling levels exceed LDS");
-    HIP_TRY(launch_emt_serve(S.d_slots, (int)S.table.size(), n_steps, lds, S.opt.prec, S.opt.warm_start,
-                             (hipStream_t)stream));
+    if (n_steps == 0 || S.slot.empty()) return HINV_OK;
+    if (!S.table.empty()) {
+        size_t lds = 0;
+        for (const ServeSlot& sl : S.table) lds = std::max(lds, serve_lds_bytes(sl.H, sl.gvec != 0));
+        if (lds > 160 * 1024) return fail(HINV_E_INVALID, "a served case's coupling levels exceed LDS");
+        HIP_TRY(launch_emt_serve(S.d_slots, (int)S.table.size(), n_steps, lds, S.opt.prec, S.opt.warm_start,
+                                 (hipStream_t)stream));
+    }
+    if (!S.ltable.empty()) {
+        if (level_lds_bytes(S.Ld, S.lR, S.opt.prec) > 160 * 1024)
+            return fail(HINV_E_INVALID, "the served cases' level tables exceed LDS together");
+        HIP_TRY(launch_emt_level_multi(S.Ld, S.lR, S.d_lcases, S.lwg.data(), S.lsync.data(), (int)S.ltable.size(),
+                                       n_steps, S.opt.prec, S.opt.warm_start, (hipStream_t)stream));
+    }
     for (emt_ctx* o : S.owner) o->step += n_steps;
     return HINV_OK;
 }
@@ -2136,7 +2195,7 @@ hinv_status serve_step(serve_handle h, int32_t n_steps, void* stream)
 hinv_status serve_active(serve_handle h, int32_t* n_active)
 {
     if (!h || !n_active) return fail(HINV_E_INVALID, "NULL argument");
-    *n_active = (int32_t)h->table.size();
+    *n_active = (int32_t)h->slot.size();
     return HINV_OK;
 }
 

@@ -356,6 +356,17 @@ struct LevelDev {
     double* VM;          // [T] max |v| of each workgroup (convergence norm)
 };
 
+// One case of a launch of several level-stepped cases (serving).
+struct LevelCase {
+    LevelDev D;
+    EmtDev E;
+    HierDev H;
+    ModDev M;
+    RunParams P;
+    int wg0;             // first workgroup of the case within its launch
+    int pad;
+};
+
 // Host-side per-level launch sizes (level l = 1..n_levels at index l-1).
 struct LevelHost {
     int nnodes, npan, ncols, max_m, max_pan_rows;
@@ -413,6 +424,12 @@ hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H
 size_t level_lds_bytes(const LevelDev& D, int R, int prec);
 hipError_t launch_emt_level(const LevelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
+// Several cases, each a team of its T workgroups, in as few cooperative launches as residency
+// allows (d_cases: device table with wg0 the running sum of T; n_wg, sync: host arrays of each
+// case's T and barrier flags; Ld: maxima of the LDS dimensions over the cases, R the largest rank).
+hipError_t launch_emt_level_multi(const LevelDev& Ld, int R, const LevelCase* d_cases, const int* n_wg,
+                                  unsigned int* const* sync, int n_cases, int n_steps, int prec, int warm,
+                                  hipStream_t s);
 // Fused stepping (k_run.hip): one workgroup per case, all steps in one launch.
 bool run_fits(const HierDev& H);
 size_t serve_lds_bytes(const HierDev& H, bool gvec);

@@ -109,16 +109,19 @@ size_t level_lds_bytes(const LevelDev& D, int R, int prec)
     return prec == HINV_FP64 ? level_layout<double, false>(D, R).total : level_layout<float, true>(D, R).total;
 }
 
+// The stepping of one case by its T workgroups (w = this workgroup's leaf).  Ld gives the LDS
+// layout (the case's own dimensions, or the maxima over the cases of one launch); D the case's
+// tables; step0 the first step of the launch.
 template <typename TB, bool MIXED, bool WARM>
-__global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, HierDev H, ModDev M, RunParams P)
+__device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M,
+                           const RunParams& P, int64_t step0, int w, unsigned char* L8)
 {
     using TA = typename LAcc<TB>::T;
-    extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
     const int R = M.R;
-    const LevelLayout Ly = level_layout<TB, MIXED>(D, R);
-    const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const LevelLayout Ly = level_layout<TB, MIXED>(Ld, R);
+    const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wavefront
-    const int n = H.n, NL = D.NL, NX = D.NX, Hn = D.H, T = D.T;
+    const int n = H.n, NL = Ld.NL, NX = Ld.NX, Hn = D.H, T = D.T;
     const int lo = D.w_lo[w], nl = D.w_nl[w], nx = D.w_nx[w], nb = D.w_nb[w];
     TB* blk = (TB*)(L8 + Ly.blk);
     TB* zown = (TB*)(L8 + Ly.zown);
@@ -216,9 +219,9 @@ __global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, H
                 }
             }
         }
-        const int* wx = D.xrow + (int64_t)w * NX;
+        const int* wx = D.xrow + (int64_t)w * D.NX;
         for (int x = tid; x < nx; x += kLThreads) xrow[x] = wx[x];
-        const int64_t rb = (int64_t)w * (NL + 1);
+        const int64_t rb = (int64_t)w * (D.NL + 1);
         for (int r = tid; r <= nl; r += kLThreads) {
             orp[r] = D.orp[rb + r];
             iptr[r] = D.iptr[rb + r];
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, H
             bt[q] = D.bt[gq];
             bg[q] = D.bg[gq];
             bal[q] = D.bal[gq];
-            hc[q] = E.h[(int64_t)(P.step0 & 1) * E.n_cases * E.nbr + D.bglob[gq]];
+            hc[q] = E.h[(int64_t)(step0 & 1) * E.n_cases * E.nbr + D.bglob[gq]];
         }
         for (int r = tid; r < nl; r += kLThreads) {
             b[r] = E.b[lo + r];
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, H
     int64_t applies = 0;
     const int ns = sptr[nl];
     for (int it = 0; it < P.n_steps && alive; ++it) {
-        const int64_t step = P.step0 + it;
+        const int64_t step = step0 + it;
         int ract = 0;
         while (ract < cnt && (int64_t)mact[ract] <= step) ++ract;
         if constexpr (!MIXED) {
@@ -485,11 +488,11 @@ __global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, H
         hc = hn;
         hn = tmp;
         __syncthreads();
-        if (P.clk && w == 0 && tid == 0 && step - P.step0 < P.clk_cap)
-            P.clk[step - P.step0] = (int64_t)wall_clock64();
+        if (P.clk && w == 0 && tid == 0 && step - step0 < P.clk_cap)
+            P.clk[step - step0] = (int64_t)wall_clock64();
     }
     if (!alive) return;
-    const int64_t nstep = P.step0 + P.n_steps;
+    const int64_t nstep = step0 + P.n_steps;
     for (int r = tid; r < nl; r += kLThreads) {
         E.b[lo + r] = b[r];
         E.v[lo + r] = v[r];
@@ -504,6 +507,42 @@ __global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, H
             *E.step = nstep;
         }
     }
+}
+
+template <typename TB, bool MIXED, bool WARM>
+__global__ __launch_bounds__(kLThreads) void k_emt_level(LevelDev D, EmtDev E, HierDev H, ModDev M, RunParams P)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
+    level_body<TB, MIXED, WARM>(D, D, E, H, M, P, P.step0, blockIdx.x, L8);
+}
+
+// Several cases in one launch (serving): case k owns workgroups cases[k].wg0 .. + its T; the
+// first step of each case comes from its device step counter.
+// Several cases in one launch (serving): case k owns workgroups cases[k].wg0 .. + its T, counted
+// from cases[0].wg0; the first step of each case comes from its device step counter.
+template <typename TB, bool MIXED, bool WARM>
+__global__ __launch_bounds__(kLThreads) void k_emt_level_multi(LevelDev Ld, const LevelCase* cases, int n_cases,
+                                                              int n_steps)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
+    __shared__ LevelCase cs;
+    __shared__ int64_t s0;
+    const int gb = (int)blockIdx.x + cases[0].wg0;
+    int k = 0;
+    for (int q = 1; q < n_cases; ++q)
+        if (gb >= cases[q].wg0) k = q;
+    {
+        const int* src = (const int*)&cases[k];
+        int* dst = (int*)&cs;
+        for (int i = threadIdx.x; i < (int)(sizeof(LevelCase) / sizeof(int)); i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s0 = *cs.E.step;
+        cs.P.n_steps = n_steps;
+    }
+    __syncthreads();
+    level_body<TB, MIXED, WARM>(Ld, cs.D, cs.E, cs.H, cs.M, cs.P, s0, gb - cs.wg0, L8);
 }
 
 template <typename TB, bool MIXED, bool WARM>
@@ -541,6 +580,52 @@ hipError_t launch_emt_level(const LevelDev& D, const EmtDev& E, const HierDev& H
     if (prec == HINV_FP64) return launch_level_t<double, false, false>(D, E, H, M, P, s);
     if (P.warm) return launch_level_t<float, true, true>(D, E, H, M, P, s);
     return launch_level_t<float, true, false>(D, E, H, M, P, s);
+}
+
+template <typename TB, bool MIXED, bool WARM>
+static hipError_t launch_level_multi_t(const LevelDev& Ld, int R, const LevelCase* d_cases, const int* n_wg,
+                                       unsigned int* const* sync, int n_cases, int n_steps, hipStream_t s)
+{
+    const size_t lds = level_layout<TB, MIXED>(Ld, R).total;
+    const void* fn = (const void*)k_emt_level_multi<TB, MIXED, WARM>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kLThreads, lds);
+    if (e != hipSuccess) return e;
+    const int cap = per * cus;
+    // consecutive launches over runs of cases whose workgroups fit the GPU at once
+    for (int k = 0; k < n_cases; ++k) {
+        if (n_wg[k] > cap) return hipErrorCooperativeLaunchTooLarge;
+        e = hipMemsetAsync(sync[k], 0, (size_t)n_wg[k] * sizeof(unsigned int), s);
+        if (e != hipSuccess) return e;
+    }
+    int k = 0;
+    while (k < n_cases) {
+        int k1 = k, wgs = 0;
+        while (k1 < n_cases && wgs + n_wg[k1] <= cap) wgs += n_wg[k1++];
+        LevelDev Lc = Ld;
+        const LevelCase* dc = d_cases + k;
+        int nc = k1 - k, ns = n_steps;
+        void* args[] = {&Lc, &dc, &nc, &ns};
+        e = hipLaunchCooperativeKernel(fn, dim3(wgs), dim3(kLThreads), args, (unsigned int)lds, s);
+        if (e != hipSuccess) return e;
+        k = k1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_emt_level_multi(const LevelDev& Ld, int R, const LevelCase* d_cases, const int* n_wg,
+                                  unsigned int* const* sync, int n_cases, int n_steps, int prec, int warm, hipStream_t s)
+{
+    if (prec == HINV_FP64)
+        return launch_level_multi_t<double, false, false>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
+    if (warm) return launch_level_multi_t<float, true, true>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
+    return launch_level_multi_t<float, true, false>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
 }
 
 }  // namespace hinv
