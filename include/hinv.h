@@ -135,6 +135,35 @@ hinv_status hinv_build(const hinv_csr* G, const hinv_tree* tree, const hinv_opti
  * (the change makes G indefinite).  Synchronises the stream. */
 hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream);
 
+/* What hinv_update_line rebuilt. */
+typedef struct {
+    int32_t lca_level;   /* tree level of the ends' lowest common ancestor (0: both ends in one leaf) */
+    int32_t leaves;      /* leaf-block inverses recomputed (1 or 2) */
+    int32_t columns;     /* coupling columns Z recomputed */
+    int32_t nodes;       /* capacitance inverses S^{-1} recomputed */
+} hinv_update_info;
+
+/* Change the base matrix itself by the same line change, G <- G + delta_g
+ * (e_a - e_b)(e_a - e_b)^T, and rebuild in FP64 only the part of the stored
+ * inverse that the change reaches (Section IV, Algorithm 2: the leaf blocks of
+ * a and b are re-inverted and the coupling data along their paths to the tree
+ * root is recomputed; the column pair of a line between two leaves gets its new
+ * weight at their lowest common ancestor).  Nodes above that ancestor are
+ * recomputed too, so the result is the exact inverse of the new G: for a change
+ * that leaves G's nonzero pattern intact it equals a fresh hinv_build of the
+ * new G bit for bit.  Changes stored by hinv_modify_line stay in force on top
+ * of the new base (their vectors are recomputed).  b = -1: between a and ground.
+ * The entry (a, b) must exist in G, and a line between two leaves must be one
+ * of the tree's coupling lines (nonzero in the built G; once set to zero by an
+ * update it keeps its column with weight 0), else HINV_E_NO_SUCH_LINE.  The new
+ * off-diagonal G[a][b] - delta_g must stay <= 0 (HINV_E_NO_SUCH_LINE).
+ * HINV_E_NOT_SPD / HINV_E_SINGULAR: the new G is not positive definite, or the
+ * stored changes become singular on it; the previous inverse is restored
+ * exactly.  out (host, may be NULL) receives what was rebuilt.  Synchronises
+ * the stream. */
+hinv_status hinv_update_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream,
+                             hinv_update_info* out);
+
 /* v = G^{-1} i for nrhs right-hand sides (Eq. (2)).  d_i, d_v: device FP64,
  * column k at offset k*ld, rows in the caller's bus order; d_i and d_v may
  * not overlap.  nrhs <= opt.max_nrhs, ld >= n.  Asynchronous on the stream;

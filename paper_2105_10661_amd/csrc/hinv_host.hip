@@ -390,6 +390,7 @@ struct hinv_ctx {
     std::vector<int> mod_a, mod_b, mod_act;
     std::vector<double> mod_dg;
     int* m_count = nullptr; int* m_a = nullptr; int* m_b = nullptr; int* m_act = nullptr; double* m_dg = nullptr;
+    int* upd_list = nullptr;   // leaves / columns / nodes a local rebuild launches over
     int64_t applies = 0;
 };
 
@@ -445,6 +446,7 @@ void carve_hier(hinv_ctx& c, Arena& A, int n_sets, int R, int max_nrhs)
     }
     c.colbuf = A.take<double>(NC);
     c.ipiv = A.take<int>(NC);
+    c.upd_list = A.take<int>((int64_t)L + NC + NI);
     c.d_flags = A.take<int>(4);
     c.X = A.take<double>((int64_t)P.n * max_nrhs);
     c.Xo = A.take<double>((int64_t)P.n * max_nrhs);
@@ -485,6 +487,26 @@ hinv_status check_options(const hinv_options* o, int min_nrhs)
     return HINV_OK;
 }
 
+// Low-precision copies of the FP64 blocks, panels and capacitance inverses.
+void convert_low(hinv_ctx& c, hipStream_t s)
+{
+    const Plan& P = c.P;
+    HierDev& H = c.H;
+    if (c.opt.prec == HINV_FP32) {
+        launch_to_f32(H.blk, H.blk32, P.leaf_entries, s);
+        launch_to_f32(H.Z, H.Z32, P.z_entries, s);
+        launch_to_f32(H.Sinv, H.Sinv32, P.s_entries, s);
+    } else if (c.opt.prec == HINV_BF16) {
+        launch_to_bf16(H.blk, H.blk16, P.leaf_entries, s);
+        launch_to_bf16(H.Z, H.Z16, P.z_entries, s);
+        launch_to_bf16(H.Sinv, H.Sinv16, P.s_entries, s);
+    } else if (c.opt.prec == HINV_FP8) {
+        launch_to_fp8(H.blk, H.blk8, H.blk8s, P.leaf_entries, s);
+        launch_to_fp8(H.Z, H.Z8, H.Z8s, P.z_entries, s);
+        launch_to_fp8(H.Sinv, H.Sinv8, H.Sinv8s, P.s_entries, s);
+    }
+}
+
 // Upload the plan and run the FP64 build (leaf inverses, then per level Z and S^{-1}).
 hinv_status build_device(hinv_ctx& c, hipStream_t s)
 {
@@ -520,19 +542,7 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
         launch_fill_s(H, l, L.nnodes, s);
         launch_gj_level(H, l, L.nnodes, L.max_m, c.colbuf, c.ipiv, c.d_flags, s);
     }
-    if (c.opt.prec == HINV_FP32) {
-        launch_to_f32(H.blk, H.blk32, P.leaf_entries, s);
-        launch_to_f32(H.Z, H.Z32, P.z_entries, s);
-        launch_to_f32(H.Sinv, H.Sinv32, P.s_entries, s);
-    } else if (c.opt.prec == HINV_BF16) {
-        launch_to_bf16(H.blk, H.blk16, P.leaf_entries, s);
-        launch_to_bf16(H.Z, H.Z16, P.z_entries, s);
-        launch_to_bf16(H.Sinv, H.Sinv16, P.s_entries, s);
-    } else if (c.opt.prec == HINV_FP8) {
-        launch_to_fp8(H.blk, H.blk8, H.blk8s, P.leaf_entries, s);
-        launch_to_fp8(H.Z, H.Z8, H.Z8s, P.z_entries, s);
-        launch_to_fp8(H.Sinv, H.Sinv8, H.Sinv8s, P.s_entries, s);
-    }
+    convert_low(c, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     int flags = 0;
@@ -569,6 +579,104 @@ void solve_new_order(hinv_ctx& c, const double* B, double* V, int nrhs, int set_
                           c.d_flags, s);
     }
     c.applies += (int64_t)nrhs * (1 + c.opt.max_refine);
+}
+
+// Stored change j of set 0: u_j = G0^{-1} (e_a - e_b) by one FP64 apply of the current hierarchy.
+hinv_status store_mod_u(hinv_ctx& c, int j, hipStream_t s)
+{
+    const int n = c.P.n;
+    std::vector<double> w(n, 0.0);
+    w[c.mod_a[j]] = 1.0;
+    if (c.mod_b[j] >= 0) w[c.mod_b[j]] = -1.0;
+    HIP_TRY(hipMemcpyAsync(c.X, w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    launch_apply(c.H, c.P.lv.data(), HINV_FP64, c.X, c.Xo, c.Y, 1, s);
+    HIP_TRY(hipMemcpyAsync(c.M.U + (int64_t)j * n, c.Xo, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (c.M.U32) launch_to_f32(c.M.U + (int64_t)j * n, c.M.U32 + (int64_t)j * n, n, s);
+    HIP_TRY(hipStreamSynchronize(s));   // w is pageable and local
+    return HINV_OK;
+}
+
+// What a change of G inside leaves la, lb (and of the coupling column pair of a line between them)
+// reaches in the stored inverse (Section IV, Algorithm 2, made exact): the two leaf blocks; at every
+// ancestor of the two leaves, the panels Z of the children that contain one of them (their subtree
+// matrix changed, or for the line's own pair at the lowest common ancestor its weight) and, where a
+// panel changed, the capacitance inverse.  Ancestors above the lowest common ancestor are included:
+// their children's subtree matrices changed too, so stopping there would leave the inverse
+// approximate.  Everything else keeps inputs identical to a full build.
+struct LocalSet {
+    std::vector<int> leaves;
+    std::vector<std::vector<int>> cols, nodes;   // per level 1..n_levels
+    int lca_level = 0;
+};
+
+LocalSet local_set(const Plan& P, int la, int lb)
+{
+    LocalSet U;
+    U.leaves.push_back(la);
+    if (lb != la) U.leaves.push_back(lb);
+    U.cols.assign(P.n_levels + 1, {});
+    U.nodes.assign(P.n_levels + 1, {});
+    std::vector<char> seen(P.node_lo.size(), 0);
+    for (int l : U.leaves) {
+        for (int k = 0; k < P.anc_stride; ++k) {
+            const int t = P.leaf_anc[(size_t)l * P.anc_stride + k];
+            if (t < 0) break;
+            if (seen[t]) {   // shared from here up: the lowest common ancestor
+                if (U.lca_level == 0) U.lca_level = P.node_level[t];
+                break;
+            }
+            seen[t] = 1;
+            const int h = P.node_level[t];
+            bool hit_any = false;
+            for (int pp = P.node_pan0[t]; pp < P.node_pan0[t] + P.node_npan[t]; ++pp) {
+                bool hit = false;
+                for (int x : U.leaves) hit |= P.leaf_lo[x] >= P.pan_lo[pp] && P.leaf_lo[x] < P.pan_lo[pp] + P.pan_n[pp];
+                if (!hit) continue;
+                hit_any = true;
+                for (int q = 0; q < P.pan_m[pp]; ++q) U.cols[h].push_back(P.pan_col0[pp] + q);
+            }
+            if (hit_any) U.nodes[h].push_back(t);
+        }
+    }
+    return U;
+}
+
+// FP64 rebuild of a local set on the device, then the low-precision copies and the stored change
+// set (its u vectors depend on the base inverse).  Returns the kernels' flags in *flags.
+hinv_status rebuild_local(hinv_ctx& c, const LocalSet& U, hipStream_t s, int* flags)
+{
+    const Plan& P = c.P;
+    std::vector<int> lst(U.leaves);
+    std::vector<int> col_at(P.n_levels + 1, 0), node_at(P.n_levels + 1, 0);
+    for (int h = 1; h <= P.n_levels; ++h) {
+        col_at[h] = (int)lst.size();
+        lst.insert(lst.end(), U.cols[h].begin(), U.cols[h].end());
+        node_at[h] = (int)lst.size();
+        lst.insert(lst.end(), U.nodes[h].begin(), U.nodes[h].end());
+    }
+    HIP_TRY(hipMemcpyAsync(c.upd_list, lst.data(), sizeof(int) * lst.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
+    launch_leaf_inverse(c.H, c.d_flags, s, c.upd_list, (int)U.leaves.size());
+    for (int h = 1; h <= P.n_levels; ++h) {
+        const int nc = (int)U.cols[h].size(), nn = (int)U.nodes[h].size();
+        if (nc > 0) launch_build_z(c.H, h, nc, s, c.upd_list + col_at[h]);
+        if (nn == 0) continue;
+        int m_max = 0;
+        for (int t : U.nodes[h]) m_max = std::max(m_max, P.node_m[t]);
+        launch_fill_s(c.H, h, nn, s, c.upd_list + node_at[h]);
+        launch_gj_level(c.H, h, nn, m_max, c.colbuf, c.ipiv, c.d_flags, s, c.upd_list + node_at[h]);
+    }
+    convert_low(c, s);
+    HIP_TRY(hipGetLastError());
+    for (int j = 0; j < (int)c.mod_a.size(); ++j) {
+        hinv_status st = store_mod_u(c, j, s);
+        if (st != HINV_OK) return st;
+    }
+    if (!c.mod_a.empty()) launch_smw_capacitance(c.M, c.d_flags, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(flags, c.d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    return HINV_OK;
 }
 
 hinv_status plan_and_size(const hinv_csr* G, const hinv_tree* T, const hinv_options* o, int n_sets, int R,
@@ -646,15 +754,14 @@ hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g
             return fail(HINV_E_NO_SUCH_LINE, "no line of conductance %g between %d and %d", -delta_g, a, b);
     }
     // u = G0^{-1} w, w = e_a - e_b, by one FP64 apply
-    std::vector<double> w(n, 0.0);
-    w[ra] = 1.0;
-    if (rb >= 0) w[rb] = -1.0;
-    HIP_TRY(hipMemcpyAsync(c.X, w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-    launch_apply(c.H, c.P.lv.data(), HINV_FP64, c.X, c.Xo, c.Y, 1, s);
-    const int R = c.M.R;
-    HIP_TRY(hipMemcpyAsync(c.M.U + (int64_t)cnt * n, c.Xo, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    if (c.M.U32) launch_to_f32(c.M.U + (int64_t)cnt * n, c.M.U32 + (int64_t)cnt * n, n, s);
     c.mod_a.push_back(ra); c.mod_b.push_back(rb); c.mod_dg.push_back(delta_g); c.mod_act.push_back(INT32_MIN);
+    {
+        hinv_status st = store_mod_u(c, cnt, s);
+        if (st != HINV_OK) {
+            c.mod_a.pop_back(); c.mod_b.pop_back(); c.mod_dg.pop_back(); c.mod_act.pop_back();
+            return st;
+        }
+    }
     std::vector<int> cntv{cnt + 1};
     HIP_TRY(hipMemcpyAsync(c.m_a, c.mod_a.data(), sizeof(int) * (cnt + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(c.m_b, c.mod_b.data(), sizeof(int) * (cnt + 1), hipMemcpyHostToDevice, s));
@@ -662,7 +769,6 @@ hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g
     HIP_TRY(hipMemcpyAsync(c.m_act, c.mod_act.data(), sizeof(int) * (cnt + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(c.m_count, cntv.data(), sizeof(int), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
-    (void)R;
     launch_smw_capacitance(c.M, c.d_flags, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
@@ -674,6 +780,95 @@ hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g
         std::vector<int> back{cnt};
         HIP_TRY(hipMemcpy(c.m_count, back.data(), sizeof(int), hipMemcpyHostToDevice));
         return fail(HINV_E_NOT_SPD, "the change makes G indefinite or singular");
+    }
+    return HINV_OK;
+}
+
+hinv_status hinv_update_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream,
+                             hinv_update_info* out)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    hinv_ctx& c = *h;
+    Plan& P = c.P;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = P.n;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return fail(HINV_E_INVALID, "bad buses (%d, %d)", a, b);
+    if (!isfinite(delta_g) || delta_g == 0.0) return fail(HINV_E_INVALID, "delta_g must be finite and non-zero");
+    const int ra = P.iperm[a], rb = b >= 0 ? P.iperm[b] : -1;
+    auto entry = [&](int r, int col) {
+        for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
+            if (P.ci[e] == col) return e;
+        return -1;
+    };
+    const int e_aa = entry(ra, ra), e_bb = rb >= 0 ? entry(rb, rb) : -1;
+    const int e_ab = rb >= 0 ? entry(ra, rb) : -1, e_ba = rb >= 0 ? entry(rb, ra) : -1;
+    if (rb >= 0 && (e_ab < 0 || e_ba < 0))
+        return fail(HINV_E_NO_SUCH_LINE, "G has no entry between buses %d and %d; a new coupling needs a rebuild", a, b);
+    const int la = P.row_leaf[ra], lb = rb >= 0 ? P.row_leaf[rb] : la;
+    // the coupling column pair of a line between two leaves
+    int ca = -1, cb = -1;
+    if (la != lb) {
+        for (int g = 0; g < (int)P.col_row.size() && ca < 0; ++g)
+            if (P.col_row[g] == ra && P.col_row[P.col_partner[g]] == rb) { ca = g; cb = P.col_partner[g]; }
+        if (ca < 0)
+            return fail(HINV_E_NO_SUCH_LINE, "buses %d and %d are in different leaves and G has no line between "
+                        "them; a new coupling needs a rebuild", a, b);
+    }
+    const double old_aa = P.cv[e_aa], old_bb = e_bb >= 0 ? P.cv[e_bb] : 0.0, old_ab = e_ab >= 0 ? P.cv[e_ab] : 0.0;
+    double new_ab = old_ab - delta_g;
+    if (e_ab >= 0) {
+        if (fabs(new_ab) <= 1e-12 * fabs(delta_g)) new_ab = 0.0;
+        if (new_ab > 0.0)
+            return fail(HINV_E_NO_SUCH_LINE, "no line of conductance %g between %d and %d", -delta_g, a, b);
+    }
+    const double old_wa = ca >= 0 ? P.col_w[ca] : 0.0;
+    auto set_values = [&](double aa, double bb, double ab, double w) -> hinv_status {
+        P.cv[e_aa] = aa;
+        HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_aa), &P.cv[e_aa], sizeof(double), hipMemcpyHostToDevice, s));
+        if (e_bb >= 0) {
+            P.cv[e_bb] = bb;
+            HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_bb), &P.cv[e_bb], sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        if (e_ab >= 0) {
+            P.cv[e_ab] = ab; P.cv[e_ba] = ab;
+            HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_ab), &P.cv[e_ab], sizeof(double), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_ba), &P.cv[e_ba], sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        if (ca >= 0) {
+            P.col_w[ca] = w; P.col_w[cb] = w;
+            HIP_TRY(hipMemcpyAsync((void*)(c.H.col_w + ca), &P.col_w[ca], sizeof(double), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync((void*)(c.H.col_w + cb), &P.col_w[cb], sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        return HINV_OK;
+    };
+    const LocalSet U = local_set(P, la, lb);
+    hinv_status st = set_values(old_aa + delta_g, old_bb + delta_g, new_ab, sqrt(fabs(new_ab)));
+    if (st != HINV_OK) return st;
+    int flags = 0;
+    st = rebuild_local(c, U, s, &flags);
+    if (st != HINV_OK) return st;
+    if (flags & (kFlagNotSPD | kFlagSingular)) {
+        // the same local rebuild with the old values restores the old inverse exactly
+        st = set_values(old_aa, old_bb, old_ab, old_wa);
+        if (st != HINV_OK) return st;
+        int back = 0;
+        st = rebuild_local(c, U, s, &back);
+        if (st != HINV_OK) return st;
+        HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (back & (kFlagNotSPD | kFlagSingular)) return fail(HINV_E_DEVICE, "restoring the inverse failed");
+        return fail((flags & kFlagNotSPD) ? HINV_E_NOT_SPD : HINV_E_SINGULAR,
+                    "the change makes G (or G with the stored line changes) indefinite or singular");
+    }
+    if (out) {
+        out->lca_level = U.lca_level;
+        out->leaves = (int32_t)U.leaves.size();
+        out->columns = 0;
+        out->nodes = 0;
+        for (int hh = 1; hh <= P.n_levels; ++hh) {
+            out->columns += (int32_t)U.cols[hh].size();
+            out->nodes += (int32_t)U.nodes[hh].size();
+        }
     }
     return HINV_OK;
 }

@@ -376,11 +376,13 @@ struct LevelHost {
 enum : int { kFlagNotSPD = 1, kFlagSingular = 2, kFlagNaN = 4, kFlagNoConv = 8, kFlagBarrier = 16, kFlagTeamRow = 32 };
 
 // ---------------- kernel launchers (k_build.hip / k_apply.hip / k_emt.hip)
-void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s);
-void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s);
-void launch_fill_s(const HierDev& H, int level, int nnodes, hipStream_t s);
+// Builders of the stored inverse.  list (device): the leaves / columns / nodes to (re)build, count
+// entries; NULL: every leaf, or every column / node of the level (ncols / nnodes of them).
+void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s, const int* list = nullptr, int count = 0);
+void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s, const int* list = nullptr);
+void launch_fill_s(const HierDev& H, int level, int nnodes, hipStream_t s, const int* list = nullptr);
 void launch_gj_level(const HierDev& H, int level, int nnodes, int m_max, double* colbuf, int* ipiv, int* flags,
-                     hipStream_t s);
+                     hipStream_t s, const int* list = nullptr);
 void launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);
 void launch_to_bf16(const double* src, uint16_t* dst, int64_t count, hipStream_t s);
 // E4M3 with one E8M0 scale per 32 entries (count rounded up to whole groups in `scale`)

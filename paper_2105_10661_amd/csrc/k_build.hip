@@ -20,12 +20,14 @@
 
 namespace hinv {
 
-__global__ __launch_bounds__(kBlock) void k_leaf_inverse(HierDev H, int* flags)
+// Every builder takes an optional list of the leaves / columns / nodes to (re)build (NULL: all of
+// them, or all of the level); a local line update rebuilds only what the change reaches.
+__global__ __launch_bounds__(kBlock) void k_leaf_inverse(HierDev H, int* flags, const int* list)
 {
     __shared__ double A[kMaxLeaf * kMaxLeaf];
     __shared__ double rowk[kMaxLeaf];
     __shared__ double colk[kMaxLeaf];
-    const int l = blockIdx.x;
+    const int l = list ? list[blockIdx.x] : (int)blockIdx.x;
     const int lo = H.leaf_lo[l], nl = H.leaf_n[l];
     const int tid = threadIdx.x;
     for (int idx = tid; idx < nl * nl; idx += blockDim.x) A[idx] = 0.0;
@@ -66,12 +68,12 @@ __global__ __launch_bounds__(kBlock) void k_leaf_inverse(HierDev H, int* flags)
 }
 
 // One block per coupling column of the level.
-__global__ __launch_bounds__(kBlock) void k_build_z(HierDev H, int level)
+__global__ __launch_bounds__(kBlock) void k_build_z(HierDev H, int level, const int* list)
 {
     extern __shared__ double sh[];
     double* s = sh;
     double* y = sh + H.max_cols;
-    const int p = H.lvl_col[level - 1] + blockIdx.x;
+    const int p = list ? list[blockIdx.x] : H.lvl_col[level - 1] + (int)blockIdx.x;
     const int P = H.col_pan[p];
     const int clo = H.pan_lo[P], cn = H.pan_n[P];
     double* z = H.Z + H.pan_zoff[P] + (int64_t)(p - H.pan_col0[P]) * cn;
@@ -115,9 +117,9 @@ __global__ __launch_bounds__(kBlock) void k_build_z(HierDev H, int level)
 }
 
 // S^T into the S^{-1} slot: slot[q*m + p] = S[p][q], S[p][q] = C[p][q] + w_p Z_q[row_p].
-__global__ __launch_bounds__(kBlock) void k_fill_s(HierDev H, int level)
+__global__ __launch_bounds__(kBlock) void k_fill_s(HierDev H, int level, const int* list)
 {
-    const int t = H.lvl_node[level - 1] + blockIdx.x;
+    const int t = list ? list[blockIdx.x] : H.lvl_node[level - 1] + (int)blockIdx.x;
     const int m = H.node_m[t], c0 = H.node_col0[t];
     double* S = H.Sinv + H.node_soff[t];
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
@@ -135,11 +137,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_s(HierDev H, int level)
 // Pivot step k for every node of the level: choose the pivot row, swap, scale
 // row k, save and clear column k of the other rows.
 __global__ __launch_bounds__(kBlock) void k_gj_pivot(HierDev H, int level, int k, double* colbuf, int* ipiv,
-                                                      int* flags)
+                                                      int* flags, const int* list)
 {
     __shared__ double bv[kBlock];
     __shared__ int bi[kBlock];
-    const int t = H.lvl_node[level - 1] + blockIdx.x;
+    const int t = list ? list[blockIdx.x] : H.lvl_node[level - 1] + (int)blockIdx.x;
     const int m = H.node_m[t];
     if (k >= m) return;
     double* A = H.Sinv + H.node_soff[t];
@@ -191,9 +193,10 @@ __global__ __launch_bounds__(kBlock) void k_gj_pivot(HierDev H, int level, int k
 }
 
 // Elimination for pivot step k: A[i][j] -= f_i * A[k][j], i != k.
-__global__ __launch_bounds__(kBlock) void k_gj_eliminate(HierDev H, int level, int k, const double* colbuf)
+__global__ __launch_bounds__(kBlock) void k_gj_eliminate(HierDev H, int level, int k, const double* colbuf,
+                                                          const int* list)
 {
-    const int t = H.lvl_node[level - 1] + blockIdx.y;
+    const int t = list ? list[blockIdx.y] : H.lvl_node[level - 1] + (int)blockIdx.y;
     const int m = H.node_m[t];
     if (k >= m) return;
     double* A = H.Sinv + H.node_soff[t];
@@ -208,9 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_gj_eliminate(HierDev H, int level, i
 }
 
 // Undo the row interchanges: swap columns k and ipiv[k], k from last to first.
-__global__ __launch_bounds__(kBlock) void k_gj_unscramble(HierDev H, int level, const int* ipiv)
+__global__ __launch_bounds__(kBlock) void k_gj_unscramble(HierDev H, int level, const int* ipiv, const int* list)
 {
-    const int t = H.lvl_node[level - 1] + blockIdx.x;
+    const int t = list ? list[blockIdx.x] : H.lvl_node[level - 1] + (int)blockIdx.x;
     const int m = H.node_m[t];
     double* A = H.Sinv + H.node_soff[t];
     const int* ip = ipiv + H.node_col0[t];
@@ -310,21 +313,22 @@ void launch_to_fp8(const double* src, uint8_t* dst, uint8_t* scale, int64_t coun
     hipLaunchKernelGGL(k_to_fp8, dim3((unsigned)blocks), dim3(kBlock), 0, s, src, dst, scale, count);
 }
 
-void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s)
+void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s, const int* list, int count)
 {
-    if (H.n_leaves > 0) hipLaunchKernelGGL(k_leaf_inverse, dim3(H.n_leaves), dim3(kBlock), 0, s, H, flags);
+    const int nb = list ? count : H.n_leaves;
+    if (nb > 0) hipLaunchKernelGGL(k_leaf_inverse, dim3(nb), dim3(kBlock), 0, s, H, flags, list);
 }
 
-void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s)
+void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s, const int* list)
 {
     if (ncols <= 0) return;
     const size_t lds = sizeof(double) * 2 * (size_t)(H.max_cols > 0 ? H.max_cols : 1);
-    hipLaunchKernelGGL(k_build_z, dim3(ncols), dim3(kBlock), lds, s, H, level);
+    hipLaunchKernelGGL(k_build_z, dim3(ncols), dim3(kBlock), lds, s, H, level, list);
 }
 
-void launch_fill_s(const HierDev& H, int level, int nnodes, hipStream_t s)
+void launch_fill_s(const HierDev& H, int level, int nnodes, hipStream_t s, const int* list)
 {
-    if (nnodes > 0) hipLaunchKernelGGL(k_fill_s, dim3(nnodes), dim3(kBlock), 0, s, H, level);
+    if (nnodes > 0) hipLaunchKernelGGL(k_fill_s, dim3(nnodes), dim3(kBlock), 0, s, H, level, list);
 }
 
 void launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t s)
@@ -339,17 +343,17 @@ void launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t s)
 // the level).  colbuf [n_cols] doubles and ipiv [n_cols] ints, indexed by the
 // node's first global column.
 void launch_gj_level(const HierDev& H, int level, int nnodes, int m_max, double* colbuf, int* ipiv, int* flags,
-                     hipStream_t s)
+                     hipStream_t s, const int* list)
 {
     if (nnodes <= 0 || m_max <= 0) return;
     const int64_t tot = (int64_t)m_max * m_max;
     int gx = (int)((tot + kBlock - 1) / kBlock);
     if (gx > 1024) gx = 1024;
     for (int k = 0; k < m_max; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(nnodes), dim3(kBlock), 0, s, H, level, k, colbuf, ipiv, flags);
-        hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, nnodes), dim3(kBlock), 0, s, H, level, k, colbuf);
+        hipLaunchKernelGGL(k_gj_pivot, dim3(nnodes), dim3(kBlock), 0, s, H, level, k, colbuf, ipiv, flags, list);
+        hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, nnodes), dim3(kBlock), 0, s, H, level, k, colbuf, list);
     }
-    hipLaunchKernelGGL(k_gj_unscramble, dim3(nnodes), dim3(kBlock), 0, s, H, level, ipiv);
+    hipLaunchKernelGGL(k_gj_unscramble, dim3(nnodes), dim3(kBlock), 0, s, H, level, ipiv, list);
 }
 
 }  // namespace hinv

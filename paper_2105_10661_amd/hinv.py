@@ -22,7 +22,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8": FP8}
 STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "NO_SUCH_LINE",
           6: "NO_CONVERGENCE", 7: "RANK_LIMIT", 8: "SINGULAR"}
 
-EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_solve", "hinv_sync_status",
+EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update_line", "hinv_solve", "hinv_sync_status",
            "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_workspace_size", "emt_create",
            "emt_step", "emt_lose_line", "emt_sync_status", "emt_get_step", "emt_get_stats", "emt_set_step_clock",
            "emt_destroy",
@@ -57,6 +57,10 @@ class _Info(ctypes.Structure):
                                              "z_entries", "s_entries", "max_leaf", "max_cols")]
 
 
+class _UpdateInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in ("lca_level", "leaves", "columns", "nodes")]
+
+
 class _Network(ctypes.Structure):
     _fields_ = [("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("from_", ctypes.c_void_p),
                 ("to", ctypes.c_void_p), ("R", ctypes.c_void_p), ("L", ctypes.c_void_p), ("C", ctypes.c_void_p),
@@ -85,6 +89,7 @@ def load() -> ctypes.CDLL:
         "hinv_workspace_size": [P, P, P, P],
         "hinv_build": [P, P, P, P, ctypes.c_size_t, P, P],
         "hinv_modify_line": [P, i32, i32, d, P],
+        "hinv_update_line": [P, i32, i32, d, P, P],
         "hinv_solve": [P, P, P, i32, i32, P],
         "hinv_sync_status": [P],
         "hinv_get_info": [P, P],
@@ -237,6 +242,14 @@ class Hierarchy:
 
     def modify_line(self, a: int, b: int, delta_g: float) -> None:
         _check(self._lib.hinv_modify_line(self._h, int(a), int(b), float(delta_g), _stream()), "hinv_modify_line")
+
+    def update_line(self, a: int, b: int, delta_g: float) -> dict:
+        """G <- G + delta_g (e_a - e_b)(e_a - e_b)^T in the base matrix, with a local FP64 rebuild
+        of the stored inverse; returns what was rebuilt."""
+        inf = _UpdateInfo()
+        _check(self._lib.hinv_update_line(self._h, int(a), int(b), float(delta_g), _stream(), ctypes.byref(inf)),
+               "hinv_update_line")
+        return {k: getattr(inf, k) for k, _ in _UpdateInfo._fields_}
 
     def sync_status(self) -> None:
         import torch

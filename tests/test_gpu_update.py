@@ -1,0 +1,254 @@
+"""GPU parity of the local line update of the base matrix (Section IV,
+Algorithm 2, made exact: the two leaf blocks are re-inverted and the coupling
+data on their paths to the root is recomputed).
+
+* For a change that keeps G's nonzero pattern, the updated inverse equals a
+  fresh build of the changed G bit for bit (every recomputed block gets the
+  same inputs as in the fresh build; every other block's inputs are
+  unchanged), for lines inside a leaf, lines whose lowest common ancestor is
+  low in the tree and lines cut at the root.
+* The updated inverse equals the oracle's inverse of the changed G (1e-12,
+  the FP64 assembled-inverse bar), also after a line is removed completely
+  (its coupling column stays with weight 0), after a change to ground and
+  after several updates in a row, on top of stored rank-1 changes (1e-11, the
+  bar of the rank-1 path), and in FP32 with FP64 refinement (1e-10).
+* Errors: a coupling that G does not have, more conductance removed than the
+  line has, a change that makes G indefinite (the previous inverse is then
+  restored bit for bit).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10661_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    from paper_2105_10661_amd import hinv
+    torch.cuda.set_device(0)
+    hinv.load()
+    return hinv
+
+
+def _gpu_inverse(H, n):
+    import torch
+    V = H.solve(torch.eye(n, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    return V.cpu().numpy().T
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _heights(parent):
+    h = np.zeros(len(parent), np.int64)
+    for _ in range(len(parent)):
+        changed = False
+        for t, p in enumerate(parent):
+            if p >= 0 and h[p] < h[t] + 1:
+                h[p] = h[t] + 1
+                changed = True
+        if not changed:
+            break
+    return h
+
+
+def _lca(parent, x, y):
+    anc = set()
+    while x >= 0:
+        anc.add(x)
+        x = parent[x]
+    while y not in anc:
+        y = parent[y]
+    return y
+
+
+def _lca_level(net, a, b):
+    """Height of the lowest common ancestor of the leaves of buses a and b (0: same leaf)."""
+    la, lb = int(net.bus_leaf[a]), int(net.bus_leaf[b])
+    if la == lb:
+        return 0
+    return int(_heights(net.parent)[_lca(net.parent, la, lb)])
+
+
+def _changed_csr(rp, ci, cv, a, b, dg):
+    """The caller's CSR with G <- G + dg (e_a - e_b)(e_a - e_b)^T."""
+    cv = cv.copy()
+
+    def at(r, c):
+        row = ci[rp[r]:rp[r + 1]]
+        return rp[r] + int(np.nonzero(row == c)[0][0])
+
+    cv[at(a, a)] += dg
+    if b >= 0:
+        cv[at(b, b)] += dg
+        v = cv[at(a, b)] - dg
+        if abs(v) <= 1e-12 * abs(dg):
+            v = 0.0
+        cv[at(a, b)] = v
+        cv[at(b, a)] = v
+    return cv
+
+
+def _changed_dense(G, a, b, dg):
+    G = G.copy()
+    w = np.zeros(G.shape[0])
+    w[a] = 1.0
+    if b >= 0:
+        w[b] = -1.0
+    return G + dg * np.outer(w, w)
+
+
+def _pick_lines(net):
+    """One branch inside a leaf, one whose leaves meet lowest in the tree, one cut at the root."""
+    lv = np.array([_lca_level(net, int(a), int(b)) for a, b in zip(net.frm, net.to)])
+    top = lv.max()
+    low = lv[lv > 0].min()
+    return [int(np.nonzero(lv == 0)[0][0]), int(np.nonzero(lv == low)[0][0]), int(np.nonzero(lv == top)[0][-1])], lv
+
+
+@pytest.mark.parametrize("name", ["c1-179", "ring4-716"])
+@pytest.mark.parametrize("frac", [-0.5, 0.25])
+def test_update_equals_fresh_build_bitwise(hv, name, frac):
+    net = {"c1-179": cases.net_179(), "ring4-716": cases.net_ring(4, 7)}[name]
+    n = net.n_bus
+    rp, ci, cv = hv.network_csr(net)
+    g = oracle.branch_conductance(net)
+    G = oracle.assemble_G(net)
+    picks, lv = _pick_lines(net)
+    assert lv[picks[0]] == 0 and lv[picks[2]] > lv[picks[1]] > 0
+    for e in picks:
+        a, b, dg = int(net.frm[e]), int(net.to[e]), frac * float(g[e])
+        print(f"[gpu] update {name} branch {e} ({a},{b}) lca level {lv[e]} dg {dg:+.3e}", flush=True)
+        H = hv.Hierarchy(rp, ci, cv, net.parent, net.bus_leaf, max_nrhs=n)
+        info = H.update_line(a, b, dg)
+        assert info["lca_level"] == lv[e]
+        assert info["leaves"] == (1 if lv[e] == 0 else 2)
+        Gi = _gpu_inverse(H, n)
+        F = hv.Hierarchy(rp, ci, _changed_csr(rp, ci, cv, a, b, dg), net.parent, net.bus_leaf, max_nrhs=n)
+        assert np.array_equal(Gi, _gpu_inverse(F, n)), e
+        assert _rel(Gi, oracle.inverse(_changed_dense(G, a, b, dg))) <= 1e-12
+        H.close()
+        F.close()
+
+
+def test_update_sequence_removal_ground_and_readd(hv):
+    net = cases.net_ring(8, 2)
+    n = net.n_bus
+    g = oracle.branch_conductance(net)
+    picks, lv = _pick_lines(net)
+    H = hv.Hierarchy.from_network(net, max_nrhs=n)
+    G = oracle.assemble_G(net)
+    root_line = picks[2]
+    a, b = int(net.frm[root_line]), int(net.to[root_line])
+    steps = [(a, b, -float(g[root_line])),                 # remove a line cut at the root completely
+             (int(net.frm[picks[0]]), int(net.to[picks[0]]), -float(g[picks[0]])),   # and one inside a leaf
+             (777, -1, 0.05),                              # a fault to ground
+             (int(net.frm[picks[1]]), int(net.to[picks[1]]), 0.5 * float(g[picks[1]])),
+             (a, b, float(g[root_line]))]                  # put the removed line back
+    for k, (x, y, dg) in enumerate(steps):
+        print(f"[gpu] update sequence step {k}: ({x},{y}) dg {dg:+.3e}", flush=True)
+        H.update_line(x, y, dg)
+        G = _changed_dense(G, x, y, dg)
+        assert _rel(_gpu_inverse(H, n), oracle.inverse(G)) <= 1e-12, k
+    H.sync_status()
+    H.close()
+
+
+def test_update_on_top_of_stored_changes(hv):
+    net = cases.net_179()
+    n = net.n_bus
+    g = oracle.branch_conductance(net)
+    picks, _ = _pick_lines(net)
+    H = hv.Hierarchy.from_network(net, max_nrhs=n, max_mod_rank=2)
+    e1 = 10 if 10 not in picks else 11
+    H.modify_line(int(net.frm[e1]), int(net.to[e1]), -float(g[e1]))
+    H.modify_line(37, -1, 0.1)
+    G = oracle.assemble_G(net)
+    G = _changed_dense(G, int(net.frm[e1]), int(net.to[e1]), -float(g[e1]))
+    G = _changed_dense(G, 37, -1, 0.1)
+    for e in picks:
+        H.update_line(int(net.frm[e]), int(net.to[e]), -0.5 * float(g[e]))
+        G = _changed_dense(G, int(net.frm[e]), int(net.to[e]), -0.5 * float(g[e]))
+        assert _rel(_gpu_inverse(H, n), oracle.inverse(G)) <= 1e-11, e
+    H.close()
+
+
+@pytest.mark.parametrize("prec,refine", [("fp32", 2), ("bf16", 18)])
+def test_update_low_precision_solves(hv, prec, refine):
+    import torch
+    net = cases.net_ring(8, 2)
+    g = oracle.branch_conductance(net)
+    picks, _ = _pick_lines(net)
+    H = hv.Hierarchy.from_network(net, prec=prec, max_refine=refine, max_nrhs=8, rel_tol=1e-9)
+    G = oracle.assemble_G(net)
+    for e in picks:
+        H.update_line(int(net.frm[e]), int(net.to[e]), -float(g[e]))
+        G = _changed_dense(G, int(net.frm[e]), int(net.to[e]), -float(g[e]))
+    B = np.random.default_rng(5).standard_normal((8, net.n_bus))
+    X = H.solve(torch.tensor(B, device="cuda")).cpu().numpy()
+    Xo = oracle.solve(G, B)
+    assert (np.abs(X - Xo).max(1) / np.abs(Xo).max(1)).max() <= 1e-10
+    H.sync_status()
+    H.close()
+
+
+def test_update_errors_and_restore(hv):
+    net = cases.net_179()
+    n = net.n_bus
+    g = oracle.branch_conductance(net)
+    H = hv.Hierarchy.from_network(net, max_nrhs=n)
+    before = _gpu_inverse(H, n)
+    G = oracle.assemble_G(net)
+    # two buses in different leaves with no line between them
+    la = net.bus_leaf
+    a = 0
+    b = next(j for j in range(n) if la[j] != la[a] and G[a, j] == 0.0)
+    with pytest.raises(hv.HinvError) as ei:
+        H.update_line(a, b, 1.0)
+    assert ei.value.name == "NO_SUCH_LINE"
+    with pytest.raises(hv.HinvError) as ei:
+        H.update_line(int(net.frm[3]), int(net.to[3]), -2.0 * float(g[3]))
+    assert ei.value.name == "NO_SUCH_LINE"
+    for bad in ((0, 0, 1.0), (-1, 2, 1.0), (0, n, 1.0), (0, 1, 0.0), (0, 1, float("nan"))):
+        with pytest.raises(hv.HinvError) as ei:
+            H.update_line(*bad)
+        assert ei.value.name == "INVALID"
+    # a fault of negative conductance that makes G indefinite
+    with pytest.raises(hv.HinvError) as ei:
+        H.update_line(5, -1, -2.0 * G[5, 5])
+    assert ei.value.name == "NOT_SPD"
+    assert np.array_equal(_gpu_inverse(H, n), before)
+    H.sync_status()
+    H.close()
+
+
+def test_update_11456_root_line_sampled_solves(hv):
+    import torch
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    net = cases.net_torus(8, 8, seed=3)
+    n = net.n_bus
+    g = oracle.branch_conductance(net)
+    H = hv.Hierarchy.from_network(net, max_nrhs=4)
+    rng = np.random.default_rng(21)
+    lines = rng.choice(net.n_branch, 40, replace=False)
+    lv = np.array([_lca_level(net, int(net.frm[e]), int(net.to[e])) for e in lines])
+    e = int(lines[np.argmax(lv)])
+    a, b, dg = int(net.frm[e]), int(net.to[e]), -0.75 * float(g[e])
+    print(f"[gpu] 11456 update branch {e} lca level {lv.max()}", flush=True)
+    info = H.update_line(a, b, dg)
+    assert info["lca_level"] == lv.max() and info["leaves"] == 2
+    w = sp.csc_matrix(([1.0, -1.0], ([a, b], [0, 0])), shape=(n, 1))
+    solve = spl.splu((oracle.sparse_G(net) + dg * (w @ w.T)).tocsc(), permc_spec="MMD_AT_PLUS_A").solve
+    B = rng.standard_normal((4, n))
+    X = H.solve(torch.tensor(B, device="cuda")).cpu().numpy()
+    for k in range(4):
+        ref = solve(B[k])
+        assert np.abs(X[k] - ref).max() / np.abs(ref).max() <= 1e-10
+    H.close()
