@@ -148,6 +148,76 @@ def study_11456(hinv, torch, khz, steps=200):
     return out
 
 
+def study_update(hinv, torch, reps=5):
+    """Cost of a persistent line change of the base matrix against where the line sits in the tree.
+
+    Per network (1432-bus ring, 11456-bus torus) and per tree level of the line ends' lowest common
+    ancestor (0: both ends in one leaf): median wall time of hinv_update_line (local FP64 rebuild of
+    the exact inverse; the call synchronises), what it rebuilt, and for comparison a full build
+    (hinv_build of the whole hierarchy, host planning included) and a rank-1 change by
+    Sherman-Morrison-Woodbury (hinv_modify_line).
+    """
+    import time
+    import oracle
+    from paper_2105_10661_amd import cases
+    out = {}
+    for name, net in (("1432-bus ring", cases.net_ring(8, 2)), ("11456-bus torus", cases.net_torus(8, 8, seed=3))):
+        g = oracle.branch_conductance(net)
+        leaf = net.bus_leaf
+        par = net.parent
+        hgt = np.zeros(len(par), np.int64)
+        for t in range(len(par)):            # heights: walk up from every leaf
+            x, d = t, 0
+            while x >= 0:
+                hgt[x] = max(hgt[x], d)
+                x, d = par[x], d + 1
+
+        def lca_level(a, b):
+            x, y = int(leaf[a]), int(leaf[b])
+            if x == y:
+                return 0
+            anc = set()
+            while x >= 0:
+                anc.add(x)
+                x = par[x]
+            while y not in anc:
+                y = par[y]
+            return int(hgt[y])
+
+        lv = np.array([lca_level(int(a), int(b)) for a, b in zip(net.frm, net.to)])
+        builds = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = hinv.Hierarchy.from_network(net, max_nrhs=1, max_mod_rank=8)
+            torch.cuda.synchronize()
+            builds.append((time.perf_counter() - t0) * 1e3)
+            if _ < 2:
+                H.close()
+        row = {"full_build_ms": round(float(np.median(builds)), 3), "update_by_lca_level": {}}
+        for L in range(int(lv.max()) + 1):
+            e = int(np.nonzero(lv == L)[0][len(np.nonzero(lv == L)[0]) // 2])
+            a, b = int(net.frm[e]), int(net.to[e])
+            ts, info = [], None
+            for k in range(2 * reps):
+                dg = -0.5 * float(g[e]) if k % 2 == 0 else 0.5 * float(g[e])
+                t0 = time.perf_counter()
+                info = H.update_line(a, b, dg)
+                ts.append((time.perf_counter() - t0) * 1e3)
+            row["update_by_lca_level"][str(L)] = dict(info, branch=e, median_ms=round(float(np.median(ts)), 3),
+                                                      min_ms=round(float(np.min(ts)), 3))
+        ts = []
+        for k in range(8):
+            t0 = time.perf_counter()
+            H.modify_line(int(net.frm[k]), int(net.to[k]), -float(g[k]))
+            ts.append((time.perf_counter() - t0) * 1e3)
+        row["smw_modify_median_ms"] = round(float(np.median(ts)), 3)
+        row.update({k: H.info()[k] for k in ("n_leaves", "n_internal", "n_levels", "n_cols", "max_cols")})
+        H.close()
+        out[name] = row
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +238,9 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first copy a buffer of this many MiB three times (device to device): the known-size "
                          "kernel that scales hardware byte counters")
+    ap.add_argument("--update-study", action="store_true",
+                    help="also time persistent line updates of the base matrix against the tree level of the "
+                         "line (local rebuild), a full build and a rank-1 change")
     ap.add_argument("--study-11456", action="store_true",
                     help="also time the 11456-bus torus per storage precision and record error vs corrections")
     args = ap.parse_args()
@@ -309,6 +382,7 @@ def main():
     study = None
     if args.study_11456:
         study = study_11456(hinv, torch, khz)
+    upd = study_update(hinv, torch) if args.update_study else None
     served = None
     if args.serve:
         from paper_2105_10661_amd import serve
@@ -357,6 +431,7 @@ def main():
         "paths": table,
         "batched_contingencies": batch,
         "torus_11456": study,
+        "line_update": upd,
         "serving": served,
         "stored_entries": entries,
         "roofline": {

@@ -79,7 +79,25 @@ struct Plan {
     std::vector<double> cv;
     int64_t leaf_entries = 0, z_entries = 0, s_entries = 0;
     int max_cols = 0, max_pan_rows = 0, max_leaf = 0;
+    // capacitance inversions, level by level: gj_list[gj_at[h] .. gj_at[h] + gj_n[h]) are the
+    // level's nodes with m > 0 in the order invert_level launches them
+    std::vector<int> gj_list, gj_at, gj_n;
+    int64_t gj_xb = 0, gj_sync = 0;   // exchange space of the largest team launch
 };
+
+// Order nodes for invert_level: m <= kNodeGjMax (one workgroup each), then m <= kGjTeamMax (a team
+// of workgroups each), then the rest (one launch pair per pivot step).  Nodes with m == 0 drop out.
+std::vector<int> order_nodes(const Plan& P, const std::vector<int>& nodes)
+{
+    std::vector<int> out;
+    for (int pass = 0; pass < 3; ++pass)
+        for (int t : nodes) {
+            const int m = P.node_m[t];
+            const int cat = m <= 0 ? -1 : m <= kNodeGjMax ? 0 : m <= kGjTeamMax ? 1 : 2;
+            if (cat == pass) out.push_back(t);
+        }
+    return out;
+}
 
 hinv_status check_csr(const hinv_csr* G)
 {
@@ -369,6 +387,23 @@ hinv_status make_plan(const hinv_csr* G, const hinv_tree* T, Plan& P)
         P.col_soff[g] = P.node_soff[t] + ((int)g - P.node_col0[t]);
     }
     if (P.max_cols > 4096) return fail(HINV_E_INVALID, "a tree node has %d coupling columns (limit 4096)", P.max_cols);
+    P.gj_at.assign(P.n_levels + 1, 0);
+    P.gj_n.assign(P.n_levels + 1, 0);
+    for (int h = 1; h <= P.n_levels; ++h) {
+        std::vector<int> lvl;
+        for (int t = P.lvl_node[h - 1]; t < P.lvl_node[h]; ++t) lvl.push_back(t);
+        const std::vector<int> ord = order_nodes(P, lvl);
+        P.gj_at[h] = (int)P.gj_list.size();
+        P.gj_n[h] = (int)ord.size();
+        P.gj_list.insert(P.gj_list.end(), ord.begin(), ord.end());
+        std::vector<int> mt;
+        for (int t : ord)
+            if (P.node_m[t] > kNodeGjMax && P.node_m[t] <= kGjTeamMax) mt.push_back(P.node_m[t]);
+        int64_t xbd = 0, syw = 0;
+        gj_team_sizes(mt, &xbd, &syw);
+        P.gj_xb = std::max(P.gj_xb, xbd);
+        P.gj_sync = std::max(P.gj_sync, syw);
+    }
     return HINV_OK;
 }
 
@@ -391,6 +426,9 @@ struct hinv_ctx {
     std::vector<double> mod_dg;
     int* m_count = nullptr; int* m_a = nullptr; int* m_b = nullptr; int* m_act = nullptr; double* m_dg = nullptr;
     int* upd_list = nullptr;   // leaves / columns / nodes a local rebuild launches over
+    int* gj_list = nullptr;    // the plan's per-level capacitance inversion lists
+    double* gj_xb = nullptr;   // team Gauss-Jordan exchange
+    unsigned int* gj_sync = nullptr;
     int64_t applies = 0;
 };
 
@@ -447,6 +485,9 @@ void carve_hier(hinv_ctx& c, Arena& A, int n_sets, int R, int max_nrhs)
     c.colbuf = A.take<double>(NC);
     c.ipiv = A.take<int>(NC);
     c.upd_list = A.take<int>((int64_t)L + NC + NI);
+    c.gj_list = A.take<int>(NI);
+    c.gj_xb = A.take<double>(P.gj_xb);
+    c.gj_sync = A.take<unsigned int>(P.gj_sync);
     c.d_flags = A.take<int>(4);
     c.X = A.take<double>((int64_t)P.n * max_nrhs);
     c.Xo = A.take<double>((int64_t)P.n * max_nrhs);
@@ -507,6 +548,30 @@ void convert_low(hinv_ctx& c, hipStream_t s)
     }
 }
 
+// S^{-1} of the nodes of one level: d_list (device) and nodes (host) hold the same nodes in
+// order_nodes order.
+hinv_status invert_level(hinv_ctx& c, int level, const int* d_list, const std::vector<int>& nodes, hipStream_t s)
+{
+    const Plan& P = c.P;
+    int ns = 0, nl = 0, ml = 0;
+    std::vector<int> mt;
+    for (int t : nodes) {
+        const int m = P.node_m[t];
+        if (m <= kNodeGjMax) ++ns;
+        else if (m <= kGjTeamMax) mt.push_back(m);
+        else { ++nl; ml = std::max(ml, m); }
+    }
+    const int nt = (int)mt.size();
+    launch_node_inverse(c.H, d_list, ns, c.d_flags, s);
+    HIP_TRY(launch_gj_team(c.H, d_list + ns, mt, c.gj_xb, c.gj_sync, c.d_flags, s));
+    if (nl > 0) {
+        const int* lst = d_list + ns + nt;
+        launch_fill_s(c.H, level, nl, ml, s, lst);
+        launch_gj_level(c.H, level, nl, ml, c.colbuf, c.ipiv, c.d_flags, s, lst);
+    }
+    return HINV_OK;
+}
+
 // Upload the plan and run the FP64 build (leaf inverses, then per level Z and S^{-1}).
 hinv_status build_device(hinv_ctx& c, hipStream_t s)
 {
@@ -531,6 +596,7 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
     HIP_TRY(up(H.frow_z, P.frow_z, s)); HIP_TRY(up(H.frow_pn, P.frow_pn, s)); HIP_TRY(up(H.frow_pm, P.frow_pm, s));
     HIP_TRY(up(H.frow_pc, P.frow_pc, s)); HIP_TRY(up(H.frow_row, P.frow_row, s));
     HIP_TRY(up(H.rp, P.rp, s)); HIP_TRY(up(H.ci, P.ci, s)); HIP_TRY(up(H.cv, P.cv, s));
+    HIP_TRY(up(c.gj_list, P.gj_list, s));
     HIP_TRY(hipMemsetAsync(c.d_flags, 0, 4 * sizeof(int), s));
     HIP_TRY(hipMemsetAsync((void*)c.M.count, 0, sizeof(int) * c.M.n_sets, s));
     HIP_TRY(hipMemsetAsync(c.stats, 0, sizeof(unsigned long long) * c.opt.max_nrhs, s));
@@ -539,8 +605,9 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
         const LevelHost& L = P.lv[l - 1];
         if (L.nnodes == 0 || L.ncols == 0) continue;
         launch_build_z(H, l, L.ncols, s);
-        launch_fill_s(H, l, L.nnodes, s);
-        launch_gj_level(H, l, L.nnodes, L.max_m, c.colbuf, c.ipiv, c.d_flags, s);
+        const std::vector<int> nodes(P.gj_list.begin() + P.gj_at[l], P.gj_list.begin() + P.gj_at[l] + P.gj_n[l]);
+        hinv_status st = invert_level(c, l, c.gj_list + P.gj_at[l], nodes, s);
+        if (st != HINV_OK) return st;
     }
     convert_low(c, s);
     HIP_TRY(hipGetLastError());
@@ -549,6 +616,7 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
     HIP_TRY(hipMemcpy(&flags, c.d_flags, sizeof(int), hipMemcpyDeviceToHost));
     if (flags & kFlagNotSPD) return fail(HINV_E_NOT_SPD, "a leaf block of G is not positive definite");
     if (flags & kFlagSingular) return fail(HINV_E_SINGULAR, "a coupling capacitance matrix is singular");
+    if (flags & kFlagBarrier) return fail(HINV_E_DEVICE, "a workgroup team of the build timed out at a barrier");
     return HINV_OK;
 }
 
@@ -648,23 +716,22 @@ hinv_status rebuild_local(hinv_ctx& c, const LocalSet& U, hipStream_t s, int* fl
     const Plan& P = c.P;
     std::vector<int> lst(U.leaves);
     std::vector<int> col_at(P.n_levels + 1, 0), node_at(P.n_levels + 1, 0);
+    std::vector<std::vector<int>> ord(P.n_levels + 1);
     for (int h = 1; h <= P.n_levels; ++h) {
         col_at[h] = (int)lst.size();
         lst.insert(lst.end(), U.cols[h].begin(), U.cols[h].end());
         node_at[h] = (int)lst.size();
-        lst.insert(lst.end(), U.nodes[h].begin(), U.nodes[h].end());
+        ord[h] = order_nodes(P, U.nodes[h]);
+        lst.insert(lst.end(), ord[h].begin(), ord[h].end());
     }
     HIP_TRY(hipMemcpyAsync(c.upd_list, lst.data(), sizeof(int) * lst.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
     launch_leaf_inverse(c.H, c.d_flags, s, c.upd_list, (int)U.leaves.size());
     for (int h = 1; h <= P.n_levels; ++h) {
-        const int nc = (int)U.cols[h].size(), nn = (int)U.nodes[h].size();
+        const int nc = (int)U.cols[h].size();
         if (nc > 0) launch_build_z(c.H, h, nc, s, c.upd_list + col_at[h]);
-        if (nn == 0) continue;
-        int m_max = 0;
-        for (int t : U.nodes[h]) m_max = std::max(m_max, P.node_m[t]);
-        launch_fill_s(c.H, h, nn, s, c.upd_list + node_at[h]);
-        launch_gj_level(c.H, h, nn, m_max, c.colbuf, c.ipiv, c.d_flags, s, c.upd_list + node_at[h]);
+        hinv_status st = invert_level(c, h, c.upd_list + node_at[h], ord[h], s);
+        if (st != HINV_OK) return st;
     }
     convert_low(c, s);
     HIP_TRY(hipGetLastError());
@@ -847,6 +914,7 @@ hinv_status hinv_update_line(hinv_handle h, int32_t a, int32_t b, double delta_g
     int flags = 0;
     st = rebuild_local(c, U, s, &flags);
     if (st != HINV_OK) return st;
+    if (flags & kFlagBarrier) return fail(HINV_E_DEVICE, "a workgroup team of the rebuild timed out at a barrier");
     if (flags & (kFlagNotSPD | kFlagSingular)) {
         // the same local rebuild with the old values restores the old inverse exactly
         st = set_values(old_aa, old_bb, old_ab, old_wa);

@@ -15,6 +15,7 @@
 //     S_t = C_t + U_t^T Z_t (m_t x m_t), stored as S_t^{-1}, column-major.
 //   Then G_t^{-1} x = v0 - Z_t S_t^{-1} U_t^T v0 with v0 = blockdiag(G_c^{-1}) x.
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -380,7 +381,17 @@ enum : int { kFlagNotSPD = 1, kFlagSingular = 2, kFlagNaN = 4, kFlagNoConv = 8, 
 // entries; NULL: every leaf, or every column / node of the level (ncols / nnodes of them).
 void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s, const int* list = nullptr, int count = 0);
 void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s, const int* list = nullptr);
-void launch_fill_s(const HierDev& H, int level, int nnodes, hipStream_t s, const int* list = nullptr);
+void launch_fill_s(const HierDev& H, int level, int nnodes, int m_max, hipStream_t s, const int* list = nullptr);
+// S^{-1} of the listed nodes (order <= kNodeGjMax each): assembly and inversion in one workgroup.
+constexpr int kNodeGjMax = 128;
+void launch_node_inverse(const HierDev& H, const int* list, int count, int* flags, hipStream_t s);
+// S^{-1} of the listed nodes of order kNodeGjMax < m <= kGjTeamMax (m_of: their orders, host):
+// blocked Gauss-Jordan by a team of workgroups per node, cooperative launches.  xb / sync:
+// device exchange doubles and barrier words, at least what gj_team_sizes reports for m_of.
+constexpr int kGjTeamMax = 1024;
+hipError_t launch_gj_team(const HierDev& H, const int* list, const std::vector<int>& m_of, double* xb,
+                          unsigned int* sync, int* flags, hipStream_t s);
+void gj_team_sizes(const std::vector<int>& m_of, int64_t* xb_doubles, int64_t* sync_words);
 void launch_gj_level(const HierDev& H, int level, int nnodes, int m_max, double* colbuf, int* ipiv, int* flags,
                      hipStream_t s, const int* list = nullptr);
 void launch_to_f32(const double* src, float* dst, int64_t count, hipStream_t s);

@@ -12,6 +12,9 @@ data on their paths to the root is recomputed).
   (its coupling column stays with weight 0), after a change to ground and
   after several updates in a row, on top of stored rank-1 changes (1e-11, the
   bar of the rank-1 path), and in FP32 with FP64 refinement (1e-10).
+* On the 11456-bus torus (root capacitance matrix of order 384, inverted by
+  a team of workgroups): sampled solves against the library sparse LU of the
+  changed G (1e-10) and bitwise against a fresh build.
 * Errors: a coupling that G does not have, more conductance removed than the
   line has, a change that makes G indefinite (the previous inverse is then
   restored bit for bit).
@@ -251,4 +254,9 @@ def test_update_11456_root_line_sampled_solves(hv):
     for k in range(4):
         ref = solve(B[k])
         assert np.abs(X[k] - ref).max() / np.abs(ref).max() <= 1e-10
+    # the root's 384-column capacitance inverse is rebuilt by a team of workgroups: same bits as a fresh build
+    rp, ci, cv = hv.network_csr(net)
+    F = hv.Hierarchy(rp, ci, _changed_csr(rp, ci, cv, a, b, dg), net.parent, net.bus_leaf, max_nrhs=4)
+    assert np.array_equal(F.solve(torch.tensor(B, device="cuda")).cpu().numpy(), X)
+    F.close()
     H.close()
