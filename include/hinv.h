@@ -81,8 +81,10 @@ typedef struct {
 
 typedef struct {
     int32_t prec;          /* hinv_precision of the per-step apply */
-    double rel_tol;        /* refinement stop: ||dv||_inf <= rel_tol * ||v||_inf (mixed precision only) */
-    int32_t max_refine;    /* refinement iterations after the first apply (mixed precision only) */
+    double rel_tol;        /* refinement stop: ||dv||_inf <= rel_tol * ||v||_inf (mixed precision or
+                              HINV_COUPLING_PAPER only) */
+    int32_t max_refine;    /* refinement iterations after the first apply (mixed precision or
+                              HINV_COUPLING_PAPER only) */
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
     int32_t warm_start;    /* EMT, mixed precision: refine from the previous step's v instead of P b */
@@ -99,7 +101,16 @@ typedef struct {
                               owners of their columns with a barrier per exchange (trees too large
                               for 3).  Engines 3-5 run exactly max_refine (+1 when warm-started)
                               corrections per step in mixed precision */
+    int32_t coupling;      /* hinv_coupling: HINV_COUPLING_EXACT stores the exact inverse;
+                              HINV_COUPLING_PAPER stores the paper's approximation (Algorithm 1 as
+                              printed: every capacitance inverse S^{-1} replaced by C, i.e. each
+                              node's off-diagonal blocks M = -G_i^{-1} H_ij G_j^{-1} of Eq. (8) built
+                              from the children's approximations); hinv_solve then runs max_refine
+                              FP64-residual corrections in any precision.  hinv_build only: the EMT
+                              and serving entry points need the exact inverse (HINV_E_INVALID) */
 } hinv_options;
+
+typedef enum { HINV_COUPLING_EXACT = 0, HINV_COUPLING_PAPER = 1 } hinv_coupling;
 
 typedef struct {
     int64_t n, n_leaves, n_internal, n_levels, n_cols;

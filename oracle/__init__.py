@@ -15,6 +15,12 @@ What is computed, and where the paper defines it:
   (the LU-based solver of the paper's Introduction and Section VI.C) and by an
   explicit inverse built from G X = I.  ``sparse_solver`` is a library sparse
   direct solve (SuperLU) used where the dense inverse does not fit.
+* ``paper_inverse``: the paper's approximate hierarchical inverse G~^{-1}
+  (Section III.A-B, Eq. (3)-(8), Algorithm 1): leaves inverted directly, every
+  internal node's diagonal blocks are its children's approximate inverses and
+  its off-diagonal blocks M = -G~_i^{-1} H_ij G~_j^{-1} (Eq. (8)).  A node with
+  more than two children takes Eq. (8) for every pair of children (for the
+  binary trees of the paper's Section III.B this is Algorithm 1 as printed).
 * ``emt_run``: the time loop of Eq. (1): at step n, G_n v_n = i_in(t_n) + i_his
   with the history currents of the trapezoidal companions.  A lost line is
   handled by full re-assembly and re-factorisation of G (the paper's
@@ -162,6 +168,50 @@ class _LU:
         x = _c(b, np.float64).copy()
         _load().orc_lu_solve(self.n, _dp(self.A), _ip(self.piv), _dp(x))
         return x
+
+
+def paper_inverse(G: np.ndarray, parent: Sequence[int], bus_leaf: Sequence[int]) -> np.ndarray:
+    """The paper's approximate inverse G~^{-1} of G for a partition tree (Section III.A-B, Algorithm 1).
+
+    parent[k]: parent of tree node k (-1 for the root); bus_leaf[a]: the leaf owning bus a.  A leaf's
+    block is inverted directly; an internal node joins its children's approximate inverses as the
+    diagonal blocks (Eq. (4)) and fills the block of children i, j with M_ij = -G~_i^{-1} H_ij G~_j^{-1}
+    (Eq. (8)), H_ij being G's block between the two children's buses (Eq. (3)).  Returned in the
+    caller's bus order.
+    """
+    G = _c(G, np.float64)
+    n = G.shape[0]
+    parent = np.asarray(parent, np.int64)
+    bus_leaf = np.asarray(bus_leaf, np.int64)
+    children = [[] for _ in range(len(parent))]
+    root = -1
+    for t, p in enumerate(parent):
+        if p < 0:
+            root = t
+        else:
+            children[p].append(t)
+
+    def approx(t):
+        if not children[t]:                                  # leaf: direct inversion
+            b = np.nonzero(bus_leaf == t)[0]
+            return b, inverse(G[np.ix_(b, b)])
+        parts = [approx(c) for c in children[t]]
+        sizes = [len(b) for b, _ in parts]
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        buses = np.concatenate([b for b, _ in parts])
+        Gt = np.zeros((len(buses), len(buses)))
+        for i, (bi, Gi) in enumerate(parts):
+            Gt[off[i]:off[i + 1], off[i]:off[i + 1]] = Gi                       # Eq. (4)
+            for j, (bj, Gj) in enumerate(parts):
+                if i != j:
+                    H = G[np.ix_(bi, bj)]                                       # Eq. (3)
+                    Gt[off[i]:off[i + 1], off[j]:off[j + 1]] = -(Gi @ H @ Gj)   # Eq. (8)
+        return buses, Gt
+
+    buses, Gt = approx(root)
+    out = np.zeros((n, n))
+    out[np.ix_(buses, buses)] = Gt
+    return out
 
 
 def sparse_G(net, alive: Optional[np.ndarray] = None):

@@ -521,10 +521,13 @@ hinv_status check_options(const hinv_options* o, int min_nrhs)
     if (o->max_mod_rank < 0 || o->max_mod_rank > kMaxModRank)
         return fail(HINV_E_INVALID, "max_mod_rank %d outside 0..%d", o->max_mod_rank, kMaxModRank);
     if (o->max_nrhs < min_nrhs) return fail(HINV_E_INVALID, "max_nrhs %d < %d", o->max_nrhs, min_nrhs);
-    if (o->prec != HINV_FP64 && (o->max_refine < 0 || o->max_refine > 64))
+    if (o->coupling != HINV_COUPLING_EXACT && o->coupling != HINV_COUPLING_PAPER)
+        return fail(HINV_E_INVALID, "coupling %d unknown", o->coupling);
+    const bool refines = o->prec != HINV_FP64 || o->coupling == HINV_COUPLING_PAPER;
+    if (refines && (o->max_refine < 0 || o->max_refine > 64))
         return fail(HINV_E_INVALID, "max_refine %d outside 0..64", o->max_refine);
     if (o->kernel_mode < 0 || o->kernel_mode > 5) return fail(HINV_E_INVALID, "kernel_mode %d unknown", o->kernel_mode);
-    if (o->prec != HINV_FP64 && !(o->rel_tol >= 0.0)) return fail(HINV_E_INVALID, "rel_tol must be >= 0");
+    if (refines && !(o->rel_tol >= 0.0)) return fail(HINV_E_INVALID, "rel_tol must be >= 0");
     return HINV_OK;
 }
 
@@ -562,6 +565,12 @@ hinv_status invert_level(hinv_ctx& c, int level, const int* d_list, const std::v
         else { ++nl; ml = std::max(ml, m); }
     }
     const int nt = (int)mt.size();
+    if (c.opt.coupling == HINV_COUPLING_PAPER) {      // Algorithm 1 as printed: S^{-1} := C (C^{-1} = C)
+        int m_max = 0;
+        for (int t : nodes) m_max = std::max(m_max, P.node_m[t]);
+        launch_fill_s(c.H, level, (int)nodes.size(), m_max, s, d_list, /*coupling_only=*/true);
+        return HINV_OK;
+    }
     launch_node_inverse(c.H, d_list, ns, c.d_flags, s);
     HIP_TRY(launch_gj_team(c.H, d_list + ns, mt, c.gj_xb, c.gj_sync, c.d_flags, s));
     if (nl > 0) {
@@ -634,7 +643,7 @@ void precond(hinv_ctx& c, int prec, const double* X, double* out, int nrhs, int 
 void solve_new_order(hinv_ctx& c, const double* B, double* V, int nrhs, int set_stride, const int64_t* step,
                      hipStream_t s)
 {
-    if (c.opt.prec == HINV_FP64) {
+    if (c.opt.prec == HINV_FP64 && c.opt.coupling == HINV_COUPLING_EXACT) {
         precond(c, HINV_FP64, B, V, nrhs, set_stride, step, s);
         c.applies += nrhs;
         return;
@@ -1199,6 +1208,7 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
     if (st != HINV_OK) return st;
     st = check_options(o, 1);
     if (st != HINV_OK) return st;
+    if (o->coupling != HINV_COUPLING_EXACT) return fail(HINV_E_INVALID, "EMT stepping needs coupling = HINV_COUPLING_EXACT");
     c.R = std::max(1, o->max_mod_rank);
     st = check_cases(C, N->n_branch, o->max_mod_rank, c.losses);
     if (st != HINV_OK) return st;
@@ -2364,6 +2374,7 @@ hinv_status serve_create(const hinv_options* opt, int32_t max_slots, void* d_ws,
     *out = nullptr;
     hinv_status st = check_options(opt, 1);
     if (st != HINV_OK) return st;
+    if (opt->coupling != HINV_COUPLING_EXACT) return fail(HINV_E_INVALID, "serving needs coupling = HINV_COUPLING_EXACT");
     size_t need = 0;
     st = serve_workspace_size(max_slots, &need);
     if (st != HINV_OK) return st;

@@ -381,7 +381,8 @@ enum : int { kFlagNotSPD = 1, kFlagSingular = 2, kFlagNaN = 4, kFlagNoConv = 8, 
 // entries; NULL: every leaf, or every column / node of the level (ncols / nnodes of them).
 void launch_leaf_inverse(const HierDev& H, int* flags, hipStream_t s, const int* list = nullptr, int count = 0);
 void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s, const int* list = nullptr);
-void launch_fill_s(const HierDev& H, int level, int nnodes, int m_max, hipStream_t s, const int* list = nullptr);
+void launch_fill_s(const HierDev& H, int level, int nnodes, int m_max, hipStream_t s, const int* list = nullptr,
+                   bool coupling_only = false);
 // S^{-1} of the listed nodes (order <= kNodeGjMax each): assembly and inversion in one workgroup.
 constexpr int kNodeGjMax = 128;
 void launch_node_inverse(const HierDev& H, const int* list, int count, int* flags, hipStream_t s);

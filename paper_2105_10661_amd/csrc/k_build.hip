@@ -596,8 +596,9 @@ __global__ __launch_bounds__(kBlock) void k_build_z(HierDev H, int level, const 
 }
 
 // S^T into the S^{-1} slot: slot[q*m + p] = S[p][q], S[p][q] = C[p][q] + w_p Z_q[row_p].
+// coupling_only: C alone (C^{-1} = C, the paper's approximation of S^{-1}).
 // Grid (x: slices of the entries, y: listed nodes).
-__global__ __launch_bounds__(kBlock) void k_fill_s(HierDev H, int level, const int* list)
+__global__ __launch_bounds__(kBlock) void k_fill_s(HierDev H, int level, const int* list, bool coupling_only)
 {
     const int t = list ? list[blockIdx.y] : H.lvl_node[level - 1] + (int)blockIdx.y;
     const int m = H.node_m[t], c0 = H.node_col0[t];
@@ -608,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_s(HierDev H, int level, const i
         double v = (H.col_partner[gp] == gq) ? H.col_sign[gp] : 0.0;
         const int P = H.col_pan[gq];
         const int rp = H.col_row[gp] - H.pan_lo[P];
-        if (rp >= 0 && rp < H.pan_n[P])
+        if (!coupling_only && rp >= 0 && rp < H.pan_n[P])
             v += H.col_w[gp] * H.Z[H.pan_zoff[P] + (int64_t)(gq - H.pan_col0[P]) * H.pan_n[P] + rp];
         S[idx] = v;
     }
@@ -806,12 +807,13 @@ void launch_build_z(const HierDev& H, int level, int ncols, hipStream_t s, const
     hipLaunchKernelGGL(k_build_z, dim3(ncols), dim3(kBlock), lds, s, H, level, list);
 }
 
-void launch_fill_s(const HierDev& H, int level, int nnodes, int m_max, hipStream_t s, const int* list)
+void launch_fill_s(const HierDev& H, int level, int nnodes, int m_max, hipStream_t s, const int* list,
+                   bool coupling_only)
 {
     if (nnodes <= 0 || m_max <= 0) return;
     int gx = (int)(((int64_t)m_max * m_max + kBlock - 1) / kBlock);
     if (gx > 256) gx = 256;
-    hipLaunchKernelGGL(k_fill_s, dim3(gx, nnodes), dim3(kBlock), 0, s, H, level, list);
+    hipLaunchKernelGGL(k_fill_s, dim3(gx, nnodes), dim3(kBlock), 0, s, H, level, list, coupling_only);
 }
 
 void launch_node_inverse(const HierDev& H, const int* list, int count, int* flags, hipStream_t s)

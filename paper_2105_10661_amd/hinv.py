@@ -49,7 +49,10 @@ class _Tree(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
                 ("max_mod_rank", ctypes.c_int32), ("max_nrhs", ctypes.c_int32), ("warm_start", ctypes.c_int32),
-                ("kernel_mode", ctypes.c_int32)]
+                ("kernel_mode", ctypes.c_int32), ("coupling", ctypes.c_int32)]
+
+
+COUPLINGS = {"exact": 0, "paper": 1}
 
 
 class _Info(ctypes.Structure):
@@ -145,13 +148,16 @@ def _stream(torch_stream=None) -> int:
 KERNEL_MODES = {"auto": 0, "per_kernel": 1, "fused": 2, "team": 3, "panel": 4, "level": 5}
 
 
-def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs, warm_start=False, kernel_mode="auto") -> _Options:
+def _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs, warm_start=False, kernel_mode="auto",
+             coupling="exact") -> _Options:
     if isinstance(prec, str):
         prec = PRECISIONS[prec]
     if isinstance(kernel_mode, str):
         kernel_mode = KERNEL_MODES[kernel_mode]
+    if isinstance(coupling, str):
+        coupling = COUPLINGS[coupling]
     return _Options(int(prec), float(rel_tol), int(max_refine), int(max_mod_rank), int(max_nrhs),
-                    int(bool(warm_start)), int(kernel_mode))
+                    int(bool(warm_start)), int(kernel_mode), int(coupling))
 
 
 class _NetArrays:
@@ -199,7 +205,7 @@ class Hierarchy:
     """Exact hierarchical inverse of a symmetric G (hinv_build / hinv_solve / hinv_modify_line)."""
 
     def __init__(self, row_ptr, col_idx, val, parent, bus_leaf, prec="fp64", rel_tol=1e-9, max_refine=2,
-                 max_mod_rank=4, max_nrhs=1, device="cuda"):
+                 max_mod_rank=4, max_nrhs=1, device="cuda", coupling="exact"):
         import torch
         self._lib = load()
         self.device = torch.device(device)
@@ -209,7 +215,7 @@ class Hierarchy:
         self.n = len(self._rp) - 1
         self._csr = _CSR(self.n, _ptr(self._rp), _ptr(self._ci), _ptr(self._cv))
         self._tree = _Tree(len(self._parent), _ptr(self._parent), _ptr(self._leaf))
-        self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs)
+        self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, max_nrhs, coupling=coupling)
         nb = ctypes.c_size_t(0)
         _check(self._lib.hinv_workspace_size(ctypes.byref(self._csr), ctypes.byref(self._tree),
                                              ctypes.byref(self._opt), ctypes.byref(nb)), "hinv_workspace_size")

@@ -256,3 +256,102 @@ def test_generator_is_deterministic():
     c = cases.net_ring(8, 3)
     k = 8 * cases.BASE_BRANCHES                 # copies share the topology; tie lines are drawn
     assert not np.array_equal(a.R, c.R) and np.array_equal(a.frm[:k], c.frm[:k])
+
+
+# ---------------------------------------------------------------------------
+# The paper's approximate inverse (Section III.A-B, Algorithm 1)
+
+def _two_leaf_tree(n, split):
+    parent = np.array([-1, 0, 0], np.int32)
+    leaf = np.where(np.arange(n) < split, 1, 2).astype(np.int32)
+    return parent, leaf
+
+
+def test_paper_inverse_two_by_two_closed_form():
+    a, b, d = 3.0, -0.7, 2.5
+    G = np.array([[a, b], [b, d]])
+    parent, leaf = _two_leaf_tree(2, 1)
+    Gt = oracle.paper_inverse(G, parent, leaf)
+    ref = np.array([[1 / a, -b / (a * d)], [-b / (a * d), 1 / d]])
+    assert np.abs(Gt - ref).max() <= 1e-15
+
+
+def test_paper_inverse_zeroes_the_off_diagonal_blocks_of_G_times_it():
+    """Eq. (5)-(6): M is chosen so that G G~^{-1} has zero off-diagonal blocks; the diagonal blocks
+    are I + H M^T and I + H^T M (Eq. (5) with the product written out; the paper prints I + M H^T)."""
+    net = cases.small_network(14, 24, seed=5)
+    G = oracle.assemble_G(net)
+    for split in (5, 7, 9):
+        parent, leaf = _two_leaf_tree(14, split)
+        Gt = oracle.paper_inverse(G, parent, leaf)
+        P = G @ Gt
+        H = G[:split, split:]
+        M = Gt[:split, split:]
+        assert np.abs(P[:split, split:]).max() <= 1e-13
+        assert np.abs(P[split:, :split]).max() <= 1e-13
+        assert np.abs(P[:split, :split] - (np.eye(split) + H @ M.T)).max() <= 1e-13
+        assert np.abs(P[split:, split:] - (np.eye(14 - split) + H.T @ M)).max() <= 1e-13
+        assert np.abs(P - np.eye(14)).max() > 1e-6          # not the exact inverse
+        # the diagonal blocks are the leaves' exact inverses (Eq. (4))
+        assert _relerr(Gt[:split, :split], np.linalg.inv(G[:split, :split])) <= 1e-13
+
+
+def test_paper_inverse_exact_special_cases():
+    net = cases.small_network(12, 18, seed=2)
+    G = oracle.assemble_G(net)
+    # one leaf: direct inversion
+    Gt = oracle.paper_inverse(G, np.array([-1]), np.zeros(12, np.int32))
+    assert _relerr(Gt, np.linalg.inv(G)) <= 1e-13
+    # uncoupled children: block-diagonal G is inverted exactly
+    Gb = G.copy()
+    Gb[:6, 6:] = 0.0
+    Gb[6:, :6] = 0.0
+    parent, leaf = _two_leaf_tree(12, 6)
+    assert _relerr(oracle.paper_inverse(Gb, parent, leaf), np.linalg.inv(Gb)) <= 1e-13
+
+
+def test_paper_inverse_recursion_uses_the_childrens_approximations():
+    """Algorithm 1: a node's diagonal blocks are its children's *approximate* inverses, built the same
+    way on the child's own subtree; brute force on a three-level binary tree."""
+    net = cases.small_network(16, 30, seed=7)
+    G = oracle.assemble_G(net)
+    parent, leaf = cases.threshold_tree(net.pos, 4)
+    Gt = oracle.paper_inverse(G, parent, leaf)
+    kids = [t for t, p in enumerate(parent) if p == 0]
+    assert len(kids) == 2
+    for c in kids:
+        sub = [t for t in range(len(parent)) if _under(parent, t, c)]
+        idx = {t: k for k, t in enumerate(sub)}
+        sp = np.array([-1 if t == c else idx[parent[t]] for t in sub], np.int32)
+        buses = np.nonzero(np.isin(leaf, sub))[0]
+        sl = np.array([idx[leaf[a]] for a in buses], np.int32)
+        Gc = oracle.paper_inverse(G[np.ix_(buses, buses)], sp, sl)
+        assert _relerr(Gt[np.ix_(buses, buses)], Gc) <= 1e-15
+        # and that child's approximation differs from its exact inverse (it has a cut of its own)
+        assert _relerr(Gc, np.linalg.inv(G[np.ix_(buses, buses)])) > 1e-9
+
+
+def _relerr(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _under(parent, t, c):
+    while t >= 0:
+        if t == c:
+            return True
+        t = parent[t]
+    return False
+
+
+def test_paper_inverse_error_falls_with_the_leaf_size():
+    """Section VI.A, Fig. 5: the error of G~^{-1} falls as the leaf threshold grows, and vanishes once
+    one leaf holds the network (trend only; the paper's values are for data not available here)."""
+    net = cases.net_179()
+    G = oracle.assemble_G(net)
+    Gi = np.linalg.inv(G)
+    errs = []
+    for d_th in (4, 16, 64, 179):
+        parent, leaf = cases.threshold_tree(net.pos, d_th)
+        Gt = oracle.paper_inverse(G, parent, leaf)
+        errs.append(np.linalg.norm(Gt - Gi) / np.linalg.norm(Gi))
+    assert errs[0] > errs[1] > errs[2] and errs[3] <= 1e-13
