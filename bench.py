@@ -272,6 +272,73 @@ def study_paper(hinv, torch):
     return {"rows": rows, "paper_values": "Fig. 5: 2.5e-3 (d_th=2) to 1.8e-9 (d_th=74) on the 179-bus WECC data"}
 
 
+def study_sizes(hinv, torch, steps=2000, copies=(1, 2, 4, 6, 8, 10, 12)):
+    """Arrays of 179-bus copies on a ring, up to 2148 buses (Section VI.B, Fig. 6): FLOPs of one network
+    solution and of the build, hierarchical inverse against the sparse Cholesky baseline, and the measured
+    GPU time per solution.
+
+    Single-phase: the EMT step of the automatic engine (`steps` steps after 200 warm-up; history and
+    right-hand side included) against the baseline's triangular solves (200 right-hand sides one after
+    the other in one launch).  Three-phase (three rows per bus, trees of 8 leaves per copy): FLOPs, the
+    baseline's time, and one hinv_solve per right-hand side (one launch per phase, launch-bound).
+    """
+    from paper_2105_10661_amd import cases
+
+    def timed(fn, reps):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / reps
+
+    rng = np.random.default_rng(17)
+    single, three = [], []
+    for k in copies:
+        net = cases.net_ring(k, 2)
+        H = hinv.Hierarchy.from_network(net)
+        hi = H.info()
+        H.close()
+        C = hinv.Chol.from_network(net)
+        ci = C.info()
+        B = torch.tensor(rng.standard_normal((200, net.n_bus)), device="cuda")
+        chol_us = timed(lambda: C.solve(B), 3) * 1e3 / 200
+        C.close()
+        emt = hinv.EMT(net, 1, losses=[[]], prec="fp64")
+        emt.step(200)
+        V = torch.empty((steps, 1, net.n_bus), dtype=torch.float64, device="cuda")
+        emt_us = timed(lambda: emt.step(steps, v_out=V), 1) * 1e3 / steps
+        emt.close()
+        single.append({"copies": k, "n": net.n_bus, "leaves": int(hi["n_leaves"]),
+                       "hinv_apply_flops": hi["apply_flops"], "hinv_build_flops": hi["build_flops"],
+                       "chol_solve_flops": ci["solve_flops"], "chol_factor_flops": ci["factor_flops"],
+                       "chol_nnz_l": int(ci["nnz_l"]), "chol_levels": [int(ci["fwd_levels"]), int(ci["bwd_levels"])],
+                       "hinv_emt_step_us": round(emt_us, 2), "chol_solve_us": round(chol_us, 2)})
+        net3 = cases.net_ring_fine(k, 2)
+        rp, cix, cv = hinv.network3_csr(net3, cases.MUTUAL_RATIO)
+        n3 = 3 * net3.n_bus
+        H = hinv.Hierarchy(rp, cix, cv, net3.parent, cases.phase_rows(net3.bus_leaf), max_nrhs=1)
+        hi = H.info()
+        b = torch.tensor(rng.standard_normal(n3), device="cuda")
+        hinv_us = timed(lambda: H.solve(b), 50) * 1e3
+        H.close()
+        C = hinv.Chol(rp, cix, cv)
+        ci = C.info()
+        B = torch.tensor(rng.standard_normal((100, n3)), device="cuda")
+        chol_us = timed(lambda: C.solve(B), 3) * 1e3 / 100
+        C.close()
+        three.append({"copies": k, "rows": n3, "leaves": int(hi["n_leaves"]), "max_cols": int(hi["max_cols"]),
+                      "hinv_apply_flops": hi["apply_flops"], "hinv_build_flops": hi["build_flops"],
+                      "chol_solve_flops": ci["solve_flops"], "chol_factor_flops": ci["factor_flops"],
+                      "chol_nnz_l": int(ci["nnz_l"]), "chol_levels": [int(ci["fwd_levels"]), int(ci["bwd_levels"])],
+                      "hinv_solve_us": round(hinv_us, 2), "chol_solve_us": round(chol_us, 2)})
+    return {"single_phase": single, "three_phase": three, "mutual_ratio": cases.MUTUAL_RATIO,
+            "paper_values": "Fig. 6b at 2148 buses: LU 5.56e6 FLOPs, fast mat-vec 1.43e6 FLOPs per solution"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +365,9 @@ def main():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="also measure the paper's approximate inverse (Algorithm 1 as printed) against the leaf "
                          "size: error, refinement contraction factor and build time")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="also count FLOPs and time per network solution for arrays of 1..12 copies "
+                         "(single- and three-phase), hierarchical inverse against a sparse Cholesky baseline")
     ap.add_argument("--study-11456", action="store_true",
                     help="also time the 11456-bus torus per storage precision and record error vs corrections")
     args = ap.parse_args()
@@ -441,6 +511,7 @@ def main():
         study = study_11456(hinv, torch, khz)
     upd = study_update(hinv, torch) if args.update_study else None
     paper = study_paper(hinv, torch) if args.paper_sweep else None
+    sizes = study_sizes(hinv, torch) if args.size_sweep else None
     served = None
     if args.serve:
         from paper_2105_10661_amd import serve
@@ -491,6 +562,7 @@ def main():
         "torus_11456": study,
         "line_update": upd,
         "paper_approximation": paper,
+        "size_sweep": sizes,
         "serving": served,
         "stored_entries": entries,
         "roofline": {

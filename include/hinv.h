@@ -116,6 +116,11 @@ typedef struct {
     int64_t n, n_leaves, n_internal, n_levels, n_cols;
     int64_t leaf_entries, z_entries, s_entries;   /* stored FP64 entries of each kind */
     int64_t max_leaf, max_cols;                   /* largest leaf, largest coupling level (2 x cut lines) */
+    double apply_flops;   /* one FP64 apply G^{-1} x: 2 nl^2 per leaf; per node m (gather) + 2 m^2 (S^{-1});
+                             2 pn pm per Z panel */
+    double build_flops;   /* the build: 2 nl^3 per leaf elimination; per Z column the leaf column and the
+                             updates of its ancestors below the node; m^2 per S assembly; 2 m^3 per S
+                             inversion */
 } hinv_info_t;
 
 /* ---- Hierarchical inverse of a conductance matrix ---------------------- */
@@ -190,6 +195,34 @@ hinv_status hinv_sync_status(hinv_handle h);
 hinv_status hinv_get_info(hinv_handle h, hinv_info_t* out);
 hinv_status hinv_destroy(hinv_handle h);
 
+/* ---- Comparison baseline: sparse Cholesky network solution -------------- */
+
+/* Not the paper's method: the sparse direct solution it replaces (the LU-based
+ * solver of the Introduction and Section VI.B; G is SPD, so Cholesky).  The
+ * factorization runs on the host (minimum-degree ordering, elimination tree,
+ * up-looking Cholesky); the two triangular solves run on the GPU, one
+ * workgroup per call, level by level (one barrier per level), x in LDS. */
+typedef struct chol_ctx* chol_handle;
+
+typedef struct {
+    int64_t n, nnz_l;            /* order; stored entries of L (diagonal included) */
+    int64_t fwd_levels, bwd_levels;   /* levels of the forward / backward solve */
+    double solve_flops;          /* per right-hand side: 4 (nnz_l - n) + 2 n */
+    double factor_flops;         /* of the numeric factorization */
+} chol_info_t;
+
+/* Device workspace for G (n <= 16384); factorizes on the host to size it.
+ * Errors: HINV_E_INVALID, HINV_E_NOT_SPD (a pivot <= 0). */
+hinv_status chol_workspace_size(const hinv_csr* G, size_t* bytes);
+/* Factorize G and upload L and the level schedules into d_ws (caller-owned,
+ * >= chol_workspace_size bytes, must outlive the handle).  Synchronises. */
+hinv_status chol_create(const hinv_csr* G, void* d_ws, size_t ws_bytes, void* stream, chol_handle* out);
+/* x = G^{-1} b for nrhs right-hand sides, one after the other in one launch;
+ * column k at offset k*ld, caller's bus order, device FP64.  Asynchronous. */
+hinv_status chol_solve(chol_handle h, const double* d_b, double* d_x, int32_t nrhs, int32_t ld, void* stream);
+hinv_status chol_get_info(chol_handle h, chol_info_t* out);
+hinv_status chol_destroy(chol_handle h);
+
 /* ---- EMT time stepping (Section II, Eq. (1)) ---------------------------- */
 
 /* Network: branch e is a series R[e]-L[e] between buses from[e] and to[e];
@@ -229,6 +262,18 @@ typedef struct {
  * row_ptr == NULL to get *nnz only; otherwise row_ptr [n_bus+1], col_idx and
  * val [*nnz] (host memory, caller-owned) are filled. */
 hinv_status emt_network_csr(const emt_network* net, int32_t* row_ptr, int32_t* col_idx, double* val, int64_t* nnz);
+
+/* The three-phase G of the same network (Section III.A: each bus has three
+ * phases): rows 3a + p, p = 0..2; branch e is a three-phase series R-L with
+ * self inductance L[e] and mutual inductance mutual * L[e] between any two
+ * phases, so its companion is the 3x3 admittance (R I + (2/dt) L_e)^{-1};
+ * shunt 2C/dt on each phase.  0 <= mutual < 0.5 (SPD), else HINV_E_INVALID.
+ * row_ptr [3 n_bus + 1]; otherwise as emt_network_csr.  For hinv_build, a
+ * three-phase tree maps all three rows of a bus to the bus's leaf (a leaf then
+ * holds at most HINV_MAX_LEAF / 3 buses).  The EMT time loop (emt_*) takes
+ * single-phase networks only. */
+hinv_status emt_network3_csr(const emt_network* net, double mutual, int32_t* row_ptr, int32_t* col_idx,
+                             double* val, int64_t* nnz);
 
 hinv_status emt_workspace_size(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
                                const emt_cases* cases, size_t* bytes);

@@ -15,6 +15,8 @@ What is computed, and where the paper defines it:
   (the LU-based solver of the paper's Introduction and Section VI.C) and by an
   explicit inverse built from G X = I.  ``sparse_solver`` is a library sparse
   direct solve (SuperLU) used where the dense inverse does not fit.
+* ``assemble_G3``: the three-phase G (each bus three rows, Section III.A)
+  with the mutual inductance of a line between its phases.
 * ``paper_inverse``: the paper's approximate hierarchical inverse G~^{-1}
   (Section III.A-B, Eq. (3)-(8), Algorithm 1): leaves inverted directly, every
   internal node's diagonal blocks are its children's approximate inverses and
@@ -168,6 +170,30 @@ class _LU:
         x = _c(b, np.float64).copy()
         _load().orc_lu_solve(self.n, _dp(self.A), _ip(self.piv), _dp(x))
         return x
+
+
+def assemble_G3(net, mutual: float) -> np.ndarray:
+    """Dense three-phase nodal conductance matrix (rows 3a + p; Section III.A, each bus has three phases).
+
+    Branch e is a three-phase series R-L: resistance R[e] per phase, self inductance L[e] and mutual
+    inductance mutual * L[e] between any two phases.  Its trapezoidal companion is the 3x3 admittance
+    Y_e = (R I + (2/dt) L_e)^{-1} (one library inverse of the 3x3 matrix), entered as the single-phase
+    conductance is: +Y_e on the two buses' diagonal blocks, -Y_e between them.  Shunt 2C/dt per phase.
+    """
+    n = net.n_bus
+    G = np.zeros((3 * n, 3 * n))
+    for a in range(n):
+        G[3 * a:3 * a + 3, 3 * a:3 * a + 3] += 2.0 * net.C[a] / net.dt * np.eye(3)
+    J = np.ones((3, 3))
+    for e in range(net.n_branch):
+        Le = net.L[e] * ((1.0 - mutual) * np.eye(3) + mutual * J)
+        Y = inverse(net.R[e] * np.eye(3) + (2.0 / net.dt) * Le)
+        a, b = int(net.frm[e]), int(net.to[e])
+        G[3 * a:3 * a + 3, 3 * a:3 * a + 3] += Y
+        G[3 * b:3 * b + 3, 3 * b:3 * b + 3] += Y
+        G[3 * a:3 * a + 3, 3 * b:3 * b + 3] -= Y
+        G[3 * b:3 * b + 3, 3 * a:3 * a + 3] -= Y
+    return G
 
 
 def paper_inverse(G: np.ndarray, parent: Sequence[int], bus_leaf: Sequence[int]) -> np.ndarray:

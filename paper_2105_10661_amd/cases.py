@@ -321,6 +321,20 @@ def net_ring(n_copies: int, seed: int) -> Network:
     return tiled_network(f"{n_copies * BASE_BUSES}-bus ring", 1, n_copies, seed, copy_levels=1)
 
 
+MUTUAL_RATIO = 0.3      # three-phase lines: mutual inductance between phases / self inductance
+
+
+def net_ring_fine(n_copies: int, seed: int) -> Network:
+    """n_copies on a ring (as net_ring) with each copy split into 8 leaves of about 22 buses, so that a
+    three-phase tree (three rows per bus) stays within the leaf limit."""
+    return tiled_network(f"{n_copies * BASE_BUSES}-bus ring, 8 leaves per copy", 1, n_copies, seed, copy_levels=3)
+
+
+def phase_rows(bus_leaf: np.ndarray, phases: int = 3) -> np.ndarray:
+    """Leaf of each row when bus a has rows phases*a .. phases*a + phases - 1."""
+    return np.repeat(np.asarray(bus_leaf, np.int32), phases)
+
+
 def net_torus(rows: int, cols: int, seed: int) -> Network:
     """rows x cols torus of copies; tree: halves -> copies -> rows -> root."""
     return tiled_network(f"{rows * cols * BASE_BUSES}-bus torus", rows, cols, seed, copy_levels=1, torus=True)

@@ -31,6 +31,22 @@ hinv_status fail(hinv_status st, const char* fmt, ...)
     return st;
 }
 
+}  // namespace
+
+// The library's error string, for the other translation units.
+hinv_status hinv::set_error(hinv_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+namespace {
+
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -131,6 +147,12 @@ hinv_status check_csr(const hinv_csr* G)
     }
     return HINV_OK;
 }
+
+}  // namespace
+
+hinv_status hinv::validate_csr(const hinv_csr* G) { return check_csr(G); }
+
+namespace {
 
 hinv_status make_plan(const hinv_csr* G, const hinv_tree* T, Plan& P)
 {
@@ -996,6 +1018,30 @@ hinv_status hinv_get_info(hinv_handle h, hinv_info_t* out)
     out->s_entries = se;
     out->max_leaf = P.max_leaf;
     out->max_cols = P.max_cols;
+    // FLOP counts of the apply and the build, from the plan
+    std::vector<double> node_upd(P.node_lo.size(), 0.0);   // one Woodbury update of a vector at node t
+    double ap = 0.0, bu = 0.0;
+    for (int x : P.leaf_n) { ap += 2.0 * x * x; bu += 2.0 * (double)x * x * x; }
+    for (size_t t = 0; t < P.node_lo.size(); ++t) {
+        const double m = P.node_m[t];
+        double u = m + 2.0 * m * m;
+        for (int pp = P.node_pan0[t]; pp < P.node_pan0[t] + P.node_npan[t]; ++pp) u += 2.0 * P.pan_n[pp] * P.pan_m[pp];
+        node_upd[t] = u;
+        ap += u;
+        bu += m * m + 2.0 * m * m * m;
+    }
+    for (size_t g = 0; g < P.col_row.size(); ++g) {
+        const int l = P.row_leaf[P.col_row[g]];
+        const int h = P.node_level[P.col_node[g]];
+        bu += P.leaf_n[l];
+        for (int k = 0; k < P.anc_stride; ++k) {
+            const int t = P.leaf_anc[(size_t)l * P.anc_stride + k];
+            if (t < 0 || P.node_level[t] >= h) break;
+            bu += node_upd[t];
+        }
+    }
+    out->apply_flops = ap;
+    out->build_flops = bu;
     return HINV_OK;
 }
 
@@ -1121,6 +1167,53 @@ void assemble_csr(const emt_network* N, std::vector<int>& rp, std::vector<int>& 
     for (size_t i = 0; i < t.size(); ++i) {
         if (t[i].r == last_row && ci.back() == t[i].c) {
             cv.back() += t[i].v;          // parallel branches and the diagonal sum up
+        } else {
+            ci.push_back(t[i].c);
+            cv.push_back(t[i].v);
+        }
+        last_row = t[i].r;
+        rp[t[i].r + 1] = (int)ci.size();
+    }
+    for (int r = 0; r < n; ++r)
+        if (rp[r + 1] < rp[r]) rp[r + 1] = rp[r];
+}
+
+// Three-phase G: rows 3a + p; branch e couples the phases of its R-L through mutual inductance
+// mutual * L[e], so its companion is the 3x3 admittance Y = (R I + (2/dt) L [(1 - mu) I + mu J])^{-1},
+// J the all-ones matrix: with alpha = R + (2L/dt)(1 - mu) and beta = (2L/dt) mu,
+// Y = I / alpha - J beta / (alpha (alpha + 3 beta)).  Shunts 2C/dt on each phase.
+void assemble_csr3(const emt_network* N, double mu, std::vector<int>& rp, std::vector<int>& ci,
+                   std::vector<double>& cv)
+{
+    const int n = 3 * N->n_bus;
+    struct T { int r, c; double v; };
+    std::vector<T> t;
+    t.reserve((size_t)n + 36 * (size_t)N->n_branch);
+    for (int a = 0; a < N->n_bus; ++a)
+        for (int p = 0; p < 3; ++p) t.push_back({3 * a + p, 3 * a + p, 2.0 * N->C[a] / N->dt});
+    for (int e = 0; e < N->n_branch; ++e) {
+        const double zl = 2.0 * N->L[e] / N->dt;
+        const double alpha = N->R[e] + zl * (1.0 - mu), beta = zl * mu;
+        const double off = -beta / (alpha * (alpha + 3.0 * beta));
+        const double dia = 1.0 / alpha + off;
+        const int a = N->from[e], b = N->to[e];
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+                const double y = (p == q) ? dia : off;
+                t.push_back({3 * a + p, 3 * a + q, y});
+                t.push_back({3 * b + p, 3 * b + q, y});
+                t.push_back({3 * a + p, 3 * b + q, -y});
+                t.push_back({3 * b + p, 3 * a + q, -y});
+            }
+    }
+    std::stable_sort(t.begin(), t.end(), [](const T& x, const T& y) { return x.r != y.r ? x.r < y.r : x.c < y.c; });
+    rp.assign(n + 1, 0);
+    ci.clear();
+    cv.clear();
+    int last_row = -1;
+    for (size_t i = 0; i < t.size(); ++i) {
+        if (t[i].r == last_row && ci.back() == t[i].c) {
+            cv.back() += t[i].v;
         } else {
             ci.push_back(t[i].c);
             cv.push_back(t[i].v);
@@ -2050,6 +2143,25 @@ hinv_status emt_network_csr(const emt_network* net, int32_t* row_ptr, int32_t* c
     std::vector<int> rp, ci;
     std::vector<double> cv;
     assemble_csr(net, rp, ci, cv);
+    *nnz = (int64_t)ci.size();
+    if (!row_ptr) return HINV_OK;
+    if (!col_idx || !val) return fail(HINV_E_INVALID, "NULL output array");
+    memcpy(row_ptr, rp.data(), sizeof(int) * rp.size());
+    memcpy(col_idx, ci.data(), sizeof(int) * ci.size());
+    memcpy(val, cv.data(), sizeof(double) * cv.size());
+    return HINV_OK;
+}
+
+hinv_status emt_network3_csr(const emt_network* net, double mutual, int32_t* row_ptr, int32_t* col_idx, double* val,
+                             int64_t* nnz)
+{
+    if (!nnz) return fail(HINV_E_INVALID, "nnz is NULL");
+    hinv_status st = check_network(net);
+    if (st != HINV_OK) return st;
+    if (!(mutual >= 0.0 && mutual < 0.5)) return fail(HINV_E_INVALID, "mutual ratio %g outside [0, 0.5)", mutual);
+    std::vector<int> rp, ci;
+    std::vector<double> cv;
+    assemble_csr3(net, mutual, rp, ci, cv);
     *nnz = (int64_t)ci.size();
     if (!row_ptr) return HINV_OK;
     if (!col_idx || !val) return fail(HINV_E_INVALID, "NULL output array");

@@ -376,6 +376,11 @@ struct LevelHost {
 // Status flag bits written by kernels.
 enum : int { kFlagNotSPD = 1, kFlagSingular = 2, kFlagNaN = 4, kFlagNoConv = 8, kFlagBarrier = 16, kFlagTeamRow = 32 };
 
+// The library's error string (hinv_last_error); returns st.
+hinv_status set_error(hinv_status st, const char* fmt, ...);
+// Symmetric CSR with sorted columns, finite values and a positive diagonal (else INVALID / NOT_SPD).
+hinv_status validate_csr(const hinv_csr* G);
+
 // ---------------- kernel launchers (k_build.hip / k_apply.hip / k_emt.hip)
 // Builders of the stored inverse.  list (device): the leaves / columns / nodes to (re)build, count
 // entries; NULL: every leaf, or every column / node of the level (ncols / nnodes of them).

@@ -23,11 +23,12 @@ STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "
           6: "NO_CONVERGENCE", 7: "RANK_LIMIT", 8: "SINGULAR"}
 
 EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update_line", "hinv_solve", "hinv_sync_status",
-           "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_workspace_size", "emt_create",
+           "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_network3_csr", "emt_workspace_size", "emt_create",
            "emt_step", "emt_lose_line", "emt_sync_status", "emt_get_step", "emt_get_stats", "emt_set_step_clock",
            "emt_destroy",
            "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
-           "serve_step", "serve_active", "serve_destroy", "hinv_last_error")
+           "serve_step", "serve_active", "serve_destroy", "chol_workspace_size", "chol_create", "chol_solve",
+           "chol_get_info", "chol_destroy", "hinv_last_error")
 
 
 class HinvError(RuntimeError):
@@ -57,11 +58,17 @@ COUPLINGS = {"exact": 0, "paper": 1}
 
 class _Info(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_leaves", "n_internal", "n_levels", "n_cols", "leaf_entries",
-                                             "z_entries", "s_entries", "max_leaf", "max_cols")]
+                                             "z_entries", "s_entries", "max_leaf", "max_cols")] + \
+               [("apply_flops", ctypes.c_double), ("build_flops", ctypes.c_double)]
 
 
 class _UpdateInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("lca_level", "leaves", "columns", "nodes")]
+
+
+class _CholInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz_l", ctypes.c_int64), ("fwd_levels", ctypes.c_int64),
+                ("bwd_levels", ctypes.c_int64), ("solve_flops", ctypes.c_double), ("factor_flops", ctypes.c_double)]
 
 
 class _Network(ctypes.Structure):
@@ -92,12 +99,18 @@ def load() -> ctypes.CDLL:
         "hinv_workspace_size": [P, P, P, P],
         "hinv_build": [P, P, P, P, ctypes.c_size_t, P, P],
         "hinv_modify_line": [P, i32, i32, d, P],
+        "chol_workspace_size": [P, P],
+        "chol_create": [P, P, ctypes.c_size_t, P, P],
+        "chol_solve": [P, P, P, i32, i32, P],
+        "chol_get_info": [P, P],
+        "chol_destroy": [P],
         "hinv_update_line": [P, i32, i32, d, P, P],
         "hinv_solve": [P, P, P, i32, i32, P],
         "hinv_sync_status": [P],
         "hinv_get_info": [P, P],
         "hinv_destroy": [P],
         "emt_network_csr": [P, P, P, P, P],
+        "emt_network3_csr": [P, d, P, P, P, P],
         "emt_workspace_size": [P, P, P, P, P],
         "emt_create": [P, P, P, P, P, ctypes.c_size_t, P, P],
         "emt_step": [P, i32, P, P, P],
@@ -201,6 +214,21 @@ def network_csr(net) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     return rp, ci, cv
 
 
+def network3_csr(net, mutual: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Three-phase G of the network (rows 3a + p) as assembled by the library (row_ptr, col_idx, val)."""
+    lib = load()
+    na = _NetArrays(net)
+    nnz = ctypes.c_int64(0)
+    _check(lib.emt_network3_csr(ctypes.byref(na.s), float(mutual), None, None, None, ctypes.byref(nnz)),
+           "emt_network3_csr")
+    rp = np.zeros(3 * net.n_bus + 1, np.int32)
+    ci = np.zeros(nnz.value, np.int32)
+    cv = np.zeros(nnz.value, np.float64)
+    _check(lib.emt_network3_csr(ctypes.byref(na.s), float(mutual), _ptr(rp), _ptr(ci), _ptr(cv), ctypes.byref(nnz)),
+           "emt_network3_csr")
+    return rp, ci, cv
+
+
 class Hierarchy:
     """Exact hierarchical inverse of a symmetric G (hinv_build / hinv_solve / hinv_modify_line)."""
 
@@ -291,6 +319,62 @@ def _case_arrays(n_cases: int, losses: Optional[Sequence[Sequence[Tuple[int, int
                 br.append(int(b))
             ptr[k + 1] = len(st)
     return ptr, np.asarray(st, np.int32), np.asarray(br, np.int32)
+
+
+class Chol:
+    """Comparison baseline: sparse Cholesky of G, triangular solves on the GPU (chol_* ABI)."""
+
+    def __init__(self, row_ptr, col_idx, val, device="cuda"):
+        import torch
+        self._lib = load()
+        self.device = torch.device(device)
+        c = np.ascontiguousarray
+        self._rp, self._ci, self._cv = c(row_ptr, np.int32), c(col_idx, np.int32), c(val, np.float64)
+        self.n = len(self._rp) - 1
+        self._csr = _CSR(self.n, _ptr(self._rp), _ptr(self._ci), _ptr(self._cv))
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.chol_workspace_size(ctypes.byref(self._csr), ctypes.byref(nb)), "chol_workspace_size")
+        self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        with torch.cuda.device(self.device):
+            _check(self._lib.chol_create(ctypes.byref(self._csr), _ptr(self._ws), nb.value, _stream(),
+                                         ctypes.byref(h)), "chol_create")
+        self._h = h
+
+    @classmethod
+    def from_network(cls, net, **kw):
+        rp, ci, cv = network_csr(net)
+        return cls(rp, ci, cv, **kw)
+
+    def solve(self, i, out=None):
+        """x = G^{-1} i; i: (n,) or (nrhs, n) float64 device tensor."""
+        import torch
+        x = i.contiguous()
+        squeeze = x.dim() == 1
+        if squeeze:
+            x = x.unsqueeze(0)
+        if x.dtype != torch.float64 or x.device.type != "cuda":
+            raise ValueError("i must be a float64 device tensor")
+        if out is None:
+            out = torch.empty_like(x)
+        _check(self._lib.chol_solve(self._h, _ptr(x), _ptr(out), x.shape[0], self.n, _stream()), "chol_solve")
+        return out[0] if squeeze else out
+
+    def info(self) -> dict:
+        inf = _CholInfo()
+        _check(self._lib.chol_get_info(self._h, ctypes.byref(inf)), "chol_get_info")
+        return {k: getattr(inf, k) for k, _ in _CholInfo._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.chol_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class EMT:

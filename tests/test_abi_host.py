@@ -144,3 +144,40 @@ def test_emt_validation(hv):
     nb2 = hv._NetArrays(bad)
     assert lib.emt_workspace_size(ctypes.byref(nb2.s), ctypes.byref(nb2.tree), ctypes.byref(op), ctypes.byref(cs),
                                   ctypes.byref(nb)) == 1
+
+
+def _chol_ws(hv, rp, ci, cv):
+    lib = hv.load()
+    c = np.ascontiguousarray
+    a = [c(rp, np.int32), c(ci, np.int32), c(cv, np.float64)]
+    csr = hv._CSR(len(a[0]) - 1, hv._ptr(a[0]), hv._ptr(a[1]), hv._ptr(a[2]))
+    nb = ctypes.c_size_t(0)
+    return lib.chol_workspace_size(ctypes.byref(csr), ctypes.byref(nb)), nb.value
+
+
+def test_cholesky_baseline_host_factorization(hv):
+    """The comparison baseline's host factorization: sizes an SPD G, rejects an indefinite one."""
+    net = cases.net_179()
+    rp, ci, cv = hv.network_csr(net)
+    st, nb = _chol_ws(hv, rp, ci, cv)
+    assert st == 0 and nb > 8 * rp[-1]
+    st, _ = _chol_ws(hv, np.array([0, 2, 4]), np.array([0, 1, 0, 1]), np.array([1.0, 2.0, 2.0, 1.0]))
+    assert hv.STATUS[st] == "NOT_SPD"
+    st, _ = _chol_ws(hv, np.array([0, 0]), np.array([], np.int32), np.array([]))
+    assert hv.STATUS[st] == "INVALID"
+
+
+def test_three_phase_G_matches_oracle(hv):
+    """The library's three-phase G (closed-form 3x3 companions) against the oracle's (3x3 inverse)."""
+    net = cases.net_ring_fine(2, 5)
+    rp, ci, cv = hv.network3_csr(net, cases.MUTUAL_RATIO)
+    n = 3 * net.n_bus
+    G = np.zeros((n, n))
+    for r in range(n):
+        G[r, ci[rp[r]:rp[r + 1]]] = cv[rp[r]:rp[r + 1]]
+    ref = oracle.assemble_G3(net, cases.MUTUAL_RATIO)
+    assert np.abs(G - ref).max() <= 1e-14 * np.abs(ref).max()
+    lib = hv.load()
+    na = hv._NetArrays(net)
+    nnz = ctypes.c_int64(0)
+    assert hv.STATUS[lib.emt_network3_csr(ctypes.byref(na.s), 0.5, None, None, None, ctypes.byref(nnz))] == "INVALID"

@@ -355,3 +355,38 @@ def test_paper_inverse_error_falls_with_the_leaf_size():
         Gt = oracle.paper_inverse(G, parent, leaf)
         errs.append(np.linalg.norm(Gt - Gi) / np.linalg.norm(Gi))
     assert errs[0] > errs[1] > errs[2] and errs[3] <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Three-phase G (Section III.A)
+
+def test_G3_without_mutual_coupling_is_three_copies_of_G():
+    net = cases.small_network(9, 14, seed=3)
+    G = oracle.assemble_G(net)
+    G3 = oracle.assemble_G3(net, 0.0)
+    assert _relerr(G3, np.kron(G, np.eye(3))) <= 1e-15
+
+
+def test_G3_structure():
+    net = cases.net_179()
+    G3 = oracle.assemble_G3(net, cases.MUTUAL_RATIO)
+    assert np.abs(G3 - G3.T).max() <= 1e-15 * np.abs(G3).max()        # symmetric up to the 3x3 inverses' rounding
+    shunt = np.repeat(2.0 * net.C / net.dt, 3)
+    assert np.abs(G3.sum(1) - shunt).max() <= 1e-12 * np.abs(G3).max()
+    np.linalg.cholesky(G3)
+    assert (np.abs(G3[0::3, 1::3]) > 0).any()            # phases are coupled
+
+
+def test_G3_two_bus_line_sequence_eigenvalues():
+    """One line between two buses with equal shunts: the eigenvalues of G3 are the shunt conductance
+    (three common modes) and gC + 2/(R + (2L/dt)(1 + 2mu)) (zero sequence), gC + 2/(R + (2L/dt)(1 - mu))
+    (twice: positive and negative sequence)."""
+    R, L, C, dt, mu = 0.8, 2e-3, 3e-6, 5e-5, 0.3
+    net = cases.Network(name="2-bus line", n_bus=2, frm=np.array([0], np.int32), to=np.array([1], np.int32),
+                        R=np.array([R]), L=np.array([L]), C=np.array([C, C]), src_bus=np.zeros(0, np.int32),
+                        src_amp=np.zeros(0), src_phase=np.zeros(0), parent=np.array([-1], np.int32),
+                        bus_leaf=np.zeros(2, np.int32), dt=dt)
+    gc, zl = 2.0 * C / dt, 2.0 * L / dt
+    ref = np.sort([gc] * 3 + [gc + 2.0 / (R + zl * (1 + 2 * mu))] + [gc + 2.0 / (R + zl * (1 - mu))] * 2)
+    ev = np.sort(np.linalg.eigvalsh(oracle.assemble_G3(net, mu)))
+    assert np.abs(ev - ref).max() <= 1e-12 * ref.max()
