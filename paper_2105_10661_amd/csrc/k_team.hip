@@ -334,22 +334,20 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                         const int pm = xpm[x * Hn + hh - 1], pc = xpc[x * Hn + hh - 1];
                         for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
                     }
-                    acc += __shfl_xor(acc, 1);
-                    acc += __shfl_xor(acc, 2);
+                    acc = quad_sum(acc);
                     if (zo >= 0) val -= (double)acc;
                 }
                 if (sub == 0) s[g] = colw[g] * val;
             }
             __syncthreads();
-            // y = S^{-1} s: kSub lanes share each column's dot product (lane shuffles)
+            // y = S^{-1} s: kSub lanes share each column's dot product (quad sums)
             for (int idx = tid; idx < (c1 - c0) * kSub; idx += kTeamThreads) {
                 const int g = c0 + idx / kSub, sub = idx & (kSub - 1);
                 const int m = cm[g], q0 = cc0[g];
                 const TB* Si = sall + cso[g];
                 TA acc = 0;
                 for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * (m + 1)] * (TA)s[q0 + p];
-                acc += __shfl_xor(acc, 1);
-                acc += __shfl_xor(acc, 2);
+                acc = quad_sum(acc);
                 if (sub == 0) y[g] = (double)acc;
             }
             __syncthreads();
@@ -372,8 +370,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                         for (int j = sub; j < pm; j += kSub) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
                     }
                 }
-                acc += __shfl_xor(acc, 1);
-                acc += __shfl_xor(acc, 2);
+                acc = quad_sum(acc);
                 if (zo >= 0) val -= (double)acc;
             }
             if (sub == 0) {

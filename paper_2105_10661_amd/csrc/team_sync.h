@@ -28,6 +28,30 @@ __device__ __forceinline__ double xchg_load(const double* p)
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Value of another lane of the same quad (lanes 4q .. 4q + 3) by a DPP quad permutation: a VALU
+// move, no LDS round trip.  CTRL 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = [2,3,0,1] (lane ^ 2).
+template <int CTRL>
+__device__ __forceinline__ double quad_mov(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float quad_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the four lanes of a quad, all four active: (a + a[^1]) + (...)[^2], every lane gets it.
+template <typename T>
+__device__ __forceinline__ T quad_sum(T a)
+{
+    a += quad_mov<0xB1>(a);
+    a += quad_mov<0x4E>(a);
+    return a;
+}
+
 // flags: the team's T flags; me: this workgroup's flag; ctl: one int of LDS.
 __device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned int epoch, int* errflags, int* ctl)
 {
