@@ -289,6 +289,8 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     double worst = 0.0;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wavefront
+    const int ns = sptr[nl];
+    int64_t sn_step = -1;
 
     // one application of the stored inverse (with the active line changes):
     // out (own rows), outx (X rows) from xin (own rows)
@@ -310,7 +312,14 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             out[r] = val;
             xchg_store(&X0[lo + r], val);
         }
-        if (!team_barrier(T.sync, w, T.T, ++epoch, P.flags, ctl)) return false;
+        team_arrive(T.sync, w, ++epoch);
+        if (sn_step >= 0) {      // source injections of the next step, by the last wavefront, while wavefront 0 polls
+            if (tid >= kTeamThreads - 64)
+                for (int q = tid - (kTeamThreads - 64); q < ns; q += 64)
+                    sn[q] = samp[q] * sin(E.omega * ((double)sn_step * E.dt) + sph[q]);
+            sn_step = -1;
+        }
+        if (!team_wait(T.sync, T.T, epoch, P.flags, ctl)) return false;
         if (want_vm) {   // the team's largest |v| (vg was cleared before the barrier)
             for (int i = tid; i < T.T; i += kTeamThreads)
                 atomicMax(vg, (unsigned long long)__double_as_longlong(xchg_load(&T.VM[(int64_t)par * T.T + i])));
@@ -462,9 +471,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     };
 
     int64_t applies = 0;
-    const int ns = sptr[nl];
     for (int it = 0; it < P.n_steps && alive; ++it) {
         const int64_t step = P.step0 + it;
+        sn_step = step + 1;      // the step's first apply computes the next step's source injections
         int ract = 0;
         while (ract < cnt && (int64_t)mact[ract] <= step) ++ract;
         if (!MIXED) {
@@ -496,10 +505,6 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 hv = bg[q] * vft + bal[q] * ie;
             }
             hn[q] = hv;
-        }
-        if (tid >= kTeamThreads - 64) {      // source injections of step+1, by the last wavefront
-            for (int q = tid - (kTeamThreads - 64); q < ns; q += 64)
-                sn[q] = samp[q] * sin(E.omega * ((double)(step + 1) * E.dt) + sph[q]);
         }
         __syncthreads();
         const int64_t j = step - P.step0;

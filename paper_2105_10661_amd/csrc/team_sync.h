@@ -52,12 +52,20 @@ __device__ __forceinline__ T quad_sum(T a)
     return a;
 }
 
-// flags: the team's T flags; me: this workgroup's flag; ctl: one int of LDS.
-__device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned int epoch, int* errflags, int* ctl)
+// The barrier in two halves, so that a workgroup can do work that no other workgroup waits for
+// while its wavefront 0 polls.  team_arrive: this workgroup's stores have completed, then its flag
+// is raised (flags: the team's T flags; me: this workgroup's flag).
+__device__ inline void team_arrive(unsigned int* flags, int me, unsigned int epoch)
 {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // gfx9 encoding of vmcnt(0): this wave's stores have completed
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(&flags[me], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// team_wait: wavefront 0 polls the team's flags (bounded), then the workgroup synchronises; ctl: one
+// int of LDS.  Returns false in every thread on time-out.
+__device__ inline bool team_wait(unsigned int* flags, int T, unsigned int epoch, int* errflags, int* ctl)
+{
     if (threadIdx.x < 64) {
         int ok = 1;
         int spins = 0;
@@ -79,6 +87,12 @@ __device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned
     }
     __syncthreads();
     return ctl[0] != 0;
+}
+
+__device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned int epoch, int* errflags, int* ctl)
+{
+    team_arrive(flags, me, epoch);
+    return team_wait(flags, T, epoch, errflags, ctl);
 }
 
 }  // namespace hinv
