@@ -291,6 +291,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wavefront
     const int ns = sptr[nl];
     int64_t sn_step = -1;
+    const int my_perm = tid < nl ? E.perm[lo + tid] : 0;   // caller's index of this thread's row (records)
 
     // one application of the stored inverse (with the active line changes):
     // out (own rows), outx (X rows) from xin (own rows)
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             const double hcn = -gC[r] * va - ic;
             hC[r] = hcn;
             bn -= hcn;
-            const int64_t o = j * (int64_t)n + E.perm[lo + r];
+            const int64_t o = j * (int64_t)n + (r == tid ? my_perm : E.perm[lo + r]);
             if (P.v_rec) P.v_rec[o] = va;
             if (P.b_rec) P.b_rec[o] = b[r];
             b[r] = bn;
