@@ -25,6 +25,7 @@ constexpr int kTeamThreads = 1024;
 constexpr int kTeamWaves = kTeamThreads / 64;
 constexpr int kGemvChunks = kTeamWaves / 2;   // leaf GEMV: 2 row halves (lanes) x 8 column chunks
 constexpr int kSub = 4;                 // lanes per coupling-column dot product
+static_assert(kMaxLeaf <= kTeamThreads, "one own row per thread in the right-hand side");
 
 template <typename TB>
 struct TAcc { using T = float; };
@@ -509,7 +510,8 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         }
         __syncthreads();
         const int64_t j = step - P.step0;
-        for (int r = tid; r < nl; r += kTeamThreads) {
+        if (tid < nl) {          // one own row per thread
+            const int r = tid;
             const double va = v[r];
             double bn = 0.0;
             for (int q = sptr[r]; q < sptr[r + 1]; ++q) bn += sn[q];
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             const double hcn = -gC[r] * va - ic;
             hC[r] = hcn;
             bn -= hcn;
-            const int64_t o = j * (int64_t)n + (r == tid ? my_perm : E.perm[lo + r]);
+            const int64_t o = j * (int64_t)n + my_perm;
             if (P.v_rec) P.v_rec[o] = va;
             if (P.b_rec) P.b_rec[o] = b[r];
             b[r] = bn;
