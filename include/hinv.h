@@ -23,8 +23,13 @@
  * This library keeps that structure but stores the exact inverse: at each
  * tree node the coupling level is a Woodbury capacitance matrix
  * S = C + U^T B^{-1} U over the cut lines (the paper's M of Eq. (8)-(9) is
- * this form with S truncated to C).  A line change is applied as a
- * Sherman-Morrison-Woodbury low-rank correction of the stored inverse.
+ * this form with S truncated to C, available as hinv_options.coupling =
+ * HINV_COUPLING_PAPER).  A line change is applied either as a
+ * Sherman-Morrison-Woodbury low-rank correction of the stored inverse
+ * (hinv_modify_line, and the line losses of the EMT time loop) or as a local
+ * rebuild of the stored inverse itself (hinv_update_line, Algorithm 2 made
+ * exact).  emt_network3_csr gives the three-phase G of a network; chol_* is a
+ * sparse Cholesky network solution kept as a comparison baseline.
  */
 #ifndef HINV_H
 #define HINV_H
@@ -192,7 +197,9 @@ hinv_status hinv_solve(hinv_handle h, const double* d_i, double* d_v, int32_t nr
  * Clears the flags. */
 hinv_status hinv_sync_status(hinv_handle h);
 
+/* Sizes and FLOP counts of the stored inverse (host memory out). */
 hinv_status hinv_get_info(hinv_handle h, hinv_info_t* out);
+/* Frees the handle (the caller still owns the workspace); NULL is accepted. */
 hinv_status hinv_destroy(hinv_handle h);
 
 /* ---- Comparison baseline: sparse Cholesky network solution -------------- */
