@@ -444,6 +444,8 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     double worst = 0.0;
     unsigned int* tflags = D.sync + (int64_t)team * T;
     const int NXs = D.NX;
+    const int ns = sptr[nl];
+    int64_t sn_step = -1;    // the step whose source injections the next apply computes (-1: none)
 
     // value of a combined row index (own row or X row) in the pair (own, X)
     auto cval = [&](const double* own, const double* xr, int comb, int c) -> double {
@@ -484,7 +486,14 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 }
             }
         }
-        if (!team_barrier(tflags, l, T, ++epoch, P.flags, ctl)) return false;
+        team_arrive(tflags, l, ++epoch);
+        if (sn_step >= 0) {      // source injections of the next step, by the last wavefront, while wavefront 0 polls
+            if (tid >= kPThreads - 64)
+                for (int q = tid - (kPThreads - 64); q < ns; q += 64)
+                    sn[q] = samp[q] * sin(E.omega * ((double)sn_step * E.dt) + sph[q]);
+            sn_step = -1;
+        }
+        if (!team_wait(tflags, T, epoch, P.flags, ctl)) return false;
         if (want_vm) {   // the team's largest |v| per case (vg was cleared before the barrier)
             for (int i = tid; i < T * kPB; i += kPThreads)
                 atomicMax(&vg[i & 15], (unsigned long long)__double_as_longlong(xchg_load(&VMp[i])));
@@ -736,9 +745,9 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     };
 
     int64_t applies = 0;
-    const int ns = sptr[nl];
     for (int it = 0; it < P.n_steps && alive; ++it) {
         const int64_t step = P.step0 + it;
+        sn_step = step + 1;      // the step's first apply computes the next step's source injections
         const int64_t jr = step - P.rec_step0;
         const bool rec = jr >= 0 && jr < P.rec_cap;
         if (!MIXED && rec && P.b_rec) {                 // b is overwritten by v below
@@ -785,7 +794,6 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             }
             h[i] = hv;
         }
-        for (int q = tid; q < ns; q += kPThreads) sn[q] = samp[q] * sin(E.omega * ((double)(step + 1) * E.dt) + sph[q]);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kPRowItems; ++k) {
