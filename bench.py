@@ -273,7 +273,7 @@ def study_paper(hinv, torch):
 
 
 def study_sizes(hinv, torch, steps=2000, copies=(1, 2, 4, 6, 8, 10, 12)):
-    """Arrays of 179-bus copies on a ring, up to 2148 buses (Section VI.B, Fig. 6): FLOPs of one network
+    """Arrays of 179-bus copies on a ring, up to 2148 buses (Section V.B, Fig. 6): FLOPs of one network
     solution and of the build, hierarchical inverse against the sparse Cholesky baseline, and the measured
     GPU time per solution.
 

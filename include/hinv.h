@@ -205,7 +205,7 @@ hinv_status hinv_destroy(hinv_handle h);
 /* ---- Comparison baseline: sparse Cholesky network solution -------------- */
 
 /* Not the paper's method: the sparse direct solution it replaces (the LU-based
- * solver of the Introduction and Section VI.B; G is SPD, so Cholesky).  The
+ * solver of the Introduction and Section V.B; G is SPD, so Cholesky).  The
  * factorization runs on the host (minimum-degree ordering, elimination tree,
  * up-looking Cholesky); the two triangular solves run on the GPU, one
  * workgroup per call, level by level (one barrier per level), x in LDS. */
@@ -302,6 +302,22 @@ hinv_status emt_step(emt_handle c, int32_t n_steps, double* d_v_record, double* 
 /* Lose branch `branch` of case `case_idx` from the next step on (Algorithm 2's
  * situation, handled by a rank-1 SMW correction).  Synchronises the stream. */
 hinv_status emt_lose_line(emt_handle c, int32_t case_idx, int32_t branch, void* stream);
+
+/* Change the network of every case from the next step on by a memoryless
+ * conductance delta_g between buses a and b (b = -1: between a and ground),
+ * G <- G + delta_g (e_a - e_b)(e_a - e_b)^T: a fault switched on (delta_g =
+ * 1/R_fault) or off again (its negative), the scenario of Section V.C.  The
+ * stored inverse is rebuilt locally as by hinv_update_line (Section IV,
+ * Algorithm 2 made exact: the result equals a fresh build of the new G), then
+ * each case's line losses are re-applied to the new base and the engine's
+ * per-workgroup tables take G's new values.  The element carries no history
+ * current, so the state of the time loop is kept as it is.  Same argument
+ * rules and errors as hinv_update_line (a and b in the network's bus order);
+ * if the change, or a case's losses on top of it, makes G indefinite or
+ * singular, nothing changes and HINV_E_NOT_SPD / HINV_E_SINGULAR is returned.
+ * `out` (may be NULL) receives what was rebuilt.  Synchronises the stream. */
+hinv_status emt_update_line(emt_handle c, int32_t a, int32_t b, double delta_g, void* stream,
+                            hinv_update_info* out);
 
 /* Device-side status of the steps run since the last call (call after the
  * stream is idle; clears it).  HINV_E_NO_CONVERGENCE: in mixed precision a

@@ -12,7 +12,7 @@ What is computed, and where the paper defines it:
   conductance 2C/dt to ground (the paper only says "discretized by numerical
   integration"; trapezoidal is the EMTP standard it cites).
 * ``solve`` / ``inverse``: v = G^{-1} i (Eq. (2)) by LU with partial pivoting
-  (the LU-based solver of the paper's Introduction and Section VI.C) and by an
+  (the LU-based solver of the paper's Introduction and Section V.C) and by an
   explicit inverse built from G X = I.  ``sparse_solver`` is a library sparse
   direct solve (SuperLU) used where the dense inverse does not fit.
 * ``assemble_G3``: the three-phase G (each bus three rows, Section III.A)
@@ -267,13 +267,20 @@ def source_current(net, t: float) -> np.ndarray:
 
 
 def emt_run(net, n_steps: int, loss_steps: Sequence[int] = (), loss_branches: Sequence[int] = (),
-            solver: str = "inv", record_b: bool = False, record_steps: Optional[np.ndarray] = None):
+            solver: str = "inv", record_b: bool = False, record_steps: Optional[np.ndarray] = None,
+            changes: Sequence = ()):
     """Node voltages v_1..v_N of the trapezoidal EMT time loop (Eq. (1)).
 
     solver: "inv" (explicit inverse times the current vector), "lu" (LU solve
     each step) or "sparse" (library sparse LU).  Returns (V, B): V[k] is the
     voltage at the k-th recorded step (steps 1..n_steps, or ``record_steps``),
     B the right-hand side i_in + i_his of the same steps (or None).
+
+    changes: (step, a, b, dg) memoryless conductances (a fault of resistance
+    1/dg between buses a and b, b = -1 for ground; a negative dg removes one)
+    in force from that step on: G_on = G_pre + dg (e_a - e_b)(e_a - e_b)^T,
+    the fault-on stage of Section IV.A.  A resistor has no history current, so
+    the right-hand side is the same with or without it.
     """
     n, dt = net.n_bus, net.dt
     fr, to = net.frm.astype(np.int64), net.to.astype(np.int64)
@@ -289,21 +296,34 @@ def emt_run(net, n_steps: int, loss_steps: Sequence[int] = (), loss_branches: Se
     B = np.zeros((len(rec), n), np.float64) if record_b else None
     h = np.zeros(net.n_branch)                        # branch history currents
     hC = -source_current(net, 0.0)                    # shunt history, KCL-consistent start
+    changes = [(int(s), int(a), int(b), float(d)) for s, a, b, d in changes]
+    if changes and solver == "sparse":
+        raise ValueError("changes need the dense solvers")
     alive_prev = None
+    on_prev = None
     apply = None
     for step in range(1, n_steps + 1):
         alive = dead_from > step
-        if alive_prev is None or not np.array_equal(alive, alive_prev):
+        on = [k for k, c in enumerate(changes) if c[0] <= step]
+        if alive_prev is None or not np.array_equal(alive, alive_prev) or on != on_prev:
+            G = None if solver == "sparse" else assemble_G(net, alive)
+            for k in on:
+                _, a, b, dg = changes[k]
+                G[a, a] += dg
+                if b >= 0:
+                    G[b, b] += dg
+                    G[a, b] -= dg
+                    G[b, a] -= dg
             if solver == "inv":
-                Ginv = inverse(assemble_G(net, alive))
+                Ginv = inverse(G)
                 apply = lambda x, M=Ginv: matvec(M, x)
             elif solver == "lu":
-                apply = _LU(assemble_G(net, alive))
+                apply = _LU(G)
             elif solver == "sparse":
                 apply = sparse_solver(net, alive)
             else:
                 raise ValueError(solver)
-            alive_prev = alive
+            alive_prev, on_prev = alive, on
         h = np.where(alive, h, 0.0)
         b = source_current(net, step * dt) - (np.bincount(fr, h, n) - np.bincount(to, h, n)) - hC
         v = apply(b)

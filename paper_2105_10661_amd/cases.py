@@ -6,7 +6,7 @@ holds none of the solver's arithmetic (no conductances, no companion models,
 no inverses), so both the FP64 oracle and the GPU library can be fed from it.
 
 The paper's case studies use copies of a 179-bus system tiled into arrays
-(Section VI, "CPU time in terms of FLOPS").  That data set is not available,
+(Section V, "CPU time in terms of FLOPS").  That data set is not available,
 so a geometric random graph with the same bus and branch counts stands in for
 it: buses at uniform positions in the unit square, a Euclidean minimum
 spanning tree, then the shortest non-tree links among each bus's six nearest

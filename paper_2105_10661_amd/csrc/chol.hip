@@ -1,5 +1,5 @@
 // Comparison baseline, not the paper's method: the sparse direct network solution that the
-// inverse-based solver replaces (the LU-based solver of the paper's Introduction and Section VI.B;
+// inverse-based solver replaces (the LU-based solver of the paper's Introduction and Section V.B;
 // G is SPD, so the factorization is Cholesky, G = P^T L L^T P).
 //
 //  host   : minimum-degree ordering on the graph of G, elimination tree, up-looking numeric

@@ -789,6 +789,120 @@ hinv_status plan_and_size(const hinv_csr* G, const hinv_tree* T, const hinv_opti
     return HINV_OK;
 }
 
+// One value change of G between buses a and b (b = -1: a to ground) and the
+// entries and old values it touched, so that it can be undone bit for bit.
+struct LineEdit {
+    int e_aa = -1, e_bb = -1, e_ab = -1, e_ba = -1, ca = -1, cb = -1;
+    double aa = 0.0, bb = 0.0, ab = 0.0, w = 0.0;    // values before the change
+    LocalSet U;
+};
+
+hinv_status set_line_values(hinv_ctx& c, const LineEdit& E, double aa, double bb, double ab, double w, hipStream_t s)
+{
+    Plan& P = c.P;
+    P.cv[E.e_aa] = aa;
+    HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + E.e_aa), &P.cv[E.e_aa], sizeof(double), hipMemcpyHostToDevice, s));
+    if (E.e_bb >= 0) {
+        P.cv[E.e_bb] = bb;
+        HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + E.e_bb), &P.cv[E.e_bb], sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (E.e_ab >= 0) {
+        P.cv[E.e_ab] = ab; P.cv[E.e_ba] = ab;
+        HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + E.e_ab), &P.cv[E.e_ab], sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + E.e_ba), &P.cv[E.e_ba], sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (E.ca >= 0) {
+        P.col_w[E.ca] = w; P.col_w[E.cb] = w;
+        HIP_TRY(hipMemcpyAsync((void*)(c.H.col_w + E.ca), &P.col_w[E.ca], sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync((void*)(c.H.col_w + E.cb), &P.col_w[E.cb], sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    return HINV_OK;
+}
+
+// Restore the values an edit_line changed and rebuild the same local set:
+// the inverse is then bitwise the one before the change.
+hinv_status undo_line(hinv_ctx& c, const LineEdit& E, hipStream_t s)
+{
+    hinv_status st = set_line_values(c, E, E.aa, E.bb, E.ab, E.w, s);
+    if (st != HINV_OK) return st;
+    int back = 0;
+    st = rebuild_local(c, E.U, s, &back);
+    if (st != HINV_OK) return st;
+    HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (back & (kFlagNotSPD | kFlagSingular)) return fail(HINV_E_DEVICE, "restoring the inverse failed");
+    return HINV_OK;
+}
+
+// Algorithm 2 made exact: change G by delta_g (e_a - e_b)(e_a - e_b)^T and
+// rebuild the two leaves and the paths up to their lowest common ancestor.
+// On an indefinite or singular result the old inverse is restored.
+hinv_status edit_line(hinv_ctx& c, int32_t a, int32_t b, double delta_g, hipStream_t s, LineEdit& E)
+{
+    Plan& P = c.P;
+    const int n = P.n;
+    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return fail(HINV_E_INVALID, "bad buses (%d, %d)", a, b);
+    if (!isfinite(delta_g) || delta_g == 0.0) return fail(HINV_E_INVALID, "delta_g must be finite and non-zero");
+    const int ra = P.iperm[a], rb = b >= 0 ? P.iperm[b] : -1;
+    auto entry = [&](int r, int col) {
+        for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
+            if (P.ci[e] == col) return e;
+        return -1;
+    };
+    E.e_aa = entry(ra, ra);
+    E.e_bb = rb >= 0 ? entry(rb, rb) : -1;
+    E.e_ab = rb >= 0 ? entry(ra, rb) : -1;
+    E.e_ba = rb >= 0 ? entry(rb, ra) : -1;
+    if (rb >= 0 && (E.e_ab < 0 || E.e_ba < 0))
+        return fail(HINV_E_NO_SUCH_LINE, "G has no entry between buses %d and %d; a new coupling needs a rebuild", a, b);
+    const int la = P.row_leaf[ra], lb = rb >= 0 ? P.row_leaf[rb] : la;
+    // the coupling column pair of a line between two leaves
+    E.ca = E.cb = -1;
+    if (la != lb) {
+        for (int g = 0; g < (int)P.col_row.size() && E.ca < 0; ++g)
+            if (P.col_row[g] == ra && P.col_row[P.col_partner[g]] == rb) { E.ca = g; E.cb = P.col_partner[g]; }
+        if (E.ca < 0)
+            return fail(HINV_E_NO_SUCH_LINE, "buses %d and %d are in different leaves and G has no line between "
+                        "them; a new coupling needs a rebuild", a, b);
+    }
+    E.aa = P.cv[E.e_aa];
+    E.bb = E.e_bb >= 0 ? P.cv[E.e_bb] : 0.0;
+    E.ab = E.e_ab >= 0 ? P.cv[E.e_ab] : 0.0;
+    E.w = E.ca >= 0 ? P.col_w[E.ca] : 0.0;
+    double new_ab = E.ab - delta_g;
+    if (E.e_ab >= 0) {
+        if (fabs(new_ab) <= 1e-12 * fabs(delta_g)) new_ab = 0.0;
+        if (new_ab > 0.0)
+            return fail(HINV_E_NO_SUCH_LINE, "no line of conductance %g between %d and %d", -delta_g, a, b);
+    }
+    E.U = local_set(P, la, lb);
+    hinv_status st = set_line_values(c, E, E.aa + delta_g, E.bb + delta_g, new_ab, sqrt(fabs(new_ab)), s);
+    if (st != HINV_OK) return st;
+    int flags = 0;
+    st = rebuild_local(c, E.U, s, &flags);
+    if (st != HINV_OK) return st;
+    if (flags & kFlagBarrier) return fail(HINV_E_DEVICE, "a workgroup team of the rebuild timed out at a barrier");
+    if (flags & (kFlagNotSPD | kFlagSingular)) {
+        st = undo_line(c, E, s);
+        if (st != HINV_OK) return st;
+        return fail((flags & kFlagNotSPD) ? HINV_E_NOT_SPD : HINV_E_SINGULAR,
+                    "the change makes G (or G with the stored line changes) indefinite or singular");
+    }
+    return HINV_OK;
+}
+
+void fill_update_info(const Plan& P, const LocalSet& U, hinv_update_info* out)
+{
+    out->lca_level = U.lca_level;
+    out->leaves = (int32_t)U.leaves.size();
+    out->columns = 0;
+    out->nodes = 0;
+    for (int hh = 1; hh <= P.n_levels; ++hh) {
+        out->columns += (int32_t)U.cols[hh].size();
+        out->nodes += (int32_t)U.nodes[hh].size();
+    }
+}
+
 }  // namespace
 
 // =============================== C ABI =====================================
@@ -886,89 +1000,10 @@ hinv_status hinv_update_line(hinv_handle h, int32_t a, int32_t b, double delta_g
                              hinv_update_info* out)
 {
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
-    hinv_ctx& c = *h;
-    Plan& P = c.P;
-    hipStream_t s = (hipStream_t)stream;
-    const int n = P.n;
-    if (a < 0 || a >= n || b < -1 || b >= n || a == b) return fail(HINV_E_INVALID, "bad buses (%d, %d)", a, b);
-    if (!isfinite(delta_g) || delta_g == 0.0) return fail(HINV_E_INVALID, "delta_g must be finite and non-zero");
-    const int ra = P.iperm[a], rb = b >= 0 ? P.iperm[b] : -1;
-    auto entry = [&](int r, int col) {
-        for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
-            if (P.ci[e] == col) return e;
-        return -1;
-    };
-    const int e_aa = entry(ra, ra), e_bb = rb >= 0 ? entry(rb, rb) : -1;
-    const int e_ab = rb >= 0 ? entry(ra, rb) : -1, e_ba = rb >= 0 ? entry(rb, ra) : -1;
-    if (rb >= 0 && (e_ab < 0 || e_ba < 0))
-        return fail(HINV_E_NO_SUCH_LINE, "G has no entry between buses %d and %d; a new coupling needs a rebuild", a, b);
-    const int la = P.row_leaf[ra], lb = rb >= 0 ? P.row_leaf[rb] : la;
-    // the coupling column pair of a line between two leaves
-    int ca = -1, cb = -1;
-    if (la != lb) {
-        for (int g = 0; g < (int)P.col_row.size() && ca < 0; ++g)
-            if (P.col_row[g] == ra && P.col_row[P.col_partner[g]] == rb) { ca = g; cb = P.col_partner[g]; }
-        if (ca < 0)
-            return fail(HINV_E_NO_SUCH_LINE, "buses %d and %d are in different leaves and G has no line between "
-                        "them; a new coupling needs a rebuild", a, b);
-    }
-    const double old_aa = P.cv[e_aa], old_bb = e_bb >= 0 ? P.cv[e_bb] : 0.0, old_ab = e_ab >= 0 ? P.cv[e_ab] : 0.0;
-    double new_ab = old_ab - delta_g;
-    if (e_ab >= 0) {
-        if (fabs(new_ab) <= 1e-12 * fabs(delta_g)) new_ab = 0.0;
-        if (new_ab > 0.0)
-            return fail(HINV_E_NO_SUCH_LINE, "no line of conductance %g between %d and %d", -delta_g, a, b);
-    }
-    const double old_wa = ca >= 0 ? P.col_w[ca] : 0.0;
-    auto set_values = [&](double aa, double bb, double ab, double w) -> hinv_status {
-        P.cv[e_aa] = aa;
-        HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_aa), &P.cv[e_aa], sizeof(double), hipMemcpyHostToDevice, s));
-        if (e_bb >= 0) {
-            P.cv[e_bb] = bb;
-            HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_bb), &P.cv[e_bb], sizeof(double), hipMemcpyHostToDevice, s));
-        }
-        if (e_ab >= 0) {
-            P.cv[e_ab] = ab; P.cv[e_ba] = ab;
-            HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_ab), &P.cv[e_ab], sizeof(double), hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemcpyAsync((void*)(c.H.cv + e_ba), &P.cv[e_ba], sizeof(double), hipMemcpyHostToDevice, s));
-        }
-        if (ca >= 0) {
-            P.col_w[ca] = w; P.col_w[cb] = w;
-            HIP_TRY(hipMemcpyAsync((void*)(c.H.col_w + ca), &P.col_w[ca], sizeof(double), hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemcpyAsync((void*)(c.H.col_w + cb), &P.col_w[cb], sizeof(double), hipMemcpyHostToDevice, s));
-        }
-        return HINV_OK;
-    };
-    const LocalSet U = local_set(P, la, lb);
-    hinv_status st = set_values(old_aa + delta_g, old_bb + delta_g, new_ab, sqrt(fabs(new_ab)));
+    LineEdit ed;
+    hinv_status st = edit_line(*h, a, b, delta_g, (hipStream_t)stream, ed);
     if (st != HINV_OK) return st;
-    int flags = 0;
-    st = rebuild_local(c, U, s, &flags);
-    if (st != HINV_OK) return st;
-    if (flags & kFlagBarrier) return fail(HINV_E_DEVICE, "a workgroup team of the rebuild timed out at a barrier");
-    if (flags & (kFlagNotSPD | kFlagSingular)) {
-        // the same local rebuild with the old values restores the old inverse exactly
-        st = set_values(old_aa, old_bb, old_ab, old_wa);
-        if (st != HINV_OK) return st;
-        int back = 0;
-        st = rebuild_local(c, U, s, &back);
-        if (st != HINV_OK) return st;
-        HIP_TRY(hipMemsetAsync(c.d_flags, 0, sizeof(int), s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (back & (kFlagNotSPD | kFlagSingular)) return fail(HINV_E_DEVICE, "restoring the inverse failed");
-        return fail((flags & kFlagNotSPD) ? HINV_E_NOT_SPD : HINV_E_SINGULAR,
-                    "the change makes G (or G with the stored line changes) indefinite or singular");
-    }
-    if (out) {
-        out->lca_level = U.lca_level;
-        out->leaves = (int32_t)U.leaves.size();
-        out->columns = 0;
-        out->nodes = 0;
-        for (int hh = 1; hh <= P.n_levels; ++hh) {
-            out->columns += (int32_t)U.cols[hh].size();
-            out->nodes += (int32_t)U.nodes[hh].size();
-        }
-    }
+    if (out) fill_update_info(h->P, ed.U, out);
     return HINV_OK;
 }
 
@@ -2131,6 +2166,38 @@ hinv_status load_case_losses(emt_ctx& c, const std::vector<int>& which, hipStrea
     return HINV_OK;
 }
 
+// Rebuild the tables of the context's workgroup engine from the current
+// plan: new line-loss endpoints must become exchange rows of every workgroup,
+// and changed values of G must reach the rows kept for the residual.  Falls
+// back to the hierarchical engines where a plan no longer fits.
+hinv_status refresh_engine_tables(emt_ctx& c, hipStream_t s)
+{
+    hinv_status st = HINV_OK;
+    if (c.engine == 3) {
+        if (!build_team_plan(c, c.R)) {
+            c.engine = run_fits(c.hc.H) ? 2 : 1;
+            c.team_ok = false;
+        } else {
+            st = upload_team(c, s);
+        }
+    } else if (c.engine == 5) {
+        if (!build_level_plan(c, c.R)) {
+            c.engine = run_fits(c.hc.H) ? 2 : 1;
+            c.level_ok = false;
+        } else {
+            st = upload_level(c, s);
+        }
+    } else if (c.engine == 4) {
+        if (!build_panel_plan(c, c.R)) {
+            c.engine = run_fits(c.hc.H) ? 2 : 1;
+            c.panel_ok = false;
+        } else {
+            st = upload_panel(c, s);
+        }
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2301,33 +2368,34 @@ hinv_status emt_lose_line(emt_handle h, int32_t case_idx, int32_t branch, void* 
     launch_emt_rebuild_rhs(c.E, case_idx, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
-    if (c.engine == 3) {       // the new endpoints must become X rows of every workgroup
-        if (!build_team_plan(c, c.R)) {
-            c.engine = run_fits(c.hc.H) ? 2 : 1;
-            c.team_ok = false;
-        } else {
-            st = upload_team(c, s);
-            if (st != HINV_OK) return st;
-        }
+    return refresh_engine_tables(c, s);
+}
+
+hinv_status emt_update_line(emt_handle h, int32_t a, int32_t b, double delta_g, void* stream,
+                            hinv_update_info* out)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    emt_ctx& c = *h;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    LineEdit ed;
+    hinv_status st = edit_line(c.hc, a, b, delta_g, s, ed);
+    if (st != HINV_OK) return st;
+    // every case's stored line losses were applied to the old inverse
+    std::vector<int> all(c.n_cases);
+    for (int k = 0; k < c.n_cases; ++k) all[k] = k;
+    st = load_case_losses(c, all, s);
+    if (st != HINV_OK) {
+        const std::string why = g_err;
+        hinv_status u = undo_line(c.hc, ed, s);
+        if (u != HINV_OK) return u;
+        u = load_case_losses(c, all, s);
+        if (u != HINV_OK) return u;
+        return fail(st, "%s (with the change of G between buses %d and %d)", why.c_str(), a, b);
     }
-    if (c.engine == 5) {       // the new endpoints must become X rows of every workgroup
-        if (!build_level_plan(c, c.R)) {
-            c.engine = run_fits(c.hc.H) ? 2 : 1;
-            c.level_ok = false;
-        } else {
-            st = upload_level(c, s);
-            if (st != HINV_OK) return st;
-        }
-    }
-    if (c.engine == 4) {       // the same for the workgroups of the case's team
-        if (!build_panel_plan(c, c.R)) {
-            c.engine = run_fits(c.hc.H) ? 2 : 1;
-            c.panel_ok = false;
-        } else {
-            st = upload_panel(c, s);
-            if (st != HINV_OK) return st;
-        }
-    }
+    st = refresh_engine_tables(c, s);
+    if (st != HINV_OK) return st;
+    if (out) fill_update_info(c.hc.P, ed.U, out);
     return HINV_OK;
 }
 

@@ -24,8 +24,8 @@ STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "
 
 EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update_line", "hinv_solve", "hinv_sync_status",
            "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_network3_csr", "emt_workspace_size", "emt_create",
-           "emt_step", "emt_lose_line", "emt_sync_status", "emt_get_step", "emt_get_stats", "emt_set_step_clock",
-           "emt_destroy",
+           "emt_step", "emt_lose_line", "emt_update_line", "emt_sync_status", "emt_get_step", "emt_get_stats",
+           "emt_set_step_clock", "emt_destroy",
            "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
            "serve_step", "serve_active", "serve_destroy", "chol_workspace_size", "chol_create", "chol_solve",
            "chol_get_info", "chol_destroy", "hinv_last_error")
@@ -115,6 +115,7 @@ def load() -> ctypes.CDLL:
         "emt_create": [P, P, P, P, P, ctypes.c_size_t, P, P],
         "emt_step": [P, i32, P, P, P],
         "emt_lose_line": [P, i32, i32, P],
+        "emt_update_line": [P, i32, i32, d, P, P],
         "emt_sync_status": [P],
         "emt_get_step": [P, P],
         "emt_get_stats": [P, P, P],
@@ -423,6 +424,15 @@ class EMT:
 
     def lose_line(self, case_idx: int, branch: int) -> None:
         _check(self._lib.emt_lose_line(self._h, int(case_idx), int(branch), _stream()), "emt_lose_line")
+
+    def update_line(self, a: int, b: int, delta_g: float) -> dict:
+        """From the next step on, every case's G <- G + delta_g (e_a - e_b)(e_a - e_b)^T (b = -1:
+        a to ground): a memoryless fault conductance switched on, or off with its negative.
+        Returns what the local rebuild of the stored inverse touched."""
+        inf = _UpdateInfo()
+        _check(self._lib.emt_update_line(self._h, int(a), int(b), float(delta_g), _stream(), ctypes.byref(inf)),
+               "emt_update_line")
+        return {k: getattr(inf, k) for k, _ in _UpdateInfo._fields_}
 
     def sync_status(self) -> None:
         """Raise HinvError if a device-side failure (barrier time-out, unmapped change

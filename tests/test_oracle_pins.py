@@ -344,7 +344,7 @@ def _under(parent, t, c):
 
 
 def test_paper_inverse_error_falls_with_the_leaf_size():
-    """Section VI.A, Fig. 5: the error of G~^{-1} falls as the leaf threshold grows, and vanishes once
+    """Section V.A, Fig. 5: the error of G~^{-1} falls as the leaf threshold grows, and vanishes once
     one leaf holds the network (trend only; the paper's values are for data not available here)."""
     net = cases.net_179()
     G = oracle.assemble_G(net)
@@ -390,3 +390,67 @@ def test_G3_two_bus_line_sequence_eigenvalues():
     ref = np.sort([gc] * 3 + [gc + 2.0 / (R + zl * (1 + 2 * mu))] + [gc + 2.0 / (R + zl * (1 - mu))] * 2)
     ev = np.sort(np.linalg.eigvalsh(oracle.assemble_G3(net, mu)))
     assert np.abs(ev - ref).max() <= 1e-12 * ref.max()
+
+
+# --------------------------------------------------------------------------
+# Faults switched in the time loop: memoryless conductances (Section IV.A's
+# fault-on stage, the Section V.C scenario)
+# --------------------------------------------------------------------------
+
+def _with_resistor(net, a, b, r):
+    """The network plus one branch of resistance r and no inductance between buses a and b."""
+    import dataclasses
+    return dataclasses.replace(net, frm=np.append(net.frm, a).astype(np.int32),
+                               to=np.append(net.to, b).astype(np.int32),
+                               R=np.append(net.R, r), L=np.append(net.L, 0.0))
+
+
+def test_fault_on_equals_a_pure_resistance_branch():
+    """A branch with L = 0 is a resistor (its trapezoidal history stays zero), so a fault of 10 ohm
+    switched on at step 1 is the network with that branch."""
+    net = cases.case_c1(n_steps=300).net
+    a, b, rf = 7, 150, 10.0
+    Vf, _ = oracle.emt_run(net, 300, changes=[(1, a, b, 1.0 / rf)])
+    Vr, _ = oracle.emt_run(_with_resistor(net, a, b, rf), 300)
+    V0, _ = oracle.emt_run(net, 300)
+    peak = np.abs(Vr).max()
+    assert np.abs(Vf - Vr).max() <= 1e-12 * peak
+    assert np.abs(Vf - V0).max() > 1e-3 * peak          # the fault matters
+
+
+def test_fault_off_equals_losing_that_branch():
+    net = cases.case_c1(n_steps=300).net
+    a, b, rf, off = 12, 40, 10.0, 170
+    Vf, _ = oracle.emt_run(net, 300, changes=[(1, a, b, 1.0 / rf), (off, a, b, -1.0 / rf)])
+    Vr, _ = oracle.emt_run(_with_resistor(net, a, b, rf), 300, loss_steps=[off], loss_branches=[net.n_branch])
+    assert np.abs(Vf - Vr).max() <= 1e-12 * np.abs(Vr).max()
+
+
+def test_ground_fault_charge_balance():
+    """Summing KCL over all buses with a ground fault of conductance g_f at bus a, on for steps
+    [s1, s2): (2/dt) sum C (v^n - v^{n-1}) = sum (i_in^n + i_in^{n-1}) - (i_f^n + i_f^{n-1}),
+    i_f^n = g_f v_a^n while on and 0 otherwise.  Holds only if the fault enters G as g_f e_a e_a^T
+    with no history current, including across both switching steps."""
+    net = cases.case_c1(n_steps=400).net
+    a, gf, s1, s2 = 33, 0.1, 120, 260
+    V, _ = oracle.emt_run(net, 400, changes=[(s1, a, -1, gf), (s2, a, -1, -gf)])
+    V0, _ = oracle.emt_run(net, 400)
+    assert np.array_equal(V[:s1 - 1], V0[:s1 - 1])          # steps before the fault
+    Vp = np.vstack([np.zeros(net.n_bus), V])
+    steps = np.arange(0, 401)
+    i_f = np.where((steps >= s1) & (steps < s2), gf * Vp[:, a], 0.0)
+    lhs = (2 / net.dt) * ((Vp[1:] - Vp[:-1]) * net.C).sum(1)
+    u = np.array([oracle.source_current(net, n * net.dt).sum() for n in steps])
+    rhs = u[1:] + u[:-1] - (i_f[1:] + i_f[:-1])
+    scale = (2 / net.dt) * (np.abs(Vp[1:] - Vp[:-1]) * net.C).sum(1) + np.abs(u[1:]) + np.abs(u[:-1])
+    assert np.all(np.abs(lhs - rhs) <= 1e-9 * scale.max())
+    assert np.abs(V[s1:s2, a]).max() < 0.5 * np.abs(V0[s1:s2, a]).max()
+
+
+def test_bolted_ground_fault_holds_the_bus_at_zero():
+    """As the fault conductance grows, v_a at the fault-on steps falls like 1/g_f."""
+    net = cases.case_c1(n_steps=200).net
+    a, s1 = 90, 60
+    va = [np.abs(oracle.emt_run(net, 200, changes=[(s1, a, -1, gf)])[0][s1 - 1:, a]).max() for gf in (1e4, 1e7)]
+    ratio = va[0] / va[1]
+    assert 5e2 < ratio < 2e3
