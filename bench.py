@@ -214,8 +214,44 @@ def study_update(hinv, torch, reps=5):
         row["smw_modify_median_ms"] = round(float(np.median(ts)), 3)
         row.update({k: H.info()[k] for k in ("n_leaves", "n_internal", "n_levels", "n_cols", "max_cols")})
         H.close()
+        if name.startswith("1432"):
+            row["fault_in_time_loop"] = _fault_switching(hinv, torch, net, g, lv, reps)
         out[name] = row
     return out
+
+
+def _fault_switching(hinv, torch, net, g, lv, reps):
+    """A 10 ohm fault switched on and off inside a running EMT context (emt_update_line) on the
+    headline network and engine (one case, its line loss scheduled): wall time of one switching
+    (local rebuild of the stored inverse, the case's losses re-applied, the engine's tables rebuilt
+    and uploaded; the call synchronises) for a fault to ground and across a line inside a leaf and at
+    the root, against the time of one step."""
+    import time
+    from paper_2105_10661_amd import cases
+    case = cases.case_c2()
+    emt = hinv.EMT(net, 1, losses=[list(zip(case.loss_steps.tolist(), case.loss_branches.tolist()))])
+    emt.step(50, record_v=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    emt.step(1000, record_v=False)
+    torch.cuda.synchronize()
+    res = {"step_us": round((time.perf_counter() - t0) * 1e3, 3)}
+    root = int(lv.max())
+    faults = {"ground": (1, -1), "line_in_leaf": None, "line_at_root": None}
+    for key, level in (("line_in_leaf", 0), ("line_at_root", root)):
+        e = int(np.nonzero(lv == level)[0][0])
+        faults[key] = (int(net.frm[e]), int(net.to[e]))
+    for key, (a, b) in faults.items():
+        ts, info = [], None
+        for k in range(2 * reps):
+            t0 = time.perf_counter()
+            info = emt.update_line(a, b, 0.1 if k % 2 == 0 else -0.1)
+            ts.append((time.perf_counter() - t0) * 1e3)
+            emt.step(20, record_v=False)
+        res[key] = dict(info, median_ms=round(float(np.median(ts)), 3), min_ms=round(float(np.min(ts)), 3))
+    emt.sync_status()
+    emt.close()
+    return res
 
 
 def study_paper(hinv, torch):

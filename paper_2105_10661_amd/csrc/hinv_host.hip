@@ -1112,6 +1112,7 @@ struct emt_ctx {
     std::vector<int> tw_lo, tw_nl, tw_nx, tw_nb, txrow, txzo, txpm, txpc, tozo, topm, topc, topan, txpan, txpos, torp,
         tocol, tbglob, tbf, tbt, tbown, tiptr, tibr, tsptr;
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
+    std::vector<int> tosrc;      // CSR entry (plus one, 0 = padding) of each toval value
     std::vector<int> tcsop;
     TeamDev TD{};
     // panel engine (cases in panels of kPanelCases, one workgroup per leaf per panel)
@@ -1423,6 +1424,7 @@ bool build_team_plan(emt_ctx& c, int R)
         std::vector<int> xrow, xzo, xpm, xpc, xpan, ozo, opm, opc, opan, xpos, orp, ocol, bglob, bf, bt, bown, iptr, ibr,
             sptr;
         std::vector<double> oval, bg, bal, samp, sph;
+        std::vector<int> osrc;       // CSR entry of each oval value, plus one
         int xz = 0, zo = 0;
     };
     std::vector<W> ws(L);
@@ -1468,6 +1470,7 @@ bool build_team_plan(emt_ctx& c, int R)
             for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
                 w.ocol.push_back(comb(P.ci[e]));
                 w.oval.push_back(P.cv[e]);
+                w.osrc.push_back(e + 1);
             }
             w.orp[r - lo + 1] = (int)w.ocol.size();
         }
@@ -1559,6 +1562,7 @@ bool build_team_plan(emt_ctx& c, int R)
     flat(c.tibr, NI, [](W& w) -> std::vector<int>& { return w.ibr; });
     flat(c.tsptr, NL + 1, [](W& w) -> std::vector<int>& { return w.sptr; });
     flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
+    flat(c.tosrc, NE, [](W& w) -> std::vector<int>& { return w.osrc; });
     flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
     flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
     flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
@@ -1622,6 +1626,7 @@ bool build_panel_plan(emt_ctx& c, int R)
     struct W {
         std::vector<int> fx, ozo, opm, opc, opan, orp, ocol, bglob, bf, bt, bown, iptr, ibr, sptr;
         std::vector<double> oval, bg, bal, samp, sph;
+        std::vector<int> osrc;       // CSR entry of each oval value, plus one
         int zo = 0;
     };
     std::vector<W> ws(L);
@@ -1650,6 +1655,7 @@ bool build_panel_plan(emt_ctx& c, int R)
             for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
                 w.ocol.push_back(comb(P.ci[e]));
                 w.oval.push_back(P.cv[e]);
+                w.osrc.push_back(e + 1);
             }
             w.orp[r - lo + 1] = (int)w.ocol.size();
         }
@@ -1804,6 +1810,7 @@ bool build_panel_plan(emt_ctx& c, int R)
     flat(c.tibr, NI, [](W& w) -> std::vector<int>& { return w.ibr; });
     flat(c.tsptr, NL + 1, [](W& w) -> std::vector<int>& { return w.sptr; });
     flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
+    flat(c.tosrc, NE, [](W& w) -> std::vector<int>& { return w.osrc; });
     flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
     flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
     flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
@@ -1910,6 +1917,7 @@ bool build_level_plan(emt_ctx& c, int R)
         std::vector<int> xr, ozo, opm, opc, opan, optr, ocl, orow, osoff, orp, ocol, bglob, bf, bt, bown, iptr, ibr,
             sptr, lpa, lpb;
         std::vector<double> oval, bg, bal, samp, sph;
+        std::vector<int> osrc;       // CSR entry of each oval value, plus one
         int zo = 0, so = 0;
     };
     std::vector<W> ws(L);
@@ -1953,6 +1961,7 @@ bool build_level_plan(emt_ctx& c, int R)
             for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
                 w.ocol.push_back(comb(P.ci[e]));
                 w.oval.push_back(P.cv[e]);
+                w.osrc.push_back(e + 1);
             }
             w.orp[r - lo + 1] = (int)w.ocol.size();
         }
@@ -2038,6 +2047,7 @@ bool build_level_plan(emt_ctx& c, int R)
     flat(c.llpa, R, [](W& w) -> std::vector<int>& { return w.lpa; });
     flat(c.llpb, R, [](W& w) -> std::vector<int>& { return w.lpb; });
     flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
+    flat(c.tosrc, NE, [](W& w) -> std::vector<int>& { return w.osrc; });
     flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
     flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
     flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
@@ -2196,6 +2206,24 @@ hinv_status refresh_engine_tables(emt_ctx& c, hipStream_t s)
         }
     }
     return st;
+}
+
+// After a change of values only (G's pattern kept), copy the new values of
+// the given CSR entries into the workgroup engine's residual rows: a few
+// element copies instead of a rebuild of every table.  Synchronises.
+hinv_status patch_engine_values(emt_ctx& c, const std::vector<int>& entries, hipStream_t s)
+{
+    const double* d_oval = c.engine == 3 ? c.TD.oval : c.engine == 4 ? c.PD.oval : c.engine == 5 ? c.LD.oval : nullptr;
+    if (!d_oval) return HINV_OK;
+    const Plan& P = c.hc.P;
+    for (size_t q = 0; q < c.tosrc.size(); ++q) {
+        const int e = c.tosrc[q] - 1;
+        if (e < 0 || std::find(entries.begin(), entries.end(), e) == entries.end()) continue;
+        c.toval[q] = P.cv[e];
+        HIP_TRY(hipMemcpyAsync((void*)(d_oval + q), &c.toval[q], sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return HINV_OK;
 }
 
 }  // namespace
@@ -2393,7 +2421,10 @@ hinv_status emt_update_line(emt_handle h, int32_t a, int32_t b, double delta_g, 
         if (u != HINV_OK) return u;
         return fail(st, "%s (with the change of G between buses %d and %d)", why.c_str(), a, b);
     }
-    st = refresh_engine_tables(c, s);
+    std::vector<int> changed{ed.e_aa};
+    for (int x : {ed.e_bb, ed.e_ab, ed.e_ba})
+        if (x >= 0) changed.push_back(x);
+    st = patch_engine_values(c, changed, s);
     if (st != HINV_OK) return st;
     if (out) fill_update_info(c.hc.P, ed.U, out);
     return HINV_OK;
