@@ -1114,6 +1114,7 @@ struct emt_ctx {
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
     std::vector<int> tosrc;      // CSR entry (plus one, 0 = padding) of each toval value
     std::vector<int> tcsop;
+    std::vector<int> taoff, talo, talen, tcpan;   // rows a_g of the two-phase coupling levels
     TeamDev TD{};
     // panel engine (cases in panels of kPanelCases, one workgroup per leaf per panel)
     bool panel_ok = false;
@@ -1520,6 +1521,47 @@ bool build_team_plan(emt_ctx& c, int R)
         }
         D.sent = (int)std::max<int64_t>(off, 1);
     }
+    // rows a_g of the two-phase coupling levels (values from launch_team_acoef): the panel of the
+    // column's row at every lower level, and the columns a_g can reach, as one range per column
+    {
+        const int Hs = std::max(H, 1);
+        c.tcpan.assign((size_t)NC * Hs, -1);
+        c.taoff.assign(NC, 0); c.talo.assign(NC, 0); c.talen.assign(NC, 0);
+        // covering ranges [lo, hi] of the columns that s_g (off its own column) and y_g depend on
+        std::vector<int> alo_(NC, INT32_MAX), ahi_(NC, -1), blo_(NC, INT32_MAX), bhi_(NC, -1);
+        for (int h = 1; h <= H; ++h) {
+            for (int g = P.lvl_col[h - 1]; g < P.lvl_col[h]; ++g) {
+                const int lf = P.row_leaf[P.col_row[g]];
+                for (int hh = 1; hh < h; ++hh) {
+                    const int pp = lpan[(size_t)lf * H + hh - 1];
+                    c.tcpan[(size_t)g * Hs + hh - 1] = pp;
+                    if (pp < 0) continue;
+                    for (int j = 0; j < P.pan_m[pp]; ++j) {
+                        const int gp = P.pan_col0[pp] + j;
+                        alo_[g] = std::min(alo_[g], blo_[gp]);
+                        ahi_[g] = std::max(ahi_[g], bhi_[gp]);
+                    }
+                }
+            }
+            for (int g = P.lvl_col[h - 1]; g < P.lvl_col[h]; ++g) {
+                const int t = P.col_node[g], c0 = P.node_col0[t], m = P.node_m[t];
+                blo_[g] = c0;
+                bhi_[g] = c0 + m - 1;
+                for (int p = 0; p < m; ++p) {
+                    blo_[g] = std::min(blo_[g], alo_[c0 + p]);
+                    bhi_[g] = std::max(bhi_[g], ahi_[c0 + p]);
+                }
+            }
+        }
+        int na = 0;
+        for (int g = 0; g < NC; ++g) {
+            c.taoff[g] = na;
+            c.talo[g] = ahi_[g] < 0 ? 0 : alo_[g];
+            c.talen[g] = ahi_[g] < 0 ? 0 : ahi_[g] - alo_[g] + 1;
+            na += c.talen[g];
+        }
+        D.nA = std::max(na, 1);
+    }
     if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
     const int Hs = std::max(H, 1);
     (void)Hs;
@@ -1593,6 +1635,12 @@ void carve_team(emt_ctx& c, Arena& A)
     D.csop = ti(D.nc);
     D.X0 = td(2 * (size_t)c.n);
     D.VM = td(2 * L);
+    D.aoff = ti(D.nc); D.alo = ti(D.nc); D.alen = ti(D.nc);
+    D.cpan = ti((size_t)D.nc * std::max<int64_t>(H, 1));
+    D.acoef = td(D.nA);
+    D.acoef32 = A.take<float>(D.nA);
+    D.am = td((size_t)D.nc * D.nc);
+    D.bm = td((size_t)D.nc * D.nc);
 }
 
 // ---------------------------------------------------------------------------
@@ -2112,7 +2160,10 @@ hinv_status upload_team(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
     HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
     HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s)); HIP_TRY(up(D.csop, c.tcsop, s));
+    HIP_TRY(up(D.aoff, c.taoff, s)); HIP_TRY(up(D.alo, c.talo, s)); HIP_TRY(up(D.alen, c.talen, s));
+    HIP_TRY(up(D.cpan, c.tcpan, s));
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
+    HIP_TRY(launch_team_acoef(D, c.hc.H, s));
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;
 }
@@ -2426,6 +2477,10 @@ hinv_status emt_update_line(emt_handle h, int32_t a, int32_t b, double delta_g, 
         if (x >= 0) changed.push_back(x);
     st = patch_engine_values(c, changed, s);
     if (st != HINV_OK) return st;
+    if (c.engine == 3) {       // the rows a_g fold in S^{-1} and Z, which the rebuild changed
+        HIP_TRY(launch_team_acoef(c.TD, c.hc.H, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     if (out) fill_update_info(c.hc.P, ed.U, out);
     return HINV_OK;
 }

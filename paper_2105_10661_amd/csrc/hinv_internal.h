@@ -252,6 +252,20 @@ struct TeamDev {
     unsigned int* sync;  // [T] barrier epoch flag of each workgroup
     double* X0;          // [2*n] exchange of leaf results (double-buffered by apply parity)
     double* VM;          // [2*T] each workgroup's max |v| (same buffering)
+    // Coupling levels in two phases.  With u_g the leaf-apply value at column g's row,
+    // s_g = w_g u_g - sum_k a_g[k] u_{alo_g + k}, where the row a_g folds the corrections that the
+    // lower levels' y would make to that row (the Z panels of the row at the lower levels through
+    // their S^{-1}), then y = S^{-1} s for every level at once.  a_g is the same for every
+    // workgroup; launch_team_acoef computes it on the device from the FP64 hierarchy.
+    int nA;              // entries of all rows a_g
+    const int* aoff;     // [n_cols] offset of a_g
+    const int* alo;      // [n_cols] first column of a_g
+    const int* alen;     // [n_cols] length of a_g (0 on the lowest level)
+    const int* cpan;     // [n_cols*H] panel of the column's row at each lower level, -1: none
+    double* acoef;       // [nA] FP64 rows a_g
+    float* acoef32;      // [nA] FP32 copy
+    double* am;          // [n_cols*n_cols] scratch: off-diagonal part of s as a map from u
+    double* bm;          // [n_cols*n_cols] scratch: y as a map from u
 };
 
 // Panel stepping (k_panel.hip): cases that share one base network advance in
@@ -432,6 +446,7 @@ void launch_emt_rebuild_rhs(const EmtDev& E, int k, hipStream_t s);
 void launch_set_rec(RecParams* d, const RecParams& val, hipStream_t s);
 // Team stepping (k_team.hip): LDS bytes of the layout, and the launch.
 size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec);
+hipError_t launch_team_acoef(const TeamDev& T, const HierDev& H, hipStream_t s);
 hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                            int prec, hipStream_t s);
 // Panel stepping (k_panel.hip): LDS bytes of the layout, and the launch (all

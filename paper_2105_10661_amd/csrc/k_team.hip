@@ -11,8 +11,10 @@
 //      vector (double-buffered by apply parity);
 //   2. one team barrier;
 //   3. every workgroup reads v0 at its X rows and computes, redundantly, every
-//      level's y = S^{-1} U^T v bottom-up, then the corrected values of its own
-//      rows and X rows, then the SMW correction.
+//      level's y = S^{-1} U^T v (all levels in two phases: each column's s from
+//      v0 and a precomputed row that folds in the lower levels' corrections of
+//      the column's row, then y = S^{-1} s), then the corrected values of its
+//      own rows and X rows, then the SMW correction.
 // Rows shared by two workgroups are computed with identical operations in
 // both, so their values agree bitwise and the history update of a tie line
 // (and the refinement residual) needs no second exchange.
@@ -33,9 +35,10 @@ template <>
 struct TAcc<double> { using T = double; };
 
 struct TeamLayout {
-    size_t blk, sall, zown, xz, uown, ux;
+    size_t blk, sall, zown, xz, uown, ux, acoef;
     size_t b, v, t, d, part, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, colw, cinv, mdg, red, tz;
     size_t xrow, xzo, xpm, xpc, ozo, opm, opc, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
+    size_t aoff, alo, alen;
     size_t lpa, lpb, loa, lob, mact, lbr, lst, vg, ctl;
     size_t total;
 };
@@ -51,20 +54,31 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
         return r;
     };
     const size_t NL = T.NL, NX = T.NX, H = T.H, nc = T.nc;
+    // FP32 storage refines against G in FP64; the FP64 path has no use for G's rows or the
+    // correction vectors, and its LDS is the tighter one
+    const bool refines = sizeof(TB) != 8;
     L.blk = take(sizeof(TB) * NL * NL);
     L.sall = take(sizeof(TB) * (size_t)T.sent);
     L.zown = take(sizeof(TB) * (size_t)T.ZO);
     L.xz = take(sizeof(TB) * (size_t)T.XZ);
     L.uown = take(sizeof(TB) * R * NL);
     L.ux = take(sizeof(TB) * R * NX);
+    L.acoef = take(sizeof(TB) * (size_t)T.nA);
     const size_t D = sizeof(double);
-    L.b = take(D * NL); L.v = take(D * NL); L.t = take(D * NL); L.d = take(D * NL);
+    L.b = take(D * NL); L.v = take(D * NL);
+    L.t = take(refines ? D * NL : 0); L.d = take(refines ? D * NL : 0);
     L.part = take(D * kGemvChunks * NL);
-    L.xv = take(D * NX); L.xd = take(D * NX);
-    L.s = take(D * nc); L.y = take(D * nc);
+    L.xv = take(D * NX); L.xd = take(refines ? D * NX : 0);
+    // s and y live from the coupling levels to the end of an apply, the GEMV partial sums only
+    // before its barrier: they share space where it fits
+    if (2 * nc <= (size_t)kGemvChunks * NL) {
+        L.s = L.part; L.y = L.part + D * nc;
+    } else {
+        L.s = take(D * nc); L.y = take(D * nc);
+    }
     L.h0 = take(D * T.NB); L.h1 = take(D * T.NB);
     L.hC = take(D * NL); L.gC = take(D * NL);
-    L.oval = take(D * T.NE); L.bg = take(D * T.NB); L.bal = take(D * T.NB);
+    L.oval = take(refines ? D * T.NE : 0); L.bg = take(D * T.NB); L.bal = take(D * T.NB);
     L.samp = take(D * T.NS); L.sph = take(D * T.NS); L.sn = take(D * T.NS);
     L.colw = take(D * nc);
     L.cinv = take(D * R * R * R); L.mdg = take(D * R);
@@ -74,7 +88,8 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.ozo = take(I * H); L.opm = take(I * H); L.opc = take(I * H);
     L.xpos = take(I * nc); L.cm = take(I * nc); L.cc0 = take(I * nc); L.cso = take(I * nc);
     L.lvlc = take(I * (H + 1));
-    L.orp = take(I * (NL + 1)); L.ocol = take(I * T.NE);
+    L.orp = take(refines ? I * (NL + 1) : 0); L.ocol = take(refines ? I * T.NE : 0);
+    L.aoff = take(I * nc); L.alo = take(I * nc); L.alen = take(I * nc);
     L.bglob = take(I * T.NB); L.bf = take(I * T.NB); L.bt = take(I * T.NB);
     L.iptr = take(I * (NL + 1)); L.ibr = take(I * T.NI); L.sptr = take(I * (NL + 1));
     L.lpa = take(I * R); L.lpb = take(I * R); L.loa = take(I * R); L.lob = take(I * R);
@@ -95,6 +110,7 @@ template <typename TB, bool MIXED, bool WARM>
 __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, HierDev H, ModDev M, RunParams P)
 {
     using TA = typename TAcc<TB>::T;
+    static_assert(MIXED == (sizeof(TB) != 8), "the LDS layout keeps the refinement buffers for FP32 storage only");
     extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
     const int R = M.R;
     const TeamLayout Ly = team_layout<TB>(T, R);
@@ -107,6 +123,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     TB* xz = (TB*)(L8 + Ly.xz);
     TB* uown = (TB*)(L8 + Ly.uown);
     TB* ux = (TB*)(L8 + Ly.ux);
+    TB* acoef = (TB*)(L8 + Ly.acoef);
     double* b = (double*)(L8 + Ly.b);
     double* v = (double*)(L8 + Ly.v);
     double* t = (double*)(L8 + Ly.t);
@@ -151,6 +168,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     int* iptr = (int*)(L8 + Ly.iptr);
     int* ibr = (int*)(L8 + Ly.ibr);
     int* sptr = (int*)(L8 + Ly.sptr);
+    int* aoff = (int*)(L8 + Ly.aoff);
+    int* alo = (int*)(L8 + Ly.alo);
+    int* alen = (int*)(L8 + Ly.alen);
     int* lpa = (int*)(L8 + Ly.lpa);
     int* lpb = (int*)(L8 + Ly.lpb);
     int* loa = (int*)(L8 + Ly.loa);
@@ -165,10 +185,13 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     const TB* gS;
     const TB* gZ;
     const TB* gU;
+    const TB* gA;
     if constexpr (sizeof(TB) == 8) {
         gblk = (const TB*)H.blk; gS = (const TB*)H.Sinv; gZ = (const TB*)H.Z; gU = (const TB*)M.U;
+        gA = (const TB*)T.acoef;
     } else {
         gblk = (const TB*)H.blk32; gS = (const TB*)H.Sinv32; gZ = (const TB*)H.Z32; gU = (const TB*)M.U32;
+        gA = (const TB*)T.acoef32;
     }
     // ---------------- load the workgroup's tables and state into LDS
     {
@@ -215,17 +238,23 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             cc0[g] = H.node_col0[node];
             cso[g] = T.csop[g];
             colw[g] = H.col_w[g];
+            aoff[g] = T.aoff[g];
+            alo[g] = T.alo[g];
+            alen[g] = T.alen[g];
         }
+        for (int i = tid; i < T.nA; i += kTeamThreads) acoef[i] = gA[i];
         for (int h = tid; h <= Hn; h += kTeamThreads) lvlc[h] = H.lvl_col[h];
         const int* worp = T.orp + (int64_t)w * (NL + 1);
         for (int r = tid; r <= nl; r += kTeamThreads) {
-            orp[r] = worp[r];
+            if (MIXED) orp[r] = worp[r];
             iptr[r] = T.iptr[(int64_t)w * (NL + 1) + r];
             sptr[r] = T.sptr[(int64_t)w * (NL + 1) + r];
         }
-        for (int e = tid; e < worp[nl]; e += kTeamThreads) {
-            ocol[e] = T.ocol[(int64_t)w * T.NE + e];
-            oval[e] = T.oval[(int64_t)w * T.NE + e];
+        if (MIXED) {
+            for (int e = tid; e < worp[nl]; e += kTeamThreads) {
+                ocol[e] = T.ocol[(int64_t)w * T.NE + e];
+                oval[e] = T.oval[(int64_t)w * T.NE + e];
+            }
         }
         for (int q = tid; q < nb; q += kTeamThreads) {
             const int64_t gq = (int64_t)w * T.NB + q;
@@ -328,32 +357,21 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         }
         for (int x = tid; x < nx; x += kTeamThreads) outx[x] = xchg_load(&X0[xrow[x]]);
         __syncthreads();
-        // coupling levels bottom-up: gather s (an endpoint row's lower-level
-        // corrections are applied inline, in the same order as the final
-        // update), then y = S^{-1} s; all rows are updated once at the end.
-        for (int h = 1; h <= Hn; ++h) {
-            const int c0 = lvlc[h - 1], c1 = lvlc[h];
-            if (c1 == c0) continue;
-            for (int idx = tid; idx < (c1 - c0) * kSub; idx += kTeamThreads) {
-                const int g = c0 + idx / kSub, sub = idx & (kSub - 1);
-                const int x = xpos[g];
-                double val = outx[x];
-                for (int hh = 1; hh < h; ++hh) {
-                    const int zo = xzo[x * Hn + hh - 1];
-                    TA acc = 0;
-                    if (zo >= 0) {
-                        const int pm = xpm[x * Hn + hh - 1], pc = xpc[x * Hn + hh - 1];
-                        for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
-                    }
-                    acc = quad_sum(acc);
-                    if (zo >= 0) val -= (double)acc;
-                }
-                if (sub == 0) s[g] = colw[g] * val;
+        // coupling levels, all at once: s_g = w_g u_g - a_g . u from the leaf-apply values u at the
+        // column rows (a_g carries the lower levels' corrections of the row), then y = S^{-1} s;
+        // kSub lanes share each column's dot products (quad sums); all rows are updated at the end.
+        if (nc > 0) {
+            for (int idx = tid; idx < nc * kSub; idx += kTeamThreads) {
+                const int g = idx / kSub, sub = idx & (kSub - 1);
+                const int a0 = aoff[g], al = alo[g], an = alen[g];
+                TA acc = 0;
+                for (int k = sub; k < an; k += kSub) acc += (TA)acoef[a0 + k] * (TA)outx[xpos[al + k]];
+                acc = quad_sum(acc);
+                if (sub == 0) s[g] = colw[g] * outx[xpos[g]] - (double)acc;
             }
             __syncthreads();
-            // y = S^{-1} s: kSub lanes share each column's dot product (quad sums)
-            for (int idx = tid; idx < (c1 - c0) * kSub; idx += kTeamThreads) {
-                const int g = c0 + idx / kSub, sub = idx & (kSub - 1);
+            for (int idx = tid; idx < nc * kSub; idx += kTeamThreads) {
+                const int g = idx / kSub, sub = idx & (kSub - 1);
                 const int m = cm[g], q0 = cc0[g];
                 const TB* Si = sall + cso[g];
                 TA acc = 0;
@@ -580,6 +598,81 @@ hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, 
     if (prec == HINV_FP64) return launch_team_t<double, false, false>(T, E, H, M, P, s);
     if (P.warm) return launch_team_t<float, true, true>(T, E, H, M, P, s);
     return launch_team_t<float, true, false>(T, E, H, M, P, s);
+}
+
+// ---------------- the rows a_g of the two-phase coupling levels
+//
+// Bottom-up over the levels, as maps from u (the leaf-apply values at the
+// column rows), for the columns g of level h and every column c:
+//   am[g][c] = w_g sum_{hh<h} sum_j Z_hh[row_g][p_j] bm[p_j][c]   (p_j: the
+//              columns of the row's level-hh panel; zero on the lowest level),
+//   bm[g][c] = sum_p S_t^{-1}[p][q_g] (w_{c0+p} [c = c0+p] - am[c0+p][c])
+//              (t: the column's node, columns c0 .. c0+m-1, q_g = g - c0),
+// so that s = diag(w) u - am u and y = bm u, as the sequential levels give.
+__global__ void k_team_am(HierDev H, TeamDev D, int h)
+{
+    const int nc = D.nc, g0 = H.lvl_col[h - 1];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)(H.lvl_col[h] - g0) * nc) return;
+    const int g = g0 + (int)(i / nc), c = (int)(i % nc);
+    const int r = H.col_row[g];
+    double acc = 0.0;
+    for (int hh = 1; hh < h; ++hh) {
+        const int pp = D.cpan[(int64_t)g * D.H + hh - 1];
+        if (pp < 0) continue;
+        const double* zp = H.Z + H.pan_zoff[pp] + (r - H.pan_lo[pp]);
+        const int p0 = H.pan_col0[pp], pn = H.pan_n[pp];
+        for (int j = 0; j < H.pan_m[pp]; ++j) acc += zp[(int64_t)j * pn] * D.bm[(int64_t)(p0 + j) * nc + c];
+    }
+    D.am[(int64_t)g * nc + c] = H.col_w[g] * acc;
+}
+
+__global__ void k_team_bm(HierDev H, TeamDev D, int h)
+{
+    const int nc = D.nc, g0 = H.lvl_col[h - 1];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)(H.lvl_col[h] - g0) * nc) return;
+    const int g = g0 + (int)(i / nc), c = (int)(i % nc);
+    const int t = H.col_node[g], m = H.node_m[t], c0 = H.node_col0[t];
+    const double* Si = H.Sinv + H.node_soff[t] + (g - c0);
+    double acc = 0.0;
+    for (int p = 0; p < m; ++p) {
+        const int gp = c0 + p;
+        const double sv = (gp == c ? H.col_w[gp] : 0.0) - D.am[(int64_t)gp * nc + c];
+        acc += Si[(int64_t)p * m] * sv;
+    }
+    D.bm[(int64_t)g * nc + c] = acc;
+}
+
+__global__ void k_team_apack(TeamDev D)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= D.nc) return;
+    const int a0 = D.aoff[g], al = D.alo[g];
+    for (int k = 0; k < D.alen[g]; ++k) {
+        const double a = D.am[(int64_t)g * D.nc + al + k];
+        D.acoef[a0 + k] = a;
+        D.acoef32[a0 + k] = (float)a;
+    }
+}
+
+hipError_t launch_team_acoef(const TeamDev& T, const HierDev& H, hipStream_t s)
+{
+    if (T.nc <= 0) return hipSuccess;
+    std::vector<int> lvl(T.H + 1);
+    hipError_t e = hipMemcpyAsync(lvl.data(), H.lvl_col, sizeof(int) * (T.H + 1), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    for (int h = 1; h <= T.H; ++h) {
+        const int64_t cnt = (int64_t)(lvl[h] - lvl[h - 1]) * T.nc;
+        if (cnt <= 0) continue;
+        const int blocks = (int)((cnt + 255) / 256);
+        k_team_am<<<blocks, 256, 0, s>>>(H, T, h);
+        k_team_bm<<<blocks, 256, 0, s>>>(H, T, h);
+    }
+    k_team_apack<<<(T.nc + 255) / 256, 256, 0, s>>>(T);
+    return hipGetLastError();
 }
 
 }  // namespace hinv
