@@ -1109,6 +1109,7 @@ struct emt_ctx {
     // team engine
     bool team_ok = false;
     int team_nx_cap = 0;
+    std::vector<int> tw_nxu, txupd;   // team: X rows whose final values a workgroup uses
     std::vector<int> tw_lo, tw_nl, tw_nx, tw_nb, txrow, txzo, txpm, txpc, tozo, topm, topc, topan, txpan, txpos, torp,
         tocol, tbglob, tbf, tbt, tbown, tiptr, tibr, tsptr;
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
@@ -1404,7 +1405,7 @@ bool build_team_plan(emt_ctx& c, int R)
     const Plan& P = c.hc.P;
     const int L = (int)P.leaf_lo.size(), H = P.n_levels, n = c.n;
     const int NC = (int)P.col_row.size();
-    if (c.n_cases != 1 || L < 1 || L > 256) return false;
+    if (c.n_cases != 1 || L < 1 || L > 256 || H > kTeamMaxLevels) return false;
     // panel of every leaf's rows at every level
     std::vector<int> lpan((size_t)L * std::max(H, 1), -1);
     for (int l = 0; l < L; ++l) {
@@ -1422,6 +1423,7 @@ bool build_team_plan(emt_ctx& c, int R)
         loss_rows.push_back(c.to_p[x.second]);
     }
     struct W {
+        std::vector<int> xupd;       // X positions of G neighbours of own rows and of line-loss endpoints
         std::vector<int> xrow, xzo, xpm, xpc, xpan, ozo, opm, opc, opan, xpos, orp, ocol, bglob, bf, bt, bown, iptr, ibr,
             sptr;
         std::vector<double> oval, bg, bal, samp, sph;
@@ -1466,6 +1468,12 @@ bool build_team_plan(emt_ctx& c, int R)
         }
         w.xpos.resize(NC);
         for (int g = 0; g < NC; ++g) w.xpos[g] = xpos_of(P.col_row[g]);
+        for (int r = lo; r < lo + nl; ++r)
+            for (int e = P.rp[r]; e < P.rp[r + 1]; ++e)
+                if (!own(P.ci[e])) w.xupd.push_back(xpos_of(P.ci[e]));
+        for (int r : loss_rows) w.xupd.push_back(xpos_of(r));   // the SMW reads endpoints as X rows
+        std::sort(w.xupd.begin(), w.xupd.end());
+        w.xupd.erase(std::unique(w.xupd.begin(), w.xupd.end()), w.xupd.end());
         w.orp.assign(nl + 1, 0);
         for (int r = lo; r < lo + nl; ++r) {
             for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
@@ -1581,10 +1589,13 @@ bool build_team_plan(emt_ctx& c, int R)
     };
     const int NXc = c.team_nx_cap > 0 ? c.team_nx_cap : NX;
     c.tw_lo = P.leaf_lo; c.tw_nl = P.leaf_n;
-    c.tw_nx.resize(L); c.tw_nb.resize(L);
-    for (int l = 0; l < L; ++l) { c.tw_nx[l] = (int)ws[l].xrow.size(); c.tw_nb[l] = (int)ws[l].bglob.size(); }
+    c.tw_nx.resize(L); c.tw_nb.resize(L); c.tw_nxu.resize(L);
+    for (int l = 0; l < L; ++l) {
+        c.tw_nx[l] = (int)ws[l].xrow.size(); c.tw_nb[l] = (int)ws[l].bglob.size(); c.tw_nxu[l] = (int)ws[l].xupd.size();
+    }
     // X-row tables use the capacity stride so that a later rebuild fits the carve
     flat(c.txrow, NXc, [](W& w) -> std::vector<int>& { return w.xrow; });
+    flat(c.txupd, NXc, [](W& w) -> std::vector<int>& { return w.xupd; });
     flat(c.txzo, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xzo; });
     flat(c.txpm, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpm; });
     flat(c.txpc, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpc; });
@@ -1622,6 +1633,7 @@ void carve_team(emt_ctx& c, Arena& A)
     auto ti = [&](size_t cnt) { return A.take<int>((int64_t)cnt); };
     auto td = [&](size_t cnt) { return A.take<double>((int64_t)cnt); };
     D.w_lo = ti(L); D.w_nl = ti(L); D.w_nx = ti(L); D.w_nb = ti(L);
+    D.w_nxu = ti(L); D.xupd = ti(L * D.NX);
     D.xrow = ti(L * D.NX); D.xzo = ti(L * D.NX * H); D.xpm = ti(L * D.NX * H); D.xpc = ti(L * D.NX * H);
     D.xpan = ti(L * D.NX * H);
     D.ozo = ti(L * H); D.opm = ti(L * H); D.opc = ti(L * H); D.opan = ti(L * H);
@@ -2150,7 +2162,7 @@ hinv_status upload_team(emt_ctx& c, hipStream_t s)
 {
     TeamDev& D = c.TD;
     HIP_TRY(up(D.w_lo, c.tw_lo, s)); HIP_TRY(up(D.w_nl, c.tw_nl, s)); HIP_TRY(up(D.w_nx, c.tw_nx, s));
-    HIP_TRY(up(D.w_nb, c.tw_nb, s));
+    HIP_TRY(up(D.w_nb, c.tw_nb, s)); HIP_TRY(up(D.w_nxu, c.tw_nxu, s)); HIP_TRY(up(D.xupd, c.txupd, s));
     HIP_TRY(up(D.xrow, c.txrow, s)); HIP_TRY(up(D.xzo, c.txzo, s)); HIP_TRY(up(D.xpm, c.txpm, s));
     HIP_TRY(up(D.xpc, c.txpc, s)); HIP_TRY(up(D.xpan, c.txpan, s));
     HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.opc, c.topc, s));

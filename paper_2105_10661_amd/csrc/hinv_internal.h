@@ -24,6 +24,7 @@
 namespace hinv {
 
 constexpr int kMaxLeaf = HINV_MAX_LEAF;
+constexpr int kTeamMaxLevels = 4;     // coupling levels of a tree the team engine takes
 constexpr int kMaxModRank = 16;
 constexpr int kBlock = 256;
 
@@ -226,6 +227,8 @@ struct TeamDev {
     const int* w_nx;
     const int* w_nb;
     const int* xrow;     // [T*NX] new-order row of each X row (sorted)
+    const int* w_nxu;    // [T] X rows whose final values the workgroup uses
+    const int* xupd;     // [T*NX] their X positions: G neighbours of own rows and line-loss endpoints
     const int* xzo;      // [T*NX*H] offset of the row's Z values at level h in the xz region, -1: none
     const int* xpm;      // [T*NX*H] columns of that panel
     const int* xpc;      // [T*NX*H] first global column of that panel

@@ -25,9 +25,10 @@ namespace hinv {
 
 constexpr int kTeamThreads = 1024;
 constexpr int kTeamWaves = kTeamThreads / 64;
-constexpr int kGemvChunks = kTeamWaves / 2;   // leaf GEMV: 2 row halves (lanes) x 8 column chunks
+constexpr int kGemvLanes = 8;           // leaf GEMV: lanes per row (column chunks), summed by DPP
 constexpr int kSub = 4;                 // lanes per coupling-column dot product
 static_assert(kMaxLeaf <= kTeamThreads, "one own row per thread in the right-hand side");
+static_assert(kMaxLeaf * kGemvLanes <= kTeamThreads, "one row per group of GEMV lanes");
 
 template <typename TB>
 struct TAcc { using T = float; };
@@ -36,8 +37,8 @@ struct TAcc<double> { using T = double; };
 
 struct TeamLayout {
     size_t blk, sall, zown, xz, uown, ux, acoef;
-    size_t b, v, t, d, part, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, colw, cinv, mdg, red, tz;
-    size_t xrow, xzo, xpm, xpc, ozo, opm, opc, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
+    size_t b, v, t, d, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, colw, cinv, mdg, red, tz;
+    size_t xrow, xupd, xtab, otab, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
     size_t aoff, alo, alen;
     size_t lpa, lpb, loa, lob, mact, lbr, lst, vg, ctl;
     size_t total;
@@ -67,15 +68,8 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     const size_t D = sizeof(double);
     L.b = take(D * NL); L.v = take(D * NL);
     L.t = take(refines ? D * NL : 0); L.d = take(refines ? D * NL : 0);
-    L.part = take(D * kGemvChunks * NL);
     L.xv = take(D * NX); L.xd = take(refines ? D * NX : 0);
-    // s and y live from the coupling levels to the end of an apply, the GEMV partial sums only
-    // before its barrier: they share space where it fits
-    if (2 * nc <= (size_t)kGemvChunks * NL) {
-        L.s = L.part; L.y = L.part + D * nc;
-    } else {
-        L.s = take(D * nc); L.y = take(D * nc);
-    }
+    L.s = take(D * nc); L.y = take(D * nc);
     L.h0 = take(D * T.NB); L.h1 = take(D * T.NB);
     L.hC = take(D * NL); L.gC = take(D * NL);
     L.oval = take(refines ? D * T.NE : 0); L.bg = take(D * T.NB); L.bal = take(D * T.NB);
@@ -84,8 +78,8 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.cinv = take(D * R * R * R); L.mdg = take(D * R);
     L.red = take(D * 2 * kTeamWaves); L.tz = take(D * 2 * R);
     const size_t I = sizeof(int);
-    L.xrow = take(I * NX); L.xzo = take(I * NX * H); L.xpm = take(I * NX * H); L.xpc = take(I * NX * H);
-    L.ozo = take(I * H); L.opm = take(I * H); L.opc = take(I * H);
+    L.xrow = take(I * NX); L.xupd = take(I * NX);
+    L.xtab = take(sizeof(int4) * NX * H); L.otab = take(sizeof(int4) * H);
     L.xpos = take(I * nc); L.cm = take(I * nc); L.cc0 = take(I * nc); L.cso = take(I * nc);
     L.lvlc = take(I * (H + 1));
     L.orp = take(refines ? I * (NL + 1) : 0); L.ocol = take(refines ? I * T.NE : 0);
@@ -116,7 +110,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     const TeamLayout Ly = team_layout<TB>(T, R);
     const int w = blockIdx.x, tid = threadIdx.x;
     const int n = H.n, NL = T.NL, NX = T.NX, Hn = T.H, nc = T.nc;
-    const int lo = T.w_lo[w], nl = T.w_nl[w], nx = T.w_nx[w], nb = T.w_nb[w];
+    const int lo = T.w_lo[w], nl = T.w_nl[w], nx = T.w_nx[w], nb = T.w_nb[w], nxu = T.w_nxu[w];
     TB* blk = (TB*)(L8 + Ly.blk);
     TB* sall = (TB*)(L8 + Ly.sall);
     TB* zown = (TB*)(L8 + Ly.zown);
@@ -128,7 +122,6 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     double* v = (double*)(L8 + Ly.v);
     double* t = (double*)(L8 + Ly.t);
     double* d = (double*)(L8 + Ly.d);
-    double* part = (double*)(L8 + Ly.part);
     double* xv = (double*)(L8 + Ly.xv);
     double* xd = (double*)(L8 + Ly.xd);
     double* s = (double*)(L8 + Ly.s);
@@ -149,12 +142,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     double* red = (double*)(L8 + Ly.red);
     double* tz = (double*)(L8 + Ly.tz);
     int* xrow = (int*)(L8 + Ly.xrow);
-    int* xzo = (int*)(L8 + Ly.xzo);
-    int* xpm = (int*)(L8 + Ly.xpm);
-    int* xpc = (int*)(L8 + Ly.xpc);
-    int* ozo = (int*)(L8 + Ly.ozo);
-    int* opm = (int*)(L8 + Ly.opm);
-    int* opc = (int*)(L8 + Ly.opc);
+    int* xupd = (int*)(L8 + Ly.xupd);
+    int4* xtab = (int4*)(L8 + Ly.xtab);   // per X row and level: Z offset (-1: none), columns, first column
+    int4* otab = (int4*)(L8 + Ly.otab);   // the same for the own rows
     int* xpos = (int*)(L8 + Ly.xpos);
     int* cm = (int*)(L8 + Ly.cm);
     int* cc0 = (int*)(L8 + Ly.cc0);
@@ -206,11 +196,10 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         }
         const int* wxrow = T.xrow + (int64_t)w * NX;
         for (int x = tid; x < nx; x += kTeamThreads) xrow[x] = wxrow[x];
+        for (int q = tid; q < T.w_nxu[w]; q += kTeamThreads) xupd[q] = T.xupd[(int64_t)w * NX + q];
         for (int i = tid; i < nx * Hn; i += kTeamThreads) {
             const int64_t gi = (int64_t)w * NX * Hn + i;
-            xzo[i] = T.xzo[gi];
-            xpm[i] = T.xpm[gi];
-            xpc[i] = T.xpc[gi];
+            xtab[i] = make_int4(T.xzo[gi], T.xpm[gi], T.xpc[gi], 0);
             const int zo = T.xzo[gi];
             if (zo >= 0) {
                 const int P = T.xpan[gi];
@@ -221,7 +210,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         }
         for (int h = 0; h < Hn; ++h) {
             const int zo = T.ozo[w * Hn + h];
-            if (tid == 0) { ozo[h] = zo; opm[h] = T.opm[w * Hn + h]; opc[h] = T.opc[w * Hn + h]; }
+            if (tid == 0) otab[h] = make_int4(zo, T.opm[w * Hn + h], T.opc[w * Hn + h], 0);
             if (zo >= 0) {
                 const int P = T.opan[w * Hn + h], pm = T.opm[w * Hn + h];
                 const TB* zp = gZ + H.pan_zoff[P] + (lo - H.pan_lo[P]);
@@ -326,22 +315,22 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     // one application of the stored inverse (with the active line changes):
     // out (own rows), outx (X rows) from xin (own rows)
     auto apply = [&](const double* xin, double* out, double* outx, int ract, bool want_vm) -> bool {
-        // wavefront w: rows 64*(w / kGemvChunks) + lane, block columns j = w % kGemvChunks (mod kGemvChunks)
-        {
-            const int r = (wave / kGemvChunks) * 64 + lane, c = wave % kGemvChunks;
-            if (r < nl) {
-                TA acc = 0;
-                for (int j = c; j < nl; j += kGemvChunks) acc += (TA)blk[j * nl + r] * (TA)xin[j];
-                part[c * NL + r] = (double)acc;
-            }
-        }
-        __syncthreads();
+        // kGemvLanes lanes per row r = tid / kGemvLanes, lane c of the group takes the block columns
+        // j = c (mod kGemvLanes); the group's partial sums are added by DPP moves (quads, then the
+        // two quads of each half row), and the group's first lane stores the row
         double* X0 = T.X0 + (int64_t)par * n;
-        for (int r = tid; r < nl; r += kTeamThreads) {
-            double val = part[r];
-            for (int q = 1; q < kGemvChunks; ++q) val += part[q * NL + r];
-            out[r] = val;
-            xchg_store(&X0[lo + r], val);
+        {
+            const int r = tid / kGemvLanes, c = tid % kGemvLanes;
+            const bool act = r < nl;    // whole groups of kGemvLanes lanes are active or not
+            TA acc = 0;
+            if (act)
+                for (int j = c; j < nl; j += kGemvLanes) acc += (TA)blk[j * nl + r] * (TA)xin[j];
+            double val = quad_sum((double)acc);
+            val += half_row_mirror(val);
+            if (act && c == 0) {
+                out[r] = val;
+                xchg_store(&X0[lo + r], val);
+            }
         }
         team_arrive(T.sync, w, ++epoch);
         if (sn_step >= 0) {      // source injections of the next step, by the last wavefront, while wavefront 0 polls
@@ -381,29 +370,41 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             }
             __syncthreads();
         }
-        // v -= sum over levels of Z y, on X rows (first nx items) and own rows, kSub lanes per row
-        for (int idx = tid; idx < (nx + nl) * kSub; idx += kTeamThreads) {
+        // v -= sum over levels of Z y, on the X rows whose final values this workgroup uses (G
+        // neighbours, line-loss endpoints: first nxu items) and the own rows, kSub lanes per row; every
+        // level's table entry is loaded first, so that the levels' loads are in flight together.  The
+        // other X rows (coupling-column rows only) keep v0: nothing reads them before the next exchange.
+        for (int idx = tid; idx < (nxu + nl) * kSub; idx += kTeamThreads) {
             const int i = idx / kSub, sub = idx & (kSub - 1);
-            const bool isx = i < nx;
-            const int r = i - nx;
-            double val = isx ? outx[i] : out[r];
-            for (int h = 1; h <= Hn; ++h) {
-                const int zo = isx ? xzo[i * Hn + h - 1] : ozo[h - 1];
-                TA acc = 0;
-                if (zo >= 0) {
-                    const int pm = isx ? xpm[i * Hn + h - 1] : opm[h - 1];
-                    const int pc = isx ? xpc[i * Hn + h - 1] : opc[h - 1];
+            const bool isx = i < nxu;
+            const int x = isx ? xupd[i] : 0, r = i - nxu;
+            int4 tb[kTeamMaxLevels];
+#pragma unroll
+            for (int h = 0; h < kTeamMaxLevels; ++h)
+                if (h < Hn) tb[h] = isx ? xtab[x * Hn + h] : otab[h];
+            TA acc[kTeamMaxLevels];
+#pragma unroll
+            for (int h = 0; h < kTeamMaxLevels; ++h) {
+                acc[h] = 0;
+                if (h < Hn && tb[h].x >= 0) {
+                    const int zo = tb[h].x, pm = tb[h].y, pc = tb[h].z;
                     if (isx) {
-                        for (int j = sub; j < pm; j += kSub) acc += (TA)xz[zo + j] * (TA)y[pc + j];
+                        for (int j = sub; j < pm; j += kSub) acc[h] += (TA)xz[zo + j] * (TA)y[pc + j];
                     } else {
-                        for (int j = sub; j < pm; j += kSub) acc += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
+                        for (int j = sub; j < pm; j += kSub) acc[h] += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
                     }
                 }
-                acc = quad_sum(acc);
-                if (zo >= 0) val -= (double)acc;
+            }
+            double val = isx ? outx[x] : out[r];
+#pragma unroll
+            for (int h = 0; h < kTeamMaxLevels; ++h) {
+                if (h < Hn) {
+                    const TA a = quad_sum(acc[h]);
+                    if (tb[h].x >= 0) val -= (double)a;
+                }
             }
             if (sub == 0) {
-                if (isx) outx[i] = val;
+                if (isx) outx[x] = val;
                 else out[r] = val;
             }
         }
@@ -423,7 +424,8 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 for (int j = 0; j < ract; ++j) acc += (double)uown[j * NL + r] * tz[R + j];
                 out[r] -= acc;
             }
-            for (int x = tid; x < nx; x += kTeamThreads) {
+            for (int q = tid; q < nxu; q += kTeamThreads) {
+                const int x = xupd[q];
                 double acc = 0.0;
                 for (int j = 0; j < ract; ++j) acc += (double)ux[j * NX + x] * tz[R + j];
                 outx[x] -= acc;

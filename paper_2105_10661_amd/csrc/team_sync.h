@@ -52,6 +52,15 @@ __device__ __forceinline__ T quad_sum(T a)
     return a;
 }
 
+// Value of lane 7 - i of the same eight lanes (DPP row_half_mirror, 0x141): after quad_sum, adding
+// it gives the sum over the eight lanes in every one of them.
+__device__ __forceinline__ double half_row_mirror(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x141, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x141, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // The barrier in two halves, so that a workgroup can do work that no other workgroup waits for
 // while its wavefront 0 polls.  team_arrive: this workgroup's stores have completed, then its flag
 // is raised (flags: the team's T flags; me: this workgroup's flag).
