@@ -1388,7 +1388,8 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
         return fail(HINV_E_INVALID, "the level engine needs FP64/FP32, one case, <= 256 leaves of <= %d rows and "
                     "tables that fit LDS", HINV_MAX_LEAF);
     if (mode == 3 && !c.team_ok)
-        return fail(HINV_E_INVALID, "the team engine needs FP64/FP32, one case, <= 256 leaves and fitting LDS");
+        return fail(HINV_E_INVALID, "the team engine needs FP64/FP32, one case, <= 256 leaves, <= %d coupling "
+                    "levels and fitting LDS", kTeamMaxLevels);
     if (mode == 4 && !c.panel_ok)
         return fail(HINV_E_INVALID, "the panel engine needs FP64/FP32, max_mod_rank <= %d, leaves of <= 96 rows, <= 256 leaves and "
                     "coupling columns, and tables that fit LDS", kPanelMaxRank);

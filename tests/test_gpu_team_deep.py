@@ -1,0 +1,75 @@
+"""GPU parity of the team engine on trees with three and four coupling levels (the 179-bus network,
+bisection trees of leaf size 24 and 12).  Each coupling column's sum is formed in one phase from the
+leaf results through a precomputed row that folds in the corrections of every lower level, so these
+trees check that fold through more than one level; the benchmark trees have two.
+
+* FP64 and FP32 + FP64 refinement against the oracle (1e-10, normalised by the peak voltage), with a
+  line loss and a 10 ohm fault to ground switched on and off (the rows are rebuilt after each
+  switching).
+* A tree with five coupling levels is refused by the team engine with a clear error.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10661_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+N_STEPS, LOSS, ON, OFF = 400, 100, 150, 300
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    from paper_2105_10661_amd import hinv
+    torch.cuda.set_device(0)
+    hinv.load()
+    return hinv
+
+
+def _net(d_th):
+    net = cases.net_179()
+    parent, leaf = cases.threshold_tree(net.pos, d_th)
+    return dataclasses.replace(net, parent=parent, bus_leaf=leaf)
+
+
+_REF = {}
+
+
+def _reference(d_th):
+    if d_th not in _REF:
+        net = _net(d_th)
+        ch = [(ON, 1, -1, 0.1), (OFF, 1, -1, -0.1)]
+        _REF[d_th] = oracle.emt_run(net, N_STEPS, loss_steps=[LOSS], loss_branches=[5], solver="lu",
+                                    changes=ch)[0]
+    return _REF[d_th]
+
+
+@pytest.mark.parametrize("d_th", [24, 12])
+@pytest.mark.parametrize("prec,refine,warm", [("fp64", 0, False), ("fp32", 2, True)])
+def test_team_deep_tree_with_loss_and_fault(hv, d_th, prec, refine, warm):
+    import torch
+    net = _net(d_th)
+    print(f"[gpu] team engine, leaf size {d_th}, {prec}", flush=True)
+    emt = hv.EMT(net, 1, losses=[[(LOSS, 5)]], prec=prec, max_refine=refine, warm_start=warm,
+                 max_mod_rank=2, kernel_mode="team")
+    V1, _ = emt.step(ON - 1)
+    emt.update_line(1, -1, 0.1)
+    V2, _ = emt.step(OFF - ON)
+    emt.update_line(1, -1, -0.1)
+    V3, _ = emt.step(N_STEPS - OFF + 1)
+    V = torch.cat([V1, V2, V3])[:, 0, :].cpu().numpy()
+    emt.sync_status()
+    emt.close()
+    ref = _reference(d_th)
+    assert np.abs(V - ref).max() / np.abs(ref).max() <= 1e-10
+
+
+def test_team_refuses_five_levels(hv):
+    net = _net(6)
+    with pytest.raises(hv.HinvError) as ex:
+        hv.EMT(net, 1, kernel_mode="team")
+    assert ex.value.name == "INVALID"
