@@ -8,6 +8,7 @@ rebuild of Algorithm 2.
   (1e-10, normalised by the peak voltage), FP64 and FP32 + FP64 refinement, for a ground fault, a
   fault across a line inside a leaf and one across a line between two leaves, with line losses
   of the cases before and during the fault.
+* Four line losses active together with a fault (the general SMW path) on four engines.
 * A change that makes some case's G indefinite is refused and leaves the context as it was: the
   trajectory goes on bit for bit as if the call had not been made.
 """
@@ -145,3 +146,28 @@ def test_refused_change_leaves_the_run_unchanged(hv, mode, n_cases):
     emt.sync_status()
     emt.close()
     ref.close()
+
+
+@pytest.mark.parametrize("mode", ["team", "level", "fused", "per_kernel"])
+def test_four_line_losses_and_a_fault(hv, mode):
+    """Rank-4 line changes (the general SMW path, beyond the rank-2 fast paths) active together
+    with a fault switched on and off, against the oracle (1e-10, FP64)."""
+    import torch
+    net = _net()
+    a, b = _fault(net, "ground")
+    br = [e for e in range(net.n_branch) if 1 not in (int(net.frm[e]), int(net.to[e]))]
+    losses = [[(60, br[3]), (90, br[40]), (90, br[77]), (130, br[150])]]
+    print(f"[gpu] four losses and a fault, engine={mode}", flush=True)
+    emt = hv.EMT(net, 1, losses=losses, prec="fp64", max_refine=0, max_mod_rank=4, kernel_mode=mode)
+    V1, _ = emt.step(99)
+    emt.update_line(a, b, G_FAULT)
+    V2, _ = emt.step(100)
+    emt.update_line(a, b, -G_FAULT)
+    V3, _ = emt.step(101)
+    V = torch.cat([V1, V2, V3])[:, 0, :].cpu().numpy()
+    emt.sync_status()
+    emt.close()
+    lst = losses[0]
+    ref = oracle.emt_run(net, 300, loss_steps=[s for s, _ in lst], loss_branches=[e for _, e in lst], solver="lu",
+                         changes=[(100, a, b, G_FAULT), (200, a, b, -G_FAULT)])[0]
+    assert np.abs(V - ref).max() / np.abs(ref).max() <= 1e-10
