@@ -1109,7 +1109,7 @@ struct emt_ctx {
     // team engine
     bool team_ok = false;
     int team_nx_cap = 0;
-    std::vector<int> tw_nxu, txupd;   // team: X rows whose final values a workgroup uses
+    std::vector<int> tw_nxu, txupd, tuzo;   // team: X rows whose final values a workgroup uses
     std::vector<int> tw_lo, tw_nl, tw_nx, tw_nb, txrow, txzo, txpm, txpc, tozo, topm, topc, topan, txpan, txpos, torp,
         tocol, tbglob, tbf, tbt, tbown, tiptr, tibr, tsptr;
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
@@ -1425,6 +1425,8 @@ bool build_team_plan(emt_ctx& c, int R)
     }
     struct W {
         std::vector<int> xupd;       // X positions of G neighbours of own rows and of line-loss endpoints
+        std::vector<int> uzo;        // [xupd.size()*H] their Z values' offsets in LDS, -1: none
+        int xzu = 0;
         std::vector<int> xrow, xzo, xpm, xpc, xpan, ozo, opm, opc, opan, xpos, orp, ocol, bglob, bf, bt, bown, iptr, ibr,
             sptr;
         std::vector<double> oval, bg, bal, samp, sph;
@@ -1432,6 +1434,7 @@ bool build_team_plan(emt_ctx& c, int R)
         int xz = 0, zo = 0;
     };
     std::vector<W> ws(L);
+    int XZU = 1;
     int NL = 1, NX = 1, NB = 1, NE = 1, NI = 1, NS = 1, XZ = 1, ZO = 1;
     for (int l = 0; l < L; ++l) {
         W& w = ws[l];
@@ -1475,6 +1478,14 @@ bool build_team_plan(emt_ctx& c, int R)
         for (int r : loss_rows) w.xupd.push_back(xpos_of(r));   // the SMW reads endpoints as X rows
         std::sort(w.xupd.begin(), w.xupd.end());
         w.xupd.erase(std::unique(w.xupd.begin(), w.xupd.end()), w.xupd.end());
+        w.uzo.assign(w.xupd.size() * (size_t)H, -1);
+        for (size_t q = 0; q < w.xupd.size(); ++q)
+            for (int h = 0; h < H; ++h) {
+                const size_t xi = (size_t)w.xupd[q] * H + h;
+                if (w.xzo[xi] < 0) continue;
+                w.uzo[q * H + h] = w.xzu;
+                w.xzu += w.xpm[xi];
+            }
         w.orp.assign(nl + 1, 0);
         for (int r = lo; r < lo + nl; ++r) {
             for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
@@ -1513,11 +1524,13 @@ bool build_team_plan(emt_ctx& c, int R)
         NL = std::max(NL, nl); NX = std::max(NX, nx); NB = std::max(NB, (int)br.size());
         NE = std::max(NE, (int)w.ocol.size()); NI = std::max(NI, (int)w.ibr.size());
         NS = std::max(NS, (int)w.samp.size()); XZ = std::max(XZ, w.xz); ZO = std::max(ZO, w.zo);
+        XZU = std::max(XZU, w.xzu);
     }
     (void)n;
     if (c.team_nx_cap > 0 && NX > c.team_nx_cap) return false;
     TeamDev& D = c.TD;
     D.T = L; D.H = H; D.NL = NL; D.NX = NX; D.NB = NB; D.NE = NE; D.NI = NI; D.NS = NS; D.XZ = XZ; D.ZO = ZO;
+    D.XZU = XZU;
     D.nc = NC;
     // S^{-1} of every node in LDS with rows padded to m+1 (breaks LDS bank aliasing of the row stride)
     c.tcsop.assign(NC, 0);
@@ -1597,6 +1610,7 @@ bool build_team_plan(emt_ctx& c, int R)
     // X-row tables use the capacity stride so that a later rebuild fits the carve
     flat(c.txrow, NXc, [](W& w) -> std::vector<int>& { return w.xrow; });
     flat(c.txupd, NXc, [](W& w) -> std::vector<int>& { return w.xupd; });
+    flat(c.tuzo, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.uzo; });
     flat(c.txzo, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xzo; });
     flat(c.txpm, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpm; });
     flat(c.txpc, (size_t)NXc * H, [](W& w) -> std::vector<int>& { return w.xpc; });
@@ -1634,7 +1648,7 @@ void carve_team(emt_ctx& c, Arena& A)
     auto ti = [&](size_t cnt) { return A.take<int>((int64_t)cnt); };
     auto td = [&](size_t cnt) { return A.take<double>((int64_t)cnt); };
     D.w_lo = ti(L); D.w_nl = ti(L); D.w_nx = ti(L); D.w_nb = ti(L);
-    D.w_nxu = ti(L); D.xupd = ti(L * D.NX);
+    D.w_nxu = ti(L); D.xupd = ti(L * D.NX); D.uzo = ti(L * D.NX * H);
     D.xrow = ti(L * D.NX); D.xzo = ti(L * D.NX * H); D.xpm = ti(L * D.NX * H); D.xpc = ti(L * D.NX * H);
     D.xpan = ti(L * D.NX * H);
     D.ozo = ti(L * H); D.opm = ti(L * H); D.opc = ti(L * H); D.opan = ti(L * H);
@@ -2164,6 +2178,7 @@ hinv_status upload_team(emt_ctx& c, hipStream_t s)
     TeamDev& D = c.TD;
     HIP_TRY(up(D.w_lo, c.tw_lo, s)); HIP_TRY(up(D.w_nl, c.tw_nl, s)); HIP_TRY(up(D.w_nx, c.tw_nx, s));
     HIP_TRY(up(D.w_nb, c.tw_nb, s)); HIP_TRY(up(D.w_nxu, c.tw_nxu, s)); HIP_TRY(up(D.xupd, c.txupd, s));
+    HIP_TRY(up(D.uzo, c.tuzo, s));
     HIP_TRY(up(D.xrow, c.txrow, s)); HIP_TRY(up(D.xzo, c.txzo, s)); HIP_TRY(up(D.xpm, c.txpm, s));
     HIP_TRY(up(D.xpc, c.txpc, s)); HIP_TRY(up(D.xpan, c.txpan, s));
     HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.opc, c.topc, s));

@@ -229,6 +229,8 @@ struct TeamDev {
     const int* xrow;     // [T*NX] new-order row of each X row (sorted)
     const int* w_nxu;    // [T] X rows whose final values the workgroup uses
     const int* xupd;     // [T*NX] their X positions: G neighbours of own rows and line-loss endpoints
+    const int* uzo;      // [T*NX*H] offset of those rows' Z values at each level in LDS, -1: none
+    int XZU;             // LDS entries of those Z values
     const int* xzo;      // [T*NX*H] offset of the row's Z values at level h in the xz region, -1: none
     const int* xpm;      // [T*NX*H] columns of that panel
     const int* xpc;      // [T*NX*H] first global column of that panel

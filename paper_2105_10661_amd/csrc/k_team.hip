@@ -38,7 +38,7 @@ struct TAcc<double> { using T = double; };
 struct TeamLayout {
     size_t blk, sall, zown, xz, uown, ux, acoef;
     size_t b, v, t, d, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, colw, cinv, mdg, red, tz;
-    size_t xrow, xupd, xtab, otab, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
+    size_t xrow, xupd, utab, otab, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
     size_t aoff, alo, alen;
     size_t lpa, lpb, loa, lob, mact, lbr, lst, vg, ctl;
     size_t total;
@@ -61,7 +61,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.blk = take(sizeof(TB) * NL * NL);
     L.sall = take(sizeof(TB) * (size_t)T.sent);
     L.zown = take(sizeof(TB) * (size_t)T.ZO);
-    L.xz = take(sizeof(TB) * (size_t)T.XZ);
+    L.xz = take(sizeof(TB) * (size_t)T.XZU);
     L.uown = take(sizeof(TB) * R * NL);
     L.ux = take(sizeof(TB) * R * NX);
     L.acoef = take(sizeof(TB) * (size_t)T.nA);
@@ -79,7 +79,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.red = take(D * 2 * kTeamWaves); L.tz = take(D * 2 * R);
     const size_t I = sizeof(int);
     L.xrow = take(I * NX); L.xupd = take(I * NX);
-    L.xtab = take(sizeof(int4) * NX * H); L.otab = take(sizeof(int4) * H);
+    L.utab = take(sizeof(int4) * NX * H); L.otab = take(sizeof(int4) * H);
     L.xpos = take(I * nc); L.cm = take(I * nc); L.cc0 = take(I * nc); L.cso = take(I * nc);
     L.lvlc = take(I * (H + 1));
     L.orp = take(refines ? I * (NL + 1) : 0); L.ocol = take(refines ? I * T.NE : 0);
@@ -143,7 +143,8 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     double* tz = (double*)(L8 + Ly.tz);
     int* xrow = (int*)(L8 + Ly.xrow);
     int* xupd = (int*)(L8 + Ly.xupd);
-    int4* xtab = (int4*)(L8 + Ly.xtab);   // per X row and level: Z offset (-1: none), columns, first column
+    int4* utab = (int4*)(L8 + Ly.utab);   // per updated X row and level: Z offset (-1: none), columns,
+                                          // first column, X position
     int4* otab = (int4*)(L8 + Ly.otab);   // the same for the own rows
     int* xpos = (int*)(L8 + Ly.xpos);
     int* cm = (int*)(L8 + Ly.cm);
@@ -197,15 +198,16 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         const int* wxrow = T.xrow + (int64_t)w * NX;
         for (int x = tid; x < nx; x += kTeamThreads) xrow[x] = wxrow[x];
         for (int q = tid; q < T.w_nxu[w]; q += kTeamThreads) xupd[q] = T.xupd[(int64_t)w * NX + q];
-        for (int i = tid; i < nx * Hn; i += kTeamThreads) {
-            const int64_t gi = (int64_t)w * NX * Hn + i;
-            xtab[i] = make_int4(T.xzo[gi], T.xpm[gi], T.xpc[gi], 0);
-            const int zo = T.xzo[gi];
+        for (int i = tid; i < nxu * Hn; i += kTeamThreads) {     // updated X rows: tables and Z values
+            const int q = i / Hn, h = i - q * Hn;
+            const int x = T.xupd[(int64_t)w * NX + q];
+            const int64_t gi = ((int64_t)w * NX + x) * Hn + h;
+            const int zo = T.uzo[(int64_t)w * NX * Hn + i], pm = T.xpm[gi];
+            utab[i] = make_int4(zo, pm, T.xpc[gi], x);
             if (zo >= 0) {
                 const int P = T.xpan[gi];
-                const int row = wxrow[i / Hn];
-                const TB* zp = gZ + H.pan_zoff[P] + (row - H.pan_lo[P]);
-                for (int j = 0; j < T.xpm[gi]; ++j) xz[zo + j] = zp[(int64_t)j * H.pan_n[P]];
+                const TB* zp = gZ + H.pan_zoff[P] + (wxrow[x] - H.pan_lo[P]);
+                for (int j = 0; j < pm; ++j) xz[zo + j] = zp[(int64_t)j * H.pan_n[P]];
             }
         }
         for (int h = 0; h < Hn; ++h) {
@@ -374,14 +376,15 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         // neighbours, line-loss endpoints: first nxu items) and the own rows, kSub lanes per row; every
         // level's table entry is loaded first, so that the levels' loads are in flight together.  The
         // other X rows (coupling-column rows only) keep v0: nothing reads them before the next exchange.
-        for (int idx = tid; idx < (nxu + nl) * kSub; idx += kTeamThreads) {
+        for (int idx = tid; Hn > 0 && idx < (nxu + nl) * kSub; idx += kTeamThreads) {
             const int i = idx / kSub, sub = idx & (kSub - 1);
             const bool isx = i < nxu;
-            const int x = isx ? xupd[i] : 0, r = i - nxu;
+            const int r = i - nxu;
             int4 tb[kTeamMaxLevels];
 #pragma unroll
             for (int h = 0; h < kTeamMaxLevels; ++h)
-                if (h < Hn) tb[h] = isx ? xtab[x * Hn + h] : otab[h];
+                if (h < Hn) tb[h] = isx ? utab[i * Hn + h] : otab[h];
+            const int x = tb[0].w;
             TA acc[kTeamMaxLevels];
 #pragma unroll
             for (int h = 0; h < kTeamMaxLevels; ++h) {
