@@ -388,6 +388,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner over the contingency batch")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving workload (Poisson arrivals of mixed-size cases)")
     ap.add_argument("--serve-cases", type=int, default=64)
@@ -527,6 +528,33 @@ def main():
                     batch[f"{eng}_{name}"]["mfma_leaf_tflops"] = round(tf, 3)
                     batch[f"{eng}_{name}"]["mfma_peak_tflops"] = peak
                     batch[f"{eng}_{name}"]["mfma_frac"] = round(tf / peak, 5)
+        if not args.no_tune:
+            # autotuner: leaf size (the tiles of the leaf products) x engine x precision path, timed on the
+            # device over the same cases; then the choice is timed like the rows above
+            from paper_2105_10661_amd import tune
+            fine = cases.net_ring(8, 4, copy_levels=2)
+            assert np.array_equal(fine.frm, base.frm) and np.array_equal(fine.R, base.R)
+            trees = {"2 leaves per copy": (base.parent, base.bus_leaf),
+                     "4 leaves per copy": (fine.parent, fine.bus_leaf)}
+            t0 = time.perf_counter()
+            tr = tune.tune(base, trees, n_cases=args.batch_cases, losses=bl, max_mod_rank=1, rel_tol=args.rel_tol,
+                           gate_steps=args.batch_steps, horizon=8000, timed_steps=200, reps=3, cache=None)
+            tune_s = time.perf_counter() - t0
+            ch = tr.choice
+            batch["tuner"] = {
+                "wall_s": round(tune_s, 2),
+                "gate": f"voltages of every case over the first {args.batch_steps} steps against the library's "
+                        "FP64 path (peak-normalised), extrapolated linearly to 8000 steps, within 1e-10",
+                "candidates": [{"label": r["label"], "us_per_step": None if r["us_per_step"] is None
+                                else round(r["us_per_step"], 2), "err": r["err"], "status": r["status"],
+                                "refused": r["reason"][:80] if not r["feasible"] else None} for r in tr.table()],
+                "choice": None if ch is None else ch.label()}
+            if ch is not None:
+                tnet = tune.with_tree(base, *trees[ch.tree])
+                r = timed_run(hinv, torch, tnet, bl, ch.prec, ch.warm, 0, args.batch_steps, args.chunk, ch.max_refine,
+                              args.rel_tol, False, khz, kernel_mode=ch.engine, max_mod_rank=1)
+                batch["tuned"], _ = summary(r, ch.prec)
+                batch["tuned"]["config"] = ch.label()
         if record:
             # accuracy of the batched mixed panel path: sampled cases against full oracle trajectories
             import oracle

@@ -316,9 +316,10 @@ def net_179(seed: int = 1) -> Network:
     return tiled_network("179-bus", 1, 1, seed, copy_levels=2)
 
 
-def net_ring(n_copies: int, seed: int) -> Network:
-    """n_copies on a ring, 3 tie lines per neighbouring pair; leaves = copy halves."""
-    return tiled_network(f"{n_copies * BASE_BUSES}-bus ring", 1, n_copies, seed, copy_levels=1)
+def net_ring(n_copies: int, seed: int, copy_levels: int = 1) -> Network:
+    """n_copies on a ring, 3 tie lines per neighbouring pair; leaves = copy halves (2**copy_levels
+    leaves per copy; the network itself does not depend on copy_levels)."""
+    return tiled_network(f"{n_copies * BASE_BUSES}-bus ring", 1, n_copies, seed, copy_levels=copy_levels)
 
 
 MUTUAL_RATIO = 0.3      # three-phase lines: mutual inductance between phases / self inductance

@@ -378,6 +378,23 @@ class Chol:
             pass
 
 
+def emt_workspace_bytes(net, n_cases: int = 1, losses=None, prec="fp64", rel_tol=1e-9, max_refine=2,
+                        max_mod_rank=2, warm_start=False, kernel_mode="auto") -> int:
+    """Device workspace an EMT context of these arguments needs (emt_workspace_size, host only).
+
+    Raises HinvError when the arguments are refused, e.g. a kernel_mode whose engine cannot take the
+    network (leaf or LDS limits)."""
+    lib = load()
+    na = _NetArrays(net)
+    ptr, st, br = _case_arrays(int(n_cases), losses)
+    cs = _Cases(int(n_cases), _ptr(ptr), _ptr(st), _ptr(br))
+    opt = _options(prec, rel_tol, max_refine, max_mod_rank, 1, warm_start, kernel_mode)
+    nb = ctypes.c_size_t(0)
+    _check(lib.emt_workspace_size(ctypes.byref(na.s), ctypes.byref(na.tree), ctypes.byref(opt), ctypes.byref(cs),
+                                  ctypes.byref(nb)), "emt_workspace_size")
+    return nb.value
+
+
 class EMT:
     """EMT time stepping of n_cases cases sharing one network (emt_create / emt_step).
 

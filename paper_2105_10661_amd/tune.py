@@ -1,0 +1,305 @@
+"""Autotuner of the EMT time loop's launch configuration.
+
+For one network, case count and loss schedule it picks, by timing on the device:
+
+- the partition tree among the caller's candidates.  The leaf blocks are the tiles of every leaf
+  product: in the panel engine a leaf of m rows is an m x m by m x 16 product on the matrix cores
+  (16x16x4 MFMA tiles), in the other engines an m x m GEMV per case.  Smaller leaves mean fewer leaf
+  flops but more coupling columns and levels, the trade-off of the leaf-size threshold of the
+  hierarchy (Section III.B);
+- the engine (the schedule of a step): 16-case panels with one workgroup per leaf and per panel
+  (``panel``), one workgroup per case (``fused``), one cooperative team per case (``team``, ``level``)
+  or one launch per phase (``per_kernel``);
+- the precision path: FP64, or FP32 applies with FP64 residual refinement and a fixed number of
+  corrections per step (warm start from the previous step's voltages).
+
+A candidate is kept only if the library accepts it (``emt_workspace_size``, host only: leaf, column
+and LDS limits of the engine) and if its voltages over the first ``gate_steps`` steps, compared with
+the FP64 path of the same library on the same tree (every case, bus and step, normalised by the
+peak voltage) and extrapolated linearly to the run's ``horizon``, stay within ``gate``.  The fastest
+kept candidate wins.  Every measurement runs in the library's kernels; this module only times them
+and compares their outputs.
+
+Results persist as JSON, keyed by the network (branch endpoints, tree candidates), the cases, the
+device name and the library binary, so a later call with the same key returns the stored choice
+without timing anything.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from dataclasses import asdict, dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import hinv
+
+SINGLE_CASE_ENGINES = ("team", "level", "fused", "per_kernel")
+BATCH_ENGINES = ("panel", "fused")
+# (precision, corrections per step, warm start)
+DEFAULT_PATHS = (("fp64", 0, False), ("fp32", 1, True), ("fp32", 2, True))
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2105_10661_amd", "tune.json")
+
+
+@dataclass(frozen=True)
+class Candidate:
+    tree: str
+    engine: str
+    prec: str
+    max_refine: int
+    warm: bool
+
+    def label(self) -> str:
+        p = "fp64" if self.prec == "fp64" else f"{self.prec}+{self.max_refine}ir"
+        return f"{self.tree}/{self.engine}/{p}"
+
+
+@dataclass
+class Row:
+    cand: Candidate
+    feasible: bool
+    reason: str = ""
+    workspace_mb: float = 0.0
+    us_per_step: float = float("inf")
+    solves_per_s: float = 0.0
+    err: float = float("inf")
+    applies_per_step: float = 0.0
+    status: str = ""
+
+    def to_json(self) -> dict:
+        d = asdict(self)
+        d["cand"] = asdict(self.cand)
+        d["label"] = self.cand.label()
+        for k in ("us_per_step", "err"):
+            if not np.isfinite(d[k]):
+                d[k] = None
+        return d
+
+    @staticmethod
+    def from_json(d: dict) -> "Row":
+        d = dict(d)
+        d.pop("label", None)
+        d["cand"] = Candidate(**d["cand"])
+        for k in ("us_per_step", "err"):
+            if d[k] is None:
+                d[k] = float("inf")
+        return Row(**d)
+
+
+@dataclass
+class TuneResult:
+    key: str
+    choice: Optional[Candidate]
+    rows: List[Row] = field(default_factory=list)
+    cached: bool = False
+    gate: float = 1e-10
+
+    def best(self) -> Optional[Row]:
+        for r in self.rows:
+            if self.choice is not None and r.cand == self.choice:
+                return r
+        return None
+
+    def table(self) -> List[dict]:
+        return [r.to_json() for r in self.rows]
+
+
+def enumerate_candidates(trees: Sequence[str], engines: Sequence[str],
+                         paths: Sequence[Tuple[str, int, bool]]) -> List[Candidate]:
+    return [Candidate(t, e, p, int(mr), bool(w)) for t in trees for e in engines for (p, mr, w) in paths]
+
+
+def select(rows: Sequence[Row], gate: float) -> Optional[Candidate]:
+    """Fastest candidate that the library accepted, that ran without a device error and whose error
+    against the FP64 reference is within the gate; ties go to the earlier candidate.  A device report
+    that a step's last correction stayed above rel_tol (NO_CONVERGENCE) does not exclude a candidate:
+    its measured error decides."""
+    best = None
+    for r in rows:
+        if not r.feasible or r.status not in ("ok", "NO_CONVERGENCE") or not (r.err <= gate) \
+                or not np.isfinite(r.us_per_step):
+            continue
+        if best is None or r.us_per_step < best.us_per_step:
+            best = r
+    return None if best is None else best.cand
+
+
+def with_tree(net, parent, bus_leaf):
+    """The same network with another partition tree."""
+    import copy
+    out = copy.copy(net)
+    out.parent = np.ascontiguousarray(parent, np.int32)
+    out.bus_leaf = np.ascontiguousarray(bus_leaf, np.int32)
+    return out
+
+
+def cache_key(net, trees: Dict[str, Tuple[np.ndarray, np.ndarray]], losses, max_mod_rank: int,
+              engines: Sequence[str], paths, gate: float, device_name: str, lib_path: str) -> str:
+    h = hashlib.sha1()
+    for a in (net.frm, net.to, net.R, net.L, net.C, net.src_bus):
+        h.update(np.ascontiguousarray(a).tobytes())
+    for name in sorted(trees):
+        h.update(name.encode())
+        for a in trees[name]:
+            h.update(np.ascontiguousarray(a, np.int32).tobytes())
+    h.update(json.dumps([losses, max_mod_rank, list(engines), [list(p) for p in paths], gate,
+                         device_name]).encode())
+    with open(lib_path, "rb") as f:
+        h.update(hashlib.sha1(f.read()).digest())
+    return h.hexdigest()
+
+
+def load_cache(path: str) -> dict:
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path: str, key: str, res: TuneResult) -> None:
+    d = load_cache(path)
+    d[key] = {"choice": None if res.choice is None else asdict(res.choice), "rows": res.table(), "gate": res.gate}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1)
+    os.replace(tmp, path)
+
+
+def from_cache(path: str, key: str) -> Optional[TuneResult]:
+    e = load_cache(path).get(key)
+    if not e:
+        return None
+    choice = None if e["choice"] is None else Candidate(**e["choice"])
+    return TuneResult(key, choice, [Row.from_json(r) for r in e["rows"]], cached=True, gate=e.get("gate", 1e-10))
+
+
+def check_feasible(net, cand: Candidate, n_cases: int, losses, max_mod_rank: int, rel_tol: float) -> Row:
+    try:
+        nb = hinv.emt_workspace_bytes(net, n_cases, losses, prec=cand.prec, rel_tol=rel_tol,
+                                      max_refine=cand.max_refine, max_mod_rank=max_mod_rank, warm_start=cand.warm,
+                                      kernel_mode=cand.engine)
+    except hinv.HinvError as e:
+        return Row(cand, False, reason=str(e))
+    return Row(cand, True, workspace_mb=round(nb / 2**20, 2))
+
+
+def _emt(net, cand: Candidate, n_cases, losses, max_mod_rank, rel_tol):
+    return hinv.EMT(net, n_cases, losses=losses, prec=cand.prec, max_refine=cand.max_refine, rel_tol=rel_tol,
+                    max_mod_rank=max_mod_rank, warm_start=cand.warm, kernel_mode=cand.engine)
+
+
+def _status(emt) -> str:
+    try:
+        emt.sync_status()
+        return "ok"
+    except hinv.HinvError as e:
+        return e.name
+
+
+def _run(net, cand: Candidate, ref_net, ref_cand: Candidate, n_cases, losses, max_mod_rank, rel_tol, gate_steps,
+         chunk, timed_steps, reps):
+    """One candidate.  Gate: gate_steps steps of the candidate and of the FP64 reference in lockstep
+    chunks, max |v - v_ref| over every case, bus and step divided by max |v_ref| (this is also the
+    warm-up).  Then `reps` timed launches of timed_steps each (HIP events on the launch stream).
+    Returns (us per step, error, applies per step, status of the candidate, status of the reference)."""
+    import torch
+    emt = _emt(net, cand, n_cases, losses, max_mod_rank, rel_tol)
+    try:
+        same = cand == ref_cand
+        ref = None if same else _emt(ref_net, ref_cand, n_cases, losses, max_mod_rank, rel_tol)
+        dmax, peak, done = 0.0, 0.0, 0
+        try:
+            while done < gate_steps:
+                k = min(chunk, gate_steps - done)
+                V, _ = emt.step(k, record_v=True)
+                if ref is not None:
+                    Vr, _ = ref.step(k, record_v=True)
+                    # recorded rows are in original bus order for every engine and tree
+                    dmax = max(dmax, float((V - Vr).abs().max().item()))
+                    peak = max(peak, float(Vr.abs().max().item()))
+                    del Vr
+                del V
+                done += k
+            ref_status = "ok" if ref is None else _status(ref)
+        finally:
+            if ref is not None:
+                ref.close()
+        err = 0.0 if same else (dmax / peak if peak > 0 else float("inf"))
+        s = torch.cuda.current_stream()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            emt.step(timed_steps, record_v=False)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        applies, _ = emt.stats()
+        status = _status(emt)
+        aps = applies / (n_cases * (gate_steps + reps * timed_steps))
+        us = float(np.median(ms)) * 1e3 / timed_steps
+        return us, err, aps, status, ref_status
+    finally:
+        emt.close()
+
+
+def tune(net, trees: Optional[Dict[str, Tuple[np.ndarray, np.ndarray]]] = None, n_cases: int = 1, losses=None,
+         engines: Optional[Sequence[str]] = None, paths: Sequence[Tuple[str, int, bool]] = DEFAULT_PATHS,
+         max_mod_rank: int = 2, rel_tol: float = 1e-9, gate: float = 1e-10, gate_steps: int = 1000,
+         horizon: Optional[int] = None, chunk: int = 250, timed_steps: int = 200, reps: int = 3,
+         cache: Optional[str] = DEFAULT_CACHE, refresh: bool = False, log=None) -> TuneResult:
+    """Pick the fastest accurate configuration for n_cases cases of `net` (see the module docstring).
+
+    trees: label -> (parent, bus_leaf); default: the network's own tree, labelled "given".
+    losses: per case a list of (step, branch), as for hinv.EMT; losses inside the first gate_steps
+    steps make the gate cover the rank-r corrections.
+    horizon: steps the cases will run.  The trajectory error of a low-precision path grows with the
+    step count (the trapezoidal step map has an eigenvalue of 1), so a candidate passes only if its
+    gate error, extrapolated linearly from gate_steps to the horizon, stays within `gate`.
+    cache: JSON file of earlier results (None: no cache); refresh: time again even if cached.
+    """
+    import torch
+    if trees is None:
+        trees = {"given": (net.parent, net.bus_leaf)}
+    if engines is None:
+        engines = BATCH_ENGINES if n_cases > 1 else SINGLE_CASE_ENGINES
+    if losses is None:
+        losses = [[] for _ in range(n_cases)]
+    losses = [[(int(s), int(b)) for (s, b) in lst] for lst in losses]
+    horizon = max(int(horizon or gate_steps), gate_steps)
+    scale = horizon / gate_steps
+    key = cache_key(net, trees, losses, max_mod_rank, engines, paths, gate,
+                    f"{torch.cuda.get_device_name()} gate {gate_steps} horizon {horizon}", hinv.LIB_PATH)
+    if cache and not refresh:
+        hit = from_cache(cache, key)
+        if hit is not None:
+            return hit
+    nets = {name: with_tree(net, *tr) for name, tr in trees.items()}
+    rows = [check_feasible(nets[c.tree], c, n_cases, losses, max_mod_rank, rel_tol)
+            for c in enumerate_candidates(list(trees), engines, paths)]
+    # FP64 reference of the same library on the candidate's own tree (its first feasible FP64 engine, else
+    # auto): two exact FP64 trees drift apart by rounding along the recursion's unit eigenvalue, which is
+    # not an error of either
+    ref_cands = {t: next((r.cand for r in rows if r.feasible and r.cand.tree == t and r.cand.prec == "fp64"),
+                         Candidate(t, "auto", "fp64", 0, False)) for t in trees}
+    for r in rows:
+        if not r.feasible:
+            continue
+        ref_cand = ref_cands[r.cand.tree]
+        us, err, aps, status, ref_status = _run(nets[r.cand.tree], r.cand, nets[r.cand.tree], ref_cand, n_cases,
+                                                losses, max_mod_rank, rel_tol, gate_steps, chunk, timed_steps, reps)
+        if ref_status != "ok":
+            raise hinv.HinvError(4, "tune", f"the FP64 reference run ({ref_cand.label()}) ended with {ref_status}")
+        r.us_per_step, r.err, r.applies_per_step, r.status = us, err * scale, round(aps, 3), status
+        r.solves_per_s = round(n_cases / (us * 1e-6), 1)
+        if log:
+            log(f"tune {r.cand.label()}: {us:.2f} us/step, err {err:.2e} (x{scale:.2f}), {status}")
+    res = TuneResult(key, select(rows, gate), rows, cached=False, gate=gate)
+    if cache:
+        save_cache(cache, key, res)
+    return res
