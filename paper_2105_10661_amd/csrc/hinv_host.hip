@@ -1110,6 +1110,7 @@ struct emt_ctx {
     bool team_ok = false;
     int team_nx_cap = 0;
     std::vector<int> tw_nxu, txupd, tuzo;   // team: X rows whose final values a workgroup uses
+    std::vector<int> ttcso, ttcld, tylist, tw_ny;   // team: columns whose y a workgroup computes, S^{-1} rows
     std::vector<int> tw_lo, tw_nl, tw_nx, tw_nb, txrow, txzo, txpm, txpc, tozo, topm, topc, topan, txpan, txpos, torp,
         tocol, tbglob, tbf, tbt, tbown, tiptr, tibr, tsptr;
     std::vector<double> toval, tbg, tbal, tsamp, tsph;
@@ -1532,16 +1533,52 @@ bool build_team_plan(emt_ctx& c, int R)
     D.T = L; D.H = H; D.NL = NL; D.NX = NX; D.NB = NB; D.NE = NE; D.NI = NI; D.NS = NS; D.XZ = XZ; D.ZO = ZO;
     D.XZU = XZU;
     D.nc = NC;
-    // S^{-1} of every node in LDS with rows padded to m+1 (breaks LDS bank aliasing of the row stride)
-    c.tcsop.assign(NC, 0);
+    // y = S^{-1} s is needed only for the columns whose Z values a workgroup applies: the panels of its
+    // own rows and of the X rows it updates, at every level.  Only those rows of each node's S^{-1} live
+    // in its LDS, as an r x m block per node (r needed rows, leading dimension r + 1 against LDS bank
+    // aliasing); the y phase runs over the workgroup's list of needed columns.
+    c.ttcso.assign((size_t)L * NC, -1);
+    c.ttcld.assign((size_t)L * NC, 0);
+    c.tylist.assign((size_t)L * NC, 0);
+    c.tw_ny.assign(L, 0);
     {
-        int64_t off = 0;
-        for (size_t t = 0; t < P.node_m.size(); ++t) {
-            const int m = P.node_m[t];
-            for (int q = 0; q < m; ++q) c.tcsop[P.node_col0[t] + q] = (int)(off + q);
-            off += (int64_t)m * (m + 1);
+        int64_t sent = 1;
+        int ny_max = 1;
+        std::vector<char> need(NC);
+        for (int l = 0; l < L; ++l) {
+            const W& w = ws[l];
+            std::fill(need.begin(), need.end(), 0);
+            for (int h = 0; h < H; ++h)
+                if (w.ozo[h] >= 0)
+                    for (int j = 0; j < w.opm[h]; ++j) need[w.opc[h] + j] = 1;
+            for (int x : w.xupd)
+                for (int h = 0; h < H; ++h) {
+                    const size_t xi = (size_t)x * H + h;
+                    if (w.xzo[xi] < 0) continue;
+                    for (int j = 0; j < w.xpm[xi]; ++j) need[w.xpc[xi] + j] = 1;
+                }
+            int64_t off = 0;
+            int ny = 0;
+            for (size_t t = 0; t < P.node_m.size(); ++t) {
+                const int m = P.node_m[t], c0 = P.node_col0[t];
+                int r = 0;
+                for (int q = 0; q < m; ++q) r += need[c0 + q];
+                if (r == 0) continue;
+                int slot = 0;
+                for (int q = 0; q < m; ++q) {
+                    if (!need[c0 + q]) continue;
+                    c.ttcso[(size_t)l * NC + c0 + q] = (int)(off + slot++);
+                    c.ttcld[(size_t)l * NC + c0 + q] = r + 1;
+                    c.tylist[(size_t)l * NC + ny++] = c0 + q;
+                }
+                off += (int64_t)(r + 1) * m;
+            }
+            c.tw_ny[l] = ny;
+            sent = std::max(sent, off);
+            ny_max = std::max(ny_max, ny);
         }
-        D.sent = (int)std::max<int64_t>(off, 1);
+        D.sent = (int)sent;
+        D.NY = ny_max;
     }
     // rows a_g of the two-phase coupling levels (values from launch_team_acoef): the panel of the
     // column's row at every lower level, and the columns a_g can reach, as one range per column
@@ -1659,7 +1696,7 @@ void carve_team(emt_ctx& c, Arena& A)
     D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
     D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
     D.sync = A.take<unsigned int>(L);
-    D.csop = ti(D.nc);
+    D.csop = ti((size_t)L * D.nc); D.cld = ti((size_t)L * D.nc); D.ylist = ti((size_t)L * D.nc); D.w_ny = ti(L);
     D.X0 = td(2 * (size_t)c.n);
     D.VM = td(2 * L);
     D.aoff = ti(D.nc); D.alo = ti(D.nc); D.alen = ti(D.nc);
@@ -2187,7 +2224,8 @@ hinv_status upload_team(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.bglob, c.tbglob, s)); HIP_TRY(up(D.bf, c.tbf, s)); HIP_TRY(up(D.bt, c.tbt, s));
     HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
     HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
-    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s)); HIP_TRY(up(D.csop, c.tcsop, s));
+    HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s)); HIP_TRY(up(D.csop, c.ttcso, s));
+    HIP_TRY(up(D.cld, c.ttcld, s)); HIP_TRY(up(D.ylist, c.tylist, s)); HIP_TRY(up(D.w_ny, c.tw_ny, s));
     HIP_TRY(up(D.aoff, c.taoff, s)); HIP_TRY(up(D.alo, c.talo, s)); HIP_TRY(up(D.alen, c.talen, s));
     HIP_TRY(up(D.cpan, c.tcpan, s));
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));

@@ -220,8 +220,11 @@ struct ServeSlot {
 // column endpoints, tie-line neighbours, line-loss endpoints) are nl + x.
 struct TeamDev {
     int T, H, NL, NX, NB, NE, NI, NS, XZ, ZO;
-    int nc, sent;        // coupling columns, S^{-1} entries in LDS (rows padded to m+1, see csop)
-    const int* csop;     // [n_cols] LDS offset of the column's node S^{-1} (row stride m+1) + column index in node
+    int nc, sent, NY;    // coupling columns, S^{-1} entries in LDS, most columns whose y a workgroup computes
+    const int* csop;     // [T*nc] LDS offset of the column's row of its node's S^{-1} (entry p at csop + p*cld), -1: y not needed
+    const int* cld;      // [T*nc] leading dimension of that node's block of needed rows in the workgroup's LDS
+    const int* ylist;    // [T*nc] columns whose y the workgroup computes (first w_ny entries)
+    const int* w_ny;     // [T]
     const int* w_lo;
     const int* w_nl;
     const int* w_nx;

@@ -38,7 +38,7 @@ struct TAcc<double> { using T = double; };
 struct TeamLayout {
     size_t blk, sall, zown, xz, uown, ux, acoef;
     size_t b, v, t, d, xv, xd, s, y, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, colw, cinv, mdg, red, tz;
-    size_t xrow, xupd, utab, otab, xpos, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
+    size_t xrow, xupd, utab, otab, xpos, cm, cc0, cso, ylist, lvlc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
     size_t aoff, alo, alen;
     size_t lpa, lpb, loa, lob, mact, lbr, lst, vg, ctl;
     size_t total;
@@ -81,6 +81,7 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     L.xrow = take(I * NX); L.xupd = take(I * NX);
     L.utab = take(sizeof(int4) * NX * H); L.otab = take(sizeof(int4) * H);
     L.xpos = take(I * nc); L.cm = take(I * nc); L.cc0 = take(I * nc); L.cso = take(I * nc);
+    L.ylist = take(I * T.NY);
     L.lvlc = take(I * (H + 1));
     L.orp = take(refines ? I * (NL + 1) : 0); L.ocol = take(refines ? I * T.NE : 0);
     L.aoff = take(I * nc); L.alo = take(I * nc); L.alen = take(I * nc);
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     const TeamLayout Ly = team_layout<TB>(T, R);
     const int w = blockIdx.x, tid = threadIdx.x;
     const int n = H.n, NL = T.NL, NX = T.NX, Hn = T.H, nc = T.nc;
-    const int lo = T.w_lo[w], nl = T.w_nl[w], nx = T.w_nx[w], nb = T.w_nb[w], nxu = T.w_nxu[w];
+    const int lo = T.w_lo[w], nl = T.w_nl[w], nx = T.w_nx[w], nb = T.w_nb[w], nxu = T.w_nxu[w], ny = T.w_ny[w];
     TB* blk = (TB*)(L8 + Ly.blk);
     TB* sall = (TB*)(L8 + Ly.sall);
     TB* zown = (TB*)(L8 + Ly.zown);
@@ -150,6 +151,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     int* cm = (int*)(L8 + Ly.cm);
     int* cc0 = (int*)(L8 + Ly.cc0);
     int* cso = (int*)(L8 + Ly.cso);
+    int* ylist = (int*)(L8 + Ly.ylist);   // columns whose y this workgroup computes
     int* lvlc = (int*)(L8 + Ly.lvlc);
     int* orp = (int*)(L8 + Ly.orp);
     int* ocol = (int*)(L8 + Ly.ocol);
@@ -188,12 +190,14 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     {
         const TB* src = gblk + H.leaf_off[w];
         for (int i = tid; i < nl * nl; i += kTeamThreads) blk[i] = src[i];
-        for (int g = tid; g < nc; g += kTeamThreads) {      // S^{-1} rows padded to m+1 in LDS
+        for (int k = tid; k < ny; k += kTeamThreads) {      // the needed rows of every S^{-1}
+            const int g = T.ylist[(int64_t)w * nc + k];
+            ylist[k] = g;
             const int node = H.col_node[g];
-            const int m = H.node_m[node], q = g - H.node_col0[node];
+            const int m = H.node_m[node], q = g - H.node_col0[node], ld = T.cld[(int64_t)w * nc + g];
             const TB* src = gS + H.node_soff[node] + q;
-            TB* dst = sall + T.csop[g];
-            for (int p = 0; p < m; ++p) dst[p * (m + 1)] = src[(int64_t)p * m];
+            TB* dst = sall + T.csop[(int64_t)w * nc + g];
+            for (int p = 0; p < m; ++p) dst[p * ld] = src[(int64_t)p * m];
         }
         const int* wxrow = T.xrow + (int64_t)w * NX;
         for (int x = tid; x < nx; x += kTeamThreads) xrow[x] = wxrow[x];
@@ -225,9 +229,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         for (int g = tid; g < nc; g += kTeamThreads) {
             xpos[g] = T.xpos[(int64_t)w * nc + g];
             const int node = H.col_node[g];
-            cm[g] = H.node_m[node];
+            cm[g] = H.node_m[node] | (T.cld[(int64_t)w * nc + g] << 16);   // order | leading dimension << 16
             cc0[g] = H.node_col0[node];
-            cso[g] = T.csop[g];
+            cso[g] = T.csop[(int64_t)w * nc + g];
             colw[g] = H.col_w[g];
             aoff[g] = T.aoff[g];
             alo[g] = T.alo[g];
@@ -361,12 +365,12 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 if (sub == 0) s[g] = colw[g] * outx[xpos[g]] - (double)acc;
             }
             __syncthreads();
-            for (int idx = tid; idx < nc * kSub; idx += kTeamThreads) {
-                const int g = idx / kSub, sub = idx & (kSub - 1);
-                const int m = cm[g], q0 = cc0[g];
+            for (int idx = tid; idx < ny * kSub; idx += kTeamThreads) {
+                const int g = ylist[idx / kSub], sub = idx & (kSub - 1);
+                const int m = cm[g] & 0xffff, ld = cm[g] >> 16, q0 = cc0[g];
                 const TB* Si = sall + cso[g];
                 TA acc = 0;
-                for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * (m + 1)] * (TA)s[q0 + p];
+                for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * ld] * (TA)s[q0 + p];
                 acc = quad_sum(acc);
                 if (sub == 0) y[g] = (double)acc;
             }

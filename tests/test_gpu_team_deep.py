@@ -73,3 +73,30 @@ def test_team_refuses_five_levels(hv):
     with pytest.raises(hv.HinvError) as ex:
         hv.EMT(net, 1, kernel_mode="team")
     assert ex.value.name == "INVALID"
+
+
+_RING = {}
+
+
+@pytest.mark.parametrize("prec,refine,warm", [("fp64", 0, False), ("fp32", 2, True)])
+def test_team_wide_ring_with_scheduled_and_dynamic_losses(hv, prec, refine, warm):
+    """A 12-copy ring (2148 buses, 24 leaves): each workgroup keeps only the rows of each S^{-1} whose
+    y it applies, which is what lets this tree fit the team engine in FP64.  A scheduled loss and a
+    loss requested between launches add X rows to some workgroups (new needed columns)."""
+    import torch
+    net = cases.net_ring(12, 21)
+    steps, s1, s2 = 300, 60, 180
+    b1, b2 = 7, net.n_branch - 5          # a line inside copy 0, a tie line
+    if "ref" not in _RING:
+        _RING["ref"] = oracle.emt_run(net, steps, loss_steps=[s1, s2], loss_branches=[b1, b2], solver="sparse")[0]
+    ref = _RING["ref"]
+    print(f"[gpu] team engine, 12-copy ring, {prec}", flush=True)
+    emt = hv.EMT(net, 1, losses=[[(s1, b1)]], prec=prec, max_refine=refine, warm_start=warm, max_mod_rank=2,
+                 kernel_mode="team")
+    V1, _ = emt.step(s2 - 1)
+    emt.lose_line(0, b2)
+    V2, _ = emt.step(steps - s2 + 1)
+    V = torch.cat([V1, V2])[:, 0, :].cpu().numpy()
+    emt.sync_status()
+    emt.close()
+    assert np.abs(V - ref).max() / np.abs(ref).max() <= 1e-10
