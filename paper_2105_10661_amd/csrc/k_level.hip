@@ -311,7 +311,7 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
         for (int hl = 1; hl <= Hn; ++hl) {
             const int k0 = optr[hl - 1], k1 = optr[hl];
             for (int k = k0 + tid; k < k1; k += kLThreads) xchg_store(&D.Sx[ocl[k]], ocw[k] * out[orow[k]]);
-            if (!team_barrier(flags, w, T, ++epoch, P.flags, ctl)) return false;
+            if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
             for (int k = k0 + wave; k < k1; k += kLWaves) {   // y of the owned columns, one wavefront each
                 const int m = om[k], c0 = oc0[k];
                 const TB* Sr = srow + osoff[k];
@@ -320,7 +320,7 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
                 for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
                 if (lane == 0) xchg_store(&D.Yx[ocl[k]], (double)acc);
             }
-            if (!team_barrier(flags, w, T, ++epoch, P.flags, ctl)) return false;
+            if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
             const int zo = ozo[hl - 1];
             if (zo >= 0) {                                     // own rows: v -= Z_t y_t
                 const int pm = opm[hl - 1], pc = opc[hl - 1];
@@ -336,7 +336,7 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
         }
         // the own rows' values for the X rows of other workgroups
         for (int r = tid; r < nl; r += kLThreads) xchg_store(&D.V1[lo + r], out[r]);
-        if (!team_barrier(flags, w, T, ++epoch, P.flags, ctl)) return false;
+        if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
         if (want_vm) {     // the team's largest |v| (vg was cleared before this apply)
             for (int i = tid; i < T; i += kLThreads)
                 atomicMax(vg, (unsigned long long)__double_as_longlong(xchg_load(&D.VM[i])));
