@@ -338,14 +338,15 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 xchg_store(&X0[lo + r], val);
             }
         }
-        team_arrive(T.sync, w, ++epoch);
+        count_arrive(T.sync);
+        ++epoch;
         if (sn_step >= 0) {      // source injections of the next step, by the last wavefront, while wavefront 0 polls
             if (tid >= kTeamThreads - 64)
                 for (int q = tid - (kTeamThreads - 64); q < ns; q += 64)
                     sn[q] = samp[q] * sin(E.omega * ((double)sn_step * E.dt) + sph[q]);
             sn_step = -1;
         }
-        if (!team_wait(T.sync, T.T, epoch, P.flags, ctl)) return false;
+        if (!count_wait(T.sync, T.T, epoch, P.flags, ctl)) return false;
         if (want_vm) {   // the team's largest |v| (vg was cleared before the barrier)
             for (int i = tid; i < T.T; i += kTeamThreads)
                 atomicMax(vg, (unsigned long long)__double_as_longlong(xchg_load(&T.VM[(int64_t)par * T.T + i])));

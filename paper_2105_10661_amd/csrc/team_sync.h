@@ -109,6 +109,33 @@ __device__ inline bool team_barrier(unsigned int* flags, int me, int T, unsigned
 // and polls the single word until all T workgroups of this epoch have arrived (epoch * T).  With
 // one flag per workgroup, a team of 128 polls 128 words from every workgroup (16K device-scope
 // loads per round); the counter costs T atomic adds and one word per poll.  Bounded like team_wait.
+// The counter barrier in two halves (as team_arrive / team_wait).
+__device__ inline void count_arrive(unsigned int* counter)
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // gfx9 encoding of vmcnt(0): this wave's stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool count_wait(unsigned int* counter, int T, unsigned int epoch, int* errflags, int* ctl)
+{
+    if (threadIdx.x == 0) {
+        const unsigned int target = epoch * (unsigned int)T;
+        int ok = 1;
+        int spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kTeamSpinLimit) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        ctl[0] = ok;
+        if (!ok) atomicOr(errflags, kFlagBarrier);
+    }
+    __syncthreads();
+    return ctl[0] != 0;
+}
+
 __device__ inline bool count_barrier(unsigned int* counter, int T, unsigned int epoch, int* errflags, int* ctl)
 {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // gfx9 encoding of vmcnt(0): this wave's stores have completed
