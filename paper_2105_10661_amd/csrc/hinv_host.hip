@@ -2009,7 +2009,7 @@ bool build_level_plan(emt_ctx& c, int R)
 {
     const Plan& P = c.hc.P;
     const int L = (int)P.leaf_lo.size(), H = P.n_levels, NC = (int)P.col_row.size();
-    if (c.n_cases != 1 || L < 1 || L > 256 || H < 0) return false;
+    if (c.n_cases != 1 || L < 1 || L > 256 || H < 0 || H > 7) return false;   // y tags hold the level in 3 bits
     std::vector<int> lpan((size_t)L * std::max(H, 1), -1);
     for (int l = 0; l < L; ++l) {
         for (int k = 0; k < P.anc_stride; ++k) {
@@ -2185,7 +2185,7 @@ void carve_level(emt_ctx& c, Arena& A)
     D.lpa = ti(L * R); D.lpb = ti(L * R);
     D.sync = A.take<unsigned int>(L);
     D.Sx = td(std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
-    D.Yx = td(std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
+    D.YL = A.take<unsigned long long>(2 * std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
     D.V1 = td(c.n);
     D.VM = td(L);
 }
@@ -2206,6 +2206,7 @@ hinv_status upload_level(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
     HIP_TRY(up(D.lpa, c.llpa, s)); HIP_TRY(up(D.lpb, c.llpb, s));
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
+    HIP_TRY(hipMemsetAsync(D.YL, 0, 2 * std::max<size_t>(c.hc.P.col_row.size(), 1) * sizeof(unsigned long long), s));   // tag 0: none
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;
 }

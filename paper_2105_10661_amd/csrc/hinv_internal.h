@@ -374,7 +374,8 @@ struct LevelDev {
     const int* lpb;
     unsigned int* sync;  // [T] barrier epoch flags
     double* Sx;          // [n_cols] exchange of s
-    double* Yx;          // [n_cols] exchange of y
+    unsigned long long* YL;   // [2*n_cols] y of every column as two tagged words (tagged_store / tagged_load),
+                              // tag (apply index of the case's run) * 8 + level; read without a barrier
     double* V1;          // [n] exchange of the own rows' values at the end of an apply
     double* VM;          // [T] max |v| of each workgroup (convergence norm)
 };

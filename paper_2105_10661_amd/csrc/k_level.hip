@@ -292,7 +292,14 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
 
     // one application of the stored inverse with the active line changes:
     // out (own rows), outx (X rows) from xin (own rows)
+    // tags of the y exchange: ((step + 1) * applies per step + apply of the step) * 8 + level, unique
+    // over the case's run (the buffer is cleared when the tables are uploaded)
+    const int64_t A = MIXED ? (int64_t)P.max_refine + 1 : 1;
+    int64_t cur_step = step0;
+    int ais = 0;
+    unsigned int ytag0 = 0;
     auto apply = [&](const double* xin, double* out, double* outx, int ract, bool want_vm) -> bool {
+        ytag0 = (unsigned int)(((cur_step + 1) * A + ais++) * 8);
         {   // leaf product: wavefront w covers rows 64*(w / kLChunks) + lane, columns j = w % kLChunks (mod kLChunks)
             const int r = (wave / kLChunks) * 64 + lane, c = wave % kLChunks;
             if (r < nl) {
@@ -312,20 +319,27 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
             const int k0 = optr[hl - 1], k1 = optr[hl];
             for (int k = k0 + tid; k < k1; k += kLThreads) xchg_store(&D.Sx[ocl[k]], ocw[k] * out[orow[k]]);
             if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
+            const unsigned int ytag = ytag0 + (unsigned int)hl;
             for (int k = k0 + wave; k < k1; k += kLWaves) {   // y of the owned columns, one wavefront each
                 const int m = om[k], c0 = oc0[k];
                 const TB* Sr = srow + osoff[k];
                 TA acc = 0;
                 for (int p = lane; p < m; p += 64) acc += (TA)Sr[p] * (TA)xchg_load(&D.Sx[c0 + p]);
                 for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-                if (lane == 0) xchg_store(&D.Yx[ocl[k]], (double)acc);
+                if (lane == 0) tagged_store(D.YL + 2 * ocl[k], (double)acc, ytag);
             }
-            if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
+            // no barrier for y: each value is read once it carries this level's tag of this apply.  A
+            // column's next write comes after the next apply's s barrier of this level, which every
+            // workgroup reaches only after it has read this apply's values
             const int zo = ozo[hl - 1];
             if (zo >= 0) {                                     // own rows: v -= Z_t y_t
                 const int pm = opm[hl - 1], pc = opc[hl - 1];
-                for (int j = tid; j < pm; j += kLThreads) yl[j] = xchg_load(&D.Yx[pc + j]);
-                __syncthreads();
+                bool ok = true;
+                for (int j = tid; j < pm; j += kLThreads) yl[j] = tagged_load(D.YL + 2 * (pc + j), ytag, &ok);
+                if (__syncthreads_or(ok ? 0 : 1)) {
+                    if (tid == 0) atomicOr(P.flags, kFlagBarrier);
+                    return false;
+                }
                 for (int r = tid; r < nl; r += kLThreads) {
                     TA acc = 0;
                     for (int j = 0; j < pm; ++j) acc += (TA)zown[zo + j * nl + r] * (TA)yl[j];
@@ -426,6 +440,8 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
     const int ns = sptr[nl];
     for (int it = 0; it < P.n_steps && alive; ++it) {
         const int64_t step = step0 + it;
+        cur_step = step;
+        ais = 0;
         int ract = 0;
         while (ract < cnt && (int64_t)mact[ract] <= step) ++ract;
         if constexpr (!MIXED) {

@@ -28,6 +28,32 @@ __device__ __forceinline__ double xchg_load(const double* p)
     return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tagged exchange of one FP64 value without a barrier: the value's low and high 32 bits, each in
+// one 64-bit word under a 32-bit tag, stored and loaded as 64-bit device-scope relaxed atomics, so a
+// reader sees each half together with its tag.  A value is read once both words carry the expected
+// tag.  The wait is bounded: on time-out *ok is cleared and 0 is returned.
+__device__ __forceinline__ void tagged_store(unsigned long long* p, double v, unsigned int tag)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long t = (unsigned long long)tag << 32;
+    __hip_atomic_store(p, t | (b & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, t | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double tagged_load(unsigned long long* p, unsigned int tag, bool* ok)
+{
+    for (int spins = 0;; ++spins) {
+        const unsigned long long w0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long w1 = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned int)(w0 >> 32) == tag && (unsigned int)(w1 >> 32) == tag)
+            return __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+        if (spins >= kTeamSpinLimit) {
+            *ok = false;
+            return 0.0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Value of another lane of the same quad (lanes 4q .. 4q + 3) by a DPP quad permutation: a VALU
 // move, no LDS round trip.  CTRL 0xB1 = quad_perm [1,0,3,2] (lane ^ 1), 0x4E = [2,3,0,1] (lane ^ 2).
 template <int CTRL>
