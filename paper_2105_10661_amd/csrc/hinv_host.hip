@@ -2187,6 +2187,7 @@ void carve_level(emt_ctx& c, Arena& A)
     D.Sx = td(std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
     D.YL = A.take<unsigned long long>(2 * std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
     D.V1 = td(c.n);
+    D.VL = A.take<unsigned long long>(2 * (int64_t)c.n);
     D.VM = td(L);
 }
 
@@ -2207,6 +2208,7 @@ hinv_status upload_level(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.lpa, c.llpa, s)); HIP_TRY(up(D.lpb, c.llpb, s));
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
     HIP_TRY(hipMemsetAsync(D.YL, 0, 2 * std::max<size_t>(c.hc.P.col_row.size(), 1) * sizeof(unsigned long long), s));   // tag 0: none
+    HIP_TRY(hipMemsetAsync(D.VL, 0, 2 * (size_t)c.n * sizeof(unsigned long long), s));
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;
 }

@@ -377,6 +377,8 @@ struct LevelDev {
     unsigned long long* YL;   // [2*n_cols] y of every column as two tagged words (tagged_store / tagged_load),
                               // tag (apply index of the case's run) * 8 + level; read without a barrier
     double* V1;          // [n] exchange of the own rows' values at the end of an apply
+    unsigned long long* VL;   // [2*n] the same as tagged words (tag: the apply's y tag, level 0), for applies
+                              // that end without a barrier
     double* VM;          // [T] max |v| of each workgroup (convergence norm)
 };
 

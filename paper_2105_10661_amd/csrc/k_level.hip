@@ -348,15 +348,28 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
                 __syncthreads();
             }
         }
-        // the own rows' values for the X rows of other workgroups
-        for (int r = tid; r < nl; r += kLThreads) xchg_store(&D.V1[lo + r], out[r]);
-        if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
-        if (want_vm) {     // the team's largest |v| (vg was cleared before this apply)
-            for (int i = tid; i < T; i += kLThreads)
-                atomicMax(vg, (unsigned long long)__double_as_longlong(xchg_load(&D.VM[i])));
+        // the own rows' values for the X rows of other workgroups.  With two or more levels and no
+        // team-wide norm to gather, they go as tagged values without a barrier: a row's next write
+        // comes after the next apply's first s barrier, and its next s values (level 1) after this
+        // apply's last s barrier, which every workgroup reaches after its reads of both
+        if (Hn >= 2 && !want_vm) {
+            for (int r = tid; r < nl; r += kLThreads) tagged_store(D.VL + 2 * (lo + r), out[r], ytag0);
+            bool ok = true;
+            for (int x = tid; x < nx; x += kLThreads) outx[x] = tagged_load(D.VL + 2 * xrow[x], ytag0, &ok);
+            if (__syncthreads_or(ok ? 0 : 1)) {
+                if (tid == 0) atomicOr(P.flags, kFlagBarrier);
+                return false;
+            }
+        } else {
+            for (int r = tid; r < nl; r += kLThreads) xchg_store(&D.V1[lo + r], out[r]);
+            if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
+            if (want_vm) {     // the team's largest |v| (vg was cleared before this apply)
+                for (int i = tid; i < T; i += kLThreads)
+                    atomicMax(vg, (unsigned long long)__double_as_longlong(xchg_load(&D.VM[i])));
+            }
+            for (int x = tid; x < nx; x += kLThreads) outx[x] = xchg_load(&D.V1[xrow[x]]);
+            __syncthreads();
         }
-        for (int x = tid; x < nx; x += kLThreads) outx[x] = xchg_load(&D.V1[xrow[x]]);
-        __syncthreads();
         if (ract > 0) {
             if (tid < ract) tz[tid] = cval(out, outx, lpa[tid]) - (lpb[tid] >= 0 ? cval(out, outx, lpb[tid]) : 0.0);
             __syncthreads();
