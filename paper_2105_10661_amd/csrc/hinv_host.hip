@@ -2184,7 +2184,8 @@ void carve_level(emt_ctx& c, Arena& A)
     D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
     D.lpa = ti(L * R); D.lpb = ti(L * R);
     D.sync = A.take<unsigned int>(L);
-    D.Sx = td(std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
+    D.Sx = td(2 * std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
+    D.SL = A.take<unsigned long long>(2 * std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
     D.YL = A.take<unsigned long long>(2 * std::max<int64_t>((int64_t)c.hc.P.col_row.size(), 1));
     D.V1 = td(c.n);
     D.VL = A.take<unsigned long long>(2 * (int64_t)c.n);
@@ -2209,6 +2210,7 @@ hinv_status upload_level(emt_ctx& c, hipStream_t s)
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.T * sizeof(unsigned int), s));
     HIP_TRY(hipMemsetAsync(D.YL, 0, 2 * std::max<size_t>(c.hc.P.col_row.size(), 1) * sizeof(unsigned long long), s));   // tag 0: none
     HIP_TRY(hipMemsetAsync(D.VL, 0, 2 * (size_t)c.n * sizeof(unsigned long long), s));
+    HIP_TRY(hipMemsetAsync(D.SL, 0, 2 * std::max<size_t>(c.hc.P.col_row.size(), 1) * sizeof(unsigned long long), s));
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
     return HINV_OK;
 }

@@ -373,7 +373,8 @@ struct LevelDev {
     const int* lpa;      // [T*R] combined index of each change's endpoints (-1: ground / unused)
     const int* lpb;
     unsigned int* sync;  // [T] barrier epoch flags
-    double* Sx;          // [n_cols] exchange of s
+    double* Sx;          // [2*n_cols] exchange of s at the top level (double-buffered by apply parity)
+    unsigned long long* SL;   // [2*n_cols] s of the lower levels as tagged words (tag as for YL)
     unsigned long long* YL;   // [2*n_cols] y of every column as two tagged words (tagged_store / tagged_load),
                               // tag (apply index of the case's run) * 8 + level; read without a barrier
     double* V1;          // [n] exchange of the own rows' values at the end of an apply

@@ -295,6 +295,7 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
     // tags of the y exchange: ((step + 1) * applies per step + apply of the step) * 8 + level, unique
     // over the case's run (the buffer is cleared when the tables are uploaded)
     const int64_t A = MIXED ? (int64_t)P.max_refine + 1 : 1;
+    const int ncol = H.lvl_col[Hn];      // coupling columns of the tree
     int64_t cur_step = step0;
     int ais = 0;
     unsigned int ytag0 = 0;
@@ -315,22 +316,38 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
             out[r] = val;
         }
         __syncthreads();
+        // The only barrier of an apply is the top level's s exchange (top-level s double-buffered by
+        // apply parity).  The s of the lower levels, every y and the final values are tagged words:
+        // every such slot is next written after the next apply has passed this apply's top-level
+        // barrier (or, for top-level y and the final values, the next apply's), and every workgroup
+        // reads the current value before it arrives there.
+        double* Sxp = D.Sx + (int64_t)((ytag0 >> 3) & 1u) * ncol;
         for (int hl = 1; hl <= Hn; ++hl) {
             const int k0 = optr[hl - 1], k1 = optr[hl];
-            for (int k = k0 + tid; k < k1; k += kLThreads) xchg_store(&D.Sx[ocl[k]], ocw[k] * out[orow[k]]);
-            if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
+            const bool top = hl == Hn;
             const unsigned int ytag = ytag0 + (unsigned int)hl;
+            if (top) {
+                for (int k = k0 + tid; k < k1; k += kLThreads) xchg_store(&Sxp[ocl[k]], ocw[k] * out[orow[k]]);
+                if (!count_barrier(flags, T, ++epoch, P.flags, ctl)) return false;
+            } else {
+                for (int k = k0 + tid; k < k1; k += kLThreads) tagged_store(D.SL + 2 * ocl[k], ocw[k] * out[orow[k]], ytag);
+            }
+            bool sok = true;
             for (int k = k0 + wave; k < k1; k += kLWaves) {   // y of the owned columns, one wavefront each
                 const int m = om[k], c0 = oc0[k];
                 const TB* Sr = srow + osoff[k];
                 TA acc = 0;
-                for (int p = lane; p < m; p += 64) acc += (TA)Sr[p] * (TA)xchg_load(&D.Sx[c0 + p]);
+                for (int p = lane; p < m; p += 64) {
+                    const double sv = top ? xchg_load(&Sxp[c0 + p]) : tagged_load(D.SL + 2 * (c0 + p), ytag, &sok);
+                    acc += (TA)Sr[p] * (TA)sv;
+                }
                 for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
                 if (lane == 0) tagged_store(D.YL + 2 * ocl[k], (double)acc, ytag);
             }
-            // no barrier for y: each value is read once it carries this level's tag of this apply.  A
-            // column's next write comes after the next apply's s barrier of this level, which every
-            // workgroup reaches only after it has read this apply's values
+            if (!top && __syncthreads_or(sok ? 0 : 1)) {
+                if (tid == 0) atomicOr(P.flags, kFlagBarrier);
+                return false;
+            }
             const int zo = ozo[hl - 1];
             if (zo >= 0) {                                     // own rows: v -= Z_t y_t
                 const int pm = opm[hl - 1], pc = opc[hl - 1];
