@@ -1,5 +1,5 @@
 """GPU parity of the team engine on trees with three and four coupling levels (the 179-bus network,
-bisection trees of leaf size 24 and 12).  Each coupling column's sum is formed in one phase from the
+bisection trees of leaf size 24 and 12), and of the level engine on trees of one to five levels.  Each coupling column's sum is formed in one phase from the
 leaf results through a precomputed row that folds in the corrections of every lower level, so these
 trees check that fold through more than one level; the benchmark trees have two.
 
@@ -99,4 +99,27 @@ def test_team_wide_ring_with_scheduled_and_dynamic_losses(hv, prec, refine, warm
     V = torch.cat([V1, V2])[:, 0, :].cpu().numpy()
     emt.sync_status()
     emt.close()
+    assert np.abs(V - ref).max() / np.abs(ref).max() <= 1e-10
+
+
+@pytest.mark.parametrize("d_th", [90, 24, 12, 6])
+@pytest.mark.parametrize("prec,refine,warm", [("fp64", 0, False), ("fp32", 2, True)])
+def test_level_engine_trees_of_one_to_five_levels(hv, d_th, prec, refine, warm):
+    """The level engine on bisection trees of 1 to 5 coupling levels (leaf sizes 90, 24, 12, 6): one
+    barrier per apply at the top level, every other exchange as tagged values (a single-level tree keeps
+    the barrier for the final values), with a line loss and a fault switched on and off."""
+    import torch
+    net = _net(d_th)
+    print(f"[gpu] level engine, leaf size {d_th}, {prec}", flush=True)
+    emt = hv.EMT(net, 1, losses=[[(LOSS, 5)]], prec=prec, max_refine=refine, warm_start=warm,
+                 max_mod_rank=2, kernel_mode="level")
+    V1, _ = emt.step(ON - 1)
+    emt.update_line(1, -1, 0.1)
+    V2, _ = emt.step(OFF - ON)
+    emt.update_line(1, -1, -0.1)
+    V3, _ = emt.step(N_STEPS - OFF + 1)
+    V = torch.cat([V1, V2, V3])[:, 0, :].cpu().numpy()
+    emt.sync_status()
+    emt.close()
+    ref = _reference(d_th)
     assert np.abs(V - ref).max() / np.abs(ref).max() <= 1e-10
