@@ -160,14 +160,20 @@ def load_cache(path: str) -> dict:
         return {}
 
 
-def save_cache(path: str, key: str, res: TuneResult) -> None:
+def save_cache(path: str, key: str, res: TuneResult) -> bool:
+    """Add one result to the JSON cache; returns False (and keeps the result) if the file cannot be
+    written, e.g. on a read-only home directory."""
     d = load_cache(path)
     d[key] = {"choice": None if res.choice is None else asdict(res.choice), "rows": res.table(), "gate": res.gate}
-    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
-    tmp = path + ".tmp"
-    with open(tmp, "w") as f:
-        json.dump(d, f, indent=1)
-    os.replace(tmp, path)
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        return False
+    return True
 
 
 def from_cache(path: str, key: str) -> Optional[TuneResult]:

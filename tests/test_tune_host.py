@@ -95,3 +95,13 @@ def test_cache_round_trip_and_key(tn, tmp_path):
     assert tn.from_cache(path, k2) is None
     tn.save_cache(path, k2, tn.TuneResult(k2, None, []))
     assert tn.from_cache(path, k1).choice == rows[0].cand and tn.from_cache(path, k2).choice is None
+
+
+def test_cache_write_failure_is_not_fatal(tn, tmp_path):
+    ro = tmp_path / "ro"
+    ro.mkdir()
+    blocker = ro / "file"
+    blocker.write_text("x")
+    # a path below a regular file cannot be created
+    assert tn.save_cache(str(blocker / "sub" / "tune.json"), "k", tn.TuneResult("k", None, [])) is False
+    assert tn.from_cache(str(blocker / "sub" / "tune.json"), "k") is None
