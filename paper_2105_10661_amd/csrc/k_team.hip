@@ -26,7 +26,8 @@ namespace hinv {
 constexpr int kTeamThreads = 1024;
 constexpr int kTeamWaves = kTeamThreads / 64;
 constexpr int kGemvLanes = 8;           // leaf GEMV: lanes per row (column chunks), summed by DPP
-constexpr int kSub = 4;                 // lanes per coupling-column dot product
+constexpr int kSub = 4;                 // lanes per coupling-column sum s_g (quad sums)
+constexpr int kSub8 = 8;                // lanes per y_g and per final-update row (sums over eight lanes)
 static_assert(kMaxLeaf <= kTeamThreads, "one own row per thread in the right-hand side");
 static_assert(kMaxLeaf * kGemvLanes <= kTeamThreads, "one row per group of GEMV lanes");
 
@@ -355,7 +356,8 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
         __syncthreads();
         // coupling levels, all at once: s_g = w_g u_g - a_g . u from the leaf-apply values u at the
         // column rows (a_g carries the lower levels' corrections of the row), then y = S^{-1} s;
-        // kSub lanes share each column's dot products (quad sums); all rows are updated at the end.
+        // kSub lanes share each column's s (quad sums), kSub8 lanes each y (eight-lane sums); all rows
+        // are updated at the end.
         if (nc > 0) {
             for (int idx = tid; idx < nc * kSub; idx += kTeamThreads) {
                 const int g = idx / kSub, sub = idx & (kSub - 1);
@@ -366,23 +368,23 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 if (sub == 0) s[g] = colw[g] * outx[xpos[g]] - (double)acc;
             }
             __syncthreads();
-            for (int idx = tid; idx < ny * kSub; idx += kTeamThreads) {
-                const int g = ylist[idx / kSub], sub = idx & (kSub - 1);
+            for (int idx = tid; idx < ny * kSub8; idx += kTeamThreads) {
+                const int g = ylist[idx / kSub8], sub = idx & (kSub8 - 1);
                 const int m = cm[g] & 0xffff, ld = cm[g] >> 16, q0 = cc0[g];
                 const TB* Si = sall + cso[g];
                 TA acc = 0;
-                for (int p = sub; p < m; p += kSub) acc += (TA)Si[p * ld] * (TA)s[q0 + p];
-                acc = quad_sum(acc);
+                for (int p = sub; p < m; p += kSub8) acc += (TA)Si[p * ld] * (TA)s[q0 + p];
+                acc = oct_sum(acc);
                 if (sub == 0) y[g] = (double)acc;
             }
             __syncthreads();
         }
         // v -= sum over levels of Z y, on the X rows whose final values this workgroup uses (G
-        // neighbours, line-loss endpoints: first nxu items) and the own rows, kSub lanes per row; every
+        // neighbours, line-loss endpoints: first nxu items) and the own rows, kSub8 lanes per row; every
         // level's table entry is loaded first, so that the levels' loads are in flight together.  The
         // other X rows (coupling-column rows only) keep v0: nothing reads them before the next exchange.
-        for (int idx = tid; Hn > 0 && idx < (nxu + nl) * kSub; idx += kTeamThreads) {
-            const int i = idx / kSub, sub = idx & (kSub - 1);
+        for (int idx = tid; Hn > 0 && idx < (nxu + nl) * kSub8; idx += kTeamThreads) {
+            const int i = idx / kSub8, sub = idx & (kSub8 - 1);
             const bool isx = i < nxu;
             const int r = i - nxu;
             int4 tb[kTeamMaxLevels];
@@ -397,9 +399,9 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
                 if (h < Hn && tb[h].x >= 0) {
                     const int zo = tb[h].x, pm = tb[h].y, pc = tb[h].z;
                     if (isx) {
-                        for (int j = sub; j < pm; j += kSub) acc[h] += (TA)xz[zo + j] * (TA)y[pc + j];
+                        for (int j = sub; j < pm; j += kSub8) acc[h] += (TA)xz[zo + j] * (TA)y[pc + j];
                     } else {
-                        for (int j = sub; j < pm; j += kSub) acc[h] += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
+                        for (int j = sub; j < pm; j += kSub8) acc[h] += (TA)zown[zo + j * nl + r] * (TA)y[pc + j];
                     }
                 }
             }
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
 #pragma unroll
             for (int h = 0; h < kTeamMaxLevels; ++h) {
                 if (h < Hn) {
-                    const TA a = quad_sum(acc[h]);
+                    const TA a = oct_sum(acc[h]);
                     if (tb[h].x >= 0) val -= (double)a;
                 }
             }

@@ -87,6 +87,19 @@ __device__ __forceinline__ double half_row_mirror(double v)
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ float half_row_mirror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+}
+
+// Sum over eight consecutive lanes (aligned), all eight active: every lane gets it.
+template <typename T>
+__device__ __forceinline__ T oct_sum(T a)
+{
+    a = quad_sum(a);
+    return a + half_row_mirror(a);
+}
+
 // The barrier in two halves, so that a workgroup can do work that no other workgroup waits for
 // while its wavefront 0 polls.  team_arrive: this workgroup's stores have completed, then its flag
 // is raised (flags: the team's T flags; me: this workgroup's flag).
