@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the FP64 team kernel per 500-step launch, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0, scales from a copy of known size; profiles/k_emt_team_1432bus_hbm_counters.md).  Valid
 # only while the kernel's sources are the profiled ones.
-TEAM_TRAFFIC = {"sources": ("k_team.hip", "team_sync.h", "hinv_internal.h"), "sha256_16": "18e447a32ef74082",
-                "launch_steps": 500, "bytes": 50329856}
+TEAM_TRAFFIC = {"sources": ("k_team.hip", "team_sync.h", "hinv_internal.h"), "sha256_16": "3f4c8f0151d4138c",
+                "launch_steps": 500, "bytes": 50325453}
 
 
 def team_traffic(chunk):
