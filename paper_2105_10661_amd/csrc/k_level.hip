@@ -357,10 +357,12 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
                     if (tid == 0) atomicOr(P.flags, kFlagBarrier);
                     return false;
                 }
-                for (int r = tid; r < nl; r += kLThreads) {
+                for (int idx = tid; idx < nl * 8; idx += kLThreads) {   // eight lanes per own row
+                    const int r = idx >> 3, sub = idx & 7;
                     TA acc = 0;
-                    for (int j = 0; j < pm; ++j) acc += (TA)zown[zo + j * nl + r] * (TA)yl[j];
-                    out[r] -= (double)acc;
+                    for (int j = sub; j < pm; j += 8) acc += (TA)zown[zo + j * nl + r] * (TA)yl[j];
+                    acc = oct_sum(acc);
+                    if (sub == 0) out[r] -= (double)acc;
                 }
                 __syncthreads();
             }
