@@ -20,7 +20,7 @@ namespace hinv {
 
 constexpr int kLThreads = 1024;
 constexpr int kLWaves = kLThreads / 64;
-constexpr int kLChunks = kLWaves / 2;   // leaf GEMV: 2 row halves (lanes) x 8 column chunks
+static_assert(HINV_MAX_LEAF * 8 <= kLThreads, "leaf GEMV: one row per group of eight lanes");
 
 template <typename TB>
 struct LAcc { using T = float; };
@@ -29,7 +29,7 @@ struct LAcc<double> { using T = double; };
 
 struct LevelLayout {
     size_t blk, zown, srow, uown, ux;
-    size_t b, v, t, d, part, xv, xd, yl, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, ocw, cinv, mdg, red, tz;
+    size_t b, v, t, d, xv, xd, yl, h0, h1, hC, gC, oval, bg, bal, samp, sph, sn, ocw, cinv, mdg, red, tz;
     size_t optr, ocl, orow, osoff, oc0, om, xrow, ozo, opm, opc, orp, ocol, bglob, bf, bt, iptr, ibr, sptr;
     size_t lpa, lpb, mact, lbr, lst, vg, ctl;
     size_t total;
@@ -56,7 +56,6 @@ __host__ __device__ inline LevelLayout level_layout(const LevelDev& D, int R)
     L.v = take(F * NL);
     L.t = take(MIXED ? F * NL : 0);
     L.d = take(MIXED ? F * NL : 0);
-    L.part = take(F * kLChunks * NL);
     L.xv = take(F * NX);
     L.xd = take(MIXED ? F * NX : 0);
     L.yl = take(F * D.PM);
@@ -132,7 +131,6 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
     double* v = (double*)(L8 + Ly.v);
     double* t = (double*)(L8 + Ly.t);
     double* d = (double*)(L8 + Ly.d);
-    double* part = (double*)(L8 + Ly.part);
     double* xv = (double*)(L8 + Ly.xv);
     double* xd = (double*)(L8 + Ly.xd);
     double* yl = (double*)(L8 + Ly.yl);
@@ -301,19 +299,15 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
     unsigned int ytag0 = 0;
     auto apply = [&](const double* xin, double* out, double* outx, int ract, bool want_vm) -> bool {
         ytag0 = (unsigned int)(((cur_step + 1) * A + ais++) * 8);
-        {   // leaf product: wavefront w covers rows 64*(w / kLChunks) + lane, columns j = w % kLChunks (mod kLChunks)
-            const int r = (wave / kLChunks) * 64 + lane, c = wave % kLChunks;
-            if (r < nl) {
-                TA acc = 0;
-                for (int j = c; j < nl; j += kLChunks) acc += (TA)blk[j * nl + r] * (TA)xin[j];
-                part[c * NL + r] = (double)acc;
-            }
-        }
-        __syncthreads();
-        for (int r = tid; r < nl; r += kLThreads) {
-            double val = part[r];
-            for (int q = 1; q < kLChunks; ++q) val += part[q * NL + r];
-            out[r] = val;
+        {   // leaf product: eight lanes per row r = tid / 8, lane c takes the block columns j = c (mod 8);
+            // the eight partial sums are added by DPP moves
+            const int r = tid >> 3, c = tid & 7;
+            const bool act = r < nl;      // whole groups of eight lanes are active or not
+            TA acc = 0;
+            if (act)
+                for (int j = c; j < nl; j += 8) acc += (TA)blk[j * nl + r] * (TA)xin[j];
+            const double val = oct_sum((double)acc);
+            if (act && c == 0) out[r] = val;
         }
         __syncthreads();
         // The only barrier of an apply is the top level's s exchange (top-level s double-buffered by
