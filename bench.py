@@ -1,21 +1,28 @@
 """Benchmark: EMT network solves/s and step latency on one MI355X.
 
-Workload: 1432-bus network (8 tiled copies of the 179-bus generator on a ring,
-3 tie lines per neighbouring pair, 16 leaves, 2 coupling levels), 10000 EMT
-steps at dt = 50 us, one random line lost at step 2000 (rank-1 SMW update).
+Headline workload (batched contingencies): one 1432-bus base network (8 tiled
+copies of the 179-bus generator on a ring, 3 tie lines per neighbouring pair,
+16 leaves, 2 coupling levels) and 256 cases of it, each losing a distinct
+random line at a random step in [500, 5000]; 8000 EMT steps at dt = 50 us.
 A "step" is one EMT time step of every case: right-hand side, hierarchical
-apply, line-loss correction, FP64 refinement (mixed precision), history
-update, all inside the fused stepping kernel.  Inputs are resident in HBM
-before the timed region.
+apply, each case's line-loss (Sherman-Morrison-Woodbury) correction, FP64
+refinement (mixed precision), history update, all inside one fused stepping
+kernel.  One solve is one (case, step) node-voltage solution.
 
-Paths on the same case: FP64 apply; FP32 apply + FP64 residual refinement
-warm-started from the previous step's voltages with two corrections
-("mixed") and with one ("mixed_2apply").  Each trajectory is compared with
-the FP64 CPU oracle's; the headline value is the fastest path whose trajectory
-meets 1e-10 relative (peak-normalised).  The oracle is also timed on the host
-as the CPU baseline.  A batch of 256
-contingency cases on the same network (each loses a different line) is timed
-as well (FP64 and mixed).
+Timed region: an untimed pre-roll to step 5000 (the end of the loss window, so
+every case's line-loss correction is active while timed), then W untimed
+warm-up steps, then exactly K timed steps in launches of at most --chunk steps,
+bracketed by HIP events on the launch stream.  Inputs and state are resident
+in HBM; nothing crosses PCIe inside the timed region.
+
+Paths on the same cases: FP64, and FP32 applies with FP64 residual refinement
+(warm start, two corrections, "mixed"), each on the panel engine (16-case
+panels, leaf blocks on the matrix cores) and on one workgroup per case.  The
+panel paths' trajectories of sampled cases (every tie-line loss among them)
+are compared with the FP64 CPU oracle over the whole 8000-step horizon; the
+headline is the fastest panel path within 1e-10 (peak-normalised).  The same
+oracle runs are the CPU baseline.  The single 1432-bus case with one loss at
+step 2000 (10000 steps, one team of workgroups per case) is reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chunk C]
 Prints one JSON line.
@@ -23,6 +30,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,74 +42,125 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "EMT network solves/s + p99 step latency, mixed vs FP64 at 1e-10 rel error"
-HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PRE_ROLL = 5000          # end of the contingency batch's loss window
+HORIZON = 8000           # steps of every contingency case
+N_CASES = 256
 
-# HBM traffic of the FP64 team kernel per 500-step launch, from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0, scales from a copy of known size; profiles/k_emt_team_1432bus_hbm_counters.md).  Valid
-# only while the kernel's sources are the profiled ones.
-TEAM_TRAFFIC = {"sources": ("k_team.hip", "team_sync.h", "hinv_internal.h"), "sha256_16": "3f4c8f0151d4138c",
-                "launch_steps": 500, "bytes": 50325453}
+# HBM traffic of the headline kernel per launch, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE,
+# each scaled by what the counter reads for a copy of known size).  Valid only while the kernel's sources
+# hash to the profiled ones and the launch carries the profiled step count.
+PANEL_TRAFFIC = None
 
 
-def team_traffic(chunk):
-    import hashlib
+def traffic_bytes(rec, steps_per_launch):
+    if rec is None or steps_per_launch != rec["launch_steps"]:
+        return None
     h = hashlib.sha256()
-    for f in TEAM_TRAFFIC["sources"]:
+    for f in rec["sources"]:
         with open(os.path.join(ROOT, "paper_2105_10661_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != TEAM_TRAFFIC["sha256_16"] or chunk != TEAM_TRAFFIC["launch_steps"]:
-        return None
-    return TEAM_TRAFFIC["bytes"]
+    return rec["bytes"] if h.hexdigest()[:16] == rec["sha256_16"] else None
 
 
-def timed_run(hinv, torch, net, losses, prec, warm, warmup, steps, chunk, max_refine, rel_tol, record, khz,
-              kernel_mode="auto", max_mod_rank=2):
-    """Chunked launches of `chunk` steps: warmup launches untimed, then the timed launches.
-
-    Returns timing of the whole timed region, the mean duration of one launch of
-    the fused kernel (HIP events on the launch stream), per-step latencies from
-    the kernel's wall-clock stamps (case 0), stats, and the recorded trajectory.
-    """
-    n_cases = len(losses)
-    emt = hinv.EMT(net, n_cases, losses=losses, prec=prec, max_refine=max_refine, rel_tol=rel_tol,
-                   max_mod_rank=max_mod_rank, warm_start=warm, kernel_mode=kernel_mode)
-    n = net.n_bus
-    total = warmup + steps
-    V = torch.empty((total, n_cases, n), dtype=torch.float64, device="cuda") if record else None
-    n_launch = steps // chunk
-    clk = torch.zeros((n_launch, chunk), dtype=torch.int64, device="cuda")
+def run_region(torch, emt, pre, steps, chunk):
+    """Untimed: `pre` steps.  Timed: `steps` steps in launches of at most `chunk` steps, each
+    bracketed by HIP events on the launch stream, with the kernel's GPU wall-clock stamp after every
+    step.  Returns the region time, the launch sizes and durations and the per-step latencies (stamp
+    differences inside each launch)."""
     s = torch.cuda.current_stream()
     done = 0
-    while done < warmup:
-        k = min(chunk, warmup - done)
-        emt.step(k, record_v=record, v_out=V[done:done + k] if record else None)
+    while done < pre:
+        k = min(chunk, pre - done)
+        emt.step(k, record_v=False)
         done += k
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n_launch)]
-    for i in range(n_launch):
-        emt.set_step_clock(clk[i])
-        ev[2 * i].record(s)
-        emt.step(chunk, record_v=record, v_out=V[done:done + chunk] if record else None)
-        ev[2 * i + 1].record(s)
-        done += chunk
+    sizes = [min(chunk, steps - i) for i in range(0, steps, chunk)]
+    clk = torch.zeros(sum(sizes), dtype=torch.int64, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sizes]
+    off = 0
+    for (e0, e1), k in zip(ev, sizes):
+        emt.set_step_clock(clk[off:off + k])
+        e0.record(s)
+        emt.step(k, record_v=False)
+        e1.record(s)
+        off += k
     torch.cuda.synchronize()
     emt.set_step_clock(None)
-    launch_ms = np.array([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(n_launch)])
-    region_ms = ev[0].elapsed_time(ev[-1])
+    launch_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    region_ms = ev[0][0].elapsed_time(ev[-1][1])
     c = clk.cpu().numpy().astype(np.float64)
-    lat_us = (np.diff(c, axis=1) / khz * 1e3).ravel()
+    return region_ms, sizes, launch_ms, c
+
+
+def summarize(emt, hinv, n_cases, total_steps, region_ms, steps, clk, sizes, khz, mixed):
+    lat = []
+    off = 0
+    for k in sizes:
+        lat.append(np.diff(clk[off:off + k]) / khz * 1e3)
+        off += k
+    lat = np.concatenate(lat) if lat else np.zeros(0)
     applies, rel = emt.stats()
     try:
         emt.sync_status()
         status = "ok"
     except hinv.HinvError as e:          # e.g. a step whose last correction stayed above rel_tol
         status = e.name
+    out = {"solves_per_s": round(n_cases * steps / (region_ms * 1e-3), 1),
+           "ms_per_step": round(region_ms / steps, 6),
+           "p50_step_us": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
+           "p99_step_us": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
+           "applies_per_step": round(applies / (n_cases * total_steps), 3),
+           "device_status": status}
+    if mixed:
+        out["max_last_correction"] = rel
+    return out
+
+
+def oracle_refs(base, bcases, sample, horizon):
+    """Oracle trajectories of the sampled cases (explicit FP64 inverse, re-inversion at the loss) and
+    the CPU time they took."""
+    import oracle
+    refs = {}
+    t0 = time.perf_counter()
+    for k in sample:
+        c = bcases[k]
+        refs[k], _ = oracle.emt_run(base, horizon, loss_steps=c.loss_steps, loss_branches=c.loss_branches,
+                                    solver="inv")
+    return refs, time.perf_counter() - t0
+
+
+def trajectory_errors(hinv, torch, net, losses, engine, prec, warm, max_refine, rel_tol, refs, horizon, chunk):
+    """Run every case over the horizon (recording in chunks) and compare the sampled cases with the oracle:
+    peak-normalised and per-step-normalised maxima over the sampled cases."""
+    emt = hinv.EMT(net, len(losses), losses=losses, prec=prec, max_refine=max_refine, rel_tol=rel_tol,
+                   max_mod_rank=1, warm_start=warm, kernel_mode=engine)
+    sample = sorted(refs)
+    idx = torch.tensor(sample, device="cuda")
+    buf = torch.empty((chunk, len(losses), net.n_bus), dtype=torch.float64, device="cuda")
+    dmax = {k: 0.0 for k in sample}
+    dstep = {k: 0.0 for k in sample}
+    done = 0
+    while done < horizon:
+        k = min(chunk, horizon - done)
+        V, _ = emt.step(k, v_out=buf[:k])
+        Vs = V.index_select(1, idx).cpu().numpy()
+        for j, c in enumerate(sample):
+            R = refs[c][done:done + k]
+            d = np.abs(Vs[:, j, :] - R).max(1)
+            dmax[c] = max(dmax[c], float(d.max()))
+            dstep[c] = max(dstep[c], float((d / np.abs(R).max(1)).max()))
+        done += k
+    try:
+        emt.sync_status()
+        status = "ok"
+    except hinv.HinvError as e:
+        status = e.name
     emt.close()
-    return {"region_ms": region_ms, "launch_ms": float(launch_ms.mean()), "steps": n_launch * chunk,
-            "lat_us": lat_us, "applies": applies, "max_last_update": rel, "V": V, "n_cases": n_cases,
-            "status": status, "warmup": warmup}
-
-
+    del buf
+    per_case = {str(c): dmax[c] / float(np.abs(refs[c]).max()) for c in sample}
+    return {"steps": horizon, "cases": sample, "peak_norm": max(per_case.values()),
+            "per_step_norm": max(dstep.values()), "peak_norm_per_case": per_case, "device_status": status}
 def study_11456(hinv, torch, khz, steps=200):
     """11456-bus 8x8 torus (3 coupling levels, root capacitance 384^2).
 
@@ -375,19 +434,132 @@ def study_sizes(hinv, torch, steps=2000, copies=(1, 2, 4, 6, 8, 10, 12)):
             "paper_values": "Fig. 6b at 2148 buses: LU 5.56e6 FLOPs, fast mat-vec 1.43e6 FLOPs per solution"}
 
 
+
+
+def contingency_batch(hinv, torch, args, khz):
+    """The headline: 256 contingency cases of the 1432-bus ring (see the module docstring)."""
+    from paper_2105_10661_amd import cases
+    base, bcases = cases.cases_c4(n_cases=N_CASES, n_steps=HORIZON)
+    losses = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
+    pre = PRE_ROLL + args.warmup
+    paths = {"panel_fp64": ("panel", "fp64", False, 0, 1e-9),
+             "panel_mixed": ("panel", "fp32", True, args.max_refine, args.rel_tol),
+             "per_case_fp64": ("fused", "fp64", False, 0, 1e-9),
+             "per_case_mixed": ("fused", "fp32", True, args.max_refine, args.rel_tol)}
+    table, launches = {}, {}
+    for name, (eng, prec, warm, mr, tol) in paths.items():
+        emt = hinv.EMT(base, N_CASES, losses=losses, prec=prec, max_refine=mr, rel_tol=tol, max_mod_rank=1,
+                       warm_start=warm, kernel_mode=eng)
+        region_ms, sizes, launch_ms, clk = run_region(torch, emt, pre, args.steps, args.chunk)
+        table[name] = summarize(emt, hinv, N_CASES, pre + args.steps, region_ms, args.steps, clk, sizes, khz,
+                                prec != "fp64")
+        table[name].update(engine=eng, precision=prec if prec == "fp64" else f"{prec} apply + fp64 refinement",
+                           corrections=mr)
+        emt.close()
+        launches[name] = (sizes, launch_ms)
+
+    # accuracy of the panel paths over the whole horizon on sampled cases (every tie-line loss, the first
+    # and the last loss step), against the oracle; the same oracle runs are the CPU baseline
+    n_copy_br = 8 * cases.BASE_BRANCHES
+    ties = [k for k, c in enumerate(bcases) if int(c.loss_branches[0]) >= n_copy_br]
+    st = np.array([int(c.loss_steps[0]) for c in bcases])
+    sample = sorted(set(ties) | {int(st.argmin()), int(st.argmax())})
+    refs, cpu_s = oracle_refs(base, bcases, sample, HORIZON)
+    if not args.no_accuracy:
+        for name in ("panel_fp64", "panel_mixed"):
+            eng, prec, warm, mr, tol = paths[name]
+            table[name]["err_vs_oracle"] = trajectory_errors(hinv, torch, base, losses, eng, prec, warm, mr, tol,
+                                                             refs, HORIZON, args.chunk)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
+    cpu = {"value": round(len(sample) * HORIZON / cpu_s, 1), "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(sample)} of the {N_CASES} cases (cases {sample}: every tie-line loss, the earliest and "
+                     f"the latest loss step), each over the full {HORIZON}-step horizon: explicit FP64 inverse "
+                     f"times the current vector per step, re-inversion at the loss; {cpu_s:.2f} s"}
+    del refs
+
+    H = hinv.Hierarchy.from_network(base)
+    info = H.info()
+    H.close()
+    entries = info["leaf_entries"] + info["z_entries"] + info["s_entries"]
+    return base, losses, table, launches, entries, cpu, sample
+
+
+def single_case(hinv, torch, args, khz):
+    """The single 1432-bus case (one team of workgroups per case): FP64 and mixed, 10000 steps with one
+    line lost at step 2000, full trajectories against the oracle."""
+    from paper_2105_10661_amd import cases
+    import oracle
+    case = cases.case_c2(n_steps=10000)
+    net = case.net
+    losses = [list(zip(case.loss_steps.tolist(), case.loss_branches.tolist()))]
+    paths = {"fp64": ("fp64", False, 0, 1e-9), "mixed": ("fp32", True, args.max_refine, args.rel_tol),
+             "mixed_2apply": ("fp32", True, 1, 1e-6)}
+    t0 = time.perf_counter()
+    Vref, _ = oracle.emt_run(net, 10000, loss_steps=case.loss_steps, loss_branches=case.loss_branches, solver="inv")
+    cpu_s = time.perf_counter() - t0
+    peak = np.abs(Vref).max()
+    out = {"workload": "1432-bus 8-copy ring, one case, 10000 steps, one line lost at step 2000",
+           "engine": "team (one workgroup per leaf, one cooperative launch per chunk)", "paths": {},
+           "oracle_solves_per_s": round(10000 / cpu_s, 1)}
+    for name, (prec, warm, mr, tol) in paths.items():
+        emt = hinv.EMT(net, 1, losses=losses, prec=prec, max_refine=mr, rel_tol=tol, warm_start=warm)
+        V = torch.empty((500, 1, net.n_bus), dtype=torch.float64, device="cuda")
+        emt.step(500, v_out=V)
+        err = float(np.abs(V[:, 0, :].cpu().numpy() - Vref[:500]).max())
+        s = torch.cuda.current_stream()
+        clk = torch.zeros((19, 500), dtype=torch.int64, device="cuda")
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(19)]
+        Vt = torch.empty((9500, 1, net.n_bus), dtype=torch.float64, device="cuda")
+        for i, (e0, e1) in enumerate(ev):
+            emt.set_step_clock(clk[i])
+            e0.record(s)
+            emt.step(500, v_out=Vt[500 * i:500 * (i + 1)])
+            e1.record(s)
+        torch.cuda.synchronize()
+        emt.set_step_clock(None)
+        region_ms = ev[0][0].elapsed_time(ev[-1][1])
+        d = np.abs(Vt[:, 0, :].cpu().numpy() - Vref[500:])
+        err = max(err, float(d.max()))
+        row = summarize(emt, hinv, 1, 10000, region_ms, 9500, clk.cpu().numpy().ravel().astype(np.float64),
+                        [500] * 19, khz, prec != "fp64")
+        row["err_vs_oracle"] = {"peak_norm": err / peak, "per_step_norm": float((d.max(1) / np.abs(Vref[500:]).max(1)).max())}
+        row["timed_steps"] = 9500
+        out["paths"][name] = row
+        emt.close()
+        del V, Vt
+    return out
+
+
+def tuner_section(hinv, torch, args, base, losses):
+    """Autotuner over the contingency batch: tree (leaf tile) x engine x precision path."""
+    from paper_2105_10661_amd import cases, tune
+    fine = cases.net_ring(8, 4, copy_levels=2)
+    assert np.array_equal(fine.frm, base.frm)
+    trees = {"2 leaves per copy": (base.parent, base.bus_leaf),
+             "4 leaves per copy": (fine.parent, fine.bus_leaf)}
+    t0 = time.perf_counter()
+    tr = tune.tune(base, trees, n_cases=N_CASES, losses=losses, max_mod_rank=1, rel_tol=args.rel_tol,
+                   gate_steps=1000, horizon=HORIZON, chunk=args.chunk, timed_steps=args.chunk, reps=2, cache=None)
+    ch = tr.choice
+    return {"wall_s": round(time.perf_counter() - t0, 2),
+            "gate": f"voltages of every case over the first 1000 steps against the library's FP64 path "
+                    f"(peak-normalised), extrapolated linearly to {HORIZON} steps, within 1e-10",
+            "candidates": [{"label": r["label"], "us_per_step": None if r["us_per_step"] is None
+                            else round(r["us_per_step"], 2), "err": r["err"], "status": r["status"],
+                            "refused": r["reason"][:80] if not r["feasible"] else None} for r in tr.table()],
+            "choice": None if ch is None else ch.label()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=9500)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--chunk", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=2500, help="timed steps (after the pre-roll and the warm-up)")
+    ap.add_argument("--warmup", type=int, default=500, help="untimed steps after the pre-roll to step 5000")
+    ap.add_argument("--chunk", type=int, default=500, help="steps per launch of the fused stepping kernel")
     ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--rel-tol", type=float, default=1e-9)
-    ap.add_argument("--batch-cases", type=int, default=256)
-    ap.add_argument("--batch-steps", type=int, default=1000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-case section")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner over the contingency batch")
     ap.add_argument("--serve", action="store_true",
                     help="also run the serving workload (Poisson arrivals of mixed-size cases)")
@@ -409,11 +581,11 @@ def main():
                     help="also time the 11456-bus torus per storage precision and record error vs corrections")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(independent cases would shard across GPUs without communication)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not measured here (independent contingency "
+              "cases would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
-    if args.steps % args.chunk or args.warmup % args.chunk:
-        print("--steps and --warmup must be multiples of --chunk", file=sys.stderr)
+    if args.steps < 1 or args.warmup < 0 or args.chunk < 1:
+        print("--steps and --chunk must be positive and --warmup non-negative", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2105_10661_amd import cases, hinv
@@ -429,150 +601,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     khz = hinv.wall_clock_khz(0)
-    n_total = args.warmup + args.steps
-    case = cases.case_c2(n_steps=n_total)
-    net = case.net
-    losses = [list(zip(case.loss_steps.tolist(), case.loss_branches.tolist()))]
-    record = not args.no_accuracy
 
-    # (precision, warm start, refinement corrections, stop tolerance on the last correction)
-    paths = {"fp64": ("fp64", False, 0, 1e-9),
-             "mixed": ("fp32", True, args.max_refine, args.rel_tol),
-             "mixed_2apply": ("fp32", True, 1, 1e-6)}
-    res = {}
-    for name, (prec, warm, mr, tol) in paths.items():
-        res[name] = timed_run(hinv, torch, net, losses, prec, warm, args.warmup, args.steps, args.chunk, mr, tol,
-                              record, khz)
-
-    H = hinv.Hierarchy.from_network(net)
-    info = H.info()
-    H.close()
-    entries = info["leaf_entries"] + info["z_entries"] + info["s_entries"]
-    rp, ci, cv = hinv.network_csr(net)
-    nnz = int(rp[-1])
-    n, nbr = net.n_bus, net.n_branch
-
-    def step_bytes(prec, applies_per_step, residuals_per_step):
-        # algorithmic bytes of one EMT step: every stored inverse entry once per apply,
-        # the CSR of G once per FP64 residual, branch/bus history state read and written once
-        eb = 8 if prec == "fp64" else 4
-        return (applies_per_step * entries * eb + residuals_per_step * (nnz * 12 + (n + 1) * 4)
-                + nbr * 40 + n * 28)
-
-    acc = {}
-    cpu = None
-    if record or not args.no_cpu_baseline:
-        import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
-        t = time.perf_counter()
-        Vref, _ = oracle.emt_run(net, n_total, loss_steps=case.loss_steps, loss_branches=case.loss_branches,
-                                 solver="inv")
-        cpu_s = time.perf_counter() - t
-        if not args.no_cpu_baseline:
-            cpu = {"value": round(n_total / cpu_s, 1), "unit": "solves/s", "cores": threads, "kind": "oracle",
-                   "sample": f"the full workload ({n_total} steps of the 1432-bus case): explicit FP64 inverse, "
-                             f"OpenMP GEMV per step, re-inversion at the line loss; {cpu_s:.2f} s"}
-        if record:
-            peak = np.abs(Vref).max()
-            for name in paths:
-                Vg = res[name]["V"][:, 0, :].cpu().numpy()
-                d = np.abs(Vg - Vref)
-                acc[name] = {"peak_norm": float(d.max() / peak),
-                             "per_step_norm": float((d.max(1) / np.abs(Vref).max(1)).max())}
-                res[name]["V"] = None
-
-    def summary(r, prec):
-        steps = r["steps"]
-        ms_step = r["region_ms"] / steps
-        aps = r["applies"] / (r["n_cases"] * (r["warmup"] + steps)) if r["n_cases"] else 0
-        out = {"solves_per_s": round(r["n_cases"] * steps / (r["region_ms"] * 1e-3), 1),
-               "ms_per_step": round(ms_step, 6),
-               "p50_step_us": round(float(np.percentile(r["lat_us"], 50)), 3),
-               "p99_step_us": round(float(np.percentile(r["lat_us"], 99)), 3),
-               "applies_per_step": round(aps, 3), "device_status": r["status"]}
-        if prec != "fp64":
-            out["max_last_correction"] = r["max_last_update"]
-        return out, aps
-
-    table = {}
-    apsd = {}
-    for name, (prec, warm, mr, tol) in paths.items():
-        table[name], apsd[name] = summary(res[name], prec)
-        if name in acc:
-            table[name]["err_vs_oracle"] = acc[name]
-
-    batch = None
-    if not args.no_batch:
-        base, bcases = cases.cases_c4(n_cases=args.batch_cases, n_steps=args.batch_steps,
-                                      step_range=(1, max(2, args.batch_steps // 2)))
-        bl = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
-        batch = {"cases": args.batch_cases, "steps": args.batch_steps,
-                 "network": "1432-bus 8-copy ring, each case loses a distinct line at a random step",
-                 "engines": {"per_case": "one workgroup per case (leaf applies as LDS GEMVs)",
-                             "panel": "panels of 16 cases, one workgroup per leaf per panel, leaf blocks applied "
-                                      "to the panel with 16x16x4 MFMA, per-case SMW fused"}}
-        Hb = hinv.Hierarchy.from_network(base)
-        binfo = Hb.info()
-        Hb.close()
-        bpaths = {"fp64": ("fp64", False, 0, 1e-9), "mixed": ("fp32", True, args.max_refine, args.rel_tol)}
-        for eng, mode in (("per_case", "fused"), ("panel", "panel")):
-            for name, (prec, warm, mr, tol) in bpaths.items():
-                r = timed_run(hinv, torch, base, bl, prec, warm, 0, args.batch_steps, args.chunk, mr, tol, False, khz,
-                              kernel_mode=mode, max_mod_rank=1)
-                batch[f"{eng}_{name}"], aps = summary(r, prec)
-                if eng == "panel":
-                    # dense work of the leaf products on the matrix cores: 2 flops per leaf entry per case per apply
-                    leaf_flops = 2.0 * binfo["leaf_entries"] * aps * args.batch_cases * args.chunk
-                    tf = leaf_flops / (r["launch_ms"] * 1e-3) / 1e12
-                    peak = 78.6 if prec == "fp64" else 157.3
-                    batch[f"{eng}_{name}"]["mfma_leaf_tflops"] = round(tf, 3)
-                    batch[f"{eng}_{name}"]["mfma_peak_tflops"] = peak
-                    batch[f"{eng}_{name}"]["mfma_frac"] = round(tf / peak, 5)
-        if not args.no_tune:
-            # autotuner: leaf size (the tiles of the leaf products) x engine x precision path, timed on the
-            # device over the same cases; then the choice is timed like the rows above
-            from paper_2105_10661_amd import tune
-            fine = cases.net_ring(8, 4, copy_levels=2)
-            assert np.array_equal(fine.frm, base.frm) and np.array_equal(fine.R, base.R)
-            trees = {"2 leaves per copy": (base.parent, base.bus_leaf),
-                     "4 leaves per copy": (fine.parent, fine.bus_leaf)}
-            t0 = time.perf_counter()
-            tr = tune.tune(base, trees, n_cases=args.batch_cases, losses=bl, max_mod_rank=1, rel_tol=args.rel_tol,
-                           gate_steps=args.batch_steps, horizon=8000, timed_steps=200, reps=3, cache=None)
-            tune_s = time.perf_counter() - t0
-            ch = tr.choice
-            batch["tuner"] = {
-                "wall_s": round(tune_s, 2),
-                "gate": f"voltages of every case over the first {args.batch_steps} steps against the library's "
-                        "FP64 path (peak-normalised), extrapolated linearly to 8000 steps, within 1e-10",
-                "candidates": [{"label": r["label"], "us_per_step": None if r["us_per_step"] is None
-                                else round(r["us_per_step"], 2), "err": r["err"], "status": r["status"],
-                                "refused": r["reason"][:80] if not r["feasible"] else None} for r in tr.table()],
-                "choice": None if ch is None else ch.label()}
-            if ch is not None:
-                tnet = tune.with_tree(base, *trees[ch.tree])
-                r = timed_run(hinv, torch, tnet, bl, ch.prec, ch.warm, 0, args.batch_steps, args.chunk, ch.max_refine,
-                              args.rel_tol, False, khz, kernel_mode=ch.engine, max_mod_rank=1)
-                batch["tuned"], _ = summary(r, ch.prec)
-                batch["tuned"]["config"] = ch.label()
-        if record:
-            # accuracy of the batched mixed panel path: sampled cases against full oracle trajectories
-            import oracle
-            r = timed_run(hinv, torch, base, bl, "fp32", True, 0, args.chunk, args.chunk, args.max_refine,
-                          args.rel_tol, True, khz, kernel_mode="panel", max_mod_rank=1)
-            Vb = r["V"]
-            errs = {}
-            for k in (0, args.batch_cases - 1):
-                st, br = bl[k][0]
-                Vo, _ = oracle.emt_run(base, args.chunk, loss_steps=[st], loss_branches=[br], solver="inv")
-                errs[k] = float(np.abs(Vb[:, k, :].cpu().numpy() - Vo).max() / np.abs(Vo).max())
-            batch["panel_mixed_err_vs_oracle"] = {"steps": args.chunk, "cases": list(errs),
-                                                  "peak_norm_max": max(errs.values())}
-            del Vb
-
-    study = None
-    if args.study_11456:
-        study = study_11456(hinv, torch, khz)
+    base, losses, table, launches, entries, cpu, sample = contingency_batch(hinv, torch, args, khz)
+    single = None if args.no_single else single_case(hinv, torch, args, khz)
+    tuner = None if args.no_tune else tuner_section(hinv, torch, args, base, losses)
+    study = study_11456(hinv, torch, khz) if args.study_11456 else None
     upd = study_update(hinv, torch) if args.update_study else None
     paper = study_paper(hinv, torch) if args.paper_sweep else None
     sizes = study_sizes(hinv, torch) if args.size_sweep else None
@@ -589,40 +622,56 @@ def main():
                   "p50_step_us": round(float(np.percentile(lat, 50)), 2),
                   "p99_step_us": round(float(np.percentile(lat, 99)), 2), "max_active": r.max_active,
                   "p99_queue_wait_s": round(float(np.percentile(r.queue_wait_s, 99)), 4),
+                  "refused": r.refused,
                   "engine": "per 100-step tick: one launch with one workgroup per case for cases that fit its LDS, "
                             "one cooperative launch with one team of workgroups per larger case (level engine); "
                             "FP32 + FP64 refinement"}
 
-    # headline: the fastest path whose trajectory meets 1e-10 (peak-normalised) against the oracle
-    ok = [k for k in paths if k in acc and acc[k]["peak_norm"] <= 1e-10] if acc else ["fp64"]
-    head = max(ok, key=lambda k: table[k]["solves_per_s"]) if ok else "fp64"
+    # headline: the fastest panel path whose sampled trajectories meet 1e-10 (peak-normalised)
+    cand = ["panel_fp64", "panel_mixed"]
+    ok = [k for k in cand if "err_vs_oracle" in table[k] and table[k]["err_vs_oracle"]["peak_norm"] <= 1e-10]
+    head = max(ok or ["panel_fp64"], key=lambda k: table[k]["solves_per_s"])
     hp = table[head]
-    r = res[head]
-    prec_h, warm_h, mr_h, _ = paths[head]
-    launch_bytes = step_bytes(prec_h, apsd[head], apsd[head] if prec_h != "fp64" else 0) * args.chunk
-    achieved = launch_bytes / (r["launch_ms"] * 1e-3) / 1e9
-    kname = ("k_emt_team<double, false, false>" if prec_h == "fp64"
-             else f"k_emt_team<float, true, {'true' if warm_h else 'false'}>")
+    prec_h = "fp64" if head.endswith("fp64") else "fp32"
+    sizes_l, launch_ms = launches[head]
+    # algorithmic matrix work: 2 flops per stored entry per case per apply (the leaf blocks, Z panels and
+    # capacitance inverses of the 1432-bus hierarchy)
+    flops = [2.0 * entries * N_CASES * hp["applies_per_step"] * k for k in sizes_l]
+    achieved = sum(flops) / (sum(launch_ms) * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[prec_h]
+    kname = "k_emt_panel<double, false, false>" if prec_h == "fp64" else "k_emt_panel<float, true, true>"
+    full = [m for k, m in zip(sizes_l, launch_ms) if k == args.chunk]
+    two = {"fp64": {"per_case": table["per_case_fp64"]["solves_per_s"], "panel": table["panel_fp64"]["solves_per_s"]},
+           "mixed": {"per_case": table["per_case_mixed"]["solves_per_s"],
+                     "panel": table["panel_mixed"]["solves_per_s"]}}
     line = {
         "metric": METRIC,
         "value": hp["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": r["steps"],
+        "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": hp["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp64" if prec_h == "fp64" else "fp32 apply + fp64 residual refinement",
+        "dtype": "f64" if prec_h == "fp64" else "f32 apply + f64 residual refinement",
         "data": "synthetic",
-        "config": {"workload": "1432-bus 8-copy ring (16 leaves, 2 coupling levels), 10000 EMT steps at dt 50 us, "
-                               "one line lost at step 2000 (rank-1 SMW); one case",
-                   "n_bus": n, "n_branch": nbr, "headline_path": head, "launch_steps": args.chunk},
+        "config": {"workload": f"batched contingencies: {N_CASES} cases of one 1432-bus 8-copy ring (16 leaves, 2 "
+                               f"coupling levels), each losing a distinct random line at a random step in [500, 5000], "
+                               f"{HORIZON} EMT steps at dt 50 us",
+                   "n_cases": N_CASES, "n_bus": int(base.n_bus), "n_branch": int(base.n_branch),
+                   "timed_window": f"steps {PRE_ROLL + args.warmup + 1}..{PRE_ROLL + args.warmup + args.steps} "
+                                   f"(untimed pre-roll to step {PRE_ROLL}, then {args.warmup} warm-up steps): every "
+                                   "case's line-loss correction is active",
+                   "headline_path": head, "launch_steps": args.chunk},
         "p50_step_us": hp["p50_step_us"],
         "p99_step_us": hp["p99_step_us"],
+        "latency_note": "GPU wall-clock stamp after each step of workgroup 0; one step advances all 256 cases",
         "paths": table,
-        "batched_contingencies": batch,
+        "table_2x2_solves_per_s": two,
+        "single_case": single,
+        "tuner": tuner,
         "torus_11456": study,
         "line_update": upd,
         "paper_approximation": paper,
@@ -630,20 +679,21 @@ def main():
         "serving": served,
         "stored_entries": entries,
         "roofline": {
-            "bound": "hbm",
-            "kernel": f"{kname} (one cooperative launch of {args.chunk} steps, one workgroup per leaf)",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": team_traffic(args.chunk) if head == "fp64" else None,
-            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "launch_ms": round(r["launch_ms"], 4),
-            "bytes_per_launch": int(launch_bytes),
+            "bound": "mfma",
+            "kernel": f"{kname} (16 teams of 16 workgroups, one per leaf; one cooperative launch per chunk)",
+            "achieved": round(achieved, 4),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5),
+            "traffic": traffic_bytes(PANEL_TRAFFIC, args.chunk) if head == "panel_fp64" else None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "flops_per_step": 2.0 * entries * N_CASES * hp["applies_per_step"],
+            "launch_ms_mean": round(float(np.mean(full or launch_ms)), 4),
+            "launch_steps": args.chunk if full else sizes_l[0],
         },
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line))
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

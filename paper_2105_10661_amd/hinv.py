@@ -507,6 +507,12 @@ class Serve:
         self._h = h
         self._cases = {}
 
+    def case_bytes(self, net, losses=None, max_mod_rank=2) -> int:
+        """Device workspace new_case would take for this case (host-only size query, builds nothing)."""
+        return emt_workspace_bytes(net, 1, [losses or []], prec=self.prec, rel_tol=self.rel_tol,
+                                   max_refine=self.max_refine, max_mod_rank=max_mod_rank,
+                                   warm_start=self.warm_start)
+
     def new_case(self, net, losses=None, max_mod_rank=2) -> "EMT":
         """An EMT handle with the pool's precision settings (one case)."""
         return EMT(net, 1, losses=[losses or []], prec=self.prec, rel_tol=self.rel_tol, max_refine=self.max_refine,
@@ -530,6 +536,10 @@ class Serve:
 
     def step(self, n_steps: int) -> None:
         _check(self._lib.serve_step(self._h, int(n_steps), _stream()), "serve_step")
+
+    def synchronize(self) -> None:
+        import torch
+        torch.cuda.current_stream().synchronize()
 
     @property
     def active(self) -> int:

@@ -1,0 +1,130 @@
+"""GPU parity at the benchmark configurations' stated horizons.
+
+* Contingency batch: 256 cases of the 1432-bus ring, each losing a distinct
+  line at a random step in [500, 5000], 8000 steps, on the panel engine in
+  FP64 and with FP32 applies + FP64 refinement.
+  - Full trajectories of 16 cases against the oracle (explicit FP64 inverse,
+    re-inversion at the loss): every tie-line loss of the batch (its SMW
+    endpoints sit in two workgroups' rows), the earliest and the latest loss,
+    and seeded picks.  Peak-normalised, 1e-10.
+  - Per solve at 64 seeded (case, step) points spread over all 256 cases and
+    the whole horizon: the engine's own right-hand side at that step, solved by
+    the oracle (library sparse LU of that step's G, pinned against the dense LU
+    in the oracle tests), against the engine's voltage.  Per-vector infinity
+    norm, 1e-10.
+  The run is recorded in 500-step chunks (the whole record would be 23 GB).
+* 11456-bus torus: 10000 steps on the level engine, FP64 and FP32 + FP64
+  refinement, one line lost at step 2000, against the oracle's sparse LU time
+  loop (refactorised only at the loss step).  Peak-normalised, 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10661_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+C4_STEPS = 8000
+CHUNK = 500
+
+
+@pytest.fixture(scope="module")
+def hv():
+    import torch
+    from paper_2105_10661_amd import hinv
+    torch.cuda.set_device(0)
+    hinv.load()
+    return hinv
+
+
+@pytest.fixture(scope="module")
+def c4():
+    base, bcases = cases.cases_c4(n_cases=256, n_steps=C4_STEPS)
+    losses = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
+    st = np.array([c[0][0] for c in losses])
+    br = np.array([c[0][1] for c in losses])
+    ties = [int(k) for k in np.nonzero(br >= 8 * cases.BASE_BRANCHES)[0]]
+    assert len(ties) >= 1
+    rng = np.random.default_rng(404)
+    pick = set(ties) | {int(st.argmin()), int(st.argmax())}
+    rest = [k for k in range(256) if k not in pick]
+    pick |= set(int(k) for k in rng.choice(rest, 16 - len(pick), replace=False))
+    sample = sorted(pick)
+    print(f"[gpu] c4 oracle trajectories of cases {sample} (tie-line losses {ties})", flush=True)
+    refs = {}
+    for k in sample:
+        refs[k], _ = oracle.emt_run(base, C4_STEPS, loss_steps=[st[k]], loss_branches=[br[k]], solver="inv")
+    points = sorted(zip(rng.integers(0, 256, 64).tolist(), rng.integers(1, C4_STEPS + 1, 64).tolist()),
+                    key=lambda p: p[1])
+    return base, losses, sample, refs, points
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,warm,refine", [("fp64", False, 0), ("fp32", True, 2)])
+def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
+    import torch
+    base, losses, sample, refs, points = c4
+    print(f"[gpu] c4 256 cases x {C4_STEPS} steps, panel engine, {prec} (refine {refine})", flush=True)
+    emt = hv.EMT(base, 256, losses=losses, prec=prec, max_refine=refine, rel_tol=1e-9, warm_start=warm,
+                 max_mod_rank=1, kernel_mode="panel")
+    Vbuf = torch.empty((CHUNK, 256, base.n_bus), dtype=torch.float64, device="cuda")
+    Bbuf = torch.empty_like(Vbuf)
+    idx = torch.tensor(sample, device="cuda")
+    dmax = {k: 0.0 for k in sample}
+    solve_err = []
+    pi = 0
+    for c0 in range(0, C4_STEPS, CHUNK):
+        emt.step(CHUNK, record_b=True, v_out=Vbuf, b_out=Bbuf)
+        Vs = Vbuf.index_select(1, idx).cpu().numpy()
+        for j, k in enumerate(sample):
+            d = np.abs(Vs[:, j, :] - refs[k][c0:c0 + CHUNK]).max()
+            dmax[k] = max(dmax[k], float(d))
+        while pi < len(points) and points[pi][1] <= c0 + CHUNK:
+            k, s = points[pi]
+            lst, lbr = losses[k][0]
+            alive = np.ones(base.n_branch, bool)
+            if s >= lst:
+                alive[lbr] = False
+            b = Bbuf[s - 1 - c0, k].cpu().numpy()
+            v = Vbuf[s - 1 - c0, k].cpu().numpy()
+            x = oracle.sparse_solver(base, alive)(b)
+            solve_err.append((np.abs(v - x).max() / np.abs(x).max(), k, s))
+            pi += 1
+    emt.sync_status()
+    emt.close()
+    assert pi == len(points)
+    worst = max(solve_err)
+    print(f"[gpu] c4 {prec}: per-solve max {worst[0]:.2e} at case {worst[1]} step {worst[2]}; trajectories "
+          + ", ".join(f"{k}:{dmax[k] / np.abs(refs[k]).max():.1e}" for k in sample), flush=True)
+    assert worst[0] <= 1e-10, worst
+    for k in sample:
+        assert dmax[k] / np.abs(refs[k]).max() <= 1e-10, (k, dmax[k] / np.abs(refs[k]).max())
+
+
+@pytest.fixture(scope="module")
+def c3_ref():
+    net = cases.case_c3(n_steps=10000).net
+    print("[gpu] c3 oracle trajectory (sparse LU, 10000 steps, loss at 2000)", flush=True)
+    Vref, _ = oracle.emt_run(net, 10000, loss_steps=[2000], loss_branches=[4321], solver="sparse")
+    return net, Vref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,warm,refine", [("fp64", False, 0), ("fp32", True, 2)])
+def test_torus_11456_full_horizon(hv, c3_ref, prec, warm, refine):
+    import torch
+    net, Vref = c3_ref
+    print(f"[gpu] c3 11456 buses x 10000 steps, level engine, {prec} (refine {refine})", flush=True)
+    emt = hv.EMT(net, 1, losses=[[(2000, 4321)]], prec=prec, max_refine=refine, rel_tol=1e-9, warm_start=warm,
+                 kernel_mode="level")
+    V = torch.empty((10000, 1, net.n_bus), dtype=torch.float64, device="cuda")
+    for c0 in range(0, 10000, CHUNK):
+        emt.step(CHUNK, v_out=V[c0:c0 + CHUNK])
+    emt.sync_status()
+    emt.close()
+    d = np.abs(V[:, 0, :].cpu().numpy() - Vref)
+    err = d.max() / np.abs(Vref).max()
+    print(f"[gpu] c3 {prec}: peak-normalised {err:.2e}, per-step-normalised "
+          f"{(d.max(1) / np.abs(Vref).max(1)).max():.2e}", flush=True)
+    assert err <= 1e-10
