@@ -27,6 +27,11 @@ pytestmark = pytest.mark.gpu
 
 C4_STEPS = 8000
 CHUNK = 500
+# The device flags a step whose last FP64-residual correction exceeds this fraction of max |v|.  The
+# error left after that correction is about the refinement's contraction factor (<= 1e-4 measured for
+# FP32 storage, worst on cases whose lost line islands a bus) times the correction, so 1e-7 keeps the
+# result well inside 1e-10; the per-solve and trajectory checks measure the error itself.
+MIXED_CHECK = 1e-7
 
 
 @pytest.fixture(scope="module")
@@ -66,7 +71,7 @@ def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
     import torch
     base, losses, sample, refs, points = c4
     print(f"[gpu] c4 256 cases x {C4_STEPS} steps, panel engine, {prec} (refine {refine})", flush=True)
-    emt = hv.EMT(base, 256, losses=losses, prec=prec, max_refine=refine, rel_tol=1e-9, warm_start=warm,
+    emt = hv.EMT(base, 256, losses=losses, prec=prec, max_refine=refine, rel_tol=MIXED_CHECK, warm_start=warm,
                  max_mod_rank=1, kernel_mode="panel")
     Vbuf = torch.empty((CHUNK, 256, base.n_bus), dtype=torch.float64, device="cuda")
     Bbuf = torch.empty_like(Vbuf)
@@ -91,7 +96,11 @@ def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
             x = oracle.sparse_solver(base, alive)(b)
             solve_err.append((np.abs(v - x).max() / np.abs(x).max(), k, s))
             pi += 1
-    emt.sync_status()
+    try:
+        emt.sync_status()
+        status = "ok"
+    except hv.HinvError as e:
+        status = e.name
     emt.close()
     assert pi == len(points)
     worst = max(solve_err)
@@ -100,6 +109,7 @@ def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
     assert worst[0] <= 1e-10, worst
     for k in sample:
         assert dmax[k] / np.abs(refs[k]).max() <= 1e-10, (k, dmax[k] / np.abs(refs[k]).max())
+    assert status == "ok", status
 
 
 @pytest.fixture(scope="module")
@@ -116,8 +126,8 @@ def test_torus_11456_full_horizon(hv, c3_ref, prec, warm, refine):
     import torch
     net, Vref = c3_ref
     print(f"[gpu] c3 11456 buses x 10000 steps, level engine, {prec} (refine {refine})", flush=True)
-    emt = hv.EMT(net, 1, losses=[[(2000, 4321)]], prec=prec, max_refine=refine, rel_tol=1e-9, warm_start=warm,
-                 kernel_mode="level")
+    emt = hv.EMT(net, 1, losses=[[(2000, 4321)]], prec=prec, max_refine=refine, rel_tol=MIXED_CHECK,
+                 warm_start=warm, kernel_mode="level")
     V = torch.empty((10000, 1, net.n_bus), dtype=torch.float64, device="cuda")
     for c0 in range(0, 10000, CHUNK):
         emt.step(CHUNK, v_out=V[c0:c0 + CHUNK])
