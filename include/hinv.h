@@ -192,6 +192,23 @@ hinv_status hinv_update_line(hinv_handle h, int32_t a, int32_t b, double delta_g
 hinv_status hinv_solve(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as hinv_solve, bit for bit, with its per-call temporaries (permuted
+ * input and output, level values, refinement residual and correction,
+ * convergence stats) in the library's static device scratch instead of the
+ * handle's workspace, so nrhs is not bounded by opt.max_nrhs.  Allocates
+ * nothing and calls no allocating routine.  The scratch is 32 MiB per GPU,
+ * held from the first hinv_build on that device until the process ends; a call
+ * needs 8 * nrhs * (4n + n_cols) bytes plus 256-byte alignment per part
+ * (n_cols: coupling columns of the tree, hinv_get_info), and a larger request
+ * fails with HINV_E_INVALID before any launch.  Every call on one GPU shares
+ * that GPU's scratch, which keeps the last call's contents: calls that overlap
+ * in time on one GPU (on different streams or threads) race and must be
+ * serialised by the caller.  Arguments, layout and errors as hinv_solve. */
+hinv_status hinv_solve_noalloc(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld,
+                               void* stream);
+
 /* After the caller has synchronised the stream: HINV_E_NO_CONVERGENCE or
  * HINV_E_NOT_SPD if a kernel flagged it since the last call, else HINV_OK.
  * Clears the flags. */

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -653,31 +654,47 @@ hinv_status build_device(hinv_ctx& c, hipStream_t s)
 
 // v = P x for nrhs columns already in the new order (X -> out), in the apply
 // precision, including the active line changes of sets set0.. .
-void precond(hinv_ctx& c, int prec, const double* X, double* out, int nrhs, int set_stride, const int64_t* step,
-             hipStream_t s)
+// Per-call temporaries of a solve: level values Y [nrhs * n_cols], residual Rv and correction D
+// [nrhs * n], per-column convergence stats [nrhs].
+struct SolveTemps {
+    double* Y;
+    double* Rv;
+    double* D;
+    unsigned long long* stats;
+};
+
+void precond(hinv_ctx& c, const SolveTemps& w, int prec, const double* X, double* out, int nrhs, int set_stride,
+             const int64_t* step, hipStream_t s)
 {
-    launch_apply(c.H, c.P.lv.data(), prec, X, out, c.Y, nrhs, s);
+    launch_apply(c.H, c.P.lv.data(), prec, X, out, w.Y, nrhs, s);
     launch_smw_apply(c.M, prec, out, nrhs, 0, set_stride, step, s);
 }
 
 // Full solve in the new order: FP64 apply, or low-precision apply + FP64
 // refinement.  set_stride 0: every column uses change set 0; 1: column k uses set k.
-void solve_new_order(hinv_ctx& c, const double* B, double* V, int nrhs, int set_stride, const int64_t* step,
-                     hipStream_t s)
+void solve_new_order(hinv_ctx& c, const SolveTemps& w, const double* B, double* V, int nrhs, int set_stride,
+                     const int64_t* step, hipStream_t s)
 {
     if (c.opt.prec == HINV_FP64 && c.opt.coupling == HINV_COUPLING_EXACT) {
-        precond(c, HINV_FP64, B, V, nrhs, set_stride, step, s);
+        precond(c, w, HINV_FP64, B, V, nrhs, set_stride, step, s);
         c.applies += nrhs;
         return;
     }
-    precond(c, c.opt.prec, B, V, nrhs, set_stride, step, s);
+    precond(c, w, c.opt.prec, B, V, nrhs, set_stride, step, s);
     for (int it = 0; it < c.opt.max_refine; ++it) {
-        launch_residual(c.H, c.M, B, V, c.Rv, nrhs, set_stride, step, s);
-        precond(c, c.opt.prec, c.Rv, c.D, nrhs, set_stride, step, s);
-        launch_axpy_stats(c.P.n, nrhs, V, c.D, (it == c.opt.max_refine - 1) ? c.stats : nullptr, c.opt.rel_tol,
+        launch_residual(c.H, c.M, B, V, w.Rv, nrhs, set_stride, step, s);
+        precond(c, w, c.opt.prec, w.Rv, w.D, nrhs, set_stride, step, s);
+        launch_axpy_stats(c.P.n, nrhs, V, w.D, (it == c.opt.max_refine - 1) ? w.stats : nullptr, c.opt.rel_tol,
                           c.d_flags, s);
     }
     c.applies += (int64_t)nrhs * (1 + c.opt.max_refine);
+}
+
+// the same with the temporaries of the handle's own workspace
+void solve_new_order(hinv_ctx& c, const double* B, double* V, int nrhs, int set_stride, const int64_t* step,
+                     hipStream_t s)
+{
+    solve_new_order(c, SolveTemps{c.Y, c.Rv, c.D, c.stats}, B, V, nrhs, set_stride, step, s);
 }
 
 // Stored change j of set 0: u_j = G0^{-1} (e_a - e_b) by one FP64 apply of the current hierarchy.
@@ -903,6 +920,51 @@ void fill_update_info(const Plan& P, const LocalSet& U, hinv_update_info* out)
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Static device scratch of the allocation-free solve (hinv_solve_noalloc).  Each GPU the library
+// runs on holds one copy of this array for the life of the process.  In host code its name is only a
+// stand-in for the symbol: the device address of each GPU's copy comes from hipGetSymbolAddress, once
+// per device, and only that address is handed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// The current device's copy of the scratch array (looked up on the first call per device).
+hinv_status scratch_of_current_device(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(HINV_E_DEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HINV_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HINV_OK;
+}
+
+// Scratch bytes of one allocation-free solve: permuted input and output, the level values, and with
+// refinement the residual, the correction and the per-column stats.
+size_t noalloc_bytes(const hinv_ctx& c, int nrhs)
+{
+    const size_t n = (size_t)c.P.n, nc = c.P.col_row.size(), k = (size_t)nrhs;
+    auto al = [](size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); };
+    size_t b = 2 * al(sizeof(double) * n * k) + al(sizeof(double) * (nc > 0 ? nc : 1) * k);
+    b += 2 * al(sizeof(double) * n * k) + al(sizeof(unsigned long long) * k);
+    return b;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
 }  // namespace
 
 // =============================== C ABI =====================================
@@ -941,9 +1003,15 @@ hinv_status hinv_build(const hinv_csr* G, const hinv_tree* tree, const hinv_opti
     c->M.R = opt->max_mod_rank;     // 0 disables the correction entirely
     st = build_device(*c, (hipStream_t)stream);
     if (st != HINV_OK) return st;
+    {   // set-up of the allocation-free solve's scratch on this device; a failure is reported by that call
+        void* ptr = nullptr;
+        const std::string keep = g_err;
+        if (scratch_of_current_device(&ptr) != HINV_OK) g_err = keep;
+    }
     *out = c.release();
     return HINV_OK;
 }
+
 
 hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream)
 {
@@ -1019,6 +1087,40 @@ hinv_status hinv_solve(hinv_handle h, const double* d_i, double* d_v, int32_t nr
     launch_permute_in(c.P.n, nrhs, c.d_perm, d_i, ld, c.X, s);
     solve_new_order(c, c.X, c.Xo, nrhs, 0, nullptr, s);
     launch_permute_out(c.P.n, nrhs, c.d_perm, c.Xo, d_v, ld, s);
+    HIP_TRY(hipGetLastError());
+    return HINV_OK;
+}
+
+hinv_status hinv_solve_noalloc(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld, void* stream)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    hinv_ctx& c = *h;
+    if (nrhs < 0) return fail(HINV_E_INVALID, "nrhs %d < 0", nrhs);
+    if (ld < c.P.n) return fail(HINV_E_INVALID, "ld %d < n %d", ld, c.P.n);
+    if (nrhs == 0) return HINV_OK;
+    if (!d_i || !d_v) return fail(HINV_E_INVALID, "NULL vector");
+    const size_t need = noalloc_bytes(c, nrhs);
+    if (need > kNoAllocScratchBytes)
+        return fail(HINV_E_INVALID, "%d right-hand sides of order %d need %zu bytes of scratch; the static scratch "
+                    "holds %zu", nrhs, c.P.n, need, kNoAllocScratchBytes);
+    void* base = nullptr;
+    hinv_status st = scratch_of_current_device(&base);
+    if (st != HINV_OK) return st;
+    Arena A;
+    A.base = (char*)base;
+    const int64_t nk = (int64_t)c.P.n * nrhs;
+    double* X = A.take<double>(nk);
+    double* Xo = A.take<double>(nk);
+    SolveTemps w{};
+    w.Y = A.take<double>((int64_t)std::max<size_t>(c.P.col_row.size(), 1) * nrhs);
+    w.Rv = A.take<double>(nk);
+    w.D = A.take<double>(nk);
+    w.stats = A.take<unsigned long long>(nrhs);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_u64, dim3((nrhs + 255) / 256), dim3(256), 0, s, w.stats, nrhs);
+    launch_permute_in(c.P.n, nrhs, c.d_perm, d_i, ld, X, s);
+    solve_new_order(c, w, X, Xo, nrhs, 0, nullptr, s);
+    launch_permute_out(c.P.n, nrhs, c.d_perm, Xo, d_v, ld, s);
     HIP_TRY(hipGetLastError());
     return HINV_OK;
 }

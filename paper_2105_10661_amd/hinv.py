@@ -22,7 +22,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp8": FP8}
 STATUS = {0: "OK", 1: "INVALID", 2: "NOT_SPD", 3: "NO_MEMORY", 4: "DEVICE", 5: "NO_SUCH_LINE",
           6: "NO_CONVERGENCE", 7: "RANK_LIMIT", 8: "SINGULAR"}
 
-EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update_line", "hinv_solve", "hinv_sync_status",
+EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update_line", "hinv_solve",
+           "hinv_solve_noalloc", "hinv_sync_status",
            "hinv_get_info", "hinv_destroy", "emt_network_csr", "emt_network3_csr", "emt_workspace_size", "emt_create",
            "emt_step", "emt_lose_line", "emt_update_line", "emt_sync_status", "emt_get_step", "emt_get_stats",
            "emt_set_step_clock", "emt_destroy",
@@ -106,6 +107,7 @@ def load() -> ctypes.CDLL:
         "chol_destroy": [P],
         "hinv_update_line": [P, i32, i32, d, P, P],
         "hinv_solve": [P, P, P, i32, i32, P],
+        "hinv_solve_noalloc": [P, P, P, i32, i32, P],
         "hinv_sync_status": [P],
         "hinv_get_info": [P, P],
         "hinv_destroy": [P],
@@ -274,6 +276,17 @@ class Hierarchy:
             out = torch.empty_like(x)
         _check(self._lib.hinv_solve(self._h, _ptr(x), _ptr(out), x.shape[0], self.n, _stream()), "hinv_solve")
         return out[0] if squeeze else out
+
+    def solve_noalloc(self, i, out):
+        """hinv_solve_noalloc: v = G^{-1} i with the library's static scratch (no allocation in the
+        library; `out` must be given).  i, out: (nrhs, n) float64 device tensors."""
+        import torch
+        if i.dim() != 2 or out.shape != i.shape or i.dtype != torch.float64 or out.dtype != torch.float64 \
+                or not i.is_contiguous() or not out.is_contiguous():
+            raise ValueError("i and out must be contiguous (nrhs, n) float64 device tensors")
+        _check(self._lib.hinv_solve_noalloc(self._h, _ptr(i), _ptr(out), i.shape[0], self.n, _stream()),
+               "hinv_solve_noalloc")
+        return out
 
     def modify_line(self, a: int, b: int, delta_g: float) -> None:
         _check(self._lib.hinv_modify_line(self._h, int(a), int(b), float(delta_g), _stream()), "hinv_modify_line")
