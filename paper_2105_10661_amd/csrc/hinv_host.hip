@@ -1012,7 +1012,6 @@ hinv_status hinv_build(const hinv_csr* G, const hinv_tree* tree, const hinv_opti
     return HINV_OK;
 }
 
-
 hinv_status hinv_modify_line(hinv_handle h, int32_t a, int32_t b, double delta_g, void* stream)
 {
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
@@ -1222,8 +1221,8 @@ struct emt_ctx {
     TeamDev TD{};
     // panel engine (cases in panels of kPanelCases, one workgroup per leaf per panel)
     bool panel_ok = false;
-    int panel_nx_cap = 0, panel_xz_cap = 0;
-    std::vector<int> pw_nx, pxrow, pxzo, pxpm, pxpc, pxpan, plpa, plpb, pczo, pcpm, pcpc, pcpan;
+    std::vector<int> pw_nx, pw_ny, pw_nt, pw_np, pxrow, pxcol, pxzo, pxpm, pxps, pxpan, plpa, plpb, pcpan, ppubr, ppubg,
+        pyslot, ptk0, ptnk, ptfo, pttile, pttp, pttl, pwtask;
     PanelDev PD{};
     // level engine (one case, distributed coupling levels)
     bool level_ok = false;
@@ -1476,7 +1475,6 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
     }
     c.panel_ok = false;
     if (((mode == 0 && c.n_cases > 1) || mode == 4) && fused_prec) {
-        c.panel_nx_cap = 0;
         c.panel_ok = build_panel_plan(c, c.R);
         if (c.panel_ok) carve_panel(c, A);
     }
@@ -1817,34 +1815,66 @@ bool build_panel_plan(emt_ctx& c, int R)
 {
     const Plan& P = c.hc.P;
     const int L = (int)P.leaf_lo.size(), H = P.n_levels, NC = (int)P.col_row.size();
-    if (R > kPanelMaxRank || L < 1 || L > 256 || NC > kPanelMaxCols || H < 0) return false;
+    // one thread per (workgroup, change, case) gathers the shares of u^T x
+    if (R > kPanelMaxRank || L < 1 || L * std::max(R, 1) * kPanelCases > kPanelWaves * 64 || NC > kPanelMaxCols || H < 0)
+        return false;
     const int n_teams = (c.n_cases + kPanelCases - 1) / kPanelCases;
-    std::vector<int> lpan((size_t)L * H, -1);
+    const int Hs = std::max(H, 1);
+    std::vector<int> lpan((size_t)L * Hs, -1);       // panel of leaf l's rows at level h
     for (int l = 0; l < L; ++l) {
         for (int k = 0; k < P.anc_stride; ++k) {
             const int t = P.leaf_anc[(size_t)l * P.anc_stride + k];
             if (t < 0) break;
             const int h = P.node_level[t];
             for (int pp = P.node_pan0[t]; pp < P.node_pan0[t] + P.node_npan[t]; ++pp)
-                if (P.pan_lo[pp] <= P.leaf_lo[l] && P.leaf_lo[l] < P.pan_lo[pp] + P.pan_n[pp]) lpan[(size_t)l * H + h - 1] = pp;
+                if (P.pan_lo[pp] <= P.leaf_lo[l] && P.leaf_lo[l] < P.pan_lo[pp] + P.pan_n[pp]) lpan[(size_t)l * Hs + h - 1] = pp;
         }
     }
-    int rowz = 1;           // largest number of Z values of one row over all levels
-    for (int l = 0; l < L; ++l) {
-        int z = 0;
-        for (int h = 1; h <= H; ++h)
-            if (lpan[(size_t)l * H + h - 1] >= 0) z += P.pan_m[lpan[(size_t)l * H + h - 1]];
-        rowz = std::max(rowz, z);
+    // the map y = M u: the panel of each column's row at every lower level (for its device build), and the
+    // columns each y depends on, as one covering range per column (bottom-up, as the levels compose)
+    c.pcpan.assign((size_t)NC * Hs, -1);
+    std::vector<int> blo(NC, 0), bhi(NC, -1);
+    {
+        std::vector<int> alo(NC, INT32_MAX), ahi(NC, -1);
+        for (int h = 1; h <= H; ++h) {
+            for (int g = P.lvl_col[h - 1]; g < P.lvl_col[h]; ++g) {
+                const int lf = P.row_leaf[P.col_row[g]];
+                for (int hh = 1; hh < h; ++hh) {
+                    const int pp = lpan[(size_t)lf * Hs + hh - 1];
+                    c.pcpan[(size_t)g * Hs + hh - 1] = pp;
+                    if (pp < 0) continue;
+                    for (int j = 0; j < P.pan_m[pp]; ++j) {
+                        const int gp = P.pan_col0[pp] + j;
+                        alo[g] = std::min(alo[g], blo[gp]);
+                        ahi[g] = std::max(ahi[g], bhi[gp]);
+                    }
+                }
+            }
+            for (int g = P.lvl_col[h - 1]; g < P.lvl_col[h]; ++g) {
+                const int t = P.col_node[g], c0 = P.node_col0[t], m = P.node_m[t];
+                blo[g] = c0;
+                bhi[g] = c0 + m - 1;
+                for (int p = 0; p < m; ++p) {
+                    if (ahi[c0 + p] < 0) continue;
+                    blo[g] = std::min(blo[g], alo[c0 + p]);
+                    bhi[g] = std::max(bhi[g], ahi[c0 + p]);
+                }
+            }
+        }
     }
-    // per leaf: fixed X rows (neighbours through G), own Z panels, CSR rows, branches, sources
+    std::vector<int> row_col(c.n, -1);               // a coupling column of each row
+    for (int g = NC - 1; g >= 0; --g) row_col[P.col_row[g]] = g;
+    // per leaf: X rows (neighbours through G in other leaves), own Z panels, CSR rows, branches, sources,
+    // published columns, y slots and tasks
     struct W {
-        std::vector<int> fx, ozo, opm, opc, opan, orp, ocol, bglob, bf, bt, bown, iptr, ibr, sptr;
+        std::vector<int> fx, xcol, ozo, opm, ops, opan, orp, ocol, bglob, bf, bt, bown, iptr, ibr, sptr, pubr, pubg;
+        std::vector<int> xzo, xpm, xps, xpan, yslot, tk0, tnk, tfo, ttile, ttp, ttl, wtask;
         std::vector<double> oval, bg, bal, samp, sph;
         std::vector<int> osrc;       // CSR entry of each oval value, plus one
-        int zo = 0;
+        int zo = 0, xz = 0, mf = 0;
     };
     std::vector<W> ws(L);
-    int NL = 1, NB = 1, NE = 1, NI = 1, NS = 1, ZO = 1;
+    int NL = 1, NB = 1, NE = 1, NI = 1, NS = 1, ZO = 1, NX = 1, XZ = 1, NY = 16, NT = 1, MF = 64, NP = 1;
     for (int l = 0; l < L; ++l) {
         W& w = ws[l];
         const int lo = P.leaf_lo[l], nl = P.leaf_n[l];
@@ -1854,16 +1884,109 @@ bool build_panel_plan(emt_ctx& c, int R)
                 if (!own(P.ci[e])) w.fx.push_back(P.ci[e]);
         std::sort(w.fx.begin(), w.fx.end());
         w.fx.erase(std::unique(w.fx.begin(), w.fx.end()), w.fx.end());
+        for (int x : w.fx) {
+            if (row_col[x] < 0) return false;        // a neighbour in another leaf is the end of a cut line
+            w.xcol.push_back(row_col[x]);
+        }
         auto comb = [&](int row) {
             return own(row) ? row - lo : nl + (int)(std::lower_bound(w.fx.begin(), w.fx.end(), row) - w.fx.begin());
         };
-        w.ozo.assign(H, -1); w.opm.assign(H, 0); w.opc.assign(H, 0); w.opan.assign(H, -1);
+        // columns whose y this workgroup applies: its own rows' panels and its X rows' panels
+        std::vector<int> need;
         for (int h = 1; h <= H; ++h) {
-            const int pp = lpan[(size_t)l * H + h - 1];
+            const int pp = lpan[(size_t)l * Hs + h - 1];
+            if (pp >= 0)
+                for (int q = 0; q < P.pan_m[pp]; ++q) need.push_back(P.pan_col0[pp] + q);
+            for (int x : w.fx) {
+                const int px = lpan[(size_t)P.row_leaf[x] * Hs + h - 1];
+                if (px >= 0)
+                    for (int q = 0; q < P.pan_m[px]; ++q) need.push_back(P.pan_col0[px] + q);
+            }
+        }
+        std::sort(need.begin(), need.end());
+        need.erase(std::unique(need.begin(), need.end()), need.end());
+        // slots: columns with the same dependency range together, each range group padded to 16-row tiles
+        std::stable_sort(need.begin(), need.end(), [&](int a, int b) {
+            return blo[a] != blo[b] ? blo[a] < blo[b] : bhi[a] != bhi[b] ? bhi[a] < bhi[b] : a < b;
+        });
+        std::vector<int> slot_of(NC, -1);
+        for (size_t q = 0; q < need.size();) {
+            size_t e = q;
+            while (e < need.size() && blo[need[e]] == blo[need[q]] && bhi[need[e]] == bhi[need[q]]) ++e;
+            for (size_t k = q; k < e; ++k) {
+                slot_of[need[k]] = (int)w.yslot.size();
+                w.yslot.push_back(need[k]);
+            }
+            while (w.yslot.size() % 16) w.yslot.push_back(-1);
+            q = e;
+        }
+        // tasks: a tile's k-steps (those of its range group) in ceil(k-steps / kPanelYChain) near-equal
+        // chains, a split that depends on the range alone
+        const int ntile = (int)w.yslot.size() / 16;
+        w.ttp.assign(ntile + 1, 0);
+        for (int t = 0; t < ntile; ++t) {
+            int g0 = -1;
+            for (int k = 0; k < 16 && g0 < 0; ++k) g0 = w.yslot[t * 16 + k];
+            const int kb = blo[g0] / 4, ke = bhi[g0] / 4 + 1, nk = ke - kb;
+            const int nsplit = (nk + kPanelYChain - 1) / kPanelYChain;
+            for (int q = 0; q < nsplit; ++q) {
+                const int a = kb + (int)((int64_t)q * nk / nsplit), b = kb + (int)((int64_t)(q + 1) * nk / nsplit);
+                w.ttl.push_back((int)w.tk0.size());
+                w.tk0.push_back(a);
+                w.tnk.push_back(b - a);
+                w.tfo.push_back(w.mf);
+                w.ttile.push_back(t);
+                w.mf += (b - a) * 64;
+            }
+            w.ttp[t + 1] = (int)w.ttl.size();
+        }
+        // tasks onto wavefronts: largest first, each to the least loaded SIMD (wavefront w runs on SIMD w % 4)
+        // and there to its least loaded wavefront with a free place
+        {
+            const int nt = (int)w.tk0.size();
+            if (nt > kPanelWaves * kPanelYTasksPerWave) return false;
+            std::vector<int> ord(nt);
+            for (int t = 0; t < nt; ++t) ord[t] = t;
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return w.tnk[a] > w.tnk[b]; });
+            std::vector<int> load(kPanelWaves, 0), used(kPanelWaves, 0), sload(4, 0);
+            w.wtask.assign(kPanelWaves * kPanelYTasksPerWave, -1);
+            for (int t : ord) {
+                int best = -1;
+                for (int q = 0; q < kPanelWaves; ++q) {
+                    if (used[q] >= kPanelYTasksPerWave) continue;
+                    if (best < 0 || sload[q % 4] < sload[best % 4] ||
+                        (sload[q % 4] == sload[best % 4] && load[q] < load[best])) best = q;
+                }
+                w.wtask[best * kPanelYTasksPerWave + used[best]++] = t;
+                load[best] += w.tnk[t];
+                sload[best % 4] += w.tnk[t];
+            }
+        }
+        w.ozo.assign(Hs, -1); w.opm.assign(Hs, 0); w.ops.assign(Hs, 0); w.opan.assign(Hs, -1);
+        for (int h = 1; h <= H; ++h) {
+            const int pp = lpan[(size_t)l * Hs + h - 1];
             if (pp < 0) continue;
-            w.opan[h - 1] = pp; w.ozo[h - 1] = w.zo; w.opm[h - 1] = P.pan_m[pp]; w.opc[h - 1] = P.pan_col0[pp];
+            w.opan[h - 1] = pp; w.ozo[h - 1] = w.zo; w.opm[h - 1] = P.pan_m[pp];
+            w.ops[h - 1] = slot_of[P.pan_col0[pp]];
             w.zo += P.pan_m[pp] * nl;
         }
+        w.xzo.assign((size_t)w.fx.size() * Hs, -1); w.xpm.assign((size_t)w.fx.size() * Hs, 0);
+        w.xps.assign((size_t)w.fx.size() * Hs, 0); w.xpan.assign((size_t)w.fx.size() * Hs, -1);
+        for (size_t x = 0; x < w.fx.size(); ++x) {
+            const int lx = P.row_leaf[w.fx[x]];
+            for (int h = 1; h <= H; ++h) {
+                const int pp = lpan[(size_t)lx * Hs + h - 1];
+                if (pp < 0) continue;
+                const size_t i = x * Hs + h - 1;
+                w.xzo[i] = w.xz; w.xpm[i] = P.pan_m[pp]; w.xps[i] = slot_of[P.pan_col0[pp]]; w.xpan[i] = pp;
+                w.xz += P.pan_m[pp];
+            }
+        }
+        for (int g = 0; g < NC; ++g)
+            if (own(P.col_row[g])) {
+                w.pubr.push_back(P.col_row[g] - lo);
+                w.pubg.push_back(g);
+            }
         w.orp.assign(nl + 1, 0);
         for (int r = lo; r < lo + nl; ++r) {
             for (int e = P.rp[r]; e < P.rp[r + 1]; ++e) {
@@ -1901,100 +2024,50 @@ bool build_panel_plan(emt_ctx& c, int R)
         NL = std::max(NL, nl); NB = std::max(NB, (int)br.size());
         NE = std::max(NE, (int)w.ocol.size()); NI = std::max(NI, (int)w.ibr.size());
         NS = std::max(NS, (int)w.samp.size()); ZO = std::max(ZO, w.zo);
+        NX = std::max(NX, (int)w.fx.size()); XZ = std::max(XZ, w.xz);
+        NY = std::max(NY, (int)w.yslot.size()); NT = std::max(NT, (int)w.tk0.size());
+        MF = std::max(MF, w.mf); NP = std::max(NP, (int)w.pubg.size());
     }
-    // coupling columns: Z values of the column's row below the column's level
-    c.pczo.assign((size_t)NC * H, -1); c.pcpm.assign((size_t)NC * H, 0);
-    c.pcpc.assign((size_t)NC * H, 0); c.pcpan.assign((size_t)NC * H, -1);
-    int CZ = 0;
-    for (int g = 0; g < NC; ++g) {
-        const int hg = P.node_level[P.col_node[g]];
-        const int lx = P.row_leaf[P.col_row[g]];
-        for (int hh = 1; hh < hg; ++hh) {
-            const int pp = lpan[(size_t)lx * H + hh - 1];
-            if (pp < 0) continue;
-            const size_t i = (size_t)g * H + hh - 1;
-            c.pczo[i] = CZ; c.pcpm[i] = P.pan_m[pp]; c.pcpc[i] = P.pan_col0[pp]; c.pcpan[i] = pp;
-            CZ += P.pan_m[pp];
-        }
-    }
-    int max_lw = 1;
-    for (int h = 1; h <= H; ++h) {
-        max_lw = std::max(max_lw, P.lvl_col[h] - P.lvl_col[h - 1]);
-        int tiles = 0;             // 16-row tiles of the level's S^{-1} (the level solve's matrix products)
-        for (int t = P.lvl_node[h - 1]; t < P.lvl_node[h]; ++t) tiles += (P.node_m[t] + 15) / 16;
-        if (tiles > kPanelMaxLevelTiles) return false;
-    }
-    // per (team, leaf): X rows = fixed rows, then the team's loss endpoints
-    std::vector<std::vector<int>> X((size_t)n_teams * L);
-    std::vector<std::vector<int>> lpa((size_t)n_teams * L), lpb((size_t)n_teams * L);
-    int NX = 1, XZ = 1;
+    // history items per thread (kernel: 6 of 512 threads' (branch, case) items); combined indices in 16 bits
+    if (NX > kPanelMaxX || NL > kPanelMaxLeaf || NB * kPanelCases > 6 * kPanelWaves * 64) return false;
+    // per (team, leaf): the combined index of each change's endpoints where it is a row of the workgroup
+    // (a change's other endpoint is then a neighbour through G, hence a row too; the refinement residual
+    // takes the change's term on such rows), -1 elsewhere
+    std::vector<int> lpa((size_t)n_teams * L * kPanelCases * R, -1), lpb((size_t)n_teams * L * kPanelCases * R, -1);
     for (int tm = 0; tm < n_teams; ++tm) {
-        std::vector<int> lrows;
-        for (int cc = 0; cc < kPanelCases; ++cc) {
-            const int k = tm * kPanelCases + cc;
-            if (k >= c.n_cases) break;
-            for (auto& x : c.losses[k]) {
-                lrows.push_back(c.fr_p[x.second]);
-                lrows.push_back(c.to_p[x.second]);
-            }
-        }
         for (int l = 0; l < L; ++l) {
+            const W& w = ws[l];
             const int lo = P.leaf_lo[l], nl = P.leaf_n[l];
-            auto own = [&](int r) { return r >= lo && r < lo + nl; };
-            std::vector<int>& xr = X[(size_t)tm * L + l];
-            xr = ws[l].fx;
-            for (int r : lrows)
-                if (!own(r) && std::find(xr.begin(), xr.end(), r) == xr.end()) xr.push_back(r);
             auto comb = [&](int row) {
-                if (own(row)) return row - lo;
-                return nl + (int)(std::find(xr.begin(), xr.end(), row) - xr.begin());
+                if (row >= lo && row < lo + nl) return row - lo;
+                auto it = std::lower_bound(w.fx.begin(), w.fx.end(), row);
+                return (it != w.fx.end() && *it == row) ? nl + (int)(it - w.fx.begin()) : -1;
             };
-            int xz = 0;
-            for (int row : xr) {
-                const int lx = P.row_leaf[row];
-                for (int h = 1; h <= H; ++h)
-                    if (lpan[(size_t)lx * H + h - 1] >= 0) xz += P.pan_m[lpan[(size_t)lx * H + h - 1]];
-            }
-            std::vector<int>& pa = lpa[(size_t)tm * L + l];
-            std::vector<int>& pb = lpb[(size_t)tm * L + l];
-            pa.assign((size_t)kPanelCases * R, -1);
-            pb.assign((size_t)kPanelCases * R, -1);
             for (int cc = 0; cc < kPanelCases; ++cc) {
                 const int k = tm * kPanelCases + cc;
                 if (k >= c.n_cases) break;
                 const auto& Lk = c.losses[k];
-                for (size_t j = 0; j < Lk.size(); ++j) {
-                    pa[(size_t)cc * R + j] = comb(c.fr_p[Lk[j].second]);
-                    pb[(size_t)cc * R + j] = comb(c.to_p[Lk[j].second]);
+                for (size_t j = 0; j < Lk.size() && (int)j < R; ++j) {
+                    const int a = comb(c.fr_p[Lk[j].second]), b = comb(c.to_p[Lk[j].second]);
+                    const bool own_a = a >= 0 && a < nl, own_b = b >= 0 && b < nl;
+                    if ((own_a && b < 0) || (own_b && a < 0)) return false;
+                    const size_t o = (((size_t)tm * L + l) * kPanelCases + cc) * R + j;
+                    lpa[o] = a;
+                    lpb[o] = b;
                 }
             }
-            NX = std::max(NX, (int)xr.size());
-            XZ = std::max(XZ, xz);
         }
     }
-    if (c.panel_nx_cap == 0) {            // room for the endpoints of later line losses
-        c.panel_nx_cap = NX + 8;
-        c.panel_xz_cap = XZ + 8 * rowz;
-    }
-    if (NX > c.panel_nx_cap || XZ > c.panel_xz_cap) return false;
     PanelDev& D = c.PD;
-    D.T = L; D.H = H; D.NL = NL; D.NLp = (NL + 15) / 16 * 16; D.NX = c.panel_nx_cap; D.NB = NB; D.NE = NE;
-    D.NI = NI; D.NS = NS; D.XZ = c.panel_xz_cap; D.ZO = ZO; D.CZ = std::max(CZ, 1); D.nc = NC; D.max_lw = max_lw;
+    D.T = L; D.H = H; D.NL = NL; D.NLp = (NL + 15) / 16 * 16; D.NX = NX; D.NB = NB; D.NE = NE;
+    D.NI = NI; D.NS = NS; D.XZ = XZ; D.ZO = ZO; D.nc = NC; D.ncp = (NC + 3) / 4 * 4;
+    D.NY = NY; D.NT = NT; D.MF = MF; D.NP = NP;
     D.n_teams = n_teams; D.team0 = 0;
-    if (D.NX > kPanelMaxX || D.NL > kPanelMaxLeaf) return false;
-    c.tcsop.assign(NC, 0);
-    {
-        int64_t off = 0;
-        for (size_t t = 0; t < P.node_m.size(); ++t) {
-            const int m = P.node_m[t];
-            for (int q = 0; q < m; ++q) c.tcsop[P.node_col0[t] + q] = (int)(off + q);
-            off += (int64_t)m * (m + 1);
-        }
-        D.sent = (int)std::max<int64_t>(off, 1);
-    }
+    D.ysep = 1;              // a region of its own for the y results if LDS allows, else they overwrite u
+    if (panel_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) D.ysep = 0;
     if (panel_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) return false;
-    auto flat = [&](std::vector<int>& dst, size_t stride, auto get) {
-        dst.assign((size_t)L * stride, 0);
+    auto flat = [&](std::vector<int>& dst, size_t stride, int fill, auto get) {
+        dst.assign((size_t)L * stride, fill);
         for (int l = 0; l < L; ++l) {
             const std::vector<int>& src = get(ws[l]);
             std::copy(src.begin(), src.end(), dst.begin() + (size_t)l * stride);
@@ -2008,99 +2081,124 @@ bool build_panel_plan(emt_ctx& c, int R)
         }
     };
     c.tw_lo = P.leaf_lo; c.tw_nl = P.leaf_n;
-    c.tw_nb.resize(L);
-    for (int l = 0; l < L; ++l) c.tw_nb[l] = (int)ws[l].bglob.size();
-    flat(c.tozo, H, [](W& w) -> std::vector<int>& { return w.ozo; });
-    flat(c.topm, H, [](W& w) -> std::vector<int>& { return w.opm; });
-    flat(c.topc, H, [](W& w) -> std::vector<int>& { return w.opc; });
-    flat(c.topan, H, [](W& w) -> std::vector<int>& { return w.opan; });
-    flat(c.torp, NL + 1, [](W& w) -> std::vector<int>& { return w.orp; });
-    flat(c.tocol, NE, [](W& w) -> std::vector<int>& { return w.ocol; });
-    flat(c.tbglob, NB, [](W& w) -> std::vector<int>& { return w.bglob; });
-    flat(c.tbf, NB, [](W& w) -> std::vector<int>& { return w.bf; });
-    flat(c.tbt, NB, [](W& w) -> std::vector<int>& { return w.bt; });
-    flat(c.tbown, NB, [](W& w) -> std::vector<int>& { return w.bown; });
-    flat(c.tiptr, NL + 1, [](W& w) -> std::vector<int>& { return w.iptr; });
-    flat(c.tibr, NI, [](W& w) -> std::vector<int>& { return w.ibr; });
-    flat(c.tsptr, NL + 1, [](W& w) -> std::vector<int>& { return w.sptr; });
+    c.tw_nb.resize(L); c.pw_nx.resize(L); c.pw_ny.resize(L); c.pw_nt.resize(L); c.pw_np.resize(L);
+    for (int l = 0; l < L; ++l) {
+        c.tw_nb[l] = (int)ws[l].bglob.size();
+        c.pw_nx[l] = (int)ws[l].fx.size();
+        c.pw_ny[l] = (int)ws[l].yslot.size();
+        c.pw_nt[l] = (int)ws[l].tk0.size();
+        c.pw_np[l] = (int)ws[l].pubg.size();
+    }
+    flat(c.tozo, Hs, -1, [](W& w) -> std::vector<int>& { return w.ozo; });
+    flat(c.topm, Hs, 0, [](W& w) -> std::vector<int>& { return w.opm; });
+    flat(c.topc, Hs, 0, [](W& w) -> std::vector<int>& { return w.ops; });
+    flat(c.topan, Hs, -1, [](W& w) -> std::vector<int>& { return w.opan; });
+    flat(c.torp, NL + 1, 0, [](W& w) -> std::vector<int>& { return w.orp; });
+    flat(c.tocol, NE, 0, [](W& w) -> std::vector<int>& { return w.ocol; });
+    flat(c.tbglob, NB, 0, [](W& w) -> std::vector<int>& { return w.bglob; });
+    flat(c.tbf, NB, 0, [](W& w) -> std::vector<int>& { return w.bf; });
+    flat(c.tbt, NB, 0, [](W& w) -> std::vector<int>& { return w.bt; });
+    flat(c.tbown, NB, 0, [](W& w) -> std::vector<int>& { return w.bown; });
+    flat(c.tiptr, NL + 1, 0, [](W& w) -> std::vector<int>& { return w.iptr; });
+    flat(c.tibr, NI, 0, [](W& w) -> std::vector<int>& { return w.ibr; });
+    flat(c.tsptr, NL + 1, 0, [](W& w) -> std::vector<int>& { return w.sptr; });
     flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
-    flat(c.tosrc, NE, [](W& w) -> std::vector<int>& { return w.osrc; });
+    flat(c.tosrc, NE, 0, [](W& w) -> std::vector<int>& { return w.osrc; });
     flatd(c.tbg, NB, [](W& w) -> std::vector<double>& { return w.bg; });
     flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
     flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
     flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
-    const size_t TW = (size_t)n_teams * L, NXc = D.NX;
-    c.pw_nx.assign(TW, 0);
-    c.pxrow.assign(TW * NXc, 0);
-    c.pxzo.assign(TW * NXc * H, -1); c.pxpm.assign(TW * NXc * H, 0); c.pxpc.assign(TW * NXc * H, 0);
-    c.pxpan.assign(TW * NXc * H, -1);
-    c.plpa.assign(TW * kPanelCases * R, -1); c.plpb.assign(TW * kPanelCases * R, -1);
-    for (size_t tw = 0; tw < TW; ++tw) {
-        const std::vector<int>& xr = X[tw];
-        c.pw_nx[tw] = (int)xr.size();
-        int xz = 0;
-        for (size_t x = 0; x < xr.size(); ++x) {
-            c.pxrow[tw * NXc + x] = xr[x];
-            const int lx = P.row_leaf[xr[x]];
-            for (int h = 1; h <= H; ++h) {
-                const int pp = lpan[(size_t)lx * H + h - 1];
-                if (pp < 0) continue;
-                const size_t i = (tw * NXc + x) * H + h - 1;
-                c.pxzo[i] = xz; c.pxpm[i] = P.pan_m[pp]; c.pxpc[i] = P.pan_col0[pp]; c.pxpan[i] = pp;
-                xz += P.pan_m[pp];
-            }
-        }
-        std::copy(lpa[tw].begin(), lpa[tw].end(), c.plpa.begin() + tw * kPanelCases * R);
-        std::copy(lpb[tw].begin(), lpb[tw].end(), c.plpb.begin() + tw * kPanelCases * R);
-    }
+    flat(c.ppubr, NP, 0, [](W& w) -> std::vector<int>& { return w.pubr; });
+    flat(c.ppubg, NP, 0, [](W& w) -> std::vector<int>& { return w.pubg; });
+    flat(c.pxrow, NX, 0, [](W& w) -> std::vector<int>& { return w.fx; });
+    flat(c.pxcol, NX, 0, [](W& w) -> std::vector<int>& { return w.xcol; });
+    flat(c.pxzo, (size_t)NX * Hs, -1, [](W& w) -> std::vector<int>& { return w.xzo; });
+    flat(c.pxpm, (size_t)NX * Hs, 0, [](W& w) -> std::vector<int>& { return w.xpm; });
+    flat(c.pxps, (size_t)NX * Hs, 0, [](W& w) -> std::vector<int>& { return w.xps; });
+    flat(c.pxpan, (size_t)NX * Hs, -1, [](W& w) -> std::vector<int>& { return w.xpan; });
+    flat(c.pyslot, NY, -1, [](W& w) -> std::vector<int>& { return w.yslot; });
+    flat(c.ptk0, NT, 0, [](W& w) -> std::vector<int>& { return w.tk0; });
+    flat(c.ptnk, NT, 0, [](W& w) -> std::vector<int>& { return w.tnk; });
+    flat(c.ptfo, NT, 0, [](W& w) -> std::vector<int>& { return w.tfo; });
+    flat(c.pttile, NT, 0, [](W& w) -> std::vector<int>& { return w.ttile; });
+    flat(c.pttp, NY / 16 + 1, 0, [](W& w) -> std::vector<int>& { return w.ttp; });
+    flat(c.pttl, NT, 0, [](W& w) -> std::vector<int>& { return w.ttl; });
+    flat(c.pwtask, kPanelWaves * kPanelYTasksPerWave, -1, [](W& w) -> std::vector<int>& { return w.wtask; });
+    c.plpa = std::move(lpa);
+    c.plpb = std::move(lpb);
     return true;
 }
 
-// Workspace for the panel tables (X-row tables with capacity strides).
+// Workspace for the panel tables.
 void carve_panel(emt_ctx& c, Arena& A)
 {
     PanelDev& D = c.PD;
-    const int64_t L = D.T, H = D.H, TW = (int64_t)D.n_teams * D.T, R = c.R;
+    const int64_t L = D.T, H = std::max(D.H, 1), TW = (int64_t)D.n_teams * D.T, R = c.R;
     auto ti = [&](int64_t cnt) { return A.take<int>(cnt); };
     auto td = [&](int64_t cnt) { return A.take<double>(cnt); };
-    D.w_lo = ti(L); D.w_nl = ti(L); D.w_nb = ti(L);
-    D.ozo = ti(L * H); D.opm = ti(L * H); D.opc = ti(L * H); D.opan = ti(L * H);
+    D.w_lo = ti(L); D.w_nl = ti(L); D.w_nb = ti(L); D.w_nx = ti(L); D.w_ny = ti(L); D.w_nt = ti(L);
+    D.ozo = ti(L * H); D.opm = ti(L * H); D.ops = ti(L * H); D.opan = ti(L * H);
     D.orp = ti(L * (D.NL + 1)); D.ocol = ti(L * D.NE); D.oval = td(L * D.NE);
     D.bglob = ti(L * D.NB); D.bf = ti(L * D.NB); D.bt = ti(L * D.NB); D.bown = ti(L * D.NB);
     D.bg = td(L * D.NB); D.bal = td(L * D.NB);
     D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
     D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
-    D.w_nx = ti(TW); D.xrow = ti(TW * D.NX);
-    D.xzo = ti(TW * D.NX * H); D.xpm = ti(TW * D.NX * H); D.xpc = ti(TW * D.NX * H); D.xpan = ti(TW * D.NX * H);
+    D.w_np = ti(L); D.pubr = ti(L * D.NP); D.pubg = ti(L * D.NP);
+    D.xrow = ti(L * D.NX); D.xcol = ti(L * D.NX);
+    D.xzo = ti(L * D.NX * H); D.xpm = ti(L * D.NX * H); D.xps = ti(L * D.NX * H); D.xpan = ti(L * D.NX * H);
+    D.yslot = ti(L * D.NY);
+    D.tk0 = ti(L * D.NT); D.tnk = ti(L * D.NT); D.tfo = ti(L * D.NT); D.ttile = ti(L * D.NT);
+    D.ttp = ti(L * (D.NY / 16 + 1)); D.ttl = ti(L * D.NT);
+    D.wtask = ti(L * kPanelWaves * kPanelYTasksPerWave);
+    D.mfr = td(L * D.MF);
+    D.mfr32 = A.take<float>(L * D.MF);
     D.lpa = ti(TW * kPanelCases * R); D.lpb = ti(TW * kPanelCases * R);
-    D.csop = ti(D.nc);
-    D.czo = ti((int64_t)D.nc * H); D.cpm = ti((int64_t)D.nc * H); D.cpc = ti((int64_t)D.nc * H);
-    D.cpan = ti((int64_t)D.nc * H);
+    D.cpan = ti((int64_t)std::max(D.nc, 1) * H);
+    D.am = td((int64_t)std::max(D.nc, 1) * std::max(D.nc, 1));
+    D.bm = td((int64_t)std::max(D.nc, 1) * std::max(D.nc, 1));
     D.sync = A.take<unsigned int>(TW);
-    D.X0 = td((int64_t)D.n_teams * 2 * c.n * kPanelCases);
+    D.X0 = td((int64_t)D.n_teams * 2 * std::max(D.nc, 1) * kPanelCases);
+    D.SP = td(TW * 2 * R * kPanelCases);
     D.VM = td(TW * 2 * kPanelCases);
+}
+
+// The panel's map y = M u and its A fragments, from the current FP64 hierarchy.
+hinv_status build_panel_map(emt_ctx& c, hipStream_t s)
+{
+    PanelDev& D = c.PD;
+    HIP_TRY(launch_coupling_map(c.hc.H, D.H, D.nc, D.cpan, D.am, D.bm, s));
+    HIP_TRY(launch_panel_mfrag(D, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HINV_OK;
 }
 
 hinv_status upload_panel(emt_ctx& c, hipStream_t s)
 {
     PanelDev& D = c.PD;
     HIP_TRY(up(D.w_lo, c.tw_lo, s)); HIP_TRY(up(D.w_nl, c.tw_nl, s)); HIP_TRY(up(D.w_nb, c.tw_nb, s));
-    HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.opc, c.topc, s));
+    HIP_TRY(up(D.w_nx, c.pw_nx, s)); HIP_TRY(up(D.w_ny, c.pw_ny, s)); HIP_TRY(up(D.w_nt, c.pw_nt, s));
+    HIP_TRY(up(D.ozo, c.tozo, s)); HIP_TRY(up(D.opm, c.topm, s)); HIP_TRY(up(D.ops, c.topc, s));
     HIP_TRY(up(D.opan, c.topan, s));
     HIP_TRY(up(D.orp, c.torp, s)); HIP_TRY(up(D.ocol, c.tocol, s)); HIP_TRY(up(D.oval, c.toval, s));
     HIP_TRY(up(D.bglob, c.tbglob, s)); HIP_TRY(up(D.bf, c.tbf, s)); HIP_TRY(up(D.bt, c.tbt, s));
     HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
     HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
     HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
-    HIP_TRY(up(D.w_nx, c.pw_nx, s)); HIP_TRY(up(D.xrow, c.pxrow, s));
-    HIP_TRY(up(D.xzo, c.pxzo, s)); HIP_TRY(up(D.xpm, c.pxpm, s)); HIP_TRY(up(D.xpc, c.pxpc, s));
-    HIP_TRY(up(D.xpan, c.pxpan, s)); HIP_TRY(up(D.lpa, c.plpa, s)); HIP_TRY(up(D.lpb, c.plpb, s));
-    HIP_TRY(up(D.csop, c.tcsop, s));
-    HIP_TRY(up(D.czo, c.pczo, s)); HIP_TRY(up(D.cpm, c.pcpm, s)); HIP_TRY(up(D.cpc, c.pcpc, s));
+    HIP_TRY(up(D.w_np, c.pw_np, s)); HIP_TRY(up(D.pubr, c.ppubr, s)); HIP_TRY(up(D.pubg, c.ppubg, s));
+    HIP_TRY(up(D.xrow, c.pxrow, s)); HIP_TRY(up(D.xcol, c.pxcol, s));
+    HIP_TRY(up(D.xzo, c.pxzo, s)); HIP_TRY(up(D.xpm, c.pxpm, s)); HIP_TRY(up(D.xps, c.pxps, s));
+    HIP_TRY(up(D.xpan, c.pxpan, s));
+    HIP_TRY(up(D.yslot, c.pyslot, s));
+    HIP_TRY(up(D.tk0, c.ptk0, s)); HIP_TRY(up(D.tnk, c.ptnk, s)); HIP_TRY(up(D.tfo, c.ptfo, s));
+    HIP_TRY(up(D.ttile, c.pttile, s)); HIP_TRY(up(D.ttp, c.pttp, s)); HIP_TRY(up(D.ttl, c.pttl, s));
+    HIP_TRY(up(D.wtask, c.pwtask, s));
+    HIP_TRY(up(D.lpa, c.plpa, s)); HIP_TRY(up(D.lpb, c.plpb, s));
     HIP_TRY(up(D.cpan, c.pcpan, s));
     HIP_TRY(hipMemsetAsync(D.sync, 0, (size_t)D.n_teams * D.T * sizeof(unsigned int), s));
+    D.epoch0 = 0;
+    HIP_TRY(panel_setup(D, c.R, c.hc.opt.prec, c.hc.opt.warm_start ? 1 : 0));
     HIP_TRY(hipStreamSynchronize(s));      // host tables may be rebuilt later
-    return HINV_OK;
+    return build_panel_map(c, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -2575,8 +2673,16 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
                     c.step, n_steps};
         if (c.engine == 3)
             HIP_TRY(launch_emt_team(c.TD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
-        else if (c.engine == 4)
+        else if (c.engine == 4) {
+            // barrier epochs continue from the previous launch (the flags are never reset in between)
+            const unsigned int per_step = c.hc.opt.prec == HINV_FP64 ? 1u : 1u + (unsigned)c.hc.opt.max_refine;
+            if ((uint64_t)c.PD.epoch0 + (uint64_t)n_steps * per_step >= (1ull << 31)) {
+                HIP_TRY(hipMemsetAsync(c.PD.sync, 0, (size_t)c.PD.n_teams * c.PD.T * sizeof(unsigned int), s));
+                c.PD.epoch0 = 0;
+            }
             HIP_TRY(launch_emt_panel(c.PD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
+            c.PD.epoch0 += (unsigned int)n_steps * per_step;
+        }
         else if (c.engine == 5)
             HIP_TRY(launch_emt_level(c.LD, c.E, c.hc.H, c.hc.M, P, c.hc.opt.prec, s));
         else
@@ -2654,6 +2760,10 @@ hinv_status emt_update_line(emt_handle h, int32_t a, int32_t b, double delta_g, 
         HIP_TRY(launch_team_acoef(c.TD, c.hc.H, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    if (c.engine == 4) {       // so does the panel's map y = M u
+        st = build_panel_map(c, s);
+        if (st != HINV_OK) return st;
+    }
     if (out) fill_update_info(c.hc.P, ed.U, out);
     return HINV_OK;
 }
@@ -2665,7 +2775,13 @@ hinv_status emt_sync_status(emt_handle h)
     HIP_TRY(hipMemcpy(flags, h->hc.d_flags, sizeof flags, hipMemcpyDeviceToHost));
     int zero[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpy(h->hc.d_flags, zero, sizeof zero, hipMemcpyHostToDevice));
-    if (flags[0] & kFlagBarrier) return fail(HINV_E_DEVICE, "an inter-workgroup barrier timed out");
+    if (flags[0] & kFlagBarrier) {
+        if (h->engine == 4 && h->panel_ok) {   // a team stopped early: start the next launch from fresh flags
+            HIP_TRY(hipMemset(h->PD.sync, 0, (size_t)h->PD.n_teams * h->PD.T * sizeof(unsigned int)));
+            h->PD.epoch0 = 0;
+        }
+        return fail(HINV_E_DEVICE, "an inter-workgroup barrier timed out");
+    }
     if (flags[0] & kFlagTeamRow) return fail(HINV_E_DEVICE, "a line change endpoint has no row in a workgroup's tables");
     if (flags[0] & (kFlagNotSPD | kFlagNaN)) return fail(HINV_E_NOT_SPD, "non-finite or indefinite result");
     if (flags[0] & kFlagNoConv) return fail(HINV_E_NO_CONVERGENCE, "refinement did not reach rel_tol");

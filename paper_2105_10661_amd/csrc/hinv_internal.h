@@ -279,27 +279,49 @@ struct TeamDev {
 // Panel stepping (k_panel.hip): cases that share one base network advance in
 // panels of kPanelCases; a team of one workgroup per leaf owns one panel and
 // applies the leaf blocks to the panel as one matrix product.  Per-leaf tables
-// use fixed strides as in TeamDev.  X rows of a (team, leaf) pair: first the
-// leaf's fixed external rows (neighbours of its buses through G, the same in
-// every team), then the endpoints of the team's line losses.  Combined index:
-// own row r -> r, X row x -> nl + x.  Vectors are row-major [row][case].
+// use fixed strides.  X rows of a leaf: its buses' neighbours through G in
+// other leaves (the same in every team); each is the row of a coupling column.
+// Combined index: own row r -> r, X row x -> nl + x.  Vectors are row-major
+// [row][case].
+//
+// Coupling levels in one map: the y of every coupling column is a linear map
+// of u, the leaf-apply values at the column rows (y = M u, M built on the
+// device from the FP64 Z panels, S^{-1} and column weights).  A workgroup
+// computes the y of the columns its own rows and X rows apply ("slots",
+// grouped by the columns' dependency range and padded to 16-row tiles) as
+// MFMA tasks; a range's k-steps are split into tasks of at most
+// kPanelYChain k-steps by a rule that depends on the range alone, so every
+// workgroup computing a column's y runs the same operations, and an X row's
+// value is formed exactly as its owner forms it.
 constexpr int kPanelCases = 16;
 constexpr int kPanelMaxRank = 2;
 constexpr int kPanelMaxLeaf = 96;    // rows of a leaf
 constexpr int kPanelMaxCols = 256;   // coupling columns of the tree
-constexpr int kPanelMaxX = 128;      // X rows of a (team, leaf) pair
-constexpr int kPanelMaxLevelTiles = 24;   // 16-row tiles of S^{-1} in one level (2 per wavefront)
+constexpr int kPanelMaxX = 128;      // X rows of a leaf
+constexpr int kPanelYChain = 14;     // most k-steps (of 4 columns) of one y task
+constexpr int kPanelYTasksPerWave = 2;
+constexpr int kPanelWaves = 8;       // wavefronts of a panel workgroup
 struct PanelDev {
-    int T, H, NL, NLp, NX, NB, NE, NI, NS, XZ, ZO, CZ, nc, sent, max_lw, n_teams, team0;
+    int T, H, NL, NLp, NX, NB, NE, NI, NS, XZ, ZO, nc, ncp, n_teams, team0;
+    int NY;              // y slots of a workgroup (multiple of 16), most over the leaves
+    int NT;              // y tasks of a workgroup, most over the leaves
+    int MF;              // M fragment entries of a workgroup (multiple of 64), most over the leaves
+    int NP;              // published (row, column) pairs of a leaf, most over the leaves
+    int ysep;            // 1: the y tasks' results have an LDS region of their own (else they overwrite u)
+    int teams_per_launch;    // teams co-resident in one cooperative launch
+    unsigned int epoch0;     // barrier epochs of earlier launches (flags are never reset between launches)
     // per leaf l
     const int* w_lo;
     const int* w_nl;
     const int* w_nb;
+    const int* w_nx;
+    const int* w_ny;     // [T] slots in use (padded)
+    const int* w_nt;     // [T] y tasks
     const int* ozo;      // [T*H] offset of the own rows' Z values at level h in the zown region, -1: none
     const int* opm;
-    const int* opc;
+    const int* ops;      // [T*H] slot of the level-h panel's first column
     const int* opan;
-    const int* orp;      // [T*(NL+1)] own CSR rows of G, combined column indices (fixed X rows)
+    const int* orp;      // [T*(NL+1)] own CSR rows of G, combined column indices
     const int* ocol;     // [T*NE]
     const double* oval;
     const int* bglob;    // [T*NB] incident branches: global id, endpoints (combined), owner flag
@@ -313,24 +335,36 @@ struct PanelDev {
     const int* sptr;     // [T*(NL+1)] sources of each own row
     const double* samp;  // [T*NS]
     const double* sph;
-    // per (team, leaf) pair tw = team*T + l
-    const int* w_nx;     // [n_teams*T]
-    const int* xrow;     // [n_teams*T*NX] new-order row of each X row
-    const int* xzo;      // [n_teams*T*NX*H] offset of the row's Z values at level h in the xz region, -1: none
+    const int* w_np;     // [T] published (own row, column) pairs
+    const int* pubr;     // [T*NP] own row of each pair
+    const int* pubg;     // [T*NP] coupling column of each pair
+    const int* xrow;     // [T*NX] new-order row of each X row
+    const int* xcol;     // [T*NX] a coupling column whose row is the X row (its exchange index)
+    const int* xzo;      // [T*NX*H] offset of the X row's Z values at level h in the xz region, -1: none
     const int* xpm;
-    const int* xpc;
+    const int* xps;      // [T*NX*H] slot of the panel's first column
     const int* xpan;
-    const int* lpa;      // [n_teams*T*kPanelCases*R] combined index of each change's endpoints (-1: ground/unused)
+    const int* yslot;    // [T*NY] coupling column of each slot, -1: padding
+    const int* tk0;      // [T*NT] y task: first absolute k-step, k-steps, fragment offset, tile
+    const int* tnk;
+    const int* tfo;
+    const int* ttile;
+    const int* ttp;      // [T*(NY/16+1)] tasks of tile t: ttl[ttp[t] .. ttp[t+1]) in k order
+    const int* ttl;      // [T*NT]
+    const int* wtask;    // [T*kPanelWaves*kPanelYTasksPerWave] tasks of each wavefront, -1: none
+    const double* mfr;   // [T*MF] M as A fragments of the y tasks (FP64)
+    const float* mfr32;  // [T*MF] FP32 copy
+    // per (team, leaf) pair tw = team*T + l
+    const int* lpa;      // [n_teams*T*kPanelCases*R] combined index of each change's endpoints (-1: not a row here)
     const int* lpb;
-    // coupling columns (the same for every workgroup)
-    const int* csop;     // [nc] LDS offset of the column's node S^{-1} (row stride m+1) + column index in node
-    const int* czo;      // [nc*H] offset of the column row's Z values at level h < level(column) in the cz region
-    const int* cpm;
-    const int* cpc;
-    const int* cpan;
+    // coupling map (device build of M)
+    const int* cpan;     // [nc*H] panel of the column's row at each lower level, -1: none
+    double* am;          // [nc*nc] scratch of the map build
+    double* bm;          // [nc*nc] M (y = M u)
     unsigned int* sync;  // [n_teams*T] barrier epoch flags
-    double* X0;          // [n_teams][2][n][kPanelCases] exchange of leaf products (double-buffered)
-    double* VM;          // [n_teams][2][T][kPanelCases] each workgroup's max |v| per case (same buffering)
+    double* X0;          // [n_teams][2][nc][kPanelCases] exchange of leaf products at the column rows
+    double* SP;          // [n_teams][2][T][R][kPanelCases] each workgroup's share of w^T v0 = u^T x per change
+    double* VM;          // [n_teams][2][T][kPanelCases] each workgroup's max |v| per case
 };
 
 // Level stepping (k_level.hip): one case, one workgroup per leaf, for trees whose coupling
@@ -459,11 +493,19 @@ void launch_set_rec(RecParams* d, const RecParams& val, hipStream_t s);
 // Team stepping (k_team.hip): LDS bytes of the layout, and the launch.
 size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec);
 hipError_t launch_team_acoef(const TeamDev& T, const HierDev& H, hipStream_t s);
+// y of every coupling column as a map of u (y = bm u; am: scratch), bottom-up over the levels from the
+// FP64 Z panels, S^{-1} and column weights (cpan: [nc*Hn] panel of the column's row at each lower level).
+hipError_t launch_coupling_map(const HierDev& H, int Hn, int nc, const int* cpan, double* am, double* bm,
+                               hipStream_t s);
 hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                            int prec, hipStream_t s);
 // Panel stepping (k_panel.hip): LDS bytes of the layout, and the launch (all
 // teams, in as many consecutive cooperative launches as residency requires).
 size_t panel_lds_bytes(const PanelDev& D, int R, int prec);
+// Launch set-up of the panel kernel for this layout (dynamic LDS limit, teams per cooperative launch).
+hipError_t panel_setup(PanelDev& D, int R, int prec, int warm);
+// M as the y tasks' A fragments (D.mfr, D.mfr32) from D.bm; after launch_coupling_map.
+hipError_t launch_panel_mfrag(const PanelDev& D, hipStream_t s);
 hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
 // Level stepping (k_level.hip): LDS bytes of the layout, and the launch.

@@ -7,34 +7,41 @@
 //
 // Per apply, in every workgroup of a team:
 //   1. own rows: V0 = B_l^{-1} X for the whole panel as one matrix product on
-//      the matrix cores (16x16x4 MFMA; the leaf block B_l^{-1} stays in
-//      registers as A fragments for the whole launch), published in the
-//      team's exchange buffer (double-buffered by apply parity);
+//      the matrix cores (16x16x4 MFMA; the leaf block stays in registers as A
+//      fragments for the whole launch).  The values at the leaf's coupling-
+//      column rows are published in the team's exchange (indexed by column,
+//      double-buffered by apply parity), and so is the workgroup's share of
+//      each case's w^T V0 = u^T X (u = G0^{-1} w, G0 symmetric) over its rows;
 //   2. one team barrier;
-//   3. the values at the coupling-column rows and at the X rows are read from
-//      the exchange; every level's Y = S^{-1} U^T V is computed in every
-//      workgroup, bottom-up, a column row's lower-level corrections applied
-//      inline; own rows and X rows are corrected once at the end, then each
-//      case's SMW correction follows.
-// A row shared by two workgroups gets identical operations in both (one dot
-// helper, the same operand order), so the history of a tie line, kept by the
-// workgroups of both endpoints, stays bitwise consistent without a second
-// exchange.
+//   3. u, the leaf-apply values at every column row, is read from the
+//      exchange; the y of every column the workgroup applies is y = M u (M:
+//      the coupling levels folded into one map) on the matrix cores; own rows
+//      and X rows subtract their Z rows times y; then each case's SMW
+//      correction with its w^T V0 summed over the team in workgroup order.
+// Rows shared by two workgroups (a line between leaves) get identical
+// operations in both: every y is formed by the same k-step groups wherever it
+// is computed, and own rows and X rows use one dot-product order, so the
+// history of a tie line, kept by the workgroups of both endpoints, stays
+// bitwise consistent without a second exchange.
 #include "hinv_internal.h"
 #include "team_sync.h"
 
 namespace hinv {
 
-constexpr int kPThreads = 768;                 // 12 wavefronts: 3 per SIMD, ~168 VGPRs each
+constexpr int kPThreads = 512;                 // 8 wavefronts: 2 per SIMD, up to 256 VGPRs each
 constexpr int kPWaves = kPThreads / 64;
 constexpr int kPB = kPanelCases;
 constexpr int kPRowItems = (kPanelMaxLeaf * kPanelCases + kPThreads - 1) / kPThreads;   // (row, case) items
-constexpr int kPColItems = (kPanelMaxCols * kPanelCases + kPThreads - 1) / kPThreads;   // (column, case) items
+constexpr int kPUItems = (kPanelMaxCols * kPanelCases + kPThreads - 1) / kPThreads;     // (column, case) items
 constexpr int kPXItems = (kPanelMaxX * kPanelCases + kPThreads - 1) / kPThreads;        // (X row, case) items
-constexpr int kPMaxFrag = 12;     // A fragments per wavefront (leaf <= 96 rows, see panel_gemm)
-constexpr int kPLevelTiles = 2;   // 16-row tiles of the level solve per wavefront
+constexpr int kPMaxFrag = 18;     // A fragments per wavefront (leaf <= 96 rows, see panel_gemm)
+constexpr int kPHelpTiles = 3;    // row tiles of each helper wavefront
+constexpr int kPHelpK = 6;        // k-steps of a tile's tail
+constexpr int kPYT = kPanelYTasksPerWave;
+constexpr int kPHItems = 6;       // (branch, case) items of a thread in the history update (<= 192 branches)
 static_assert(kPB == 16, "the panel is the N dimension of a 16x16x4 MFMA");
 static_assert(kPThreads % kPB == 0, "all items of a thread belong to one case");
+static_assert(kPWaves == kPanelWaves, "wavefront count shared with the host plan");
 
 template <typename TB>
 struct PAcc { using T = float; };
@@ -57,6 +64,9 @@ struct Mfma16<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+    // element and lane of D[r][c]
+    __device__ static __forceinline__ int elem(int r) { return r >> 2; }
+    __device__ static __forceinline__ int lane(int r, int c) { return ((r & 3) << 4) | c; }
 };
 template <>
 struct Mfma16<float> {
@@ -66,49 +76,76 @@ struct Mfma16<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     __device__ static __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+    __device__ static __forceinline__ int elem(int r) { return r & 3; }
+    __device__ static __forceinline__ int lane(int r, int c) { return ((r >> 2) << 4) | c; }
 };
 
 __device__ __forceinline__ double pfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float pfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// sum_j z[j*zs] * y[(pc+j)*kPB + c], accumulated in TA (one helper for own
-// rows, X rows and column rows keeps shared rows bitwise identical)
+// sum_j z[j*zs] * y[(ps+j)*kPB + c] over the slots ps .. ps+pm-1, accumulated in TA (one helper for
+// own rows and X rows keeps shared rows bitwise identical)
 template <typename TA, typename TB>
-__device__ __forceinline__ TA pdot(const TB* z, int zs, const double* y, int pc, int pm, int c)
+__device__ __forceinline__ TA pdot(const TB* z, int zs, const double* y, int ps, int pm, int c)
 {
     TA acc = 0;
-    for (int j = 0; j < pm; ++j) acc = pfma((TA)z[j * zs], (TA)y[(pc + j) * kPB + c], acc);
+    for (int j = 0; j < pm; ++j) acc = pfma((TA)z[j * zs], (TA)y[(ps + j) * kPB + c], acc);
     return acc;
 }
 
-// Split of the leaf product over the wavefronts: MT row tiles of 16, KS
-// k-steps of 4; KSPLIT wavefronts share a row tile (partial sums through LDS).
+// The same chain with the operands loaded eight at a time ahead of the multiply-adds (identical
+// arithmetic, so rows computed by pdot and by pdot_pf agree bitwise).
+template <typename TA, typename TB>
+__device__ __forceinline__ TA pdot_pf(const TB* z, int zs, const double* y, int ps, int pm, int c)
+{
+    TA acc = 0;
+    for (int j0 = 0; j0 < pm; j0 += 8) {
+        TA zz[8], yy[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int j = j0 + k < pm ? j0 + k : pm - 1;
+            zz[k] = (TA)z[j * zs];
+            yy[k] = (TA)y[(ps + j) * kPB + c];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (j0 + k < pm) acc = pfma(zz[k], yy[k], acc);
+    }
+    return acc;
+}
+
+// Split of the leaf product (MT row tiles of 16, KS k-steps of 4): wavefront t < MT takes the first KM
+// k-steps of tile t; the last KT = KS - KM k-steps of every tile go to the helper wavefronts 6 and 7
+// (tile t to helper t % 2), whose results meet the main ones through LDS.  With MT = 6 every SIMD
+// (wavefronts w and w + 4) issues the same number of products.
 struct PanelGemm {
-    int MT, KS, KSPLIT, KSC;
+    int MT, KS, KM, KT;
 };
 __host__ __device__ inline PanelGemm panel_gemm(int NLp)
 {
     PanelGemm g;
     g.MT = NLp / 16;
     g.KS = NLp / 4;
-    const int a = kPWaves / g.MT, b = 1 + 8 / g.MT;
-    g.KSPLIT = a < b ? a : b;
-    g.KSC = (g.KS + g.KSPLIT - 1) / g.KSPLIT;
+    const int h = (g.MT + 1) / 2;                    // tiles per helper
+    g.KM = (g.KS * h + h) / (h + 1);                 // ceil(KS h / (h + 1))
+    g.KT = g.KS - g.KM;
     return g;
 }
+static_assert(kPWaves == 8, "six main and two helper wavefronts");
 
 struct PanelLayout {
-    size_t sall, zown, xz, cz, uo, ux;
-    size_t b, v, td, xv, xd, y, h, gC, colw, oval, bg, bal, samp, sph, sn, cinv, mdg, tz, red;
-    size_t xrow, xzo, xpm, xpc, ozo, opm, opc, czo, cpm, cpc, crow, cm, cc0, cso, lvlc, orp, ocol, bglob, bf, bt, iptr,
-        ibr, sptr, prow, lpa, lpb, mact, lbr, lst, cnt, nlost, ract, vg, ctl;
+    size_t mfr, zown, xz, uo, ux;
+    size_t b, v, td, xv, xd, U, yres, y, h, gC, oval, bg, bal, samp, sph, sn, cinv, mdg, tz, red, red2, red3;
+    size_t xcol, xzo, xpm, xps, ozo, opm, ops, orp, ocol, iptr, ibr, sptr, prow, pubr, pubg, tk0, tnk, tfo, ttp,
+        wtask, lpa, lpb, mact, cnt, ract, vg, ctl;
     size_t total;
 };
 
 // LDS layout.  FP64 (one apply per step) keeps b and v in one buffer: the
 // leaf product overwrites b with v, and the right-hand side of the next step
-// overwrites v row by row.  The y region also holds, in turn, the leaf
-// product's partial sums, the raw values at the coupling-column rows and s.
+// overwrites v row by row.  The U region holds, in turn, the leaf product's
+// partial sums, u (the exchanged values at the column rows) and the y
+// tasks' results.
 template <typename TB, bool MIXED>
 __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
 {
@@ -119,15 +156,15 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
         o = (o + bytes + 15) & ~(size_t)15;
         return r;
     };
-    const size_t NL = D.NL, NLp = D.NLp, NX = D.NX, NB = D.NB, nc = D.nc, H = D.H, B = kPB;
+    const size_t NL = D.NL, NLp = D.NLp, NX = D.NX, NB = D.NB, H = D.H, B = kPB;
     const PanelGemm g = panel_gemm(D.NLp);
-    const size_t part = (size_t)(g.KSPLIT - 1) * g.MT * 256;
-    const size_t yn = nc * B > part ? nc * B : part;
+    size_t un = (size_t)D.ncp * B;
+    if ((size_t)D.NT * 256 > un) un = (size_t)D.NT * 256;
+    if ((size_t)g.MT * 256 > un) un = (size_t)g.MT * 256;
     const size_t S = sizeof(TB), F = sizeof(double), I = sizeof(int);
-    L.sall = take(S * D.sent);
+    L.mfr = take(S * D.MF);
     L.zown = take(S * D.ZO);
     L.xz = take(S * D.XZ);
-    L.cz = take(S * D.CZ);
     L.uo = take(S * R * NLp * B);
     L.ux = take(S * R * NX * B);
     L.b = take(F * NLp * B);
@@ -135,51 +172,48 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
     L.td = take(MIXED ? F * NLp * B : 0);
     L.xv = take(F * NX * B);
     L.xd = take(MIXED ? F * NX * B : 0);
-    L.y = take(F * yn);
+    L.U = take(F * un);
+    L.yres = D.ysep ? take(F * D.NT * 256) : L.U;   // y task results (in the U region when LDS is short)
+    L.y = take(F * D.NY * B);
     L.h = take(F * NB * B);
     L.gC = take(F * NL);
-    L.colw = take(F * nc);
     L.oval = take(MIXED ? F * D.NE : 0);
     L.bg = take(F * NB);
     L.bal = take(F * NB);
     L.samp = take(F * D.NS);
     L.sph = take(F * D.NS);
-    L.sn = take(F * D.NS);
-    L.cinv = take(F * B * R * R * R);
+    L.sn = take(F * NL);          // source injection of each own row at the next step
+    L.cinv = take(F * B * (R * (R + 1) * (2 * R + 1) / 6));   // per case the r x r inverses, r = 1..R, packed
     L.mdg = take(F * B * R);
     L.tz = take(F * B * 2 * R);
     L.red = take(MIXED ? F * 2 * kPWaves * B : 0);
-    L.xrow = take(I * NX);
+    // red2 (shares per wavefront, before the barrier) and red3 (the team's shares, after it) share one region
+    L.red2 = take(F * (kPWaves > D.T ? kPWaves : D.T) * R * B);
+    L.red3 = L.red2;
+    L.xcol = take(I * NX);
     L.xzo = take(I * NX * H);
     L.xpm = take(I * NX * H);
-    L.xpc = take(I * NX * H);
+    L.xps = take(I * NX * H);
     L.ozo = take(I * H);
     L.opm = take(I * H);
-    L.opc = take(I * H);
-    L.czo = take(I * nc * H);
-    L.cpm = take(I * nc * H);
-    L.cpc = take(I * nc * H);
-    L.crow = take(I * nc);
-    L.cm = take(I * nc);
-    L.cc0 = take(I * nc);
-    L.cso = take(I * nc);
-    L.lvlc = take(I * (H + 1));
+    L.ops = take(I * H);
     L.orp = take(I * (NL + 1));
     L.ocol = take(MIXED ? I * D.NE : 0);
-    L.bglob = take(I * NB);
-    L.bf = take(I * NB);
-    L.bt = take(I * NB);
     L.iptr = take(I * (NL + 1));
     L.ibr = take(I * D.NI);
     L.sptr = take(I * (NL + 1));
     L.prow = take(I * NL);
+    L.pubr = take(I * D.NP);
+    L.pubg = take(I * D.NP);
+    L.tk0 = take(I * D.NT);
+    L.tnk = take(I * D.NT);
+    L.tfo = take(I * D.NT);
+    L.ttp = take(I * (D.NY / 16 + 1));
+    L.wtask = take(I * kPWaves * kPYT);
     L.lpa = take(I * B * R);
     L.lpb = take(I * B * R);
     L.mact = take(I * B * R);
-    L.lbr = take(I * B * R);
-    L.lst = take(I * B * R);
     L.cnt = take(I * B);
-    L.nlost = take(I * B);
     L.ract = take(I * B);
     L.vg = take(sizeof(unsigned long long) * B);
     L.ctl = take(I * 8);
@@ -205,12 +239,12 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     const int nvc = K - case0 < kPB ? K - case0 : kPB;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wavefront
-    const int lo = D.w_lo[l], nl = D.w_nl[l], nb = D.w_nb[l], nx = D.w_nx[tw];
-    const int NLp = D.NLp;
-    TB* sall = (TB*)(L8 + Ly.sall);
+    const int lo = D.w_lo[l], nl = D.w_nl[l], nb = D.w_nb[l], nx = D.w_nx[l], ny = D.w_ny[l], nt = D.w_nt[l];
+    const int npub = D.w_np[l];
+    const int NLp = D.NLp, NX = D.NX, ncp = D.ncp;
+    TB* mfr = (TB*)(L8 + Ly.mfr);
     TB* zown = (TB*)(L8 + Ly.zown);
     TB* xz = (TB*)(L8 + Ly.xz);
-    TB* cz = (TB*)(L8 + Ly.cz);
     TB* uo = (TB*)(L8 + Ly.uo);
     TB* ux = (TB*)(L8 + Ly.ux);
     double* b = (double*)(L8 + Ly.b);
@@ -218,10 +252,11 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     double* td = (double*)(L8 + Ly.td);
     double* xv = (double*)(L8 + Ly.xv);
     double* xd = (double*)(L8 + Ly.xd);
+    double* U = (double*)(L8 + Ly.U);
+    double* yres = (double*)(L8 + Ly.yres);
     double* y = (double*)(L8 + Ly.y);
     double* h = (double*)(L8 + Ly.h);
     double* gC = (double*)(L8 + Ly.gC);
-    double* colw = (double*)(L8 + Ly.colw);
     double* oval = (double*)(L8 + Ly.oval);
     double* bg = (double*)(L8 + Ly.bg);
     double* bal = (double*)(L8 + Ly.bal);
@@ -232,82 +267,63 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     double* mdg = (double*)(L8 + Ly.mdg);
     double* tz = (double*)(L8 + Ly.tz);
     double* red = (double*)(L8 + Ly.red);
-    int* xrow = (int*)(L8 + Ly.xrow);
+    double* red2 = (double*)(L8 + Ly.red2);
+    int* xcol = (int*)(L8 + Ly.xcol);
     int* xzo = (int*)(L8 + Ly.xzo);
     int* xpm = (int*)(L8 + Ly.xpm);
-    int* xpc = (int*)(L8 + Ly.xpc);
+    int* xps = (int*)(L8 + Ly.xps);
     int* ozo = (int*)(L8 + Ly.ozo);
     int* opm = (int*)(L8 + Ly.opm);
-    int* opc = (int*)(L8 + Ly.opc);
-    int* czo = (int*)(L8 + Ly.czo);
-    int* cpm = (int*)(L8 + Ly.cpm);
-    int* cpc = (int*)(L8 + Ly.cpc);
-    int* crow = (int*)(L8 + Ly.crow);
-    int* cm = (int*)(L8 + Ly.cm);
-    int* cc0 = (int*)(L8 + Ly.cc0);
-    int* cso = (int*)(L8 + Ly.cso);
-    int* lvlc = (int*)(L8 + Ly.lvlc);
+    int* ops = (int*)(L8 + Ly.ops);
     int* orp = (int*)(L8 + Ly.orp);
     int* ocol = (int*)(L8 + Ly.ocol);
-    int* bglob = (int*)(L8 + Ly.bglob);
-    int* bf = (int*)(L8 + Ly.bf);
-    int* bt = (int*)(L8 + Ly.bt);
     int* iptr = (int*)(L8 + Ly.iptr);
     int* ibr = (int*)(L8 + Ly.ibr);
     int* sptr = (int*)(L8 + Ly.sptr);
     int* prow = (int*)(L8 + Ly.prow);
+    int* pubr = (int*)(L8 + Ly.pubr);
+    int* pubg = (int*)(L8 + Ly.pubg);
+    double* red3 = (double*)(L8 + Ly.red3);
+    int* tk0 = (int*)(L8 + Ly.tk0);
+    int* tnk = (int*)(L8 + Ly.tnk);
+    int* tfo = (int*)(L8 + Ly.tfo);
+    int* ttp = (int*)(L8 + Ly.ttp);
+    int* wtask = (int*)(L8 + Ly.wtask);
     int* lpa = (int*)(L8 + Ly.lpa);
     int* lpb = (int*)(L8 + Ly.lpb);
     int* mact = (int*)(L8 + Ly.mact);
-    int* lbr = (int*)(L8 + Ly.lbr);
-    int* lst = (int*)(L8 + Ly.lst);
     int* cnt = (int*)(L8 + Ly.cnt);
-    int* nlost = (int*)(L8 + Ly.nlost);
     int* ract = (int*)(L8 + Ly.ract);
     unsigned long long* vg = (unsigned long long*)(L8 + Ly.vg);
     int* ctl = (int*)(L8 + Ly.ctl);
 
     const TB* gblk;
-    const TB* gS;
     const TB* gZ;
     const TB* gU;
+    const TB* gM;
     if constexpr (sizeof(TB) == 8) {
-        gblk = (const TB*)H.blk; gS = (const TB*)H.Sinv; gZ = (const TB*)H.Z; gU = (const TB*)M.U;
+        gblk = (const TB*)H.blk; gZ = (const TB*)H.Z; gU = (const TB*)M.U; gM = (const TB*)D.mfr;
     } else {
-        gblk = (const TB*)H.blk32; gS = (const TB*)H.Sinv32; gZ = (const TB*)H.Z32; gU = (const TB*)M.U32;
+        gblk = (const TB*)H.blk32; gZ = (const TB*)H.Z32; gU = (const TB*)M.U32; gM = (const TB*)D.mfr32;
     }
     // ---------------- tables and state into LDS
-    for (int g = tid; g < nc; g += kPThreads) {          // S^{-1} rows padded to m+1
-        const int node = H.col_node[g];
-        const int m = H.node_m[node], q = g - H.node_col0[node];
-        const TB* src = gS + H.node_soff[node] + q;
-        TB* dst = sall + D.csop[g];
-        for (int p = 0; p < m; ++p) dst[p * (m + 1)] = src[(int64_t)p * m];
-        crow[g] = H.col_row[g];
-        cm[g] = m;
-        cc0[g] = H.node_col0[node];
-        cso[g] = D.csop[g];
-        colw[g] = H.col_w[g];
+    for (int i = tid; i < D.MF; i += kPThreads) mfr[i] = gM[(int64_t)l * D.MF + i];
+    for (int t = tid; t < nt; t += kPThreads) {
+        const int64_t gi = (int64_t)l * D.NT + t;
+        tk0[t] = D.tk0[gi];
+        tnk[t] = D.tnk[gi];
+        tfo[t] = D.tfo[gi];
     }
-    for (int i = tid; i < nc * Hn; i += kPThreads) {     // column rows: Z values below the column's level
-        const int zo = D.czo[i];
-        czo[i] = zo;
-        cpm[i] = D.cpm[i];
-        cpc[i] = D.cpc[i];
-        if (zo >= 0) {
-            const int pan = D.cpan[i];
-            const TB* zp = gZ + H.pan_zoff[pan] + (H.col_row[i / Hn] - H.pan_lo[pan]);
-            for (int j = 0; j < D.cpm[i]; ++j) cz[zo + j] = zp[(int64_t)j * H.pan_n[pan]];
-        }
-    }
-    const int64_t xb = (int64_t)tw * D.NX;
-    for (int x = tid; x < nx; x += kPThreads) xrow[x] = D.xrow[xb + x];
+    for (int t = tid; t <= ny / 16; t += kPThreads) ttp[t] = D.ttp[(int64_t)l * (D.NY / 16 + 1) + t];
+    for (int i = tid; i < kPWaves * kPYT; i += kPThreads) wtask[i] = D.wtask[(int64_t)l * kPWaves * kPYT + i];
+    const int64_t xb = (int64_t)l * NX;
+    for (int x = tid; x < nx; x += kPThreads) xcol[x] = D.xcol[xb + x];
     for (int i = tid; i < nx * Hn; i += kPThreads) {     // X rows: Z values at every level
         const int64_t gi = xb * Hn + i;
         const int zo = D.xzo[gi];
         xzo[i] = zo;
         xpm[i] = D.xpm[gi];
-        xpc[i] = D.xpc[gi];
+        xps[i] = D.xps[gi];
         if (zo >= 0) {
             const int pan = D.xpan[gi];
             const TB* zp = gZ + H.pan_zoff[pan] + (D.xrow[xb + i / Hn] - H.pan_lo[pan]);
@@ -316,7 +332,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     }
     for (int hh = 0; hh < Hn; ++hh) {                    // own rows: Z panel rows at every level
         const int zo = D.ozo[l * Hn + hh];
-        if (tid == 0) { ozo[hh] = zo; opm[hh] = D.opm[l * Hn + hh]; opc[hh] = D.opc[l * Hn + hh]; }
+        if (tid == 0) { ozo[hh] = zo; opm[hh] = D.opm[l * Hn + hh]; ops[hh] = D.ops[l * Hn + hh]; }
         if (zo >= 0) {
             const int pan = D.opan[l * Hn + hh], pm = D.opm[l * Hn + hh];
             const TB* zp = gZ + H.pan_zoff[pan] + (lo - H.pan_lo[pan]);
@@ -326,7 +342,6 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             }
         }
     }
-    for (int hh = tid; hh <= Hn; hh += kPThreads) lvlc[hh] = H.lvl_col[hh];
     {
         const int64_t rb = (int64_t)l * (D.NL + 1);
         for (int r = tid; r <= nl; r += kPThreads) {
@@ -334,13 +349,21 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             iptr[r] = D.iptr[rb + r];
             sptr[r] = D.sptr[rb + r];
         }
+        for (int q = tid; q < npub; q += kPThreads) {
+            pubr[q] = D.pubr[(int64_t)l * D.NP + q];
+            pubg[q] = D.pubg[(int64_t)l * D.NP + q];
+        }
         if (MIXED) {
             for (int e = tid; e < D.orp[rb + nl]; e += kPThreads) {
                 ocol[e] = D.ocol[(int64_t)l * D.NE + e];
                 oval[e] = D.oval[(int64_t)l * D.NE + e];
             }
         }
-        for (int i = tid; i < D.iptr[rb + nl]; i += kPThreads) ibr[i] = D.ibr[(int64_t)l * D.NI + i];
+        for (int r = tid; r < nl; r += kPThreads)        // incident branches: ~lb where the row is the to-bus
+            for (int q = D.iptr[rb + r]; q < D.iptr[rb + r + 1]; ++q) {
+                const int lb = D.ibr[(int64_t)l * D.NI + q];
+                ibr[q] = D.bf[(int64_t)l * D.NB + lb] == r ? lb : ~lb;
+            }
         for (int i = tid; i < D.sptr[rb + nl]; i += kPThreads) {
             samp[i] = D.samp[(int64_t)l * D.NS + i];
             sph[i] = D.sph[(int64_t)l * D.NS + i];
@@ -348,9 +371,6 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     }
     for (int q = tid; q < nb; q += kPThreads) {
         const int64_t gq = (int64_t)l * D.NB + q;
-        bglob[q] = D.bglob[gq];
-        bf[q] = D.bf[gq];
-        bt[q] = D.bt[gq];
         bg[q] = D.bg[gq];
         bal[q] = D.bal[gq];
     }
@@ -381,18 +401,16 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         const int c = tid, k = case0 + c;
         const bool ok = c < nvc;
         cnt[c] = ok ? M.count[k] : 0;
-        nlost[c] = ok ? E.loss_cnt[k] : 0;
         for (int j = 0; j < R; ++j) {
             mact[c * R + j] = ok ? M.act[k * R + j] : 0x7fffffff;
             mdg[c * R + j] = ok ? M.dg[k * R + j] : 0.0;
-            lbr[c * R + j] = ok ? E.loss_br[k * R + j] : -1;
-            lst[c * R + j] = ok ? E.loss_step[k * R + j] : 0x7fffffff;
             lpa[c * R + j] = D.lpa[((int64_t)tw * kPB + c) * R + j];
             lpb[c * R + j] = D.lpb[((int64_t)tw * kPB + c) * R + j];
-            if (ok && j < M.count[k] && (lpa[c * R + j] < 0 || (M.b[k * R + j] >= 0 && lpb[c * R + j] < 0)))
-                atomicOr(P.flags, kFlagTeamRow);
         }
-        for (int i = 0; i < R * R * R; ++i) cinv[c * R * R * R + i] = ok ? M.Cinv[(int64_t)k * R * R * R + i] : 0.0;
+        const int cs = R * (R + 1) * (2 * R + 1) / 6;
+        for (int r = 1, o = 0; r <= R; o += r * r, ++r)
+            for (int i = 0; i < r * r; ++i)
+                cinv[c * cs + o + i] = ok ? M.Cinv[((int64_t)k * R + (r - 1)) * R * R + (i / r) * R + i % r] : 0.0;
     }
     // SMW vectors u_j of each case at own rows ([j][r][c]) and X rows ([j][x][c])
     for (int i = tid; i < R * NLp * kPB; i += kPThreads) {
@@ -401,11 +419,39 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         if (r < nl && c < nvc && j < M.count[case0 + c]) u = gU[((int64_t)(case0 + c) * R + j) * n + lo + r];
         uo[i] = u;
     }
-    for (int i = tid; i < R * D.NX * kPB; i += kPThreads) {
-        const int j = i / (D.NX * kPB), xc = i - j * D.NX * kPB, x = xc >> 4, c = xc & 15;
+    for (int i = tid; i < R * NX * kPB; i += kPThreads) {
+        const int j = i / (NX * kPB), xc = i - j * NX * kPB, x = xc >> 4, c = xc & 15;
         TB u = 0;
         if (x < nx && c < nvc && j < M.count[case0 + c]) u = gU[((int64_t)(case0 + c) * R + j) * n + D.xrow[xb + x]];
         ux[i] = u;
+    }
+    // the thread's (branch, case) items of the history update: endpoints (combined, packed) and the first
+    // step from which the branch is lost for the case, in registers
+    int hbft[kPHItems], hlost[kPHItems];
+#pragma unroll
+    for (int k = 0; k < kPHItems; ++k) {
+        const int i = tid + k * kPThreads, q = i >> 4, c = i & 15;
+        hbft[k] = 0;
+        hlost[k] = 0x7fffffff;
+        if (q < nb) {
+            const int64_t gq = (int64_t)l * D.NB + q;
+            hbft[k] = D.bf[gq] | (D.bt[gq] << 16);
+            if (c < nvc)
+                for (int j = 0; j < E.loss_cnt[case0 + c]; ++j)
+                    if (E.loss_br[(case0 + c) * R + j] == D.bglob[gq])
+                        hlost[k] = min(hlost[k], E.loss_step[(case0 + c) * R + j]);
+        }
+    }
+    // the thread's own-row items of the right-hand side: range of incident branches (first | count << 16)
+    int rinc[kPRowItems];
+#pragma unroll
+    for (int k = 0; k < kPRowItems; ++k) {
+        const int r = (tid + k * kPThreads) >> 4;
+        rinc[k] = 0;
+        if (r < nl) {
+            const int64_t rb = (int64_t)l * (D.NL + 1);
+            rinc[k] = D.iptr[rb + r] | ((D.iptr[rb + r + 1] - D.iptr[rb + r]) << 16);
+        }
     }
     // capacitor histories of the thread's (row, case) items, in registers
     double hcr[kPRowItems];
@@ -416,35 +462,36 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     }
     // leaf block as A fragments (zero outside the leaf)
     const PanelGemm gm = panel_gemm(NLp);
-    const bool gwave = wave < gm.MT * gm.KSPLIT;
-    const int mt = wave % gm.MT, kp = wave / gm.MT;
-    const int ks0 = kp * gm.KSC;
-    int nks = 0;
-    if (gwave) {
-        const int e = ks0 + gm.KSC < gm.KS ? ks0 + gm.KSC : gm.KS;
-        nks = e > ks0 ? e - ks0 : 0;
-    }
-    TB afrag[kPMaxFrag];
+    const bool mainw = wave < gm.MT, helper = wave >= 6;
+    TB afrag[kPMaxFrag];          // zero outside the leaf and past the wavefront's k-steps
     {
         const TB* src = gblk + H.leaf_off[l];
-        const int row = mt * 16 + (lane & 15);
 #pragma unroll
         for (int f = 0; f < kPMaxFrag; ++f) {
+            int t, ks;
+            bool ok;
+            if (helper) {
+                t = (wave - 6) + 2 * (f / kPHelpK);
+                ks = gm.KM + f % kPHelpK;
+                ok = t < gm.MT && f % kPHelpK < gm.KT;
+            } else {
+                t = wave;
+                ks = f;
+                ok = mainw && f < gm.KM;
+            }
+            const int row = t * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
             TB a = 0;
-            const int col = (ks0 + f) * 4 + (lane >> 4);
-            if (f < nks && row < nl && col < nl) a = src[(int64_t)col * nl + row];
+            if (ok && row < nl && col < nl) a = src[(int64_t)col * nl + row];
             afrag[f] = a;
         }
     }
     __syncthreads();
 
     int par = 0;
-    unsigned int epoch = 0;
+    unsigned int epoch = D.epoch0;
     bool alive = true;
     double worst = 0.0;
     unsigned int* tflags = D.sync + (int64_t)team * T;
-    const int NXs = D.NX;
-    const int ns = sptr[nl];
     int64_t sn_step = -1;    // the step whose source injections the next apply computes (-1: none)
 
     // value of a combined row index (own row or X row) in the pair (own, X)
@@ -456,41 +503,95 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     // out (own rows), outx (X rows) from xin (own rows, zero beyond nl); out
     // may be xin (it is written after every wavefront has read xin)
     auto apply = [&](const double* xin, double* out, double* outx, bool anyact, bool want_vm) -> bool {
-        double* X0p = D.X0 + ((int64_t)team * 2 + par) * (int64_t)n * kPB;
+        double* X0p = D.X0 + ((int64_t)team * 2 + par) * (int64_t)nc * kPB;
+        double* SPp = D.SP + ((int64_t)team * 2 + par) * (int64_t)T * R * kPB;
         const double* VMp = D.VM + ((int64_t)team * 2 + par) * T * kPB;
-        {
-            typename Mfma16<TB>::V acc = {0, 0, 0, 0};
+        if (anyact) {   // this workgroup's share of u_j^T x per case (the thread's items all belong to case tid & 15)
+            double sj[kPanelMaxRank];
 #pragma unroll
-            for (int f = 0; f < kPMaxFrag; ++f) {
-                if (f < nks) {
-                    const int k = (ks0 + f) * 4 + (lane >> 4);
-                    acc = Mfma16<TB>::op(afrag[f], (TB)xin[k * kPB + (lane & 15)], acc);
-                }
+            for (int j = 0; j < kPanelMaxRank; ++j) sj[j] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kPRowItems; ++k) {
+                const int i = tid + k * kPThreads;
+                if (i < nl * kPB)
+#pragma unroll
+                    for (int j = 0; j < kPanelMaxRank; ++j)
+                        if (j < R) sj[j] = pfma((double)uo[j * NLp * kPB + i], xin[i], sj[j]);
             }
-            if (gwave && kp > 0) {
-                double* pp = y + ((kp - 1) * gm.MT + mt) * 256;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) pp[i * 64 + lane] = (double)acc[i];
+            for (int j = 0; j < kPanelMaxRank; ++j) {
+                sj[j] += __shfl_xor(sj[j], 16);
+                sj[j] += __shfl_xor(sj[j], 32);
+                if (j < R && lane < kPB) red2[(wave * R + j) * kPB + lane] = sj[j];
+            }
+        }
+        {
+            // rows past a wavefront's k-steps are clamped (their A fragments are zero)
+            typename Mfma16<TB>::V acc = {0, 0, 0, 0};
+            if (helper) {
+#pragma unroll
+                for (int i = 0; i < kPHelpTiles; ++i) {
+                    typename Mfma16<TB>::V ht = {0, 0, 0, 0};
+                    TB bop[kPHelpK];
+#pragma unroll
+                    for (int f = 0; f < kPHelpK; ++f) {
+                        const int k = (gm.KM + f) * 4 + (lane >> 4);
+                        bop[f] = (TB)xin[(k < NLp ? k : NLp - 1) * kPB + (lane & 15)];
+                    }
+#pragma unroll
+                    for (int f = 0; f < kPHelpK; ++f) ht = Mfma16<TB>::op(afrag[i * kPHelpK + f], bop[f], ht);
+                    const int t = (wave - 6) + 2 * i;
+                    if (t < gm.MT)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) U[t * 256 + e * 64 + lane] = (double)ht[e];
+                }
+            } else if (mainw) {
+#pragma unroll
+                for (int f0 = 0; f0 < kPMaxFrag; f0 += kPHelpK) {
+                    TB bop[kPHelpK];
+#pragma unroll
+                    for (int f = 0; f < kPHelpK; ++f) {
+                        const int k = (f0 + f) * 4 + (lane >> 4);
+                        bop[f] = (TB)xin[(k < NLp ? k : NLp - 1) * kPB + (lane & 15)];
+                    }
+#pragma unroll
+                    for (int f = 0; f < kPHelpK; ++f) acc = Mfma16<TB>::op(afrag[f0 + f], bop[f], acc);
+                }
             }
             __syncthreads();
-            if (gwave && kp == 0) {
+            if (mainw) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    double val = (double)acc[i];
-                    for (int q = 1; q < gm.KSPLIT; ++q) val += y[((q - 1) * gm.MT + mt) * 256 + i * 64 + lane];
-                    const int r = mt * 16 + Mfma16<TB>::row(lane, i), c = lane & 15;
-                    if (r < nl) {
-                        out[r * kPB + c] = val;
-                        xchg_store(&X0p[(int64_t)(lo + r) * kPB + c], val);
-                    }
+                    const double val = (double)acc[i] + U[wave * 256 + i * 64 + lane];
+                    const int r = wave * 16 + Mfma16<TB>::row(lane, i), c = lane & 15;
+                    if (r < nl) out[r * kPB + c] = val;
                 }
+            }
+            __syncthreads();
+            // publish the values at the leaf's coupling-column rows, and the share of u^T x
+            for (int i = tid; i < npub * kPB; i += kPThreads) {
+                const int q = i >> 4, c = i & 15;
+                xchg_store(&X0p[pubg[q] * kPB + c], out[pubr[q] * kPB + c]);
+            }
+            if (anyact && tid < R * kPB) {
+                const int j = tid >> 4, c = tid & 15;
+                double sw[kPWaves];
+#pragma unroll
+                for (int w = 0; w < kPWaves; ++w) sw[w] = red2[(w * R + j) * kPB + c];
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < kPWaves; ++w) s += sw[w];
+                xchg_store(&SPp[((int64_t)l * R + j) * kPB + c], s);
             }
         }
         team_arrive(tflags, l, ++epoch);
-        if (sn_step >= 0) {      // source injections of the next step, by the last wavefront, while wavefront 0 polls
+        if (sn_step >= 0) {      // source injections of the next step, by the last wave, while wavefront 0 polls
             if (tid >= kPThreads - 64)
-                for (int q = tid - (kPThreads - 64); q < ns; q += 64)
-                    sn[q] = samp[q] * sin(E.omega * ((double)sn_step * E.dt) + sph[q]);
+                for (int r = tid - (kPThreads - 64); r < nl; r += 64) {
+                    double sr = 0.0;
+                    for (int q = sptr[r]; q < sptr[r + 1]; ++q) sr += samp[q] * sin(E.omega * ((double)sn_step * E.dt) + sph[q]);
+                    sn[r] = sr;
+                }
             sn_step = -1;
         }
         if (!team_wait(tflags, T, epoch, P.flags, ctl)) return false;
@@ -499,99 +600,87 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 atomicMax(&vg[i & 15], (unsigned long long)__double_as_longlong(xchg_load(&VMp[i])));
         }
         {   // every load of the exchange is issued before the first wait
-            double xl[kPXItems], cl[kPColItems];
+            double ul[kPUItems], xl[kPXItems];
+#pragma unroll
+            for (int it = 0; it < kPUItems; ++it) {
+                const int i = tid + it * kPThreads;
+                ul[it] = i < nc * kPB ? xchg_load(&X0p[i]) : 0.0;
+            }
 #pragma unroll
             for (int it = 0; it < kPXItems; ++it) {
                 const int i = tid + it * kPThreads;
-                xl[it] = i < nx * kPB ? xchg_load(&X0p[(int64_t)xrow[i >> 4] * kPB + (i & 15)]) : 0.0;
+                xl[it] = i < nx * kPB ? xchg_load(&X0p[xcol[i >> 4] * kPB + (i & 15)]) : 0.0;
             }
+            const double spv = (anyact && tid < T * R * kPB) ? xchg_load(&SPp[tid]) : 0.0;   // the team's shares
+            if (anyact && tid < T * R * kPB) red3[tid] = spv;
 #pragma unroll
-            for (int it = 0; it < kPColItems; ++it) {
+            for (int it = 0; it < kPUItems; ++it) {
                 const int i = tid + it * kPThreads;
-                cl[it] = i < nc * kPB ? xchg_load(&X0p[(int64_t)crow[i >> 4] * kPB + (i & 15)]) : 0.0;
+                if (i < ncp * kPB) U[i] = ul[it];
             }
 #pragma unroll
             for (int it = 0; it < kPXItems; ++it) {
                 const int i = tid + it * kPThreads;
                 if (i < nx * kPB) outx[i] = xl[it];
             }
-#pragma unroll
-            for (int it = 0; it < kPColItems; ++it) {
-                const int i = tid + it * kPThreads;
-                if (i < nc * kPB) y[i] = cl[it];
-            }
         }
         __syncthreads();
-        // coupling levels bottom-up; a level's slots of y hold the raw values,
-        // then s = U^T v (lower-level corrections inline), then y = S^{-1} s
-        for (int hl = 1; hl <= Hn; ++hl) {
-            const int c0 = lvlc[hl - 1], c1 = lvlc[hl];
-            if (c1 == c0) continue;
-            for (int i = c0 * kPB + tid; i < c1 * kPB; i += kPThreads) {
-                const int g = i >> 4, c = i & 15;
-                double val = y[i];
-                for (int hh = 1; hh < hl; ++hh) {
-                    const int zo = czo[g * Hn + hh - 1];
-                    if (zo >= 0) val -= (double)pdot<TA>(cz + zo, 1, y, cpc[g * Hn + hh - 1], cpm[g * Hn + hh - 1], c);
+        if (anyact && tid < kPB) {   // w^T v0 of each active change (the shares in workgroup order), z = C^{-1} t
+            const int c = tid, ra = ract[c];
+            double t[kPanelMaxRank];
+#pragma unroll
+            for (int j = 0; j < kPanelMaxRank; ++j) {
+                t[j] = 0.0;
+                if (j < R)
+                    for (int q0 = 0; q0 < T; q0 += 8) {
+                        double v8[8];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) v8[k] = q0 + k < T ? red3[((q0 + k) * R + j) * kPB + c] : 0.0;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) t[j] += v8[k];
+                    }
+            }
+            if (ra > 0) {
+                const double* Ci = cinv + c * (R * (R + 1) * (2 * R + 1) / 6) + (ra - 1) * ra * (2 * ra - 1) / 6;
+                for (int j = 0; j < ra; ++j) {
+                    double z = 0.0;
+                    for (int q = 0; q < ra; ++q) z += Ci[j * ra + q] * t[q];
+                    tz[c * 2 * R + R + j] = z;
                 }
-                y[i] = colw[g] * val;
+            }
+        }
+        if (nc == 0) __syncthreads();        // z visible to the final update (no y phase in between)
+        if (nc > 0) {
+            // y = M u for the workgroup's slots: each task is one MFMA chain over an absolute group of
+            // k-steps of one 16-row tile; a tile's tasks are summed in k order
+            typename Mfma16<TB>::V yacc[kPYT];
+#pragma unroll
+            for (int k2 = 0; k2 < kPYT; ++k2) {
+                yacc[k2] = typename Mfma16<TB>::V{0, 0, 0, 0};
+                const int tk = __builtin_amdgcn_readfirstlane(wtask[wave * kPYT + k2]);
+                if (tk >= 0) {
+                    const int k0 = __builtin_amdgcn_readfirstlane(tk0[tk]);
+                    const int nk = __builtin_amdgcn_readfirstlane(tnk[tk]);
+                    const int fo = __builtin_amdgcn_readfirstlane(tfo[tk]);
+                    for (int kk = 0; kk < nk; ++kk)
+                        yacc[k2] = Mfma16<TB>::op(mfr[fo + kk * 64 + lane], (TB)U[(k0 + kk) * 64 + lane], yacc[k2]);
+                }
+            }
+            if (!D.ysep) __syncthreads();     // the results overwrite u: every task has read it
+#pragma unroll
+            for (int k2 = 0; k2 < kPYT; ++k2) {
+                const int tk = __builtin_amdgcn_readfirstlane(wtask[wave * kPYT + k2]);
+                if (tk >= 0)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) yres[tk * 256 + e * 64 + lane] = (double)yacc[k2][e];
             }
             __syncthreads();
-            // y = S^{-1} s on the matrix cores: every node's S^{-1} in 16-row tiles (zero beyond m)
-            // times the node's s for the 16 cases, k-steps of 4; wavefront w takes the level's
-            // tiles w and w + kPWaves (the host keeps a level at <= 2 * kPWaves tiles)
-            {
-                int tg[kPLevelTiles], tqt[kPLevelTiles];
-#pragma unroll
-                for (int k = 0; k < kPLevelTiles; ++k) tg[k] = -1;
-                {
-                    int tcount = 0;
-                    for (int g = c0; g < c1; g += cm[g]) {
-                        for (int qt = 0; qt * 16 < cm[g]; ++qt, ++tcount) {
-#pragma unroll
-                            for (int k = 0; k < kPLevelTiles; ++k)
-                                if (tcount == wave + k * kPWaves) { tg[k] = g; tqt[k] = qt; }
-                        }
-                    }
-                }
-                typename Mfma16<TB>::V yacc[kPLevelTiles];
-#pragma unroll
-                for (int k = 0; k < kPLevelTiles; ++k) {
-                    yacc[k] = typename Mfma16<TB>::V{0, 0, 0, 0};
-                    if (tg[k] >= 0) {
-                        const int g0 = __builtin_amdgcn_readfirstlane(tg[k]);
-                        const int m = __builtin_amdgcn_readfirstlane(cm[g0]);
-                        const TB* Si = sall + cso[g0];
-                        const int q = tqt[k] * 16 + (lane & 15), qc = q < m ? q : m - 1;
-                        // four k-steps per round: clamped loads first (zero outside the node's
-                        // m x m block), then four dependent matrix products
-                        for (int k0 = 0; k0 < m; k0 += 16) {
-                            TB a[4], bb[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int pp = k0 + u * 4 + (lane >> 4), pc = pp < m ? pp : m - 1;
-                                const TB a0 = Si[qc + pc * (m + 1)];
-                                const TB b0 = (TB)y[(g0 + pc) * kPB + (lane & 15)];
-                                a[u] = (q < m && pp < m) ? a0 : (TB)0;
-                                bb[u] = pp < m ? b0 : (TB)0;
-                            }
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) yacc[k] = Mfma16<TB>::op(a[u], bb[u], yacc[k]);
-                        }
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < kPLevelTiles; ++k) {
-                    if (tg[k] >= 0) {
-                        const int g0 = tg[k], m = cm[g0];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int q = tqt[k] * 16 + Mfma16<TB>::row(lane, e);
-                            if (q < m) y[(g0 + q) * kPB + (lane & 15)] = (double)yacc[k][e];
-                        }
-                    }
-                }
+            for (int i = tid; i < ny * kPB; i += kPThreads) {     // a tile's tasks are consecutive, in k order
+                const int s = i >> 4, c = i & 15, t = s >> 4, rr = s & 15;
+                const int e = Mfma16<TB>::elem(rr), ln = Mfma16<TB>::lane(rr, c);
+                double acc = 0.0;
+                for (int q = ttp[t]; q < ttp[t + 1]; ++q) acc += yres[q * 256 + e * 64 + ln];
+                y[i] = acc;
             }
             __syncthreads();
         }
@@ -601,7 +690,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             // own rows on the matrix cores, one 16-row tile per wavefront: the FP64 16x16x4 product
             // rounds as a chain of fused multiply-adds over k (measured bitwise on gfx950), which is
             // the chain the X-row loop below uses for the same rows in other workgroups
-            if (wave < gm.MT) {
+            if (mainw) {
                 const int r0 = wave * 16, c = lane & 15;
                 double val[4];
 #pragma unroll
@@ -613,21 +702,25 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 for (int hh = 0; hh < Hn; ++hh) {
                     const int zo = __builtin_amdgcn_readfirstlane(ozo[hh]);
                     if (zo < 0) continue;
-                    const int pm = __builtin_amdgcn_readfirstlane(opm[hh]), pc = opc[hh];
+                    const int pm = __builtin_amdgcn_readfirstlane(opm[hh]), ps = ops[hh];
                     typename Mfma16<TB>::V acc = {0, 0, 0, 0};
                     for (int k0 = 0; k0 < pm; k0 += 4) {
                         const int j = k0 + (lane >> 4), jc = j < pm ? j : pm - 1;
                         const TB a0 = zown[zo + jc * nl + rc];
-                        const TB b0 = (TB)y[(pc + jc) * kPB + c];
+                        const TB b0 = (TB)y[(ps + jc) * kPB + c];
                         acc = Mfma16<TB>::op((ra_ < nl && j < pm) ? a0 : (TB)0, j < pm ? b0 : (TB)0, acc);
                     }
 #pragma unroll
                     for (int e = 0; e < 4; ++e) val[e] -= (double)acc[e];
                 }
+                const int ra = anyact ? ract[c] : 0;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int r = r0 + Mfma16<TB>::row(lane, e);
-                    if (r < nl) out[r * kPB + c] = val[e];
+                    double sa = 0.0;          // per-case SMW correction
+                    for (int j = 0; j < ra; ++j)
+                        sa = pfma((double)uo[j * NLp * kPB + r * kPB + c], tz[c * 2 * R + R + j], sa);
+                    if (r < nl) out[r * kPB + c] = val[e] - sa;
                 }
             }
         } else {
@@ -636,52 +729,28 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 double val = out[i];
                 for (int hh = 0; hh < Hn; ++hh) {
                     const int zo = ozo[hh];
-                    if (zo >= 0) val -= (double)pdot<TA>(zown + zo + r, nl, y, opc[hh], opm[hh], c);
+                    if (zo >= 0) val -= (double)pdot<TA>(zown + zo + r, nl, y, ops[hh], opm[hh], c);
                 }
-                out[i] = val;
+                const int ra = anyact ? ract[c] : 0;
+                double sa = 0.0;              // per-case SMW correction
+                for (int j = 0; j < ra; ++j) sa = pfma((double)uo[j * NLp * kPB + i], tz[c * 2 * R + R + j], sa);
+                out[i] = val - sa;
             }
         }
-        for (int i = tid; i < nx * kPB; i += kPThreads) {
+        // X rows, starting on the helper wavefronts (no own-row tile in the update above)
+        for (int i = (tid + kPThreads - 6 * 64) % kPThreads; i < nx * kPB; i += kPThreads) {
             const int x = i >> 4, c = i & 15;
             double val = outx[i];
             for (int hh = 0; hh < Hn; ++hh) {
                 const int zo = xzo[x * Hn + hh];
-                if (zo >= 0) val -= (double)pdot<TA>(xz + zo, 1, y, xpc[x * Hn + hh], xpm[x * Hn + hh], c);
+                if (zo >= 0) val -= (double)pdot_pf<TA>(xz + zo, 1, y, xps[x * Hn + hh], xpm[x * Hn + hh], c);
             }
-            outx[i] = val;
+            const int ra = anyact ? ract[c] : 0;
+            double sa = 0.0;                  // per-case SMW correction
+            for (int j = 0; j < ra; ++j) sa = pfma((double)ux[j * NX * kPB + i], tz[c * 2 * R + R + j], sa);
+            outx[i] = val - sa;
         }
         __syncthreads();
-        if (anyact) {                                   // per-case SMW correction
-            if (tid < kPB) {
-                const int c = tid, ra = ract[c];
-                for (int j = 0; j < ra; ++j) {
-                    const int a = lpa[c * R + j], bb = lpb[c * R + j];
-                    tz[c * 2 * R + j] = cval(out, outx, a, c) - (bb >= 0 ? cval(out, outx, bb, c) : 0.0);
-                }
-                if (ra > 0) {
-                    const double* Ci = cinv + (int64_t)c * R * R * R + (ra - 1) * R * R;
-                    for (int j = 0; j < ra; ++j) {
-                        double acc = 0.0;
-                        for (int q = 0; q < ra; ++q) acc += Ci[j * R + q] * tz[c * 2 * R + q];
-                        tz[c * 2 * R + R + j] = acc;
-                    }
-                }
-            }
-            __syncthreads();
-            for (int i = tid; i < nl * kPB; i += kPThreads) {
-                const int c = i & 15, ra = ract[c];
-                double acc = 0.0;
-                for (int j = 0; j < ra; ++j) acc = pfma((double)uo[j * NLp * kPB + i], tz[c * 2 * R + R + j], acc);
-                out[i] -= acc;
-            }
-            for (int i = tid; i < nx * kPB; i += kPThreads) {
-                const int c = i & 15, ra = ract[c];
-                double acc = 0.0;
-                for (int j = 0; j < ra; ++j) acc = pfma((double)ux[j * NXs * kPB + i], tz[c * 2 * R + R + j], acc);
-                outx[i] -= acc;
-            }
-            __syncthreads();
-        }
         par ^= 1;
         return true;
     };
@@ -780,19 +849,15 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         }
         if (!alive) break;
         // history: new branch histories, then the right-hand side of step+1
-        for (int i = tid; i < nb * kPB; i += kPThreads) {
-            const int q = i >> 4, c = i & 15;
-            const int e = bglob[q];
-            bool lost = false;
-            for (int j = 0; j < nlost[c]; ++j)
-                if (lbr[c * R + j] == e && (int64_t)lst[c * R + j] <= step + 1) lost = true;
-            double hv = 0.0;
-            if (!lost) {
-                const double vft = cval(v, xv, bf[q], c) - cval(v, xv, bt[q], c);
+#pragma unroll
+        for (int k = 0; k < kPHItems; ++k) {
+            const int i = tid + k * kPThreads, q = i >> 4, c = i & 15;
+            if (q < nb) {
+                const bool lost = (int64_t)hlost[k] <= step + 1;
+                const double vft = cval(v, xv, hbft[k] & 0xffff, c) - cval(v, xv, hbft[k] >> 16, c);
                 const double ie = bg[q] * vft + h[i];
-                hv = bg[q] * vft + bal[q] * ie;
+                h[i] = lost ? 0.0 : bg[q] * vft + bal[q] * ie;
             }
-            h[i] = hv;
         }
         __syncthreads();
 #pragma unroll
@@ -800,12 +865,12 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             const int i = tid + k * kPThreads, r = i >> 4, c = i & 15;
             if (r < nl) {
                 const double va = v[i];
-                double bn = 0.0;
-                for (int q = sptr[r]; q < sptr[r + 1]; ++q) bn += sn[q];
-                for (int q = iptr[r]; q < iptr[r + 1]; ++q) {
+                double bn = sn[r];
+                const int q0 = rinc[k] & 0xffff, qn = rinc[k] >> 16;
+                for (int q = q0; q < q0 + qn; ++q) {
                     const int lb = ibr[q];
-                    const double hv = h[lb * kPB + c];
-                    bn -= (bf[lb] == r) ? hv : -hv;
+                    const double hv = h[(lb >= 0 ? lb : ~lb) * kPB + c];
+                    bn -= lb >= 0 ? hv : -hv;
                 }
                 const double ic = gC[r] * va + hcr[k];
                 const double hcn = -gC[r] * va - ic;
@@ -842,7 +907,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     double* hdst = E.h + (int64_t)(nstep & 1) * K * E.nbr;
     for (int i = tid; i < nb * kPB; i += kPThreads) {
         const int q = i >> 4, c = i & 15;
-        if (c < nvc && D.bown[(int64_t)l * D.NB + q]) hdst[(int64_t)(case0 + c) * E.nbr + bglob[q]] = h[i];
+        if (c < nvc && D.bown[(int64_t)l * D.NB + q]) hdst[(int64_t)(case0 + c) * E.nbr + D.bglob[(int64_t)l * D.NB + q]] = h[i];
     }
     if (tid < nvc) {
         if (MIXED && P.stats) atomicMax(&P.stats[case0 + tid], (unsigned long long)__double_as_longlong(worst));
@@ -851,12 +916,49 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     if (blockIdx.x == 0 && tid == 0) *E.step = nstep;
 }
 
-template <typename TB, bool MIXED, bool WARM>
-static hipError_t launch_panel_t(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M,
-                                 const RunParams& P, hipStream_t s)
+// ---------------- M as the y tasks' A fragments: lane l of k-step kk of task t holds M[g][4 k + l/16] of
+// the slot 16 tile + l%16 (g its column; zero for padding slots and columns beyond nc).  Grid (T, NT).
+__global__ void k_panel_mfrag(PanelDev D)
 {
-    const size_t lds = panel_layout<TB, MIXED>(D, M.R).total;
-    const void* fn = (const void*)k_emt_panel<TB, MIXED, WARM>;
+    const int l = blockIdx.x, t = blockIdx.y;
+    if (t >= D.w_nt[l]) return;
+    const int64_t ti = (int64_t)l * D.NT + t;
+    const int k0 = D.tk0[ti], nk = D.tnk[ti], fo = D.tfo[ti], tile = D.ttile[ti];
+    double* m64 = const_cast<double*>(D.mfr) + (int64_t)l * D.MF + fo;
+    float* m32 = const_cast<float*>(D.mfr32) + (int64_t)l * D.MF + fo;
+    for (int i = threadIdx.x; i < nk * 64; i += blockDim.x) {
+        const int kk = i >> 6, ln = i & 63;
+        const int g = D.yslot[(int64_t)l * D.NY + tile * 16 + (ln & 15)];
+        const int col = (k0 + kk) * 4 + (ln >> 4);
+        const double val = (g >= 0 && col < D.nc) ? D.bm[(int64_t)g * D.nc + col] : 0.0;
+        m64[i] = val;
+        m32[i] = (float)val;
+    }
+}
+
+hipError_t launch_panel_mfrag(const PanelDev& D, hipStream_t s)
+{
+    if (D.nc <= 0 || D.NT <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_panel_mfrag, dim3(D.T, D.NT), dim3(256), 0, s, D);
+    return hipGetLastError();
+}
+
+template <typename TB, bool MIXED, bool WARM>
+static const void* panel_fn()
+{
+    return (const void*)k_emt_panel<TB, MIXED, WARM>;
+}
+
+static const void* panel_kernel(int prec, int warm)
+{
+    if (prec == HINV_FP64) return panel_fn<double, false, false>();
+    return warm ? panel_fn<float, true, true>() : panel_fn<float, true, false>();
+}
+
+hipError_t panel_setup(PanelDev& D, int R, int prec, int warm)
+{
+    const size_t lds = panel_lds_bytes(D, R, prec);
+    const void* fn = panel_kernel(prec, warm);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     int dev = 0, cus = 0, per = 0;
@@ -866,12 +968,19 @@ static hipError_t launch_panel_t(const PanelDev& D, const EmtDev& E, const HierD
     if (e != hipSuccess) return e;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kPThreads, lds);
     if (e != hipSuccess) return e;
-    const int teams_per_launch = (per * cus) / D.T;     // teams that are co-resident in one launch
-    if (teams_per_launch < 1) return hipErrorCooperativeLaunchTooLarge;
-    e = hipMemsetAsync(D.sync, 0, (size_t)D.n_teams * D.T * sizeof(unsigned int), s);
-    if (e != hipSuccess) return e;
-    for (int t0 = 0; t0 < D.n_teams; t0 += teams_per_launch) {
-        const int nt = D.n_teams - t0 < teams_per_launch ? D.n_teams - t0 : teams_per_launch;
+    D.teams_per_launch = (per * cus) / D.T;     // teams that are co-resident in one launch
+    if (D.teams_per_launch < 1) return hipErrorCooperativeLaunchTooLarge;
+    return hipSuccess;
+}
+
+hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
+                            int prec, hipStream_t s)
+{
+    const size_t lds = panel_lds_bytes(D, M.R, prec);
+    const void* fn = panel_kernel(prec, P.warm);
+    if (D.teams_per_launch < 1) return hipErrorCooperativeLaunchTooLarge;
+    for (int t0 = 0; t0 < D.n_teams; t0 += D.teams_per_launch) {
+        const int nt = D.n_teams - t0 < D.teams_per_launch ? D.n_teams - t0 : D.teams_per_launch;
         PanelDev Dc = D;
         Dc.team0 = t0;
         EmtDev Ec = E;
@@ -879,18 +988,10 @@ static hipError_t launch_panel_t(const PanelDev& D, const EmtDev& E, const HierD
         ModDev Mc = M;
         RunParams Pc = P;
         void* args[] = {&Dc, &Ec, &Hc, &Mc, &Pc};
-        e = hipLaunchCooperativeKernel(fn, dim3(nt * D.T), dim3(kPThreads), args, (unsigned int)lds, s);
+        hipError_t e = hipLaunchCooperativeKernel(fn, dim3(nt * D.T), dim3(kPThreads), args, (unsigned int)lds, s);
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
-                            int prec, hipStream_t s)
-{
-    if (prec == HINV_FP64) return launch_panel_t<double, false, false>(D, E, H, M, P, s);
-    if (P.warm) return launch_panel_t<float, true, true>(D, E, H, M, P, s);
-    return launch_panel_t<float, true, false>(D, E, H, M, P, s);
 }
 
 }  // namespace hinv

@@ -621,7 +621,14 @@ hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, 
 //   bm[g][c] = sum_p S_t^{-1}[p][q_g] (w_{c0+p} [c = c0+p] - am[c0+p][c])
 //              (t: the column's node, columns c0 .. c0+m-1, q_g = g - c0),
 // so that s = diag(w) u - am u and y = bm u, as the sequential levels give.
-__global__ void k_team_am(HierDev H, TeamDev D, int h)
+struct CouplingMap {
+    int nc, Hn;
+    const int* cpan;
+    double* am;
+    double* bm;
+};
+
+__global__ void k_coupling_am(HierDev H, CouplingMap D, int h)
 {
     const int nc = D.nc, g0 = H.lvl_col[h - 1];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -630,7 +637,7 @@ __global__ void k_team_am(HierDev H, TeamDev D, int h)
     const int r = H.col_row[g];
     double acc = 0.0;
     for (int hh = 1; hh < h; ++hh) {
-        const int pp = D.cpan[(int64_t)g * D.H + hh - 1];
+        const int pp = D.cpan[(int64_t)g * D.Hn + hh - 1];
         if (pp < 0) continue;
         const double* zp = H.Z + H.pan_zoff[pp] + (r - H.pan_lo[pp]);
         const int p0 = H.pan_col0[pp], pn = H.pan_n[pp];
@@ -639,7 +646,7 @@ __global__ void k_team_am(HierDev H, TeamDev D, int h)
     D.am[(int64_t)g * nc + c] = H.col_w[g] * acc;
 }
 
-__global__ void k_team_bm(HierDev H, TeamDev D, int h)
+__global__ void k_coupling_bm(HierDev H, CouplingMap D, int h)
 {
     const int nc = D.nc, g0 = H.lvl_col[h - 1];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -654,6 +661,26 @@ __global__ void k_team_bm(HierDev H, TeamDev D, int h)
         acc += Si[(int64_t)p * m] * sv;
     }
     D.bm[(int64_t)g * nc + c] = acc;
+}
+
+hipError_t launch_coupling_map(const HierDev& H, int Hn, int nc, const int* cpan, double* am, double* bm,
+                               hipStream_t s)
+{
+    if (nc <= 0) return hipSuccess;
+    std::vector<int> lvl(Hn + 1);
+    hipError_t e = hipMemcpyAsync(lvl.data(), H.lvl_col, sizeof(int) * (Hn + 1), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    const CouplingMap D{nc, Hn, cpan, am, bm};
+    for (int h = 1; h <= Hn; ++h) {
+        const int64_t cnt = (int64_t)(lvl[h] - lvl[h - 1]) * nc;
+        if (cnt <= 0) continue;
+        const int blocks = (int)((cnt + 255) / 256);
+        k_coupling_am<<<blocks, 256, 0, s>>>(H, D, h);
+        k_coupling_bm<<<blocks, 256, 0, s>>>(H, D, h);
+    }
+    return hipGetLastError();
 }
 
 __global__ void k_team_apack(TeamDev D)
@@ -671,18 +698,8 @@ __global__ void k_team_apack(TeamDev D)
 hipError_t launch_team_acoef(const TeamDev& T, const HierDev& H, hipStream_t s)
 {
     if (T.nc <= 0) return hipSuccess;
-    std::vector<int> lvl(T.H + 1);
-    hipError_t e = hipMemcpyAsync(lvl.data(), H.lvl_col, sizeof(int) * (T.H + 1), hipMemcpyDeviceToHost, s);
+    hipError_t e = launch_coupling_map(H, T.H, T.nc, T.cpan, T.am, T.bm, s);
     if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    for (int h = 1; h <= T.H; ++h) {
-        const int64_t cnt = (int64_t)(lvl[h] - lvl[h - 1]) * T.nc;
-        if (cnt <= 0) continue;
-        const int blocks = (int)((cnt + 255) / 256);
-        k_team_am<<<blocks, 256, 0, s>>>(H, T, h);
-        k_team_bm<<<blocks, 256, 0, s>>>(H, T, h);
-    }
     k_team_apack<<<(T.nc + 255) / 256, 256, 0, s>>>(T);
     return hipGetLastError();
 }
