@@ -80,7 +80,7 @@ def run_region(torch, emt, pre, steps, chunk):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sizes]
     off = 0
     for (e0, e1), k in zip(ev, sizes):
-        emt.set_step_clock(clk[off:off + k])
+        emt.set_step_clock(clk[off:off + k])      # host-side bookkeeping, outside the bracket
         e0.record(s)
         emt.step(k, record_v=False)
         e1.record(s)

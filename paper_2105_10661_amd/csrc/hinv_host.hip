@@ -1221,6 +1221,7 @@ struct emt_ctx {
     TeamDev TD{};
     // panel engine (cases in panels of kPanelCases, one workgroup per leaf per panel)
     bool panel_ok = false;
+    std::vector<int> phbft, phlost, pxzsrc, pw_xz;
     std::vector<int> pw_nx, pw_ny, pw_nt, pw_np, pxrow, pxcol, pxzo, pxpm, pxps, pxpan, plpa, plpb, pcpan, ppubr, ppubg,
         pyslot, ptk0, ptnk, ptfo, pttile, pttp, pttl, pwtask;
     PanelDev PD{};
@@ -1868,7 +1869,7 @@ bool build_panel_plan(emt_ctx& c, int R)
     // published columns, y slots and tasks
     struct W {
         std::vector<int> fx, xcol, ozo, opm, ops, opan, orp, ocol, bglob, bf, bt, bown, iptr, ibr, sptr, pubr, pubg;
-        std::vector<int> xzo, xpm, xps, xpan, yslot, tk0, tnk, tfo, ttile, ttp, ttl, wtask;
+        std::vector<int> xzo, xpm, xps, xpan, yslot, tk0, tnk, tfo, ttile, ttp, ttl, wtask, ibrs, hbft, xzsrc;
         std::vector<double> oval, bg, bal, samp, sph;
         std::vector<int> osrc;       // CSR entry of each oval value, plus one
         int zo = 0, xz = 0, mf = 0;
@@ -1979,6 +1980,8 @@ bool build_panel_plan(emt_ctx& c, int R)
                 if (pp < 0) continue;
                 const size_t i = x * Hs + h - 1;
                 w.xzo[i] = w.xz; w.xpm[i] = P.pan_m[pp]; w.xps[i] = slot_of[P.pan_col0[pp]]; w.xpan[i] = pp;
+                for (int j = 0; j < P.pan_m[pp]; ++j)
+                    w.xzsrc.push_back((int)(P.pan_zoff[pp] + (w.fx[x] - P.pan_lo[pp]) + (int64_t)j * P.pan_n[pp]));
                 w.xz += P.pan_m[pp];
             }
         }
@@ -2005,6 +2008,7 @@ bool build_panel_plan(emt_ctx& c, int R)
             w.bglob.push_back(e);
             w.bf.push_back(comb(c.fr_p[e]));
             w.bt.push_back(comb(c.to_p[e]));
+            w.hbft.push_back(w.bf.back() | (w.bt.back() << 16));
             w.bown.push_back(own(c.fr_p[e]) ? 1 : 0);
             w.bg.push_back(c.g[e]);
             w.bal.push_back(c.alpha[e]);
@@ -2012,8 +2016,11 @@ bool build_panel_plan(emt_ctx& c, int R)
         w.iptr.assign(nl + 1, 0);
         w.sptr.assign(nl + 1, 0);
         for (int r = lo; r < lo + nl; ++r) {
-            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q)
-                w.ibr.push_back((int)(std::lower_bound(br.begin(), br.end(), c.inc_br[q]) - br.begin()));
+            for (int q = c.inc_ptr[r]; q < c.inc_ptr[r + 1]; ++q) {
+                const int lb = (int)(std::lower_bound(br.begin(), br.end(), c.inc_br[q]) - br.begin());
+                w.ibr.push_back(lb);
+                w.ibrs.push_back(w.bf[lb] == r - lo ? lb : ~lb);
+            }
             w.iptr[r - lo + 1] = (int)w.ibr.size();
             for (int q = c.src_ptr[r]; q < c.src_ptr[r + 1]; ++q) {
                 w.samp.push_back(c.samp[q]);
@@ -2058,6 +2065,20 @@ bool build_panel_plan(emt_ctx& c, int R)
             }
         }
     }
+    std::vector<int> hlost((size_t)n_teams * L * NB * kPanelCases, 0x7fffffff);
+    for (int tm = 0; tm < n_teams; ++tm)
+        for (int cc = 0; cc < kPanelCases; ++cc) {
+            const int k = tm * kPanelCases + cc;
+            if (k >= c.n_cases) break;
+            for (const auto& ls : c.losses[k])
+                for (int l = 0; l < L; ++l) {
+                    const auto& bgl = ws[l].bglob;
+                    const auto it = std::lower_bound(bgl.begin(), bgl.end(), ls.second);
+                    if (it == bgl.end() || *it != ls.second) continue;
+                    int& v = hlost[(((size_t)tm * L + l) * NB + (it - bgl.begin())) * kPanelCases + cc];
+                    v = std::min(v, ls.first);
+                }
+        }
     PanelDev& D = c.PD;
     D.T = L; D.H = H; D.NL = NL; D.NLp = (NL + 15) / 16 * 16; D.NX = NX; D.NB = NB; D.NE = NE;
     D.NI = NI; D.NS = NS; D.XZ = XZ; D.ZO = ZO; D.nc = NC; D.ncp = (NC + 3) / 4 * 4;
@@ -2100,7 +2121,9 @@ bool build_panel_plan(emt_ctx& c, int R)
     flat(c.tbt, NB, 0, [](W& w) -> std::vector<int>& { return w.bt; });
     flat(c.tbown, NB, 0, [](W& w) -> std::vector<int>& { return w.bown; });
     flat(c.tiptr, NL + 1, 0, [](W& w) -> std::vector<int>& { return w.iptr; });
-    flat(c.tibr, NI, 0, [](W& w) -> std::vector<int>& { return w.ibr; });
+    flat(c.tibr, NI, 0, [](W& w) -> std::vector<int>& { return w.ibrs; });
+    flat(c.phbft, NB, 0, [](W& w) -> std::vector<int>& { return w.hbft; });
+    flat(c.pxzsrc, XZ, 0, [](W& w) -> std::vector<int>& { return w.xzsrc; });
     flat(c.tsptr, NL + 1, 0, [](W& w) -> std::vector<int>& { return w.sptr; });
     flatd(c.toval, NE, [](W& w) -> std::vector<double>& { return w.oval; });
     flat(c.tosrc, NE, 0, [](W& w) -> std::vector<int>& { return w.osrc; });
@@ -2126,6 +2149,9 @@ bool build_panel_plan(emt_ctx& c, int R)
     flat(c.pwtask, kPanelWaves * kPanelYTasksPerWave, -1, [](W& w) -> std::vector<int>& { return w.wtask; });
     c.plpa = std::move(lpa);
     c.plpb = std::move(lpb);
+    c.phlost = std::move(hlost);
+    c.pw_xz.resize(L);
+    for (int l = 0; l < L; ++l) c.pw_xz[l] = ws[l].xz;
     return true;
 }
 
@@ -2143,6 +2169,8 @@ void carve_panel(emt_ctx& c, Arena& A)
     D.bg = td(L * D.NB); D.bal = td(L * D.NB);
     D.iptr = ti(L * (D.NL + 1)); D.ibr = ti(L * D.NI);
     D.sptr = ti(L * (D.NL + 1)); D.samp = td(L * D.NS); D.sph = td(L * D.NS);
+    D.hbft = ti(L * D.NB); D.hlost = ti(TW * D.NB * kPanelCases);
+    D.w_xz = ti(L); D.xzsrc = ti(L * D.XZ);
     D.w_np = ti(L); D.pubr = ti(L * D.NP); D.pubg = ti(L * D.NP);
     D.xrow = ti(L * D.NX); D.xcol = ti(L * D.NX);
     D.xzo = ti(L * D.NX * H); D.xpm = ti(L * D.NX * H); D.xps = ti(L * D.NX * H); D.xpan = ti(L * D.NX * H);
@@ -2156,6 +2184,8 @@ void carve_panel(emt_ctx& c, Arena& A)
     D.cpan = ti((int64_t)std::max(D.nc, 1) * H);
     D.am = td((int64_t)std::max(D.nc, 1) * std::max(D.nc, 1));
     D.bm = td((int64_t)std::max(D.nc, 1) * std::max(D.nc, 1));
+    D.imgb = panel_image_bytes(D, (int)R, c.hc.opt.prec);
+    D.img = A.take<unsigned char>(L * (int64_t)D.imgb);
     D.sync = A.take<unsigned int>(TW);
     D.X0 = td((int64_t)D.n_teams * 2 * std::max(D.nc, 1) * kPanelCases);
     D.SP = td(TW * 2 * R * kPanelCases);
@@ -2168,6 +2198,7 @@ hinv_status build_panel_map(emt_ctx& c, hipStream_t s)
     PanelDev& D = c.PD;
     HIP_TRY(launch_coupling_map(c.hc.H, D.H, D.nc, D.cpan, D.am, D.bm, s));
     HIP_TRY(launch_panel_mfrag(D, s));
+    HIP_TRY(launch_panel_image(D, c.E, c.hc.H, c.R, c.hc.opt.prec, s));
     HIP_TRY(hipStreamSynchronize(s));
     return HINV_OK;
 }
@@ -2184,6 +2215,8 @@ hinv_status upload_panel(emt_ctx& c, hipStream_t s)
     HIP_TRY(up(D.bown, c.tbown, s)); HIP_TRY(up(D.bg, c.tbg, s)); HIP_TRY(up(D.bal, c.tbal, s));
     HIP_TRY(up(D.iptr, c.tiptr, s)); HIP_TRY(up(D.ibr, c.tibr, s)); HIP_TRY(up(D.sptr, c.tsptr, s));
     HIP_TRY(up(D.samp, c.tsamp, s)); HIP_TRY(up(D.sph, c.tsph, s));
+    HIP_TRY(up(D.hbft, c.phbft, s)); HIP_TRY(up(D.hlost, c.phlost, s));
+    HIP_TRY(up(D.w_xz, c.pw_xz, s)); HIP_TRY(up(D.xzsrc, c.pxzsrc, s));
     HIP_TRY(up(D.w_np, c.pw_np, s)); HIP_TRY(up(D.pubr, c.ppubr, s)); HIP_TRY(up(D.pubg, c.ppubg, s));
     HIP_TRY(up(D.xrow, c.pxrow, s)); HIP_TRY(up(D.xcol, c.pxcol, s));
     HIP_TRY(up(D.xzo, c.pxzo, s)); HIP_TRY(up(D.xpm, c.pxpm, s)); HIP_TRY(up(D.xps, c.pxps, s));

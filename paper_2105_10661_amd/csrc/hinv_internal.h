@@ -308,6 +308,8 @@ struct PanelDev {
     int MF;              // M fragment entries of a workgroup (multiple of 64), most over the leaves
     int NP;              // published (row, column) pairs of a leaf, most over the leaves
     int ysep;            // 1: the y tasks' results have an LDS region of their own (else they overwrite u)
+    size_t imgb;         // bytes of one leaf's image of its LDS tables
+    unsigned char* img;  // [T*imgb] the leaves' images (k_panel_image), copied into LDS at every launch
     int teams_per_launch;    // teams co-resident in one cooperative launch
     unsigned int epoch0;     // barrier epochs of earlier launches (flags are never reset between launches)
     // per leaf l
@@ -331,7 +333,9 @@ struct PanelDev {
     const double* bg;
     const double* bal;
     const int* iptr;     // [T*(NL+1)] incident local branches of each own row
-    const int* ibr;      // [T*NI]
+    const int* ibr;      // [T*NI] local branch index, or its complement where the row is the branch's to-bus
+    const int* hbft;     // [T*NB] the branch's endpoints (combined indices), from | to << 16
+    const int* hlost;    // [n_teams*T*NB*kPanelCases] first step from which the branch is lost for the case
     const int* sptr;     // [T*(NL+1)] sources of each own row
     const double* samp;  // [T*NS]
     const double* sph;
@@ -340,6 +344,8 @@ struct PanelDev {
     const int* pubg;     // [T*NP] coupling column of each pair
     const int* xrow;     // [T*NX] new-order row of each X row
     const int* xcol;     // [T*NX] a coupling column whose row is the X row (its exchange index)
+    const int* w_xz;     // [T] Z values of the X rows
+    const int* xzsrc;    // [T*XZ] index of each of them in the hierarchy's Z array
     const int* xzo;      // [T*NX*H] offset of the X row's Z values at level h in the xz region, -1: none
     const int* xpm;
     const int* xps;      // [T*NX*H] slot of the panel's first column
@@ -506,6 +512,9 @@ size_t panel_lds_bytes(const PanelDev& D, int R, int prec);
 hipError_t panel_setup(PanelDev& D, int R, int prec, int warm);
 // M as the y tasks' A fragments (D.mfr, D.mfr32) from D.bm; after launch_coupling_map.
 hipError_t launch_panel_mfrag(const PanelDev& D, hipStream_t s);
+// Each leaf's image of its LDS tables (after the tables, M fragments and Z values are current).
+size_t panel_image_bytes(const PanelDev& D, int R, int prec);
+hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev& H, int R, int prec, hipStream_t s);
 hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
 // Level stepping (k_level.hip): LDS bytes of the layout, and the launch.

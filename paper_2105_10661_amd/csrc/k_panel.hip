@@ -134,6 +134,7 @@ __host__ __device__ inline PanelGemm panel_gemm(int NLp)
 static_assert(kPWaves == 8, "six main and two helper wavefronts");
 
 struct PanelLayout {
+    size_t stat;         // end of the per-leaf tables (the first bytes of the layout; copied from the leaf's image)
     size_t mfr, zown, xz, uo, ux;
     size_t b, v, td, xv, xd, U, yres, y, h, gC, oval, bg, bal, samp, sph, sn, cinv, mdg, tz, red, red2, red3;
     size_t xcol, xzo, xpm, xps, ozo, opm, ops, orp, ocol, iptr, ibr, sptr, prow, pubr, pubg, tk0, tnk, tfo, ttp,
@@ -162,34 +163,16 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
     if ((size_t)D.NT * 256 > un) un = (size_t)D.NT * 256;
     if ((size_t)g.MT * 256 > un) un = (size_t)g.MT * 256;
     const size_t S = sizeof(TB), F = sizeof(double), I = sizeof(int);
+    // per-leaf tables (the same in every team; one image per leaf is copied at the launch)
     L.mfr = take(S * D.MF);
     L.zown = take(S * D.ZO);
     L.xz = take(S * D.XZ);
-    L.uo = take(S * R * NLp * B);
-    L.ux = take(S * R * NX * B);
-    L.b = take(F * NLp * B);
-    L.v = MIXED ? take(F * NL * B) : L.b;
-    L.td = take(MIXED ? F * NLp * B : 0);
-    L.xv = take(F * NX * B);
-    L.xd = take(MIXED ? F * NX * B : 0);
-    L.U = take(F * un);
-    L.yres = D.ysep ? take(F * D.NT * 256) : L.U;   // y task results (in the U region when LDS is short)
-    L.y = take(F * D.NY * B);
-    L.h = take(F * NB * B);
     L.gC = take(F * NL);
     L.oval = take(MIXED ? F * D.NE : 0);
     L.bg = take(F * NB);
     L.bal = take(F * NB);
     L.samp = take(F * D.NS);
     L.sph = take(F * D.NS);
-    L.sn = take(F * NL);          // source injection of each own row at the next step
-    L.cinv = take(F * B * (R * (R + 1) * (2 * R + 1) / 6));   // per case the r x r inverses, r = 1..R, packed
-    L.mdg = take(F * B * R);
-    L.tz = take(F * B * 2 * R);
-    L.red = take(MIXED ? F * 2 * kPWaves * B : 0);
-    // red2 (shares per wavefront, before the barrier) and red3 (the team's shares, after it) share one region
-    L.red2 = take(F * (kPWaves > D.T ? kPWaves : D.T) * R * B);
-    L.red3 = L.red2;
     L.xcol = take(I * NX);
     L.xzo = take(I * NX * H);
     L.xpm = take(I * NX * H);
@@ -210,6 +193,27 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
     L.tfo = take(I * D.NT);
     L.ttp = take(I * (D.NY / 16 + 1));
     L.wtask = take(I * kPWaves * kPYT);
+    L.stat = o;
+    // the team's cases and the state
+    L.uo = take(S * R * NLp * B);
+    L.ux = take(S * R * NX * B);
+    L.b = take(F * NLp * B);
+    L.v = MIXED ? take(F * NL * B) : L.b;
+    L.td = take(MIXED ? F * NLp * B : 0);
+    L.xv = take(F * NX * B);
+    L.xd = take(MIXED ? F * NX * B : 0);
+    L.U = take(F * un);
+    L.yres = D.ysep ? take(F * D.NT * 256) : L.U;   // y task results (in the U region when LDS is short)
+    L.y = take(F * D.NY * B);
+    L.h = take(F * NB * B);
+    L.sn = take(F * NL);          // source injection of each own row at the next step
+    L.cinv = take(F * B * (R * (R + 1) * (2 * R + 1) / 6));   // per case the r x r inverses, r = 1..R, packed
+    L.mdg = take(F * B * R);
+    L.tz = take(F * B * 2 * R);
+    L.red = take(MIXED ? F * 2 * kPWaves * B : 0);
+    // red2 (shares per wavefront, before the barrier) and red3 (the team's shares, after it) share one region
+    L.red2 = take(F * (kPWaves > D.T ? kPWaves : D.T) * R * B);
+    L.red3 = L.red2;
     L.lpa = take(I * B * R);
     L.lpb = take(I * B * R);
     L.mact = take(I * B * R);
@@ -224,6 +228,117 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
 size_t panel_lds_bytes(const PanelDev& D, int R, int prec)
 {
     return prec == HINV_FP64 ? panel_layout<double, false>(D, R).total : panel_layout<float, true>(D, R).total;
+}
+
+// The per-leaf tables of the layout, written at base (LDS or a leaf's image in global memory) by nth
+// threads: M fragments, Z rows of the own rows and X rows, y tasks, publish list, CSR rows, branch and
+// source tables.
+template <typename TB, bool MIXED>
+__device__ void panel_fill_static(const PanelDev& D, const EmtDev& E, const HierDev& H, const PanelLayout& Ly,
+                                  unsigned char* base, int l, int tid, int nth)
+{
+    const int Hn = D.H, NX = D.NX;
+    const int lo = D.w_lo[l], nl = D.w_nl[l], nb = D.w_nb[l], nx = D.w_nx[l], ny = D.w_ny[l], nt = D.w_nt[l];
+    const int npub = D.w_np[l];
+    TB* mfr = (TB*)(base + Ly.mfr);
+    TB* zown = (TB*)(base + Ly.zown);
+    TB* xz = (TB*)(base + Ly.xz);
+    double* gC = (double*)(base + Ly.gC);
+    double* oval = (double*)(base + Ly.oval);
+    double* bg = (double*)(base + Ly.bg);
+    double* bal = (double*)(base + Ly.bal);
+    double* samp = (double*)(base + Ly.samp);
+    double* sph = (double*)(base + Ly.sph);
+    int* xcol = (int*)(base + Ly.xcol);
+    int* xzo = (int*)(base + Ly.xzo);
+    int* xpm = (int*)(base + Ly.xpm);
+    int* xps = (int*)(base + Ly.xps);
+    int* ozo = (int*)(base + Ly.ozo);
+    int* opm = (int*)(base + Ly.opm);
+    int* ops = (int*)(base + Ly.ops);
+    int* orp = (int*)(base + Ly.orp);
+    int* ocol = (int*)(base + Ly.ocol);
+    int* iptr = (int*)(base + Ly.iptr);
+    int* ibr = (int*)(base + Ly.ibr);
+    int* sptr = (int*)(base + Ly.sptr);
+    int* prow = (int*)(base + Ly.prow);
+    int* pubr = (int*)(base + Ly.pubr);
+    int* pubg = (int*)(base + Ly.pubg);
+    int* tk0 = (int*)(base + Ly.tk0);
+    int* tnk = (int*)(base + Ly.tnk);
+    int* tfo = (int*)(base + Ly.tfo);
+    int* ttp = (int*)(base + Ly.ttp);
+    int* wtask = (int*)(base + Ly.wtask);
+    const TB* gZ;
+    const TB* gM;
+    if constexpr (sizeof(TB) == 8) {
+        gZ = (const TB*)H.Z; gM = (const TB*)D.mfr;
+    } else {
+        gZ = (const TB*)H.Z32; gM = (const TB*)D.mfr32;
+    }
+    for (int i = tid; i < D.MF; i += nth) mfr[i] = gM[(int64_t)l * D.MF + i];
+    for (int t = tid; t < nt; t += nth) {
+        const int64_t gi = (int64_t)l * D.NT + t;
+        tk0[t] = D.tk0[gi];
+        tnk[t] = D.tnk[gi];
+        tfo[t] = D.tfo[gi];
+    }
+    for (int t = tid; t <= ny / 16; t += nth) ttp[t] = D.ttp[(int64_t)l * (D.NY / 16 + 1) + t];
+    for (int i = tid; i < kPWaves * kPYT; i += nth) wtask[i] = D.wtask[(int64_t)l * kPWaves * kPYT + i];
+    const int64_t xb = (int64_t)l * NX;
+    for (int x = tid; x < nx; x += nth) xcol[x] = D.xcol[xb + x];
+    for (int i = tid; i < nx * Hn; i += nth) {
+        const int64_t gi = xb * Hn + i;
+        xzo[i] = D.xzo[gi];
+        xpm[i] = D.xpm[gi];
+        xps[i] = D.xps[gi];
+    }
+    for (int i = tid; i < D.w_xz[l]; i += nth) xz[i] = gZ[D.xzsrc[(int64_t)l * D.XZ + i]];
+    for (int hh = tid; hh < Hn; hh += nth) {
+        ozo[hh] = D.ozo[l * Hn + hh];
+        opm[hh] = D.opm[l * Hn + hh];
+        ops[hh] = D.ops[l * Hn + hh];
+    }
+    for (int hh = 0; hh < Hn; ++hh) {                    // own rows: Z panel rows at every level
+        const int zo = D.ozo[l * Hn + hh];
+        if (zo < 0) continue;
+        const int pan = D.opan[l * Hn + hh], pm = D.opm[l * Hn + hh];
+        const TB* zp = gZ + H.pan_zoff[pan] + (lo - H.pan_lo[pan]);
+        for (int i = tid; i < pm * nl; i += nth) {
+            const int j = i / nl, r = i - j * nl;
+            zown[zo + i] = zp[(int64_t)j * H.pan_n[pan] + r];
+        }
+    }
+    const int64_t rb = (int64_t)l * (D.NL + 1);
+    for (int r = tid; r <= nl; r += nth) {
+        orp[r] = D.orp[rb + r];
+        iptr[r] = D.iptr[rb + r];
+        sptr[r] = D.sptr[rb + r];
+    }
+    for (int q = tid; q < npub; q += nth) {
+        pubr[q] = D.pubr[(int64_t)l * D.NP + q];
+        pubg[q] = D.pubg[(int64_t)l * D.NP + q];
+    }
+    if (MIXED) {
+        for (int e = tid; e < D.orp[rb + nl]; e += nth) {
+            ocol[e] = D.ocol[(int64_t)l * D.NE + e];
+            oval[e] = D.oval[(int64_t)l * D.NE + e];
+        }
+    }
+    for (int i = tid; i < D.iptr[rb + nl]; i += nth) ibr[i] = D.ibr[(int64_t)l * D.NI + i];
+    for (int i = tid; i < D.sptr[rb + nl]; i += nth) {
+        samp[i] = D.samp[(int64_t)l * D.NS + i];
+        sph[i] = D.sph[(int64_t)l * D.NS + i];
+    }
+    for (int q = tid; q < nb; q += nth) {
+        const int64_t gq = (int64_t)l * D.NB + q;
+        bg[q] = D.bg[gq];
+        bal[q] = D.bal[gq];
+    }
+    for (int r = tid; r < nl; r += nth) {
+        gC[r] = E.gC[lo + r];
+        prow[r] = E.perm[lo + r];
+    }
 }
 
 template <typename TB, bool MIXED, bool WARM>
@@ -306,82 +421,20 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     } else {
         gblk = (const TB*)H.blk32; gZ = (const TB*)H.Z32; gU = (const TB*)M.U32; gM = (const TB*)D.mfr32;
     }
-    // ---------------- tables and state into LDS
-    for (int i = tid; i < D.MF; i += kPThreads) mfr[i] = gM[(int64_t)l * D.MF + i];
-    for (int t = tid; t < nt; t += kPThreads) {
-        const int64_t gi = (int64_t)l * D.NT + t;
-        tk0[t] = D.tk0[gi];
-        tnk[t] = D.tnk[gi];
-        tfo[t] = D.tfo[gi];
-    }
-    for (int t = tid; t <= ny / 16; t += kPThreads) ttp[t] = D.ttp[(int64_t)l * (D.NY / 16 + 1) + t];
-    for (int i = tid; i < kPWaves * kPYT; i += kPThreads) wtask[i] = D.wtask[(int64_t)l * kPWaves * kPYT + i];
-    const int64_t xb = (int64_t)l * NX;
-    for (int x = tid; x < nx; x += kPThreads) xcol[x] = D.xcol[xb + x];
-    for (int i = tid; i < nx * Hn; i += kPThreads) {     // X rows: Z values at every level
-        const int64_t gi = xb * Hn + i;
-        const int zo = D.xzo[gi];
-        xzo[i] = zo;
-        xpm[i] = D.xpm[gi];
-        xps[i] = D.xps[gi];
-        if (zo >= 0) {
-            const int pan = D.xpan[gi];
-            const TB* zp = gZ + H.pan_zoff[pan] + (D.xrow[xb + i / Hn] - H.pan_lo[pan]);
-            for (int j = 0; j < D.xpm[gi]; ++j) xz[zo + j] = zp[(int64_t)j * H.pan_n[pan]];
-        }
-    }
-    for (int hh = 0; hh < Hn; ++hh) {                    // own rows: Z panel rows at every level
-        const int zo = D.ozo[l * Hn + hh];
-        if (tid == 0) { ozo[hh] = zo; opm[hh] = D.opm[l * Hn + hh]; ops[hh] = D.ops[l * Hn + hh]; }
-        if (zo >= 0) {
-            const int pan = D.opan[l * Hn + hh], pm = D.opm[l * Hn + hh];
-            const TB* zp = gZ + H.pan_zoff[pan] + (lo - H.pan_lo[pan]);
-            for (int i = tid; i < pm * nl; i += kPThreads) {
-                const int j = i / nl, r = i - j * nl;
-                zown[zo + i] = zp[(int64_t)j * H.pan_n[pan] + r];
-            }
-        }
-    }
+    // ---------------- the leaf's tables (its image), then the team's cases and the state, into LDS
     {
-        const int64_t rb = (int64_t)l * (D.NL + 1);
-        for (int r = tid; r <= nl; r += kPThreads) {
-            orp[r] = D.orp[rb + r];
-            iptr[r] = D.iptr[rb + r];
-            sptr[r] = D.sptr[rb + r];
-        }
-        for (int q = tid; q < npub; q += kPThreads) {
-            pubr[q] = D.pubr[(int64_t)l * D.NP + q];
-            pubg[q] = D.pubg[(int64_t)l * D.NP + q];
-        }
-        if (MIXED) {
-            for (int e = tid; e < D.orp[rb + nl]; e += kPThreads) {
-                ocol[e] = D.ocol[(int64_t)l * D.NE + e];
-                oval[e] = D.oval[(int64_t)l * D.NE + e];
-            }
-        }
-        for (int r = tid; r < nl; r += kPThreads)        // incident branches: ~lb where the row is the to-bus
-            for (int q = D.iptr[rb + r]; q < D.iptr[rb + r + 1]; ++q) {
-                const int lb = D.ibr[(int64_t)l * D.NI + q];
-                ibr[q] = D.bf[(int64_t)l * D.NB + lb] == r ? lb : ~lb;
-            }
-        for (int i = tid; i < D.sptr[rb + nl]; i += kPThreads) {
-            samp[i] = D.samp[(int64_t)l * D.NS + i];
-            sph[i] = D.sph[(int64_t)l * D.NS + i];
-        }
+        const uint4* src = (const uint4*)(D.img + (int64_t)l * D.imgb);
+        uint4* dst = (uint4*)L8;
+        const int nq = (int)(Ly.stat / 16);
+#pragma unroll 4
+        for (int i = tid; i < nq; i += kPThreads) dst[i] = src[i];
     }
-    for (int q = tid; q < nb; q += kPThreads) {
-        const int64_t gq = (int64_t)l * D.NB + q;
-        bg[q] = D.bg[gq];
-        bal[q] = D.bal[gq];
-    }
-    for (int r = tid; r < nl; r += kPThreads) {
-        gC[r] = E.gC[lo + r];
-        prow[r] = E.perm[lo + r];
-    }
+    const int64_t xb = (int64_t)l * NX;
     const double* hsrc = E.h + (int64_t)(P.step0 & 1) * K * E.nbr;
-    for (int i = tid; i < nb * kPB; i += kPThreads) {
-        const int q = i >> 4, c = i & 15;
-        h[i] = c < nvc ? hsrc[(int64_t)(case0 + c) * E.nbr + D.bglob[(int64_t)l * D.NB + q]] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kPHItems; ++k) {
+        const int i = tid + k * kPThreads, q = i >> 4, c = i & 15;
+        if (q < nb) h[i] = c < nvc ? hsrc[(int64_t)(case0 + c) * E.nbr + D.bglob[(int64_t)l * D.NB + q]] : 0.0;
     }
     for (int i = tid; i < NLp * kPB; i += kPThreads) {  // rows beyond the leaf stay zero (product input)
         const int r = i >> 4, c = i & 15;
@@ -430,17 +483,9 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     int hbft[kPHItems], hlost[kPHItems];
 #pragma unroll
     for (int k = 0; k < kPHItems; ++k) {
-        const int i = tid + k * kPThreads, q = i >> 4, c = i & 15;
-        hbft[k] = 0;
-        hlost[k] = 0x7fffffff;
-        if (q < nb) {
-            const int64_t gq = (int64_t)l * D.NB + q;
-            hbft[k] = D.bf[gq] | (D.bt[gq] << 16);
-            if (c < nvc)
-                for (int j = 0; j < E.loss_cnt[case0 + c]; ++j)
-                    if (E.loss_br[(case0 + c) * R + j] == D.bglob[gq])
-                        hlost[k] = min(hlost[k], E.loss_step[(case0 + c) * R + j]);
-        }
+        const int i = tid + k * kPThreads, q = i >> 4;
+        hbft[k] = q < nb ? D.hbft[(int64_t)l * D.NB + q] : 0;
+        hlost[k] = q < nb ? D.hlost[(int64_t)tw * D.NB * kPB + i] : 0x7fffffff;
     }
     // the thread's own-row items of the right-hand side: range of incident branches (first | count << 16)
     int rinc[kPRowItems];
@@ -940,6 +985,27 @@ hipError_t launch_panel_mfrag(const PanelDev& D, hipStream_t s)
 {
     if (D.nc <= 0 || D.NT <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_panel_mfrag, dim3(D.T, D.NT), dim3(256), 0, s, D);
+    return hipGetLastError();
+}
+
+// Each leaf's image of its tables (block l; the layout of the context's precision path).
+template <typename TB, bool MIXED>
+__global__ void k_panel_image(PanelDev D, EmtDev E, HierDev H, int R)
+{
+    const PanelLayout Ly = panel_layout<TB, MIXED>(D, R);
+    panel_fill_static<TB, MIXED>(D, E, H, Ly, D.img + (int64_t)blockIdx.x * D.imgb, blockIdx.x, threadIdx.x, blockDim.x);
+}
+
+size_t panel_image_bytes(const PanelDev& D, int R, int prec)
+{
+    const size_t b = prec == HINV_FP64 ? panel_layout<double, false>(D, R).stat : panel_layout<float, true>(D, R).stat;
+    return (b + 255) / 256 * 256;
+}
+
+hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev& H, int R, int prec, hipStream_t s)
+{
+    if (prec == HINV_FP64) hipLaunchKernelGGL((k_panel_image<double, false>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
+    else hipLaunchKernelGGL((k_panel_image<float, true>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
     return hipGetLastError();
 }
 
