@@ -16,7 +16,8 @@ What is computed, and where the paper defines it:
   explicit inverse built from G X = I.  ``sparse_solver`` is a library sparse
   direct solve (SuperLU) used where the dense inverse does not fit.
 * ``assemble_G3``: the three-phase G (each bus three rows, Section III.A)
-  with the mutual inductance of a line between its phases.
+  with the mutual inductance of a line between its phases; ``emt_run3`` the
+  time loop of Eq. (1) on it, with 3x3 line companions.
 * ``paper_inverse``: the paper's approximate hierarchical inverse G~^{-1}
   (Section III.A-B, Eq. (3)-(8), Algorithm 1): leaves inverted directly, every
   internal node's diagonal blocks are its children's approximate inverses and
@@ -34,7 +35,12 @@ Readings where the paper is silent (listed in the design notes as well):
     t = 0, i.e. the shunt history at step 1 is -i_in(0);
   - a branch lost at step s carries no current from step s on: it is absent
     from G_s and its history is zero; capacitor histories are untouched;
-  - sources are amp*sin(2*pi*f*t + phase), t_n = n*dt.
+  - sources are amp*sin(2*pi*f*t + phase), t_n = n*dt;
+  - three-phase networks: every line has the same ratio of mutual to self
+    inductance between its phases (a transposed line), shunts are per phase
+    to ground, a source drives phase p of its bus with its phase plus
+    shift[p] (balanced by default: 0, -120, +120 degrees), and a lost line
+    loses all three phases.
 
 Parity unpinned: nothing here.  Every function is pinned by the
 ``tests/test_oracle_*.py`` checks against closed forms, an independent
@@ -172,28 +178,113 @@ class _LU:
         return x
 
 
-def assemble_G3(net, mutual: float) -> np.ndarray:
+def line_matrices3(net, mutual: float):
+    """Per line e, the 3x3 series impedance of its trapezoidal companion and what follows from it.
+
+    Line e is a three-phase series R-L: resistance R[e] per phase, self inductance L[e] and mutual
+    inductance mutual * L[e] between any two phases, L_e = L[e] ((1 - mutual) I + mutual J), J the
+    all-ones matrix.  The trapezoidal rule applied to R i + L_e di/dt = v over one step gives
+    (R I + (2/dt) L_e) i^n = v^n + v^{n-1} + ((2/dt) L_e - R I) i^{n-1}, so with
+    Y_e = (R I + (2/dt) L_e)^{-1} (a library 3x3 inverse) and A_e = Y_e ((2/dt) L_e - R I):
+    i^n = Y_e v^n + h^n and h^{n+1} = Y_e v^n + A_e i^n.  Returns (Y, A), each (n_branch, 3, 3).
+    """
+    J = np.ones((3, 3))
+    Y = np.empty((net.n_branch, 3, 3))
+    A = np.empty((net.n_branch, 3, 3))
+    for e in range(net.n_branch):
+        Le = net.L[e] * ((1.0 - mutual) * np.eye(3) + mutual * J)
+        Y[e] = inverse(net.R[e] * np.eye(3) + (2.0 / net.dt) * Le)
+        A[e] = Y[e] @ ((2.0 / net.dt) * Le - net.R[e] * np.eye(3))
+    return Y, A
+
+
+def assemble_G3(net, mutual: float, alive: Optional[np.ndarray] = None) -> np.ndarray:
     """Dense three-phase nodal conductance matrix (rows 3a + p; Section III.A, each bus has three phases).
 
-    Branch e is a three-phase series R-L: resistance R[e] per phase, self inductance L[e] and mutual
-    inductance mutual * L[e] between any two phases.  Its trapezoidal companion is the 3x3 admittance
-    Y_e = (R I + (2/dt) L_e)^{-1} (one library inverse of the 3x3 matrix), entered as the single-phase
-    conductance is: +Y_e on the two buses' diagonal blocks, -Y_e between them.  Shunt 2C/dt per phase.
+    Line e's companion admittance Y_e (``line_matrices3``) is entered as the single-phase conductance
+    is: +Y_e on the two buses' diagonal blocks, -Y_e between them; a lost line (alive[e] false) enters
+    nothing.  Shunt 2C/dt per phase.
     """
     n = net.n_bus
     G = np.zeros((3 * n, 3 * n))
     for a in range(n):
         G[3 * a:3 * a + 3, 3 * a:3 * a + 3] += 2.0 * net.C[a] / net.dt * np.eye(3)
-    J = np.ones((3, 3))
+    Ys, _ = line_matrices3(net, mutual)
     for e in range(net.n_branch):
-        Le = net.L[e] * ((1.0 - mutual) * np.eye(3) + mutual * J)
-        Y = inverse(net.R[e] * np.eye(3) + (2.0 / net.dt) * Le)
+        if alive is not None and not alive[e]:
+            continue
+        Y = Ys[e]
         a, b = int(net.frm[e]), int(net.to[e])
         G[3 * a:3 * a + 3, 3 * a:3 * a + 3] += Y
         G[3 * b:3 * b + 3, 3 * b:3 * b + 3] += Y
         G[3 * a:3 * a + 3, 3 * b:3 * b + 3] -= Y
         G[3 * b:3 * b + 3, 3 * a:3 * a + 3] -= Y
     return G
+
+
+BALANCED = (0.0, -2.0 * np.pi / 3.0, 2.0 * np.pi / 3.0)
+
+
+def source_current3(net, t: float, shift=BALANCED) -> np.ndarray:
+    """Three-phase injections (n_bus, 3): source q drives phase p of its bus with
+    amp*sin(2*pi*f*t + phase + shift[p]); the default shift is a balanced (positive-sequence) set."""
+    out = np.zeros((net.n_bus, 3))
+    for p in range(3):
+        val = net.src_amp * np.sin(2.0 * np.pi * net.freq * t + net.src_phase + shift[p])
+        out[:, p] = np.bincount(net.src_bus, weights=val, minlength=net.n_bus)
+    return out
+
+
+def emt_run3(net, n_steps: int, mutual: float, loss_steps: Sequence[int] = (), loss_branches: Sequence[int] = (),
+             solver: str = "lu", shift=BALANCED, record_b: bool = False):
+    """Node voltages of the three-phase trapezoidal EMT time loop (Eq. (1) with three rows per bus).
+
+    Same loop as ``emt_run`` with every quantity a 3-vector per bus or line: the line companions are
+    3x3 (``line_matrices3``), shunts are per phase, sources per ``source_current3``.  A line lost at
+    step s loses all three phases: it is absent from G_s and its history is zero from step s on.
+    Returns (V, B) with V[k] (3 n_bus,) the voltages at step k + 1 in row order 3a + p.
+    solver: "lu" (dense LU each new G) or "inv" (explicit inverse times the current vector).
+    """
+    n, dt = net.n_bus, net.dt
+    fr, to = net.frm.astype(np.int64), net.to.astype(np.int64)
+    Y, A = line_matrices3(net, mutual)
+    gC = (2.0 * net.C / dt)[:, None]
+    dead_from = np.full(net.n_branch, np.iinfo(np.int64).max, np.int64)
+    for s, e in zip(loss_steps, loss_branches):
+        dead_from[int(e)] = min(dead_from[int(e)], int(s))
+    V = np.zeros((n_steps, 3 * n))
+    B = np.zeros((n_steps, 3 * n)) if record_b else None
+    h = np.zeros((net.n_branch, 3))                   # line history currents, per phase
+    hC = -source_current3(net, 0.0, shift)            # KCL-consistent start, per phase
+    alive_prev, apply = None, None
+    for step in range(1, n_steps + 1):
+        alive = dead_from > step
+        if alive_prev is None or not np.array_equal(alive, alive_prev):
+            G = assemble_G3(net, mutual, alive)
+            if solver == "inv":
+                Ginv = inverse(G)
+                apply = lambda x, M=Ginv: matvec(M, x)
+            elif solver == "lu":
+                apply = _LU(G)
+            else:
+                raise ValueError(solver)
+            alive_prev = alive
+        h = np.where(alive[:, None], h, 0.0)
+        inj = np.zeros((n, 3))
+        np.add.at(inj, fr, h)
+        np.add.at(inj, to, -h)
+        b = source_current3(net, step * dt, shift) - inj - hC
+        v = apply(b.ravel()).reshape(n, 3)
+        vft = v[fr] - v[to]
+        yv = np.einsum("epq,eq->ep", Y, vft)
+        i = yv + h                                     # line currents at step n
+        h = np.where(alive[:, None], yv + np.einsum("epq,eq->ep", A, i), 0.0)
+        iC = gC * v + hC
+        hC = -gC * v - iC
+        V[step - 1] = v.ravel()
+        if B is not None:
+            B[step - 1] = b.ravel()
+    return V, B
 
 
 def paper_inverse(G: np.ndarray, parent: Sequence[int], bus_leaf: Sequence[int]) -> np.ndarray:

@@ -393,6 +393,142 @@ def test_G3_two_bus_line_sequence_eigenvalues():
 
 
 # --------------------------------------------------------------------------
+# Three-phase time loop (3x3 line companions, Section III.A's three rows per bus)
+# --------------------------------------------------------------------------
+
+def _shifted(net, **kw):
+    import dataclasses
+    return dataclasses.replace(net, **kw)
+
+
+def test_three_phase_without_mutual_is_three_single_phase_runs():
+    """mutual = 0: phase p is the single-phase network driven by the sources shifted by shift[p]; the
+    lost line is lost in every phase."""
+    net = cases.small_network(8, 12, seed=5)
+    V3, _ = oracle.emt_run3(net, 300, 0.0, loss_steps=[137], loss_branches=[4])
+    for p in range(3):
+        net_p = _shifted(net, src_phase=net.src_phase + oracle.BALANCED[p])
+        V1, _ = oracle.emt_run(net_p, 300, loss_steps=[137], loss_branches=[4], solver="lu")
+        assert np.abs(V3[:, p::3] - V1).max() <= 1e-11 * np.abs(V1).max()
+
+
+@pytest.mark.parametrize("n_bus,n_branch,loss", [(2, 1, None), (7, 10, (120, 3))])
+def test_three_phase_sequence_decoupling(n_bus, n_branch, loss):
+    """Lines with mutual inductance mu L between phases: a zero-sequence drive (equal currents in the
+    three phases) sees the inductance L (1 + 2 mu) in every phase, a positive- or negative-sequence drive
+    (currents summing to zero) sees L (1 - mu).  Each is a single-phase run with that inductance; on the
+    two-bus line and on a meshed network with a line lost mid-run."""
+    mu = 0.3
+    if n_bus == 2:
+        net = _net_from(2, [0], [1], [0.7], [2e-3], [3e-6, 5e-6], [0], [1.3], [0.4], 5e-5)
+    else:
+        net = cases.small_network(n_bus, n_branch, seed=11)
+    kw = dict(loss_steps=[loss[0]], loss_branches=[loss[1]]) if loss else {}
+    zero = (0.0, 0.0, 0.0)
+    negative = (0.0, 2.0 * np.pi / 3.0, -2.0 * np.pi / 3.0)
+    for shift, ratio in ((zero, 1 + 2 * mu), (oracle.BALANCED, 1 - mu), (negative, 1 - mu)):
+        V3, _ = oracle.emt_run3(net, 400, mu, shift=shift, **kw)
+        for p in range(3):
+            net_p = _shifted(net, L=net.L * ratio, src_phase=net.src_phase + shift[p])
+            V1, _ = oracle.emt_run(net_p, 400, solver="lu", **kw)
+            assert np.abs(V3[:, p::3] - V1).max() <= 1e-11 * np.abs(V1).max(), (shift, p)
+    # and the modes really differ (the check is not vacuous)
+    Vz, _ = oracle.emt_run3(net, 400, mu, shift=zero, **kw)
+    Vz0, _ = oracle.emt_run3(net, 400, 0.0, shift=zero, **kw)
+    assert np.abs(Vz - Vz0).max() > 1e-3 * np.abs(Vz0).max()
+
+
+def test_three_phase_charge_balance_across_loss():
+    """Summing KCL over all buses, phase by phase (lines only move charge between buses):
+    (2/dt) sum_a C_a (v_ap^n - v_ap^{n-1}) = sum_a (i_in,ap^n + i_in,ap^{n-1}), across a line loss."""
+    net = cases.net_ring_fine(1, 1)
+    n_steps = 300
+    V, _ = oracle.emt_run3(net, n_steps, cases.MUTUAL_RATIO, loss_steps=[120], loss_branches=[40], solver="inv")
+    Vp = np.vstack([np.zeros(3 * net.n_bus), V])
+    t = np.arange(0, n_steps + 1) * net.dt
+    u = np.array([oracle.source_current3(net, tt).sum(0) for tt in t])       # (steps + 1, 3)
+    for p in range(3):
+        d = (Vp[1:, p::3] - Vp[:-1, p::3]) * net.C
+        lhs = (2 / net.dt) * d.sum(1)
+        rhs = u[1:, p] + u[:-1, p]
+        scale = (2 / net.dt) * np.abs(d).sum(1).max() + np.abs(rhs).max()
+        assert np.all(np.abs(lhs - rhs) <= 1e-9 * scale)
+
+
+def _state_space_run3(net, mu, n_steps, shift, loss_steps=(), loss_branches=()):
+    """Independent check: the trapezoidal (Tustin) rule on the state (3 n bus voltages, 3 m line
+    currents): C_a dv_a/dt = u_a - sum_e A[a,e] i_e per phase; L_e di_e/dt = v_from - v_to - R_e i_e
+    with the 3x3 inductance matrix L_e = L[e] ((1 - mu) I + mu J).  A lost line's currents are held at
+    zero from its loss step on."""
+    n, m, dt = net.n_bus, net.n_branch, net.dt
+    N, M3 = 3 * n, 3 * m
+    Ainc = np.zeros((N, M3))
+    for e in range(m):
+        for p in range(3):
+            Ainc[3 * net.frm[e] + p, 3 * e + p] = 1.0
+            Ainc[3 * net.to[e] + p, 3 * e + p] = -1.0
+    Linv = np.zeros((M3, M3))
+    J = np.ones((3, 3))
+    for e in range(m):
+        Linv[3 * e:3 * e + 3, 3 * e:3 * e + 3] = np.linalg.inv(net.L[e] * ((1 - mu) * np.eye(3) + mu * J))
+    Rd = np.diag(np.repeat(net.R, 3))
+    Cd = np.repeat(net.C, 3)
+    dead_from = np.full(m, 1 << 60)
+    for s, e in zip(loss_steps, loss_branches):
+        dead_from[e] = s
+
+    def jac(step):
+        alive = np.repeat((dead_from > step).astype(float), 3)
+        K = np.zeros((N + M3, N + M3))
+        K[:N, N:] = -(Ainc * alive) / Cd[:, None]
+        K[N:, :N] = (Linv @ Ainc.T) * alive[:, None]
+        K[N:, N:] = -(Linv @ Rd) * alive[:, None]
+        return K, alive
+
+    def src(step):
+        u = np.zeros(N + M3)
+        u[:N] = oracle.source_current3(net, step * dt, shift).ravel() / Cd
+        return u
+
+    x = np.zeros(N + M3)
+    out = np.zeros((n_steps, N))
+    Kp, _ = jac(0)
+    for step in range(1, n_steps + 1):
+        K, alive = jac(step)
+        rhs = x + dt / 2 * (Kp @ x + src(step - 1) + src(step))
+        Mx = np.eye(N + M3) - dt / 2 * K
+        dead = np.where(alive == 0)[0] + N
+        Mx[dead, :] = 0.0
+        Mx[dead, dead] = 1.0
+        rhs[dead] = 0.0
+        x = np.linalg.solve(Mx, rhs)
+        out[step - 1] = x[:N]
+        Kp = K
+    return out
+
+
+def test_three_phase_matches_state_space_trapezoid_unbalanced():
+    """Unbalanced drive (phase shifts 0, -1.9, 2.6 rad, so every sequence is excited), mutual 0.3, a
+    line lost at step 150: the nodal loop with 3x3 companions against the state-space Tustin rule."""
+    net = cases.small_network(7, 10, seed=3)
+    shift = (0.0, -1.9, 2.6)
+    V, _ = oracle.emt_run3(net, 400, 0.3, loss_steps=[150], loss_branches=[2], shift=shift)
+    ref = _state_space_run3(net, 0.3, 400, shift, loss_steps=[150], loss_branches=[2])
+    assert np.abs(V - ref).max() <= 1e-9 * np.abs(ref).max()
+    V0, _ = oracle.emt_run3(net, 400, 0.3, shift=shift)
+    assert np.abs(V0 - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+def test_three_phase_kcl_residual_every_step():
+    net = cases.small_network(9, 14, seed=7)
+    V, B = oracle.emt_run3(net, 200, 0.3, loss_steps=[80], loss_branches=[5], record_b=True)
+    for lo, hi, alive in ((0, 79, None), (79, 200, np.arange(net.n_branch) != 5)):
+        G3 = oracle.assemble_G3(net, 0.3, alive)
+        r = B[lo:hi] - V[lo:hi] @ G3.T
+        assert np.abs(r).max() <= 1e-9 * np.abs(G3).max() * np.abs(V).max()
+
+
+# --------------------------------------------------------------------------
 # Faults switched in the time loop: memoryless conductances (Section IV.A's
 # fault-on stage, the Section V.C scenario)
 # --------------------------------------------------------------------------
