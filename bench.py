@@ -47,24 +47,31 @@ PRE_ROLL = 5000          # end of the contingency batch's loss window
 HORIZON = 8000           # steps of every contingency case
 N_CASES = 256
 
-# HBM traffic of the headline kernel per launch, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE,
-# each scaled by what the counter reads for a copy of known size).  Valid only while the kernel's sources
-# hash to the profiled ones and the launch carries the profiled step count.
-PANEL_TRAFFIC = None
+# HBM traffic of the FP64 panel kernel per launch, from two rocprofv3 --pmc passes over
+# `bench.py --gpus 1 --steps 20 --warmup 5 --no-single --no-tune --no-accuracy --copy-probe-mb 512`
+# (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch).  A 512 MiB device copy read 262,156 KiB of
+# FETCH_SIZE and 524,288 KiB of WRITE_SIZE, so FETCH is scaled by 2.0 and WRITE by 1.0.  Keyed by the
+# launch's step count: the 20-step launch of that command, and the steady 500-step launches of its
+# pre-roll (steps 2001-5000).  Valid only while the kernel's sources hash to the profiled ones.
+PANEL_TRAFFIC = {"sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "f58eb33c3c0051bd",
+                 "bytes": {20: 123932672, 500: 1705242556}}
 
 
 def traffic_bytes(rec, steps_per_launch):
-    if rec is None or steps_per_launch != rec["launch_steps"]:
+    if rec is None or steps_per_launch not in rec["bytes"]:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
         with open(os.path.join(ROOT, "paper_2105_10661_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return rec["bytes"] if h.hexdigest()[:16] == rec["sha256_16"] else None
+    return rec["bytes"][steps_per_launch] if h.hexdigest()[:16] == rec["sha256_16"] else None
 
 
-def run_region(torch, emt, pre, steps, chunk):
-    """Untimed: `pre` steps.  Timed: `steps` steps in launches of at most `chunk` steps, each
+def run_region(torch, emt, pre, warm, steps, chunk):
+    """Untimed: `pre` steps, synchronised, then `warm` warm-up steps left in flight so that the timed
+    launches queue behind them (everything the host prepares for the timed window is made before the
+    warm-up is enqueued, so the first timed launch is submitted while the GPU is still busy instead of
+    opening the window on an idle GPU).  Timed: `steps` steps in launches of at most `chunk` steps, each
     bracketed by HIP events on the launch stream, with the kernel's GPU wall-clock stamp after every
     step.  Returns the region time, the launch sizes and durations and the per-step latencies (stamp
     differences inside each launch)."""
@@ -74,17 +81,25 @@ def run_region(torch, emt, pre, steps, chunk):
         k = min(chunk, pre - done)
         emt.step(k, record_v=False)
         done += k
-    torch.cuda.synchronize()
     sizes = [min(chunk, steps - i) for i in range(0, steps, chunk)]
     clk = torch.zeros(sum(sizes), dtype=torch.int64, device="cuda")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sizes]
+    views = []
     off = 0
-    for (e0, e1), k in zip(ev, sizes):
-        emt.set_step_clock(clk[off:off + k])      # host-side bookkeeping, outside the bracket
+    for k in sizes:
+        views.append(clk[off:off + k])
+        off += k
+    torch.cuda.synchronize()
+    done = 0
+    while done < warm:
+        k = min(chunk, warm - done)
+        emt.step(k, record_v=False)
+        done += k
+    for (e0, e1), k, c in zip(ev, sizes, views):
+        emt.set_step_clock(c)      # host-side bookkeeping, outside the bracket
         e0.record(s)
         emt.step(k, record_v=False)
         e1.record(s)
-        off += k
     torch.cuda.synchronize()
     emt.set_step_clock(None)
     launch_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
@@ -441,7 +456,6 @@ def contingency_batch(hinv, torch, args, khz):
     from paper_2105_10661_amd import cases
     base, bcases = cases.cases_c4(n_cases=N_CASES, n_steps=HORIZON)
     losses = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
-    pre = PRE_ROLL + args.warmup
     paths = {"panel_fp64": ("panel", "fp64", False, 0, 1e-9),
              "panel_mixed": ("panel", "fp32", True, args.max_refine, args.rel_tol),
              "per_case_fp64": ("fused", "fp64", False, 0, 1e-9),
@@ -450,8 +464,8 @@ def contingency_batch(hinv, torch, args, khz):
     for name, (eng, prec, warm, mr, tol) in paths.items():
         emt = hinv.EMT(base, N_CASES, losses=losses, prec=prec, max_refine=mr, rel_tol=tol, max_mod_rank=1,
                        warm_start=warm, kernel_mode=eng)
-        region_ms, sizes, launch_ms, clk = run_region(torch, emt, pre, args.steps, args.chunk)
-        table[name] = summarize(emt, hinv, N_CASES, pre + args.steps, region_ms, args.steps, clk, sizes, khz,
+        region_ms, sizes, launch_ms, clk = run_region(torch, emt, PRE_ROLL, args.warmup, args.steps, args.chunk)
+        table[name] = summarize(emt, hinv, N_CASES, PRE_ROLL + args.warmup + args.steps, region_ms, args.steps, clk, sizes, khz,
                                 prec != "fp64")
         table[name].update(engine=eng, precision=prec if prec == "fp64" else f"{prec} apply + fp64 refinement",
                            corrections=mr)
@@ -644,6 +658,7 @@ def main():
     peak = MFMA_PEAK_TFLOPS[prec_h]
     kname = "k_emt_panel<double, false, false>" if prec_h == "fp64" else "k_emt_panel<float, true, true>"
     full = [m for k, m in zip(sizes_l, launch_ms) if k == args.chunk]
+    launch_steps = args.chunk if full else sizes_l[0]
     two = {"fp64": {"per_case": table["per_case_fp64"]["solves_per_s"], "panel": table["panel_fp64"]["solves_per_s"]},
            "mixed": {"per_case": table["per_case_mixed"]["solves_per_s"],
                      "panel": table["panel_mixed"]["solves_per_s"]}}
@@ -667,7 +682,7 @@ def main():
                    "timed_window": f"steps {PRE_ROLL + args.warmup + 1}..{PRE_ROLL + args.warmup + args.steps} "
                                    f"(untimed pre-roll to step {PRE_ROLL}, then {args.warmup} warm-up steps): every "
                                    "case's line-loss correction is active",
-                   "headline_path": head, "launch_steps": args.chunk},
+                   "headline_path": head, "launch_steps": launch_steps},
         "p50_step_us": hp["p50_step_us"],
         "p99_step_us": hp["p99_step_us"],
         "latency_note": "GPU wall-clock stamp after each step of workgroup 0; one step advances all 256 cases",
@@ -688,15 +703,17 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5),
-            "traffic": traffic_bytes(PANEL_TRAFFIC, args.chunk) if head == "panel_fp64" else None,
+            "traffic": traffic_bytes(PANEL_TRAFFIC, launch_steps) if head == "panel_fp64" else None,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flops_per_step": 2.0 * entries * N_CASES * hp["applies_per_step"],
             "launch_ms_mean": round(float(np.mean(full or launch_ms)), 4),
-            "launch_steps": args.chunk if full else sizes_l[0],
+            "launch_steps": launch_steps,
         },
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    hinv.close_all()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -28,8 +28,9 @@
  * Sherman-Morrison-Woodbury low-rank correction of the stored inverse
  * (hinv_modify_line, and the line losses of the EMT time loop) or as a local
  * rebuild of the stored inverse itself (hinv_update_line, Algorithm 2 made
- * exact).  emt_network3_csr gives the three-phase G of a network; chol_* is a
- * sparse Cholesky network solution kept as a comparison baseline.
+ * exact).  emt_network3_csr gives the three-phase G of a network and
+ * emt3_create its time loop; chol_* is a sparse Cholesky network solution kept
+ * as a comparison baseline.
  */
 #ifndef HINV_H
 #define HINV_H
@@ -294,10 +295,37 @@ hinv_status emt_network_csr(const emt_network* net, int32_t* row_ptr, int32_t* c
  * shunt 2C/dt on each phase.  0 <= mutual < 0.5 (SPD), else HINV_E_INVALID.
  * row_ptr [3 n_bus + 1]; otherwise as emt_network_csr.  For hinv_build, a
  * three-phase tree maps all three rows of a bus to the bus's leaf (a leaf then
- * holds at most HINV_MAX_LEAF / 3 buses).  The EMT time loop (emt_*) takes
- * single-phase networks only. */
+ * holds at most HINV_MAX_LEAF / 3 buses).  emt3_create runs the EMT time loop
+ * on this G. */
 hinv_status emt_network3_csr(const emt_network* net, double mutual, int32_t* row_ptr, int32_t* col_idx,
                              double* val, int64_t* nnz);
+
+/* Three-phase EMT time loop (Section II, Eq. (1), on the three-phase network
+ * of Section III.A): G is emt_network3_csr's, rows 3a + p of bus a's phases
+ * p = 0..2 in every vector and record.  Line e's trapezoidal companion is the
+ * 3x3 admittance Y = (R I + (2/dt) L_e)^{-1}, L_e = L[e]((1 - mutual) I +
+ * mutual J): its phase currents are i^n = Y v_ft^n + h^n with the history
+ * h^{n+1} = Y v_ft^n + A i^n, A = Y ((2/dt) L_e - R I), v_ft the three phase
+ * differences between its buses; shunt C[a] and its trapezoidal history per
+ * phase.  Source q drives phase p of its bus with amp*sin(2 pi f t + phase +
+ * shift[p]) (host [3]; NULL: 0, -2pi/3, +2pi/3, a balanced set).  tree is the
+ * network's bus-level tree; each leaf then owns 3x its buses as rows (at most
+ * HINV_MAX_LEAF).  loss_branch of the cases names lines: a lost line loses its
+ * three phases, held as three changes w_p = e_from,p - e_to,p coupled by D =
+ * -Y (G <- G + W D W^T, the capacitance then takes D^{-1} = -Z), so a case
+ * holds at most max_mod_rank / 3 line losses (RANK_LIMIT beyond).  Steps on
+ * the per-kernel engine (kernel_mode 0 or 1, else HINV_E_INVALID), in FP64
+ * or with FP32/BF16/FP8 storage and FP64 refinement.  The handle takes
+ * emt_step, emt_lose_line (line index), emt_sync_status, emt_get_step,
+ * emt_get_stats and emt_destroy as a single-phase one does; emt_update_line
+ * and serve_attach refuse it with HINV_E_INVALID.  Other errors as
+ * emt_workspace_size / emt_create, plus HINV_E_INVALID for mutual outside
+ * [0, 0.5) or a non-finite shift. */
+hinv_status emt3_workspace_size(const emt_network* net, double mutual, const double* shift, const hinv_tree* tree,
+                                const hinv_options* opt, const emt_cases* cases, size_t* bytes);
+hinv_status emt3_create(const emt_network* net, double mutual, const double* shift, const hinv_tree* tree,
+                        const hinv_options* opt, const emt_cases* cases, void* d_ws, size_t ws_bytes, void* stream,
+                        emt_handle* out);
 
 hinv_status emt_workspace_size(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
                                const emt_cases* cases, size_t* bytes);

@@ -1230,6 +1230,20 @@ struct emt_ctx {
     int level_nx_cap = 0;
     std::vector<int> lw_nx, loptr, locl, lorow, losoff, lxrow, llpa, llpb;
     LevelDev LD{};
+    // three-phase networks (emt3_create): rows are bus phases (row 3a + p of the caller's order), branch
+    // 3l + p is phase p of line l; per line the 3x3 companion admittance Y, history weight A = I - 2 R Y
+    // and impedance Z = Y^{-1} (row-major)
+    int ph = 1;
+    int n_lines = 0;
+    std::vector<double> y3, a3, z3;
+    double* m_d3 = nullptr;
+    double* m_dinv3 = nullptr;
+};
+
+// Three-phase network parameters of emt3_create.
+struct Phase3 {
+    double mu;           // mutual / self inductance of every line
+    double shift[3];     // source phase shift of each phase
 };
 
 namespace {
@@ -1384,6 +1398,16 @@ void carve_emt(emt_ctx& c, Arena& A, int n_src)
     c.d_rec = A.take<RecParams>(1);
     c.d_applies = A.take<unsigned long long>(K);
     c.gscr = A.take<double>(4 * (int64_t)n * K);
+    E.Y3 = E.A3 = nullptr;
+    if (c.ph == 3) {
+        E.Y3 = A.take<double>(9 * (int64_t)c.n_lines);
+        E.A3 = A.take<double>(9 * (int64_t)c.n_lines);
+        c.m_d3 = A.take<double>((int64_t)K * R * 3);
+        c.m_dinv3 = A.take<double>((int64_t)K * R * 3);
+        c.hc.M.grp3 = 1;
+        c.hc.M.d3 = c.m_d3;
+        c.hc.M.dinv3 = c.m_dinv3;
+    }
 }
 
 // Network data in the new bus order (kept on the host for uploads and the team plan).
@@ -1427,6 +1451,69 @@ void prepare_network(emt_ctx& c, const emt_network* net)
     }
 }
 
+// Three-phase network data in the new row order.  Line l is a transposed R-L: per phase R, self
+// inductance L and mutual inductance mu L between any two phases, so its trapezoidal impedance is
+// Z = al I + be J (al = R + (2L/dt)(1 - mu), be = (2L/dt) mu, J all ones) and its companion admittance
+// Y = Z^{-1} = I / al - J be / (al (al + 3 be)), the values assemble_csr3 puts into G.  The history
+// weight Y ((2/dt) L_e - R I) equals Y (Z - 2 R I) = I - 2 R Y.  Source q drives phase p of its bus with
+// its phase plus shift[p].
+void prepare_network3(emt_ctx& c, const emt_network* net, const Phase3& p3)
+{
+    const Plan& P = c.hc.P;
+    const int n = c.n, nl = c.n_lines, nbr = c.nbr;
+    c.fr_p.assign(nbr, 0); c.to_p.assign(nbr, 0); c.g.assign(nbr, 0.0); c.alpha.assign(nbr, 0.0);
+    c.y3.assign(9 * (size_t)nl, 0.0); c.a3.assign(9 * (size_t)nl, 0.0); c.z3.assign(9 * (size_t)nl, 0.0);
+    c.gC.assign(n, 0.0);
+    c.inc_ptr.assign(n + 1, 0);
+    c.inc_br.assign(2 * (size_t)nbr, 0);
+    for (int l = 0; l < nl; ++l) {
+        const double R = net->R[l], zl = 2.0 * net->L[l] / net->dt;
+        const double al = R + zl * (1.0 - p3.mu), be = zl * p3.mu;
+        const double off = -be / (al * (al + 3.0 * be));
+        const double dia = 1.0 / al + off;
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) {
+                const double y = (p == q) ? dia : off;
+                c.y3[9 * l + 3 * p + q] = y;
+                c.a3[9 * l + 3 * p + q] = (p == q ? 1.0 : 0.0) - 2.0 * R * y;
+                c.z3[9 * l + 3 * p + q] = (p == q ? al : 0.0) + be;
+            }
+        for (int p = 0; p < 3; ++p) {
+            const int e = 3 * l + p;
+            c.fr_p[e] = P.iperm[3 * net->from[l] + p];
+            c.to_p[e] = P.iperm[3 * net->to[l] + p];
+            c.g[e] = dia;
+            c.alpha[e] = 1.0 - 2.0 * R * dia;
+            c.inc_ptr[c.fr_p[e] + 1]++;
+            c.inc_ptr[c.to_p[e] + 1]++;
+        }
+    }
+    for (int r = 0; r < n; ++r) {
+        c.inc_ptr[r + 1] += c.inc_ptr[r];
+        c.gC[r] = 2.0 * net->C[P.perm[r] / 3] / net->dt;
+    }
+    std::vector<int> fill(c.inc_ptr.begin(), c.inc_ptr.end() - 1);
+    for (int e = 0; e < nbr; ++e) {
+        c.inc_br[fill[c.fr_p[e]]++] = e;
+        c.inc_br[fill[c.to_p[e]]++] = e;
+    }
+    const int ns = 3 * net->n_src;
+    c.src_ptr.assign(n + 1, 0);
+    c.samp.assign(ns, 0.0);
+    c.sph.assign(ns, 0.0);
+    for (int q = 0; q < net->n_src; ++q)
+        for (int p = 0; p < 3; ++p) c.src_ptr[P.iperm[3 * net->src_bus[q] + p] + 1]++;
+    for (int r = 0; r < n; ++r) c.src_ptr[r + 1] += c.src_ptr[r];
+    std::vector<int> sf(c.src_ptr.begin(), c.src_ptr.end() - 1);
+    for (int q = 0; q < net->n_src; ++q)
+        for (int p = 0; p < 3; ++p) {
+            const int r = P.iperm[3 * net->src_bus[q] + p];
+            c.samp[sf[r]] = net->amp[q];
+            c.sph[sf[r]] = net->phase[q] + p3.shift[p];
+            sf[r]++;
+        }
+}
+
 bool build_team_plan(emt_ctx& c, int R);
 void carve_team(emt_ctx& c, Arena& A);
 bool build_panel_plan(emt_ctx& c, int R);
@@ -1435,8 +1522,13 @@ bool build_level_plan(emt_ctx& c, int R);
 void carve_level(emt_ctx& c, Arena& A);
 hinv_status upload_level(emt_ctx& c, hipStream_t s);
 
+hinv_status emt_plan3(const emt_network* N, const Phase3& p3, const hinv_tree* T, const hinv_options* o,
+                      const emt_cases* C, emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci,
+                      std::vector<double>& cv, size_t* bytes);
+
 hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_options* o, const emt_cases* C,
-                     emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv, size_t* bytes)
+                     emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci, std::vector<double>& cv, size_t* bytes,
+                     const Phase3* p3 = nullptr)
 {
     hinv_status st = check_network(N);
     if (st != HINV_OK) return st;
@@ -1444,6 +1536,7 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
     if (st != HINV_OK) return st;
     if (o->coupling != HINV_COUPLING_EXACT) return fail(HINV_E_INVALID, "EMT stepping needs coupling = HINV_COUPLING_EXACT");
     c.R = std::max(1, o->max_mod_rank);
+    if (p3) return emt_plan3(N, *p3, T, o, C, c, rp, ci, cv, bytes);
     st = check_cases(C, N->n_branch, o->max_mod_rank, c.losses);
     if (st != HINV_OK) return st;
     c.n = N->n_bus;
@@ -1497,6 +1590,48 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
                     "coupling columns, and tables that fit LDS", kPanelMaxRank);
     if (mode == 2 && !fits) return fail(HINV_E_INVALID, "the one-workgroup-per-case engine needs FP64/FP32 and a case that fits LDS");
     c.engine = (mode >= 1) ? mode : c.team_ok ? 3 : c.panel_ok ? 4 : c.level_ok ? 5 : fits ? 2 : 1;
+    *bytes = A.off + kAlign;
+    return HINV_OK;
+}
+
+// Three-phase plan: G from assemble_csr3 over rows 3a + p, the bus-level tree with every row in its
+// bus's leaf, line losses as groups of three changes (so a case holds max_mod_rank / 3 of them), and
+// the per-kernel engine.
+hinv_status emt_plan3(const emt_network* N, const Phase3& p3, const hinv_tree* T, const hinv_options* o,
+                      const emt_cases* C, emt_ctx& c, std::vector<int>& rp, std::vector<int>& ci,
+                      std::vector<double>& cv, size_t* bytes)
+{
+    if (!(p3.mu >= 0.0 && p3.mu < 0.5)) return fail(HINV_E_INVALID, "mutual ratio %g outside [0, 0.5)", p3.mu);
+    for (int p = 0; p < 3; ++p)
+        if (!isfinite(p3.shift[p])) return fail(HINV_E_INVALID, "phase shift %d is not finite", p);
+    if (o->kernel_mode != 0 && o->kernel_mode != 1)
+        return fail(HINV_E_INVALID, "three-phase networks step on the per-kernel engine (kernel_mode 0 or 1)");
+    if (!T || !T->parent || !T->bus_leaf) return fail(HINV_E_INVALID, "tree is missing");
+    hinv_status st = check_cases(C, N->n_branch, o->max_mod_rank / 3, c.losses);
+    if (st != HINV_OK) return st;
+    c.ph = 3;
+    c.n_lines = N->n_branch;
+    c.n = 3 * N->n_bus;
+    c.nbr = 3 * N->n_branch;
+    c.n_cases = C->n_cases;
+    int total_losses = 0;
+    for (auto& l : c.losses) total_losses += 3 * (int)l.size();
+    assemble_csr3(N, p3.mu, rp, ci, cv);
+    hinv_csr G{c.n, rp.data(), ci.data(), cv.data()};
+    std::vector<int> leaf3(3 * (size_t)N->n_bus);
+    for (int a = 0; a < N->n_bus; ++a)
+        for (int p = 0; p < 3; ++p) leaf3[3 * a + p] = T->bus_leaf[a];
+    const hinv_tree T3{T->n_nodes, T->parent, leaf3.data()};
+    st = make_plan(&G, &T3, c.hc.P);
+    if (st != HINV_OK) return st;
+    c.hc.opt = *o;
+    c.hc.opt.max_nrhs = std::max(std::max(c.n_cases, c.R), std::max(total_losses, 1));
+    prepare_network3(c, N, p3);
+    Arena A;
+    carve_hier(c.hc, A, c.n_cases, c.R, c.hc.opt.max_nrhs);
+    carve_emt(c, A, 3 * N->n_src);
+    c.team_ok = c.panel_ok = c.level_ok = false;
+    c.engine = 1;
     *bytes = A.off + kAlign;
     return HINV_OK;
 }
@@ -2486,21 +2621,53 @@ hinv_status load_case_losses(emt_ctx& c, const std::vector<int>& which, hipStrea
         std::vector<double> dg(R, 0.0);
         std::vector<int> lst(R, INT32_MAX), lbr(R, -1);
         const auto& L = c.losses[k];
-        for (size_t j = 0; j < L.size(); ++j) {
-            const int e = L[j].second;
-            a[j] = c.fr_p[e];
-            b[j] = c.to_p[e];
-            dg[j] = -c.g[e];
-            act[j] = L[j].first;
-            lst[j] = L[j].first;
-            lbr[j] = e;
-            cols.push_back(k * R + (int)j);
-            std::vector<double> w(n, 0.0);
-            w[a[j]] = 1.0;
-            w[b[j]] = -1.0;
-            W.insert(W.end(), w.begin(), w.end());
+        std::vector<double> d3, dinv3;
+        if (c.ph == 3) {
+            // a lost line is three changes, one per phase (w_p = e_from,p - e_to,p), coupled by
+            // D = -Y of the line: G - W Y W^T removes the line's 3x3 companion; D^{-1} = -Z
+            d3.assign(3 * (size_t)R, 0.0);
+            dinv3.assign(3 * (size_t)R, 0.0);
+            for (size_t j = 0; j < L.size(); ++j) {
+                const int l = L[j].second;
+                for (int p = 0; p < 3; ++p) {
+                    const int i = 3 * (int)j + p, e = 3 * l + p;
+                    a[i] = c.fr_p[e];
+                    b[i] = c.to_p[e];
+                    dg[i] = -c.y3[9 * l + 4 * p];
+                    act[i] = lst[i] = L[j].first;
+                    lbr[i] = e;
+                    for (int q = 0; q < 3; ++q) {
+                        d3[3 * i + q] = -c.y3[9 * l + 3 * p + q];
+                        dinv3[3 * i + q] = -c.z3[9 * l + 3 * p + q];
+                    }
+                    cols.push_back(k * R + i);
+                    std::vector<double> w(n, 0.0);
+                    w[a[i]] = 1.0;
+                    w[b[i]] = -1.0;
+                    W.insert(W.end(), w.begin(), w.end());
+                }
+            }
+            HIP_TRY(hipMemcpyAsync(c.m_d3 + (int64_t)k * R * 3, d3.data(), sizeof(double) * 3 * R,
+                                   hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(c.m_dinv3 + (int64_t)k * R * 3, dinv3.data(), sizeof(double) * 3 * R,
+                                   hipMemcpyHostToDevice, s));
+        } else {
+            for (size_t j = 0; j < L.size(); ++j) {
+                const int e = L[j].second;
+                a[j] = c.fr_p[e];
+                b[j] = c.to_p[e];
+                dg[j] = -c.g[e];
+                act[j] = L[j].first;
+                lst[j] = L[j].first;
+                lbr[j] = e;
+                cols.push_back(k * R + (int)j);
+                std::vector<double> w(n, 0.0);
+                w[a[j]] = 1.0;
+                w[b[j]] = -1.0;
+                W.insert(W.end(), w.begin(), w.end());
+            }
         }
-        const int cnt = (int)L.size();
+        const int cnt = c.ph * (int)L.size();
         HIP_TRY(hipMemcpyAsync((void*)(h.m_a + k * R), a.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void*)(h.m_b + k * R), b.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync((void*)(h.m_act + k * R), act.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
@@ -2632,8 +2799,9 @@ hinv_status emt_workspace_size(const emt_network* net, const hinv_tree* tree, co
     return emt_plan(net, tree, opt, cases, *c, rp, ci, cv, bytes);
 }
 
-hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
-                       const emt_cases* cases, void* d_ws, size_t ws_bytes, void* stream, emt_handle* out)
+static hinv_status emt_create_impl(const emt_network* net, const Phase3* p3, const hinv_tree* tree,
+                                   const hinv_options* opt, const emt_cases* cases, void* d_ws, size_t ws_bytes,
+                                   void* stream, emt_handle* out)
 {
     if (!out) return fail(HINV_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -2642,7 +2810,7 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     std::vector<int> rp, ci;
     std::vector<double> cv;
     size_t need = 0;
-    hinv_status st = emt_plan(net, tree, opt, cases, *c, rp, ci, cv, &need);
+    hinv_status st = emt_plan(net, tree, opt, cases, *c, rp, ci, cv, &need, p3);
     if (st != HINV_OK) return st;
     if (!d_ws) return fail(HINV_E_INVALID, "workspace is NULL");
     if (ws_bytes < need) return fail(HINV_E_NO_MEMORY, "workspace has %zu bytes, needs %zu", ws_bytes, need);
@@ -2650,7 +2818,7 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     Arena A;
     A.base = (char*)d_ws;
     carve_hier(c->hc, A, c->n_cases, c->R, c->hc.opt.max_nrhs);
-    carve_emt(*c, A, net->n_src);
+    carve_emt(*c, A, c->ph * net->n_src);
     if (c->team_ok) carve_team(*c, A);
     if (c->panel_ok) carve_panel(*c, A);
     if (c->level_ok) carve_level(*c, A);
@@ -2664,6 +2832,10 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     HIP_TRY(up(E.alpha, c->alpha, s)); HIP_TRY(up(E.gC, c->gC, s));
     HIP_TRY(up(E.inc_ptr, c->inc_ptr, s)); HIP_TRY(up(E.inc_br, c->inc_br, s));
     HIP_TRY(up(E.src_ptr, c->src_ptr, s)); HIP_TRY(up(E.src_amp, c->samp, s)); HIP_TRY(up(E.src_ph, c->sph, s));
+    if (c->ph == 3) {
+        HIP_TRY(up(E.Y3, c->y3, s));
+        HIP_TRY(up(E.A3, c->a3, s));
+    }
     st = build_device(c->hc, s);        // synchronises
     if (st != HINV_OK) return st;
     if (c->team_ok) {
@@ -2691,6 +2863,40 @@ hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv
     c->step = 1;
     *out = c.release();
     return HINV_OK;
+}
+
+hinv_status emt_create(const emt_network* net, const hinv_tree* tree, const hinv_options* opt,
+                       const emt_cases* cases, void* d_ws, size_t ws_bytes, void* stream, emt_handle* out)
+{
+    return emt_create_impl(net, nullptr, tree, opt, cases, d_ws, ws_bytes, stream, out);
+}
+
+static Phase3 phase3_of(double mutual, const double* shift)
+{
+    Phase3 p3{mutual, {0.0, -2.0 * M_PI / 3.0, 2.0 * M_PI / 3.0}};
+    if (shift)
+        for (int p = 0; p < 3; ++p) p3.shift[p] = shift[p];
+    return p3;
+}
+
+hinv_status emt3_workspace_size(const emt_network* net, double mutual, const double* shift, const hinv_tree* tree,
+                                const hinv_options* opt, const emt_cases* cases, size_t* bytes)
+{
+    if (!bytes) return fail(HINV_E_INVALID, "bytes is NULL");
+    std::unique_ptr<emt_ctx> c(new (std::nothrow) emt_ctx);
+    if (!c) return fail(HINV_E_NO_MEMORY, "host allocation failed");
+    std::vector<int> rp, ci;
+    std::vector<double> cv;
+    const Phase3 p3 = phase3_of(mutual, shift);
+    return emt_plan(net, tree, opt, cases, *c, rp, ci, cv, bytes, &p3);
+}
+
+hinv_status emt3_create(const emt_network* net, double mutual, const double* shift, const hinv_tree* tree,
+                        const hinv_options* opt, const emt_cases* cases, void* d_ws, size_t ws_bytes, void* stream,
+                        emt_handle* out)
+{
+    const Phase3 p3 = phase3_of(mutual, shift);
+    return emt_create_impl(net, &p3, tree, opt, cases, d_ws, ws_bytes, stream, out);
 }
 
 hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* d_b_record, void* stream)
@@ -2726,7 +2932,10 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
     launch_set_rec(c.d_rec, RecParams{d_v_record, d_b_record, c.step, n_steps}, s);
     for (int i = 0; i < n_steps; ++i) {
         solve_new_order(c.hc, c.E.b, c.E.v, c.n_cases, 1, c.E.step, s);
-        launch_emt_history(c.E, c.d_rec, s);
+        if (c.ph == 3)
+            launch_emt_history3(c.E, c.d_rec, s);
+        else
+            launch_emt_history(c.E, c.d_rec, s);
     }
     HIP_TRY(hipGetLastError());
     c.step += n_steps;
@@ -2738,11 +2947,11 @@ hinv_status emt_lose_line(emt_handle h, int32_t case_idx, int32_t branch, void* 
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
     emt_ctx& c = *h;
     if (case_idx < 0 || case_idx >= c.n_cases) return fail(HINV_E_INVALID, "case %d out of range", case_idx);
-    if (branch < 0 || branch >= c.nbr) return fail(HINV_E_INVALID, "branch %d out of range", branch);
+    if (branch < 0 || branch >= c.nbr / c.ph) return fail(HINV_E_INVALID, "branch %d out of range", branch);
     auto& L = c.losses[case_idx];
     for (auto& x : L)
         if (x.second == branch) return fail(HINV_E_NO_SUCH_LINE, "branch %d is already lost in case %d", branch, case_idx);
-    if ((int)L.size() >= c.hc.opt.max_mod_rank)
+    if (c.ph * ((int)L.size() + 1) > c.hc.opt.max_mod_rank)
         return fail(HINV_E_RANK_LIMIT, "case %d already has %d losses", case_idx, (int)L.size());
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
@@ -2767,6 +2976,7 @@ hinv_status emt_update_line(emt_handle h, int32_t a, int32_t b, double delta_g, 
 {
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
     emt_ctx& c = *h;
+    if (c.ph == 3) return fail(HINV_E_INVALID, "emt_update_line takes single-phase networks only");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipStreamSynchronize(s));
     LineEdit ed;
@@ -2987,6 +3197,7 @@ hinv_status serve_attach(serve_handle h, emt_handle e, double* d_v_record, int64
     emt_ctx& c = *e;
     if ((int)S.slot.size() >= S.max_slots) return fail(HINV_E_NO_MEMORY, "all %d slots are in use", S.max_slots);
     if (c.n_cases != 1) return fail(HINV_E_INVALID, "a served handle holds exactly one case");
+    if (c.ph != 1) return fail(HINV_E_INVALID, "the serving pool takes single-phase networks only");
     if (c.hc.opt.prec != S.opt.prec || (c.hc.opt.prec != HINV_FP64 && (c.hc.opt.warm_start != 0) != (S.opt.warm_start != 0)))
         return fail(HINV_E_INVALID, "the case's precision / warm start differ from the pool's");
     for (emt_ctx* o : S.owner)

@@ -141,6 +141,12 @@ struct ModDev {
     double* U;              // [n_sets*R*n] u_j = G0^{-1} w_j
     float* U32;             // low-precision copy
     double* Cinv;           // [n_sets*R*R*R]: inverse of the leading r x r capacitance, r = 1..R
+    // Three-phase line changes: changes 3g, 3g+1, 3g+2 of a set are the phases of one line, whose 3x3
+    // coupling D (G <- G + W D W^T, W the three phase-difference vectors) is not diagonal.  Row p of D
+    // and of D^{-1} for change 3g+p (null / 0 for single-phase sets, where D = diag(dg)).
+    int grp3;
+    const double* d3;       // [n_sets*R*3]
+    const double* dinv3;    // [n_sets*R*3]
 };
 
 // EMT network and per-case state (new bus order), kernel argument.
@@ -167,6 +173,10 @@ struct EmtDev {
     double* v;              // [n_cases*n]
     int64_t* step;          // next step to compute
     unsigned int* done;     // block counter for the step advance
+    // three-phase networks: rows are bus phases, branch 3l+p is phase p of line l, whose companion is
+    // the 3x3 admittance Y3[l] with history weight A3[l] (row-major, phase order); null otherwise
+    const double* Y3;       // [nbr/3 * 9]
+    const double* A3;       // [nbr/3 * 9]
 };
 
 // Where emt_step records v and b (device struct, updated per call).
@@ -536,5 +546,6 @@ hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, co
                           hipStream_t s);
 // History update with v_n and assembly of b_{n+1}; records; advances *E.step.
 void launch_emt_history(const EmtDev& E, const RecParams* rec, hipStream_t s);
+void launch_emt_history3(const EmtDev& E, const RecParams* rec, hipStream_t s);
 
 }  // namespace hinv

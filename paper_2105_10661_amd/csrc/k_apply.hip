@@ -223,6 +223,11 @@ void launch_smw_apply(const ModDev& M, int prec, double* V, int nrhs, int set0, 
 // inverted by Gauss-Jordan with partial pivoting into Cinv slot r.  The
 // changed G stays positive definite iff every new change's Schur complement
 // 1 / Cinv_r[r-1][r-1] has the sign of its delta_g (Haynsworth inertia).
+// Three-phase sets (M.grp3) change whole lines: D is block diagonal with the
+// lines' 3x3 blocks, only prefixes ending on a line are formed (the three
+// phases of a line become active together), and the new line keeps G positive
+// definite iff its 3x3 block of Cinv_r (the inverse of its Schur complement)
+// has the inertia of its D block, negative definite for a lost line.
 __global__ void k_smw_capacitance(ModDev M, int* flags)
 {
     const int set = blockIdx.x;
@@ -232,12 +237,17 @@ __global__ void k_smw_capacitance(ModDev M, int* flags)
     double A[kMaxModRank * kMaxModRank];
     double I[kMaxModRank * kMaxModRank];
     for (int r = 1; r <= cnt; ++r) {
+        if (M.grp3 && r % 3 != 0) continue;
         for (int i = 0; i < r; ++i) {
             const int a = M.a[set * R + i], b = M.b[set * R + i];
             for (int j = 0; j < r; ++j) {
                 const double* u = M.U + ((int64_t)set * R + j) * M.n;
                 double v = u[a] - (b >= 0 ? u[b] : 0.0);
-                if (i == j) v += 1.0 / M.dg[set * R + i];
+                if (M.grp3) {
+                    if (i / 3 == j / 3) v += M.dinv3[((int64_t)set * R + i) * 3 + j % 3];
+                } else if (i == j) {
+                    v += 1.0 / M.dg[set * R + i];
+                }
                 A[i * r + j] = v;
                 I[i * r + j] = (i == j) ? 1.0 : 0.0;
             }
@@ -266,6 +276,16 @@ __global__ void k_smw_capacitance(ModDev M, int* flags)
         if (!ok) { atomicOr(flags, kFlagSingular); return; }
         for (int i = 0; i < r; ++i)
             for (int j = 0; j < r; ++j) out[i * R + j] = I[i * r + j];
+        if (M.grp3) {           // -block SPD by its leading minors (a lost line: D negative definite)
+            const double* B = I + (r - 3) * r + (r - 3);
+            const double m1 = -B[0];
+            const double m2 = B[0] * B[r + 1] - B[1] * B[r];
+            const double m3 = -(B[0] * (B[r + 1] * B[2 * r + 2] - B[r + 2] * B[2 * r + 1]) -
+                                B[1] * (B[r] * B[2 * r + 2] - B[r + 2] * B[2 * r]) +
+                                B[2] * (B[r] * B[2 * r + 1] - B[r + 1] * B[2 * r]));
+            if (!(m1 > 0.0 && m2 > 0.0 && m3 > 0.0)) atomicOr(flags, kFlagNotSPD);
+            continue;
+        }
         const double schur_inv = I[(r - 1) * r + (r - 1)];
         if (!((schur_inv > 0.0) == (M.dg[set * R + r - 1] > 0.0))) atomicOr(flags, kFlagNotSPD);
     }
@@ -292,6 +312,17 @@ __global__ __launch_bounds__(kBlock) void k_residual(HierDev H, ModDev M, const 
         for (int j = 0; j < r; ++j) {
             const int a = M.a[set * M.R + j], b = M.b[set * M.R + j];
             if (i != a && i != b) continue;
+            if (M.grp3) {          // row j of the line's 3x3 D times its three phase differences
+                const int g0 = j - j % 3;
+                const double* d = M.d3 + ((int64_t)set * M.R + j) * 3;
+                double dw = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    const int aq = M.a[set * M.R + g0 + q], bq = M.b[set * M.R + g0 + q];
+                    dw += d[q] * (V[c + aq] - (bq >= 0 ? V[c + bq] : 0.0));
+                }
+                acc += (i == a ? 1.0 : -1.0) * dw;
+                continue;
+            }
             const double wv = V[c + a] - (b >= 0 ? V[c + b] : 0.0);
             acc += (i == a ? 1.0 : -1.0) * M.dg[set * M.R + j] * wv;
         }

@@ -116,6 +116,77 @@ void launch_emt_history(const EmtDev& E, const RecParams* rec, hipStream_t s)
     hipLaunchKernelGGL(k_emt_history, dim3((E.n + kBlock - 1) / kBlock, E.n_cases), dim3(kBlock), 0, s, E, rec);
 }
 
+// Three-phase networks (rows are bus phases; branch 3l+p is phase p of line l).  Line l's companion is
+// the 3x3 admittance Y = Y3[l] with history weight A = A3[l]:
+//   i_l^n = Y v_ft^n + h_l^n,   h_l^{n+1} = Y v_ft^n + A i_l^n      (3-vectors, v_ft = v_from - v_to)
+// so the new history of phase p needs the voltages and histories of all three phases of the line.
+// Same threading as k_emt_history: one thread per (row, case); each row recomputes its incident
+// phase-branches' histories in one fixed operation order, so both ends of a line agree bitwise.
+__global__ __launch_bounds__(kBlock) void k_emt_history3(EmtDev E, const RecParams* __restrict__ rec)
+{
+    const int k = blockIdx.y;
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    const int64_t step = *E.step;
+    if (a < E.n) {
+        const int64_t base = (int64_t)k * E.n;
+        const double* v = E.v + base;
+        const double* hcur = E.h + (int64_t)(step & 1) * E.n_cases * E.nbr + (int64_t)k * E.nbr;
+        double* hnext = E.h + (int64_t)((step + 1) & 1) * E.n_cases * E.nbr + (int64_t)k * E.nbr;
+        const double va = v[a];
+        double bn = source_at(E, a, (double)(step + 1) * E.dt);
+        for (int q = E.inc_ptr[a]; q < E.inc_ptr[a + 1]; ++q) {
+            const int e = E.inc_br[q];
+            const int l = e / 3, p = e - 3 * l;
+            double hn = 0.0;
+            if (!lost_by(E, k, e, step + 1)) {
+                const double* Y = E.Y3 + 9 * l;
+                const double* A = E.A3 + 9 * l;
+                double vft[3], il[3];
+                for (int r = 0; r < 3; ++r) vft[r] = v[E.fr[3 * l + r]] - v[E.to[3 * l + r]];
+                double yv = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    double y = 0.0;
+                    for (int c = 0; c < 3; ++c) y = fma(Y[3 * r + c], vft[c], y);
+                    il[r] = y + hcur[3 * l + r];
+                    if (r == p) yv = y;
+                }
+                double ai = 0.0;
+                for (int c = 0; c < 3; ++c) ai = fma(A[3 * p + c], il[c], ai);
+                hn = yv + ai;
+            }
+            bn -= (a == E.fr[e]) ? hn : -hn;
+            if (a == E.fr[e]) hnext[e] = hn;
+        }
+        const double ic = E.gC[a] * va + E.hC[base + a];
+        const double hcn = -E.gC[a] * va - ic;
+        E.hC[base + a] = hcn;
+        bn -= hcn;
+        const int64_t j = step - rec->step0;
+        if (j >= 0 && j < rec->nsteps) {
+            const int64_t o = (j * E.n_cases + k) * (int64_t)E.n + E.perm[a];
+            if (rec->v) rec->v[o] = va;
+            if (rec->b) rec->b[o] = E.b[base + a];
+        }
+        E.b[base + a] = bn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int total = gridDim.x * gridDim.y;
+        const unsigned int prev = atomicAdd(E.done, 1u);
+        if (prev == total - 1) {
+            *E.done = 0;
+            __threadfence();
+            *E.step = step + 1;
+        }
+    }
+}
+
+void launch_emt_history3(const EmtDev& E, const RecParams* rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_emt_history3, dim3((E.n + kBlock - 1) / kBlock, E.n_cases), dim3(kBlock), 0, s, E, rec);
+}
+
 // Re-assemble b of the current step for case k from the stored histories,
 // after a line loss was added for this step: b_a = i_in,a(t_n) - sum_e A[a,e] h_e^n
 // - hC_a^n, with lost branches contributing nothing (same operation order as

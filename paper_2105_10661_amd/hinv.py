@@ -7,8 +7,10 @@ not built this module raises instead of computing anything itself.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -29,7 +31,7 @@ EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update
            "emt_set_step_clock", "emt_destroy",
            "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
            "serve_step", "serve_active", "serve_destroy", "chol_workspace_size", "chol_create", "chol_solve",
-           "chol_get_info", "chol_destroy", "hinv_last_error")
+           "chol_get_info", "chol_destroy", "hinv_last_error", "emt3_workspace_size", "emt3_create")
 
 
 class HinvError(RuntimeError):
@@ -85,6 +87,16 @@ class _Cases(ctypes.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()      # every open handle, closed explicitly at interpreter exit
+
+
+def close_all() -> None:
+    """Destroy every handle still open: serving pools first, then EMT batches, then hierarchies and
+    factorisations.  Registered with atexit when the library is loaded (after torch, so it runs before
+    torch's own exit handlers), so no handle is left to garbage collection during interpreter teardown."""
+    order = {"Serve": 0, "EMT": 1, "Hierarchy": 2, "Chol": 2}
+    for obj in sorted(list(_live), key=lambda o: order.get(type(o).__name__, 3)):
+        obj.close()
 
 
 def load() -> ctypes.CDLL:
@@ -115,6 +127,8 @@ def load() -> ctypes.CDLL:
         "emt_network3_csr": [P, d, P, P, P, P],
         "emt_workspace_size": [P, P, P, P, P],
         "emt_create": [P, P, P, P, P, ctypes.c_size_t, P, P],
+        "emt3_workspace_size": [P, d, P, P, P, P, P],
+        "emt3_create": [P, d, P, P, P, P, P, ctypes.c_size_t, P, P],
         "emt_step": [P, i32, P, P, P],
         "emt_lose_line": [P, i32, i32, P],
         "emt_update_line": [P, i32, i32, d, P, P],
@@ -139,6 +153,7 @@ def load() -> ctypes.CDLL:
     lib.hinv_last_error.restype = ctypes.c_char_p
     lib.hinv_last_error.argtypes = []
     _lib = lib
+    atexit.register(close_all)
     return lib
 
 
@@ -257,6 +272,7 @@ class Hierarchy:
             _check(self._lib.hinv_build(ctypes.byref(self._csr), ctypes.byref(self._tree), ctypes.byref(self._opt),
                                         _ptr(self._ws), nb.value, _stream(), ctypes.byref(h)), "hinv_build")
         self._h = h
+        _live.add(self)
 
     @classmethod
     def from_network(cls, net, **kw):
@@ -354,6 +370,7 @@ class Chol:
             _check(self._lib.chol_create(ctypes.byref(self._csr), _ptr(self._ws), nb.value, _stream(),
                                          ctypes.byref(h)), "chol_create")
         self._h = h
+        _live.add(self)
 
     @classmethod
     def from_network(cls, net, **kw):
@@ -412,32 +429,50 @@ class EMT:
     """EMT time stepping of n_cases cases sharing one network (emt_create / emt_step).
 
     losses: per case a list of (step, branch) line losses (branch lost from that step on).
+    mutual: None for the single-phase network; a float makes it the three-phase network with that
+    ratio of mutual to self inductance between a line's phases (emt3_create): vectors then have
+    3 n_bus rows (3a + p), losses name lines (all three phases lost), each taking 3 of max_mod_rank.
+    shift: three-phase source phase shifts (None: balanced 0, -120, +120 degrees).
     """
 
     def __init__(self, net, n_cases: int = 1, losses=None, prec="fp64", rel_tol=1e-9, max_refine=2,
-                 max_mod_rank=2, warm_start=False, kernel_mode="auto", device="cuda"):
+                 max_mod_rank=2, warm_start=False, kernel_mode="auto", device="cuda", mutual=None, shift=None):
         import torch
         self._lib = load()
         self.device = torch.device(device)
         self.net = net
-        self.n = int(net.n_bus)
+        self.phases = 1 if mutual is None else 3
+        self.n = self.phases * int(net.n_bus)
         self.n_cases = int(n_cases)
         self._na = _NetArrays(net)
         self._ptr, self._st, self._br = _case_arrays(self.n_cases, losses)
         self._cases = _Cases(self.n_cases, _ptr(self._ptr), _ptr(self._st), _ptr(self._br))
         self._opt = _options(prec, rel_tol, max_refine, max_mod_rank, 1, warm_start, kernel_mode)
+        self._shift = None if shift is None else np.ascontiguousarray(shift, np.float64)
         nb = ctypes.c_size_t(0)
-        _check(self._lib.emt_workspace_size(ctypes.byref(self._na.s), ctypes.byref(self._na.tree),
-                                            ctypes.byref(self._opt), ctypes.byref(self._cases), ctypes.byref(nb)),
-               "emt_workspace_size")
+        if mutual is None:
+            _check(self._lib.emt_workspace_size(ctypes.byref(self._na.s), ctypes.byref(self._na.tree),
+                                                ctypes.byref(self._opt), ctypes.byref(self._cases), ctypes.byref(nb)),
+                   "emt_workspace_size")
+        else:
+            _check(self._lib.emt3_workspace_size(ctypes.byref(self._na.s), float(mutual), _ptr(self._shift),
+                                                 ctypes.byref(self._na.tree), ctypes.byref(self._opt),
+                                                 ctypes.byref(self._cases), ctypes.byref(nb)), "emt3_workspace_size")
         self.ws_bytes = nb.value
         self._ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p(0)
         with torch.cuda.device(self.device):
-            _check(self._lib.emt_create(ctypes.byref(self._na.s), ctypes.byref(self._na.tree), ctypes.byref(self._opt),
-                                        ctypes.byref(self._cases), _ptr(self._ws), nb.value, _stream(),
-                                        ctypes.byref(h)), "emt_create")
+            if mutual is None:
+                _check(self._lib.emt_create(ctypes.byref(self._na.s), ctypes.byref(self._na.tree),
+                                            ctypes.byref(self._opt), ctypes.byref(self._cases), _ptr(self._ws),
+                                            nb.value, _stream(), ctypes.byref(h)), "emt_create")
+            else:
+                _check(self._lib.emt3_create(ctypes.byref(self._na.s), float(mutual), _ptr(self._shift),
+                                             ctypes.byref(self._na.tree), ctypes.byref(self._opt),
+                                             ctypes.byref(self._cases), _ptr(self._ws), nb.value, _stream(),
+                                             ctypes.byref(h)), "emt3_create")
         self._h = h
+        _live.add(self)
 
     def step(self, n_steps: int, record_v: bool = True, record_b: bool = False, v_out=None, b_out=None):
         """Advance all cases; returns (V, B) of shape (n_steps, n_cases, n_bus) or None."""
@@ -518,6 +553,7 @@ class Serve:
         _check(self._lib.serve_create(ctypes.byref(self._opt), int(max_slots), _ptr(self._ws), nb.value,
                                       ctypes.byref(h)), "serve_create")
         self._h = h
+        _live.add(self)
         self._cases = {}
 
     def case_bytes(self, net, losses=None, max_mod_rank=2) -> int:

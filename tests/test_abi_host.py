@@ -181,3 +181,38 @@ def test_three_phase_G_matches_oracle(hv):
     na = hv._NetArrays(net)
     nnz = ctypes.c_int64(0)
     assert hv.STATUS[lib.emt_network3_csr(ctypes.byref(na.s), 0.5, None, None, None, ctypes.byref(nnz))] == "INVALID"
+
+
+def test_emt3_validation(hv):
+    """emt3_workspace_size (host only): a line loss takes three of max_mod_rank, the three-phase loop
+    runs on the per-kernel engine only, and the mutual ratio and phase shifts are checked."""
+    lib = hv.load()
+    net = cases.net_ring_fine(2, 5)
+    na = hv._NetArrays(net)
+    nb = ctypes.c_size_t(0)
+
+    def size(losses, rank, mode="auto", mutual=cases.MUTUAL_RATIO, shift=None):
+        ptr, st, br = hv._case_arrays(2, losses)
+        cs = hv._Cases(2, hv._ptr(ptr), hv._ptr(st), hv._ptr(br))
+        op = hv._options("fp64", 1e-9, 2, rank, 1, False, mode)
+        sh = None if shift is None else np.ascontiguousarray(shift, np.float64)
+        return hv.STATUS[lib.emt3_workspace_size(ctypes.byref(na.s), float(mutual), hv._ptr(sh), ctypes.byref(na.tree),
+                                                 ctypes.byref(op), ctypes.byref(cs), ctypes.byref(nb))]
+
+    assert size([[(5, 3)], []], 3) == "OK" and nb.value > 0
+    assert size([[(5, 3)], []], 2) == "RANK_LIMIT"                    # one line loss = rank 3
+    assert size([[(5, 3), (9, 4)], [(7, 10)]], 6) == "OK"
+    assert size([[(5, 3), (9, 4)], [(7, 10)]], 5) == "RANK_LIMIT"
+    assert size([[(5, net.n_branch)], []], 3) == "INVALID"           # lines, not phase branches
+    assert size([[(5, 3)], []], 3, mode="panel") == "INVALID"
+    assert size([[(5, 3)], []], 3, mode="per_kernel") == "OK"
+    assert size(None, 3, mutual=0.5) == "INVALID"
+    assert size(None, 3, shift=[0.0, np.nan, 1.0]) == "INVALID"
+    assert size(None, 3, shift=[0.0, 0.0, 0.0]) == "OK"
+    big = cases.net_ring(2, 5)                                        # 45-bus leaves: 135 rows > 128
+    nbig = hv._NetArrays(big)
+    ptr, st, br = hv._case_arrays(1, None)
+    cs = hv._Cases(1, hv._ptr(ptr), hv._ptr(st), hv._ptr(br))
+    op = hv._options("fp64", 1e-9, 2, 3, 1)
+    assert hv.STATUS[lib.emt3_workspace_size(ctypes.byref(nbig.s), 0.3, None, ctypes.byref(nbig.tree),
+                                             ctypes.byref(op), ctypes.byref(cs), ctypes.byref(nb))] == "INVALID"

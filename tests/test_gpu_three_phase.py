@@ -86,3 +86,70 @@ def test_three_phase_paper_approximation(hv):
     ref = oracle.paper_inverse(oracle.assemble_G3(net, cases.MUTUAL_RATIO), net.parent, leaf)
     assert _rel(V.cpu().numpy().T, ref) <= 1e-12
     H.close()
+
+
+# ---------------------------------------------------------------------------
+# Three-phase EMT time loop (emt3_create): 3x3 line companions and histories, losses of whole lines
+
+@pytest.fixture(scope="module")
+def ring3():
+    """2-copy ring (358 buses, 1074 rows), mutual 0.3: oracle trajectories (dense LU, re-factorised at
+    the loss) of a tie-line loss, a loss inside a copy, and an unbalanced drive with a loss."""
+    net = cases.net_ring_fine(2, 21)
+    n_steps = 3000
+    runs = {"tie": ((1000, 528), oracle.BALANCED), "inner": ((1500, 40), oracle.BALANCED),
+            "unbalanced": ((700, 300), (0.0, -1.9, 2.6))}
+    print(f"[gpu] three-phase oracle runs, {3 * net.n_bus} rows x {n_steps} steps", flush=True)
+    refs = {k: oracle.emt_run3(net, n_steps, cases.MUTUAL_RATIO, loss_steps=[ls[0]], loss_branches=[ls[1]],
+                               shift=sh)[0] for k, (ls, sh) in runs.items()}
+    return net, n_steps, runs, refs
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,warm,refine", [("fp64", False, 0), ("fp32", True, 2)])
+def test_three_phase_emt_ring_trajectories(hv, ring3, prec, warm, refine):
+    """Balanced cases batched (one tie-line loss, one loss inside a copy), the unbalanced one alone;
+    every trajectory against the oracle, peak-normalised, 1e-10."""
+    import torch
+    net, n_steps, runs, refs = ring3
+    groups = [(["tie", "inner"], None), (["unbalanced"], runs["unbalanced"][1])]
+    for names, shift in groups:
+        print(f"[gpu] three-phase EMT {prec}: {names}", flush=True)
+        emt = hv.EMT(net, len(names), losses=[[runs[k][0]] for k in names], prec=prec, max_refine=refine,
+                     rel_tol=1e-7, warm_start=warm, max_mod_rank=3, mutual=cases.MUTUAL_RATIO, shift=shift)
+        assert emt.n == 3 * net.n_bus
+        V = torch.empty((n_steps, len(names), emt.n), dtype=torch.float64, device="cuda")
+        for c0 in range(0, n_steps, 500):
+            emt.step(500, v_out=V[c0:c0 + 500])
+        emt.sync_status()
+        emt.close()
+        Vh = V.cpu().numpy()
+        for j, k in enumerate(names):
+            err = np.abs(Vh[:, j, :] - refs[k]).max() / np.abs(refs[k]).max()
+            print(f"[gpu]   {k}: {err:.2e}", flush=True)
+            assert err <= 1e-10, (k, err)
+
+
+def test_three_phase_lose_line_now_equals_scheduled(hv, ring3):
+    """emt_lose_line on a three-phase handle (line index, all phases, rank 3) at the step a scheduled
+    loss takes effect gives the same trajectory."""
+    import torch
+    net, n_steps, runs, refs = ring3
+    (ls, line), _ = runs["tie"]
+    print("[gpu] three-phase emt_lose_line", flush=True)
+    a = hv.EMT(net, 1, losses=[[(ls, line)]], max_mod_rank=3, mutual=cases.MUTUAL_RATIO)
+    b = hv.EMT(net, 1, max_mod_rank=3, mutual=cases.MUTUAL_RATIO)
+    Va, _ = a.step(ls + 200)
+    Vb1, _ = b.step(ls - 1)
+    b.lose_line(0, line)
+    Vb2, _ = b.step(201)
+    torch.cuda.synchronize()
+    Vb = torch.cat([Vb1, Vb2]).cpu().numpy()
+    assert np.abs(Va.cpu().numpy() - Vb).max() <= 1e-13 * np.abs(refs["tie"]).max()
+    assert np.abs(Vb[:, 0, :] - refs["tie"][:ls + 200]).max() <= 1e-10 * np.abs(refs["tie"]).max()
+    with pytest.raises(hv.HinvError):
+        b.lose_line(0, line)                  # already lost
+    with pytest.raises(hv.HinvError):
+        b.lose_line(0, 3)                     # rank 3 holds one line
+    a.close()
+    b.close()
