@@ -210,6 +210,42 @@ hinv_status hinv_solve(hinv_handle h, const double* d_i, double* d_v, int32_t nr
 hinv_status hinv_solve_noalloc(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld,
                                void* stream);
 
+/* What hinv_solve_gmres did. */
+typedef struct {
+    int32_t corrections;       /* outer corrections (FP64 residual + GMRES solve + update) */
+    int32_t inner_iterations;  /* GMRES iterations summed over the corrections (each one applies M, i.e. the
+                                  stored inverse once and G `smooth` times, and G once to every column) */
+    double last_update;        /* max over columns of ||d||_inf / ||x||_inf of the last correction */
+} hinv_gmres_info;
+
+/* Device workspace of hinv_solve_gmres for nrhs columns and at most m GMRES
+ * iterations per correction (1 <= m <= 64): about 8 n nrhs (2m + 7) bytes. */
+hinv_status hinv_gmres_workspace_size(hinv_handle h, int32_t nrhs, int32_t m, size_t* bytes);
+
+/* v = G^{-1} i (Eq. (2)) to FP64 accuracy when the stored inverse is too
+ * coarse for plain refinement (BF16 or scaled FP8 storage, whose apply error
+ * makes the refinement of hinv_solve converge slowly or diverge): GMRES-based
+ * iterative refinement with the preconditioner M = the stored inverse P applied
+ * in its storage precision (with the stored line changes, as in hinv_solve),
+ * followed by `smooth` (0..16) damped-Jacobi sweeps z += (2/3) D^{-1} (v - G z),
+ * D = diag(G): a coarse stored inverse errs most where G amplifies, at high
+ * frequencies, which these sweeps damp.  x_0 = M i.  Each correction:
+ * r = i - G x in FP64 with the sparse G (and the stored changes); d ~ G^{-1} r
+ * by flexible GMRES in FP64 on G M (right preconditioned; classical
+ * Gram-Schmidt applied twice; Givens rotations), stopped once every column's
+ * residual estimate is <= inner_tol ||r|| or after m iterations; x += d.  Stops
+ * when max ||d||_inf / ||x||_inf <= rel_tol or after max_outer corrections
+ * (then HINV_E_NO_CONVERGENCE, with the iterate written).  Vectors and layout
+ * as hinv_solve (no bound by opt.max_nrhs); d_ws: device workspace of
+ * hinv_gmres_workspace_size(h, nrhs, m) bytes, caller-owned, contents
+ * overwritten.  0 < inner_tol < 1, rel_tol > 0, max_outer >= 0.  info (host,
+ * may be NULL) receives the counts.  The host decides when to stop from one
+ * small device-to-host copy per GMRES iteration, so the call synchronises the
+ * stream. */
+hinv_status hinv_solve_gmres(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld, int32_t m,
+                             int32_t max_outer, int32_t smooth, double inner_tol, double rel_tol, void* d_ws,
+                             size_t ws_bytes, void* stream, hinv_gmres_info* info);
+
 /* After the caller has synchronised the stream: HINV_E_NO_CONVERGENCE or
  * HINV_E_NOT_SPD if a kernel flagged it since the last call, else HINV_OK.
  * Clears the flags. */
@@ -313,9 +349,10 @@ hinv_status emt_network3_csr(const emt_network* net, double mutual, int32_t* row
  * HINV_MAX_LEAF).  loss_branch of the cases names lines: a lost line loses its
  * three phases, held as three changes w_p = e_from,p - e_to,p coupled by D =
  * -Y (G <- G + W D W^T, the capacitance then takes D^{-1} = -Z), so a case
- * holds at most max_mod_rank / 3 line losses (RANK_LIMIT beyond).  Steps on
- * the per-kernel engine (kernel_mode 0 or 1, else HINV_E_INVALID), in FP64
- * or with FP32/BF16/FP8 storage and FP64 refinement.  The handle takes
+ * holds at most max_mod_rank / 3 line losses (RANK_LIMIT beyond).  Engines:
+ * one workgroup per case (kernel_mode 2, and the automatic choice when the
+ * case fits its LDS in FP64 or FP32 storage) or one launch per phase
+ * (kernel_mode 1, any storage precision); other modes HINV_E_INVALID.  The handle takes
  * emt_step, emt_lose_line (line index), emt_sync_status, emt_get_step,
  * emt_get_stats and emt_destroy as a single-phase one does; emt_update_line
  * and serve_attach refuse it with HINV_E_INVALID.  Other errors as

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhinv.so")
-SOURCES = ["hinv_host.hip", "k_build.hip", "k_apply.hip", "k_emt.hip", "k_run.hip", "k_team.hip", "k_panel.hip", "k_level.hip", "chol.hip"]
+SOURCES = ["hinv_host.hip", "k_build.hip", "k_apply.hip", "k_emt.hip", "k_run.hip", "k_team.hip", "k_panel.hip", "k_level.hip", "chol.hip", "k_gmres.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from forming packed FP32 instructions

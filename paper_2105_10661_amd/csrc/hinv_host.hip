@@ -1124,6 +1124,142 @@ hinv_status hinv_solve_noalloc(hinv_handle h, const double* d_i, double* d_v, in
     return HINV_OK;
 }
 
+// Workspace of hinv_solve_gmres (base == nullptr: measure only).
+struct GmresWs {
+    double *B, *X, *R, *D, *W, *Zero, *V, *Z, *Y, *dots, *nrm, *Hs, *cs, *sn, *g, *res, *y;
+    unsigned long long* stats;
+};
+
+static void carve_gmres(const hinv_ctx& c, Arena& A, int nrhs, int m, GmresWs& w)
+{
+    const int64_t nk = (int64_t)c.P.n * nrhs;
+    w.B = A.take<double>(nk); w.X = A.take<double>(nk); w.R = A.take<double>(nk); w.D = A.take<double>(nk);
+    w.W = A.take<double>(nk); w.Zero = A.take<double>(nk);
+    w.V = A.take<double>((int64_t)(m + 1) * nk);
+    w.Z = A.take<double>((int64_t)m * nk);
+    w.Y = A.take<double>((int64_t)std::max<size_t>(c.P.col_row.size(), 1) * nrhs);
+    w.dots = A.take<double>((int64_t)2 * (m + 1) * nrhs);
+    w.nrm = A.take<double>(nrhs);
+    w.Hs = A.take<double>((int64_t)(m + 1) * m * nrhs);
+    w.cs = A.take<double>((int64_t)m * nrhs); w.sn = A.take<double>((int64_t)m * nrhs);
+    w.g = A.take<double>((int64_t)(m + 1) * nrhs);
+    w.res = A.take<double>(nrhs);
+    w.y = A.take<double>((int64_t)m * nrhs);
+    w.stats = A.take<unsigned long long>(nrhs);
+}
+
+hinv_status hinv_gmres_workspace_size(hinv_handle h, int32_t nrhs, int32_t m, size_t* bytes)
+{
+    if (!h || !bytes) return fail(HINV_E_INVALID, "NULL argument");
+    if (nrhs < 1 || m < 1 || m > kGmresMaxInner)
+        return fail(HINV_E_INVALID, "nrhs %d < 1 or m %d outside 1..%d", nrhs, m, kGmresMaxInner);
+    Arena A;
+    GmresWs w{};
+    carve_gmres(*h, A, nrhs, m, w);
+    *bytes = A.off + kAlign;
+    return HINV_OK;
+}
+
+hinv_status hinv_solve_gmres(hinv_handle h, const double* d_i, double* d_v, int32_t nrhs, int32_t ld, int32_t m,
+                             int32_t max_outer, int32_t smooth, double inner_tol, double rel_tol, void* d_ws,
+                             size_t ws_bytes, void* stream, hinv_gmres_info* info)
+{
+    if (!h) return fail(HINV_E_INVALID, "handle is NULL");
+    hinv_ctx& c = *h;
+    if (info) *info = hinv_gmres_info{0, 0, 0.0};
+    if (nrhs < 1 || m < 1 || m > kGmresMaxInner || max_outer < 0 || smooth < 0 || smooth > 16)
+        return fail(HINV_E_INVALID, "nrhs %d < 1, m %d outside 1..%d, max_outer %d < 0 or smooth %d outside 0..16",
+                    nrhs, m, kGmresMaxInner, max_outer, smooth);
+    if (ld < c.P.n) return fail(HINV_E_INVALID, "ld %d < n %d", ld, c.P.n);
+    if (!d_i || !d_v || !d_ws) return fail(HINV_E_INVALID, "NULL vector or workspace");
+    if (!(inner_tol > 0.0 && inner_tol < 1.0) || !(rel_tol > 0.0))
+        return fail(HINV_E_INVALID, "inner_tol must be in (0, 1) and rel_tol positive");
+    size_t need = 0;
+    hinv_status st = hinv_gmres_workspace_size(h, nrhs, m, &need);
+    if (st != HINV_OK) return st;
+    if (ws_bytes < need) return fail(HINV_E_NO_MEMORY, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    Arena A;
+    A.base = (char*)d_ws;
+    GmresWs w{};
+    carve_gmres(c, A, nrhs, m, w);
+    const int n = c.P.n;
+    const int64_t nk = (int64_t)n * nrhs;
+    const int prec = c.opt.prec;
+    hipStream_t s = (hipStream_t)stream;
+    const SolveTemps tmp{w.Y, w.R, w.D, w.stats};
+    // M v: the stored inverse in its storage precision, then `smooth` damped-Jacobi sweeps (W as scratch)
+    auto apply_m = [&](const double* Vin, double* Zout) {
+        precond(c, tmp, prec, Vin, Zout, nrhs, 0, nullptr, s);
+        for (int q = 0; q < smooth; ++q) {
+            launch_residual(c.H, c.M, Vin, Zout, w.W, nrhs, 0, nullptr, s);
+            launch_gm_jacobi(c.H, nrhs, w.W, 2.0 / 3.0, Zout, s);
+        }
+    };
+    HIP_TRY(hipMemsetAsync(w.Zero, 0, sizeof(double) * nk, s));
+    launch_permute_in(n, nrhs, c.d_perm, d_i, ld, w.B, s);
+    apply_m(w.B, w.X);                                                  // x_0 = M b
+    std::vector<double> beta(nrhs), res(nrhs);
+    std::vector<unsigned long long> upd(nrhs);
+    int outer = 0, inner_total = 0;
+    double last = INFINITY;
+    while (outer < max_outer && !(last <= rel_tol)) {
+        launch_residual(c.H, c.M, w.B, w.X, w.R, nrhs, 0, nullptr, s);   // r = b - G x, FP64
+        launch_gm_norms(n, nrhs, w.R, w.nrm, s);
+        launch_gm_start(nrhs, m, w.nrm, w.g, w.res, s);
+        launch_gm_scale(n, nrhs, w.R, w.nrm, 1, 1.0, w.V, s);             // v_0 = r / ||r||
+        HIP_TRY(hipMemcpyAsync(beta.data(), w.nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        bool zero = true;
+        for (double b : beta) zero = zero && b == 0.0;
+        if (zero) { last = 0.0; break; }
+        int j = 0;
+        while (j < m) {
+            double* Vj = w.V + (int64_t)j * nk;
+            double* Zj = w.Z + (int64_t)j * nk;
+            apply_m(Vj, Zj);                                                  // z_j = M v_j
+            launch_residual(c.H, c.M, w.Zero, Zj, w.W, nrhs, 0, nullptr, s);   // W = -G z_j = -w
+            for (int pass = 0; pass < 2; ++pass) {                            // w -= sum h v_i, twice
+                double* h2 = w.dots + pass * (m + 1);
+                launch_gm_dots(n, nrhs, j + 1, w.V, w.W, -1.0, h2, 2 * (m + 1), s);
+                launch_gm_update(n, nrhs, j + 1, w.V, h2, 2 * (m + 1), 1.0, w.W, s);
+            }
+            launch_gm_norms(n, nrhs, w.W, w.nrm, s);
+            launch_gm_givens(nrhs, m, j, w.dots, w.nrm, w.Hs, w.cs, w.sn, w.g, w.res, s);
+            launch_gm_scale(n, nrhs, w.W, w.nrm, 1, -1.0, w.V + (int64_t)(j + 1) * nk, s);   // v_{j+1} = w/||w||
+            ++j;
+            ++inner_total;
+            HIP_TRY(hipMemcpyAsync(res.data(), w.res, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            bool done = true;
+            for (int k = 0; k < nrhs; ++k) done = done && !(res[k] > inner_tol * beta[k]);
+            if (done) break;
+        }
+        launch_gm_backsolve(nrhs, m, j, w.Hs, w.g, w.y, s);
+        HIP_TRY(hipMemsetAsync(w.D, 0, sizeof(double) * nk, s));
+        launch_gm_update(n, nrhs, j, w.Z, w.y, m, 1.0, w.D, s);             // d = sum_j y_j z_j
+        hipLaunchKernelGGL(k_zero_u64, dim3((nrhs + 255) / 256), dim3(256), 0, s, w.stats, nrhs);
+        launch_axpy_stats(n, nrhs, w.X, w.D, w.stats, 1e300, c.d_flags, s);  // x += d, ||d||/||x|| per column
+        HIP_TRY(hipMemcpyAsync(upd.data(), w.stats, sizeof(unsigned long long) * nrhs, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        last = 0.0;
+        for (unsigned long long u : upd) {
+            double r;
+            memcpy(&r, &u, sizeof r);
+            last = std::max(last, r);
+        }
+        ++outer;
+    }
+    launch_permute_out(n, nrhs, c.d_perm, w.X, d_v, ld, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    c.applies += (int64_t)nrhs * (1 + inner_total) * (1 + smooth);
+    if (info) *info = hinv_gmres_info{outer, inner_total, last};
+    if (!(last <= rel_tol))
+        return fail(HINV_E_NO_CONVERGENCE, "GMRES refinement: last update %g above rel_tol %g after %d corrections",
+                    last, rel_tol, outer);
+    return HINV_OK;
+}
+
 hinv_status hinv_sync_status(hinv_handle h)
 {
     if (!h) return fail(HINV_E_INVALID, "handle is NULL");
@@ -1604,8 +1740,9 @@ hinv_status emt_plan3(const emt_network* N, const Phase3& p3, const hinv_tree* T
     if (!(p3.mu >= 0.0 && p3.mu < 0.5)) return fail(HINV_E_INVALID, "mutual ratio %g outside [0, 0.5)", p3.mu);
     for (int p = 0; p < 3; ++p)
         if (!isfinite(p3.shift[p])) return fail(HINV_E_INVALID, "phase shift %d is not finite", p);
-    if (o->kernel_mode != 0 && o->kernel_mode != 1)
-        return fail(HINV_E_INVALID, "three-phase networks step on the per-kernel engine (kernel_mode 0 or 1)");
+    if (o->kernel_mode != 0 && o->kernel_mode != 1 && o->kernel_mode != 2)
+        return fail(HINV_E_INVALID, "three-phase networks step on the per-kernel or the one-workgroup-per-case "
+                    "engine (kernel_mode 0, 1 or 2)");
     if (!T || !T->parent || !T->bus_leaf) return fail(HINV_E_INVALID, "tree is missing");
     hinv_status st = check_cases(C, N->n_branch, o->max_mod_rank / 3, c.losses);
     if (st != HINV_OK) return st;
@@ -1631,7 +1768,10 @@ hinv_status emt_plan3(const emt_network* N, const Phase3& p3, const hinv_tree* T
     carve_hier(c.hc, A, c.n_cases, c.R, c.hc.opt.max_nrhs);
     carve_emt(c, A, 3 * N->n_src);
     c.team_ok = c.panel_ok = c.level_ok = false;
-    c.engine = 1;
+    const bool fits = run_fits(c.hc.H) && (o->prec == HINV_FP64 || o->prec == HINV_FP32);
+    if (o->kernel_mode == 2 && !fits)
+        return fail(HINV_E_INVALID, "the one-workgroup-per-case engine needs FP64/FP32 and a case that fits LDS");
+    c.engine = (o->kernel_mode == 1 || !fits) ? 1 : 2;
     *bytes = A.off + kAlign;
     return HINV_OK;
 }

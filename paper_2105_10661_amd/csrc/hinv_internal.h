@@ -545,7 +545,42 @@ hipError_t launch_emt_serve(const ServeSlot* d_slots, int n_slots, int n_steps, 
 hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, int prec,
                           hipStream_t s);
 // History update with v_n and assembly of b_{n+1}; records; advances *E.step.
+// New history of phase p of three-phase line l from the line's phase voltages v_ft and current
+// histories: i = Y v_ft + h (3-vectors), h_p' = (Y v_ft)_p + (A i)_p.  One fixed operation order, so
+// every caller (both ends of the line, every engine) gets the same bits.
+__device__ inline double line3_history(const EmtDev& E, const double* v, const double* hcur, int l, int p)
+{
+    const double* Y = E.Y3 + 9 * l;
+    const double* A = E.A3 + 9 * l;
+    double vft[3], il[3];
+    for (int r = 0; r < 3; ++r) vft[r] = v[E.fr[3 * l + r]] - v[E.to[3 * l + r]];
+    double yv = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        double y = 0.0;
+        for (int c = 0; c < 3; ++c) y = fma(Y[3 * r + c], vft[c], y);
+        il[r] = y + hcur[3 * l + r];
+        if (r == p) yv = y;
+    }
+    double ai = 0.0;
+    for (int c = 0; c < 3; ++c) ai = fma(A[3 * p + c], il[c], ai);
+    return yv + ai;
+}
+
 void launch_emt_history(const EmtDev& E, const RecParams* rec, hipStream_t s);
+// GMRES-based refinement (k_gmres.hip)
+constexpr int kGmresMaxInner = 64;
+void launch_gm_dots(int n, int nrhs, int nv, const double* V, const double* W, double sgn, double* out, int ld_out,
+                    hipStream_t s);
+void launch_gm_norms(int n, int nrhs, const double* W, double* out, hipStream_t s);
+void launch_gm_update(int n, int nrhs, int nv, const double* V, const double* h, int ld_h, double sgn, double* W,
+                      hipStream_t s);
+void launch_gm_scale(int n, int nrhs, const double* W, const double* nrm, int ld_nrm, double sgn, double* Vout,
+                     hipStream_t s);
+void launch_gm_givens(int nrhs, int m, int j, const double* dots, const double* nrm, double* Hs, double* cs,
+                      double* sn, double* g, double* res, hipStream_t s);
+void launch_gm_start(int nrhs, int m, const double* nrm, double* g, double* res, hipStream_t s);
+void launch_gm_backsolve(int nrhs, int m, int nj, const double* Hs, const double* g, double* y, hipStream_t s);
+void launch_gm_jacobi(const HierDev& H, int nrhs, const double* R, double omega, double* Z, hipStream_t s);
 void launch_emt_history3(const EmtDev& E, const RecParams* rec, hipStream_t s);
 
 }  // namespace hinv

@@ -138,22 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_emt_history3(EmtDev E, const RecPara
             const int e = E.inc_br[q];
             const int l = e / 3, p = e - 3 * l;
             double hn = 0.0;
-            if (!lost_by(E, k, e, step + 1)) {
-                const double* Y = E.Y3 + 9 * l;
-                const double* A = E.A3 + 9 * l;
-                double vft[3], il[3];
-                for (int r = 0; r < 3; ++r) vft[r] = v[E.fr[3 * l + r]] - v[E.to[3 * l + r]];
-                double yv = 0.0;
-                for (int r = 0; r < 3; ++r) {
-                    double y = 0.0;
-                    for (int c = 0; c < 3; ++c) y = fma(Y[3 * r + c], vft[c], y);
-                    il[r] = y + hcur[3 * l + r];
-                    if (r == p) yv = y;
-                }
-                double ai = 0.0;
-                for (int c = 0; c < 3; ++c) ai = fma(A[3 * p + c], il[c], ai);
-                hn = yv + ai;
-            }
+            if (!lost_by(E, k, e, step + 1)) hn = line3_history(E, v, hcur, l, p);
             bn -= (a == E.fr[e]) ? hn : -hn;
             if (a == E.fr[e]) hnext[e] = hn;
         }

@@ -157,6 +157,17 @@ __device__ void wg_residual(const HierDev& H, const ModDev& M, int k, int64_t st
         for (int j = 0; j < r; ++j) {
             const int a = M.a[k * M.R + j], bb = M.b[k * M.R + j];
             if (i != a && i != bb) continue;
+            if (M.grp3) {          // row j of the line's 3x3 D times its three phase differences
+                const int g0 = j - j % 3;
+                const double* dj = M.d3 + ((int64_t)k * M.R + j) * 3;
+                double dw = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    const int aq = M.a[k * M.R + g0 + q], bq = M.b[k * M.R + g0 + q];
+                    dw += dj[q] * (v[aq] - (bq >= 0 ? v[bq] : 0.0));
+                }
+                acc += (i == a ? 1.0 : -1.0) * dw;
+                continue;
+            }
             const double wv = v[a] - (bb >= 0 ? v[bb] : 0.0);
             acc += (i == a ? 1.0 : -1.0) * M.dg[k * M.R + j] * wv;
         }
@@ -251,9 +262,13 @@ __device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, 
                 const int f = E.fr[e], to = E.to[e];
                 double hn = 0.0;
                 if (!run_lost_by(E, k, e, step + 1)) {
-                    const double vft = v[f] - v[to];
-                    const double ie = E.g[e] * vft + hcur[e];
-                    hn = E.g[e] * vft + E.alpha[e] * ie;
+                    if (E.Y3) {        // three-phase: phase e % 3 of line e / 3
+                        hn = line3_history(E, v, hcur, e / 3, e % 3);
+                    } else {
+                        const double vft = v[f] - v[to];
+                        const double ie = E.g[e] * vft + hcur[e];
+                        hn = E.g[e] * vft + E.alpha[e] * ie;
+                    }
                 }
                 bn -= (a == f) ? hn : -hn;
                 if (a == f) hnext[e] = hn;

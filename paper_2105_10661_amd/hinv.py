@@ -31,7 +31,8 @@ EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update
            "emt_set_step_clock", "emt_destroy",
            "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
            "serve_step", "serve_active", "serve_destroy", "chol_workspace_size", "chol_create", "chol_solve",
-           "chol_get_info", "chol_destroy", "hinv_last_error", "emt3_workspace_size", "emt3_create")
+           "chol_get_info", "chol_destroy", "hinv_last_error", "emt3_workspace_size", "emt3_create",
+           "hinv_gmres_workspace_size", "hinv_solve_gmres")
 
 
 class HinvError(RuntimeError):
@@ -63,6 +64,10 @@ class _Info(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_leaves", "n_internal", "n_levels", "n_cols", "leaf_entries",
                                              "z_entries", "s_entries", "max_leaf", "max_cols")] + \
                [("apply_flops", ctypes.c_double), ("build_flops", ctypes.c_double)]
+
+
+class _GmresInfo(ctypes.Structure):
+    _fields_ = [("corrections", ctypes.c_int32), ("inner_iterations", ctypes.c_int32), ("last_update", ctypes.c_double)]
 
 
 class _UpdateInfo(ctypes.Structure):
@@ -128,6 +133,8 @@ def load() -> ctypes.CDLL:
         "emt_workspace_size": [P, P, P, P, P],
         "emt_create": [P, P, P, P, P, ctypes.c_size_t, P, P],
         "emt3_workspace_size": [P, d, P, P, P, P, P],
+        "hinv_gmres_workspace_size": [P, i32, i32, P],
+        "hinv_solve_gmres": [P, P, P, i32, i32, i32, i32, i32, d, d, P, ctypes.c_size_t, P, P],
         "emt3_create": [P, d, P, P, P, P, P, ctypes.c_size_t, P, P],
         "emt_step": [P, i32, P, P, P],
         "emt_lose_line": [P, i32, i32, P],
@@ -292,6 +299,29 @@ class Hierarchy:
             out = torch.empty_like(x)
         _check(self._lib.hinv_solve(self._h, _ptr(x), _ptr(out), x.shape[0], self.n, _stream()), "hinv_solve")
         return out[0] if squeeze else out
+
+    def solve_gmres(self, i, m=30, max_outer=6, smooth=0, inner_tol=1e-6, rel_tol=1e-12, raise_on_fail=True):
+        """hinv_solve_gmres: v = G^{-1} i by GMRES-based refinement with the stored inverse (in its
+        storage precision, then `smooth` damped-Jacobi sweeps) as preconditioner.  i: (nrhs, n) float64
+        device tensor.  Returns (v, info); info: corrections, inner_iterations, last_update, status."""
+        import torch
+        x = i.contiguous()
+        if x.dim() != 2 or x.dtype != torch.float64 or x.device.type != "cuda":
+            raise ValueError("i must be a (nrhs, n) float64 device tensor")
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.hinv_gmres_workspace_size(self._h, x.shape[0], int(m), ctypes.byref(nb)),
+               "hinv_gmres_workspace_size")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+        out = torch.empty_like(x)
+        inf = _GmresInfo()
+        st = self._lib.hinv_solve_gmres(self._h, _ptr(x), _ptr(out), x.shape[0], self.n, int(m), int(max_outer),
+                                        int(smooth), float(inner_tol), float(rel_tol), _ptr(ws), nb.value, _stream(),
+                                        ctypes.byref(inf))
+        info = {k: getattr(inf, k) for k, _ in _GmresInfo._fields_}
+        info["status"] = STATUS.get(st, st)
+        if raise_on_fail:
+            _check(st, "hinv_solve_gmres")
+        return out, info
 
     def solve_noalloc(self, i, out):
         """hinv_solve_noalloc: v = G^{-1} i with the library's static scratch (no allocation in the

@@ -206,6 +206,7 @@ def test_emt3_validation(hv):
     assert size([[(5, net.n_branch)], []], 3) == "INVALID"           # lines, not phase branches
     assert size([[(5, 3)], []], 3, mode="panel") == "INVALID"
     assert size([[(5, 3)], []], 3, mode="per_kernel") == "OK"
+    assert size([[(5, 3)], []], 3, mode="fused") == "OK"
     assert size(None, 3, mutual=0.5) == "INVALID"
     assert size(None, 3, shift=[0.0, np.nan, 1.0]) == "INVALID"
     assert size(None, 3, shift=[0.0, 0.0, 0.0]) == "OK"

@@ -8,8 +8,9 @@
   with one power-of-two scale 2^k per 32 consecutive stored entries, k the
   smallest integer with max|x| / 2^k <= 448.
 * Refinement: FP32 and BF16 storage reach the FP64 oracle within 1e-10 with
-  enough FP64-residual corrections on the 11456-bus network; FP8 is measured
-  (not required to converge).
+  enough FP64-residual corrections on the 11456-bus network; with scaled FP8
+  plain refinement diverges (asserted), and GMRES-based refinement brings BF16
+  and FP8 within 1e-10 in at most 6 corrections.
 """
 import numpy as np
 import pytest
@@ -92,16 +93,53 @@ def c3():
     return net, B, X
 
 
-@pytest.mark.parametrize("prec,refine,must", [("fp32", 2, True), ("bf16", 18, True), ("fp8", 6, False)])
-def test_refinement_on_11456_buses(hv, c3, prec, refine, must):
+@pytest.mark.parametrize("prec,refine,converges", [("fp32", 2, True), ("bf16", 18, True), ("fp8", 6, False)])
+def test_refinement_on_11456_buses(hv, c3, prec, refine, converges):
+    """Plain refinement: FP32 and BF16 reach 1e-10; scaled FP8 does not (its apply error exceeds the
+    solution, the contraction factor is above 1 and six corrections leave an error above 1e-3), which
+    is what the GMRES-based refinement below recovers."""
     import torch
     net, B, Xo = c3
     H = hv.Hierarchy.from_network(net, prec=prec, max_refine=refine, max_nrhs=2, rel_tol=1.0)
     X = H.solve(torch.tensor(B, device="cuda")).cpu().numpy()
     err = float((np.abs(X - Xo).max(1) / np.abs(Xo).max(1)).max())
     print(f"[gpu] {prec} with {refine} corrections: rel err {err:.3e}", flush=True)
-    if must:
+    if converges:
         assert err <= 1e-10
+    else:
+        assert err > 1e-3
+    H.close()
+
+
+@pytest.mark.parametrize("prec,smooth", [("bf16", 0), ("fp8", 1), ("fp8", 2)])
+def test_gmres_refinement_on_11456_buses(hv, c3, prec, smooth):
+    """GMRES-based refinement (FP64 residuals, FP64 flexible GMRES on G M, M the BF16 / scaled FP8
+    stored inverse followed by `smooth` damped-Jacobi sweeps): per-solve parity within 1e-10 of the
+    oracle with at most 6 corrections, on the base network and after a line loss held as a stored
+    change (the loss enters both M, through its SMW correction, and the residual's G)."""
+    import torch
+    net, B, Xo = c3
+    H = hv.Hierarchy.from_network(net, prec=prec, max_refine=0, max_nrhs=2, rel_tol=1.0)
+    X, info = H.solve_gmres(torch.tensor(B, device="cuda"), m=60, max_outer=6, smooth=smooth, inner_tol=1e-6,
+                            rel_tol=1e-12)
+    err = float((np.abs(X.cpu().numpy() - Xo).max(1) / np.abs(Xo).max(1)).max())
+    print(f"[gpu] {prec} + {smooth} sweeps GMRES refinement: rel err {err:.3e}, {info}", flush=True)
+    assert info["status"] == "OK" and info["corrections"] <= 6
+    assert err <= 1e-10
+    e = 4321
+    g = float(oracle.branch_conductance(net)[e])
+    perm_a, perm_b = int(net.frm[e]), int(net.to[e])
+    H.modify_line(perm_a, perm_b, -g)
+    alive = np.ones(net.n_branch, bool)
+    alive[e] = False
+    solve = oracle.sparse_solver(net, alive)
+    Xl = np.stack([solve(b) for b in B])
+    X, info = H.solve_gmres(torch.tensor(B, device="cuda"), m=60, max_outer=6, smooth=smooth, inner_tol=1e-6,
+                            rel_tol=1e-12)
+    err = float((np.abs(X.cpu().numpy() - Xl).max(1) / np.abs(Xl).max(1)).max())
+    print(f"[gpu] {prec} + {smooth} sweeps GMRES refinement after a line loss: rel err {err:.3e}, {info}", flush=True)
+    assert info["status"] == "OK" and info["corrections"] <= 6
+    assert err <= 1e-10
     H.close()
 
 

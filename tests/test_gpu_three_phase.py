@@ -106,17 +106,20 @@ def ring3():
 
 
 @pytest.mark.timeout(600)
+@pytest.mark.parametrize("engine", ["per_kernel", "fused"])
 @pytest.mark.parametrize("prec,warm,refine", [("fp64", False, 0), ("fp32", True, 2)])
-def test_three_phase_emt_ring_trajectories(hv, ring3, prec, warm, refine):
+def test_three_phase_emt_ring_trajectories(hv, ring3, prec, warm, refine, engine):
     """Balanced cases batched (one tie-line loss, one loss inside a copy), the unbalanced one alone;
-    every trajectory against the oracle, peak-normalised, 1e-10."""
+    every trajectory against the oracle, peak-normalised, 1e-10; one launch per phase and one
+    workgroup per case."""
     import torch
     net, n_steps, runs, refs = ring3
     groups = [(["tie", "inner"], None), (["unbalanced"], runs["unbalanced"][1])]
     for names, shift in groups:
-        print(f"[gpu] three-phase EMT {prec}: {names}", flush=True)
+        print(f"[gpu] three-phase EMT {prec} {engine}: {names}", flush=True)
         emt = hv.EMT(net, len(names), losses=[[runs[k][0]] for k in names], prec=prec, max_refine=refine,
-                     rel_tol=1e-7, warm_start=warm, max_mod_rank=3, mutual=cases.MUTUAL_RATIO, shift=shift)
+                     rel_tol=1e-7, warm_start=warm, max_mod_rank=3, mutual=cases.MUTUAL_RATIO, shift=shift,
+                     kernel_mode=engine)
         assert emt.n == 3 * net.n_bus
         V = torch.empty((n_steps, len(names), emt.n), dtype=torch.float64, device="cuda")
         for c0 in range(0, n_steps, 500):
@@ -137,8 +140,8 @@ def test_three_phase_lose_line_now_equals_scheduled(hv, ring3):
     net, n_steps, runs, refs = ring3
     (ls, line), _ = runs["tie"]
     print("[gpu] three-phase emt_lose_line", flush=True)
-    a = hv.EMT(net, 1, losses=[[(ls, line)]], max_mod_rank=3, mutual=cases.MUTUAL_RATIO)
-    b = hv.EMT(net, 1, max_mod_rank=3, mutual=cases.MUTUAL_RATIO)
+    a = hv.EMT(net, 1, losses=[[(ls, line)]], max_mod_rank=3, mutual=cases.MUTUAL_RATIO, kernel_mode="fused")
+    b = hv.EMT(net, 1, max_mod_rank=3, mutual=cases.MUTUAL_RATIO, kernel_mode="fused")
     Va, _ = a.step(ls + 200)
     Vb1, _ = b.step(ls - 1)
     b.lose_line(0, line)

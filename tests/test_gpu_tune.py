@@ -2,7 +2,8 @@
 
 * Two partition trees (2 and 4 leaves per 179-bus copy) x two engines (16-case panels on the matrix
   cores, one workgroup per case) x three precision paths are timed; every candidate that ran has an
-  error against the FP64 reference, the FP64 candidates at the FP64 floor.
+  error against the FP64 reference over the horizon (every step of the first 160, every 40th after),
+  the FP64 candidates at the FP64 floor.
 * The choice is the fastest candidate within the gate, and it is accurate against the FP64 oracle
   on sampled cases (1e-10 of the peak voltage).
 * A second call with the same key comes from the JSON cache without running anything.
@@ -18,6 +19,7 @@ from paper_2105_10661_amd import cases
 pytestmark = pytest.mark.gpu
 
 STEPS = 160
+HORIZON = 400       # the gate samples every 40th step after the first 160
 
 
 @pytest.fixture(scope="module")
@@ -35,8 +37,8 @@ def tuned(tmp_path_factory):
     losses = [[(int(s), int(b))] for s, b in zip(st, br)]
     trees = {k: (v.parent, v.bus_leaf) for k, v in nets.items()}
     path = str(tmp_path_factory.mktemp("tune") / "tune.json")
-    res = tune.tune(net, trees, n_cases=32, losses=losses, max_mod_rank=1, gate_steps=STEPS, timed_steps=50,
-                    reps=2, cache=path)
+    res = tune.tune(net, trees, n_cases=32, losses=losses, max_mod_rank=1, gate_steps=STEPS, horizon=HORIZON,
+                    stride=40, timed_steps=50, reps=2, cache=path)
     return tune, net, nets, losses, trees, path, res
 
 
@@ -51,6 +53,8 @@ def test_every_candidate_ran_or_was_refused(tuned):
         assert r.status in ("ok", "NO_CONVERGENCE"), (r.cand, r.status)
         assert np.isfinite(r.us_per_step) and r.us_per_step > 0
         assert np.isfinite(r.err)
+        assert r.err >= r.err_first          # the horizon includes the first gate_steps steps
+        assert r.err_extrapolated == pytest.approx(r.err_first * HORIZON / STEPS)
         if r.cand.prec == "fp64":
             assert r.err <= 1e-11, (r.cand, r.err)
     assert sum(r.feasible for r in res.rows) >= 8
@@ -86,8 +90,8 @@ def test_choice_matches_the_oracle(tuned):
 def test_second_call_comes_from_the_cache(tuned):
     tune, net, nets, losses, trees, path, res = tuned
     t = time.perf_counter()
-    again = tune.tune(net, trees, n_cases=32, losses=losses, max_mod_rank=1, gate_steps=STEPS, timed_steps=50,
-                      reps=2, cache=path)
+    again = tune.tune(net, trees, n_cases=32, losses=losses, max_mod_rank=1, gate_steps=STEPS, horizon=HORIZON,
+                      stride=40, timed_steps=50, reps=2, cache=path)
     assert again.cached and again.choice == res.choice and again.key == res.key
     assert [r.us_per_step for r in again.rows] == pytest.approx([r.us_per_step for r in res.rows])
     assert time.perf_counter() - t < 5.0
