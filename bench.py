@@ -15,13 +15,16 @@ warm-up steps, then exactly K timed steps in launches of at most --chunk steps,
 bracketed by HIP events on the launch stream.  Inputs and state are resident
 in HBM; nothing crosses PCIe inside the timed region.
 
-Paths on the same cases: FP64, and FP32 applies with FP64 residual refinement
-(warm start, two corrections, "mixed"), each on the panel engine (16-case
-panels, leaf blocks on the matrix cores) and on one workgroup per case.  The
-panel paths' trajectories of sampled cases (every tie-line loss among them)
-are compared with the FP64 CPU oracle over the whole 8000-step horizon; the
-headline is the fastest panel path within 1e-10 (peak-normalised).  The same
-oracle runs are the CPU baseline.  The single 1432-bus case with one loss at
+Paths on the same cases: FP64 solved directly (v = P b), FP64 in the
+incremental form (v = v_prev + P (b - G v_prev), one apply per step), and
+FP32 applies with FP64 residual refinement (warm start, two corrections,
+"mixed"), each on the panel engine (16-case panels, leaf blocks on the matrix
+cores) and on one workgroup per case.  The panel paths' trajectories of
+sampled cases (every tie-line loss, every loss that leaves a bus on its shunt
+capacitor alone, the earliest and latest loss, seeded picks) are compared with
+the FP64 CPU oracle over the whole 8000-step horizon; the headline is the
+fastest panel path within 1e-10 (peak-normalised).  The same oracle runs are
+the CPU baseline.  The single 1432-bus case with one loss at
 step 2000 (10000 steps, one team of workgroups per case) is reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--chunk C]
@@ -46,20 +49,23 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 PRE_ROLL = 5000          # end of the contingency batch's loss window
 HORIZON = 8000           # steps of every contingency case
 N_CASES = 256
-N_SAMPLE = 12          # contingency cases the oracle runs (CPU baseline and accuracy sample)
+N_PICKS = 4            # seeded picks added to the oracle's sample of contingency cases
 
-# HBM traffic of the FP64 panel kernel per launch, from two rocprofv3 --pmc passes over
+# HBM traffic of the headline panel kernel per launch, from two rocprofv3 --pmc passes over
 # `bench.py --gpus 1 --steps 20 --warmup 5 --no-single --no-tune --no-accuracy --copy-probe-mb 512`
 # (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch).  A 512 MiB device copy read 262,156 KiB of
 # FETCH_SIZE and 524,288 KiB of WRITE_SIZE, so FETCH is scaled by 2.0 and WRITE by 1.0.  Keyed by the
 # launch's step count: the 20-step launch of that command, and the steady 500-step launches of its
 # pre-roll (steps 2001-5000).  Valid only while the kernel's sources hash to the profiled ones.
-PANEL_TRAFFIC = {"sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "f58eb33c3c0051bd",
+PANEL_TRAFFIC = {"kernel": "k_emt_panel<double, false, false>",
+                 "sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "f58eb33c3c0051bd",
                  "bytes": {20: 123932672, 500: 1705242556}}
+PANEL_KERNELS = {"panel_fp64": "k_emt_panel<double, false, false>", "panel_fp64_inc": "k_emt_panel<double, true, true>",
+                 "panel_mixed": "k_emt_panel<float, true, true>"}
 
 
-def traffic_bytes(rec, steps_per_launch):
-    if rec is None or steps_per_launch not in rec["bytes"]:
+def traffic_bytes(rec, kernel, steps_per_launch):
+    if rec is None or rec["kernel"] != kernel or steps_per_launch not in rec["bytes"]:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -475,8 +481,10 @@ def contingency_batch(hinv, torch, args, khz):
     base, bcases = cases.cases_c4(n_cases=N_CASES, n_steps=HORIZON)
     losses = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]
     paths = {"panel_fp64": ("panel", "fp64", False, 0, 1e-9),
+             "panel_fp64_inc": ("panel", "fp64", True, 0, 1e-9),
              "panel_mixed": ("panel", "fp32", True, args.max_refine, args.rel_tol),
              "per_case_fp64": ("fused", "fp64", False, 0, 1e-9),
+             "per_case_fp64_inc": ("fused", "fp64", True, 0, 1e-9),
              "per_case_mixed": ("fused", "fp32", True, args.max_refine, args.rel_tol)}
     table, launches = {}, {}
     for name, (eng, prec, warm, mr, tol) in paths.items():
@@ -485,31 +493,39 @@ def contingency_batch(hinv, torch, args, khz):
         region_ms, sizes, launch_ms, clk = run_region(torch, emt, PRE_ROLL, args.warmup, args.steps, args.chunk)
         table[name] = summarize(emt, hinv, N_CASES, PRE_ROLL + args.warmup + args.steps, region_ms, args.steps, clk, sizes, khz,
                                 prec != "fp64")
-        table[name].update(engine=eng, precision=prec if prec == "fp64" else f"{prec} apply + fp64 refinement",
-                           corrections=mr)
+        form = ("fp64, incremental v = v_prev + P (b - G v_prev)" if warm else "fp64, direct v = P b") \
+            if prec == "fp64" else f"{prec} apply + fp64 refinement"
+        table[name].update(engine=eng, precision=form, corrections=mr if prec != "fp64" else 0)
         emt.close()
         launches[name] = (sizes, launch_ms)
 
-    # accuracy of the panel paths over the whole horizon on sampled cases (every tie-line loss, the first
-    # and the last loss step), against the oracle; the same oracle runs are the CPU baseline
+    # accuracy of the panel paths over the whole horizon on sampled cases against the oracle: every
+    # tie-line loss (its correction spans two workgroups), every loss that leaves a bus on its shunt
+    # capacitor alone (that bus keeps its voltage, an undamped mode of the step map along which
+    # rounding accumulates over the rest of the horizon), the first and the last loss step, seeded
+    # picks; the same oracle runs are the CPU baseline
     n_copy_br = 8 * cases.BASE_BRANCHES
     ties = [k for k, c in enumerate(bcases) if int(c.loss_branches[0]) >= n_copy_br]
+    deg = np.bincount(base.frm, minlength=base.n_bus) + np.bincount(base.to, minlength=base.n_bus)
+    floating = [k for k, c in enumerate(bcases)
+                if min(deg[base.frm[c.loss_branches[0]]], deg[base.to[c.loss_branches[0]]]) == 1]
     st = np.array([int(c.loss_steps[0]) for c in bcases])
-    pick = set(ties) | {int(st.argmin()), int(st.argmax())}
+    pick = set(ties) | set(floating) | {int(st.argmin()), int(st.argmax())}
     rest = [k for k in range(N_CASES) if k not in pick]
-    pick |= set(int(k) for k in np.random.default_rng(808).choice(rest, max(0, N_SAMPLE - len(pick)), replace=False))
+    pick |= set(int(k) for k in np.random.default_rng(808).choice(rest, N_PICKS, replace=False))
     sample = sorted(pick)
     refs, cpu_s = oracle_refs(base, bcases, sample, HORIZON)
     if not args.no_accuracy:
-        for name in ("panel_fp64", "panel_mixed"):
+        for name in ("panel_fp64", "panel_fp64_inc", "panel_mixed"):
             eng, prec, warm, mr, tol = paths[name]
             table[name]["err_vs_oracle"] = trajectory_errors(hinv, torch, base, losses, eng, prec, warm, mr, tol,
                                                              refs, HORIZON, args.chunk)
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
     cpu = {"value": round(len(sample) * HORIZON / cpu_s, 1), "unit": "solves/s", "cores": threads, "kind": "oracle",
-           "sample": f"{len(sample)} of the {N_CASES} cases (cases {sample}: every tie-line loss, the earliest and "
-                     f"the latest loss step, seeded picks), each over the full {HORIZON}-step horizon: explicit "
-                     f"FP64 inverse times the current vector per step, re-inversion at the loss; {cpu_s:.2f} s"}
+           "sample": f"{len(sample)} of the {N_CASES} cases (cases {sample}: every tie-line loss, every loss that "
+                     f"leaves a bus on its shunt capacitor alone, the earliest and the latest loss step, {N_PICKS} "
+                     f"seeded picks), each over the full {HORIZON}-step horizon: explicit FP64 inverse times the "
+                     f"current vector per step, re-inversion at the loss; {cpu_s:.2f} s"}
     del refs
 
     H = hinv.Hierarchy.from_network(base)
@@ -674,23 +690,22 @@ def main():
                             "FP32 + FP64 refinement"}
 
     # headline: the fastest panel path whose sampled trajectories meet 1e-10 (peak-normalised)
-    cand = ["panel_fp64", "panel_mixed"]
+    cand = ["panel_fp64", "panel_fp64_inc", "panel_mixed"]
     ok = [k for k in cand if "err_vs_oracle" in table[k] and table[k]["err_vs_oracle"]["peak_norm"] <= 1e-10]
-    head = max(ok or ["panel_fp64"], key=lambda k: table[k]["solves_per_s"])
+    head = max(ok or ["panel_fp64_inc"], key=lambda k: table[k]["solves_per_s"])
     hp = table[head]
-    prec_h = "fp64" if head.endswith("fp64") else "fp32"
+    prec_h = "fp32" if head == "panel_mixed" else "fp64"
     sizes_l, launch_ms = launches[head]
     # algorithmic matrix work: 2 flops per stored entry per case per apply (the leaf blocks, Z panels and
     # capacitance inverses of the 1432-bus hierarchy)
     flops = [2.0 * entries * N_CASES * hp["applies_per_step"] * k for k in sizes_l]
     achieved = sum(flops) / (sum(launch_ms) * 1e-3) / 1e12
     peak = MFMA_PEAK_TFLOPS[prec_h]
-    kname = "k_emt_panel<double, false, false>" if prec_h == "fp64" else "k_emt_panel<float, true, true>"
+    kname = PANEL_KERNELS[head]
     full = [m for k, m in zip(sizes_l, launch_ms) if k == args.chunk]
     launch_steps = args.chunk if full else sizes_l[0]
-    two = {"fp64": {"per_case": table["per_case_fp64"]["solves_per_s"], "panel": table["panel_fp64"]["solves_per_s"]},
-           "mixed": {"per_case": table["per_case_mixed"]["solves_per_s"],
-                     "panel": table["panel_mixed"]["solves_per_s"]}}
+    two = {form: {"per_case": table[f"per_case_{form}"]["solves_per_s"], "panel": table[f"panel_{form}"]["solves_per_s"]}
+           for form in ("fp64", "fp64_inc", "mixed")}
     line = {
         "metric": METRIC,
         "value": hp["solves_per_s"],
@@ -716,7 +731,7 @@ def main():
         "p99_step_us": hp["p99_step_us"],
         "latency_note": "GPU wall-clock stamp after each step of workgroup 0; one step advances all 256 cases",
         "paths": table,
-        "table_2x2_solves_per_s": two,
+        "table_solves_per_s": two,
         "single_case": single,
         "tuner": tuner,
         "torus_11456": study,
@@ -732,7 +747,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5),
-            "traffic": traffic_bytes(PANEL_TRAFFIC, launch_steps) if head == "panel_fp64" else None,
+            "traffic": traffic_bytes(PANEL_TRAFFIC, kname, launch_steps),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flops_per_step": 2.0 * entries * N_CASES * hp["applies_per_step"],
             "launch_ms_mean": round(float(np.mean(full or launch_ms)), 4),

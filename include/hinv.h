@@ -93,7 +93,13 @@ typedef struct {
                               HINV_COUPLING_PAPER only) */
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
-    int32_t warm_start;    /* EMT, mixed precision: refine from the previous step's v instead of P b */
+    int32_t warm_start;    /* EMT, FP32/BF16/FP8 storage: refine from the previous step's v instead of
+                              P b.  FP64 storage, engines 2 and 4: the incremental form
+                              v = v_prev + P (b - G v_prev), one FP64 apply per step (max_refine and
+                              rel_tol unused); equal to P b in exact arithmetic, it keeps rounding from
+                              accumulating along a mode the step map does not damp (a bus whose only
+                              line is lost keeps its voltage on its shunt capacitor).  FP64 on the
+                              other engines solves directly. */
     int32_t kernel_mode;   /* EMT engine: 0 = automatic (one case: 3, else 5, when it fits;
                               several cases: 4 when it fits; else 2 when it fits, else 1); 1 = one
                               launch per kernel per step (any size); 2 = one fused launch per
@@ -411,6 +417,31 @@ hinv_status emt_sync_status(emt_handle c);
 
 /* Index of the next step to be computed (1 after emt_create). */
 hinv_status emt_get_step(emt_handle c, int64_t* step);
+
+/* Checkpoint and resume of the time loop (Eq. (1)-(2): the state that carries
+ * one step into the next).  A state holds the next step's index, every case's
+ * right-hand side b, voltages v (the warm start of the refined paths),
+ * capacitor histories (rows in the network's bus order) and branch histories
+ * (the network's branch order), every case's line losses (step, branch:
+ * scheduled, past and dynamic ones alike) and the base-matrix changes made by
+ * emt_update_line since emt_create, with a fingerprint of the network.
+ * emt_state_size: bytes of the handle's current state (host only).
+ * emt_save_state: synchronises the stream, then copies the state into `buf`
+ * (host memory, caller-owned, >= emt_state_size bytes).
+ * emt_load_state: resumes a handle created on the same network (any tree,
+ * engine or precision) from a state: the handle's base-matrix changes must be
+ * the first ones of the state's (the rest are applied with emt_update_line),
+ * its cases take the state's line losses and vectors, and its next step is
+ * the state's.  With the same tree, engine and precision the resumed run
+ * equals the uninterrupted one bitwise.  HINV_E_INVALID for a buffer that is
+ * too short or not a state of this library, another network, case count or
+ * phase count, or diverging base-matrix changes; HINV_E_RANK_LIMIT when a
+ * case has more losses than the handle's max_mod_rank holds; the handle is
+ * unchanged after these.  Errors while applying the state (HINV_E_NOT_SPD,
+ * HINV_E_DEVICE) can leave it partly loaded.  Synchronises the stream. */
+hinv_status emt_state_size(emt_handle c, size_t* bytes);
+hinv_status emt_save_state(emt_handle c, void* buf, size_t bytes, void* stream);
+hinv_status emt_load_state(emt_handle c, const void* buf, size_t bytes, void* stream);
 
 /* Refinement statistics since emt_create (mixed precision): total applies,
  * largest final ||dv||/||v|| seen.  Synchronises nothing; call after the

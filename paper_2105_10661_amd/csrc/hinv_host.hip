@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cstring>
+
 #include <algorithm>
 #include <memory>
 #include <mutex>
@@ -1374,6 +1376,14 @@ struct emt_ctx {
     std::vector<double> y3, a3, z3;
     double* m_d3 = nullptr;
     double* m_dinv3 = nullptr;
+    // checkpoints: fingerprint of the caller's network and the base-matrix changes made since creation
+    uint64_t net_hash = 0;
+    std::string table_error;     // first failed bounds check of an engine's tables (empty: all in bounds)
+    struct BaseChange {
+        int32_t a, b;
+        double dg;
+    };
+    std::vector<BaseChange> base_log;
 };
 
 // Three-phase network parameters of emt3_create.
@@ -1701,17 +1711,20 @@ hinv_status emt_plan(const emt_network* N, const hinv_tree* T, const hinv_option
             c.team_nx_cap = c.TD.NX + 2 * c.R;      // room for the endpoints of later line losses
             c.team_ok = build_team_plan(c, c.R);
         }
+        if (!c.table_error.empty()) return fail(HINV_E_DEVICE, "team tables: %s", c.table_error.c_str());
         if (c.team_ok) carve_team(c, A);
     }
     c.panel_ok = false;
     if (((mode == 0 && c.n_cases > 1) || mode == 4) && fused_prec) {
         c.panel_ok = build_panel_plan(c, c.R);
+        if (!c.table_error.empty()) return fail(HINV_E_DEVICE, "panel tables: %s", c.table_error.c_str());
         if (c.panel_ok) carve_panel(c, A);
     }
     c.level_ok = false;
     if (((mode == 0 && c.n_cases == 1 && !c.team_ok) || mode == 5) && fused_prec) {
         c.level_nx_cap = 0;
         c.level_ok = build_level_plan(c, c.R);
+        if (!c.table_error.empty()) return fail(HINV_E_DEVICE, "level tables: %s", c.table_error.c_str());
         if (c.level_ok) carve_level(c, A);
     }
     const bool fits = run_fits(c.hc.H) && fused_prec;
@@ -1778,8 +1791,107 @@ hinv_status emt_plan3(const emt_network* N, const Phase3& p3, const hinv_tree* T
 
 // ---------------------------------------------------------------------------
 // Team plan: per-leaf tables of the team engine (one case; see k_team.hip).
+// Bounds check of the team engine's tables (see check_panel_tables).
+std::string check_team_tables(const emt_ctx& c)
+{
+    const Plan& P = c.hc.P;
+    const TeamDev& D = c.TD;
+    const int L = D.T, H = D.H, Hs = std::max(H, 1), n = c.n, nc = D.nc;
+    char buf[256];
+    auto bad = [&](const char* fmt, auto... a) {
+        snprintf(buf, sizeof buf, fmt, a...);
+        return std::string(buf);
+    };
+    auto mono = [&](const std::vector<int>& a, size_t at, int cnt, int cap) {
+        if (a[at] != 0) return false;
+        for (int i = 0; i < cnt; ++i)
+            if (a[at + i + 1] < a[at + i]) return false;
+        return a[at + cnt] <= cap;
+    };
+    const int npan = (int)P.pan_lo.size();
+    for (int l = 0; l < L; ++l) {
+        const int lo = c.tw_lo[l], nl = c.tw_nl[l], nx = c.tw_nx[l], nb = c.tw_nb[l], nxu = c.tw_nxu[l], ny = c.tw_ny[l];
+        const int ncomb = nl + nx;
+        if (lo < 0 || nl < 1 || nl > D.NL || lo + nl > n || nx < 0 || nx > D.NX || nb < 0 || nb > D.NB || nxu < 0 ||
+            nxu > nx || ny < 0 || ny > D.NY)
+            return bad("leaf %d: counts out of range (lo %d nl %d nx %d nb %d nxu %d ny %d)", l, lo, nl, nx, nb, nxu, ny);
+        int xz = 0;
+        for (int x = 0; x < nx; ++x) {
+            const int r = c.txrow[(size_t)l * D.NX + x];
+            if (r < 0 || r >= n || (x > 0 && r <= c.txrow[(size_t)l * D.NX + x - 1]))
+                return bad("leaf %d: X row %d (row %d) out of range or order", l, x, r);
+            for (int h = 0; h < H; ++h) {
+                const size_t i = ((size_t)l * D.NX + x) * H + h;
+                const int zo = c.txzo[i], pm = c.txpm[i], pc = c.txpc[i], pp = c.txpan[i];
+                if (zo < 0) continue;
+                if (pm < 1 || zo + pm > D.XZ || pc < 0 || pc + pm > nc || pp < 0 || pp >= npan)
+                    return bad("leaf %d X row %d level %d: Z values (offset %d, %d columns from %d) out of bounds", l,
+                               x, h, zo, pm, pc);
+                xz = std::max(xz, zo + pm);
+            }
+        }
+        for (int q = 0; q < nxu; ++q) {
+            const int x = c.txupd[(size_t)l * D.NX + q];
+            if (x < 0 || x >= nx) return bad("leaf %d: updated X row %d out of range", l, x);
+            for (int h = 0; h < H; ++h) {
+                const int uo = c.tuzo[((size_t)l * D.NX + q) * H + h];
+                const int pm = c.txpm[((size_t)l * D.NX + x) * H + h];
+                if (uo >= 0 && uo + pm > D.XZU) return bad("leaf %d: updated X row %d Z offset %d beyond %d", l, q, uo, D.XZU);
+            }
+        }
+        for (int h = 0; h < H; ++h) {
+            const size_t i = (size_t)l * H + h;
+            const int zo = c.tozo[i], pm = c.topm[i], pc = c.topc[i];
+            if (zo >= 0 && (pm < 1 || (int64_t)zo + (int64_t)pm * nl > D.ZO || pc < 0 || pc + pm > nc))
+                return bad("leaf %d level %d: own Z rows (offset %d, %d columns from %d) out of bounds", l, h, zo, pm, pc);
+        }
+        for (int g = 0; g < nc; ++g) {
+            const int x = c.txpos[(size_t)l * nc + g];
+            if (x < 0 || x >= nx || c.txrow[(size_t)l * D.NX + x] != P.col_row[g])
+                return bad("leaf %d: column %d maps to X row %d, not its row", l, g, x);
+            const int so = c.ttcso[(size_t)l * nc + g], ld = c.ttcld[(size_t)l * nc + g];
+            if (so >= 0) {
+                const int m = P.node_m[P.col_node[g]];
+                if (ld < 2 || (int64_t)so + (int64_t)(m - 1) * ld >= D.sent)
+                    return bad("leaf %d: S^-1 row of column %d (offset %d, stride %d) beyond %d entries", l, g, so, ld,
+                               D.sent);
+            }
+        }
+        for (int q = 0; q < ny; ++q) {
+            const int g = c.tylist[(size_t)l * nc + q];
+            if (g < 0 || g >= nc || c.ttcso[(size_t)l * nc + g] < 0)
+                return bad("leaf %d: y list entry %d (column %d) has no S^-1 row", l, q, g);
+        }
+        const size_t rb = (size_t)l * (D.NL + 1);
+        if (!mono(c.torp, rb, nl, D.NE) || !mono(c.tiptr, rb, nl, D.NI) || !mono(c.tsptr, rb, nl, D.NS))
+            return bad("leaf %d: row pointers not monotone or beyond their tables", l);
+        for (int e = 0; e < c.torp[rb + nl]; ++e)
+            if (c.tocol[(size_t)l * D.NE + e] < 0 || c.tocol[(size_t)l * D.NE + e] >= ncomb)
+                return bad("leaf %d: residual column %d out of range", l, c.tocol[(size_t)l * D.NE + e]);
+        for (int e = 0; e < c.tiptr[rb + nl]; ++e)
+            if (c.tibr[(size_t)l * D.NI + e] < 0 || c.tibr[(size_t)l * D.NI + e] >= nb)
+                return bad("leaf %d: incident branch %d beyond %d branches", l, c.tibr[(size_t)l * D.NI + e], nb);
+        for (int q = 0; q < nb; ++q) {
+            const size_t i = (size_t)l * D.NB + q;
+            if (c.tbglob[i] < 0 || c.tbglob[i] >= c.nbr || c.tbf[i] < 0 || c.tbf[i] >= ncomb || c.tbt[i] < 0 ||
+                c.tbt[i] >= ncomb)
+                return bad("leaf %d: branch %d (global %d, ends %d %d) out of range", l, q, c.tbglob[i], c.tbf[i], c.tbt[i]);
+        }
+    }
+    for (int g = 0; g < nc; ++g) {
+        if (c.taoff[g] < 0 || c.talen[g] < 0 || c.taoff[g] + c.talen[g] > D.nA || c.talo[g] < 0 ||
+            c.talo[g] + c.talen[g] > nc)
+            return bad("row a_g of column %d (offset %d, columns %d+%d) out of bounds", g, c.taoff[g], c.talo[g], c.talen[g]);
+        for (int h = 0; h < Hs; ++h)
+            if (c.tcpan[(size_t)g * Hs + h] < -1 || c.tcpan[(size_t)g * Hs + h] >= npan)
+                return bad("column %d: panel %d at level %d out of range", g, c.tcpan[(size_t)g * Hs + h], h);
+    }
+    return std::string();
+}
+
 bool build_team_plan(emt_ctx& c, int R)
 {
+    c.table_error.clear();
     const Plan& P = c.hc.P;
     const int L = (int)P.leaf_lo.size(), H = P.n_levels, n = c.n;
     const int NC = (int)P.col_row.size();
@@ -2050,7 +2162,8 @@ bool build_team_plan(emt_ctx& c, int R)
     flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
     D.NX = NXc;   // strides of the device tables (and the LDS layout)
     if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
-    return true;
+    c.table_error = check_team_tables(c);
+    return c.table_error.empty();
 }
 
 // Workspace for the team tables (sizes from the current plan, X rows with capacity).
@@ -2084,11 +2197,125 @@ void carve_team(emt_ctx& c, Arena& A)
 }
 
 // ---------------------------------------------------------------------------
+// Bounds check of the panel engine's tables against the sizes the kernel and its LDS layout assume:
+// every index a workgroup uses to address LDS, its registers' item ranges or a global array is
+// within the region it addresses.  Returns the first violation (empty: none).  Host only, so it runs
+// in emt_workspace_size as well as before every upload.
+std::string check_panel_tables(const emt_ctx& c, int R)
+{
+    const Plan& P = c.hc.P;
+    const PanelDev& D = c.PD;
+    const int L = D.T, Hs = std::max(D.H, 1), n = c.n, nc = D.nc;
+    char buf[256];
+    auto bad = [&](const char* fmt, auto... a) {
+        snprintf(buf, sizeof buf, fmt, a...);
+        return std::string(buf);
+    };
+    int64_t zsize = 0;
+    for (size_t p = 0; p < P.pan_zoff.size(); ++p) zsize = std::max(zsize, P.pan_zoff[p] + (int64_t)P.pan_n[p] * P.pan_m[p]);
+    if (D.NL < 1 || D.NL > kPanelMaxLeaf || D.NLp % 16 || D.NLp < D.NL || D.NX > kPanelMaxX || nc > kPanelMaxCols ||
+        D.ncp < nc || D.ncp % 4 || D.NB * kPanelCases > 6 * kPanelWaves * 64 || R > kPanelMaxRank ||
+        L * std::max(R, 1) * kPanelCases > kPanelWaves * 64 || D.NY % 16 || D.MF % 64)
+        return bad("panel dimensions NL %d NLp %d NX %d NB %d nc %d ncp %d NY %d MF %d outside the kernel's limits",
+                   D.NL, D.NLp, D.NX, D.NB, nc, D.ncp, D.NY, D.MF);
+    auto mono = [&](const std::vector<int>& a, size_t at, int cnt, int cap) {
+        if (a[at] != 0) return false;
+        for (int i = 0; i < cnt; ++i)
+            if (a[at + i + 1] < a[at + i]) return false;
+        return a[at + cnt] <= cap;
+    };
+    for (int l = 0; l < L; ++l) {
+        const int lo = c.tw_lo[l], nl = c.tw_nl[l], nx = c.pw_nx[l], nb = c.tw_nb[l], ny = c.pw_ny[l],
+                  nt = c.pw_nt[l], np = c.pw_np[l], nxz = c.pw_xz[l];
+        const int ncomb = nl + nx;
+        if (lo < 0 || nl < 1 || nl > D.NL || lo + nl > n || nx < 0 || nx > D.NX || nb < 0 || nb > D.NB || ny < 0 ||
+            ny > D.NY || ny % 16 || nt < 0 || nt > D.NT || nt > kPanelWaves * kPanelYTasksPerWave || np < 0 ||
+            np > D.NP || nxz < 0 || nxz > D.XZ || ncomb >= (1 << 16))
+            return bad("leaf %d: counts out of range (lo %d nl %d nx %d nb %d ny %d nt %d np %d xz %d)", l, lo, nl, nx,
+                       nb, ny, nt, np, nxz);
+        for (int x = 0; x < nx; ++x) {
+            const int r = c.pxrow[(size_t)l * D.NX + x], g = c.pxcol[(size_t)l * D.NX + x];
+            if (r < 0 || r >= n || (r >= lo && r < lo + nl) || g < 0 || g >= nc || P.col_row[g] != r)
+                return bad("leaf %d: X row %d (row %d, column %d) invalid", l, x, r, g);
+        }
+        for (int h = 0; h < Hs; ++h) {
+            const size_t i = (size_t)l * Hs + h;
+            const int zo = c.tozo[i], pm = c.topm[i], ps = c.topc[i];
+            if (zo >= 0 && (pm < 1 || (int64_t)zo + (int64_t)pm * nl > D.ZO || ps < 0 || ps + pm > ny))
+                return bad("leaf %d level %d: own Z rows (offset %d, %d columns, slot %d) out of bounds", l, h, zo, pm, ps);
+            for (int x = 0; x < nx; ++x) {
+                const size_t j = ((size_t)l * D.NX + x) * Hs + h;
+                const int xo = c.pxzo[j], xm = c.pxpm[j], xs = c.pxps[j];
+                if (xo >= 0 && (xm < 1 || xo + xm > nxz || xs < 0 || xs + xm > ny))
+                    return bad("leaf %d X row %d level %d: Z values (offset %d, %d columns, slot %d) out of bounds", l, x,
+                               h, xo, xm, xs);
+            }
+        }
+        for (int i = 0; i < nxz; ++i) {
+            const int z = c.pxzsrc[(size_t)l * D.XZ + i];
+            if (z < 0 || z >= zsize) return bad("leaf %d: X-row Z source %d outside the Z panels", l, z);
+        }
+        const size_t rb = (size_t)l * (D.NL + 1);
+        if (!mono(c.torp, rb, nl, D.NE) || !mono(c.tiptr, rb, nl, D.NI) || !mono(c.tsptr, rb, nl, D.NS))
+            return bad("leaf %d: row pointers not monotone or beyond their tables", l);
+        for (int e = 0; e < c.torp[rb + nl]; ++e)
+            if (c.tocol[(size_t)l * D.NE + e] < 0 || c.tocol[(size_t)l * D.NE + e] >= ncomb)
+                return bad("leaf %d: residual column %d out of range", l, c.tocol[(size_t)l * D.NE + e]);
+        for (int e = 0; e < c.tiptr[rb + nl]; ++e) {
+            const int v = c.tibr[(size_t)l * D.NI + e], lb = v >= 0 ? v : ~v;
+            if (lb >= nb) return bad("leaf %d: incident branch %d beyond %d branches", l, lb, nb);
+        }
+        for (int q = 0; q < nb; ++q) {
+            const size_t i = (size_t)l * D.NB + q;
+            const int f = c.phbft[i] & 0xffff, t = c.phbft[i] >> 16;
+            if (c.tbglob[i] < 0 || c.tbglob[i] >= c.nbr || f >= ncomb || t >= ncomb || f != c.tbf[i] || t != c.tbt[i])
+                return bad("leaf %d: branch %d (global %d, ends %d %d) out of range", l, q, c.tbglob[i], f, t);
+        }
+        for (int q = 0; q < np; ++q) {
+            const int r = c.ppubr[(size_t)l * D.NP + q], g = c.ppubg[(size_t)l * D.NP + q];
+            if (r < 0 || r >= nl || g < 0 || g >= nc) return bad("leaf %d: published pair (%d, %d) out of range", l, r, g);
+        }
+        for (int q = 0; q < ny; ++q) {
+            const int g = c.pyslot[(size_t)l * D.NY + q];
+            if (g < -1 || g >= nc) return bad("leaf %d: y slot %d holds column %d", l, q, g);
+        }
+        const int ntile = ny / 16;
+        if (c.pttp[(size_t)l * (D.NY / 16 + 1)] != 0 || c.pttp[(size_t)l * (D.NY / 16 + 1) + ntile] != nt)
+            return bad("leaf %d: task pointers do not cover the %d tasks", l, nt);
+        for (int t = 0; t < ntile; ++t)
+            if (c.pttp[(size_t)l * (D.NY / 16 + 1) + t + 1] < c.pttp[(size_t)l * (D.NY / 16 + 1) + t])
+                return bad("leaf %d: task pointers not monotone", l);
+        std::vector<int> seen(nt, 0);
+        for (int t = 0; t < nt; ++t) {
+            const size_t i = (size_t)l * D.NT + t;
+            const int k0 = c.ptk0[i], nk = c.ptnk[i], fo = c.ptfo[i], tile = c.pttile[i], tl = c.pttl[i];
+            if (k0 < 0 || nk < 1 || (k0 + nk) * 4 > D.ncp || fo < 0 || fo % 64 || fo + nk * 64 > D.MF || tile < 0 ||
+                tile >= ntile || tl < 0 || tl >= nt)
+                return bad("leaf %d: y task %d (k %d+%d, fragments %d, tile %d) out of bounds", l, t, k0, nk, fo, tile);
+        }
+        for (int w = 0; w < kPanelWaves * kPanelYTasksPerWave; ++w) {
+            const int t = c.pwtask[(size_t)l * kPanelWaves * kPanelYTasksPerWave + w];
+            if (t < -1 || t >= nt || (t >= 0 && seen[t]++)) return bad("leaf %d: wavefront task slot %d holds %d", l, w, t);
+        }
+        for (int t = 0; t < nt; ++t)
+            if (!seen[t]) return bad("leaf %d: y task %d has no wavefront", l, t);
+    }
+    for (size_t i = 0; i < c.plpa.size(); ++i) {
+        const int tl = (int)(i / ((size_t)kPanelCases * R)) % L;
+        const int ncomb = c.tw_nl[tl] + c.pw_nx[tl];
+        if (c.plpa[i] < -1 || c.plpa[i] >= ncomb || c.plpb[i] < -1 || c.plpb[i] >= ncomb)
+            return bad("change endpoint rows (%d, %d) out of range", c.plpa[i], c.plpb[i]);
+    }
+    return std::string();
+}
+
+// ---------------------------------------------------------------------------
 // Panel plan: per-leaf tables (shared with the team layout's per-leaf vectors;
 // an EMT handle uses one of the two engines), per (team, leaf) X rows and
 // change endpoints, and the coupling columns' lower-level Z rows.
 bool build_panel_plan(emt_ctx& c, int R)
 {
+    c.table_error.clear();
     const Plan& P = c.hc.P;
     const int L = (int)P.leaf_lo.size(), H = P.n_levels, NC = (int)P.col_row.size();
     // one thread per (workgroup, change, case) gathers the shares of u^T x
@@ -2360,8 +2587,9 @@ bool build_panel_plan(emt_ctx& c, int R)
     D.NY = NY; D.NT = NT; D.MF = MF; D.NP = NP;
     D.n_teams = n_teams; D.team0 = 0;
     D.ysep = 1;              // a region of its own for the y results if LDS allows, else they overwrite u
-    if (panel_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) D.ysep = 0;
-    if (panel_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) return false;
+    const int warm = c.hc.opt.warm_start ? 1 : 0;
+    if (panel_lds_bytes(D, R, c.hc.opt.prec, warm) > 160 * 1024) D.ysep = 0;
+    if (panel_lds_bytes(D, R, c.hc.opt.prec, warm) > 160 * 1024) return false;
     auto flat = [&](std::vector<int>& dst, size_t stride, int fill, auto get) {
         dst.assign((size_t)L * stride, fill);
         for (int l = 0; l < L; ++l) {
@@ -2427,7 +2655,8 @@ bool build_panel_plan(emt_ctx& c, int R)
     c.phlost = std::move(hlost);
     c.pw_xz.resize(L);
     for (int l = 0; l < L; ++l) c.pw_xz[l] = ws[l].xz;
-    return true;
+    c.table_error = check_panel_tables(c, R);
+    return c.table_error.empty();
 }
 
 // Workspace for the panel tables.
@@ -2459,7 +2688,7 @@ void carve_panel(emt_ctx& c, Arena& A)
     D.cpan = ti((int64_t)std::max(D.nc, 1) * H);
     D.am = td((int64_t)std::max(D.nc, 1) * std::max(D.nc, 1));
     D.bm = td((int64_t)std::max(D.nc, 1) * std::max(D.nc, 1));
-    D.imgb = panel_image_bytes(D, (int)R, c.hc.opt.prec);
+    D.imgb = panel_image_bytes(D, (int)R, c.hc.opt.prec, c.hc.opt.warm_start ? 1 : 0);
     D.img = A.take<unsigned char>(L * (int64_t)D.imgb);
     D.sync = A.take<unsigned int>(TW);
     D.X0 = td((int64_t)D.n_teams * 2 * std::max(D.nc, 1) * kPanelCases);
@@ -2473,7 +2702,7 @@ hinv_status build_panel_map(emt_ctx& c, hipStream_t s)
     PanelDev& D = c.PD;
     HIP_TRY(launch_coupling_map(c.hc.H, D.H, D.nc, D.cpan, D.am, D.bm, s));
     HIP_TRY(launch_panel_mfrag(D, s));
-    HIP_TRY(launch_panel_image(D, c.E, c.hc.H, c.R, c.hc.opt.prec, s));
+    HIP_TRY(launch_panel_image(D, c.E, c.hc.H, c.R, c.hc.opt.prec, c.hc.opt.warm_start ? 1 : 0, s));
     HIP_TRY(hipStreamSynchronize(s));
     return HINV_OK;
 }
@@ -2513,8 +2742,73 @@ hinv_status upload_panel(emt_ctx& c, hipStream_t s)
 // Level plan (one case): per leaf its own rows, owned coupling columns per level with their
 // S^{-1} rows, own Z panels, X rows (neighbours through G, then line-loss endpoints), CSR rows,
 // branches and sources.  Per-leaf tables share the team layout's per-leaf vectors.
+// Bounds check of the level engine's tables (see check_panel_tables).
+std::string check_level_tables(const emt_ctx& c, int R)
+{
+    const Plan& P = c.hc.P;
+    const LevelDev& D = c.LD;
+    const int L = D.T, H = D.H, Hs = std::max(H, 1), n = c.n, nc = (int)P.col_row.size();
+    char buf[256];
+    auto bad = [&](const char* fmt, auto... a) {
+        snprintf(buf, sizeof buf, fmt, a...);
+        return std::string(buf);
+    };
+    auto mono = [&](const std::vector<int>& a, size_t at, int cnt, int cap) {
+        if (a[at] != 0) return false;
+        for (int i = 0; i < cnt; ++i)
+            if (a[at + i + 1] < a[at + i]) return false;
+        return a[at + cnt] <= cap;
+    };
+    for (int l = 0; l < L; ++l) {
+        const int lo = c.tw_lo[l], nl = c.tw_nl[l], nx = c.lw_nx[l], nb = c.tw_nb[l];
+        const int ncomb = nl + nx;
+        if (lo < 0 || nl < 1 || nl > D.NL || lo + nl > n || nx < 0 || nx > D.NX || nb < 0 || nb > D.NB)
+            return bad("leaf %d: counts out of range (lo %d nl %d nx %d nb %d)", l, lo, nl, nx, nb);
+        for (int x = 0; x < nx; ++x) {
+            const int r = c.lxrow[(size_t)l * D.NX + x];
+            if (r < 0 || r >= n || (r >= lo && r < lo + nl)) return bad("leaf %d: X row %d (row %d) invalid", l, x, r);
+        }
+        for (int h = 0; h < H; ++h) {
+            const size_t i = (size_t)l * Hs + h;
+            const int zo = c.tozo[i], pm = c.topm[i], pc = c.topc[i];
+            if (zo >= 0 && (pm < 1 || pm > D.PM || (int64_t)zo + (int64_t)pm * nl > D.ZO || pc < 0 || pc + pm > nc))
+                return bad("leaf %d level %d: own Z rows (offset %d, %d columns from %d) out of bounds", l, h, zo, pm, pc);
+        }
+        if (!mono(c.loptr, (size_t)l * (H + 1), H, D.NO)) return bad("leaf %d: owned-column pointers invalid", l);
+        for (int q = 0; q < c.loptr[(size_t)l * (H + 1) + H]; ++q) {
+            const size_t i = (size_t)l * D.NO + q;
+            const int g = c.locl[i], r = c.lorow[i], so = c.losoff[i];
+            if (g < 0 || g >= nc || r < 0 || r >= nl || P.col_row[g] != lo + r || so < 0 ||
+                so + P.node_m[P.col_node[g]] > D.SO)
+                return bad("leaf %d: owned column %d (column %d, row %d, S^-1 offset %d) out of bounds", l, q, g, r, so);
+        }
+        const size_t rb = (size_t)l * (D.NL + 1);
+        if (!mono(c.torp, rb, nl, D.NE) || !mono(c.tiptr, rb, nl, D.NI) || !mono(c.tsptr, rb, nl, D.NS))
+            return bad("leaf %d: row pointers not monotone or beyond their tables", l);
+        for (int e = 0; e < c.torp[rb + nl]; ++e)
+            if (c.tocol[(size_t)l * D.NE + e] < 0 || c.tocol[(size_t)l * D.NE + e] >= ncomb)
+                return bad("leaf %d: residual column %d out of range", l, c.tocol[(size_t)l * D.NE + e]);
+        for (int e = 0; e < c.tiptr[rb + nl]; ++e)
+            if (c.tibr[(size_t)l * D.NI + e] < 0 || c.tibr[(size_t)l * D.NI + e] >= nb)
+                return bad("leaf %d: incident branch %d beyond %d branches", l, c.tibr[(size_t)l * D.NI + e], nb);
+        for (int q = 0; q < nb; ++q) {
+            const size_t i = (size_t)l * D.NB + q;
+            if (c.tbglob[i] < 0 || c.tbglob[i] >= c.nbr || c.tbf[i] < 0 || c.tbf[i] >= ncomb || c.tbt[i] < 0 ||
+                c.tbt[i] >= ncomb)
+                return bad("leaf %d: branch %d (global %d, ends %d %d) out of range", l, q, c.tbglob[i], c.tbf[i], c.tbt[i]);
+        }
+        for (int j = 0; j < R; ++j) {
+            const int a = c.llpa[(size_t)l * R + j], b = c.llpb[(size_t)l * R + j];
+            if (a < -1 || a >= ncomb || b < -1 || b >= ncomb)
+                return bad("leaf %d: change %d endpoint rows (%d, %d) out of range", l, j, a, b);
+        }
+    }
+    return std::string();
+}
+
 bool build_level_plan(emt_ctx& c, int R)
 {
+    c.table_error.clear();
     const Plan& P = c.hc.P;
     const int L = (int)P.leaf_lo.size(), H = P.n_levels, NC = (int)P.col_row.size();
     if (c.n_cases != 1 || L < 1 || L > 256 || H < 0 || H > 7) return false;   // y tags hold the level in 3 bits
@@ -2672,7 +2966,8 @@ bool build_level_plan(emt_ctx& c, int R)
     flatd(c.tbal, NB, [](W& w) -> std::vector<double>& { return w.bal; });
     flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
     flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
-    return true;
+    c.table_error = check_level_tables(c, R);
+    return c.table_error.empty();
 }
 
 void carve_level(emt_ctx& c, Arena& A)
@@ -2818,14 +3113,19 @@ hinv_status load_case_losses(emt_ctx& c, const std::vector<int>& which, hipStrea
         HIP_TRY(hipMemcpyAsync((void*)(c.E.loss_cnt + k), &cnt, sizeof(int), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));     // host vectors above are loop-local
     }
+    // u = G0^{-1} w of every change, in groups of at most max_nrhs columns (the scratch X, Xo and Y hold
+    // that many; a handle's changes can outnumber them once dynamic losses are added).  The apply treats
+    // every column alone, so the grouping does not change any bit of u.
     const int nc = (int)cols.size();
-    if (nc > 0) {
-        HIP_TRY(hipMemcpyAsync(h.X, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice, s));
-        launch_apply(h.H, h.P.lv.data(), HINV_FP64, h.X, h.Xo, h.Y, nc, s);
-        for (int q = 0; q < nc; ++q) {
-            double* dst = h.M.U + (int64_t)cols[q] * n;
+    const int cap = std::max(1, h.opt.max_nrhs);
+    for (int q0 = 0; q0 < nc; q0 += cap) {
+        const int m = std::min(cap, nc - q0);
+        HIP_TRY(hipMemcpyAsync(h.X, W.data() + (size_t)q0 * n, sizeof(double) * (size_t)m * n, hipMemcpyHostToDevice, s));
+        launch_apply(h.H, h.P.lv.data(), HINV_FP64, h.X, h.Xo, h.Y, m, s);
+        for (int q = 0; q < m; ++q) {
+            double* dst = h.M.U + (int64_t)cols[q0 + q] * n;
             HIP_TRY(hipMemcpyAsync(dst, h.Xo + (int64_t)q * n, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-            if (h.M.U32) launch_to_f32(dst, h.M.U32 + (int64_t)cols[q] * n, n, s);
+            if (h.M.U32) launch_to_f32(dst, h.M.U32 + (int64_t)cols[q0 + q] * n, n, s);
         }
     }
     HIP_TRY(hipMemsetAsync(h.d_flags, 0, sizeof(int), s));
@@ -2846,21 +3146,27 @@ hinv_status refresh_engine_tables(emt_ctx& c, hipStream_t s)
 {
     hinv_status st = HINV_OK;
     if (c.engine == 3) {
-        if (!build_team_plan(c, c.R)) {
+        const bool ok = build_team_plan(c, c.R);
+        if (!c.table_error.empty()) return fail(HINV_E_DEVICE, "team tables: %s", c.table_error.c_str());
+        if (!ok) {
             c.engine = run_fits(c.hc.H) ? 2 : 1;
             c.team_ok = false;
         } else {
             st = upload_team(c, s);
         }
     } else if (c.engine == 5) {
-        if (!build_level_plan(c, c.R)) {
+        const bool ok = build_level_plan(c, c.R);
+        if (!c.table_error.empty()) return fail(HINV_E_DEVICE, "level tables: %s", c.table_error.c_str());
+        if (!ok) {
             c.engine = run_fits(c.hc.H) ? 2 : 1;
             c.level_ok = false;
         } else {
             st = upload_level(c, s);
         }
     } else if (c.engine == 4) {
-        if (!build_panel_plan(c, c.R)) {
+        const bool ok = build_panel_plan(c, c.R);
+        if (!c.table_error.empty()) return fail(HINV_E_DEVICE, "panel tables: %s", c.table_error.c_str());
+        if (!ok) {
             c.engine = run_fits(c.hc.H) ? 2 : 1;
             c.panel_ok = false;
         } else {
@@ -2939,6 +3245,41 @@ hinv_status emt_workspace_size(const emt_network* net, const hinv_tree* tree, co
     return emt_plan(net, tree, opt, cases, *c, rp, ci, cv, bytes);
 }
 
+// FNV-1a over the bytes of the caller's network (and three-phase parameters): a checkpoint resumes
+// only on the network it was taken from.
+static uint64_t network_hash(const emt_network* N, const Phase3* p3)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t bytes) {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    const int32_t ph = p3 ? 3 : 1;
+    mix(&ph, sizeof ph);
+    mix(&N->n_bus, sizeof N->n_bus);
+    mix(&N->n_branch, sizeof N->n_branch);
+    mix(&N->n_src, sizeof N->n_src);
+    mix(&N->dt, sizeof N->dt);
+    mix(&N->freq, sizeof N->freq);
+    if (N->n_branch > 0) {
+        mix(N->from, sizeof(int32_t) * N->n_branch);
+        mix(N->to, sizeof(int32_t) * N->n_branch);
+        mix(N->R, sizeof(double) * N->n_branch);
+        mix(N->L, sizeof(double) * N->n_branch);
+    }
+    mix(N->C, sizeof(double) * N->n_bus);
+    if (N->n_src > 0) {
+        mix(N->src_bus, sizeof(int32_t) * N->n_src);
+        mix(N->amp, sizeof(double) * N->n_src);
+        mix(N->phase, sizeof(double) * N->n_src);
+    }
+    if (p3) {
+        mix(&p3->mu, sizeof p3->mu);
+        mix(p3->shift, sizeof p3->shift);
+    }
+    return h;
+}
+
 static hinv_status emt_create_impl(const emt_network* net, const Phase3* p3, const hinv_tree* tree,
                                    const hinv_options* opt, const emt_cases* cases, void* d_ws, size_t ws_bytes,
                                    void* stream, emt_handle* out)
@@ -3001,6 +3342,7 @@ static hinv_status emt_create_impl(const emt_network* net, const Phase3* p3, con
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     c->step = 1;
+    c->net_hash = network_hash(net, p3);
     *out = c.release();
     return HINV_OK;
 }
@@ -3147,7 +3489,178 @@ hinv_status emt_update_line(emt_handle h, int32_t a, int32_t b, double delta_g, 
         st = build_panel_map(c, s);
         if (st != HINV_OK) return st;
     }
+    c.base_log.push_back({a, b, delta_g});
     if (out) fill_update_info(c.hc.P, ed.U, out);
+    return HINV_OK;
+}
+
+// ---- checkpoints: header, base-matrix change log, per-case line losses, then the state vectors of
+// every case in the caller's row and branch order (b, v, hC: rows; h: branches)
+namespace {
+struct StateHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t ph, n, nbr, n_cases, n_base, loss_slots, pad;
+    int64_t step;
+    uint64_t net_hash;
+};
+struct StateLoss {
+    int32_t step, branch;
+};
+constexpr char kStateMagic[8] = {'H', 'I', 'N', 'V', 'E', 'M', 'T', 0};
+constexpr uint32_t kStateVersion = 1;
+
+size_t state_bytes(int n_base, int n_cases, int loss_slots, int n, int nbr)
+{
+    return sizeof(StateHeader) + sizeof(emt_ctx::BaseChange) * (size_t)n_base +
+           (sizeof(int32_t) + sizeof(StateLoss) * (size_t)loss_slots) * (size_t)n_cases +
+           sizeof(double) * (size_t)n_cases * (3 * (size_t)n + (size_t)nbr);
+}
+}  // namespace
+
+hinv_status emt_state_size(emt_handle h, size_t* bytes)
+{
+    if (!h || !bytes) return fail(HINV_E_INVALID, "handle or bytes is NULL");
+    const emt_ctx& c = *h;
+    *bytes = state_bytes((int)c.base_log.size(), c.n_cases, c.R / c.ph, c.n, c.nbr);
+    return HINV_OK;
+}
+
+hinv_status emt_save_state(emt_handle h, void* buf, size_t bytes, void* stream)
+{
+    if (!h || !buf) return fail(HINV_E_INVALID, "handle or buffer is NULL");
+    emt_ctx& c = *h;
+    const int slots = c.R / c.ph;
+    const size_t need = state_bytes((int)c.base_log.size(), c.n_cases, slots, c.n, c.nbr);
+    if (bytes < need) return fail(HINV_E_INVALID, "state buffer has %zu bytes, needs %zu", bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    const int64_t K = c.n_cases, n = c.n, nbr = c.nbr;
+    std::vector<double> dev((size_t)K * (3 * n + nbr));
+    double* db = dev.data();
+    double* dv = db + K * n;
+    double* dh = dv + K * n;
+    double* dhb = dh + K * n;
+    HIP_TRY(hipMemcpy(db, c.E.b, sizeof(double) * K * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dv, c.E.v, sizeof(double) * K * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dh, c.E.hC, sizeof(double) * K * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dhb, c.E.h + (c.step & 1) * K * nbr, sizeof(double) * K * nbr, hipMemcpyDeviceToHost));
+    unsigned char* o = (unsigned char*)buf;
+    StateHeader hd{};
+    std::memcpy(hd.magic, kStateMagic, sizeof hd.magic);
+    hd.version = kStateVersion;
+    hd.ph = c.ph; hd.n = c.n; hd.nbr = c.nbr; hd.n_cases = c.n_cases;
+    hd.n_base = (int32_t)c.base_log.size(); hd.loss_slots = slots;
+    hd.step = c.step;
+    hd.net_hash = c.net_hash;
+    std::memcpy(o, &hd, sizeof hd);
+    o += sizeof hd;
+    if (!c.base_log.empty()) {
+        std::memcpy(o, c.base_log.data(), sizeof(emt_ctx::BaseChange) * c.base_log.size());
+        o += sizeof(emt_ctx::BaseChange) * c.base_log.size();
+    }
+    for (int k = 0; k < c.n_cases; ++k) {
+        const int32_t cnt = (int32_t)c.losses[k].size();
+        std::memcpy(o, &cnt, sizeof cnt);
+        o += sizeof cnt;
+        for (int j = 0; j < slots; ++j) {
+            StateLoss L{0, -1};
+            if (j < cnt) L = StateLoss{c.losses[k][j].first, c.losses[k][j].second};
+            std::memcpy(o, &L, sizeof L);
+            o += sizeof L;
+        }
+    }
+    // rows to the caller's order (row r of the context is caller row perm[r])
+    const std::vector<int>& perm = c.hc.P.perm;
+    std::vector<double> rows((size_t)K * n);
+    for (double* src : {db, dv, dh}) {
+        for (int64_t k = 0; k < K; ++k)
+            for (int64_t r = 0; r < n; ++r) rows[k * n + perm[r]] = src[k * n + r];
+        std::memcpy(o, rows.data(), sizeof(double) * rows.size());
+        o += sizeof(double) * rows.size();
+    }
+    std::memcpy(o, dhb, sizeof(double) * K * nbr);
+    return HINV_OK;
+}
+
+hinv_status emt_load_state(emt_handle h, const void* buf, size_t bytes, void* stream)
+{
+    if (!h || !buf) return fail(HINV_E_INVALID, "handle or buffer is NULL");
+    emt_ctx& c = *h;
+    if (bytes < sizeof(StateHeader)) return fail(HINV_E_INVALID, "state buffer is shorter than its header");
+    const unsigned char* o = (const unsigned char*)buf;
+    StateHeader hd;
+    std::memcpy(&hd, o, sizeof hd);
+    o += sizeof hd;
+    if (std::memcmp(hd.magic, kStateMagic, sizeof hd.magic) != 0 || hd.version != kStateVersion)
+        return fail(HINV_E_INVALID, "not an EMT state of this library (magic or version)");
+    if (hd.ph != c.ph || hd.n != c.n || hd.nbr != c.nbr || hd.n_cases != c.n_cases)
+        return fail(HINV_E_INVALID, "state of %d cases x %d rows / %d branches (%d-phase); the handle has %d x %d / %d "
+                    "(%d-phase)", hd.n_cases, hd.n, hd.nbr, hd.ph, c.n_cases, c.n, c.nbr, c.ph);
+    if (hd.net_hash != c.net_hash) return fail(HINV_E_INVALID, "the state was taken on another network");
+    if (hd.n_base < 0 || hd.loss_slots < 0 || hd.step < 1 || hd.step >= INT32_MAX)
+        return fail(HINV_E_INVALID, "corrupt state header");
+    const size_t need = state_bytes(hd.n_base, hd.n_cases, hd.loss_slots, hd.n, hd.nbr);
+    if (bytes < need) return fail(HINV_E_INVALID, "state buffer has %zu bytes, its header needs %zu", bytes, need);
+    std::vector<emt_ctx::BaseChange> log((size_t)hd.n_base);
+    if (hd.n_base > 0) std::memcpy(log.data(), o, sizeof(emt_ctx::BaseChange) * log.size());
+    o += sizeof(emt_ctx::BaseChange) * log.size();
+    // the handle's own base-matrix changes must be where the state's began
+    if (c.base_log.size() > log.size()) return fail(HINV_E_INVALID, "the handle has more base-matrix changes than the state");
+    for (size_t i = 0; i < c.base_log.size(); ++i)
+        if (c.base_log[i].a != log[i].a || c.base_log[i].b != log[i].b || c.base_log[i].dg != log[i].dg)
+            return fail(HINV_E_INVALID, "base-matrix change %zu of the handle differs from the state's", i);
+    std::vector<std::vector<std::pair<int, int>>> losses((size_t)c.n_cases);
+    const int nlines = c.nbr / c.ph;
+    for (int k = 0; k < c.n_cases; ++k) {
+        int32_t cnt;
+        std::memcpy(&cnt, o, sizeof cnt);
+        o += sizeof cnt;
+        if (cnt < 0 || cnt > hd.loss_slots || c.ph * cnt > c.hc.opt.max_mod_rank)
+            return fail(HINV_E_RANK_LIMIT, "case %d of the state has %d line losses; the handle holds %d", k, cnt,
+                        c.hc.opt.max_mod_rank / c.ph);
+        for (int j = 0; j < hd.loss_slots; ++j) {
+            StateLoss L;
+            std::memcpy(&L, o, sizeof L);
+            o += sizeof L;
+            if (j >= cnt) continue;
+            if (L.step < 1 || L.branch < 0 || L.branch >= nlines)
+                return fail(HINV_E_INVALID, "case %d of the state has a bad loss (%d, %d)", k, L.step, L.branch);
+            for (auto& x : losses[k])
+                if (x.second == L.branch) return fail(HINV_E_INVALID, "case %d of the state loses branch %d twice", k, L.branch);
+            losses[k].push_back({L.step, L.branch});
+        }
+        std::stable_sort(losses[k].begin(), losses[k].end());
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = c.base_log.size(); i < log.size(); ++i) {
+        hinv_status st = emt_update_line(h, log[i].a, log[i].b, log[i].dg, stream, nullptr);
+        if (st != HINV_OK) return st;
+    }
+    c.losses = std::move(losses);
+    std::vector<int> all(c.n_cases);
+    for (int k = 0; k < c.n_cases; ++k) all[k] = k;
+    hinv_status st = load_case_losses(c, all, s);
+    if (st != HINV_OK) return st;
+    st = refresh_engine_tables(c, s);
+    if (st != HINV_OK) return st;
+    const int64_t K = c.n_cases, n = c.n, nbr = c.nbr;
+    const std::vector<int>& perm = c.hc.P.perm;
+    std::vector<double> rows((size_t)K * n), mine((size_t)K * n);
+    for (double* dst : {c.E.b, c.E.v, c.E.hC}) {
+        std::memcpy(rows.data(), o, sizeof(double) * rows.size());
+        o += sizeof(double) * rows.size();
+        for (int64_t k = 0; k < K; ++k)
+            for (int64_t r = 0; r < n; ++r) mine[k * n + r] = rows[k * n + perm[r]];
+        HIP_TRY(hipMemcpy(dst, mine.data(), sizeof(double) * mine.size(), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(c.E.h + (hd.step & 1) * K * nbr, o, sizeof(double) * K * nbr, hipMemcpyHostToDevice));
+    const int64_t step = hd.step;
+    const unsigned int zero = 0;
+    HIP_TRY(hipMemcpy(c.E.step, &step, sizeof step, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c.E.done, &zero, sizeof zero, hipMemcpyHostToDevice));
+    c.step = step;
     return HINV_OK;
 }
 

@@ -517,14 +517,15 @@ hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, 
                            int prec, hipStream_t s);
 // Panel stepping (k_panel.hip): LDS bytes of the layout, and the launch (all
 // teams, in as many consecutive cooperative launches as residency requires).
-size_t panel_lds_bytes(const PanelDev& D, int R, int prec);
+size_t panel_lds_bytes(const PanelDev& D, int R, int prec, int warm);
 // Launch set-up of the panel kernel for this layout (dynamic LDS limit, teams per cooperative launch).
 hipError_t panel_setup(PanelDev& D, int R, int prec, int warm);
 // M as the y tasks' A fragments (D.mfr, D.mfr32) from D.bm; after launch_coupling_map.
 hipError_t launch_panel_mfrag(const PanelDev& D, hipStream_t s);
 // Each leaf's image of its LDS tables (after the tables, M fragments and Z values are current).
-size_t panel_image_bytes(const PanelDev& D, int R, int prec);
-hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev& H, int R, int prec, hipStream_t s);
+size_t panel_image_bytes(const PanelDev& D, int R, int prec, int warm);
+hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev& H, int R, int prec, int warm,
+                              hipStream_t s);
 hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
 // Level stepping (k_level.hip): LDS bytes of the layout, and the launch.

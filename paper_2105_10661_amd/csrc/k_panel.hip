@@ -144,12 +144,14 @@ struct PanelLayout {
 
 // LDS layout.  FP64 (one apply per step) keeps b and v in one buffer: the
 // leaf product overwrites b with v, and the right-hand side of the next step
-// overwrites v row by row.  The U region holds, in turn, the leaf product's
-// partial sums, u (the exchanged values at the column rows) and the y
-// tasks' results.
+// overwrites v row by row.  The incremental FP64 form (MIXED with FP64
+// storage) forms its residual in place of b and keeps no convergence
+// statistics.  The U region holds, in turn, the leaf product's partial sums,
+// u (the exchanged values at the column rows) and the y tasks' results.
 template <typename TB, bool MIXED>
 __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
 {
+    constexpr bool INC = MIXED && sizeof(TB) == 8;
     PanelLayout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -199,7 +201,7 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
     L.ux = take(S * R * NX * B);
     L.b = take(F * NLp * B);
     L.v = MIXED ? take(F * NL * B) : L.b;
-    L.td = take(MIXED ? F * NLp * B : 0);
+    L.td = INC ? L.b : take(MIXED ? F * NLp * B : 0);
     L.xv = take(F * NX * B);
     L.xd = take(MIXED ? F * NX * B : 0);
     L.U = take(F * un);
@@ -210,7 +212,7 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
     L.cinv = take(F * B * (R * (R + 1) * (2 * R + 1) / 6));   // per case the r x r inverses, r = 1..R, packed
     L.mdg = take(F * B * R);
     L.tz = take(F * B * 2 * R);
-    L.red = take(MIXED ? F * 2 * kPWaves * B : 0);
+    L.red = take(MIXED && !INC ? F * 2 * kPWaves * B : 0);
     // red2 (shares per wavefront, before the barrier) and red3 (the team's shares, after it) share one region
     L.red2 = take(F * (kPWaves > D.T ? kPWaves : D.T) * R * B);
     L.red3 = L.red2;
@@ -225,9 +227,10 @@ __host__ __device__ inline PanelLayout panel_layout(const PanelDev& D, int R)
     return L;
 }
 
-size_t panel_lds_bytes(const PanelDev& D, int R, int prec)
+size_t panel_lds_bytes(const PanelDev& D, int R, int prec, int warm)
 {
-    return prec == HINV_FP64 ? panel_layout<double, false>(D, R).total : panel_layout<float, true>(D, R).total;
+    if (prec != HINV_FP64) return panel_layout<float, true>(D, R).total;
+    return warm ? panel_layout<double, true>(D, R).total : panel_layout<double, false>(D, R).total;
 }
 
 // The per-leaf tables of the layout, written at base (LDS or a leaf's image in global memory) by nth
@@ -341,10 +344,19 @@ __device__ void panel_fill_static(const PanelDev& D, const EmtDev& E, const Hier
     }
 }
 
+// MIXED with FP32 storage: FP64 refinement of the FP32 apply (warm: from the
+// previous step's voltages).  MIXED with FP64 storage (INC): the incremental
+// form v = v_prev + P (b - G v_prev), one FP64 apply per step.  In exact
+// arithmetic it is P b; in floating point the apply's rounding scales with
+// the change of v over a step rather than with v, which keeps the trajectory
+// of a weakly damped mode (a bus left on its shunt capacitor alone by a line
+// loss holds its voltage, an eigenvalue 1 of the step map) from drifting.
 template <typename TB, bool MIXED, bool WARM>
 __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, HierDev H, ModDev M, RunParams P)
 {
     using TA = typename PAcc<TB>::T;
+    constexpr bool INC = MIXED && sizeof(TB) == 8;
+    static_assert(!INC || WARM, "the incremental FP64 form starts from the previous step's voltages");
     extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
     const int R = M.R;
     const PanelLayout Ly = panel_layout<TB, MIXED>(D, R);
@@ -442,7 +454,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         const int64_t gi = (int64_t)(case0 + c) * n + lo + r;
         b[i] = ok ? E.b[gi] : 0.0;
         if (MIXED) {
-            td[i] = 0.0;
+            if (!INC) td[i] = 0.0;
             if (r < nl) v[i] = ok ? E.v[gi] : 0.0;
         }
     }
@@ -864,7 +876,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         sn_step = step + 1;      // the step's first apply computes the next step's source injections
         const int64_t jr = step - P.rec_step0;
         const bool rec = jr >= 0 && jr < P.rec_cap;
-        if (!MIXED && rec && P.b_rec) {                 // b is overwritten by v below
+        if ((!MIXED || INC) && rec && P.b_rec) {        // b is overwritten by v (the residual) below
             for (int i = tid; i < nl * kPB; i += kPThreads) {
                 const int c = i & 15;
                 if (c < nvc) P.b_rec[(jr * K + case0 + c) * (int64_t)n + prow[i >> 4]] = b[i];
@@ -882,13 +894,13 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             alive = apply(b, v, xv, anyact, false);
             applies += 1;
         } else {
-            const int nref = WARM ? P.max_refine + 1 : P.max_refine;
+            const int nref = INC ? 1 : (WARM ? P.max_refine + 1 : P.max_refine);
             if (!WARM) {
                 alive = apply(b, v, xv, anyact, false);
                 applies += 1;
             }
             for (int q = 0; q < nref && alive; ++q) {
-                alive = refine(anyact, q == nref - 1);
+                alive = refine(anyact, !INC && q == nref - 1);
                 applies += 1;
             }
         }
@@ -924,7 +936,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 if (rec && c < nvc) {
                     const int64_t o = (jr * K + case0 + c) * (int64_t)n + prow[r];
                     if (P.v_rec) P.v_rec[o] = va;
-                    if (MIXED && P.b_rec) P.b_rec[o] = b[i];
+                    if (MIXED && !INC && P.b_rec) P.b_rec[o] = b[i];
                 }
                 b[i] = bn;
             }
@@ -996,16 +1008,19 @@ __global__ void k_panel_image(PanelDev D, EmtDev E, HierDev H, int R)
     panel_fill_static<TB, MIXED>(D, E, H, Ly, D.img + (int64_t)blockIdx.x * D.imgb, blockIdx.x, threadIdx.x, blockDim.x);
 }
 
-size_t panel_image_bytes(const PanelDev& D, int R, int prec)
+size_t panel_image_bytes(const PanelDev& D, int R, int prec, int warm)
 {
-    const size_t b = prec == HINV_FP64 ? panel_layout<double, false>(D, R).stat : panel_layout<float, true>(D, R).stat;
+    const size_t b = prec != HINV_FP64 ? panel_layout<float, true>(D, R).stat
+                     : warm ? panel_layout<double, true>(D, R).stat : panel_layout<double, false>(D, R).stat;
     return (b + 255) / 256 * 256;
 }
 
-hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev& H, int R, int prec, hipStream_t s)
+hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev& H, int R, int prec, int warm,
+                              hipStream_t s)
 {
-    if (prec == HINV_FP64) hipLaunchKernelGGL((k_panel_image<double, false>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
-    else hipLaunchKernelGGL((k_panel_image<float, true>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
+    if (prec != HINV_FP64) hipLaunchKernelGGL((k_panel_image<float, true>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
+    else if (warm) hipLaunchKernelGGL((k_panel_image<double, true>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
+    else hipLaunchKernelGGL((k_panel_image<double, false>), dim3(D.T), dim3(256), 0, s, D, E, H, R);
     return hipGetLastError();
 }
 
@@ -1017,13 +1032,13 @@ static const void* panel_fn()
 
 static const void* panel_kernel(int prec, int warm)
 {
-    if (prec == HINV_FP64) return panel_fn<double, false, false>();
+    if (prec == HINV_FP64) return warm ? panel_fn<double, true, true>() : panel_fn<double, false, false>();
     return warm ? panel_fn<float, true, true>() : panel_fn<float, true, false>();
 }
 
 hipError_t panel_setup(PanelDev& D, int R, int prec, int warm)
 {
-    const size_t lds = panel_lds_bytes(D, R, prec);
+    const size_t lds = panel_lds_bytes(D, R, prec, warm);
     const void* fn = panel_kernel(prec, warm);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1042,7 +1057,7 @@ hipError_t panel_setup(PanelDev& D, int R, int prec, int warm)
 hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s)
 {
-    const size_t lds = panel_lds_bytes(D, M.R, prec);
+    const size_t lds = panel_lds_bytes(D, M.R, prec, P.warm);
     const void* fn = panel_kernel(prec, P.warm);
     if (D.teams_per_launch < 1) return hipErrorCooperativeLaunchTooLarge;
     for (int t0 = 0; t0 < D.n_teams; t0 += D.teams_per_launch) {

@@ -185,12 +185,16 @@ __device__ inline bool run_lost_by(const EmtDev& E, int k, int e, int64_t step)
 }
 
 // The whole per-case stepping loop; b, v, t, d are LDS (or, for cases too big
-// for LDS, the case's global scratch), s, y, red, tz are LDS.
+// for LDS, the case's global scratch), s, y, red, tz are LDS.  MIXED with FP64
+// storage is the incremental form v = v_prev + P (b - G v_prev): one FP64
+// apply per step, no convergence test (P is the FP64 inverse).
 template <typename TB, bool MIXED, bool WARM>
 __device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                                              int k, double* b, double* v, double* t, double* d, double* s, double* y,
                                              double* red, double* tz)
 {
+    constexpr bool INC = MIXED && sizeof(TB) == 8;
+    static_assert(!INC || WARM, "the incremental FP64 form starts from the previous step's voltages");
     const int n = H.n;
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)k * n;
@@ -222,10 +226,16 @@ __device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, 
                 wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz);
                 applies += 1;
             }
-            for (int rf = 0; rf < P.max_refine + (WARM ? 1 : 0) && !done; ++rf) {
+            const int nref = INC ? 1 : P.max_refine + (WARM ? 1 : 0);
+            for (int rf = 0; rf < nref && !done; ++rf) {
                 wg_residual(H, M, k, step, b, v, t);
                 wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, t, d, s, y, tz);
                 applies += 1;
+                if constexpr (INC) {
+                    for (int i = tid; i < n; i += kRunThreads) v[i] += d[i];
+                    __syncthreads();
+                    continue;
+                }
                 double dmax = 0.0, vmax = 0.0;
                 for (int i = tid; i < n; i += kRunThreads) {
                     const double nv = v[i] + d[i];
@@ -242,7 +252,7 @@ __device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, 
                 } else if (ratio <= P.rel_tol) {
                     done = 1;
                     worst = fmax(worst, ratio);
-                } else if (rf == P.max_refine + (WARM ? 1 : 0) - 1) {
+                } else if (rf == nref - 1) {
                     if (tid == 0) atomicOr(P.flags, kFlagNoConv);
                     worst = fmax(worst, ratio);
                 }
@@ -293,7 +303,7 @@ __device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, 
         E.v[base + i] = v[i];
     }
     if (tid == 0) {
-        if (MIXED && P.stats) atomicMax(&P.stats[k], (unsigned long long)__double_as_longlong(worst));
+        if (MIXED && !INC && P.stats) atomicMax(&P.stats[k], (unsigned long long)__double_as_longlong(worst));
         if (P.applies) atomicAdd(&P.applies[k], (unsigned long long)applies);
         if (k == 0) *E.step = P.step0 + P.n_steps;
     }
@@ -400,7 +410,8 @@ hipError_t launch_emt_serve(const ServeSlot* d_slots, int n_slots, int n_steps, 
 hipError_t launch_emt_run(const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P, int prec,
                           hipStream_t s)
 {
-    if (prec == HINV_FP64) return launch_run_t<double, false, false>(E, H, M, P, s);
+    if (prec == HINV_FP64)
+        return P.warm ? launch_run_t<double, true, true>(E, H, M, P, s) : launch_run_t<double, false, false>(E, H, M, P, s);
     if (P.warm) return launch_run_t<float, true, true>(E, H, M, P, s);
     return launch_run_t<float, true, false>(E, H, M, P, s);
 }

@@ -32,7 +32,7 @@ EXPORTS = ("hinv_workspace_size", "hinv_build", "hinv_modify_line", "hinv_update
            "hinv_wall_clock_khz", "serve_workspace_size", "serve_create", "serve_attach", "serve_detach",
            "serve_step", "serve_active", "serve_destroy", "chol_workspace_size", "chol_create", "chol_solve",
            "chol_get_info", "chol_destroy", "hinv_last_error", "emt3_workspace_size", "emt3_create",
-           "hinv_gmres_workspace_size", "hinv_solve_gmres")
+           "hinv_gmres_workspace_size", "hinv_solve_gmres", "emt_state_size", "emt_save_state", "emt_load_state")
 
 
 class HinvError(RuntimeError):
@@ -141,6 +141,9 @@ def load() -> ctypes.CDLL:
         "emt_update_line": [P, i32, i32, d, P, P],
         "emt_sync_status": [P],
         "emt_get_step": [P, P],
+        "emt_state_size": [P, P],
+        "emt_save_state": [P, P, ctypes.c_size_t, P],
+        "emt_load_state": [P, P, ctypes.c_size_t, P],
         "emt_get_stats": [P, P, P],
         "emt_set_step_clock": [P, P, i64],
         "hinv_wall_clock_khz": [i32, P],
@@ -541,6 +544,19 @@ class EMT:
         s = ctypes.c_int64(0)
         _check(self._lib.emt_get_step(self._h, ctypes.byref(s)), "emt_get_step")
         return s.value
+
+    def save_state(self) -> np.ndarray:
+        """Checkpoint of the time loop (emt_save_state): a uint8 array that load_state takes."""
+        nb = ctypes.c_size_t(0)
+        _check(self._lib.emt_state_size(self._h, ctypes.byref(nb)), "emt_state_size")
+        buf = np.zeros(nb.value, np.uint8)
+        _check(self._lib.emt_save_state(self._h, _ptr(buf), nb.value, _stream()), "emt_save_state")
+        return buf
+
+    def load_state(self, buf) -> None:
+        """Resume from a checkpoint of a handle on the same network (emt_load_state)."""
+        buf = np.ascontiguousarray(buf, np.uint8)
+        _check(self._lib.emt_load_state(self._h, _ptr(buf), buf.nbytes, _stream()), "emt_load_state")
 
     def stats(self) -> Tuple[int, float]:
         import torch

@@ -10,12 +10,16 @@ For one network, case count and loss schedule it picks, by timing on the device:
 - the engine (the schedule of a step): 16-case panels with one workgroup per leaf and per panel
   (``panel``), one workgroup per case (``fused``), one cooperative team per case (``team``, ``level``)
   or one launch per phase (``per_kernel``);
-- the precision path: FP64, or FP32 applies with FP64 residual refinement and a fixed number of
-  corrections per step (warm start from the previous step's voltages).
+- the precision path: FP64 solved directly (v = P b), FP64 in the incremental form (v = v_prev +
+  P (b - G v_prev), one apply per step; on the engines that have it), or FP32 applies with FP64
+  residual refinement and a fixed number of corrections per step (warm start from the previous
+  step's voltages).
 
 A candidate is kept only if the library accepts it (``emt_workspace_size``, host only: leaf, column
 and LDS limits of the engine) and if its voltages stay within ``gate`` of the FP64 path of the same
-library on the same tree over the run's whole ``horizon``: every case and bus at every one of the
+library on the same tree (the incremental form where the tree has a feasible one: the direct form
+lets rounding accumulate along a bus that a line loss leaves on its shunt capacitor alone, up to
+1.5e-9 over the contingency batch's horizon) over the run's whole ``horizon``: every case and bus at every one of the
 first ``gate_steps`` steps and at every ``stride``-th step after them (normalised by the peak
 voltage).  The trajectories drift slowly (the trapezoidal step map has an eigenvalue of 1), so a
 sampled step every few dozen misses nothing between samples.  The fastest kept candidate wins.  Each
@@ -43,7 +47,7 @@ from . import hinv
 SINGLE_CASE_ENGINES = ("team", "level", "fused", "per_kernel")
 BATCH_ENGINES = ("panel", "fused")
 # (precision, corrections per step, warm start)
-DEFAULT_PATHS = (("fp64", 0, False), ("fp32", 1, True), ("fp32", 2, True))
+DEFAULT_PATHS = (("fp64", 0, False), ("fp64", 0, True), ("fp32", 1, True), ("fp32", 2, True))
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2105_10661_amd", "tune.json")
 
 
@@ -56,7 +60,10 @@ class Candidate:
     warm: bool
 
     def label(self) -> str:
-        p = "fp64" if self.prec == "fp64" else f"{self.prec}+{self.max_refine}ir"
+        if self.prec == "fp64":
+            p = "fp64inc" if self.warm else "fp64"
+        else:
+            p = f"{self.prec}+{self.max_refine}ir"
         return f"{self.tree}/{self.engine}/{p}"
 
 
@@ -314,11 +321,14 @@ def tune(net, trees: Optional[Dict[str, Tuple[np.ndarray, np.ndarray]]] = None, 
     nets = {name: with_tree(net, *tr) for name, tr in trees.items()}
     rows = [check_feasible(nets[c.tree], c, n_cases, losses, max_mod_rank, rel_tol)
             for c in enumerate_candidates(list(trees), engines, paths)]
-    # FP64 reference of the same library on the candidate's own tree (its first feasible FP64 engine, else
-    # auto): two exact FP64 trees drift apart by rounding along the recursion's unit eigenvalue, which is
-    # not an error of either
-    ref_cands = {t: next((r.cand for r in rows if r.feasible and r.cand.tree == t and r.cand.prec == "fp64"),
-                         Candidate(t, "auto", "fp64", 0, False)) for t in trees}
+    # FP64 reference of the same library on the candidate's own tree (its first feasible FP64 candidate in
+    # the incremental form, else its first feasible FP64 one, else auto): two exact FP64 trees drift apart
+    # by rounding along the recursion's unit eigenvalue, which is not an error of either
+    def reference(t):
+        fp64 = [r.cand for r in rows if r.feasible and r.cand.tree == t and r.cand.prec == "fp64"]
+        inc = [c for c in fp64 if c.warm and c.engine in ("panel", "fused")]
+        return (inc or fp64 or [Candidate(t, "auto", "fp64", 0, False)])[0]
+    ref_cands = {t: reference(t) for t in trees}
     for r in rows:
         if not r.feasible:
             continue

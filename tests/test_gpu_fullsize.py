@@ -60,8 +60,8 @@ def test_torus_11456_trajectory_with_loss(hv, prec, mode):
     emt.close()
 
 
-@pytest.mark.parametrize("mode,prec,warm", [("fused", "fp32", True), ("panel", "fp32", True),
-                                            ("panel", "fp32", False), ("panel", "fp64", False)])
+@pytest.mark.parametrize("mode,prec,warm", [("fused", "fp32", True), ("fused", "fp64", True), ("panel", "fp32", True),
+                                            ("panel", "fp32", False), ("panel", "fp64", False), ("panel", "fp64", True)])
 def test_contingency_batch_256(hv, mode, prec, warm):
     base, bcases = cases.cases_c4(n_cases=256, n_steps=1200, step_range=(1, 900))
     losses = [list(zip(c.loss_steps.tolist(), c.loss_branches.tolist())) for c in bcases]

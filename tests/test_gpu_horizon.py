@@ -1,18 +1,27 @@
 """GPU parity at the benchmark configurations' stated horizons.
 
 * Contingency batch: 256 cases of the 1432-bus ring, each losing a distinct
-  line at a random step in [500, 5000], 8000 steps, on the panel engine in
-  FP64 and with FP32 applies + FP64 refinement.
-  - Full trajectories of 16 cases against the oracle (explicit FP64 inverse,
+  line at a random step in [500, 5000], 8000 steps, on the panel engine: FP64
+  in the incremental form v = v_prev + P (b - G v_prev) and FP32 applies +
+  FP64 refinement.
+  - Full trajectories of 39 cases against the oracle (explicit FP64 inverse,
     re-inversion at the loss): every tie-line loss of the batch (its SMW
-    endpoints sit in two workgroups' rows), the earliest and the latest loss,
-    and seeded picks.  Peak-normalised, 1e-10.
+    endpoints sit in two workgroups' rows), every loss that leaves a bus on
+    its shunt capacitor alone (26 cases: that bus keeps its voltage, a mode the
+    step map does not damp, so rounding accumulates along it for the rest of
+    the horizon), the earliest and the latest loss, and seeded picks.
+    Peak-normalised, 1e-10.
   - Per solve at 64 seeded (case, step) points spread over all 256 cases and
     the whole horizon: the engine's own right-hand side at that step, solved by
     the oracle (library sparse LU of that step's G, pinned against the dense LU
     in the oracle tests), against the engine's voltage.  Per-vector infinity
     norm, 1e-10.
   The run is recorded in 500-step chunks (the whole record would be 23 GB).
+  FP64 solved directly (v = P b) meets 1e-10 per solve and on the cases whose
+  loss leaves no bus floating; on the floating ones its trajectory error grows
+  after the loss (rounding of the SMW-corrected apply, amplified by the
+  capacitance, adds up along the undamped mode: 1.5e-9 at worst, 8 of the 26
+  above 1e-10), which is what the incremental form removes.
 * 11456-bus torus: 10000 steps on the level engine, FP64 and FP32 + FP64
   refinement, one line lost at step 2000, against the oracle's sparse LU time
   loop (refactorised only at the loss step).  Peak-normalised, 1e-10.
@@ -51,26 +60,31 @@ def c4():
     br = np.array([c[0][1] for c in losses])
     ties = [int(k) for k in np.nonzero(br >= 8 * cases.BASE_BRANCHES)[0]]
     assert len(ties) >= 1
+    deg = np.bincount(base.frm, minlength=base.n_bus) + np.bincount(base.to, minlength=base.n_bus)
+    floating = [k for k in range(256) if min(deg[base.frm[br[k]]], deg[base.to[br[k]]]) == 1]
+    assert len(floating) == 26
     rng = np.random.default_rng(404)
-    pick = set(ties) | {int(st.argmin()), int(st.argmax())}
+    pick = set(ties) | set(floating) | {int(st.argmin()), int(st.argmax())}
     rest = [k for k in range(256) if k not in pick]
-    pick |= set(int(k) for k in rng.choice(rest, 16 - len(pick), replace=False))
+    pick |= set(int(k) for k in rng.choice(rest, 8, replace=False))
     sample = sorted(pick)
-    print(f"[gpu] c4 oracle trajectories of cases {sample} (tie-line losses {ties})", flush=True)
+    print(f"[gpu] c4 oracle trajectories of cases {sample} (tie-line losses {ties}, floating buses {floating})",
+          flush=True)
     refs = {}
     for k in sample:
         refs[k], _ = oracle.emt_run(base, C4_STEPS, loss_steps=[st[k]], loss_branches=[br[k]], solver="inv")
     points = sorted(zip(rng.integers(0, 256, 64).tolist(), rng.integers(1, C4_STEPS + 1, 64).tolist()),
                     key=lambda p: p[1])
-    return base, losses, sample, refs, points
+    return base, losses, sample, refs, points, floating
 
 
-@pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec,warm,refine", [("fp64", False, 0), ("fp32", True, 2)])
-def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
+def _batch_errors(hv, c4, prec, warm, refine):
+    """Run the batch over the horizon; per sampled case the peak-normalised trajectory error, the
+    per-solve errors at the seeded points and the device status."""
     import torch
-    base, losses, sample, refs, points = c4
-    print(f"[gpu] c4 256 cases x {C4_STEPS} steps, panel engine, {prec} (refine {refine})", flush=True)
+    base, losses, sample, refs, points, floating = c4
+    form = "incremental" if prec == "fp64" and warm else "direct" if prec == "fp64" else f"refine {refine}"
+    print(f"[gpu] c4 256 cases x {C4_STEPS} steps, panel engine, {prec} ({form})", flush=True)
     emt = hv.EMT(base, 256, losses=losses, prec=prec, max_refine=refine, rel_tol=MIXED_CHECK, warm_start=warm,
                  max_mod_rank=1, kernel_mode="panel")
     Vbuf = torch.empty((CHUNK, 256, base.n_bus), dtype=torch.float64, device="cuda")
@@ -104,11 +118,32 @@ def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
     emt.close()
     assert pi == len(points)
     worst = max(solve_err)
-    print(f"[gpu] c4 {prec}: per-solve max {worst[0]:.2e} at case {worst[1]} step {worst[2]}; trajectories "
-          + ", ".join(f"{k}:{dmax[k] / np.abs(refs[k]).max():.1e}" for k in sample), flush=True)
+    traj = {k: dmax[k] / np.abs(refs[k]).max() for k in sample}
+    print(f"[gpu] c4 {prec} ({form}): per-solve max {worst[0]:.2e} at case {worst[1]} step {worst[2]}; "
+          "trajectories " + ", ".join(f"{k}:{traj[k]:.1e}" for k in sample), flush=True)
+    return traj, worst, status
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,warm,refine", [("fp64", True, 0), ("fp32", True, 2)])
+def test_contingency_batch_full_horizon(hv, c4, prec, warm, refine):
+    traj, worst, status = _batch_errors(hv, c4, prec, warm, refine)
     assert worst[0] <= 1e-10, worst
-    for k in sample:
-        assert dmax[k] / np.abs(refs[k]).max() <= 1e-10, (k, dmax[k] / np.abs(refs[k]).max())
+    for k, e in traj.items():
+        assert e <= 1e-10, (k, e)
+    assert status == "ok", status
+
+
+@pytest.mark.timeout(900)
+def test_contingency_batch_direct_fp64(hv, c4):
+    """FP64 solved directly: 1e-10 per solve and on every sampled case whose loss leaves no bus
+    floating; on the floating ones the drift along the undamped mode is bounded by 2e-9 (1.5e-9
+    measured), recorded here as the reason the incremental form exists."""
+    floating = set(c4[5])
+    traj, worst, status = _batch_errors(hv, c4, "fp64", False, 0)
+    assert worst[0] <= 1e-10, worst
+    for k, e in traj.items():
+        assert e <= (2e-9 if k in floating else 1e-10), (k, e)
     assert status == "ok", status
 
 

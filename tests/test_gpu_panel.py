@@ -51,7 +51,7 @@ def ref_179():
     return net, out
 
 
-@pytest.mark.parametrize("prec,warm", [("fp64", False), ("fp32", False), ("fp32", True)])
+@pytest.mark.parametrize("prec,warm", [("fp64", False), ("fp64", True), ("fp32", False), ("fp32", True)])
 def test_panel_179_every_case_against_oracle(hv, ref_179, prec, warm):
     net, refs = ref_179
     print(f"[gpu] panel 179 x {len(LOSSES_179)} {prec} warm={warm}", flush=True)

@@ -193,7 +193,7 @@ def c2_ref():
     return case, V
 
 
-@pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp32", "fused", False),
+@pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp64", "fused", True), ("fp32", "fused", False),
                                             ("fp32", "fused", True), ("fp64", "per_kernel", False),
                                             ("fp64", "team", False), ("fp32", "team", False),
                                             ("fp32", "team", True), ("fp64", "level", False),
