@@ -39,6 +39,7 @@ constexpr int kPHelpTiles = 3;    // row tiles of each helper wavefront
 constexpr int kPHelpK = 6;        // k-steps of a tile's tail
 constexpr int kPYT = kPanelYTasksPerWave;
 constexpr int kPHItems = 6;       // (branch, case) items of a thread in the history update (<= 192 branches)
+constexpr int kRW = 2;            // residual entries loaded ahead of their multiply-adds
 static_assert(kPB == 16, "the panel is the N dimension of a 16x16x4 MFMA");
 static_assert(kPThreads % kPB == 0, "all items of a thread belong to one case");
 static_assert(kPWaves == kPanelWaves, "wavefront count shared with the host plan");
@@ -558,7 +559,9 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
 
     // one application of the stored inverse with each case's active changes:
     // out (own rows), outx (X rows) from xin (own rows, zero beyond nl); out
-    // may be xin (it is written after every wavefront has read xin)
+    // may be xin (it is written after every wavefront has read xin).  The
+    // incremental FP64 form adds the result to v and xv instead of storing it
+    // (out and outx then only hold intermediate values).
     auto apply = [&](const double* xin, double* out, double* outx, bool anyact, bool want_vm) -> bool {
         double* X0p = D.X0 + ((int64_t)team * 2 + par) * (int64_t)nc * kPB;
         double* SPp = D.SP + ((int64_t)team * 2 + par) * (int64_t)T * R * kPB;
@@ -777,7 +780,10 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                     double sa = 0.0;          // per-case SMW correction
                     for (int j = 0; j < ra; ++j)
                         sa = pfma((double)uo[j * NLp * kPB + r * kPB + c], tz[c * 2 * R + R + j], sa);
-                    if (r < nl) out[r * kPB + c] = val[e] - sa;
+                    if (r < nl) {
+                        if constexpr (INC) v[r * kPB + c] += val[e] - sa;
+                        else out[r * kPB + c] = val[e] - sa;
+                    }
                 }
             }
         } else {
@@ -791,7 +797,8 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 const int ra = anyact ? ract[c] : 0;
                 double sa = 0.0;              // per-case SMW correction
                 for (int j = 0; j < ra; ++j) sa = pfma((double)uo[j * NLp * kPB + i], tz[c * 2 * R + R + j], sa);
-                out[i] = val - sa;
+                if constexpr (INC) v[i] += val - sa;
+                else out[i] = val - sa;
             }
         }
         // X rows, starting on the helper wavefronts (no own-row tile in the update above)
@@ -805,27 +812,59 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             const int ra = anyact ? ract[c] : 0;
             double sa = 0.0;                  // per-case SMW correction
             for (int j = 0; j < ra; ++j) sa = pfma((double)ux[j * NX * kPB + i], tz[c * 2 * R + R + j], sa);
-            outx[i] = val - sa;
+            if constexpr (INC) xv[i] += val - sa;
+            else outx[i] = val - sa;
         }
         __syncthreads();
         par ^= 1;
         return true;
     };
 
-    // t = b - G_step v on own rows (FP64), then v += P t; stats on the last pass
+    // t = b - G_step v on own rows (FP64), then v += P t; stats on the last pass.  The residual runs one
+    // thread per (row, four cases): the row's CSR entries are loaded once for its four cases, whose
+    // voltages sit next to each other (two 16-byte loads per entry); per case the entries are summed
+    // in CSR order, then the case's active changes
     auto refine = [&](bool anyact, bool last) -> bool {
-        for (int i = tid; i < nl * kPB; i += kPThreads) {
-            const int r = i >> 4, c = i & 15;
-            double acc = 0.0;
-            for (int e = orp[r]; e < orp[r + 1]; ++e) acc += oval[e] * cval(v, xv, ocol[e], c);
-            const int ra = ract[c];
-            for (int j = 0; j < ra; ++j) {
-                const int a = lpa[c * R + j], bb = lpb[c * R + j];
-                if (a != r && bb != r) continue;
-                const double wv = cval(v, xv, a, c) - (bb >= 0 ? cval(v, xv, bb, c) : 0.0);
-                acc += (a == r ? 1.0 : -1.0) * mdg[c * R + j] * wv;
+        for (int q = tid; q < nl * (kPB / 4); q += kPThreads) {
+            const int r = q >> 2, c0 = (q & 3) * 4;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            const int e0 = orp[r], e1 = orp[r + 1];
+            for (int eb = e0; eb < e1; eb += kRW) {
+                double2 x[kRW][2];
+                double w[kRW];
+#pragma unroll
+                for (int k = 0; k < kRW; ++k) {
+                    const int e = eb + k < e1 ? eb + k : e1 - 1;
+                    const int col = ocol[e];
+                    w[k] = oval[e];
+                    const double2* src = (const double2*)(col < nl ? v + col * kPB + c0 : xv + (col - nl) * kPB + c0);
+                    x[k][0] = src[0];
+                    x[k][1] = src[1];
+                }
+#pragma unroll
+                for (int k = 0; k < kRW; ++k)
+                    if (eb + k < e1) {
+                        acc[0] += w[k] * x[k][0].x;
+                        acc[1] += w[k] * x[k][0].y;
+                        acc[2] += w[k] * x[k][1].x;
+                        acc[3] += w[k] * x[k][1].y;
+                    }
             }
-            td[i] = b[i] - acc;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u, ra = ract[c];
+                for (int j = 0; j < ra; ++j) {
+                    const int a = lpa[c * R + j], bb = lpb[c * R + j];
+                    if (a != r && bb != r) continue;
+                    const double wv = cval(v, xv, a, c) - (bb >= 0 ? cval(v, xv, bb, c) : 0.0);
+                    acc[u] += (a == r ? 1.0 : -1.0) * mdg[c * R + j] * wv;
+                }
+            }
+            const double2* bs = (const double2*)(b + r * kPB + c0);
+            const double2 b0 = bs[0], b1 = bs[1];
+            double2* ts = (double2*)(td + r * kPB + c0);
+            ts[0] = double2{b0.x - acc[0], b0.y - acc[1]};
+            ts[1] = double2{b1.x - acc[2], b1.y - acc[3]};
         }
         if (last) {        // publish this workgroup's max |v| per case for the team-wide norm
             double vm = 0.0;     // the thread's items all belong to case tid & 15
@@ -843,6 +882,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         }
         __syncthreads();
         if (!apply(td, td, xd, anyact, last)) return false;
+        if constexpr (INC) return true;          // the apply added its result to v and xv
         double dm = 0.0;     // the thread's items all belong to case tid & 15
         for (int i = tid; i < nl * kPB; i += kPThreads) {
             v[i] += td[i];
