@@ -964,10 +964,16 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 const double va = v[i];
                 double bn = sn[r];
                 const int q0 = rinc[k] & 0xffff, qn = rinc[k] >> 16;
-                for (int q = q0; q < q0 + qn; ++q) {
-                    const int lb = ibr[q];
-                    const double hv = h[(lb >= 0 ? lb : ~lb) * kPB + c];
-                    bn -= lb >= 0 ? hv : -hv;
+                for (int qb = q0; qb < q0 + qn; qb += 4) {      // indices first, then the histories
+                    int lb[4];
+                    double hv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) lb[u] = ibr[qb + u < q0 + qn ? qb + u : q0 + qn - 1];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) hv[u] = h[(lb[u] >= 0 ? lb[u] : ~lb[u]) * kPB + c];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (qb + u < q0 + qn) bn -= lb[u] >= 0 ? hv[u] : -hv[u];
                 }
                 const double ic = gC[r] * va + hcr[k];
                 const double hcn = -gC[r] * va - ic;
