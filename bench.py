@@ -597,8 +597,9 @@ def tuner_section(hinv, torch, args, base, losses):
     ok = sorted([r for r in rows if r["feasible"] and r["err"] is not None and r["err"] <= tr.gate
                  and r["status"] in ("ok", "NO_CONVERGENCE")], key=lambda r: r["us_per_step"])
     return {"wall_s": round(time.perf_counter() - t0, 2),
-            "gate": f"voltages of every case and bus against the library's FP64 path on the same tree "
-                    f"(peak-normalised) at each of the first 1000 steps and every 50th step to {HORIZON}, "
+            "gate": f"voltages of every case and bus against the library's incremental FP64 path on the same "
+                    f"tree (each case normalised by its own peak) at each of the first 1000 steps and every "
+                    f"50th step to {HORIZON}, "
                     f"within 1e-10; err_first is the error over the first 1000 steps and err_extrapolated "
                     f"its linear extrapolation to {HORIZON} steps, the estimate this gate replaced",
             "candidates": [{"label": r["label"], "us_per_step": None if r["us_per_step"] is None

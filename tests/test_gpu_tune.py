@@ -1,9 +1,10 @@
 """GPU checks of the autotuner on a 32-case contingency batch of the 716-bus ring.
 
 * Two partition trees (2 and 4 leaves per 179-bus copy) x two engines (16-case panels on the matrix
-  cores, one workgroup per case) x three precision paths are timed; every candidate that ran has an
-  error against the FP64 reference over the horizon (every step of the first 160, every 40th after),
-  the FP64 candidates at the FP64 floor.
+  cores, one workgroup per case) x four precision paths are timed; every candidate that ran has an
+  error against the FP64 reference (the incremental form) over the horizon (every step of the first
+  160, every 40th after; each case normalised by its own peak), the incremental FP64 candidates at
+  the FP64 floor.
 * The choice is the fastest candidate within the gate, and it is accurate against the FP64 oracle
   on sampled cases (1e-10 of the peak voltage).
 * A second call with the same key comes from the JSON cache without running anything.
@@ -55,8 +56,12 @@ def test_every_candidate_ran_or_was_refused(tuned):
         assert np.isfinite(r.err)
         assert r.err >= r.err_first          # the horizon includes the first gate_steps steps
         assert r.err_extrapolated == pytest.approx(r.err_first * HORIZON / STEPS)
-        if r.cand.prec == "fp64":
+        if r.cand.prec == "fp64" and r.cand.warm:
             assert r.err <= 1e-11, (r.cand, r.err)
+        elif r.cand.prec == "fp64":
+            # the direct form drifts along a bus that a loss leaves floating (its error grows with the
+            # steps after the loss); each case is normalised by its own peak voltage
+            assert r.err <= 1e-9, (r.cand, r.err)
     assert sum(r.feasible for r in res.rows) >= 8
 
 
