@@ -56,10 +56,10 @@ N_PICKS = 4            # seeded picks added to the oracle's sample of contingenc
 # (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch).  A 512 MiB device copy read 262,156 KiB of
 # FETCH_SIZE and 524,288 KiB of WRITE_SIZE, so FETCH is scaled by 2.0 and WRITE by 1.0.  Keyed by the
 # launch's step count: the 20-step launch of that command, and the steady 500-step launches of its
-# pre-roll (steps 2001-5000).  Valid only while the kernel's sources hash to the profiled ones.
-PANEL_TRAFFIC = {"kernel": "k_emt_panel<double, false, false>",
-                 "sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "f58eb33c3c0051bd",
-                 "bytes": {20: 123932672, 500: 1705242556}}
+# pre-roll (steps 2501-5000).  Valid only for that kernel and while its sources hash to the profiled ones.
+PANEL_TRAFFIC = {"kernel": "k_emt_panel<double, true, true>",
+                 "sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "16d4ab6601f561d8",
+                 "bytes": {20: 139676262, 500: 1723495629}}
 PANEL_KERNELS = {"panel_fp64": "k_emt_panel<double, false, false>", "panel_fp64_inc": "k_emt_panel<double, true, true>",
                  "panel_mixed": "k_emt_panel<float, true, true>"}
 

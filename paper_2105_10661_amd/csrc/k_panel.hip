@@ -434,34 +434,94 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
     } else {
         gblk = (const TB*)H.blk32; gZ = (const TB*)H.Z32; gU = (const TB*)M.U32; gM = (const TB*)D.mfr32;
     }
-    // ---------------- the leaf's tables (its image), then the team's cases and the state, into LDS
+    // ---------------- the leaf's tables (its image), the team's cases and the state, into LDS and
+    // registers.  The global loads go in two rounds issued ahead of any use: first every value that needs
+    // no other loaded value, then those addressed by the first round's indices; the LDS image is copied
+    // while they are in flight.  (One loop per table costs a memory round trip each, ~18 us per launch.)
+    // Every item of a thread belongs to case tid & 15 (512 threads, 16 cases).
+    const int64_t xb = (int64_t)l * NX;
+    const double* hsrc = E.h + (int64_t)(P.step0 & 1) * K * E.nbr;
+    const int cme = tid & 15;
+    const bool cok = cme < nvc;
+    const int64_t crow = (int64_t)(case0 + cme) * n;        // the case's row block of n entries
+    int gbr[kPHItems], hbft[kPHItems], hlost[kPHItems], xrw[kPXItems], rinc[kPRowItems];
+    double lb[kPRowItems], lv[kPRowItems], hcr[kPRowItems];
+    TB lu[kPanelMaxRank * kPRowItems];
+    // round 1
+    const int ucnt = cok ? M.count[case0 + cme] : 0;        // changes stored for the thread's case
+#pragma unroll
+    for (int k = 0; k < kPHItems; ++k) {
+        const int i = tid + k * kPThreads, q = i >> 4;
+        gbr[k] = q < nb ? D.bglob[(int64_t)l * D.NB + q] : 0;
+        hbft[k] = q < nb ? D.hbft[(int64_t)l * D.NB + q] : 0;
+        hlost[k] = q < nb ? D.hlost[(int64_t)tw * D.NB * kPB + i] : 0x7fffffff;
+    }
+#pragma unroll
+    for (int k = 0; k < kPRowItems; ++k) {
+        const int r = (tid + k * kPThreads) >> 4;
+        const bool ok = r < nl && cok;
+        lb[k] = ok ? E.b[crow + lo + r] : 0.0;
+        lv[k] = (MIXED && ok) ? E.v[crow + lo + r] : 0.0;
+        hcr[k] = ok ? E.hC[crow + lo + r] : 0.0;
+        const int64_t rb = (int64_t)l * (D.NL + 1);
+        rinc[k] = r < nl ? (D.iptr[rb + r] | ((D.iptr[rb + r + 1] - D.iptr[rb + r]) << 16)) : 0;
+#pragma unroll
+        for (int j = 0; j < kPanelMaxRank; ++j)      // u_j at own rows (any stored slot is a valid address)
+            lu[j * kPRowItems + k] = (j < R && ok) ? gU[((int64_t)(case0 + cme) * R + j) * n + lo + r] : (TB)0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPXItems; ++k) {
+        const int i = tid + k * kPThreads;
+        xrw[k] = i < nx * kPB ? D.xrow[xb + (i >> 4)] : 0;
+    }
+    const TB* ablk = gblk + H.leaf_off[l];
+    // round 2
+    double lh[kPHItems], lx[kPXItems];
+    TB lux[kPanelMaxRank * kPXItems];
+#pragma unroll
+    for (int k = 0; k < kPHItems; ++k) {
+        const int q = (tid + k * kPThreads) >> 4;
+        lh[k] = (q < nb && cok) ? hsrc[(int64_t)(case0 + cme) * E.nbr + gbr[k]] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPXItems; ++k) {
+        const bool ok = tid + k * kPThreads < nx * kPB && cok;
+        lx[k] = ok ? E.v[crow + xrw[k]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kPanelMaxRank; ++j)
+            lux[j * kPXItems + k] = (ok && j < R) ? gU[((int64_t)(case0 + cme) * R + j) * n + xrw[k]] : (TB)0;
+    }
+    // leaf block as A fragments (zero outside the leaf)
+    const PanelGemm gm = panel_gemm(NLp);
+    const bool mainw = wave < gm.MT, helper = wave >= 6;
+    TB afrag[kPMaxFrag];          // zero outside the leaf and past the wavefront's k-steps
+    {
+#pragma unroll
+        for (int f = 0; f < kPMaxFrag; ++f) {
+            int t, ks;
+            bool ok;
+            if (helper) {
+                t = (wave - 6) + 2 * (f / kPHelpK);
+                ks = gm.KM + f % kPHelpK;
+                ok = t < gm.MT && f % kPHelpK < gm.KT;
+            } else {
+                t = wave;
+                ks = f;
+                ok = mainw && f < gm.KM;
+            }
+            const int row = t * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
+            TB a = 0;
+            if (ok && row < nl && col < nl) a = ablk[(int64_t)col * nl + row];
+            afrag[f] = a;
+        }
+    }
+    // the image copy while the loads above are in flight
     {
         const uint4* src = (const uint4*)(D.img + (int64_t)l * D.imgb);
         uint4* dst = (uint4*)L8;
         const int nq = (int)(Ly.stat / 16);
-#pragma unroll 4
+#pragma unroll 8
         for (int i = tid; i < nq; i += kPThreads) dst[i] = src[i];
-    }
-    const int64_t xb = (int64_t)l * NX;
-    const double* hsrc = E.h + (int64_t)(P.step0 & 1) * K * E.nbr;
-#pragma unroll
-    for (int k = 0; k < kPHItems; ++k) {
-        const int i = tid + k * kPThreads, q = i >> 4, c = i & 15;
-        if (q < nb) h[i] = c < nvc ? hsrc[(int64_t)(case0 + c) * E.nbr + D.bglob[(int64_t)l * D.NB + q]] : 0.0;
-    }
-    for (int i = tid; i < NLp * kPB; i += kPThreads) {  // rows beyond the leaf stay zero (product input)
-        const int r = i >> 4, c = i & 15;
-        const bool ok = r < nl && c < nvc;
-        const int64_t gi = (int64_t)(case0 + c) * n + lo + r;
-        b[i] = ok ? E.b[gi] : 0.0;
-        if (MIXED) {
-            if (!INC) td[i] = 0.0;
-            if (r < nl) v[i] = ok ? E.v[gi] : 0.0;
-        }
-    }
-    for (int i = tid; i < nx * kPB; i += kPThreads) {
-        const int x = i >> 4, c = i & 15;
-        xv[i] = c < nvc ? E.v[(int64_t)(case0 + c) * n + D.xrow[xb + x]] : 0.0;
     }
     if (tid < kPB) {                                    // line changes and losses of each case
         const int c = tid, k = case0 + c;
@@ -478,70 +538,33 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             for (int i = 0; i < r * r; ++i)
                 cinv[c * cs + o + i] = ok ? M.Cinv[((int64_t)k * R + (r - 1)) * R * R + (i / r) * R + i % r] : 0.0;
     }
-    // SMW vectors u_j of each case at own rows ([j][r][c]) and X rows ([j][x][c])
-    for (int i = tid; i < R * NLp * kPB; i += kPThreads) {
-        const int j = i / (NLp * kPB), rc = i - j * NLp * kPB, r = rc >> 4, c = rc & 15;
-        TB u = 0;
-        if (r < nl && c < nvc && j < M.count[case0 + c]) u = gU[((int64_t)(case0 + c) * R + j) * n + lo + r];
-        uo[i] = u;
-    }
-    for (int i = tid; i < R * NX * kPB; i += kPThreads) {
-        const int j = i / (NX * kPB), xc = i - j * NX * kPB, x = xc >> 4, c = xc & 15;
-        TB u = 0;
-        if (x < nx && c < nvc && j < M.count[case0 + c]) u = gU[((int64_t)(case0 + c) * R + j) * n + D.xrow[xb + x]];
-        ux[i] = u;
-    }
-    // the thread's (branch, case) items of the history update: endpoints (combined, packed) and the first
-    // step from which the branch is lost for the case, in registers
-    int hbft[kPHItems], hlost[kPHItems];
+    // the loaded values into LDS (rows beyond the leaf stay zero: product input)
 #pragma unroll
     for (int k = 0; k < kPHItems; ++k) {
-        const int i = tid + k * kPThreads, q = i >> 4;
-        hbft[k] = q < nb ? D.hbft[(int64_t)l * D.NB + q] : 0;
-        hlost[k] = q < nb ? D.hlost[(int64_t)tw * D.NB * kPB + i] : 0x7fffffff;
+        const int i = tid + k * kPThreads;
+        if ((i >> 4) < nb) h[i] = lh[k];
     }
-    // the thread's own-row items of the right-hand side: range of incident branches (first | count << 16)
-    int rinc[kPRowItems];
 #pragma unroll
     for (int k = 0; k < kPRowItems; ++k) {
-        const int r = (tid + k * kPThreads) >> 4;
-        rinc[k] = 0;
-        if (r < nl) {
-            const int64_t rb = (int64_t)l * (D.NL + 1);
-            rinc[k] = D.iptr[rb + r] | ((D.iptr[rb + r + 1] - D.iptr[rb + r]) << 16);
-        }
-    }
-    // capacitor histories of the thread's (row, case) items, in registers
-    double hcr[kPRowItems];
-#pragma unroll
-    for (int it = 0; it < kPRowItems; ++it) {
-        const int i = tid + it * kPThreads, r = i >> 4, c = i & 15;
-        hcr[it] = (r < nl && c < nvc) ? E.hC[(int64_t)(case0 + c) * n + lo + r] : 0.0;
-    }
-    // leaf block as A fragments (zero outside the leaf)
-    const PanelGemm gm = panel_gemm(NLp);
-    const bool mainw = wave < gm.MT, helper = wave >= 6;
-    TB afrag[kPMaxFrag];          // zero outside the leaf and past the wavefront's k-steps
-    {
-        const TB* src = gblk + H.leaf_off[l];
-#pragma unroll
-        for (int f = 0; f < kPMaxFrag; ++f) {
-            int t, ks;
-            bool ok;
-            if (helper) {
-                t = (wave - 6) + 2 * (f / kPHelpK);
-                ks = gm.KM + f % kPHelpK;
-                ok = t < gm.MT && f % kPHelpK < gm.KT;
-            } else {
-                t = wave;
-                ks = f;
-                ok = mainw && f < gm.KM;
+        const int i = tid + k * kPThreads, r = i >> 4;
+        if (i < NLp * kPB) {
+            b[i] = lb[k];
+            if (MIXED) {
+                if (!INC) td[i] = 0.0;
+                if (r < nl) v[i] = lv[k];
             }
-            const int row = t * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
-            TB a = 0;
-            if (ok && row < nl && col < nl) a = src[(int64_t)col * nl + row];
-            afrag[f] = a;
+#pragma unroll
+            for (int j = 0; j < kPanelMaxRank; ++j)      // SMW vectors u_j at own rows ([j][r][c])
+                if (j < R) uo[j * NLp * kPB + i] = j < ucnt ? lu[j * kPRowItems + k] : (TB)0;
         }
+    }
+#pragma unroll
+    for (int k = 0; k < kPXItems; ++k) {
+        const int i = tid + k * kPThreads;
+        if (i < nx * kPB) xv[i] = lx[k];
+#pragma unroll
+        for (int j = 0; j < kPanelMaxRank; ++j)          // and at X rows ([j][x][c]), zero past nx
+            if (j < R && i < NX * kPB) ux[j * NX * kPB + i] = (i < nx * kPB && j < ucnt) ? lux[j * kPXItems + k] : (TB)0;
     }
     __syncthreads();
 
