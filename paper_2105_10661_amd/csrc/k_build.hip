@@ -288,6 +288,8 @@ __global__ __launch_bounds__(kGjThreads) void k_node_inverse(HierDev H, const in
 // pivot that is zero or not finite raises kFlagSingular; the whole team stops after the same
 // barrier.
 constexpr int kGjNB = 16;
+constexpr int kGjMS = kGjNB + 1;    // row stride of the LDS row copies: 17 doubles, so the rows of a
+                                    // wavefront's lanes start in different banks (16 put them all in one)
 constexpr int kGjTeamThreads = 1024;
 static_assert(kGjTeamMax <= kGjTeamThreads, "one row per thread");
 
@@ -300,7 +302,7 @@ __host__ __device__ inline GjTeamLayout gj_team_layout(int mmax)
     GjTeamLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = (off + bytes + 15) / 16 * 16; return o; };
-    L.mir = take(sizeof(double) * (size_t)mmax * kGjNB);     // row i's copy at i * kGjNB
+    L.mir = take(sizeof(double) * (size_t)mmax * kGjMS);     // row i's copy at i * kGjMS
     L.oldp = take(sizeof(double) * kGjNB * kGjNB);
     L.wmax = take(sizeof(unsigned) * 32);
     L.rof = take(sizeof(int) * (size_t)mmax);
@@ -355,7 +357,7 @@ __device__ __forceinline__ void gj_team_step(double (&x)[kGjNB], int& used, bool
     const int r = 1023 - (int)(kv & 0x3FF);
     double pr[kGjNB];
 #pragma unroll
-    for (int jj = 0; jj < kGjNB; ++jj) pr[jj] = S.mir[r * kGjNB + jj];
+    for (int jj = 0; jj < kGjNB; ++jj) pr[jj] = S.mir[r * kGjMS + jj];
     const double p = pr[KK];
     if (!(fabs(p) > 0.0) || !isfinite(p)) { bad = true; return; }
     const double pinv = 1.0 / p;
@@ -371,7 +373,7 @@ __device__ __forceinline__ void gj_team_step(double (&x)[kGjNB], int& used, bool
         for (int jj = 0; jj < kGjNB; ++jj) x[jj] = (jj == KK) ? -xk * pinv : x[jj] - xk * pr[jj];
         if (!used)
 #pragma unroll
-            for (int jj = 0; jj < kGjNB; ++jj) S.mir[S.tid * kGjNB + jj] = x[jj];
+            for (int jj = 0; jj < kGjNB; ++jj) S.mir[S.tid * kGjMS + jj] = x[jj];
     }
 }
 
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(kGjTeamThreads) void k_gj_team(HierDev H, const int
         if (q == w) {
             if (!used)
 #pragma unroll
-                for (int jj = 0; jj < kGjNB; ++jj) mir[tid * kGjNB + jj] = x[jj];
+                for (int jj = 0; jj < kGjNB; ++jj) mir[tid * kGjMS + jj] = x[jj];
             bool bad = false;
             const GjTeamStep S{mir, wmax, rof, sof, k0, tid, lane, wave};
 #define HINV_GJ_STEP(K) if (K < nk && !bad) gj_team_step<K>(x, used, bad, S);
