@@ -461,6 +461,9 @@ __global__ __launch_bounds__(kGjTeamThreads) void k_gj_team(HierDev H, const int
             if (tid < kGjNB) xchg_store(&xq[(int64_t)m * kGjNB + tid], bad ? -1.0 : (tid < nk ? (double)rof[k0 + tid] : 0.0));
         }
         if (!team_barrier(flg, w, W, ++epoch, flags, ctl + 2)) return;
+        double pv[kGjNB];    // the panel's transformed rows, loaded with the pivot list (one round trip)
+#pragma unroll
+        for (int b = 0; b < kGjNB; ++b) pv[b] = (own && q != w && b < nk) ? xchg_load(&xq[(int64_t)tid * kGjNB + b]) : 0.0;
         if (tid < kGjNB) piv[tid] = (int)xchg_load(&xq[(int64_t)m * kGjNB + tid]);
         __syncthreads();
         if (piv[0] < 0) {
@@ -479,9 +482,6 @@ __global__ __launch_bounds__(kGjTeamThreads) void k_gj_team(HierDev H, const int
         if (tid < nk) { rof[k0 + tid] = piv[tid]; sof[piv[tid]] = k0 + tid; }
         __syncthreads();
         if (own) {
-            double pv[kGjNB];
-#pragma unroll
-            for (int b = 0; b < kGjNB; ++b) pv[b] = b < nk ? xchg_load(&xq[(int64_t)tid * kGjNB + b]) : 0.0;
 #pragma unroll
             for (int jj = 0; jj < kGjNB; ++jj) x[jj] = (mine >= 0) ? 0.0 : x[jj];
 #pragma unroll
