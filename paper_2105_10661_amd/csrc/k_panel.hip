@@ -537,6 +537,9 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
         for (int r = 1, o = 0; r <= R; o += r * r, ++r)
             for (int i = 0; i < r * r; ++i)
                 cinv[c * cs + o + i] = ok ? M.Cinv[((int64_t)k * R + (r - 1)) * R * R + (i / r) * R + i % r] : 0.0;
+        int ra = 0;                                     // changes active at the launch's first step
+        while (ra < (ok ? M.count[k] : 0) && (int64_t)(ok ? M.act[k * R + ra] : 0x7fffffff) <= P.step0) ++ra;
+        ract[c] = ra;
     }
     // the loaded values into LDS (rows beyond the leaf stay zero: product input)
 #pragma unroll
@@ -945,13 +948,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 if (c < nvc) P.b_rec[(jr * K + case0 + c) * (int64_t)n + prow[i >> 4]] = b[i];
             }
         }
-        if (tid < kPB) {
-            int ra = 0;
-            while (ra < cnt[tid] && (int64_t)mact[tid * R + ra] <= step) ++ra;
-            ract[tid] = ra;
-        }
-        __syncthreads();
-        bool anyact = false;
+        bool anyact = false;      // ract holds this step's active changes (set before the last barrier)
         for (int c = 0; c < kPB; ++c) anyact |= ract[c] > 0;
         if constexpr (!MIXED) {
             alive = apply(b, v, xv, anyact, false);
@@ -980,6 +977,11 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             }
         }
         __syncthreads();
+        if (tid < kPB) {          // the next step's active changes (nothing reads ract until then)
+            int ra = 0;
+            while (ra < cnt[tid] && (int64_t)mact[tid * R + ra] <= step + 1) ++ra;
+            ract[tid] = ra;
+        }
 #pragma unroll
         for (int k = 0; k < kPRowItems; ++k) {
             const int i = tid + k * kPThreads, r = i >> 4, c = i & 15;
