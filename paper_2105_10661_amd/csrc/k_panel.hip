@@ -947,6 +947,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                 const int c = i & 15;
                 if (c < nvc) P.b_rec[(jr * K + case0 + c) * (int64_t)n + prow[i >> 4]] = b[i];
             }
+            __syncthreads();     // every thread has read b before the incremental form's residual replaces it
         }
         bool anyact = false;      // ract holds this step's active changes (set before the last barrier)
         for (int c = 0; c < kPB; ++c) anyact |= ract[c] > 0;

@@ -103,20 +103,36 @@ __device__ void wg_levels(const HierDev& H, const TB* __restrict__ Z, const TB* 
     }
 }
 
-// Active line changes of case k at `step` on out (LDS).
+// Active line changes of case k at `step` on out (LDS); x is the apply's input.  Each change's
+// coefficient is t_j = u_j^T x with u_j = G0^{-1} w_j (G0 symmetric: the same as w_j^T G0^{-1} x), taken
+// from x rather than from the apply's values at the change's endpoints, which carry the stored
+// inverse's rounding (FP32 storage: ~1e-7 relative) into a term that the capacitance's inverse
+// amplifies when the change nearly separates the network (a bus left on its shunt capacitor).  The
+// sum over rows is a fixed tree (per wavefront, then the wavefronts in order): red holds one value per
+// wavefront.
 template <typename TU>
-__device__ void wg_smw(const ModDev& M, const TU* __restrict__ U, int k, int64_t step, double* out, double* tz)
+__device__ void wg_smw(const ModDev& M, const TU* __restrict__ U, int k, int64_t step, const double* x, double* out,
+                       double* tz, double* red)
 {
     const int cnt = M.count[k];
     int r = 0;
     while (r < cnt && (int64_t)M.act[k * M.R + r] <= step) ++r;
     if (r == 0) return;
-    const int tid = threadIdx.x;
-    if (tid < r) {
-        const int a = M.a[k * M.R + tid], b = M.b[k * M.R + tid];
-        tz[tid] = out[a] - (b >= 0 ? out[b] : 0.0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = 0; j < r; ++j) {
+        const TU* u = U + ((int64_t)k * M.R + j) * M.n;
+        double acc = 0.0;
+        for (int i = tid; i < M.n; i += kRunThreads) acc = fma((double)u[i], x[i], acc);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) red[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < kRunThreads / 64; ++w) sum += red[w];
+            tz[j] = sum;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (tid < r) {
         const double* Ci = M.Cinv + ((int64_t)k * M.R + (r - 1)) * M.R * M.R;
         double acc = 0.0;
@@ -135,11 +151,11 @@ __device__ void wg_smw(const ModDev& M, const TU* __restrict__ U, int k, int64_t
 template <typename TB>
 __device__ void wg_precond(const HierDev& H, const ModDev& M, const TB* blk, const TB* Z, const TB* Sinv,
                            const TB* U, int k, int64_t step, const double* x, double* out, double* s, double* y,
-                           double* tz)
+                           double* tz, double* red)
 {
     wg_leaf_apply<TB>(H, blk, x, out);
     wg_levels<TB>(H, Z, Sinv, out, s, y);
-    if (M.R > 0) wg_smw<TB>(M, U, k, step, out, tz);
+    if (M.R > 0) wg_smw<TB>(M, U, k, step, x, out, tz, red);
 }
 
 // t = b - G_step v (FP64, LDS vectors).
@@ -218,18 +234,18 @@ __device__ __forceinline__ void emt_run_body(const EmtDev& E, const HierDev& H, 
         const int64_t step = P.step0 + it;
         // ---- solve G_step v = b
         if (!MIXED) {
-            wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz);
+            wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz, red);
             applies += 1;
         } else {
             int done = 0;
             if (!WARM) {
-                wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz);
+                wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, b, v, s, y, tz, red);
                 applies += 1;
             }
             const int nref = INC ? 1 : P.max_refine + (WARM ? 1 : 0);
             for (int rf = 0; rf < nref && !done; ++rf) {
                 wg_residual(H, M, k, step, b, v, t);
-                wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, t, d, s, y, tz);
+                wg_precond<TB>(H, M, blk, Zs, Si, U, k, step, t, d, s, y, tz, red);
                 applies += 1;
                 if constexpr (INC) {
                     for (int i = tid; i < n; i += kRunThreads) v[i] += d[i];
