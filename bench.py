@@ -536,15 +536,16 @@ def contingency_batch(hinv, torch, args, khz):
 
 
 def single_case(hinv, torch, args, khz):
-    """The single 1432-bus case (one team of workgroups per case): FP64 and mixed, 10000 steps with one
-    line lost at step 2000, full trajectories against the oracle."""
+    """The single 1432-bus case (one team of workgroups per case): FP64 solved directly and in the
+    incremental form, and mixed, 10000 steps with one line lost at step 2000, full trajectories against
+    the oracle."""
     from paper_2105_10661_amd import cases
     import oracle
     case = cases.case_c2(n_steps=10000)
     net = case.net
     losses = [list(zip(case.loss_steps.tolist(), case.loss_branches.tolist()))]
-    paths = {"fp64": ("fp64", False, 0, 1e-9), "mixed": ("fp32", True, args.max_refine, args.rel_tol),
-             "mixed_2apply": ("fp32", True, 1, 1e-6)}
+    paths = {"fp64": ("fp64", False, 0, 1e-9), "fp64_inc": ("fp64", True, 0, 1e-9),
+             "mixed": ("fp32", True, args.max_refine, args.rel_tol), "mixed_2apply": ("fp32", True, 1, 1e-6)}
     t0 = time.perf_counter()
     Vref, _ = oracle.emt_run(net, 10000, loss_steps=case.loss_steps, loss_branches=case.loss_branches, solver="inv")
     cpu_s = time.perf_counter() - t0

@@ -2109,7 +2109,7 @@ bool build_team_plan(emt_ctx& c, int R)
         }
         D.nA = std::max(na, 1);
     }
-    if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
+    if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec, c.hc.opt.warm_start ? 1 : 0) > 160 * 1024) return false;
     const int Hs = std::max(H, 1);
     (void)Hs;
     auto flat = [&](std::vector<int>& dst, size_t stride, auto get) {
@@ -2161,7 +2161,7 @@ bool build_team_plan(emt_ctx& c, int R)
     flatd(c.tsamp, NS, [](W& w) -> std::vector<double>& { return w.samp; });
     flatd(c.tsph, NS, [](W& w) -> std::vector<double>& { return w.sph; });
     D.NX = NXc;   // strides of the device tables (and the LDS layout)
-    if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec) > 160 * 1024) return false;
+    if (team_lds_bytes(D, c.hc.H, R, c.hc.opt.prec, c.hc.opt.warm_start ? 1 : 0) > 160 * 1024) return false;
     c.table_error = check_team_tables(c);
     return c.table_error.empty();
 }
@@ -2921,7 +2921,7 @@ bool build_level_plan(emt_ctx& c, int R)
     LevelDev& D = c.LD;
     D.T = L; D.H = H; D.NL = NL; D.NX = c.level_nx_cap; D.NB = NB; D.NE = NE; D.NI = NI; D.NS = NS; D.ZO = ZO;
     D.NO = NO; D.SO = SO; D.PM = PM;
-    if (level_lds_bytes(D, R, c.hc.opt.prec) > 160 * 1024) return false;
+    if (level_lds_bytes(D, R, c.hc.opt.prec, c.hc.opt.warm_start ? 1 : 0) > 160 * 1024) return false;
     const int Hs = std::max(H, 1);
     auto flat = [&](std::vector<int>& dst, size_t stride, auto get) {
         dst.assign((size_t)L * stride, 0);
@@ -3909,7 +3909,7 @@ hinv_status serve_step(serve_handle h, int32_t n_steps, void* stream)
                                  (hipStream_t)stream));
     }
     if (!S.ltable.empty()) {
-        if (level_lds_bytes(S.Ld, S.lR, S.opt.prec) > 160 * 1024)
+        if (level_lds_bytes(S.Ld, S.lR, S.opt.prec, 0) > 160 * 1024)       // serving: FP64 solved directly
             return fail(HINV_E_INVALID, "the served cases' level tables exceed LDS together");
         HIP_TRY(launch_emt_level_multi(S.Ld, S.lR, S.d_lcases, S.lwg.data(), S.lsync.data(), (int)S.ltable.size(),
                                        n_steps, S.opt.prec, S.opt.warm_start, (hipStream_t)stream));

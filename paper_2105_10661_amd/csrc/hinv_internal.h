@@ -507,7 +507,7 @@ void launch_emt_rebuild_rhs(const EmtDev& E, int k, hipStream_t s);
 // Stream-ordered update of the record parameters (kernel argument, no host buffer to keep alive).
 void launch_set_rec(RecParams* d, const RecParams& val, hipStream_t s);
 // Team stepping (k_team.hip): LDS bytes of the layout, and the launch.
-size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec);
+size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec, int warm);
 hipError_t launch_team_acoef(const TeamDev& T, const HierDev& H, hipStream_t s);
 // y of every coupling column as a map of u (y = bm u; am: scratch), bottom-up over the levels from the
 // FP64 Z panels, S^{-1} and column weights (cpan: [nc*Hn] panel of the column's row at each lower level).
@@ -529,7 +529,7 @@ hipError_t launch_panel_image(const PanelDev& D, const EmtDev& E, const HierDev&
 hipError_t launch_emt_panel(const PanelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
 // Level stepping (k_level.hip): LDS bytes of the layout, and the launch.
-size_t level_lds_bytes(const LevelDev& D, int R, int prec);
+size_t level_lds_bytes(const LevelDev& D, int R, int prec, int warm);   // warm: FP64 incremental form
 hipError_t launch_emt_level(const LevelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s);
 // Several cases, each a team of its T workgroups, in as few cooperative launches as residency

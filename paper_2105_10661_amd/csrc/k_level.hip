@@ -103,9 +103,10 @@ __host__ __device__ inline LevelLayout level_layout(const LevelDev& D, int R)
     return L;
 }
 
-size_t level_lds_bytes(const LevelDev& D, int R, int prec)
+size_t level_lds_bytes(const LevelDev& D, int R, int prec, int warm)
 {
-    return prec == HINV_FP64 ? level_layout<double, false>(D, R).total : level_layout<float, true>(D, R).total;
+    if (prec != HINV_FP64) return level_layout<float, true>(D, R).total;
+    return warm ? level_layout<double, true>(D, R).total : level_layout<double, false>(D, R).total;
 }
 
 // The stepping of one case by its T workgroups (w = this workgroup's leaf).  Ld gives the LDS
@@ -116,6 +117,10 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
                            const RunParams& P, int64_t step0, int w, unsigned char* L8)
 {
     using TA = typename LAcc<TB>::T;
+    // MIXED with FP64 storage is the incremental form v = v_prev + P (b - G v_prev): one FP64 apply of
+    // the residual per step, no convergence statistics
+    constexpr bool INC = MIXED && sizeof(TB) == 8;
+    static_assert(!INC || WARM, "the incremental FP64 form starts from the previous step's voltages");
     const int R = M.R;
     const LevelLayout Ly = level_layout<TB, MIXED>(Ld, R);
     const int tid = threadIdx.x, lane = tid & 63;
@@ -292,7 +297,7 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
     // out (own rows), outx (X rows) from xin (own rows)
     // tags of the y exchange: ((step + 1) * applies per step + apply of the step) * 8 + level, unique
     // over the case's run (the buffer is cleared when the tables are uploaded)
-    const int64_t A = MIXED ? (int64_t)P.max_refine + 1 : 1;
+    const int64_t A = (MIXED && !INC) ? (int64_t)P.max_refine + 1 : 1;
     const int ncol = H.lvl_col[Hn];      // coupling columns of the tree
     int64_t cur_step = step0;
     int ais = 0;
@@ -474,13 +479,13 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
             alive = apply(b, v, xv, ract, false);
             applies += 1;
         } else {
-            const int nref = WARM ? P.max_refine + 1 : P.max_refine;
+            const int nref = INC ? 1 : (WARM ? P.max_refine + 1 : P.max_refine);
             if (!WARM) {
                 alive = apply(b, v, xv, ract, false);
                 applies += 1;
             }
             for (int q = 0; q < nref && alive; ++q) {
-                alive = refine(ract, q == nref - 1);
+                alive = refine(ract, !INC && q == nref - 1);
                 applies += 1;
             }
         }
@@ -543,7 +548,7 @@ __device__ void level_body(const LevelDev& Ld, const LevelDev& D, const EmtDev& 
     for (int q = tid; q < nb; q += kLThreads)
         if (D.bown[(int64_t)w * D.NB + q]) E.h[(int64_t)(nstep & 1) * E.n_cases * E.nbr + bglob[q]] = hc[q];
     if (tid == 0) {
-        if (MIXED && P.stats) atomicMax(&P.stats[0], (unsigned long long)__double_as_longlong(worst));
+        if (MIXED && !INC && P.stats) atomicMax(&P.stats[0], (unsigned long long)__double_as_longlong(worst));
         if (w == 0) {
             if (P.applies) atomicAdd(&P.applies[0], (unsigned long long)applies);
             *E.step = nstep;
@@ -619,7 +624,8 @@ static hipError_t launch_level_t(const LevelDev& D, const EmtDev& E, const HierD
 hipError_t launch_emt_level(const LevelDev& D, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                             int prec, hipStream_t s)
 {
-    if (prec == HINV_FP64) return launch_level_t<double, false, false>(D, E, H, M, P, s);
+    if (prec == HINV_FP64)
+        return P.warm ? launch_level_t<double, true, true>(D, E, H, M, P, s) : launch_level_t<double, false, false>(D, E, H, M, P, s);
     if (P.warm) return launch_level_t<float, true, true>(D, E, H, M, P, s);
     return launch_level_t<float, true, false>(D, E, H, M, P, s);
 }

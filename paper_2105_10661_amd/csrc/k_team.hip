@@ -46,7 +46,7 @@ struct TeamLayout {
 };
 
 template <typename TB>
-__host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
+__host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R, bool refines)
 {
     TeamLayout L{};
     size_t o = 0;
@@ -56,9 +56,9 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
         return r;
     };
     const size_t NL = T.NL, NX = T.NX, H = T.H, nc = T.nc;
-    // FP32 storage refines against G in FP64; the FP64 path has no use for G's rows or the
-    // correction vectors, and its LDS is the tighter one
-    const bool refines = sizeof(TB) != 8;
+    // FP32 storage refines against G in FP64, and so does the incremental FP64 form (its residual);
+    // the direct FP64 path has no use for G's rows or the correction vectors, and its LDS is the
+    // tighter one
     L.blk = take(sizeof(TB) * NL * NL);
     L.sall = take(sizeof(TB) * (size_t)T.sent);
     L.zown = take(sizeof(TB) * (size_t)T.ZO);
@@ -96,20 +96,24 @@ __host__ __device__ inline TeamLayout team_layout(const TeamDev& T, int R)
     return L;
 }
 
-size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec)
+size_t team_lds_bytes(const TeamDev& T, const HierDev& H, int R, int prec, int warm)
 {
     (void)H;
-    return prec == HINV_FP64 ? team_layout<double>(T, R).total : team_layout<float>(T, R).total;
+    return prec == HINV_FP64 ? team_layout<double>(T, R, warm != 0).total : team_layout<float>(T, R, true).total;
 }
 
 template <typename TB, bool MIXED, bool WARM>
 __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, HierDev H, ModDev M, RunParams P)
 {
     using TA = typename TAcc<TB>::T;
-    static_assert(MIXED == (sizeof(TB) != 8), "the LDS layout keeps the refinement buffers for FP32 storage only");
+    // MIXED with FP64 storage is the incremental form v = v_prev + P (b - G v_prev): one FP64 apply of
+    // the residual per step, no convergence statistics
+    constexpr bool INC = MIXED && sizeof(TB) == 8;
+    static_assert(MIXED || sizeof(TB) == 8, "FP32 storage refines");
+    static_assert(!INC || WARM, "the incremental FP64 form starts from the previous step's voltages");
     extern __shared__ __attribute__((aligned(16))) unsigned char L8[];
     const int R = M.R;
-    const TeamLayout Ly = team_layout<TB>(T, R);
+    const TeamLayout Ly = team_layout<TB>(T, R, MIXED);
     const int w = blockIdx.x, tid = threadIdx.x;
     const int n = H.n, NL = T.NL, NX = T.NX, Hn = T.H, nc = T.nc;
     const int lo = T.w_lo[w], nl = T.w_nl[w], nx = T.w_nx[w], nb = T.w_nb[w], nxu = T.w_nxu[w], ny = T.w_ny[w];
@@ -512,13 +516,13 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
             alive = apply(b, v, xv, ract, false);
             applies += 1;
         } else {
-            const int nref = WARM ? P.max_refine + 1 : P.max_refine;
+            const int nref = INC ? 1 : (WARM ? P.max_refine + 1 : P.max_refine);
             if (!WARM) {
                 alive = apply(b, v, xv, ract, false);
                 applies += 1;
             }
             for (int q = 0; q < nref && alive; ++q) {
-                alive = refine(ract, q == nref - 1);
+                alive = refine(ract, !INC && q == nref - 1);
                 applies += 1;
             }
         }
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(kTeamThreads) void k_emt_team(TeamDev T, EmtDev E, 
     for (int q = tid; q < nb; q += kTeamThreads)
         if (T.bown[(int64_t)w * T.NB + q]) E.h[(int64_t)(nstep & 1) * E.n_cases * E.nbr + bglob[q]] = hc[q];
     if (tid == 0) {
-        if (MIXED && P.stats) atomicMax(&P.stats[0], (unsigned long long)__double_as_longlong(worst));
+        if (MIXED && !INC && P.stats) atomicMax(&P.stats[0], (unsigned long long)__double_as_longlong(worst));
         if (w == 0) {
             if (P.applies) atomicAdd(&P.applies[0], (unsigned long long)applies);
             *E.step = nstep;
@@ -587,7 +591,7 @@ template <typename TB, bool MIXED, bool WARM>
 static hipError_t launch_team_t(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M,
                                 const RunParams& P, hipStream_t s)
 {
-    const size_t lds = team_layout<TB>(T, M.R).total;
+    const size_t lds = team_layout<TB>(T, M.R, MIXED).total;
     const void* fn = (const void*)k_emt_team<TB, MIXED, WARM>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -607,7 +611,8 @@ static hipError_t launch_team_t(const TeamDev& T, const EmtDev& E, const HierDev
 hipError_t launch_emt_team(const TeamDev& T, const EmtDev& E, const HierDev& H, const ModDev& M, const RunParams& P,
                            int prec, hipStream_t s)
 {
-    if (prec == HINV_FP64) return launch_team_t<double, false, false>(T, E, H, M, P, s);
+    if (prec == HINV_FP64)
+        return P.warm ? launch_team_t<double, true, true>(T, E, H, M, P, s) : launch_team_t<double, false, false>(T, E, H, M, P, s);
     if (P.warm) return launch_team_t<float, true, true>(T, E, H, M, P, s);
     return launch_team_t<float, true, false>(T, E, H, M, P, s);
 }
