@@ -98,8 +98,9 @@ typedef struct {
                               v = v_prev + P (b - G v_prev), one FP64 apply per step (max_refine and
                               rel_tol unused); equal to P b in exact arithmetic, it keeps rounding from
                               accumulating along a mode the step map does not damp (a bus whose only
-                              line is lost keeps its voltage on its shunt capacitor).  FP64 on the
-                              per-kernel engine 1 and in serving solves directly. */
+                              line is lost keeps its voltage on its shunt capacitor); serving takes the
+                              pool's warm_start the same way.  FP64 on the per-kernel engine 1 solves
+                              directly. */
     int32_t kernel_mode;   /* EMT engine: 0 = automatic (one case: 3, else 5, when it fits;
                               several cases: 4 when it fits; else 2 when it fits, else 1); 1 = one
                               launch per kernel per step (any size); 2 = one fused launch per

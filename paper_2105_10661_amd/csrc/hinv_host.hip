@@ -3851,7 +3851,7 @@ hinv_status serve_attach(serve_handle h, emt_handle e, double* d_v_record, int64
     if ((int)S.slot.size() >= S.max_slots) return fail(HINV_E_NO_MEMORY, "all %d slots are in use", S.max_slots);
     if (c.n_cases != 1) return fail(HINV_E_INVALID, "a served handle holds exactly one case");
     if (c.ph != 1) return fail(HINV_E_INVALID, "the serving pool takes single-phase networks only");
-    if (c.hc.opt.prec != S.opt.prec || (c.hc.opt.prec != HINV_FP64 && (c.hc.opt.warm_start != 0) != (S.opt.warm_start != 0)))
+    if (c.hc.opt.prec != S.opt.prec || (c.hc.opt.warm_start != 0) != (S.opt.warm_start != 0))
         return fail(HINV_E_INVALID, "the case's precision / warm start differ from the pool's");
     for (emt_ctx* o : S.owner)
         if (o == e) return fail(HINV_E_INVALID, "the case is already attached");
@@ -3909,7 +3909,7 @@ hinv_status serve_step(serve_handle h, int32_t n_steps, void* stream)
                                  (hipStream_t)stream));
     }
     if (!S.ltable.empty()) {
-        if (level_lds_bytes(S.Ld, S.lR, S.opt.prec, 0) > 160 * 1024)       // serving: FP64 solved directly
+        if (level_lds_bytes(S.Ld, S.lR, S.opt.prec, S.opt.warm_start ? 1 : 0) > 160 * 1024)
             return fail(HINV_E_INVALID, "the served cases' level tables exceed LDS together");
         HIP_TRY(launch_emt_level_multi(S.Ld, S.lR, S.d_lcases, S.lwg.data(), S.lsync.data(), (int)S.ltable.size(),
                                        n_steps, S.opt.prec, S.opt.warm_start, (hipStream_t)stream));

@@ -671,7 +671,8 @@ hipError_t launch_emt_level_multi(const LevelDev& Ld, int R, const LevelCase* d_
                                   unsigned int* const* sync, int n_cases, int n_steps, int prec, int warm, hipStream_t s)
 {
     if (prec == HINV_FP64)
-        return launch_level_multi_t<double, false, false>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
+        return warm ? launch_level_multi_t<double, true, true>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s)
+                    : launch_level_multi_t<double, false, false>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
     if (warm) return launch_level_multi_t<float, true, true>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
     return launch_level_multi_t<float, true, false>(Ld, R, d_cases, n_wg, sync, n_cases, n_steps, s);
 }

@@ -418,7 +418,9 @@ hipError_t launch_emt_serve(const ServeSlot* d_slots, int n_slots, int n_steps, 
                             hipStream_t s)
 {
     if (n_slots <= 0) return hipSuccess;
-    if (prec == HINV_FP64) return launch_serve_t<double, false, false>(d_slots, n_slots, n_steps, lds, s);
+    if (prec == HINV_FP64)
+        return warm ? launch_serve_t<double, true, true>(d_slots, n_slots, n_steps, lds, s)
+                    : launch_serve_t<double, false, false>(d_slots, n_slots, n_steps, lds, s);
     if (warm) return launch_serve_t<float, true, true>(d_slots, n_slots, n_steps, lds, s);
     return launch_serve_t<float, true, false>(d_slots, n_slots, n_steps, lds, s);
 }
