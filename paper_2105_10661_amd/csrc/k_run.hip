@@ -3,12 +3,14 @@
 // per step; Section IV's line change as the SMW correction).
 //
 // Per step, inside the workgroup:
-//   apply        v0 = B^{-1} b leaf by leaf, then every coupling level bottom-up
+//   apply        v0 = B^{-1} x leaf by leaf, then every coupling level bottom-up
 //                (s = U^T v, y = S^{-1} s, v -= Z y), then the active line
-//                changes v -= U_m C_m^{-1} W_m^T v;
+//                changes v -= U_m C_m^{-1} (U_m^T x) (U_m = G0^{-1} W_m, so U_m^T x
+//                equals W_m^T G0^{-1} x, taken from the input x);
 //   refinement   (low-precision storage) t = b - G v in FP64, v += P t, until the
 //                correction is below rel_tol * |v| or max_refine corrections;
-//                optionally warm-started from the previous step's v;
+//                optionally warm-started from the previous step's v; FP64 storage
+//                warm-started is the incremental form, one pass v += P (b - G v);
 //   history      trapezoidal history currents with v_n and b_{n+1}.
 // The case's vectors b (right-hand side), v (solution), t (residual) and d
 // (correction) live in LDS for the whole launch; the stored

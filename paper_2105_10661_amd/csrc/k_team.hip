@@ -17,7 +17,9 @@
 //      own rows and X rows, then the SMW correction.
 // Rows shared by two workgroups are computed with identical operations in
 // both, so their values agree bitwise and the history update of a tie line
-// (and the refinement residual) needs no second exchange.
+// (and the refinement residual) needs no second exchange.  FP32 storage refines
+// against the FP64 residual; FP64 storage warm-started runs the incremental form
+// v = v_prev + P (b - G v_prev), one apply per step.
 #include "hinv_internal.h"
 #include "team_sync.h"
 
