@@ -12,7 +12,9 @@
 //   3. the own rows' values are published; barrier; every workgroup reads its X rows
 //      (neighbours through G, line-loss endpoints) and applies the active line changes' SMW
 //      correction to own rows and X rows with the same operations, so shared rows agree bitwise.
-// Each exchanged value has exactly one writer, so no row is computed twice.
+// Each exchanged value has exactly one writer, so no row is computed twice.  FP32 storage refines
+// against the FP64 residual; FP64 storage warm-started runs the incremental form
+// v = v_prev + P (b - G v_prev), one apply per step.
 #include "hinv_internal.h"
 #include "team_sync.h"
 
