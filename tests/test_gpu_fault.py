@@ -107,6 +107,21 @@ def test_fault_scenario_fp64(hv, mode, n_cases, kind):
         assert info["leaves"] == 1 and info["lca_level"] == 0
 
 
+@pytest.mark.parametrize("kind", ["ground", "between_leaves"])
+@pytest.mark.parametrize("mode,n_cases", [("fused", 1), ("team", 1), ("level", 1), ("panel", 3)])
+def test_fault_scenario_fp64_incremental(hv, mode, n_cases, kind):
+    """The incremental FP64 form (warm_start): its residual takes the step's G, so the switched fault's
+    conductance enters through the residual as well as through the rebuilt inverse."""
+    net = _net()
+    a, b = _fault(net, kind)
+    losses = _losses(net, a, b, n_cases)
+    print(f"[gpu] fault {kind} ({a},{b}) engine={mode} cases={n_cases} fp64 incremental", flush=True)
+    V, _ = _run(hv, net, kind, losses, prec="fp64", max_refine=0, max_mod_rank=1, warm_start=True, kernel_mode=mode)
+    for k, ref in enumerate(_reference(net, kind, losses)):
+        err = np.abs(V[:, k, :] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-10, (k, err)
+
+
 @pytest.mark.parametrize("mode,n_cases", [("team", 1), ("level", 1), ("panel", 3), ("fused", 1)])
 def test_fault_scenario_fp32_refined(hv, mode, n_cases):
     net = _net()
