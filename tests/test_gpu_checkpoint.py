@@ -66,8 +66,13 @@ def _run_a(hv, net, kw, losses, dyn, fault):
 ENGINES = [("per_kernel", 3), ("fused", 3), ("panel", 20), ("team", 1), ("level", 1)]
 
 
-@pytest.mark.parametrize("engine,n_cases", ENGINES)
-@pytest.mark.parametrize("prec,warm,refine", [("fp64", False, 0), ("fp32", True, 2)])
+RESUME_CASES = ([(e, n, "fp64", False, 0) for e, n in ENGINES] + [(e, n, "fp32", True, 2) for e, n in ENGINES]
+                # the incremental FP64 form (v carries over from step to step); the panel's incremental layout
+                # takes one change per case, this scenario two
+                + [(e, n, "fp64", True, 0) for e, n in ENGINES if e in ("fused", "team", "level")])
+
+
+@pytest.mark.parametrize("engine,n_cases,prec,warm,refine", RESUME_CASES)
 def test_resume_is_bitwise(hv, engine, n_cases, prec, warm, refine):
     import torch
     net = cases.net_ring(8, 4) if engine in ("panel", "team", "level") else cases.net_179()
