@@ -94,13 +94,12 @@ typedef struct {
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
     int32_t warm_start;    /* EMT, FP32/BF16/FP8 storage: refine from the previous step's v instead of
-                              P b.  FP64 storage, engines 2, 3, 4 and 5: the incremental form
+                              P b.  FP64 storage, every engine: the incremental form
                               v = v_prev + P (b - G v_prev), one FP64 apply per step (max_refine and
                               rel_tol unused); equal to P b in exact arithmetic, it keeps rounding from
                               accumulating along a mode the step map does not damp (a bus whose only
                               line is lost keeps its voltage on its shunt capacitor); serving takes the
-                              pool's warm_start the same way.  FP64 on the per-kernel engine 1 solves
-                              directly. */
+                              pool's warm_start the same way. */
     int32_t kernel_mode;   /* EMT engine: 0 = automatic (one case: 3, else 5, when it fits;
                               several cases: 4 when it fits; else 2 when it fits, else 1); 1 = one
                               launch per kernel per step (any size); 2 = one fused launch per

@@ -69,7 +69,7 @@ ENGINES = [("per_kernel", 3), ("fused", 3), ("panel", 20), ("team", 1), ("level"
 RESUME_CASES = ([(e, n, "fp64", False, 0) for e, n in ENGINES] + [(e, n, "fp32", True, 2) for e, n in ENGINES]
                 # the incremental FP64 form (v carries over from step to step); the panel's incremental layout
                 # takes one change per case, this scenario two
-                + [(e, n, "fp64", True, 0) for e, n in ENGINES if e in ("fused", "team", "level")])
+                + [(e, n, "fp64", True, 0) for e, n in ENGINES if e in ("per_kernel", "fused", "team", "level")])
 
 
 @pytest.mark.parametrize("engine,n_cases,prec,warm,refine", RESUME_CASES)

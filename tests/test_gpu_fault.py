@@ -108,7 +108,7 @@ def test_fault_scenario_fp64(hv, mode, n_cases, kind):
 
 
 @pytest.mark.parametrize("kind", ["ground", "between_leaves"])
-@pytest.mark.parametrize("mode,n_cases", [("fused", 1), ("team", 1), ("level", 1), ("panel", 3)])
+@pytest.mark.parametrize("mode,n_cases", [("per_kernel", 2), ("fused", 1), ("team", 1), ("level", 1), ("panel", 3)])
 def test_fault_scenario_fp64_incremental(hv, mode, n_cases, kind):
     """The incremental FP64 form (warm_start): its residual takes the step's G, so the switched fault's
     conductance enters through the residual as well as through the rebuilt inverse."""

@@ -206,8 +206,8 @@ def floating_single():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("mode", ["team", "level"])
-@pytest.mark.parametrize("prec,refine", [("fp64", 0), ("fp32", 2)])
+@pytest.mark.parametrize("mode,prec,refine", [(m, p, r) for p, r in [("fp64", 0), ("fp32", 2)] for m in ("team", "level")]
+                         + [("per_kernel", "fp64", 0)])
 def test_single_case_floating_bus_full_horizon(hv, floating_single, mode, prec, refine):
     base, br, Vref = floating_single
     print(f"[gpu] single case, floating-bus loss, {mode} engine, {prec} warm", flush=True)
