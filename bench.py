@@ -58,8 +58,8 @@ N_PICKS = 4            # seeded picks added to the oracle's sample of contingenc
 # launch's step count: the 20-step launch of that command, and the steady 500-step launches of its
 # pre-roll (steps 2501-5000).  Valid only for that kernel and while its sources hash to the profiled ones.
 PANEL_TRAFFIC = {"kernel": "k_emt_panel<double, true, true>",
-                 "sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "8cbc955da570c4a6",
-                 "bytes": {20: 148185088, 500: 1730218639}}
+                 "sources": ["k_panel.hip", "team_sync.h", "hinv_internal.h"], "sha256_16": "cf4eb192cd0c27c2",
+                 "bytes": {20: 148232800, 500: 1732028909}}
 PANEL_KERNELS = {"panel_fp64": "k_emt_panel<double, false, false>", "panel_fp64_inc": "k_emt_panel<double, true, true>",
                  "panel_mixed": "k_emt_panel<float, true, true>"}
 

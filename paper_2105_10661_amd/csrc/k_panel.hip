@@ -39,7 +39,9 @@ constexpr int kPHelpTiles = 3;    // row tiles of each helper wavefront
 constexpr int kPHelpK = 6;        // k-steps of a tile's tail
 constexpr int kPYT = kPanelYTasksPerWave;
 constexpr int kPHItems = 6;       // (branch, case) items of a thread in the history update (<= 192 branches)
-constexpr int kRW = 2;            // residual entries loaded ahead of their multiply-adds
+// residual entries loaded ahead of their multiply-adds: 2 with FP64 storage, 3 with FP32 (measured; the
+// FP64 form holds more registers across the residual, and larger batches there cost more than they hide)
+template <typename TB> constexpr int kRW = sizeof(TB) == 8 ? 2 : 3;
 static_assert(kPB == 16, "the panel is the N dimension of a 16x16x4 MFMA");
 static_assert(kPThreads % kPB == 0, "all items of a thread belong to one case");
 static_assert(kPWaves == kPanelWaves, "wavefront count shared with the host plan");
@@ -855,11 +857,11 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
             const int r = q >> 2, c0 = (q & 3) * 4;
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
             const int e0 = orp[r], e1 = orp[r + 1];
-            for (int eb = e0; eb < e1; eb += kRW) {
-                double2 x[kRW][2];
-                double w[kRW];
+            for (int eb = e0; eb < e1; eb += kRW<TB>) {
+                double2 x[kRW<TB>][2];
+                double w[kRW<TB>];
 #pragma unroll
-                for (int k = 0; k < kRW; ++k) {
+                for (int k = 0; k < kRW<TB>; ++k) {
                     const int e = eb + k < e1 ? eb + k : e1 - 1;
                     const int col = ocol[e];
                     w[k] = oval[e];
@@ -868,7 +870,7 @@ __global__ __launch_bounds__(kPThreads) void k_emt_panel(PanelDev D, EmtDev E, H
                     x[k][1] = src[1];
                 }
 #pragma unroll
-                for (int k = 0; k < kRW; ++k)
+                for (int k = 0; k < kRW<TB>; ++k)
                     if (eb + k < e1) {
                         acc[0] += w[k] * x[k][0].x;
                         acc[1] += w[k] * x[k][0].y;
