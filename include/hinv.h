@@ -93,8 +93,9 @@ typedef struct {
                               HINV_COUPLING_PAPER only) */
     int32_t max_mod_rank;  /* line changes a handle (or each case) can hold, 0..16 */
     int32_t max_nrhs;      /* largest nrhs passed to hinv_solve (>= 1) */
-    int32_t warm_start;    /* EMT, FP32/BF16/FP8 storage: refine from the previous step's v instead of
-                              P b.  FP64 storage, every engine: the incremental form
+    int32_t warm_start;    /* EMT, FP32/BF16/FP8 storage, every engine: max_refine + 1 corrections
+                              per step starting from the previous step's v instead of P b plus
+                              max_refine corrections.  FP64 storage, every engine: the incremental form
                               v = v_prev + P (b - G v_prev), one FP64 apply per step (max_refine and
                               rel_tol unused); equal to P b in exact arithmetic, it keeps rounding from
                               accumulating along a mode the step map does not damp (a bus whose only
@@ -111,8 +112,8 @@ typedef struct {
                               product (max_mod_rank <= 2); 5 = one fused cooperative launch, one
                               workgroup per leaf of a single case, coupling levels computed by the
                               owners of their columns with a barrier per exchange (trees too large
-                              for 3).  Engines 3-5 run exactly max_refine (+1 when warm-started)
-                              corrections per step in mixed precision */
+                              for 3).  Engines 1 and 3-5 run exactly max_refine (+1 when
+                              warm-started) corrections per step in mixed precision */
     int32_t coupling;      /* hinv_coupling: HINV_COUPLING_EXACT stores the exact inverse;
                               HINV_COUPLING_PAPER stores the paper's approximation (Algorithm 1 as
                               printed: every capacitance inverse S^{-1} replaced by C, i.e. each

@@ -699,18 +699,25 @@ void solve_new_order(hinv_ctx& c, const double* B, double* V, int nrhs, int set_
     solve_new_order(c, SolveTemps{c.Y, c.Rv, c.D, c.stats}, B, V, nrhs, set_stride, step, s);
 }
 
-// FP64 solve that starts from the previous solution in V: v += P (b - G v).  Through a unit
-// eigenvalue of the companion update (a floating bus) P b alone carries P's rounding forward
-// from step to step; the residual form keeps each step's error at one apply's rounding of the
-// step's change.  Handle's own temporaries; V holds zeros before the first step.
-void solve_incremental(hinv_ctx& c, const double* B, double* V, int nrhs, int set_stride, const int64_t* step,
-                       hipStream_t s)
+// Solve that starts from the previous solution in V (EMT with warm_start): passes of v += P (b - G v).
+// FP64 storage: one pass, the incremental form.  Through a unit eigenvalue of the companion update
+// (a floating bus) P b alone carries P's rounding forward from step to step; the residual form keeps
+// each step's error at one apply's rounding of the step's change.  Lower storage precisions:
+// max_refine + 1 passes, the last one's ||d|| / ||v|| checked against rel_tol.  Handle's own
+// temporaries; V holds zeros before the first step.
+void solve_from_previous(hinv_ctx& c, const double* B, double* V, int nrhs, int set_stride, const int64_t* step,
+                         hipStream_t s)
 {
     const SolveTemps w{c.Y, c.Rv, c.D, c.stats};
-    launch_residual(c.H, c.M, B, V, w.Rv, nrhs, set_stride, step, s);
-    precond(c, w, HINV_FP64, w.Rv, w.D, nrhs, set_stride, step, s);
-    launch_axpy_stats(c.P.n, nrhs, V, w.D, nullptr, 1e300, c.d_flags, s);
-    c.applies += nrhs;
+    const bool fp64 = c.opt.prec == HINV_FP64;
+    const int passes = fp64 ? 1 : c.opt.max_refine + 1;
+    for (int it = 0; it < passes; ++it) {
+        launch_residual(c.H, c.M, B, V, w.Rv, nrhs, set_stride, step, s);
+        precond(c, w, c.opt.prec, w.Rv, w.D, nrhs, set_stride, step, s);
+        const bool last = !fp64 && it == passes - 1;
+        launch_axpy_stats(c.P.n, nrhs, V, w.D, last ? w.stats : nullptr, last ? c.opt.rel_tol : 1e300, c.d_flags, s);
+    }
+    c.applies += (int64_t)nrhs * passes;
 }
 
 // Stored change j of set 0: u_j = G0^{-1} (e_a - e_b) by one FP64 apply of the current hierarchy.
@@ -3426,11 +3433,11 @@ hinv_status emt_step(emt_handle h, int32_t n_steps, double* d_v_record, double* 
         return HINV_OK;
     }
     launch_set_rec(c.d_rec, RecParams{d_v_record, d_b_record, c.step, n_steps}, s);
-    // FP64 storage with warm_start: the incremental form v += P (b - G v), one FP64 apply per step
-    const bool inc = c.hc.opt.prec == HINV_FP64 && c.hc.opt.warm_start && c.hc.opt.coupling == HINV_COUPLING_EXACT;
+    // warm_start: every step starts from the previous step's v (FP64: the incremental form)
+    const bool warm = c.hc.opt.warm_start && c.hc.opt.coupling == HINV_COUPLING_EXACT;
     for (int i = 0; i < n_steps; ++i) {
-        if (inc)
-            solve_incremental(c.hc, c.E.b, c.E.v, c.n_cases, 1, c.E.step, s);
+        if (warm)
+            solve_from_previous(c.hc, c.E.b, c.E.v, c.n_cases, 1, c.E.step, s);
         else
             solve_new_order(c.hc, c.E.b, c.E.v, c.n_cases, 1, c.E.step, s);
         if (c.ph == 3)

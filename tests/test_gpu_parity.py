@@ -148,7 +148,8 @@ def c1_ref():
 
 @pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp32", "fused", False),
                                             ("fp32", "fused", True), ("fp64", "per_kernel", False),
-                                            ("fp32", "per_kernel", False), ("fp64", "team", False),
+                                            ("fp32", "per_kernel", False), ("fp32", "per_kernel", True),
+                                            ("fp64", "team", False),
                                             ("fp32", "team", False), ("fp32", "team", True),
                                             ("fp64", "level", False), ("fp32", "level", False),
                                             ("fp32", "level", True)])
@@ -195,6 +196,7 @@ def c2_ref():
 
 @pytest.mark.parametrize("prec,mode,warm", [("fp64", "fused", False), ("fp64", "fused", True), ("fp32", "fused", False),
                                             ("fp32", "fused", True), ("fp64", "per_kernel", False),
+                                            ("fp64", "per_kernel", True), ("fp32", "per_kernel", True),
                                             ("fp64", "team", False), ("fp32", "team", False),
                                             ("fp32", "team", True), ("fp64", "level", False),
                                             ("fp32", "level", True)])
